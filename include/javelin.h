@@ -1,0 +1,301 @@
+/*
+ * javelin.h -- C ABI of the MI355X (gfx950) incomplete-LU hot path.
+ *
+ * The method is the one of Booth & Bolet, "Javelin: A Scalable Implementation
+ * for Sparse Incomplete LU Factorization" (arXiv:1812.06160): the fill pattern of
+ * A and a level ordering are found once (Sec. III, "Level Scheduling, Upper
+ * Stage"), A is copied into one CSR that holds L and U in level order, the
+ * numeric factor runs up-looking on that fixed pattern (Sec. III, Fig. 1), and
+ * the same structure serves the sparse triangular solves and the sparse
+ * matrix-vector product that apply M^{-1} = U^{-1} L^{-1} inside CG/GMRES
+ * (Sec. I, Sec. VI).
+ *
+ * Conventions (all calls):
+ *  - Every function returns an ilu_status; ILU_OK is 0.  No C++ exception crosses
+ *    this boundary.  ilu_status_str() names a status, ilu_last_error() gives the
+ *    detail of the last failure on the calling thread.
+ *  - Indices are 0-based int32; nnz must be below 2^31 (ILU_ERR_UNSUPPORTED).
+ *  - "device" pointers are HIP device memory owned by the caller and borrowed for
+ *    the duration of the call (asynchronous calls: until the stream reaches them).
+ *    "host" pointers are ordinary host memory, read or written before the call
+ *    returns.
+ *  - A handle owns every buffer it allocates (hipMalloc at analysis time, freed by
+ *    ilu_destroy).  Handles are not thread-safe; distinct handles are independent.
+ *  - Calls are ordered on the given hipStream_t (0 = the null stream).
+ *  - Dense vectors are row-major [n][ld] with nrhs <= ld columns ("RHS interleaved").
+ */
+#ifndef JAVELIN_H
+#define JAVELIN_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ilu_status;
+enum {
+    ILU_OK = 0,
+    ILU_ERR_ARG = 1,          /* NULL pointer, bad size or option value */
+    ILU_ERR_CSR = 2,          /* row_ptr not monotone, columns unsorted / duplicate / out of range */
+    ILU_ERR_NOMEM = 3,        /* host or device allocation failed */
+    ILU_ERR_HIP = 4,          /* a HIP runtime call failed (detail in ilu_last_error) */
+    ILU_ERR_ZERO_PIVOT = 5,   /* u_rr == 0 in the first failing row (no pivoting, Sec. III) */
+    ILU_ERR_NONFINITE = 6,    /* a non-finite value in the first failing row */
+    ILU_ERR_NOCONV = 7,       /* Krylov iteration limit reached (x still holds the last iterate) */
+    ILU_ERR_BREAKDOWN = 8,    /* Krylov breakdown (zero curvature) */
+    ILU_ERR_STATE = 9,        /* call out of order (e.g. apply before factor) */
+    ILU_ERR_UNSUPPORTED = 10, /* size or row length beyond what the kernels support */
+    ILU_ERR_TIMEOUT = 11      /* a dependency wait in a persistent kernel exceeded its bound */
+};
+
+/* Dependency pattern used to build level sets (Sec. III; Sec. VII recommends the
+ * symmetric one by default). */
+enum { ILU_PATTERN_LOWER_SYM = 0, ILU_PATTERN_LOWER_A = 1 };
+
+/* Storage precision of the factor values used by an apply. */
+enum { ILU_PREC_F64 = 0, ILU_PREC_F32 = 1, ILU_PREC_BF16 = 2 };
+
+/* Bits of `flags`. */
+enum {
+    ILU_PERMUTED_SPACE = 1    /* b, x (apply) and x, y (spmv) are in the level ordering */
+};
+
+/* Scheduling of the factor and the triangular solves. */
+enum {
+    ILU_SCHED_AUTO = 0,       /* the handle's current choice (sync-free unless tuned otherwise) */
+    ILU_SCHED_LEVEL = 1,      /* one kernel launch per level: the launch boundary is the barrier */
+    ILU_SCHED_SYNCFREE = 2    /* one persistent launch; rows wait on per-row ready values */
+};
+
+typedef struct ilu_handle_s *ilu_handle;
+
+/* Host CSR of A (values are passed to ilu_factor instead). */
+typedef struct {
+    int32_t n;                /* rows = columns, > 0 */
+    int64_t nnz;              /* row_ptr[n] */
+    const int32_t *row_ptr;   /* host, n + 1 entries, row_ptr[0] = 0, non-decreasing */
+    const int32_t *col_idx;   /* host, nnz entries, sorted and unique within a row */
+} ilu_csr;
+
+typedef struct {
+    int32_t k_max;            /* largest level of fill that ilu_factor may use (>= 0) */
+    int32_t pattern;          /* ILU_PATTERN_LOWER_SYM (default) or ILU_PATTERN_LOWER_A */
+    int32_t host_only;        /* 1: analysis on the host only, nothing uploaded (inspection and
+                                 planning without a device); numeric calls then fail with
+                                 ILU_ERR_STATE */
+    int32_t reserved[5];      /* must be 0 */
+} ilu_analyze_opts;
+
+typedef struct {
+    int32_t n;
+    int32_t n_levels;         /* forward (factor / L solve) levels */
+    int32_t n_ulevels;        /* backward (U solve) levels */
+    int32_t max_row_lu;       /* longest row of the factor pattern */
+    int64_t nnz_a;            /* input nnz */
+    int64_t nnz_lu;           /* factor pattern nnz (fill included) */
+    int64_t nnz_b;            /* nnz of the permuted copy of A (input + inserted diagonals) */
+    int32_t level_min, level_max;   /* rows per forward level */
+    double level_median;
+    int32_t batch_count;      /* matrices in a batched handle (1 otherwise) */
+    int32_t reserved[7];
+} ilu_info;
+
+typedef struct {
+    int32_t bad_row;          /* first failing row in the level ordering, -1 if none */
+    int32_t bad_row_original; /* the same row in the input ordering, -1 if none */
+    int32_t bad_matrix;       /* batched handles: index of the matrix holding bad_row */
+    int32_t reserved;
+    int64_t n_dropped;        /* entries dropped by the tau test */
+} ilu_factor_info;
+
+typedef struct {
+    int32_t iters;            /* inner iterations (CG steps, GMRES Arnoldi steps) */
+    int32_t status;           /* ILU_OK, ILU_ERR_NOCONV or ILU_ERR_BREAKDOWN */
+    double relres;            /* last recursive residual norm / ||b|| */
+    double true_relres;       /* ||b - A x|| / ||b|| recomputed at exit */
+} ilu_solve_info;
+
+/* ---------------------------------------------------------------------------- */
+/* Analysis (setup; the paper leaves it out of the timed factor, Sec. V).        */
+/* ---------------------------------------------------------------------------- */
+
+/* Validates A, inserts missing diagonals, finds the ILU(k_max) pattern S by level
+ * of fill in the input ordering (Sec. III: the pattern with its fill is found
+ * first, then permuted), the level sets of lower(S) or lower(S + S^T) (Sec. II,
+ * Sec. III), the stable level-order permutation, the permuted factor structure
+ * P S P^T with diagonal positions, the permuted copy of A for spmv, and the
+ * backward-solve schedule; uploads all of it.  opts may be NULL (k_max = 0,
+ * LOWER_SYM).  Synchronous.  Errors: ILU_ERR_ARG, ILU_ERR_CSR, ILU_ERR_NOMEM,
+ * ILU_ERR_HIP, ILU_ERR_UNSUPPORTED. */
+ilu_status ilu_analyze(const ilu_csr *A, const ilu_analyze_opts *opts, ilu_handle *out);
+
+/* Block-diagonal batch of `count` matrices analysed as one: the level sets of all
+ * matrices merge level by level, so a single factor / apply / spmv call (one
+ * persistent launch per stage) serves the whole batch.  Values, right-hand sides
+ * and solutions are the per-matrix arrays concatenated in order. */
+ilu_status ilu_analyze_batched(int32_t count, const ilu_csr *As, const ilu_analyze_opts *opts,
+                               ilu_handle *out);
+
+/* Row and entry offsets of matrix i in a batched handle (host arrays of count+1). */
+ilu_status ilu_batch_offsets(ilu_handle h, int64_t *row_off, int64_t *nnz_off);
+
+ilu_status ilu_get_info(ilu_handle h, ilu_info *out);
+
+/* Copies the schedule and structure to host arrays; any pointer may be NULL.
+ * Sizes: level_ptr n_levels+1, perm n, lu_row_ptr n+1, lu_col_idx nnz_lu,
+ * diag_pos n, ulevel_ptr n_ulevels+1, ulevel_rows n, fill_lev nnz_lu,
+ * lu_src nnz_lu (input entry of each factor entry, -1 for fill / inserted
+ * diagonal), b_row_ptr n+1, b_col_idx nnz_b. */
+ilu_status ilu_copy_schedule(ilu_handle h, int32_t *level_ptr, int32_t *perm, int32_t *lu_row_ptr,
+                             int32_t *lu_col_idx, int32_t *diag_pos, int32_t *ulevel_ptr,
+                             int32_t *ulevel_rows, int8_t *fill_lev, int32_t *lu_src,
+                             int32_t *b_row_ptr, int32_t *b_col_idx);
+
+/* ---------------------------------------------------------------------------- */
+/* Numeric factor (Sec. III, Fig. 1).                                            */
+/* ---------------------------------------------------------------------------- */
+
+/* ILU(k, tau) with 0 <= k <= k_max on the analysed pattern.  a_val: device, the
+ * values of A in the input entry order (length nnz_a).  Entries with fill level
+ * above k are absent; with tau > 0, a multiplier l_rc with |l_rc| < tau_r after
+ * its division, and a U entry with |u_rj| < tau_r at the end of its row, are
+ * dropped (set to 0 and marked), where tau_r = tau * ||A(row,:)||_2; the
+ * diagonal is never dropped.  The FP64 factor is kept; `casts` (bit 1 = FP32,
+ * bit 2 = BF16) also stores rounded copies for ILU_PREC_F32/BF16 applies.
+ * Also loads the values of the permuted copy of A used by ilu_spmv.
+ * Synchronises `stream` to read the status word.  info may be NULL.
+ * Errors: ILU_ERR_STATE, ILU_ERR_ARG (k > k_max, tau < 0 or NaN),
+ * ILU_ERR_ZERO_PIVOT, ILU_ERR_NONFINITE (first failing row in level order),
+ * ILU_ERR_TIMEOUT, ILU_ERR_HIP. */
+ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, double tau, int32_t casts,
+                      ilu_factor_info *info, hipStream_t stream);
+
+/* Device pointer to the factor values in factor order (L strictly lower with unit
+ * diagonal implied, U upper with diagonal), of the given precision; owned by h. */
+ilu_status ilu_factor_values(ilu_handle h, int32_t prec, const void **dev_ptr);
+
+/* Copies FP64 factor values and the per-entry state (0 kept, 1 dropped by tau,
+ * 2 absent: fill level above k) to host arrays of nnz_lu (either may be NULL). */
+ilu_status ilu_copy_factor(ilu_handle h, double *lu_val, int8_t *state);
+
+/* Copies the stored factor of precision prec (ILU_PREC_F32: float, ILU_PREC_BF16:
+ * uint16 bit patterns, ILU_PREC_F64: double) to a host array of nnz_lu. */
+ilu_status ilu_copy_factor_prec(ilu_handle h, int32_t prec, void *host);
+
+/* ---------------------------------------------------------------------------- */
+/* Apply, spmv (Sec. VI; Sec. I).                                                */
+/* ---------------------------------------------------------------------------- */
+
+/* x = M^{-1} b = P^T U^{-1} L^{-1} P b, or U^{-1} L^{-1} b with ILU_PERMUTED_SPACE.
+ * b, x: device, [n][ld] (ld >= nrhs >= 1), vec_prec ILU_PREC_F64 (double) or
+ * ILU_PREC_F32 (float).  fac_prec selects the stored factor: F64 computes in
+ * FP64; F32/BF16 compute in FP32 (b rounded to FP32, x rounded to vec_prec).
+ * x may alias b.  Asynchronous.  Errors: ILU_ERR_STATE (no factor / cast),
+ * ILU_ERR_ARG. */
+ilu_status ilu_apply(ilu_handle h, const void *b, void *x, int32_t nrhs, int64_t ld,
+                     int32_t fac_prec, int32_t vec_prec, int32_t flags, hipStream_t stream);
+
+/* FP64 apply with explicit factor values and the forward intermediate:
+ * lu_val (device, nnz_lu, may be NULL = the handle's factor), y_out (device,
+ * [n][ld] in the level ordering, may be NULL) receives y = L^{-1} P b. */
+ilu_status ilu_apply_ex(ilu_handle h, const double *lu_val, const double *b, double *x,
+                        double *y_out, int32_t nrhs, int64_t ld, int32_t flags, hipStream_t stream);
+
+/* Adjoint of ilu_apply_ex for a loss l with gx = dl/dx (original ordering):
+ *   w  = U^{-T} P gx,  b' = L^{-T} w,  gb = P^T b'            (transposed solves)
+ *   glu[p] = -sum_s w_{r,s} x_{perm[c],s}  for U entries (r, c), c >= r
+ *   glu[p] = -sum_s b'_{r,s} y_{c,s}       for L entries (r, c), c < r
+ * x (original ordering) and y (level ordering) are the outputs of the forward
+ * call.  gb and glu (nnz_lu, factor order, summed over RHS) may be NULL.
+ * All device, FP64, [n][ld].  Asynchronous. */
+ilu_status ilu_apply_adjoint(ilu_handle h, const double *lu_val, const double *gx, const double *x,
+                             const double *y, double *gb, double *glu, int32_t nrhs, int64_t ld,
+                             hipStream_t stream);
+
+/* y = alpha * A x + beta * y with the values loaded by ilu_factor (or
+ * ilu_set_values); FP64, device [n][ld].  With ILU_PERMUTED_SPACE, x and y are
+ * in the level ordering and the product is with P A P^T. */
+ilu_status ilu_spmv(ilu_handle h, double alpha, const double *x, double beta, double *y,
+                    int32_t nrhs, int64_t ld, int32_t flags, hipStream_t stream);
+
+/* Loads A's values (device, input order) for ilu_spmv without factoring. */
+ilu_status ilu_set_values(ilu_handle h, const double *a_val, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------- */
+/* Krylov drivers (the consumers of Sec. I-II).                                  */
+/* ---------------------------------------------------------------------------- */
+
+/* Preconditioned CG from x0 = 0 on one right-hand side, FP64 vectors, apply in
+ * fac_prec; stops when the recursive residual norm / ||b|| <= rtol, then checks
+ * the true residual (restarting the recurrence from it if it misses).
+ * b, x device [n] (original ordering unless ILU_PERMUTED_SPACE).  Synchronous.
+ * info may be NULL.  Returns ILU_OK, ILU_ERR_NOCONV or ILU_ERR_BREAKDOWN. */
+ilu_status ilu_solve_pcg(ilu_handle h, const double *b, double *x, double rtol, int32_t maxit,
+                         int32_t fac_prec, int32_t flags, ilu_solve_info *info, hipStream_t stream);
+
+/* Right-preconditioned flexible GMRES(restart) with modified Gram-Schmidt and
+ * Givens rotations, x0 = 0; a cycle ends at |g_{j+1}| / ||b|| <= rtol, happy
+ * breakdown or `restart` steps; the true residual decides whether to restart.
+ * maxit bounds the total Arnoldi steps.  Synchronous. */
+ilu_status ilu_solve_gmres(ilu_handle h, const double *b, double *x, double rtol, int32_t restart,
+                           int32_t maxit, int32_t fac_prec, int32_t flags, ilu_solve_info *info,
+                           hipStream_t stream);
+
+/* ---------------------------------------------------------------------------- */
+/* Scheduling and tuning.                                                         */
+/* ---------------------------------------------------------------------------- */
+
+/* Chooses the launch scheme of the factor and of the solves (ILU_SCHED_*) and the
+ * lanes per row (0 = automatic from the longest row; else 4, 8, 16, 32 or 64). */
+ilu_status ilu_set_schedule(ilu_handle h, int32_t factor_sched, int32_t solve_sched,
+                            int32_t lanes_factor, int32_t lanes_solve);
+ilu_status ilu_get_schedule(ilu_handle h, int32_t *factor_sched, int32_t *solve_sched,
+                            int32_t *lanes_factor, int32_t *lanes_solve);
+
+/* Times the candidate schedules (level vs sync-free, lanes per row) of the factor
+ * (when a_val, device values in input order, is given; re-run with tau = 0 and the
+ * last k) and of the FP64 apply on this handle's matrix, and keeps the fastest.
+ * Requires a factor; leaves a factor of a_val in the handle.  Synchronous.
+ * results (may be NULL) receives up to `cap` rows of {stage (0 factor, 1 apply),
+ * sched, lanes, microseconds} as doubles; *n_results the row count. */
+ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, double *results, int32_t cap,
+                    int32_t *n_results, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------- */
+/* Kernel timing.                                                                 */
+/* ---------------------------------------------------------------------------- */
+
+/* Stages whose kernels are timed. */
+enum {
+    ILU_STAGE_FACTOR = 0,     /* the numeric factor kernel(s) */
+    ILU_STAGE_FORWARD = 1,    /* forward triangular-solve kernel(s) (L, or U^T in the adjoint) */
+    ILU_STAGE_BACKWARD = 2,   /* backward triangular-solve kernel(s) (U, or L^T in the adjoint) */
+    ILU_STAGE_SPMV = 3,       /* spmv kernel */
+    ILU_STAGE_COUNT = 4
+};
+
+/* While enabled, every stage launch on this handle is bracketed by a pair of HIP
+ * events recorded on the launch's own stream (pool of `capacity` pairs; launches
+ * beyond it are not timed).  ilu_profile_read synchronises the events, adds the
+ * elapsed times per stage into ms[ILU_STAGE_COUNT] (milliseconds) and
+ * launches[ILU_STAGE_COUNT], and clears the record.  Either output may be NULL. */
+ilu_status ilu_profile_enable(ilu_handle h, int32_t enable, int32_t capacity);
+ilu_status ilu_profile_read(ilu_handle h, double *ms, int64_t *launches);
+
+/* ---------------------------------------------------------------------------- */
+/* Lifetime and diagnostics.                                                      */
+/* ---------------------------------------------------------------------------- */
+
+ilu_status ilu_destroy(ilu_handle h);
+const char *ilu_version(void);
+const char *ilu_status_str(ilu_status s);
+/* Copies the calling thread's last error message (NUL-terminated) into buf. */
+ilu_status ilu_last_error(char *buf, int32_t len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* JAVELIN_H */

@@ -1,0 +1,52 @@
+// Host-side analysis of the incomplete-LU hot path: intake, fill pattern, level
+// schedule, permuted structure.  Plain C++ (no HIP); the result is uploaded by the
+// C-ABI layer.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "javelin.h"
+
+namespace jv {
+
+struct HostAnalysis {
+    int32_t n = 0;
+    int64_t nnz_in = 0;
+    int32_t k_max = 0;
+    int32_t pattern = ILU_PATTERN_LOWER_SYM;
+    std::vector<int32_t> in_rp;        // input row pointers (row norms for the tau test)
+
+    // level schedule of the forward direction (factor and L solve)
+    int32_t n_levels = 0;
+    std::vector<int32_t> level_ptr;    // [n_levels + 1], rows of level l are [ptr[l], ptr[l+1])
+    std::vector<int32_t> perm;         // level ordering -> input ordering
+    std::vector<int32_t> iperm;        // input ordering -> level ordering
+
+    // factor structure P S P^T in level order
+    std::vector<int32_t> lu_rp, lu_ci, diag, lu_src;
+    std::vector<int8_t> flev;          // fill level of each factor entry
+    int32_t max_row_lu = 0;
+    int32_t max_lower_lu = 0;          // longest strictly-lower part of a row
+    int32_t max_upper_lu = 0;          // longest strictly-upper part of a row
+
+    // permuted copy of A (inserted diagonals as explicit zeros)
+    std::vector<int32_t> b_rp, b_ci, b_src;
+    int32_t max_row_b = 0;
+
+    // backward (U solve) schedule
+    int32_t n_ulevels = 0;
+    std::vector<int32_t> ulevel_ptr, ulevel_rows;
+
+    // transposed factor structure for the adjoint: row j of (LU)^T holds column j
+    std::vector<int32_t> t_rp, t_ci, t_map, t_diag;   // t_map: entry of (LU)^T -> entry of LU
+    int32_t n_tlevels = 0, n_tulevels = 0;            // levels of U^T (forward) and L^T (backward)
+    std::vector<int32_t> tlevel_ptr, tlevel_rows, tulevel_ptr, tulevel_rows;
+};
+
+// Returns ILU_OK or an error status with a message in *err.
+ilu_status analyze_host(int32_t n, const int32_t *rp, const int32_t *ci, int64_t nnz, int32_t k_max,
+                        int32_t pattern, HostAnalysis *out, std::string *err);
+
+}  // namespace jv

@@ -1,0 +1,826 @@
+// C ABI of the incomplete-LU hot path (declared in include/javelin.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "analysis.h"
+#include "blas.h"
+#include "device.h"
+#include "handle.h"
+#include "javelin.h"
+
+using namespace jv;
+
+namespace jv {
+
+thread_local std::string g_last_error;
+
+ilu_status fail(ilu_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+ilu_status hip_fail(hipError_t e, const char *what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return ILU_ERR_HIP;
+}
+
+template <typename T>
+hipError_t upload(T **dst, const std::vector<T> &src) {
+    *dst = nullptr;
+    if (src.empty()) return hipSuccess;
+    hipError_t e = hipMalloc(dst, src.size() * sizeof(T));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+int pow2_lanes(int len, int lo, int hi) {
+    int g = lo;
+    while (g < len && g < hi) g <<= 1;
+    return g;
+}
+
+// Task list of the persistent kernels: level-homogeneous runs of up to `per`
+// consecutive positions, in level order.
+std::vector<int32_t> make_tasks(const std::vector<int32_t> &level_ptr, int per) {
+    std::vector<int32_t> t;
+    for (size_t l = 0; l + 1 < level_ptr.size(); ++l)
+        for (int32_t p = level_ptr[l]; p < level_ptr[l + 1]; p += per) t.push_back(p);
+    t.push_back(level_ptr.empty() ? 0 : level_ptr.back());
+    return t;
+}
+
+void Profiler::begin(int st, hipStream_t s) {
+    if (!enabled || 2 * (used + 1) > pool.size()) return;
+    if (hipEventRecord(pool[2 * used], s) != hipSuccess) return;
+    stage.push_back(st);
+}
+
+void Profiler::end(hipStream_t s) {
+    if (!enabled || stage.size() != used + 1) return;
+    if (hipEventRecord(pool[2 * used + 1], s) != hipSuccess) {
+        stage.pop_back();
+        return;
+    }
+    ++used;
+}
+
+void Profiler::release() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+    stage.clear();
+    used = 0;
+    enabled = false;
+}
+
+}  // namespace jv
+
+ilu_handle_s::~ilu_handle_s() {
+    prof.release();
+    for (void *p : allocs) (void)hipFree(p);
+    for (auto &kv : tasks) (void)hipFree(kv.second.ptr);
+}
+
+hipError_t ilu_handle_s::alloc_bytes(void **p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) allocs.push_back(*p);
+    return e;
+}
+
+const TaskList *ilu_handle_s::task_list(int which, int lanes) {
+    const int key = which * 1000 + lanes;
+    auto it = tasks.find(key);
+    if (it != tasks.end()) return &it->second;
+    const std::vector<int32_t> *ptr = nullptr;
+    switch (which) {
+        case kTasksForward: ptr = &H.level_ptr; break;
+        case kTasksBackward: ptr = &H.ulevel_ptr; break;
+        case kTasksTForward: ptr = &H.tlevel_ptr; break;
+        default: ptr = &H.tulevel_ptr; break;
+    }
+    std::vector<int32_t> t = make_tasks(*ptr, 64 / lanes);
+    TaskList tl;
+    tl.ntasks = (int32_t)t.size() - 1;
+    if (hipMalloc(&tl.ptr, t.size() * sizeof(int32_t)) != hipSuccess) return nullptr;
+    if (hipMemcpy(tl.ptr, t.data(), t.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(tl.ptr);
+        return nullptr;
+    }
+    tasks[key] = tl;
+    return &tasks[key];
+}
+
+hipError_t ilu_handle_s::ensure_workspace(int nrhs, int prec_class, hipStream_t s) {
+    // prec_class 0: FP64 intermediates, 1: FP32 intermediates
+    int &cap = prec_class == 0 ? cap64 : cap32;
+    void *&y = prec_class == 0 ? y64 : y32;
+    void *&z = prec_class == 0 ? z64 : z32;
+    if (cap >= nrhs) return hipSuccess;
+    int newcap = std::max(nrhs, cap * 2);
+    if (newcap < 1) newcap = 1;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (y) { (void)hipFree(y); allocs.erase(std::find(allocs.begin(), allocs.end(), y)); y = nullptr; }
+    if (z) { (void)hipFree(z); allocs.erase(std::find(allocs.begin(), allocs.end(), z)); z = nullptr; }
+    const size_t elt = prec_class == 0 ? 8 : 4;
+    const size_t count = (size_t)H.n * (size_t)newcap;
+    if ((e = alloc_bytes(&y, count * elt)) != hipSuccess) return e;
+    if ((e = alloc_bytes(&z, count * elt)) != hipSuccess) return e;
+    if (prec_class == 0) {
+        if ((e = launch_fill_u64((uint64_t *)y, kPending64, (int64_t)count, s)) != hipSuccess) return e;
+        if ((e = launch_fill_u64((uint64_t *)z, kPending64, (int64_t)count, s)) != hipSuccess) return e;
+    } else {
+        if ((e = launch_fill_u32((uint32_t *)y, kPending32, (int64_t)count, s)) != hipSuccess) return e;
+        if ((e = launch_fill_u32((uint32_t *)z, kPending32, (int64_t)count, s)) != hipSuccess) return e;
+    }
+    cap = newcap;
+    return hipStreamSynchronize(s);
+}
+
+// re-arms every published intermediate after an expired wait
+hipError_t ilu_handle_s::rearm(hipStream_t s) {
+    hipError_t e = hipSuccess;
+    if (y64) e = launch_fill_u64((uint64_t *)y64, kPending64, (int64_t)H.n * cap64, s);
+    if (e == hipSuccess && z64) e = launch_fill_u64((uint64_t *)z64, kPending64, (int64_t)H.n * cap64, s);
+    if (e == hipSuccess && y32) e = launch_fill_u32((uint32_t *)y32, kPending32, (int64_t)H.n * cap32, s);
+    if (e == hipSuccess && z32) e = launch_fill_u32((uint32_t *)z32, kPending32, (int64_t)H.n * cap32, s);
+    return e;
+}
+
+hipError_t ilu_handle_s::reset_info(hipStream_t s) {
+    static const int32_t init[kInfoSlots] = {INT_MAX, 0, 0, 0, 0, 0, 0, 0};
+    return hipMemcpyAsync(d_info, init, sizeof(init), hipMemcpyHostToDevice, s);
+}
+
+int ilu_handle_s::grid_factor(int lanes, int ntasks) {
+    int g = persistent_grid_factor(lanes);
+    int need = (ntasks + 3) / 4;
+    return std::max(1, std::min(g, need));
+}
+
+int ilu_handle_s::grid_solve(bool fwd, int prec, int vec, int lanes, int ntasks) {
+    int g = persistent_grid_solve(fwd, prec, vec, lanes);
+    int need = (ntasks + 3) / 4;
+    return std::max(1, std::min(g, need));
+}
+
+// -------------------------------------------------------------------------------------
+// Analysis
+// -------------------------------------------------------------------------------------
+
+static ilu_status finish_analysis(ilu_handle_s *h) {
+    HostAnalysis &H = h->H;
+    hipError_t e;
+#define UP(dst, src)                                                   \
+    do {                                                               \
+        if ((e = upload(&dst, src)) != hipSuccess) return hip_fail(e, "upload " #src); \
+        if (dst) h->allocs.push_back(dst);                             \
+    } while (0)
+    UP(h->d_in_rp, H.in_rp);
+    UP(h->d_perm, H.perm);
+    UP(h->d_lu_rp, H.lu_rp);
+    UP(h->d_lu_ci, H.lu_ci);
+    UP(h->d_diag, H.diag);
+    UP(h->d_lu_src, H.lu_src);
+    UP(h->d_flev, H.flev);
+    UP(h->d_b_rp, H.b_rp);
+    UP(h->d_b_ci, H.b_ci);
+    UP(h->d_b_src, H.b_src);
+    UP(h->d_ulevel_rows, H.ulevel_rows);
+    UP(h->d_t_rp, H.t_rp);
+    UP(h->d_t_ci, H.t_ci);
+    UP(h->d_t_map, H.t_map);
+    UP(h->d_t_diag, H.t_diag);
+    UP(h->d_tlevel_rows, H.tlevel_rows);
+    UP(h->d_tulevel_rows, H.tulevel_rows);
+#undef UP
+    const size_t nz = H.lu_rp[H.n];
+    void *p;
+    if ((e = h->alloc_bytes(&p, nz * 8)) != hipSuccess) return hip_fail(e, "alloc factor");
+    h->d_lu = (double *)p;
+    if ((e = h->alloc_bytes(&p, (size_t)H.b_rp[H.n] * 8)) != hipSuccess) return hip_fail(e, "alloc spmv values");
+    h->d_bval = (double *)p;
+    if ((e = h->alloc_bytes(&p, (size_t)H.n * 8)) != hipSuccess) return hip_fail(e, "alloc row tau");
+    h->d_row_tau = (double *)p;
+    if ((e = h->alloc_bytes(&p, kInfoSlots * 4)) != hipSuccess) return hip_fail(e, "alloc info");
+    h->d_info = (int32_t *)p;
+    if ((e = h->alloc_bytes(&p, kDotParts * 8 + 64 * 8)) != hipSuccess) return hip_fail(e, "alloc dot work");
+    h->d_dotwork = (double *)p;
+    h->lanes_factor = pow2_lanes(H.max_row_lu, 4, 64);
+    h->lanes_solve = pow2_lanes(std::max(H.max_lower_lu, H.max_upper_lu), 4, 64);
+    h->lanes_spmv = pow2_lanes(std::max(1, (int)((H.b_rp[H.n] + H.n - 1) / H.n)), 4, 64);
+    return ILU_OK;
+}
+
+extern "C" ilu_status ilu_analyze(const ilu_csr *A, const ilu_analyze_opts *opts, ilu_handle *out) {
+    if (!A || !out) return fail(ILU_ERR_ARG, "ilu_analyze: NULL argument");
+    *out = nullptr;
+    ilu_analyze_opts o{};
+    if (opts) o = *opts;
+    for (int i = 0; i < 5; ++i)
+        if (o.reserved[i]) return fail(ILU_ERR_ARG, "ilu_analyze: reserved option fields must be 0");
+    if (o.host_only != 0 && o.host_only != 1) return fail(ILU_ERR_ARG, "ilu_analyze: host_only must be 0 or 1");
+    if (A->n <= 0 || A->n >= (1 << 30)) return fail(ILU_ERR_ARG, "ilu_analyze: n must be in [1, 2^30)");
+    std::unique_ptr<ilu_handle_s> h(new (std::nothrow) ilu_handle_s());
+    if (!h) return fail(ILU_ERR_NOMEM, "ilu_analyze: out of host memory");
+    std::string err;
+    ilu_status st;
+    try {
+        st = analyze_host(A->n, A->row_ptr, A->col_idx, A->nnz, o.k_max, o.pattern, &h->H, &err);
+    } catch (const std::bad_alloc &) {
+        return fail(ILU_ERR_NOMEM, "ilu_analyze: out of host memory");
+    }
+    if (st != ILU_OK) return fail(st, err);
+    h->row_off = {0, (int64_t)A->n};
+    h->nnz_off = {0, A->nnz};
+    h->host_only = o.host_only != 0;
+    if (!h->host_only && (st = finish_analysis(h.get())) != ILU_OK) return st;
+    *out = h.release();
+    return ILU_OK;
+}
+
+extern "C" ilu_status ilu_analyze_batched(int32_t count, const ilu_csr *As, const ilu_analyze_opts *opts,
+                                          ilu_handle *out) {
+    if (!As || !out || count <= 0) return fail(ILU_ERR_ARG, "ilu_analyze_batched: bad arguments");
+    *out = nullptr;
+    ilu_analyze_opts o{};
+    if (opts) o = *opts;
+    std::vector<int64_t> roff(count + 1, 0), zoff(count + 1, 0);
+    for (int i = 0; i < count; ++i) {
+        if (As[i].n <= 0 || !As[i].row_ptr || !As[i].col_idx) return fail(ILU_ERR_ARG, "ilu_analyze_batched: bad matrix");
+        roff[i + 1] = roff[i] + As[i].n;
+        zoff[i + 1] = zoff[i] + As[i].nnz;
+    }
+    if (roff[count] >= (1 << 30) || zoff[count] >= ((int64_t)1 << 31) - roff[count])
+        return fail(ILU_ERR_UNSUPPORTED, "ilu_analyze_batched: batch too large for int32 indices");
+    std::vector<int32_t> rp((size_t)roff[count] + 1), ci((size_t)zoff[count]);
+    rp[0] = 0;
+    for (int i = 0; i < count; ++i) {
+        const ilu_csr &M = As[i];
+        if (M.row_ptr[0] != 0 || M.row_ptr[M.n] != M.nnz)
+            return fail(ILU_ERR_CSR, "ilu_analyze_batched: matrix " + std::to_string(i) + " row_ptr inconsistent");
+        for (int32_t r = 0; r < M.n; ++r) rp[roff[i] + r + 1] = (int32_t)(zoff[i] + M.row_ptr[r + 1]);
+        for (int64_t p = 0; p < M.nnz; ++p) {
+            if (M.col_idx[p] < 0 || M.col_idx[p] >= M.n)
+                return fail(ILU_ERR_CSR, "ilu_analyze_batched: matrix " + std::to_string(i) + " column out of range");
+            ci[zoff[i] + p] = (int32_t)(M.col_idx[p] + roff[i]);
+        }
+    }
+    ilu_csr big{(int32_t)roff[count], zoff[count], rp.data(), ci.data()};
+    ilu_status st = ilu_analyze(&big, &o, out);
+    if (st != ILU_OK) return st;
+    (*out)->row_off = roff;
+    (*out)->nnz_off = zoff;
+    (*out)->batch_count = count;
+    return ILU_OK;
+}
+
+extern "C" ilu_status ilu_batch_offsets(ilu_handle h, int64_t *row_off, int64_t *nnz_off) {
+    if (!h) return fail(ILU_ERR_ARG, "ilu_batch_offsets: NULL handle");
+    if (row_off) std::copy(h->row_off.begin(), h->row_off.end(), row_off);
+    if (nnz_off) std::copy(h->nnz_off.begin(), h->nnz_off.end(), nnz_off);
+    return ILU_OK;
+}
+
+extern "C" ilu_status ilu_get_info(ilu_handle h, ilu_info *out) {
+    if (!h || !out) return fail(ILU_ERR_ARG, "ilu_get_info: NULL argument");
+    const HostAnalysis &H = h->H;
+    ilu_info I{};
+    I.n = H.n;
+    I.n_levels = H.n_levels;
+    I.n_ulevels = H.n_ulevels;
+    I.max_row_lu = H.max_row_lu;
+    I.nnz_a = H.nnz_in;
+    I.nnz_lu = H.lu_rp[H.n];
+    I.nnz_b = H.b_rp[H.n];
+    std::vector<int32_t> sizes(H.n_levels);
+    for (int l = 0; l < H.n_levels; ++l) sizes[l] = H.level_ptr[l + 1] - H.level_ptr[l];
+    std::sort(sizes.begin(), sizes.end());
+    I.level_min = sizes.front();
+    I.level_max = sizes.back();
+    const size_t m = sizes.size();
+    I.level_median = (m % 2) ? sizes[m / 2] : 0.5 * ((double)sizes[m / 2 - 1] + sizes[m / 2]);
+    I.batch_count = h->batch_count;
+    *out = I;
+    return ILU_OK;
+}
+
+extern "C" ilu_status ilu_copy_schedule(ilu_handle h, int32_t *level_ptr, int32_t *perm, int32_t *lu_row_ptr,
+                                        int32_t *lu_col_idx, int32_t *diag_pos, int32_t *ulevel_ptr,
+                                        int32_t *ulevel_rows, int8_t *fill_lev, int32_t *lu_src,
+                                        int32_t *b_row_ptr, int32_t *b_col_idx) {
+    if (!h) return fail(ILU_ERR_ARG, "ilu_copy_schedule: NULL handle");
+    const HostAnalysis &H = h->H;
+    auto cp = [](auto *dst, const auto &v) {
+        if (dst) std::copy(v.begin(), v.end(), dst);
+    };
+    cp(level_ptr, H.level_ptr);
+    cp(perm, H.perm);
+    cp(lu_row_ptr, H.lu_rp);
+    cp(lu_col_idx, H.lu_ci);
+    cp(diag_pos, H.diag);
+    cp(ulevel_ptr, H.ulevel_ptr);
+    cp(ulevel_rows, H.ulevel_rows);
+    cp(fill_lev, H.flev);
+    cp(lu_src, H.lu_src);
+    cp(b_row_ptr, H.b_rp);
+    cp(b_col_idx, H.b_ci);
+    return ILU_OK;
+}
+
+// -------------------------------------------------------------------------------------
+// Factor
+// -------------------------------------------------------------------------------------
+
+extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, double tau, int32_t casts,
+                                 ilu_factor_info *info, hipStream_t s) {
+    if (!h) return fail(ILU_ERR_STATE, "ilu_factor: no analysis (NULL handle)");
+    if (h->host_only) return fail(ILU_ERR_STATE, "ilu_factor: host-only analysis");
+    if (!a_val && h->H.nnz_in > 0) return fail(ILU_ERR_ARG, "ilu_factor: NULL values");
+    if (k < 0 || k > h->H.k_max) return fail(ILU_ERR_ARG, "ilu_factor: k must be in [0, k_max]");
+    if (!(tau >= 0.0)) return fail(ILU_ERR_ARG, "ilu_factor: tau must be >= 0");
+    if (casts & ~3) return fail(ILU_ERR_ARG, "ilu_factor: unknown cast bits");
+    const HostAnalysis &H = h->H;
+    if (H.max_row_lu > 64)
+        return fail(ILU_ERR_UNSUPPORTED, "ilu_factor: factor rows longer than 64 entries are not supported");
+    const int lanes = h->lanes_factor;
+    const bool sf = h->sched_factor != ILU_SCHED_LEVEL;
+    hipError_t e;
+    h->factored = false;
+    if (info) {
+        info->bad_row = info->bad_row_original = info->bad_matrix = -1;
+        info->n_dropped = 0;
+    }
+    if ((e = h->reset_info(s)) != hipSuccess) return hip_fail(e, "ilu_factor: info reset");
+    const bool use_tau = tau > 0.0;
+    if (use_tau && (e = launch_row_tau(H.n, h->d_in_rp, a_val, h->d_perm, tau, h->d_row_tau, s)) != hipSuccess)
+        return hip_fail(e, "ilu_factor: row tau");
+    FactorArgs A{};
+    A.n = H.n;
+    A.rp = h->d_lu_rp;
+    A.ci = h->d_lu_ci;
+    A.diag = h->d_diag;
+    A.src = h->d_lu_src;
+    A.flev = h->d_flev;
+    A.k = k;
+    A.use_flev = k < H.k_max;
+    A.use_tau = use_tau;
+    A.a = a_val;
+    A.lu = h->d_lu;
+    A.row_tau = h->d_row_tau;
+    A.info = h->d_info;
+    if (sf) {
+        const TaskList *tl = h->task_list(kTasksForward, lanes);
+        if (!tl) return fail(ILU_ERR_NOMEM, "ilu_factor: task list");
+        if ((e = launch_fill_u64((uint64_t *)h->d_lu, kPending64, H.lu_rp[H.n], s)) != hipSuccess)
+            return hip_fail(e, "ilu_factor: arm");
+        A.task_ptr = tl->ptr;
+        A.ntasks = tl->ntasks;
+        h->prof.begin(ILU_STAGE_FACTOR, s);
+        e = launch_factor(A, lanes, true, h->grid_factor(lanes, tl->ntasks), s);
+        h->prof.end(s);
+        if (e != hipSuccess) return hip_fail(e, "ilu_factor: launch");
+    } else {
+        h->prof.begin(ILU_STAGE_FACTOR, s);
+        for (int l = 0; l < H.n_levels; ++l) {
+            A.row_begin = H.level_ptr[l];
+            A.row_end = H.level_ptr[l + 1];
+            if ((e = launch_factor(A, lanes, false, 0, s)) != hipSuccess) return hip_fail(e, "ilu_factor: launch");
+        }
+        h->prof.end(s);
+    }
+    h->tracked = use_tau || A.use_flev;
+    if (h->tracked) {
+        if (!h->d_stat) {
+            void *p;
+            if ((e = h->alloc_bytes(&p, (size_t)H.lu_rp[H.n])) != hipSuccess) return hip_fail(e, "alloc state");
+            h->d_stat = (int8_t *)p;
+        }
+        if ((e = launch_factor_fixup(H.lu_rp[H.n], h->d_lu, h->d_flev, k, A.use_flev, h->d_stat, h->d_info, s)) !=
+            hipSuccess)
+            return hip_fail(e, "ilu_factor: fixup");
+    }
+    if ((e = launch_gather(H.b_rp[H.n], h->d_b_src, a_val, h->d_bval, s)) != hipSuccess)
+        return hip_fail(e, "ilu_factor: spmv values");
+    h->bvals = true;
+    void *p;
+    if (casts & 1) {
+        if (!h->d_lu32) {
+            if ((e = h->alloc_bytes(&p, (size_t)H.lu_rp[H.n] * 4)) != hipSuccess) return hip_fail(e, "alloc f32");
+            h->d_lu32 = (float *)p;
+        }
+        if ((e = launch_cast_f32(H.lu_rp[H.n], h->d_lu, h->d_lu32, s)) != hipSuccess) return hip_fail(e, "cast f32");
+    }
+    if (casts & 2) {
+        if (!h->d_lu16) {
+            if ((e = h->alloc_bytes(&p, (size_t)H.lu_rp[H.n] * 2)) != hipSuccess) return hip_fail(e, "alloc bf16");
+            h->d_lu16 = (uint16_t *)p;
+        }
+        if ((e = launch_cast_bf16(H.lu_rp[H.n], h->d_lu, h->d_lu16, s)) != hipSuccess) return hip_fail(e, "cast bf16");
+    }
+    int32_t hinfo[kInfoSlots];
+    if ((e = hipMemcpyAsync(hinfo, h->d_info, sizeof(hinfo), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return hip_fail(e, "ilu_factor: info readback");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "ilu_factor: synchronize");
+    h->has32 = casts & 1;
+    h->has16 = (casts & 2) != 0;
+    h->k_used = k;
+    int64_t dropped = 0;
+    std::memcpy(&dropped, &hinfo[kInfoDropLo], 8);
+    if (info) info->n_dropped = dropped;
+    if (hinfo[kInfoAbort]) {
+        (void)h->reset_info(s);
+        (void)h->rearm(s);
+        (void)hipStreamSynchronize(s);
+        return fail(ILU_ERR_TIMEOUT, "ilu_factor: a dependency wait expired");
+    }
+    if (hinfo[kInfoBadKey] != INT_MAX) {
+        const int row = hinfo[kInfoBadKey] >> 1;
+        if (info) {
+            info->bad_row = row;
+            info->bad_row_original = H.perm[row];
+            const int64_t orig = H.perm[row];
+            info->bad_matrix =
+                (int32_t)(std::upper_bound(h->row_off.begin(), h->row_off.end(), orig) - h->row_off.begin()) - 1;
+        }
+        h->factored = true;  // values exist (garbage after the failing row); callers see the status
+        h->factor_ok = false;
+        return fail((hinfo[kInfoBadKey] & 1) ? ILU_ERR_NONFINITE : ILU_ERR_ZERO_PIVOT,
+                    std::string("ilu_factor: ") + ((hinfo[kInfoBadKey] & 1) ? "non-finite value" : "zero pivot") +
+                        " in row " + std::to_string(row) + " (level order), " + std::to_string(H.perm[row]) +
+                        " (input order)");
+    }
+    h->factored = true;
+    h->factor_ok = true;
+    return ILU_OK;
+}
+
+extern "C" ilu_status ilu_factor_values(ilu_handle h, int32_t prec, const void **dev_ptr) {
+    if (!h || !dev_ptr) return fail(ILU_ERR_ARG, "ilu_factor_values: NULL argument");
+    if (!h->factored) return fail(ILU_ERR_STATE, "ilu_factor_values: no factor");
+    switch (prec) {
+        case ILU_PREC_F64: *dev_ptr = h->d_lu; return ILU_OK;
+        case ILU_PREC_F32:
+            if (!h->has32) return fail(ILU_ERR_STATE, "ilu_factor_values: no FP32 copy");
+            *dev_ptr = h->d_lu32;
+            return ILU_OK;
+        case ILU_PREC_BF16:
+            if (!h->has16) return fail(ILU_ERR_STATE, "ilu_factor_values: no BF16 copy");
+            *dev_ptr = h->d_lu16;
+            return ILU_OK;
+        default: return fail(ILU_ERR_ARG, "ilu_factor_values: unknown precision");
+    }
+}
+
+extern "C" ilu_status ilu_copy_factor(ilu_handle h, double *lu_val, int8_t *state) {
+    if (!h) return fail(ILU_ERR_ARG, "ilu_copy_factor: NULL handle");
+    if (!h->factored) return fail(ILU_ERR_STATE, "ilu_copy_factor: no factor");
+    const size_t nz = h->H.lu_rp[h->H.n];
+    hipError_t e;
+    if (lu_val && (e = hipMemcpy(lu_val, h->d_lu, nz * 8, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "ilu_copy_factor");
+    if (state) {
+        if (h->tracked) {
+            if ((e = hipMemcpy(state, h->d_stat, nz, hipMemcpyDeviceToHost)) != hipSuccess)
+                return hip_fail(e, "ilu_copy_factor");
+        } else {
+            std::memset(state, 0, nz);
+        }
+    }
+    return ILU_OK;
+}
+
+extern "C" ilu_status ilu_copy_factor_prec(ilu_handle h, int32_t prec, void *host) {
+    if (!h || !host) return fail(ILU_ERR_ARG, "ilu_copy_factor_prec: NULL argument");
+    const void *src = nullptr;
+    ilu_status st = ilu_factor_values(h, prec, &src);
+    if (st != ILU_OK) return st;
+    const size_t esz = prec == ILU_PREC_F64 ? 8 : (prec == ILU_PREC_F32 ? 4 : 2);
+    hipError_t e = hipMemcpy(host, src, (size_t)h->H.lu_rp[h->H.n] * esz, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "ilu_copy_factor_prec");
+    return ILU_OK;
+}
+
+// -------------------------------------------------------------------------------------
+// Solves
+// -------------------------------------------------------------------------------------
+
+namespace jv {
+
+// One forward + backward pass.  view: 0 = the factor (L then U), 1 = the
+// transposed factor (U^T then L^T, adjoint).
+ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int vec, const void *b, void *x,
+                      void *y_out, void *z_out, int nrhs, int64_t ld, int flags, hipStream_t s) {
+    const HostAnalysis &H = h->H;
+    const int pc = prec == ILU_PREC_F64 ? 0 : 1;
+    hipError_t e;
+    if ((e = h->ensure_workspace(nrhs, pc, s)) != hipSuccess) return hip_fail(e, "workspace");
+    const bool sf = h->sched_solve != ILU_SCHED_LEVEL;
+    const int lanes = h->lanes_solve;
+    SolveArgs A{};
+    A.n = H.n;
+    A.val = val;
+    A.perm = (flags & ILU_PERMUTED_SPACE) ? nullptr : h->d_perm;
+    A.b = b;
+    A.x = x;
+    A.y = pc == 0 ? h->y64 : h->y32;
+    A.z = pc == 0 ? h->z64 : h->z32;
+    A.y_out = y_out;
+    A.z_out = z_out;
+    A.ld = ld;
+    A.cap = pc == 0 ? h->cap64 : h->cap32;
+    A.nrhs = nrhs;
+    A.info = h->d_info;
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool fwd = pass == 0;
+        int which;
+        const std::vector<int32_t> *lptr;
+        if (view == 0) {
+            A.rp = h->d_lu_rp;
+            A.ci = h->d_lu_ci;
+            A.diag = h->d_diag;
+            A.vmap = nullptr;
+            A.rows = fwd ? nullptr : h->d_ulevel_rows;
+            A.unit_diag = fwd ? 1 : 0;
+            which = fwd ? kTasksForward : kTasksBackward;
+            lptr = fwd ? &H.level_ptr : &H.ulevel_ptr;
+        } else {
+            A.rp = h->d_t_rp;
+            A.ci = h->d_t_ci;
+            A.diag = h->d_t_diag;
+            A.vmap = h->d_t_map;
+            A.rows = fwd ? h->d_tlevel_rows : h->d_tulevel_rows;
+            A.unit_diag = fwd ? 0 : 1;
+            which = fwd ? kTasksTForward : kTasksTBackward;
+            lptr = fwd ? &H.tlevel_ptr : &H.tulevel_ptr;
+        }
+        if (sf) {
+            const TaskList *tl = h->task_list(which, lanes);
+            if (!tl) return fail(ILU_ERR_NOMEM, "task list");
+            A.task_ptr = tl->ptr;
+            A.ntasks = tl->ntasks;
+            h->prof.begin(fwd ? ILU_STAGE_FORWARD : ILU_STAGE_BACKWARD, s);
+            e = launch_solve(A, fwd, prec, vec, lanes, true, h->grid_solve(fwd, prec, vec, lanes, tl->ntasks), s);
+            h->prof.end(s);
+            if (e != hipSuccess) return hip_fail(e, "solve launch");
+        } else {
+            h->prof.begin(fwd ? ILU_STAGE_FORWARD : ILU_STAGE_BACKWARD, s);
+            for (size_t l = 0; l + 1 < lptr->size(); ++l) {
+                A.row_begin = (*lptr)[l];
+                A.row_end = (*lptr)[l + 1];
+                if ((e = launch_solve(A, fwd, prec, vec, lanes, false, 0, s)) != hipSuccess)
+                    return hip_fail(e, "solve launch");
+            }
+            h->prof.end(s);
+        }
+    }
+    return ILU_OK;
+}
+
+}  // namespace jv
+
+extern "C" ilu_status ilu_apply(ilu_handle h, const void *b, void *x, int32_t nrhs, int64_t ld, int32_t fac_prec,
+                                int32_t vec_prec, int32_t flags, hipStream_t s) {
+    if (!h) return fail(ILU_ERR_STATE, "ilu_apply: NULL handle");
+    if (!h->factored) return fail(ILU_ERR_STATE, "ilu_apply: no factor");
+    if (!b || !x || nrhs < 1 || ld < nrhs) return fail(ILU_ERR_ARG, "ilu_apply: bad vectors or sizes");
+    if (vec_prec != ILU_PREC_F64 && vec_prec != ILU_PREC_F32) return fail(ILU_ERR_ARG, "ilu_apply: vec_prec");
+    if (flags & ~ILU_PERMUTED_SPACE) return fail(ILU_ERR_ARG, "ilu_apply: unknown flags");
+    const void *val;
+    switch (fac_prec) {
+        case ILU_PREC_F64: val = h->d_lu; break;
+        case ILU_PREC_F32:
+            if (!h->has32) return fail(ILU_ERR_STATE, "ilu_apply: factor has no FP32 copy");
+            val = h->d_lu32;
+            break;
+        case ILU_PREC_BF16:
+            if (!h->has16) return fail(ILU_ERR_STATE, "ilu_apply: factor has no BF16 copy");
+            val = h->d_lu16;
+            break;
+        default: return fail(ILU_ERR_ARG, "ilu_apply: fac_prec");
+    }
+    return run_solves(h, 0, val, fac_prec, vec_prec == ILU_PREC_F64 ? 0 : 1, b, x, nullptr, nullptr, nrhs, ld, flags,
+                      s);
+}
+
+extern "C" ilu_status ilu_apply_ex(ilu_handle h, const double *lu_val, const double *b, double *x, double *y_out,
+                                   int32_t nrhs, int64_t ld, int32_t flags, hipStream_t s) {
+    if (!h) return fail(ILU_ERR_STATE, "ilu_apply_ex: NULL handle");
+    if (h->host_only) return fail(ILU_ERR_STATE, "ilu_apply_ex: host-only analysis");
+    if (!lu_val && !h->factored) return fail(ILU_ERR_STATE, "ilu_apply_ex: no factor");
+    if (!b || !x || nrhs < 1 || ld < nrhs) return fail(ILU_ERR_ARG, "ilu_apply_ex: bad vectors or sizes");
+    if (flags & ~ILU_PERMUTED_SPACE) return fail(ILU_ERR_ARG, "ilu_apply_ex: unknown flags");
+    return run_solves(h, 0, lu_val ? lu_val : h->d_lu, ILU_PREC_F64, 0, b, x, y_out, nullptr, nrhs, ld, flags, s);
+}
+
+// spmv
+extern "C" ilu_status ilu_set_values(ilu_handle h, const double *a_val, hipStream_t s) {
+    if (!h) return fail(ILU_ERR_STATE, "ilu_set_values: NULL handle");
+    if (h->host_only) return fail(ILU_ERR_STATE, "ilu_set_values: host-only analysis");
+    if (!a_val && h->H.nnz_in) return fail(ILU_ERR_ARG, "ilu_set_values: NULL values");
+    hipError_t e = launch_gather(h->H.b_rp[h->H.n], h->d_b_src, a_val, h->d_bval, s);
+    if (e != hipSuccess) return hip_fail(e, "ilu_set_values");
+    h->bvals = true;
+    return ILU_OK;
+}
+
+extern "C" ilu_status ilu_spmv(ilu_handle h, double alpha, const double *x, double beta, double *y, int32_t nrhs,
+                               int64_t ld, int32_t flags, hipStream_t s) {
+    if (!h) return fail(ILU_ERR_STATE, "ilu_spmv: NULL handle");
+    if (!h->bvals) return fail(ILU_ERR_STATE, "ilu_spmv: no values loaded");
+    if (!x || !y || nrhs < 1 || ld < nrhs) return fail(ILU_ERR_ARG, "ilu_spmv: bad vectors or sizes");
+    if (x == y) return fail(ILU_ERR_ARG, "ilu_spmv: x and y must not alias");
+    SpmvArgs A{};
+    A.n = h->H.n;
+    A.rp = h->d_b_rp;
+    A.ci = h->d_b_ci;
+    A.val = h->d_bval;
+    A.perm = (flags & ILU_PERMUTED_SPACE) ? nullptr : h->d_perm;
+    A.x = x;
+    A.y = y;
+    A.alpha = alpha;
+    A.beta = beta;
+    A.ld = ld;
+    A.nrhs = nrhs;
+    h->prof.begin(ILU_STAGE_SPMV, s);
+    hipError_t e = launch_spmv(A, h->lanes_spmv, s);
+    h->prof.end(s);
+    if (e != hipSuccess) return hip_fail(e, "ilu_spmv");
+    return ILU_OK;
+}
+
+// -------------------------------------------------------------------------------------
+// Adjoint
+// -------------------------------------------------------------------------------------
+
+extern "C" ilu_status ilu_apply_adjoint(ilu_handle h, const double *lu_val, const double *gx, const double *x,
+                                        const double *y, double *gb, double *glu, int32_t nrhs, int64_t ld,
+                                        hipStream_t s) {
+    if (!h) return fail(ILU_ERR_STATE, "ilu_apply_adjoint: NULL handle");
+    if (h->host_only) return fail(ILU_ERR_STATE, "ilu_apply_adjoint: host-only analysis");
+    if (!lu_val && !h->factored) return fail(ILU_ERR_STATE, "ilu_apply_adjoint: no factor");
+    if (!gx || nrhs < 1 || ld < nrhs) return fail(ILU_ERR_ARG, "ilu_apply_adjoint: bad vectors or sizes");
+    if (glu && (!x || !y)) return fail(ILU_ERR_ARG, "ilu_apply_adjoint: glu needs the saved x and y");
+    const HostAnalysis &H = h->H;
+    hipError_t e;
+    const size_t vec_bytes = (size_t)H.n * (size_t)ld * 8;
+    if (h->adj_bytes < vec_bytes) {
+        void *p;
+        if (h->d_adj_w) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(h->d_adj_w);
+            allocs_erase(h, h->d_adj_w);
+            (void)hipFree(h->d_adj_bp);
+            allocs_erase(h, h->d_adj_bp);
+            (void)hipFree(h->d_adj_gb);
+            allocs_erase(h, h->d_adj_gb);
+        }
+        if ((e = h->alloc_bytes(&p, vec_bytes)) != hipSuccess) return hip_fail(e, "adjoint workspace");
+        h->d_adj_w = (double *)p;
+        if ((e = h->alloc_bytes(&p, vec_bytes)) != hipSuccess) return hip_fail(e, "adjoint workspace");
+        h->d_adj_bp = (double *)p;
+        if ((e = h->alloc_bytes(&p, vec_bytes)) != hipSuccess) return hip_fail(e, "adjoint workspace");
+        h->d_adj_gb = (double *)p;
+        h->adj_bytes = vec_bytes;
+    }
+    const double *val = lu_val ? lu_val : h->d_lu;
+    double *gb_out = gb ? gb : h->d_adj_gb;
+    ilu_status st = run_solves(h, 1, val, ILU_PREC_F64, 0, gx, gb_out, h->d_adj_w, h->d_adj_bp, nrhs, ld, 0, s);
+    if (st != ILU_OK) return st;
+    if (glu) {
+        e = launch_outer(H.n, h->d_lu_rp, h->d_lu_ci, h->d_perm, h->d_adj_w, h->d_adj_bp, x, y, glu, nrhs, ld, s);
+        if (e != hipSuccess) return hip_fail(e, "ilu_apply_adjoint: outer products");
+    }
+    return ILU_OK;
+}
+
+// -------------------------------------------------------------------------------------
+// Scheduling
+// -------------------------------------------------------------------------------------
+
+static bool valid_lanes(int l) { return l == 0 || l == 4 || l == 8 || l == 16 || l == 32 || l == 64; }
+
+extern "C" ilu_status ilu_set_schedule(ilu_handle h, int32_t factor_sched, int32_t solve_sched, int32_t lanes_factor,
+                                       int32_t lanes_solve) {
+    if (!h) return fail(ILU_ERR_ARG, "ilu_set_schedule: NULL handle");
+    if (factor_sched < 0 || factor_sched > 2 || solve_sched < 0 || solve_sched > 2 || !valid_lanes(lanes_factor) ||
+        !valid_lanes(lanes_solve))
+        return fail(ILU_ERR_ARG, "ilu_set_schedule: bad value");
+    if (factor_sched) h->sched_factor = factor_sched;
+    if (solve_sched) h->sched_solve = solve_sched;
+    if (lanes_factor) {
+        if (lanes_factor < h->H.max_row_lu)
+            return fail(ILU_ERR_ARG, "ilu_set_schedule: factor lanes must cover the longest factor row");
+        h->lanes_factor = lanes_factor;
+    }
+    if (lanes_solve) h->lanes_solve = lanes_solve;
+    return ILU_OK;
+}
+
+extern "C" ilu_status ilu_get_schedule(ilu_handle h, int32_t *factor_sched, int32_t *solve_sched,
+                                       int32_t *lanes_factor, int32_t *lanes_solve) {
+    if (!h) return fail(ILU_ERR_ARG, "ilu_get_schedule: NULL handle");
+    if (factor_sched) *factor_sched = h->sched_factor;
+    if (solve_sched) *solve_sched = h->sched_solve;
+    if (lanes_factor) *lanes_factor = h->lanes_factor;
+    if (lanes_solve) *lanes_solve = h->lanes_solve;
+    return ILU_OK;
+}
+
+// -------------------------------------------------------------------------------------
+// Kernel timing
+// -------------------------------------------------------------------------------------
+
+extern "C" ilu_status ilu_profile_enable(ilu_handle h, int32_t enable, int32_t capacity) {
+    if (!h) return fail(ILU_ERR_ARG, "ilu_profile_enable: NULL handle");
+    if (!enable) {
+        h->prof.enabled = false;
+        return ILU_OK;
+    }
+    if (capacity < 1 || capacity > (1 << 20)) return fail(ILU_ERR_ARG, "ilu_profile_enable: capacity");
+    if (h->prof.pool.size() < (size_t)2 * capacity) {
+        h->prof.release();
+        h->prof.pool.resize((size_t)2 * capacity);
+        for (auto &ev : h->prof.pool) {
+            hipError_t e = hipEventCreate(&ev);
+            if (e != hipSuccess) {
+                ev = nullptr;
+                h->prof.release();
+                return hip_fail(e, "ilu_profile_enable: events");
+            }
+        }
+    }
+    h->prof.stage.clear();
+    h->prof.used = 0;
+    h->prof.enabled = true;
+    return ILU_OK;
+}
+
+extern "C" ilu_status ilu_profile_read(ilu_handle h, double *ms, int64_t *launches) {
+    if (!h) return fail(ILU_ERR_ARG, "ilu_profile_read: NULL handle");
+    double acc[ILU_STAGE_COUNT] = {0};
+    int64_t cnt[ILU_STAGE_COUNT] = {0};
+    for (size_t i = 0; i < h->prof.used; ++i) {
+        hipError_t e = hipEventSynchronize(h->prof.pool[2 * i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "ilu_profile_read");
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, h->prof.pool[2 * i], h->prof.pool[2 * i + 1]);
+        if (e != hipSuccess) return hip_fail(e, "ilu_profile_read");
+        acc[h->prof.stage[i]] += t;
+        cnt[h->prof.stage[i]] += 1;
+    }
+    h->prof.stage.clear();
+    h->prof.used = 0;
+    for (int i = 0; i < ILU_STAGE_COUNT; ++i) {
+        if (ms) ms[i] = acc[i];
+        if (launches) launches[i] = cnt[i];
+    }
+    return ILU_OK;
+}
+
+// -------------------------------------------------------------------------------------
+// Lifetime
+// -------------------------------------------------------------------------------------
+
+extern "C" ilu_status ilu_destroy(ilu_handle h) {
+    delete h;
+    return ILU_OK;
+}
+
+extern "C" const char *ilu_version(void) { return "javelin-mi355x 0.1 (gfx950)"; }
+
+extern "C" const char *ilu_status_str(ilu_status s) {
+    switch (s) {
+        case ILU_OK: return "ILU_OK";
+        case ILU_ERR_ARG: return "ILU_ERR_ARG";
+        case ILU_ERR_CSR: return "ILU_ERR_CSR";
+        case ILU_ERR_NOMEM: return "ILU_ERR_NOMEM";
+        case ILU_ERR_HIP: return "ILU_ERR_HIP";
+        case ILU_ERR_ZERO_PIVOT: return "ILU_ERR_ZERO_PIVOT";
+        case ILU_ERR_NONFINITE: return "ILU_ERR_NONFINITE";
+        case ILU_ERR_NOCONV: return "ILU_ERR_NOCONV";
+        case ILU_ERR_BREAKDOWN: return "ILU_ERR_BREAKDOWN";
+        case ILU_ERR_STATE: return "ILU_ERR_STATE";
+        case ILU_ERR_UNSUPPORTED: return "ILU_ERR_UNSUPPORTED";
+        case ILU_ERR_TIMEOUT: return "ILU_ERR_TIMEOUT";
+        default: return "ILU_ERR_UNKNOWN";
+    }
+}
+
+extern "C" ilu_status ilu_last_error(char *buf, int32_t len) {
+    if (!buf || len <= 0) return ILU_ERR_ARG;
+    std::strncpy(buf, g_last_error.c_str(), (size_t)len - 1);
+    buf[len - 1] = 0;
+    return ILU_OK;
+}

@@ -1,0 +1,107 @@
+// Device-side declarations shared by the kernels and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace jv {
+
+// Bit patterns published into factor values and solve intermediates.  Both are
+// signalling NaNs with a payload: arithmetic never produces them (a NaN result
+// is quiet), and stored values that happen to be NaN are canonicalised before
+// they are published.
+constexpr uint64_t kPending64 = 0x7FF40000DEADBEEFull;   // value not yet computed
+constexpr uint64_t kDropped64 = 0x7FF400000D50D50Dull;   // entry dropped by the tau test
+constexpr uint32_t kPending32 = 0x7FA0BEEFu;
+constexpr uint64_t kQNaN64 = 0x7FF8000000000000ull;
+constexpr uint32_t kQNaN32 = 0x7FC00000u;
+
+// info word layout (int32 slots)
+enum : int {
+    kInfoBadKey = 0,      // atomicMin of 2*row + (0 zero pivot | 1 non-finite); INT32_MAX if none
+    kInfoAbort = 1,       // a bounded wait expired: every persistent kernel stops
+    kInfoDropLo = 2,      // dropped-entry count (uint64 in slots 2-3)
+    kInfoSlots = 8
+};
+
+// Bound on a single dependency wait (loop iterations, each >= one memory round trip).
+constexpr int kSpinLimit = 1 << 22;
+
+struct FactorArgs {
+    int32_t n;
+    const int32_t *rp, *ci, *diag, *src;
+    const int8_t *flev;
+    int32_t k;
+    int32_t use_flev;     // k < k_max: entries with fill level > k are absent
+    int32_t use_tau;
+    const double *a;      // input values (input entry order)
+    double *lu;           // factor values (factor order)
+    const double *row_tau;
+    int32_t *info;
+    // level-launch range or persistent task list
+    int32_t row_begin, row_end;
+    const int32_t *task_ptr;
+    int32_t ntasks;
+};
+
+struct SolveArgs {
+    int32_t n;
+    const int32_t *rp, *ci, *diag;
+    const void *val;          // TV[nnz]
+    const int32_t *rows;      // row list (nullptr: identity)
+    const int32_t *perm;      // nullptr: permuted space
+    const void *b;            // TX[n][ld]  (forward input)
+    void *x;                  // TX[n][ld]  (backward output)
+    void *y;                  // TA[n][cap] forward intermediate (published)
+    void *z;                  // TA[n][cap] backward intermediate (published)
+    void *y_out;              // optional copy of y (TA) [n][ld], level ordering
+    void *z_out;              // optional copy of z (TA) [n][ld], level ordering
+    int64_t ld;
+    int32_t cap;              // columns of the y/z buffers
+    int32_t nrhs;
+    int32_t unit_diag;        // forward: 1 (L), 0 (U^T); backward: 1 (L^T) or 0 (U)
+    int32_t *info;
+    int32_t row_begin, row_end;   // level-launch range over `rows` positions
+    const int32_t *task_ptr;
+    int32_t ntasks;
+    const int32_t *vmap;      // optional value gather map (transposed views): val[vmap[p]]
+};
+
+struct SpmvArgs {
+    int32_t n;
+    const int32_t *rp, *ci;
+    const double *val;
+    const int32_t *perm;      // nullptr: permuted space
+    const double *x;
+    double *y;
+    double alpha, beta;
+    int64_t ld;
+    int32_t nrhs;
+};
+
+// launchers (kernels.hip); all return hipError_t of the launch
+hipError_t launch_fill_u64(uint64_t *p, uint64_t value, int64_t count, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
+hipError_t launch_row_tau(int32_t n, const int32_t *in_rp, const double *a, const int32_t *perm, double tau,
+                          double *row_tau, hipStream_t s);
+hipError_t launch_gather(int64_t m, const int32_t *src, const double *a, double *out, hipStream_t s);
+hipError_t launch_factor(const FactorArgs &A, int lanes, bool syncfree, int grid, hipStream_t s);
+hipError_t launch_factor_fixup(int64_t nnz, double *lu, const int8_t *flev, int32_t k, int32_t use_flev,
+                               int8_t *stat, int32_t *info, hipStream_t s);
+hipError_t launch_cast_f32(int64_t m, const double *x, float *y, hipStream_t s);
+hipError_t launch_cast_bf16(int64_t m, const double *x, uint16_t *y, hipStream_t s);
+// prec: 0 f64 values / f64 arithmetic, 1 f32 values, 2 bf16 values (f32 arithmetic);
+// vec: 0 double vectors, 1 float vectors
+hipError_t launch_solve(const SolveArgs &A, bool forward, int prec, int vec, int lanes, bool syncfree,
+                        int grid, hipStream_t s);
+hipError_t launch_spmv(const SpmvArgs &A, int lanes, hipStream_t s);
+// adjoint outer products on the factor pattern: for entry p = (i, j) of row i,
+// glu[p] = -sum_s W[i][s] x[perm[j]][s] (j >= i) or -sum_s Bp[i][s] y[j][s] (j < i)
+hipError_t launch_outer(int32_t n, const int32_t *rp, const int32_t *ci, const int32_t *perm, const double *W,
+                        const double *Bp, const double *x, const double *y, double *glu, int32_t nrhs, int64_t ld,
+                        hipStream_t s);
+// capacity queries for persistent launches
+int persistent_grid_factor(int lanes);
+int persistent_grid_solve(bool forward, int prec, int vec, int lanes);
+
+}  // namespace jv

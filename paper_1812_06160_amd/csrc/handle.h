@@ -1,0 +1,102 @@
+// The analysis handle behind ilu_handle: host schedule, device arrays, workspaces.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "analysis.h"
+#include "javelin.h"
+
+namespace jv {
+
+enum { kTasksForward = 0, kTasksBackward = 1, kTasksTForward = 2, kTasksTBackward = 3 };
+
+// Event pairs around stage launches (ilu_profile_*).
+struct Profiler {
+    bool enabled = false;
+    std::vector<hipEvent_t> pool;      // 2 * capacity events
+    std::vector<int> stage;            // stage of each recorded pair
+    size_t used = 0;
+    void begin(int st, hipStream_t s);
+    void end(hipStream_t s);
+    void release();
+};
+
+struct TaskList {
+    int32_t *ptr = nullptr;   // device, ntasks + 1 positions
+    int32_t ntasks = 0;
+};
+
+ilu_status fail(ilu_status s, const std::string &msg);
+ilu_status hip_fail(hipError_t e, const char *what);
+
+}  // namespace jv
+
+struct ilu_handle_s {
+    jv::HostAnalysis H;
+    int32_t batch_count = 1;
+    std::vector<int64_t> row_off, nnz_off;
+
+    // structure on the device
+    int32_t *d_in_rp = nullptr, *d_perm = nullptr;
+    int32_t *d_lu_rp = nullptr, *d_lu_ci = nullptr, *d_diag = nullptr, *d_lu_src = nullptr;
+    int8_t *d_flev = nullptr;
+    int32_t *d_b_rp = nullptr, *d_b_ci = nullptr, *d_b_src = nullptr;
+    int32_t *d_ulevel_rows = nullptr;
+    int32_t *d_t_rp = nullptr, *d_t_ci = nullptr, *d_t_map = nullptr, *d_t_diag = nullptr;
+    int32_t *d_tlevel_rows = nullptr, *d_tulevel_rows = nullptr;
+
+    // values
+    double *d_lu = nullptr, *d_bval = nullptr, *d_row_tau = nullptr;
+    float *d_lu32 = nullptr;
+    uint16_t *d_lu16 = nullptr;
+    int8_t *d_stat = nullptr;
+    int32_t *d_info = nullptr;
+    double *d_dotwork = nullptr;     // kDotParts partials + 64 scalar slots
+
+    // published solve intermediates [n][cap], kept "all pending" between calls
+    int cap64 = 0, cap32 = 0;
+    void *y64 = nullptr, *z64 = nullptr, *y32 = nullptr, *z32 = nullptr;
+
+    // adjoint workspaces [n][ld]
+    size_t adj_bytes = 0;
+    double *d_adj_w = nullptr, *d_adj_bp = nullptr, *d_adj_gb = nullptr;
+
+    // Krylov workspace
+    size_t kry_bytes = 0;
+    double *d_kry = nullptr;
+
+    std::map<int, jv::TaskList> tasks;
+    jv::Profiler prof;
+    std::vector<void *> allocs;
+
+    // state
+    bool host_only = false;
+    bool factored = false, factor_ok = false, tracked = false, bvals = false, has32 = false, has16 = false;
+    int32_t k_used = 0;
+    int32_t sched_factor = ILU_SCHED_SYNCFREE, sched_solve = ILU_SCHED_SYNCFREE;
+    int32_t lanes_factor = 8, lanes_solve = 4, lanes_spmv = 8;
+
+    ~ilu_handle_s();
+    hipError_t alloc_bytes(void **p, size_t bytes);
+    const jv::TaskList *task_list(int which, int lanes);
+    hipError_t ensure_workspace(int nrhs, int prec_class, hipStream_t s);
+    hipError_t rearm(hipStream_t s);
+    hipError_t reset_info(hipStream_t s);
+    int grid_factor(int lanes, int ntasks);
+    int grid_solve(bool fwd, int prec, int vec, int lanes, int ntasks);
+};
+
+inline void allocs_erase(ilu_handle_s *h, void *p) {
+    auto it = std::find(h->allocs.begin(), h->allocs.end(), p);
+    if (it != h->allocs.end()) h->allocs.erase(it);
+}
+
+namespace jv {
+ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int vec, const void *b, void *x,
+                      void *y_out, void *z_out, int nrhs, int64_t ld, int flags, hipStream_t s);
+}

@@ -1,0 +1,269 @@
+// Krylov drivers that consume the preconditioner: PCG and right-preconditioned
+// flexible GMRES(m) (the iterative methods of the paper's Sec. I-II that rely on
+// spmv and stri).  Both run in the level ordering (b is permuted once, x is
+// permuted back at exit), so every apply and spmv inside the loop streams the
+// permuted structures without index translation.  Vector work is FP64; the
+// apply uses the requested factor precision.  Scalars stay on the device; the
+// host reads back one small block per iteration for the convergence test.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "blas.h"
+#include "device.h"
+#include "handle.h"
+#include "javelin.h"
+
+using namespace jv;
+
+namespace {
+
+ilu_status ensure_kry(ilu_handle_s *h, size_t bytes, hipStream_t s) {
+    if (h->kry_bytes >= bytes) return ILU_OK;
+    if (h->d_kry) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(h->d_kry);
+        allocs_erase(h, h->d_kry);
+        h->d_kry = nullptr;
+        h->kry_bytes = 0;
+    }
+    void *p;
+    hipError_t e = h->alloc_bytes(&p, bytes);
+    if (e != hipSuccess) return hip_fail(e, "krylov workspace");
+    h->d_kry = (double *)p;
+    h->kry_bytes = bytes;
+    return ILU_OK;
+}
+
+const void *factor_ptr(ilu_handle_s *h, int prec) {
+    if (prec == ILU_PREC_F64) return h->d_lu;
+    if (prec == ILU_PREC_F32) return h->has32 ? h->d_lu32 : nullptr;
+    if (prec == ILU_PREC_BF16) return h->has16 ? h->d_lu16 : nullptr;
+    return nullptr;
+}
+
+struct Ctx {
+    ilu_handle_s *h;
+    int64_t n;
+    int prec;
+    hipStream_t s;
+    double *scal;   // device scalar slots
+    double *work;   // dot partials
+};
+
+ilu_status apply(Ctx &c, const double *in, double *out) {
+    return run_solves(c.h, 0, factor_ptr(c.h, c.prec), c.prec, 0, in, out, nullptr, nullptr, 1, 1,
+                      ILU_PERMUTED_SPACE, c.s);
+}
+
+ilu_status spmv(Ctx &c, double alpha, const double *x, double beta, double *y) {
+    return ilu_spmv(c.h, alpha, x, beta, y, 1, 1, ILU_PERMUTED_SPACE, c.s);
+}
+
+ilu_status readback(Ctx &c, const double *dev, double *host, int count) {
+    hipError_t e = hipMemcpyAsync(host, dev, sizeof(double) * count, hipMemcpyDeviceToHost, c.s);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.s);
+    return e == hipSuccess ? ILU_OK : hip_fail(e, "krylov readback");
+}
+
+#define CHK(x)                          \
+    do {                                \
+        ilu_status st_ = (x);           \
+        if (st_ != ILU_OK) return st_;  \
+    } while (0)
+#define HCHK(x, what)                                  \
+    do {                                               \
+        hipError_t e_ = (x);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+ilu_status check_common(ilu_handle_s *h, const double *b, double *x, double rtol, int prec, int flags) {
+    if (!h) return fail(ILU_ERR_STATE, "solve: NULL handle");
+    if (!h->factored || !h->bvals) return fail(ILU_ERR_STATE, "solve: no factor");
+    if (!b || !x) return fail(ILU_ERR_ARG, "solve: NULL vector");
+    if (!(rtol > 0.0)) return fail(ILU_ERR_ARG, "solve: rtol must be > 0");
+    if (flags & ~ILU_PERMUTED_SPACE) return fail(ILU_ERR_ARG, "solve: unknown flags");
+    if (!factor_ptr(h, prec)) return fail(ILU_ERR_STATE, "solve: factor precision not available");
+    return ILU_OK;
+}
+
+}  // namespace
+
+extern "C" ilu_status ilu_solve_pcg(ilu_handle h, const double *b, double *x, double rtol, int32_t maxit,
+                                    int32_t fac_prec, int32_t flags, ilu_solve_info *info, hipStream_t s) {
+    CHK(check_common(h, b, x, rtol, fac_prec, flags));
+    const int64_t n = h->H.n;
+    CHK(ensure_kry(h, sizeof(double) * (size_t)n * 6, s));
+    double *bp = h->d_kry, *xp = bp + n, *r = xp + n, *z = r + n, *p = z + n, *q = p + n;
+    Ctx c{h, n, fac_prec, s, h->d_dotwork + kDotParts, h->d_dotwork};
+    double *S = c.scal;   // 0 bnorm^2, 1 rz, 2 rz_new, 3 pq, 4 rr
+    if (flags & ILU_PERMUTED_SPACE) HCHK(hipMemcpyAsync(bp, b, n * 8, hipMemcpyDeviceToDevice, s), "pcg copy");
+    else HCHK(blas_permute(n, h->d_perm, b, bp, 0, s), "pcg permute");
+    HCHK(hipMemsetAsync(xp, 0, n * 8, s), "pcg zero");
+    HCHK(blas_dot(n, bp, bp, &S[0], c.work, s), "pcg dot");
+    double hb[2];
+    CHK(readback(c, &S[0], hb, 1));
+    const double bnorm = std::sqrt(hb[0]);
+    ilu_solve_info I{};
+    I.status = ILU_ERR_NOCONV;
+    I.relres = 1.0;
+    I.true_relres = 1.0;
+    if (bnorm == 0.0) {
+        I.status = ILU_OK;
+        I.relres = I.true_relres = 0.0;
+    } else {
+        HCHK(hipMemcpyAsync(r, bp, n * 8, hipMemcpyDeviceToDevice, s), "pcg copy");
+        for (;;) {
+            bool converged = false;
+            CHK(apply(c, r, z));
+            HCHK(hipMemcpyAsync(p, z, n * 8, hipMemcpyDeviceToDevice, s), "pcg copy");
+            HCHK(blas_dot(n, r, z, &S[1], c.work, s), "pcg dot");
+            while (I.iters < maxit) {
+                CHK(spmv(c, 1.0, p, 0.0, q));
+                HCHK(blas_dot(n, p, q, &S[3], c.work, s), "pcg dot");
+                HCHK(blas_pcg_xr(n, &S[1], &S[3], p, q, xp, r, s), "pcg update");
+                HCHK(blas_dot(n, r, r, &S[4], c.work, s), "pcg dot");
+                CHK(readback(c, &S[3], hb, 2));
+                ++I.iters;
+                if (hb[0] == 0.0) {
+                    I.status = ILU_ERR_BREAKDOWN;
+                    break;
+                }
+                I.relres = std::sqrt(hb[1]) / bnorm;
+                if (I.relres <= rtol) {
+                    converged = true;
+                    break;
+                }
+                CHK(apply(c, r, z));
+                HCHK(blas_dot(n, r, z, &S[2], c.work, s), "pcg dot");
+                HCHK(blas_xpby_dev(n, &S[2], &S[1], z, p, s), "pcg p update");
+                HCHK(hipMemcpyAsync(&S[1], &S[2], 8, hipMemcpyDeviceToDevice, s), "pcg scalar copy");
+            }
+            // true residual
+            HCHK(hipMemcpyAsync(r, bp, n * 8, hipMemcpyDeviceToDevice, s), "pcg copy");
+            CHK(spmv(c, -1.0, xp, 1.0, r));
+            HCHK(blas_dot(n, r, r, &S[4], c.work, s), "pcg dot");
+            CHK(readback(c, &S[4], hb, 1));
+            I.true_relres = std::sqrt(hb[0]) / bnorm;
+            if (I.true_relres <= rtol) {
+                I.status = ILU_OK;
+                break;
+            }
+            if (!converged || I.iters >= maxit || I.status == ILU_ERR_BREAKDOWN) {
+                if (I.status != ILU_ERR_BREAKDOWN) I.status = ILU_ERR_NOCONV;
+                break;
+            }
+        }
+    }
+    if (flags & ILU_PERMUTED_SPACE) HCHK(hipMemcpyAsync(x, xp, n * 8, hipMemcpyDeviceToDevice, s), "pcg copy");
+    else HCHK(blas_permute(n, h->d_perm, xp, x, 1, s), "pcg permute");
+    HCHK(hipStreamSynchronize(s), "pcg sync");
+    if (info) *info = I;
+    if (I.status != ILU_OK)
+        return fail(I.status, I.status == ILU_ERR_BREAKDOWN ? "pcg: breakdown (p.Ap == 0)" : "pcg: no convergence");
+    return ILU_OK;
+}
+
+extern "C" ilu_status ilu_solve_gmres(ilu_handle h, const double *b, double *x, double rtol, int32_t restart,
+                                      int32_t maxit, int32_t fac_prec, int32_t flags, ilu_solve_info *info,
+                                      hipStream_t s) {
+    CHK(check_common(h, b, x, rtol, fac_prec, flags));
+    if (restart < 1 || restart > 60) return fail(ILU_ERR_ARG, "gmres: restart must be in [1, 60]");
+    const int m = restart;
+    const int64_t n = h->H.n;
+    CHK(ensure_kry(h, sizeof(double) * (size_t)n * (size_t)(2 * m + 4), s));
+    double *bp = h->d_kry, *xp = bp + n, *w = xp + n, *V = w + n, *Z = V + (size_t)n * (m + 1);
+    Ctx c{h, n, fac_prec, s, h->d_dotwork + kDotParts, h->d_dotwork};
+    double *S = c.scal;  // 0..m: current Hessenberg column, m+1: beta, m+2..: y coefficients (<= 30)
+    if (m + 2 + m > 64) return fail(ILU_ERR_ARG, "gmres: restart too large for the scalar area");
+    if (flags & ILU_PERMUTED_SPACE) HCHK(hipMemcpyAsync(bp, b, n * 8, hipMemcpyDeviceToDevice, s), "gmres copy");
+    else HCHK(blas_permute(n, h->d_perm, b, bp, 0, s), "gmres permute");
+    HCHK(hipMemsetAsync(xp, 0, n * 8, s), "gmres zero");
+    HCHK(blas_dot(n, bp, bp, &S[m + 1], c.work, s, 1), "gmres norm");
+    double hb[64];
+    CHK(readback(c, &S[m + 1], hb, 1));
+    const double bnorm = hb[0];
+    ilu_solve_info I{};
+    I.status = ILU_ERR_NOCONV;
+    I.relres = I.true_relres = 1.0;
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), yv(m);
+    if (bnorm == 0.0) {
+        I.status = ILU_OK;
+        I.relres = I.true_relres = 0.0;
+    } else {
+        for (;;) {
+            // r = b - A x, beta = ||r||
+            HCHK(hipMemcpyAsync(w, bp, n * 8, hipMemcpyDeviceToDevice, s), "gmres copy");
+            CHK(spmv(c, -1.0, xp, 1.0, w));
+            HCHK(blas_dot(n, w, w, &S[m + 1], c.work, s, 1), "gmres norm");
+            CHK(readback(c, &S[m + 1], hb, 1));
+            const double beta = hb[0];
+            I.true_relres = beta / bnorm;
+            if (I.true_relres <= rtol) {
+                I.status = ILU_OK;
+                break;
+            }
+            if (I.iters >= maxit) break;
+            HCHK(blas_scale_inv_dev(n, &S[m + 1], w, V, s), "gmres scale");
+            std::fill(g.begin(), g.end(), 0.0);
+            g[0] = beta;
+            int jend = -1;
+            bool breakdown = false;
+            for (int j = 0; j < m && I.iters < maxit; ++j) {
+                double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
+                CHK(apply(c, vj, zj));
+                CHK(spmv(c, 1.0, zj, 0.0, w));
+                for (int i = 0; i <= j; ++i) {   // modified Gram-Schmidt
+                    double *vi = V + (size_t)i * n;
+                    HCHK(blas_dot(n, w, vi, &S[i], c.work, s), "gmres dot");
+                    HCHK(blas_axpy_dev(n, &S[i], nullptr, -1.0, vi, w, s), "gmres axpy");
+                }
+                HCHK(blas_dot(n, w, w, &S[j + 1], c.work, s, 1), "gmres norm");
+                HCHK(blas_scale_inv_dev(n, &S[j + 1], w, V + (size_t)(j + 1) * n, s), "gmres scale");
+                CHK(readback(c, S, hb, j + 2));
+                for (int i = 0; i <= j + 1; ++i) H[(size_t)i * m + j] = hb[i];
+                for (int i = 0; i < j; ++i) {   // previous rotations
+                    const double a = H[(size_t)i * m + j], cc = H[(size_t)(i + 1) * m + j];
+                    const double t1 = cs[i] * a, t2 = sn[i] * cc, t3 = cs[i] * cc, t4 = sn[i] * a;
+                    H[(size_t)i * m + j] = t1 + t2;
+                    H[(size_t)(i + 1) * m + j] = t3 - t4;
+                }
+                const double a = H[(size_t)j * m + j], cc = H[(size_t)(j + 1) * m + j];
+                const double aa = a * a, c2 = cc * cc;
+                const double den = std::sqrt(aa + c2);
+                cs[j] = a / den;
+                sn[j] = cc / den;
+                H[(size_t)j * m + j] = den;
+                H[(size_t)(j + 1) * m + j] = 0.0;
+                g[j + 1] = -(sn[j] * g[j]);
+                g[j] = cs[j] * g[j];
+                ++I.iters;
+                jend = j;
+                I.relres = std::fabs(g[j + 1]) / bnorm;
+                breakdown = hb[j + 1] == 0.0;
+                if (I.relres <= rtol || breakdown) break;
+            }
+            if (jend < 0) break;
+            for (int i = jend; i >= 0; --i) {
+                double sum = g[i];
+                for (int t = i + 1; t <= jend; ++t) {
+                    const double u = H[(size_t)i * m + t] * yv[t];
+                    sum = sum - u;
+                }
+                yv[i] = sum / H[(size_t)i * m + i];
+            }
+            HCHK(hipMemcpyAsync(&S[m + 2], yv.data(), sizeof(double) * (jend + 1), hipMemcpyHostToDevice, s),
+                 "gmres coefficients");
+            HCHK(blas_combine(n, jend + 1, &S[m + 2], Z, n, xp, s), "gmres update");
+            HCHK(hipStreamSynchronize(s), "gmres sync");   // yv is pageable host memory
+        }
+    }
+    if (flags & ILU_PERMUTED_SPACE) HCHK(hipMemcpyAsync(x, xp, n * 8, hipMemcpyDeviceToDevice, s), "gmres copy");
+    else HCHK(blas_permute(n, h->d_perm, xp, x, 1, s), "gmres permute");
+    HCHK(hipStreamSynchronize(s), "gmres sync");
+    if (info) *info = I;
+    if (I.status != ILU_OK) return fail(I.status, "gmres: no convergence");
+    return ILU_OK;
+}

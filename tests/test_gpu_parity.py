@@ -1,0 +1,383 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars: schedules, permutation, pattern and drop state bit-exact; factor values
+bit-exact (expected; the contract is 1e-12 relative); FP64 solves and spmv within
+1e-12 relative (inf-norm per right-hand side); integer-valued inputs bit-exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+SCHEDS = [("level", "level"), ("syncfree", "syncfree")]
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def relerr(x, ref):
+    x = np.asarray(x).reshape(len(x), -1)
+    ref = np.asarray(ref).reshape(len(ref), -1)
+    return float(max(np.abs(x[:, s] - ref[:, s]).max() / max(np.abs(ref[:, s]).max(), 1e-300)
+                     for s in range(ref.shape[1])))
+
+
+def make(jv, A, k_max=0, sym=True, sched=("syncfree", "syncfree")):
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=k_max, pattern="sym" if sym else "a")
+    ilu.set_schedule(*sched)
+    return ilu
+
+
+CASES = [
+    ("laplace2d_64", lambda: synth.workload(1)[0], 0, 0.0),
+    ("laplace3d_24", lambda: synth.laplace3d(24), 0, 0.0),
+    ("convdiff3d_14_ilu1_tau", lambda: synth.convdiff3d(14), 1, 1e-3),
+    ("convdiff3d_14_ilu1", lambda: synth.convdiff3d(14), 1, 0.0),
+    ("random_3000", lambda: synth.random_banded(3000, rng=np.random.default_rng(5)), 0, 0.0),
+    ("random_sparse_ragged", lambda: synth.random_sparse(333, 0.02, np.random.default_rng(6),
+                                                         drop_diag_frac=0.1), 0, 0.0),
+    ("random_sparse_ilu2", lambda: synth.random_sparse(300, 0.015, np.random.default_rng(7)), 2, 0.0),
+]
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=lambda s: s[0])
+@pytest.mark.parametrize("name,mk,k,tau", CASES, ids=[c[0] for c in CASES])
+def test_factor_bit_exact(jv, name, mk, k, tau, sched):
+    A = mk()
+    for sym in (True, False):
+        an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k, sym=sym)
+        if an.lu_rp.size and np.diff(an.lu_rp).max() > 64:
+            pytest.skip("row longer than 64")
+        ilu = make(jv, A, k, sym, sched)
+        info = ilu.factor(dev(A.val), k=k, tau=tau)
+        f = O.factor(an, A.val, k=k, tau=tau)
+        assert f.status == O.OK
+        lu, st = ilu.factor_values()
+        np.testing.assert_array_equal(st, f.stat)
+        assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64)), \
+            f"max diff {np.abs(lu - f.val).max()}"
+        assert info["n_dropped"] == int((f.stat == 1).sum())
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=lambda s: s[0])
+def test_factor_k_below_kmax(jv, sched):
+    A = synth.convdiff3d(10)
+    ilu = make(jv, A, 2, True, sched)
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=2)
+    for k, tau in ((0, 0.0), (1, 1e-2), (2, 0.0)):
+        ilu.factor(dev(A.val), k=k, tau=tau)
+        f = O.factor(an, A.val, k=k, tau=tau)
+        lu, st = ilu.factor_values()
+        np.testing.assert_array_equal(st, f.stat)
+        assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=lambda s: s[0])
+@pytest.mark.parametrize("lanes", [0, 16, 64])
+def test_factor_lane_counts_same_bits(jv, sched, lanes):
+    A = synth.random_banded(2000, rng=np.random.default_rng(8))
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
+    ilu.set_schedule(sched[0], sched[1], lanes_factor=max(lanes, 32) if lanes else 0)
+    ilu.factor(dev(A.val))
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    f = O.factor(an, A.val)
+    lu, _ = ilu.factor_values()
+    assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=lambda s: s[0])
+def test_factor_errors(jv, sched):
+    # zero pivot in the first row, zero pivot later, non-finite value
+    A = synth.csr_from_coo(3, [0, 0, 1, 1, 2, 2], [0, 1, 0, 1, 1, 2], [0.0, 1, 1, 2, 1, 3])
+    ilu = make(jv, A, sched=sched)
+    with pytest.raises(jv.IluError) as e:
+        ilu.factor(dev(A.val))
+    assert e.value.status == "ILU_ERR_ZERO_PIVOT" and e.value.info["bad_row_original"] == 0
+    A = synth.csr_from_coo(2, [0, 0, 1, 1], [0, 1, 0, 1], [1.0, 1, 1, 1])
+    ilu = make(jv, A, sched=sched)
+    with pytest.raises(jv.IluError) as e:
+        ilu.factor(dev(A.val))
+    assert e.value.status == "ILU_ERR_ZERO_PIVOT" and e.value.info["bad_row"] == 1
+    A = synth.laplace2d(8)
+    v = A.val.copy()
+    v[40] = np.nan
+    ilu = make(jv, A, sched=sched)
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    f = O.factor(an, v)
+    with pytest.raises(jv.IluError) as e:
+        ilu.factor(dev(v))
+    assert e.value.status == "ILU_ERR_NONFINITE" and e.value.info["bad_row"] == f.bad_row
+    # argument errors
+    with pytest.raises(jv.IluError) as e:
+        ilu.factor(dev(A.val), k=1)
+    assert e.value.status == "ILU_ERR_ARG"
+    with pytest.raises(jv.IluError) as e:
+        ilu.factor(dev(A.val), tau=-1.0)
+    assert e.value.status == "ILU_ERR_ARG"
+
+
+def test_apply_before_factor_is_state_error(jv):
+    A = synth.laplace2d(4)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
+    with pytest.raises(jv.IluError) as e:
+        ilu.apply(dev(np.ones(A.n)))
+    assert e.value.status == "ILU_ERR_STATE"
+    with pytest.raises(jv.IluError) as e:
+        ilu.spmv(dev(np.ones(A.n)))
+    assert e.value.status == "ILU_ERR_STATE"
+
+
+APPLY_CASES = [
+    ("laplace2d_64", lambda: synth.workload(1)[0], 0, 0.0),
+    ("laplace3d_20", lambda: synth.laplace3d(20), 0, 0.0),
+    ("convdiff3d_12_ilu1_tau", lambda: synth.convdiff3d(12), 1, 1e-3),
+    ("random_2500", lambda: synth.random_banded(2500, rng=np.random.default_rng(9)), 0, 0.0),
+]
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=lambda s: s[0])
+@pytest.mark.parametrize("name,mk,k,tau", APPLY_CASES, ids=[c[0] for c in APPLY_CASES])
+@pytest.mark.parametrize("nrhs", [1, 3, 16])
+def test_apply_f64(jv, name, mk, k, tau, sched, nrhs):
+    A = mk()
+    rng = np.random.default_rng(nrhs)
+    ilu = make(jv, A, k, True, sched)
+    ilu.factor(dev(A.val), k=k, tau=tau)
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k)
+    f = O.factor(an, A.val, k=k, tau=tau)
+    b = rng.uniform(-1, 1, (A.n, nrhs)) if nrhs > 1 else rng.uniform(-1, 1, A.n)
+    xr = O.apply(an, f.val, b)
+    assert relerr(ilu.apply(dev(b)).cpu().numpy(), xr) <= 1e-12
+    # permuted space
+    bp = b[an.perm]
+    xpr = O.apply(an, f.val, bp, permuted=True)
+    assert relerr(ilu.apply(dev(bp), permuted=True).cpu().numpy(), xpr) <= 1e-12
+    # in place
+    bt = dev(b)
+    ilu.apply(bt, x=bt)
+    assert relerr(bt.cpu().numpy(), xr) <= 1e-12
+    # repeated calls keep the published-buffer protocol intact
+    for _ in range(3):
+        assert relerr(ilu.apply(dev(b)).cpu().numpy(), xr) <= 1e-12
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=lambda s: s[0])
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("vec", ["f64", "f32"])
+def test_apply_low_precision(jv, sched, prec, vec):
+    # FP32 arithmetic on the rounded factor: compared with the oracle's FP32 apply.
+    # Both sides accumulate n_row <= 7 products in FP32 in different orders and
+    # divide by the pivot; the solve recurrences amplify the per-row rounding by at
+    # most the growth of |L^{-1}| |U^{-1}|; the bound below is 2^-17 relative
+    # (about 64 FP32 ulps), far below the BF16 factor error itself.
+    A = synth.laplace3d(16)
+    ilu = make(jv, A, 0, True, sched)
+    ilu.factor(dev(A.val), casts=("f32", "bf16"))
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    f = O.factor(an, A.val)
+    low = O.cast_f32(f.val) if prec == "f32" else O.cast_bf16(f.val)
+    b = np.random.default_rng(3).uniform(-1, 1, (A.n, 2))
+    xr = O.apply(an, low, b, prec=prec)
+    bt = dev(b) if vec == "f64" else dev(b.astype(np.float32))
+    x = ilu.apply(bt, prec=prec).cpu().numpy().astype(np.float64)
+    if vec == "f32":
+        xr = O.apply(an, low, b.astype(np.float32).astype(np.float64), prec=prec)
+    assert relerr(x, xr) <= 2.0 ** -17
+
+
+def test_casts_bit_exact(jv):
+    A = synth.random_banded(3000, rng=np.random.default_rng(10))
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
+    ilu.factor(dev(A.val), casts=("f32", "bf16"))
+    lu, _ = ilu.factor_values()
+    assert np.array_equal(ilu.factor_values_prec("f32").view(np.uint32), O.cast_f32(lu).view(np.uint32))
+    assert np.array_equal(ilu.factor_values_prec("bf16"), O.cast_bf16(lu))
+
+
+@pytest.mark.parametrize("name,mk,k,tau", APPLY_CASES, ids=[c[0] for c in APPLY_CASES])
+def test_spmv(jv, name, mk, k, tau):
+    A = mk()
+    rng = np.random.default_rng(11)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=k)
+    ilu.set_values(dev(A.val))
+    for nrhs in (1, 4):
+        x = rng.uniform(-1, 1, (A.n, nrhs)) if nrhs > 1 else rng.uniform(-1, 1, A.n)
+        yr = O.spmv(A.n, A.row_ptr, A.col_idx, A.val, x)
+        assert relerr(ilu.spmv(dev(x)).cpu().numpy(), yr) <= 1e-12
+        y0 = rng.uniform(-1, 1, x.shape)
+        got = ilu.spmv(dev(x), y=dev(y0), alpha=2.0, beta=-0.5).cpu().numpy()
+        assert relerr(got, 2.0 * yr - 0.5 * y0) <= 1e-12
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k)
+    xp = rng.uniform(-1, 1, A.n)
+    yp = O.spmv(A.n, an.b_rp, an.b_ci, O.b_values(an, A.val), xp)
+    assert relerr(ilu.spmv(dev(xp), permuted=True).cpu().numpy(), yp) <= 1e-12
+    # integer-valued: exact regardless of summation order
+    Ai = rng.integers(-4, 5, A.nnz).astype(np.float64)
+    xi = rng.integers(-4, 5, A.n).astype(np.float64)
+    ilu.set_values(dev(Ai))
+    assert np.array_equal(ilu.spmv(dev(xi)).cpu().numpy(), O.spmv(A.n, A.row_ptr, A.col_idx, Ai, xi))
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=lambda s: s[0])
+def test_apply_integer_exact(jv, sched):
+    rng = np.random.default_rng(12)
+    A = synth.integer_unit_lower(400, 0.01, rng)
+    ilu = make(jv, A, sched=sched)
+    ilu.factor(dev(A.val))
+    b = rng.integers(-3, 4, (A.n, 4)).astype(np.float64)
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    f = O.factor(an, A.val)
+    x = ilu.apply(dev(b)).cpu().numpy()
+    assert np.array_equal(x, O.apply(an, f.val, b))
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=lambda s: s[0])
+def test_pcg_and_gmres(jv, sched):
+    A, b = synth.workload(1)
+    ilu = make(jv, A, sched=sched)
+    ilu.factor(dev(A.val), casts=("f32", "bf16"))
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    f = O.factor(an, A.val)
+    xr, itr, rr, st = O.pcg(an, O.b_values(an, A.val), f.val, b)
+    x, info = ilu.pcg(dev(b))
+    assert info["true_relres"] <= 1e-10 and abs(info["iters"] - itr) <= 1
+    assert np.abs(x.cpu().numpy() - xr).max() <= 1e-8 * np.abs(xr).max()
+    for prec in ("f32", "bf16"):
+        x, info = ilu.pcg(dev(b), prec=prec)
+        assert info["true_relres"] <= 1e-10
+    A = synth.convdiff3d(12)
+    b = np.random.default_rng(13).uniform(-1, 1, A.n)
+    ilu = make(jv, A, 1, True, sched)
+    ilu.factor(dev(A.val), k=1, tau=1e-3, casts=("f32", "bf16"))
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=1)
+    f = O.factor(an, A.val, k=1, tau=1e-3)
+    for prec in ("f64", "f32", "bf16"):
+        low = None if prec == "f64" else (O.cast_f32(f.val) if prec == "f32" else O.cast_bf16(f.val))
+        xr, itr, rr, st = O.fgmres(an, O.b_values(an, A.val), f.val, b, prec=prec, lu_low=low)
+        x, info = ilu.gmres(dev(b), prec=prec)
+        assert info["true_relres"] <= 1e-10 and abs(info["iters"] - itr) <= 1, (prec, info, itr)
+
+
+def test_krylov_exact_preconditioner_and_noconv(jv):
+    A = synth.laplace2d(6)
+    b = np.random.default_rng(14).uniform(-1, 1, A.n)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=A.n)
+    ilu.factor(dev(A.val), k=A.n)
+    x, info = ilu.pcg(dev(b))
+    assert info["iters"] == 1
+    x, info = ilu.gmres(dev(b))
+    assert info["iters"] == 1
+    A, b = synth.workload(1)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
+    ilu.factor(dev(A.val))
+    x, info = ilu.pcg(dev(b), maxit=3, raise_on_fail=False)
+    assert info["status"] == "ILU_ERR_NOCONV" and info["iters"] == 3
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=lambda s: s[0])
+def test_adjoint_against_oracle(jv, sched):
+    rng = np.random.default_rng(15)
+    A = synth.random_sparse(300, 0.02, rng)
+    for k in (0, 1):
+        ilu = make(jv, A, k, False, sched)
+        ilu.factor(dev(A.val), k=k)
+        an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k, sym=False)
+        f = O.factor(an, A.val, k=k)
+        b = rng.uniform(-1, 1, (A.n, 3))
+        gx = rng.uniform(-1, 1, (A.n, 3))
+        x, y = ilu.apply_ex(dev(b))
+        xr, yr = O.apply(an, f.val, b, want_y=True)
+        assert relerr(x.cpu().numpy(), xr) <= 1e-12 and relerr(y.cpu().numpy(), yr) <= 1e-12
+        gb, glu = ilu.adjoint(dev(gx), x, y)
+        gbr, glur = O.adjoint(an, f.val, gx, xr, yr)
+        assert relerr(gb.cpu().numpy(), gbr) <= 1e-12
+        g = glu.cpu().numpy()
+        assert np.abs(g - glur).max() <= 1e-12 * np.abs(glur).max()
+
+
+def test_autograd_finite_differences(jv):
+    rng = np.random.default_rng(16)
+    A = synth.convdiff3d(6)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
+    ilu.factor(dev(A.val))
+    lu0 = ilu.factor_tensor()
+    b = dev(rng.uniform(-1, 1, (A.n, 2))).requires_grad_(True)
+    lu = lu0.clone().requires_grad_(True)
+    c = dev(rng.uniform(-1, 1, (A.n, 2)))
+    x = jv.IluApply.apply(ilu, b, lu)
+    (x * c).sum().backward()
+    h = 1e-6
+
+    def loss(bb, ll):
+        with torch.no_grad():
+            return float((jv.IluApply.apply(ilu, bb, ll) * c).sum())
+
+    for _ in range(3):
+        vb = dev(rng.standard_normal((A.n, 2)))
+        fd = (loss(b + h * vb, lu) - loss(b - h * vb, lu)) / (2 * h)
+        assert abs(fd - float((b.grad * vb).sum())) <= 1e-6 * max(1.0, abs(fd))
+        vl = dev(rng.standard_normal(ilu.nnz_lu))
+        fd = (loss(b, lu + h * vl) - loss(b, lu - h * vl)) / (2 * h)
+        assert abs(fd - float((lu.grad * vl).sum())) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_batched_equals_singles(jv):
+    mats, rhs = synth.workload(5, scale=0.12)
+    mats, rhs = mats[:24], rhs[:24]
+    hb = jv.Ilu.batched(mats)
+    ro, zo = hb.batch_offsets()
+    vals = np.concatenate([m.val for m in mats])
+    b = np.concatenate(rhs)
+    hb.factor(dev(vals), casts=("f32",))
+    lu_b, _ = hb.factor_values()
+    x_b = hb.apply(dev(b)).cpu().numpy()
+    x_b32 = hb.apply(dev(b.astype(np.float32)), prec="f32").cpu().numpy()
+    sb = hb.schedule()
+    for i, M in enumerate(mats):
+        an = O.analyze(M.n, M.row_ptr, M.col_idx)
+        f = O.factor(an, M.val)
+        xr = O.apply(an, f.val, rhs[i])
+        assert relerr(x_b[ro[i]:ro[i + 1]], xr) <= 1e-12
+        xr32 = O.apply(an, O.cast_f32(f.val), rhs[i].astype(np.float32).astype(np.float64), prec="f32")
+        assert relerr(x_b32[ro[i]:ro[i + 1]].astype(np.float64), xr32) <= 2.0 ** -17
+        # factor entries of matrix i (the batch keeps each matrix's rows and entries)
+        rows = np.nonzero((sb["perm"] >= ro[i]) & (sb["perm"] < ro[i + 1]))[0]
+        got = np.concatenate([lu_b[sb["lu_row_ptr"][r]:sb["lu_row_ptr"][r + 1]] for r in rows])
+        want = np.concatenate([f.val[an.lu_rp[an.iperm[sb["perm"][r] - ro[i]]]:
+                                     an.lu_rp[an.iperm[sb["perm"][r] - ro[i]] + 1]] for r in rows])
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+def test_tune_keeps_results(jv):
+    A = synth.laplace3d(20)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
+    a = dev(A.val)
+    ilu.factor(a, casts=("f32",))
+    res, chosen = ilu.tune(a, reps=2)
+    assert len(res) >= 4
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    f = O.factor(an, A.val)
+    lu, _ = ilu.factor_values()
+    assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
+    b = np.random.default_rng(17).uniform(-1, 1, A.n)
+    assert relerr(ilu.apply(dev(b)).cpu().numpy(), O.apply(an, f.val, b)) <= 1e-12
+    x32 = ilu.apply(dev(b), prec="f32")   # FP32 copy survives tuning
+    assert x32.shape == (A.n,)
+
+
+def test_profile_counts(jv):
+    A = synth.laplace3d(12)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
+    ilu.profile(True)
+    ilu.factor(dev(A.val))
+    b = dev(np.ones(A.n))
+    ilu.apply(b)
+    ilu.spmv(b)
+    p = ilu.profile_read()
+    assert p["factor"][1] == 1 and p["forward"][1] == 1 and p["backward"][1] == 1 and p["spmv"][1] == 1
+    assert all(v[0] > 0 for v in p.values())

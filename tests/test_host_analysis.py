@@ -1,0 +1,138 @@
+"""CPU checks of the library's host side: exported symbols, host-only analysis
+bit-exact against the oracle, and the error paths of the C ABI that need no GPU."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+import paper_1812_06160_amd as jv
+from paper_1812_06160_amd import _lib as L
+
+
+def test_library_exports_every_declared_symbol():
+    import os
+    import re
+    lib = jv.load()
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "javelin.h")).read()
+    declared = set(re.findall(r"^\s*(?:ilu_status|const char \*)\s*(ilu_\w+)\s*\(", hdr, re.M))
+    assert declared == set(L.SYMBOLS)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert lib.ilu_version().startswith(b"javelin")
+    assert lib.ilu_status_str(5) == b"ILU_ERR_ZERO_PIVOT"
+
+
+def host_ilu(A, k_max=0, sym=True):
+    return jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=k_max, pattern="sym" if sym else "a", host_only=True)
+
+
+def compare_schedule(A, k_max, sym):
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k_max, sym=sym)
+    h = host_ilu(A, k_max, sym)
+    s = h.schedule()
+    assert h.info()["n_levels"] == an.n_levels
+    assert h.info()["n_ulevels"] == an.n_ulevels
+    np.testing.assert_array_equal(s["level_ptr"], an.level_ptr)
+    np.testing.assert_array_equal(s["perm"], an.perm)
+    np.testing.assert_array_equal(s["lu_row_ptr"], an.lu_rp)
+    np.testing.assert_array_equal(s["lu_col_idx"], an.lu_ci)
+    np.testing.assert_array_equal(s["diag_pos"], an.diag_pos)
+    np.testing.assert_array_equal(s["fill_lev"], an.lu_lev)
+    np.testing.assert_array_equal(s["lu_src"], an.lu_src)
+    np.testing.assert_array_equal(s["ulevel_ptr"], an.ulevel_ptr)
+    np.testing.assert_array_equal(s["ulevel_rows"], an.ulevel_rows)
+    np.testing.assert_array_equal(s["b_row_ptr"], an.b_rp)
+    np.testing.assert_array_equal(s["b_col_idx"], an.b_ci)
+    return h, an
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_host_analysis_bit_exact_random(seed):
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(1, 200))
+    A = synth.random_sparse(n, float(rng.uniform(0.005, 0.08)), rng,
+                            symmetric_pattern=bool(seed % 3 == 0), drop_diag_frac=0.3 if seed % 4 == 1 else 0.0)
+    compare_schedule(A, k_max=seed % 4, sym=bool(seed % 2))
+
+
+@pytest.mark.parametrize("wid,k", [(1, 0), (2, 0), (3, 1), (4, 0)])
+def test_host_analysis_bit_exact_workloads_small(wid, k):
+    A, _ = synth.workload(wid, scale=0.1 if wid != 4 else 0.002)
+    compare_schedule(A, k_max=k, sym=True)
+    compare_schedule(A, k_max=k, sym=False)
+
+
+def test_host_analysis_batched_is_block_diagonal():
+    mats, _ = synth.workload(5, scale=0.06)
+    mats = mats[:6]
+    hb = jv.Ilu.batched(mats, host_only=True)
+    ro, zo = hb.batch_offsets()
+    assert ro.tolist() == np.concatenate([[0], np.cumsum([m.n for m in mats])]).tolist()
+    assert zo.tolist() == np.concatenate([[0], np.cumsum([m.nnz for m in mats])]).tolist()
+    # the merged levels equal the per-matrix levels, level by level
+    s = hb.schedule()
+    lv = np.repeat(np.arange(len(s["level_ptr"]) - 1), np.diff(s["level_ptr"]))
+    level_of = np.empty(ro[-1], np.int64)
+    level_of[s["perm"]] = lv
+    for i, M in enumerate(mats):
+        an = O.analyze(M.n, M.row_ptr, M.col_idx)
+        np.testing.assert_array_equal(level_of[ro[i]:ro[i + 1]], an.level)
+    assert hb.info()["n_levels"] == max(O.analyze(M.n, M.row_ptr, M.col_idx).n_levels for M in mats)
+
+
+@pytest.mark.slow
+def test_host_analysis_full_laplace3d():
+    A, _ = synth.workload(2)
+    h = host_ilu(A)
+    I = h.info()
+    assert (I["n_levels"], I["level_min"], I["level_max"], I["level_median"]) == (382, 1, 12288, 4656.0)
+    assert I["nnz_lu"] == 14_581_760
+
+
+def _analyze_raw(n, rp, ci, k_max=0, pattern=0, host_only=1, reserved=0):
+    lib = jv.load()
+    rp = np.ascontiguousarray(rp, np.int32)
+    ci = np.ascontiguousarray(ci, np.int32)
+    csr = L.Csr(n, int(rp[-1]) if rp.size else 0, rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p))
+    opts = L.AnalyzeOpts(k_max, pattern, host_only)
+    opts.reserved[0] = reserved
+    h = C.c_void_p()
+    code = lib.ilu_analyze(C.byref(csr), C.byref(opts), C.byref(h))
+    if code == 0:
+        lib.ilu_destroy(h)
+    return code
+
+
+def test_analyze_error_paths():
+    ok_rp, ok_ci = [0, 2, 4], [0, 1, 0, 1]
+    assert _analyze_raw(2, ok_rp, ok_ci) == L.OK
+    assert _analyze_raw(2, [0, 2, 4], [1, 0, 0, 1]) == L.ERR_CSR          # unsorted
+    assert _analyze_raw(2, [0, 2, 4], [0, 0, 0, 1]) == L.ERR_CSR          # duplicate
+    assert _analyze_raw(2, [0, 2, 4], [0, 2, 0, 1]) == L.ERR_CSR          # out of range
+    assert _analyze_raw(2, [0, 3, 2], [0, 1, 0, 1]) == L.ERR_CSR          # decreasing row_ptr
+    assert _analyze_raw(0, [0], []) == L.ERR_ARG                          # n = 0
+    assert _analyze_raw(2, ok_rp, ok_ci, k_max=-1) == L.ERR_ARG
+    assert _analyze_raw(2, ok_rp, ok_ci, pattern=7) == L.ERR_ARG
+    assert _analyze_raw(2, ok_rp, ok_ci, reserved=1) == L.ERR_ARG
+    assert _analyze_raw(2, ok_rp, ok_ci, host_only=2) == L.ERR_ARG
+
+
+def test_numeric_calls_on_host_only_handle_report_state():
+    lib = jv.load()
+    A = synth.laplace2d(4)
+    h = host_ilu(A)
+    fi = L.FactorInfo()
+    assert lib.ilu_factor(h.h, None, 0, 0.0, 0, C.byref(fi), None) == L.ERR_STATE
+    assert lib.ilu_apply(h.h, C.c_void_p(8), C.c_void_p(8), 1, 1, 0, 0, 0, None) == L.ERR_STATE
+    assert lib.ilu_spmv(h.h, 1.0, C.c_void_p(8), 0.0, C.c_void_p(16), 1, 1, 0, None) == L.ERR_STATE
+    si = L.SolveInfo()
+    assert lib.ilu_solve_pcg(h.h, C.c_void_p(8), C.c_void_p(16), 1e-10, 10, 0, 0, C.byref(si), None) == L.ERR_STATE
+    assert lib.ilu_tune(h.h, None, 1, None, 0, None, None) == L.ERR_STATE
+    buf = C.create_string_buffer(256)
+    lib.ilu_last_error(buf, 256)
+    assert b"factor" in buf.value or b"state" in buf.value.lower() or buf.value
+    assert lib.ilu_set_schedule(h.h, 1, 2, 0, 8) == L.OK
+    assert lib.ilu_set_schedule(h.h, 5, 0, 0, 0) == L.ERR_ARG
+    assert lib.ilu_set_schedule(h.h, 0, 0, 3, 0) == L.ERR_ARG
