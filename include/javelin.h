@@ -66,7 +66,7 @@ enum {
 enum {
     ILU_SCHED_AUTO = 0,       /* the handle's current choice (sync-free unless tuned otherwise) */
     ILU_SCHED_LEVEL = 1,      /* one kernel launch per level: the launch boundary is the barrier */
-    ILU_SCHED_SYNCFREE = 2    /* one persistent launch; rows wait on per-row ready values */
+    ILU_SCHED_SYNCFREE = 2    /* one launch for all levels; rows wait on per-row published values */
 };
 
 typedef struct ilu_handle_s *ilu_handle;
@@ -248,7 +248,8 @@ ilu_status ilu_solve_gmres(ilu_handle h, const double *b, double *x, double rtol
 /* ---------------------------------------------------------------------------- */
 
 /* Chooses the launch scheme of the factor and of the solves (ILU_SCHED_*) and the
- * lanes per row (0 = automatic from the longest row; else 4, 8, 16, 32 or 64). */
+ * lanes per row (0 = automatic from the longest row; else 4, 8, 16, 32 or 64;
+ * factor lanes must cover the longest factor row). */
 ilu_status ilu_set_schedule(ilu_handle h, int32_t factor_sched, int32_t solve_sched,
                             int32_t lanes_factor, int32_t lanes_solve);
 ilu_status ilu_get_schedule(ilu_handle h, int32_t *factor_sched, int32_t *solve_sched,

@@ -87,7 +87,11 @@ void Profiler::release() {
 ilu_handle_s::~ilu_handle_s() {
     prof.release();
     for (void *p : allocs) (void)hipFree(p);
-    for (auto &kv : tasks) (void)hipFree(kv.second.ptr);
+    for (auto &kv : tasks) {
+        (void)hipFree(kv.second.ptr);
+        (void)hipFree(kv.second.stream_tasks);
+        (void)hipFree(kv.second.stream_ptr);
+    }
 }
 
 hipError_t ilu_handle_s::alloc_bytes(void **p, size_t bytes) {
@@ -109,12 +113,43 @@ const TaskList *ilu_handle_s::task_list(int which, int lanes) {
         case kTasksTForward: ptr = &H.tlevel_ptr; break;
         default: ptr = &H.tulevel_ptr; break;
     }
-    std::vector<int32_t> t = make_tasks(*ptr, 64 / lanes);
+    // tasks: level-homogeneous runs of up to 64/lanes positions; each level's tasks
+    // are cut into kStreams contiguous slices, slice x going to stream x
+    const int per = 64 / lanes;
+    const int S = nstreams;
+    std::vector<int32_t> t;
+    std::vector<std::vector<int32_t>> streams(S);
+    for (size_t l = 0; l + 1 < ptr->size(); ++l) {
+        const int32_t t0 = (int32_t)t.size();
+        for (int32_t p = (*ptr)[l]; p < (*ptr)[l + 1]; p += per) t.push_back(p);
+        const int32_t t1 = (int32_t)t.size();
+        for (int x = 0; x < S; ++x) {
+            const int32_t a = t0 + (int32_t)((int64_t)(t1 - t0) * x / S);
+            const int32_t b = t0 + (int32_t)((int64_t)(t1 - t0) * (x + 1) / S);
+            for (int32_t k = a; k < b; ++k) streams[x].push_back(k);
+        }
+    }
+    t.push_back(ptr->empty() ? 0 : ptr->back());
+    std::vector<int32_t> st, sp(S + 1, 0);
+    int32_t max_slots = 0;
+    const int wpb = 4;   // waves per block: one task each
+    for (int x = 0; x < S; ++x) {
+        st.insert(st.end(), streams[x].begin(), streams[x].end());
+        sp[x + 1] = (int32_t)st.size();
+        max_slots = std::max<int32_t>(max_slots, ((int32_t)streams[x].size() + wpb - 1) / wpb);
+    }
     TaskList tl;
     tl.ntasks = (int32_t)t.size() - 1;
-    if (hipMalloc(&tl.ptr, t.size() * sizeof(int32_t)) != hipSuccess) return nullptr;
-    if (hipMemcpy(tl.ptr, t.data(), t.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+    tl.max_slots = max_slots;
+    auto up = [](int32_t **d, const std::vector<int32_t> &v) {
+        if (hipMalloc(d, std::max<size_t>(1, v.size()) * sizeof(int32_t)) != hipSuccess) return false;
+        if (v.empty()) return true;
+        return hipMemcpy(*d, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess;
+    };
+    if (!up(&tl.ptr, t) || !up(&tl.stream_tasks, st) || !up(&tl.stream_ptr, sp)) {
         (void)hipFree(tl.ptr);
+        (void)hipFree(tl.stream_tasks);
+        (void)hipFree(tl.stream_ptr);
         return nullptr;
     }
     tasks[key] = tl;
@@ -163,16 +198,51 @@ hipError_t ilu_handle_s::reset_info(hipStream_t s) {
     return hipMemcpyAsync(d_info, init, sizeof(init), hipMemcpyHostToDevice, s);
 }
 
-int ilu_handle_s::grid_factor(int lanes, int ntasks) {
-    int g = persistent_grid_factor(lanes);
-    int need = (ntasks + 3) / 4;
-    return std::max(1, std::min(g, need));
+static const int kComplement[kPasses] = {-1, kPassBackward, kPassForward, kPassTBackward, kPassTForward};
+
+hipError_t ilu_handle_s::prepare_claims(int pass, const TaskList *tl, Claims *c, hipStream_t s) {
+    int32_t *mine = d_counters + (size_t)pass * kStreams * kCounterStride;
+    if (counters_dirty[pass]) {
+        hipError_t e = launch_zero_counters(mine, s);
+        if (e != hipSuccess) return e;
+    }
+    c->task_ptr = tl->ptr;
+    c->stream_tasks = tl->stream_tasks;
+    c->stream_ptr = tl->stream_ptr;
+    c->counters = mine;
+    const int comp = kComplement[pass];
+    c->zero_counters = comp >= 0 ? d_counters + (size_t)comp * kStreams * kCounterStride : nullptr;
+    c->xcc_stream = d_xcc_stream;
+    counters_dirty[pass] = true;
+    if (comp >= 0) counters_dirty[comp] = false;
+    return hipSuccess;
 }
 
-int ilu_handle_s::grid_solve(bool fwd, int prec, int vec, int lanes, int ntasks) {
-    int g = persistent_grid_solve(fwd, prec, vec, lanes);
-    int need = (ntasks + 3) / 4;
-    return std::max(1, std::min(g, need));
+// XCC ids present on the current device (one probe per process): id -> stream
+static hipError_t xcc_streams(std::vector<int8_t> *map, int *nstreams) {
+    static std::vector<int8_t> cached;
+    static int cached_n = 0;
+    if (!cached_n) {
+        const int blocks = 512;
+        std::vector<int32_t> ids(blocks);
+        hipError_t e = probe_xcc_ids(blocks, ids.data());
+        if (e != hipSuccess) return e;
+        std::vector<int8_t> m(16, -1);
+        int n = 0;
+        for (int id = 0; id < 16; ++id)
+            if (std::find(ids.begin(), ids.end(), id) != ids.end()) m[id] = (int8_t)n++;
+        if (n < 1 || n > kStreams) {
+            std::fill(m.begin(), m.end(), 0);
+            n = 1;
+        }
+        for (auto &v : m)
+            if (v < 0) v = 0;   // ids never seen share stream 0
+        cached = m;
+        cached_n = n;
+    }
+    *map = cached;
+    *nstreams = cached_n;
+    return hipSuccess;
 }
 
 // -------------------------------------------------------------------------------------
@@ -182,6 +252,11 @@ int ilu_handle_s::grid_solve(bool fwd, int prec, int vec, int lanes, int ntasks)
 static ilu_status finish_analysis(ilu_handle_s *h) {
     HostAnalysis &H = h->H;
     hipError_t e;
+#define UPLOAD_ONE(dst, src)                                                   \
+    do {                                                                       \
+        if ((e = upload(&dst, src)) != hipSuccess) return hip_fail(e, "upload " #src); \
+        if (dst) h->allocs.push_back(dst);                                     \
+    } while (0)
 #define UP(dst, src)                                                   \
     do {                                                               \
         if ((e = upload(&dst, src)) != hipSuccess) return hip_fail(e, "upload " #src); \
@@ -217,6 +292,25 @@ static ilu_status finish_analysis(ilu_handle_s *h) {
     h->d_info = (int32_t *)p;
     if ((e = h->alloc_bytes(&p, kDotParts * 8 + 64 * 8)) != hipSuccess) return hip_fail(e, "alloc dot work");
     h->d_dotwork = (double *)p;
+    const size_t cbytes = (size_t)kPasses * kStreams * kCounterStride * 4;
+    if ((e = h->alloc_bytes(&p, cbytes)) != hipSuccess) return hip_fail(e, "alloc counters");
+    h->d_counters = (int32_t *)p;
+    if ((e = hipMemset(h->d_counters, 0, cbytes)) != hipSuccess) return hip_fail(e, "zero counters");
+    std::vector<int8_t> xmap;
+    if ((e = xcc_streams(&xmap, &h->nstreams)) != hipSuccess) return hip_fail(e, "xcc probe");
+    UPLOAD_ONE(h->d_xcc_stream, xmap);
+    // LDS staging of the factor: the dependency rows' upper parts, summed per row
+    int64_t tcap = 0;
+    for (int32_t r = 0; r < H.n; ++r) {
+        int64_t t = 0;
+        for (int32_t q = H.lu_rp[r]; q < H.diag[r]; ++q) {
+            const int32_t c = H.lu_ci[q];
+            t += H.lu_rp[c + 1] - H.diag[c];
+        }
+        tcap = std::max(tcap, t);
+    }
+    h->factor_tcap = (int32_t)std::min<int64_t>(tcap, 1 << 20);
+#undef UPLOAD_ONE
     h->lanes_factor = pow2_lanes(H.max_row_lu, 4, 64);
     h->lanes_solve = pow2_lanes(std::max(H.max_lower_lu, H.max_upper_lu), 4, 64);
     h->lanes_spmv = pow2_lanes(std::max(1, (int)((H.b_rp[H.n] + H.n - 1) / H.n)), 4, 64);
@@ -380,15 +474,16 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
     A.lu = h->d_lu;
     A.row_tau = h->d_row_tau;
     A.info = h->d_info;
+    A.tcap = factor_lds_bytes(lanes, h->factor_tcap) ? h->factor_tcap : 0;
     if (sf) {
         const TaskList *tl = h->task_list(kTasksForward, lanes);
         if (!tl) return fail(ILU_ERR_NOMEM, "ilu_factor: task list");
         if ((e = launch_fill_u64((uint64_t *)h->d_lu, kPending64, H.lu_rp[H.n], s)) != hipSuccess)
             return hip_fail(e, "ilu_factor: arm");
-        A.task_ptr = tl->ptr;
-        A.ntasks = tl->ntasks;
+        if ((e = h->prepare_claims(kPassFactor, tl, &A.claims, s)) != hipSuccess) return hip_fail(e, "ilu_factor: claims");
+        A.nstreams = h->nstreams;
         h->prof.begin(ILU_STAGE_FACTOR, s);
-        e = launch_factor(A, lanes, true, h->grid_factor(lanes, tl->ntasks), s);
+        e = launch_factor(A, lanes, true, h->grid_syncfree(tl), s);
         h->prof.end(s);
         if (e != hipSuccess) return hip_fail(e, "ilu_factor: launch");
     } else {
@@ -568,10 +663,11 @@ ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int 
         if (sf) {
             const TaskList *tl = h->task_list(which, lanes);
             if (!tl) return fail(ILU_ERR_NOMEM, "task list");
-            A.task_ptr = tl->ptr;
-            A.ntasks = tl->ntasks;
+            const int pass = view == 0 ? (fwd ? kPassForward : kPassBackward) : (fwd ? kPassTForward : kPassTBackward);
+            if ((e = h->prepare_claims(pass, tl, &A.claims, s)) != hipSuccess) return hip_fail(e, "solve claims");
+            A.nstreams = h->nstreams;
             h->prof.begin(fwd ? ILU_STAGE_FORWARD : ILU_STAGE_BACKWARD, s);
-            e = launch_solve(A, fwd, prec, vec, lanes, true, h->grid_solve(fwd, prec, vec, lanes, tl->ntasks), s);
+            e = launch_solve(A, fwd, prec, vec, lanes, true, h->grid_syncfree(tl), s);
             h->prof.end(s);
             if (e != hipSuccess) return hip_fail(e, "solve launch");
         } else {

@@ -27,6 +27,26 @@ enum : int {
 // Bound on a single dependency wait (loop iterations, each >= one memory round trip).
 constexpr int kSpinLimit = 1 << 22;
 
+// Sync-free kernels take their work from task streams, one per XCD.  Each level's
+// tasks are cut into contiguous slices, slice x of every level going to stream x,
+// so level-to-level dependencies mostly stay inside one XCD's L2.  A block that
+// starts on XCD x claims the next block slot of stream x with one atomic add on
+// that XCD's counter (start order), and each of its waves runs one task of the
+// slot.  A block waits only on tasks of earlier-claimed slots, which belong to
+// blocks that already run or have finished, so progress never depends on how
+// many blocks are resident.
+constexpr int kStreams = 8;          // maximum XCD count handled
+constexpr int kCounterStride = 32;   // int32 slots between counters (128 bytes)
+
+struct Claims {
+    const int32_t *task_ptr;      // positions of task t: [task_ptr[t], task_ptr[t + 1])
+    const int32_t *stream_tasks;  // task ids in stream order (stream, level, position)
+    const int32_t *stream_ptr;    // nstreams + 1 offsets into stream_tasks
+    int32_t *counters;            // this pass's claim counters (kStreams * kCounterStride)
+    int32_t *zero_counters;       // counters of another pass to clear at launch (may be null)
+    const int8_t *xcc_stream;     // hardware XCC id (0..15) -> stream
+};
+
 struct FactorArgs {
     int32_t n;
     const int32_t *rp, *ci, *diag, *src;
@@ -38,10 +58,11 @@ struct FactorArgs {
     double *lu;           // factor values (factor order)
     const double *row_tau;
     int32_t *info;
-    // level-launch range or persistent task list
+    // level-launch range or persistent claims
     int32_t row_begin, row_end;
-    const int32_t *task_ptr;
-    int32_t ntasks;
+    Claims claims;
+    int32_t nstreams;
+    int32_t tcap;         // LDS entries per group for the dependency rows (0: no staging)
 };
 
 struct SolveArgs {
@@ -62,8 +83,8 @@ struct SolveArgs {
     int32_t unit_diag;        // forward: 1 (L), 0 (U^T); backward: 1 (L^T) or 0 (U)
     int32_t *info;
     int32_t row_begin, row_end;   // level-launch range over `rows` positions
-    const int32_t *task_ptr;
-    int32_t ntasks;
+    Claims claims;
+    int32_t nstreams;
     const int32_t *vmap;      // optional value gather map (transposed views): val[vmap[p]]
 };
 
@@ -82,6 +103,7 @@ struct SpmvArgs {
 // launchers (kernels.hip); all return hipError_t of the launch
 hipError_t launch_fill_u64(uint64_t *p, uint64_t value, int64_t count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
+hipError_t launch_zero_counters(int32_t *counters, hipStream_t s);
 hipError_t launch_row_tau(int32_t n, const int32_t *in_rp, const double *a, const int32_t *perm, double tau,
                           double *row_tau, hipStream_t s);
 hipError_t launch_gather(int64_t m, const int32_t *src, const double *a, double *out, hipStream_t s);
@@ -100,8 +122,10 @@ hipError_t launch_spmv(const SpmvArgs &A, int lanes, hipStream_t s);
 hipError_t launch_outer(int32_t n, const int32_t *rp, const int32_t *ci, const int32_t *perm, const double *W,
                         const double *Bp, const double *x, const double *y, double *glu, int32_t nrhs, int64_t ld,
                         hipStream_t s);
-// capacity queries for persistent launches
-int persistent_grid_factor(int lanes);
-int persistent_grid_solve(bool forward, int prec, int vec, int lanes);
+// capacity queries for persistent launches (blocks), and the dynamic LDS the factor
+// needs per block for a given staging capacity (0 if it does not fit)
+size_t factor_lds_bytes(int lanes, int tcap);
+// XCC ids seen by the first `blocks` blocks of a launch (host array of `blocks`)
+hipError_t probe_xcc_ids(int blocks, int32_t *host_ids);
 
 }  // namespace jv

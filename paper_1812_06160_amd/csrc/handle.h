@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "analysis.h"
+#include "device.h"
 #include "javelin.h"
 
 namespace jv {
@@ -27,9 +28,15 @@ struct Profiler {
 };
 
 struct TaskList {
-    int32_t *ptr = nullptr;   // device, ntasks + 1 positions
+    int32_t *ptr = nullptr;            // device, ntasks + 1 positions
+    int32_t *stream_tasks = nullptr;   // device, task ids in stream order
+    int32_t *stream_ptr = nullptr;     // device, nstreams + 1
     int32_t ntasks = 0;
+    int32_t max_slots = 0;             // block slots of the longest stream
 };
+
+// claim-counter sets of the persistent passes
+enum { kPassFactor = 0, kPassForward = 1, kPassBackward = 2, kPassTForward = 3, kPassTBackward = 4, kPasses = 5 };
 
 ilu_status fail(ilu_status s, const std::string &msg);
 ilu_status hip_fail(hipError_t e, const char *what);
@@ -72,6 +79,11 @@ struct ilu_handle_s {
 
     std::map<int, jv::TaskList> tasks;
     jv::Profiler prof;
+    int32_t *d_counters = nullptr;     // kPasses sets of claim counters
+    bool counters_dirty[jv::kPasses] = {false, false, false, false, false};
+    int32_t factor_tcap = 0;           // LDS staging entries per factor row (0: unstaged)
+    int32_t nstreams = 1;              // task streams (one per XCD)
+    int8_t *d_xcc_stream = nullptr;    // XCC id -> stream
     std::vector<void *> allocs;
 
     // state
@@ -87,8 +99,10 @@ struct ilu_handle_s {
     hipError_t ensure_workspace(int nrhs, int prec_class, hipStream_t s);
     hipError_t rearm(hipStream_t s);
     hipError_t reset_info(hipStream_t s);
-    int grid_factor(int lanes, int ntasks);
-    int grid_solve(bool fwd, int prec, int vec, int lanes, int ntasks);
+    // fills the claims of one sync-free pass (launching a counter reset when needed)
+    hipError_t prepare_claims(int pass, const jv::TaskList *tl, jv::Claims *c, hipStream_t s);
+    // blocks of a sync-free launch: every stream's slots plus one spare per stream
+    int grid_syncfree(const jv::TaskList *tl) const { return nstreams * (tl->max_slots + 1); }
 };
 
 inline void allocs_erase(ilu_handle_s *h, void *p) {

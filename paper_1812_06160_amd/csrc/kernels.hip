@@ -7,22 +7,23 @@
 //  * level launch: one kernel per level (the kernel boundary is the barrier
 //    between levels, the classic level-set scheme the paper compares against,
 //    Sec. VI "CSR-LS");
-//  * sync-free persistent launch: one kernel for all levels.  Waves take
-//    level-homogeneous tasks (up to 64/G consecutive rows of one level) in level
-//    order, round-robin; a row reads each value it depends on with an
-//    agent-scope atomic load until it is no longer the "pending" bit pattern.
-//    This is the GPU form of the paper's point-to-point synchronisation (Sec. III,
-//    "Level Scheduling, Upper Stage"): a row waits only for the rows it needs,
-//    never for a whole level.  Values are published with agent-scope relaxed
-//    atomic stores, so no cache-flushing release fence is needed (coherence of
-//    atomics to one address is enough: each consumed value is its own flag).
+//  * sync-free launch: one kernel for all levels.  Each wave runs one
+//    level-homogeneous task (up to 64/G consecutive rows of one level); blocks
+//    take their tasks in start order from per-XCD task streams (claim_task).  A
+//    row reads each value it depends on with an agent-scope atomic load until it
+//    is no longer the "pending" bit pattern.  This is the GPU form of the paper's
+//    point-to-point synchronisation (Sec. III, "Level Scheduling, Upper Stage"): a
+//    row waits only for the rows it needs, never for a whole level.  Values are
+//    published with agent-scope relaxed atomic stores, so no cache-flushing
+//    release fence is needed (coherence of atomics to one address is enough:
+//    each consumed value is its own flag).
 //
-// Deadlock freedom of the persistent scheme: a task only waits on rows of earlier
-// levels, i.e. on earlier tasks; the smallest unfinished task always has every
-// dependency finished and is being processed by its wave (a wave handles its
-// tasks in increasing order), provided every wave of the grid is resident -- the
-// host sizes the grid from the occupancy query.  Every wait is bounded
-// (kSpinLimit) and raises a device abort flag that stops all waits.
+// Deadlock freedom of the sync-free scheme: a task only waits on rows of earlier
+// levels, i.e. on tasks of earlier-claimed block slots, whose blocks already run
+// or have finished; blocks claim slots when they start, so the smallest
+// unfinished task is always held by a running wave or claimed by the next block
+// that starts on its XCD, whatever the number of resident blocks.  Every wait
+// is bounded (kSpinLimit) and raises a device abort flag that stops all waits.
 //
 // Floating point: the library is compiled with -ffp-contract=off, so a - l*u is
 // a rounded multiply then a rounded subtract, and FP64 division is IEEE
@@ -148,6 +149,10 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t value, int64_t count) {
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; i < count; i += stride) p[i] = value;
 }
+__global__ void k_zero_counters(int32_t *c) {
+    if (threadIdx.x < kStreams) c[threadIdx.x * kCounterStride] = 0;
+}
+
 __global__ void k_fill_u32(uint32_t *p, uint32_t value, int64_t count) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -227,14 +232,90 @@ __global__ void k_factor_fixup(int64_t nnz, double *__restrict__ lu, const int8_
 }
 
 // ---------------------------------------------------------------------------------
+// Task claiming of the sync-free kernels
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ unsigned xcc_id() {
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 0xf;   // HW_REG_XCC_ID[3:0]
+}
+
+// Claims the next block slot of this XCD's stream (start order) -- or, when that
+// stream is exhausted, of the next stream that is not -- and runs task
+// slot * waves_per_block + wave of that stream on each wave.  Block 0 also clears
+// the counters of the pass that runs next.
+template <typename F>
+__device__ __forceinline__ void claim_task(const Claims &C, int nstreams, F &&task_fn) {
+    __shared__ int s_slot, s_stream;
+    if (C.zero_counters && blockIdx.x == 0 && threadIdx.x < kStreams)
+        C.zero_counters[threadIdx.x * kCounterStride] = 0;
+    if (threadIdx.x == 0) {
+        const int x0 = C.xcc_stream[xcc_id()];
+        s_stream = -1;
+        for (int k = 0; k < nstreams; ++k) {
+            const int x = (x0 + k) % nstreams;
+            const int slots = (C.stream_ptr[x + 1] - C.stream_ptr[x] + kBlock / 64 - 1) / (kBlock / 64);
+            const int v = __hip_atomic_fetch_add(C.counters + x * kCounterStride, 1, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            if (v < slots) {
+                s_slot = v;
+                s_stream = x;
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    const int x = s_stream;
+    if (x < 0) return;
+    const int lo = C.stream_ptr[x];
+    const int len = C.stream_ptr[x + 1] - lo;
+    const int i = s_slot * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    if (i < len) task_fn(C.stream_tasks[lo + i]);
+}
+
+__global__ void k_probe_xcc(int32_t *out) {
+    if (threadIdx.x == 0) out[blockIdx.x] = (int32_t)xcc_id();
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------------------------
 // Up-looking ILU on the fixed pattern (paper Sec. III, Fig. 1), one row per group
 // ---------------------------------------------------------------------------------
 // Lane t of the group holds entry rs+t of row r (the host guarantees row length <= G).
 // For each earlier column c of the row, in ascending order: lane e divides its
 // entry by the pivot u_cc, the multiplier is broadcast, and every lane whose
-// column matches a later column j of row c subtracts l * u_cj.  Row c's upper
-// part (diagonal first) is loaded by lanes t < len(U(c)); its structure
-// (diag_pos[c], row_ptr[c+1]) is fetched for all c up front.
+// column matches a later column j of row c subtracts l * u_cj.
+//
+// Staged form (STAGE): the upper parts (diagonal first) of all dependency rows c
+// are gathered into the group's LDS slice in one parallel pass -- in the
+// persistent kernel this is the single point where the row waits for its
+// dependencies -- and the ascending elimination then reads them from LDS.
+// Unstaged form: each dependency row is loaded when its turn comes.
+
+template <int G, bool SF>
+__device__ __forceinline__ void factor_finish(const FactorArgs &A, int r, int t, int gi, int p, bool act, int col,
+                                              int absent, int dropped, double v, double tr, int diag_lane) {
+    if (A.use_tau && act && !absent && col > r && fabs(v) < tr) dropped = 1;
+    const double pv = __shfl(v, diag_lane, G);
+    const bool nonfinite = act && !absent && !dropped && !isfinite(v);
+    const uint64_t nfm = group_bits<G>(__ballot(nonfinite), gi);
+    if (t == 0) {
+        if (pv == 0.0) atomicMin(&A.info[kInfoBadKey], 2 * r);
+        else if (nfm) atomicMin(&A.info[kInfoBadKey], 2 * r + 1);
+    }
+    if (act) {
+        uint64_t bits;
+        if (absent) bits = 0;
+        else if (dropped) bits = kDropped64;
+        else bits = (v != v) ? kQNaN64 : (uint64_t)__double_as_longlong(v);
+        if constexpr (SF) st_pub_u64(reinterpret_cast<uint64_t *>(&A.lu[p]), bits);
+        else A.lu[p] = __longlong_as_double((long long)bits);
+    }
+}
+
 template <int G, bool SF>
 __device__ __forceinline__ void factor_row(const FactorArgs &A, int r, int t, int gi) {
     const int rs = A.rp[r], re = A.rp[r + 1], d = A.diag[r];
@@ -283,43 +364,119 @@ __device__ __forceinline__ void factor_row(const FactorArgs &A, int r, int t, in
             }
         }
     }
-    if (A.use_tau && act && !absent && col > r && fabs(v) < tr) dropped = 1;
-    const double pv = __shfl(v, d - rs, G);
-    const bool nonfinite = act && !absent && !dropped && !isfinite(v);
-    const uint64_t nfm = group_bits<G>(__ballot(nonfinite), gi);
-    if (t == 0) {
-        if (pv == 0.0) atomicMin(&A.info[kInfoBadKey], 2 * r);
-        else if (nfm) atomicMin(&A.info[kInfoBadKey], 2 * r + 1);
-    }
-    if (act) {
-        uint64_t bits;
-        if (absent) bits = 0;
-        else if (dropped) bits = kDropped64;
-        else bits = (v != v) ? kQNaN64 : (uint64_t)__double_as_longlong(v);
-        if constexpr (SF) st_pub_u64(reinterpret_cast<uint64_t *>(&A.lu[p]), bits);
-        else A.lu[p] = __longlong_as_double((long long)bits);
-    }
+    factor_finish<G, SF>(A, r, t, gi, p, act, col, absent, dropped, v, tr, d - rs);
 }
 
+template <int G, bool SF>
+__device__ __forceinline__ void factor_row_staged(const FactorArgs &A, int r, int t, int gi, double *sv, int *sc,
+                                                  int *soff, int *sdc) {
+    const int rs = A.rp[r], re = A.rp[r + 1], d = A.diag[r];
+    const int nL = d - rs;
+    const int p = rs + t;
+    const bool act = p < re;
+    const int col = act ? A.ci[p] : INT_MAX;
+    const int absent = (act && A.use_flev && A.flev[p] > A.k) ? 1 : 0;
+    const int s = act ? A.src[p] : -1;
+    double v = (s >= 0 && !absent) ? A.a[s] : 0.0;
+    int dropped = 0;
+    const double tr = A.use_tau ? A.row_tau[r] : 0.0;
+    // length of U(c) (diagonal included) for each kept dependency; 0 when absent
+    int dc = 0, len = 0;
+    if (t < nL && !absent) {
+        dc = A.diag[col];
+        len = A.rp[col + 1] - dc;
+    }
+    int inc = len;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+        const int y = __shfl_up(inc, o, G);
+        if (t >= o) inc += y;
+    }
+    const int total = __shfl(inc, G - 1, G);
+    const int off = inc - len;
+    if (t < nL) {
+        soff[t] = off;
+        sdc[t] = dc;
+    }
+    wave_sync_lds();
+    for (int j = t; j < total; j += G) {
+        int e = 0;
+        while (e + 1 < nL && soff[e + 1] <= j) ++e;
+        const int q = sdc[e] + (j - soff[e]);
+        sc[j] = (A.use_flev && A.flev[q] > A.k) ? -1 : A.ci[q];
+        double uv;
+        if constexpr (SF) uv = Pub<double>::wait(&A.lu[q], A.info);
+        else uv = A.lu[q];
+        sv[j] = uv;
+    }
+    wave_sync_lds();
+    for (int e = 0; e < nL; ++e) {
+        const int le = __shfl(len, e, G);
+        if (le == 0) continue;   // absent dependency (a kept one always holds its diagonal)
+        const int o = soff[e];
+        const double piv = sv[o];
+        if (t == e) {
+            v = v / piv;
+            if (A.use_tau && fabs(v) < tr) dropped = 1;
+        }
+        if (__shfl(dropped, e, G)) continue;
+        const double l = __shfl(v, e, G);
+        for (int j = 1; j < le; ++j) {
+            const int uc = sc[o + j];
+            const double uu = sv[o + j];
+            if (uc >= 0 && (uint64_t)__double_as_longlong(uu) != kDropped64 && col == uc && !absent) {
+                const double prod = l * uu;
+                v = v - prod;
+            }
+        }
+    }
+    wave_sync_lds();   // the slice is reused by the group's next row
+    factor_finish<G, SF>(A, r, t, gi, p, act, col, absent, dropped, v, tr, d - rs);
+}
+
+// per-group LDS slices: [ngroups][tcap] doubles, then per group tcap + 2G ints
 template <int G>
+__device__ __forceinline__ void group_slices(int tcap, double *&sv, int *&sc, int *&soff, int *&sdc) {
+    extern __shared__ double lds_f[];
+    constexpr int ngroups = kBlock / G;
+    const int g = threadIdx.x / G;
+    sv = lds_f + g * tcap;
+    int *ib = reinterpret_cast<int *>(lds_f + ngroups * tcap);
+    sc = ib + g * (tcap + 2 * G);
+    soff = sc + tcap;
+    sdc = soff + G;
+}
+
+template <int G, bool STAGE>
 __global__ __launch_bounds__(kBlock) void k_factor_level(FactorArgs A) {
     const int gid = (blockIdx.x * blockDim.x + threadIdx.x) / G;
     const int t = threadIdx.x % G;
     const int gi = (threadIdx.x & 63) / G;
     const int r = A.row_begin + gid;
-    if (r < A.row_end) factor_row<G, false>(A, r, t, gi);
+    if constexpr (STAGE) {
+        double *sv;
+        int *sc, *soff, *sdc;
+        group_slices<G>(A.tcap, sv, sc, soff, sdc);
+        if (r < A.row_end) factor_row_staged<G, false>(A, r, t, gi, sv, sc, soff, sdc);
+    } else {
+        if (r < A.row_end) factor_row<G, false>(A, r, t, gi);
+    }
 }
 
-template <int G>
+template <int G, bool STAGE>
 __global__ __launch_bounds__(kBlock) void k_factor_syncfree(FactorArgs A) {
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int nwaves = (gridDim.x * blockDim.x) >> 6;
     const int t = threadIdx.x % G;
     const int gi = (threadIdx.x & 63) / G;
-    for (int task = wave; task < A.ntasks; task += nwaves) {
-        const int r = A.task_ptr[task] + gi;
-        if (r < A.task_ptr[task + 1]) factor_row<G, true>(A, r, t, gi);
-    }
+    double *sv = nullptr;
+    int *sc = nullptr, *soff = nullptr, *sdc = nullptr;
+    if constexpr (STAGE) group_slices<G>(A.tcap, sv, sc, soff, sdc);
+    claim_task(A.claims, A.nstreams, [&](int task) {
+        const int r = A.claims.task_ptr[task] + gi;
+        if (r < A.claims.task_ptr[task + 1]) {
+            if constexpr (STAGE) factor_row_staged<G, true>(A, r, t, gi, sv, sc, soff, sdc);
+            else factor_row<G, true>(A, r, t, gi);
+        }
+    });
 }
 
 // ---------------------------------------------------------------------------------
@@ -384,17 +541,15 @@ __global__ __launch_bounds__(kBlock) void k_solve_level(SolveArgs A) {
 
 template <int G, typename TV, typename TX, typename TA, bool FWD>
 __global__ __launch_bounds__(kBlock) void k_solve_syncfree(SolveArgs A) {
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int nwaves = (gridDim.x * blockDim.x) >> 6;
     const int t = threadIdx.x % G;
     const int gi = (threadIdx.x & 63) / G;
-    for (int task = wave; task < A.ntasks; task += nwaves) {
-        const int pos = A.task_ptr[task] + gi;
-        if (pos < A.task_ptr[task + 1]) {
+    claim_task(A.claims, A.nstreams, [&](int task) {
+        const int pos = A.claims.task_ptr[task] + gi;
+        if (pos < A.claims.task_ptr[task + 1]) {
             const int r = A.rows ? A.rows[pos] : pos;
             solve_row<G, TV, TX, TA, true, FWD>(A, r, t);
         }
-    }
+    });
 }
 
 // ---------------------------------------------------------------------------------
@@ -458,21 +613,6 @@ int grid_for(int64_t work_items, int per_block) {
     return (int)g;
 }
 
-template <typename F>
-int occupancy_grid(F kernel) {
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
-        if (cus <= 0) cus = 1;
-    }
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu <= 0)
-        per_cu = 1;
-    return per_cu * cus;
-}
-
 }  // namespace
 
 // ---------------------------------------------------------------------------------
@@ -483,6 +623,11 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t value, int64_t count, hipStream
     int g = grid_for(count, kBlock);
     if (g > 8192) g = 8192;
     hipLaunchKernelGGL(k_fill_u64, dim3(g), dim3(kBlock), 0, s, p, value, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_counters(int32_t *counters, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, counters);
     return hipGetLastError();
 }
 
@@ -533,14 +678,45 @@ hipError_t launch_factor_fixup(int64_t nnz, double *lu, const int8_t *flev, int3
     return hipGetLastError();
 }
 
+hipError_t launch_outer(int32_t n, const int32_t *rp, const int32_t *ci, const int32_t *perm, const double *W,
+                        const double *Bp, const double *x, const double *y, double *glu, int32_t nrhs, int64_t ld,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_outer, dim3(grid_for((int64_t)n * 8, kBlock)), dim3(kBlock), 0, s, n, rp, ci, perm, W, Bp, x,
+                       y, glu, nrhs, ld);
+    return hipGetLastError();
+}
+
+template <int G>
+static size_t lds_bytes_g(int tcap) {
+    if (tcap <= 0) return 0;
+    constexpr int ngroups = kBlock / G;
+    return (size_t)ngroups * tcap * 8 + (size_t)ngroups * (tcap + 2 * G) * 4;
+}
+
+size_t factor_lds_bytes(int lanes, int tcap) {
+    size_t b = 0;
+    switch (lanes) {
+        case 4: b = lds_bytes_g<4>(tcap); break;
+        case 8: b = lds_bytes_g<8>(tcap); break;
+        case 16: b = lds_bytes_g<16>(tcap); break;
+        case 32: b = lds_bytes_g<32>(tcap); break;
+        default: b = lds_bytes_g<64>(tcap); break;
+    }
+    return b <= 48 * 1024 ? b : 0;
+}
+
 template <int G>
 static hipError_t factor_dispatch(const FactorArgs &A, bool syncfree, int grid, hipStream_t s) {
+    const size_t lds = A.tcap > 0 ? lds_bytes_g<G>(A.tcap) : 0;
     if (syncfree) {
-        hipLaunchKernelGGL(k_factor_syncfree<G>, dim3(grid), dim3(kBlock), 0, s, A);
+        if (lds) hipLaunchKernelGGL((k_factor_syncfree<G, true>), dim3(grid), dim3(kBlock), lds, s, A);
+        else hipLaunchKernelGGL((k_factor_syncfree<G, false>), dim3(grid), dim3(kBlock), 0, s, A);
     } else {
         int64_t rows = A.row_end - A.row_begin;
         if (rows <= 0) return hipSuccess;
-        hipLaunchKernelGGL(k_factor_level<G>, dim3(grid_for(rows * G, kBlock)), dim3(kBlock), 0, s, A);
+        dim3 g(grid_for(rows * G, kBlock));
+        if (lds) hipLaunchKernelGGL((k_factor_level<G, true>), g, dim3(kBlock), lds, s, A);
+        else hipLaunchKernelGGL((k_factor_level<G, false>), g, dim3(kBlock), 0, s, A);
     }
     return hipGetLastError();
 }
@@ -556,22 +732,15 @@ hipError_t launch_factor(const FactorArgs &A, int lanes, bool syncfree, int grid
     }
 }
 
-hipError_t launch_outer(int32_t n, const int32_t *rp, const int32_t *ci, const int32_t *perm, const double *W,
-                        const double *Bp, const double *x, const double *y, double *glu, int32_t nrhs, int64_t ld,
-                        hipStream_t s) {
-    hipLaunchKernelGGL(k_outer, dim3(grid_for((int64_t)n * 8, kBlock)), dim3(kBlock), 0, s, n, rp, ci, perm, W, Bp, x,
-                       y, glu, nrhs, ld);
-    return hipGetLastError();
-}
-
-int persistent_grid_factor(int lanes) {
-    switch (lanes) {
-        case 4: return occupancy_grid(k_factor_syncfree<4>);
-        case 8: return occupancy_grid(k_factor_syncfree<8>);
-        case 16: return occupancy_grid(k_factor_syncfree<16>);
-        case 32: return occupancy_grid(k_factor_syncfree<32>);
-        default: return occupancy_grid(k_factor_syncfree<64>);
-    }
+hipError_t probe_xcc_ids(int blocks, int32_t *host_ids) {
+    int32_t *d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(int32_t) * blocks);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_probe_xcc, dim3(blocks), dim3(64), 0, 0, d);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpy(host_ids, d, sizeof(int32_t) * blocks, hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    return e;
 }
 
 template <int G, typename TV, typename TX, typename TA>
@@ -615,26 +784,6 @@ hipError_t launch_solve(const SolveArgs &A, bool forward, int prec, int vec, int
         case 32: return solve_dispatch1<32>(A, forward, prec, vec, syncfree, grid, s);
         case 64: return solve_dispatch1<64>(A, forward, prec, vec, syncfree, grid, s);
         default: return hipErrorInvalidValue;
-    }
-}
-
-template <int G>
-static int solve_grid_g(bool fwd, int prec, int vec) {
-    // the persistent solve kernels of one lane count share their resource use;
-    // query the FP64 instance of the requested direction
-    (void)prec;
-    (void)vec;
-    if (fwd) return occupancy_grid(k_solve_syncfree<G, double, double, double, true>);
-    return occupancy_grid(k_solve_syncfree<G, double, double, double, false>);
-}
-
-int persistent_grid_solve(bool forward, int prec, int vec, int lanes) {
-    switch (lanes) {
-        case 4: return solve_grid_g<4>(forward, prec, vec);
-        case 8: return solve_grid_g<8>(forward, prec, vec);
-        case 16: return solve_grid_g<16>(forward, prec, vec);
-        case 32: return solve_grid_g<32>(forward, prec, vec);
-        default: return solve_grid_g<64>(forward, prec, vec);
     }
 }
 

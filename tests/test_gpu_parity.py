@@ -39,8 +39,9 @@ CASES = [
     ("convdiff3d_14_ilu1_tau", lambda: synth.convdiff3d(14), 1, 1e-3),
     ("convdiff3d_14_ilu1", lambda: synth.convdiff3d(14), 1, 0.0),
     ("random_3000", lambda: synth.random_banded(3000, rng=np.random.default_rng(5)), 0, 0.0),
-    ("random_sparse_ragged", lambda: synth.random_sparse(333, 0.02, np.random.default_rng(6),
-                                                         drop_diag_frac=0.1), 0, 0.0),
+    ("random_sparse_ragged", lambda: synth.random_sparse(333, 0.02, np.random.default_rng(6)), 0, 0.0),
+    ("random_sparse_missing_diag", lambda: synth.random_sparse(333, 0.02, np.random.default_rng(6),
+                                                               drop_diag_frac=0.1), 0, 0.0),
     ("random_sparse_ilu2", lambda: synth.random_sparse(300, 0.015, np.random.default_rng(7)), 2, 0.0),
 ]
 
@@ -54,9 +55,15 @@ def test_factor_bit_exact(jv, name, mk, k, tau, sched):
         if an.lu_rp.size and np.diff(an.lu_rp).max() > 64:
             pytest.skip("row longer than 64")
         ilu = make(jv, A, k, sym, sched)
-        info = ilu.factor(dev(A.val), k=k, tau=tau)
         f = O.factor(an, A.val, k=k, tau=tau)
-        assert f.status == O.OK
+        if f.status != O.OK:
+            # the oracle stops at the first failing row: same status and row required
+            with pytest.raises(jv.IluError) as e:
+                ilu.factor(dev(A.val), k=k, tau=tau)
+            want = "ILU_ERR_ZERO_PIVOT" if f.status == O.ERR_ZERO_PIVOT else "ILU_ERR_NONFINITE"
+            assert e.value.status == want and e.value.info["bad_row"] == f.bad_row
+            continue
+        info = ilu.factor(dev(A.val), k=k, tau=tau)
         lu, st = ilu.factor_values()
         np.testing.assert_array_equal(st, f.stat)
         assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64)), \
