@@ -15,6 +15,7 @@ Kernel durations come from HIP events the library records around each kernel
 launch on its own stream during the timed steps.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py --workload convdiff3d_96 | random_1m | batch512   (other workloads)
 """
 import argparse
 import json
@@ -73,10 +74,16 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="grid scale (1.0 = 128^3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sched", default="syncfree", choices=["syncfree", "level"])
+    ap.add_argument("--workload", default="laplace3d_128",
+                    choices=["laplace3d_128", "convdiff3d_96", "random_1m", "batch512"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "laplace3d_128":
+        import bench_workloads
+        bench_workloads.run(args)
+        return
 
     import torch
     import synth

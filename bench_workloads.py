@@ -1,0 +1,164 @@
+"""Measurements of the other workloads (bench.py --workload ...): one JSON line each.
+
+convdiff3d_96  96^3 upwind convection-diffusion, ILU(1, tau=1e-3): factor, applies,
+               FGMRES(30) to 1e-10 with FP64, FP32 and BF16 factors.
+random_1m      n = 1e6 random unsymmetric rows (8 banded + 8 scattered off-diagonals):
+               ILU(0) factor, applies over 16 right-hand sides (FP64, and FP32 factors
+               with FP32 vectors).
+batch512       512 variable-coefficient 2D diffusion matrices in one block-diagonal
+               handle: factor, FP32 apply of 4 right-hand sides each through a
+               captured graph, FP64 forward + adjoint.
+"""
+import json
+import sys
+import time
+
+import numpy as np
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _stage_times(ilu, fn, reps):
+    import torch
+    ilu.profile_read()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    p = ilu.profile_read()
+    return {k: (v[0] / max(v[1], 1), v[1]) for k, v in p.items()}
+
+
+def _bytes(n, nnz_lu, nnz_l, nnz_b, s_v=8, s_x=8, nrhs=1):
+    return dict(factor=20 * nnz_lu + 8 * n,
+                apply=(4 + s_v) * nnz_lu + 16 * n + nrhs * 4 * s_x * n,
+                spmv=12 * nnz_b + 4 * (n + 1) + nrhs * 2 * s_x * n)
+
+
+def _nnz_l(ilu):
+    sc = ilu.schedule()
+    return int((sc["diag_pos"] - sc["lu_row_ptr"][:-1]).sum())
+
+
+def run(args):
+    import torch
+    import synth
+    import paper_1812_06160_amd as jv
+    torch.cuda.set_device(0)
+    jv.load()
+    wl = args.workload
+    out = dict(workload=wl, data="synthetic", n_gpus=1)
+    if wl == "convdiff3d_96":
+        A, b = synth.workload(3)
+        ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=1)
+        ilu.set_schedule(args.sched, args.sched)
+        a = _dev(A.val)
+        bt = _dev(b)
+        ilu.factor(a, k=1, tau=1e-3, casts=("f32", "bf16"))
+        ilu.profile(True, 1 << 16)
+        st = _stage_times(ilu, lambda: ilu.factor(a, k=1, tau=1e-3, casts=("f32", "bf16")), 5)
+        t_apply = {}
+        for prec in ("f64", "f32", "bf16"):
+            p = _stage_times(ilu, lambda: ilu.apply(bt, prec=prec), 10)
+            t_apply[prec] = p["forward"][0] + p["backward"][0]
+        info = ilu.info()
+        B = _bytes(A.n, info["nnz_lu"], _nnz_l(ilu), info["nnz_b"])
+        res = {}
+        for prec in ("f64", "f32", "bf16"):
+            ilu.gmres(bt, rtol=1e-10, restart=30, prec=prec)       # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, si = ilu.gmres(bt, rtol=1e-10, restart=30, prec=prec)
+            torch.cuda.synchronize()
+            res[prec] = dict(seconds=round(time.perf_counter() - t0, 4), iters=si["iters"],
+                             true_relres=si["true_relres"])
+            log(f"gmres {prec}: {res[prec]}")
+        fi = ilu.factor(a, k=1, tau=1e-3, casts=("f32", "bf16"))
+        out.update(n=A.n, nnz=A.nnz, nnz_lu=info["nnz_lu"], levels=info["n_levels"], dropped=fi["n_dropped"],
+                   factor_us=round(1e3 * st["factor"][0], 1),
+                   factor_gbs=round(B["factor"] / st["factor"][0] / 1e6, 1),
+                   apply_us={k: round(1e3 * v, 1) for k, v in t_apply.items()},
+                   apply_gbs_f64=round(B["apply"] / t_apply["f64"] / 1e6, 1),
+                   gmres30=res,
+                   gmres_speedup_f32=round(res["f64"]["seconds"] / res["f32"]["seconds"], 3),
+                   gmres_speedup_bf16=round(res["f64"]["seconds"] / res["bf16"]["seconds"], 3))
+    elif wl == "random_1m":
+        A, Bm = synth.workload(4)
+        ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
+        ilu.set_schedule(args.sched, args.sched)
+        a = _dev(A.val)
+        ilu.factor(a, casts=("f32",))
+        ilu.profile(True, 1 << 16)
+        st = _stage_times(ilu, lambda: ilu.factor(a, casts=("f32",)), 3)
+        b64 = _dev(Bm)
+        b32 = _dev(Bm.astype(np.float32))
+        p64 = _stage_times(ilu, lambda: ilu.apply(b64), 5)
+        p32 = _stage_times(ilu, lambda: ilu.apply(b32, prec="f32"), 5)
+        b1 = _dev(np.ascontiguousarray(Bm[:, 0]))
+        p1 = _stage_times(ilu, lambda: ilu.apply(b1), 5)
+        info = ilu.info()
+        nl = _nnz_l(ilu)
+        B16 = _bytes(A.n, info["nnz_lu"], nl, info["nnz_b"], s_v=4, s_x=4, nrhs=16)
+        B64 = _bytes(A.n, info["nnz_lu"], nl, info["nnz_b"], s_v=8, s_x=8, nrhs=16)
+        t64 = p64["forward"][0] + p64["backward"][0]
+        t32 = p32["forward"][0] + p32["backward"][0]
+        t1 = p1["forward"][0] + p1["backward"][0]
+        out.update(n=A.n, nnz=A.nnz, levels=info["n_levels"], ulevels=info["n_ulevels"],
+                   level_median=info["level_median"],
+                   factor_us=round(1e3 * st["factor"][0], 1),
+                   apply16_f32_us=round(1e3 * t32, 1), apply16_f32_gbs=round(B16["apply"] / t32 / 1e6, 1),
+                   apply16_f64_us=round(1e3 * t64, 1), apply16_f64_gbs=round(B64["apply"] / t64 / 1e6, 1),
+                   apply1_f64_us=round(1e3 * t1, 1),
+                   us_per_level_apply1=round(1e3 * t1 / (info["n_levels"] + info["n_ulevels"]), 3))
+    elif wl == "batch512":
+        mats, rhs = synth.workload(5)
+        t0 = time.perf_counter()
+        hb = jv.Ilu.batched(mats)
+        t_an = time.perf_counter() - t0
+        hb.set_schedule(args.sched, args.sched)
+        vals = _dev(np.concatenate([m.val for m in mats]))
+        hb.factor(vals, casts=("f32",))
+        b = np.concatenate(rhs)
+        b32 = _dev(b.astype(np.float32))
+        x32 = torch.empty_like(b32)
+        g = hb.apply_graph(b32, x32, prec="f32")
+        hb.profile(True, 1 << 16)
+        st = _stage_times(hb, lambda: hb.factor(vals, casts=("f32",)), 3)
+        torch.cuda.synchronize()
+        reps = 20
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.launch()
+        torch.cuda.synchronize()
+        t_graph = (time.perf_counter() - t0) / reps
+        pe = _stage_times(hb, lambda: hb.apply(b32, x=x32, prec="f32"), 10)
+        t_eager = pe["forward"][0] + pe["backward"][0]
+        # forward (FP64) + adjoint
+        b64 = _dev(b)
+        lu = hb.factor_tensor()
+        bb = b64.clone().requires_grad_(True)
+        ll = lu.clone().requires_grad_(True)
+        c = _dev(np.random.default_rng(3).uniform(-1, 1, b.shape))
+        x = jv.IluApply.apply(hb, bb, ll)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            x = jv.IluApply.apply(hb, bb, ll)
+            (x * c).sum().backward()
+        torch.cuda.synchronize()
+        t_fb = (time.perf_counter() - t0) / 5
+        info = hb.info()
+        B32 = _bytes(info["n"], info["nnz_lu"], _nnz_l(hb), info["nnz_b"], s_v=4, s_x=4, nrhs=4)
+        out.update(matrices=len(mats), n=info["n"], nnz=info["nnz_a"], levels=info["n_levels"],
+                   analyze_s=round(t_an, 3), factor_us=round(1e3 * st["factor"][0], 1),
+                   apply_f32_4rhs_graph_us=round(1e6 * t_graph, 1),
+                   apply_f32_4rhs_kernels_us=round(1e3 * t_eager, 1),
+                   apply_f32_4rhs_gbs=round(B32["apply"] / t_eager / 1e6, 1),
+                   forward_backward_f64_ms=round(1e3 * t_fb, 3))
+    print(json.dumps(out), flush=True)

@@ -214,6 +214,18 @@ ilu_status ilu_apply_adjoint(ilu_handle h, const double *lu_val, const double *g
                              const double *y, double *gb, double *glu, int32_t nrhs, int64_t ld,
                              hipStream_t stream);
 
+/* A graph holding one captured ilu_apply with fixed arguments (its sync-free
+ * launches and counter resets), replayed with ilu_graph_launch on any stream.
+ * Each replay leaves the handle ready for the next one, so replays may be
+ * interleaved with ordinary calls on the same handle (not concurrently).  The
+ * graph borrows b and x (device) and the handle; destroy it before either.
+ * The factor values it reads are the handle's current ones at replay time. */
+typedef struct ilu_graph_s *ilu_graph;
+ilu_status ilu_apply_graph_create(ilu_handle h, const void *b, void *x, int32_t nrhs, int64_t ld,
+                                  int32_t fac_prec, int32_t vec_prec, int32_t flags, ilu_graph *out);
+ilu_status ilu_graph_launch(ilu_graph g, hipStream_t stream);
+ilu_status ilu_graph_destroy(ilu_graph g);
+
 /* y = alpha * A x + beta * y with the values loaded by ilu_factor (or
  * ilu_set_values); FP64, device [n][ld].  With ILU_PERMUTED_SPACE, x and y are
  * in the level ordering and the product is with P A P^T. */
@@ -254,6 +266,13 @@ ilu_status ilu_set_schedule(ilu_handle h, int32_t factor_sched, int32_t solve_sc
                             int32_t lanes_factor, int32_t lanes_solve);
 ilu_status ilu_get_schedule(ilu_handle h, int32_t *factor_sched, int32_t *solve_sched,
                             int32_t *lanes_factor, int32_t *lanes_solve);
+
+/* Named tuning knobs.  Settable: "poll_sleep" (0..64, pause steps of about 64
+ * clocks between polls of a value that is still pending).  Readable as well:
+ * "nstreams" (task streams = XCDs found), "factor_tcap" (LDS entries staged per
+ * factor row).  Unknown keys give ILU_ERR_ARG. */
+ilu_status ilu_set_tuning(ilu_handle h, const char *key, int64_t value);
+ilu_status ilu_get_tuning(ilu_handle h, const char *key, int64_t *value);
 
 /* Times the candidate schedules (level vs sync-free, lanes per row) of the factor
  * (when a_val, device values in input order, is given; re-run with tau = 0 and the

@@ -26,8 +26,8 @@ STAGES = ["factor", "forward", "backward", "spmv"]
 SYMBOLS = [
     "ilu_analyze", "ilu_analyze_batched", "ilu_batch_offsets", "ilu_get_info", "ilu_copy_schedule",
     "ilu_factor", "ilu_factor_values", "ilu_copy_factor", "ilu_copy_factor_prec", "ilu_apply", "ilu_apply_ex",
-    "ilu_apply_adjoint", "ilu_spmv", "ilu_set_values", "ilu_solve_pcg", "ilu_solve_gmres",
-    "ilu_set_schedule", "ilu_get_schedule", "ilu_tune", "ilu_profile_enable", "ilu_profile_read",
+    "ilu_apply_adjoint", "ilu_apply_graph_create", "ilu_graph_launch", "ilu_graph_destroy", "ilu_spmv", "ilu_set_values", "ilu_solve_pcg", "ilu_solve_gmres",
+    "ilu_set_schedule", "ilu_get_schedule", "ilu_set_tuning", "ilu_get_tuning", "ilu_tune", "ilu_profile_enable", "ilu_profile_read",
     "ilu_destroy", "ilu_version",
     "ilu_status_str", "ilu_last_error",
 ]
@@ -86,12 +86,17 @@ def load(path: str = LIB_PATH):
         "ilu_apply": [H, vp, vp, i32, i64, i32, i32, i32, vp],
         "ilu_apply_ex": [H, vp, vp, vp, vp, i32, i64, i32, vp],
         "ilu_apply_adjoint": [H, vp, vp, vp, vp, vp, vp, i32, i64, vp],
+        "ilu_apply_graph_create": [H, vp, vp, i32, i64, i32, i32, i32, C.POINTER(vp)],
+        "ilu_graph_launch": [vp, vp],
+        "ilu_graph_destroy": [vp],
         "ilu_spmv": [H, f64, vp, f64, vp, i32, i64, i32, vp],
         "ilu_set_values": [H, vp, vp],
         "ilu_solve_pcg": [H, vp, vp, f64, i32, i32, i32, C.POINTER(SolveInfo), vp],
         "ilu_solve_gmres": [H, vp, vp, f64, i32, i32, i32, i32, C.POINTER(SolveInfo), vp],
         "ilu_set_schedule": [H, i32, i32, i32, i32],
         "ilu_get_schedule": [H, vp, vp, vp, vp],
+        "ilu_set_tuning": [H, C.c_char_p, i64],
+        "ilu_get_tuning": [H, C.c_char_p, C.POINTER(i64)],
         "ilu_tune": [H, vp, i32, vp, i32, vp, vp],
         "ilu_profile_enable": [H, i32, i32],
         "ilu_profile_read": [H, vp, vp],

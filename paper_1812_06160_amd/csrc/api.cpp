@@ -482,6 +482,7 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
             return hip_fail(e, "ilu_factor: arm");
         if ((e = h->prepare_claims(kPassFactor, tl, &A.claims, s)) != hipSuccess) return hip_fail(e, "ilu_factor: claims");
         A.nstreams = h->nstreams;
+        A.poll_sleep = h->poll_sleep;
         h->prof.begin(ILU_STAGE_FACTOR, s);
         e = launch_factor(A, lanes, true, h->grid_syncfree(tl), s);
         h->prof.end(s);
@@ -666,6 +667,7 @@ ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int 
             const int pass = view == 0 ? (fwd ? kPassForward : kPassBackward) : (fwd ? kPassTForward : kPassTBackward);
             if ((e = h->prepare_claims(pass, tl, &A.claims, s)) != hipSuccess) return hip_fail(e, "solve claims");
             A.nstreams = h->nstreams;
+            A.poll_sleep = h->poll_sleep;
             h->prof.begin(fwd ? ILU_STAGE_FORWARD : ILU_STAGE_BACKWARD, s);
             e = launch_solve(A, fwd, prec, vec, lanes, true, h->grid_syncfree(tl), s);
             h->prof.end(s);
@@ -718,6 +720,69 @@ extern "C" ilu_status ilu_apply_ex(ilu_handle h, const double *lu_val, const dou
     if (!b || !x || nrhs < 1 || ld < nrhs) return fail(ILU_ERR_ARG, "ilu_apply_ex: bad vectors or sizes");
     if (flags & ~ILU_PERMUTED_SPACE) return fail(ILU_ERR_ARG, "ilu_apply_ex: unknown flags");
     return run_solves(h, 0, lu_val ? lu_val : h->d_lu, ILU_PREC_F64, 0, b, x, y_out, nullptr, nrhs, ld, flags, s);
+}
+
+// -------------------------------------------------------------------------------------
+// Graph capture of an apply
+// -------------------------------------------------------------------------------------
+
+struct ilu_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ilu_handle h = nullptr;
+    ~ilu_graph_s() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+extern "C" ilu_status ilu_apply_graph_create(ilu_handle h, const void *b, void *x, int32_t nrhs, int64_t ld,
+                                             int32_t fac_prec, int32_t vec_prec, int32_t flags, ilu_graph *out) {
+    if (!h || !out) return fail(ILU_ERR_ARG, "ilu_apply_graph_create: NULL argument");
+    *out = nullptr;
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "ilu_apply_graph_create: stream");
+    // an eager apply first: allocates workspaces and builds the task lists outside the capture
+    ilu_status st = ilu_apply(h, b, x, nrhs, ld, fac_prec, vec_prec, flags, cs);
+    if (st == ILU_OK && (e = hipStreamSynchronize(cs)) != hipSuccess) st = hip_fail(e, "ilu_apply_graph_create");
+    const bool prof = h->prof.enabled;
+    h->prof.enabled = false;
+    std::unique_ptr<ilu_graph_s> g(new (std::nothrow) ilu_graph_s());
+    if (st == ILU_OK && !g) st = fail(ILU_ERR_NOMEM, "ilu_apply_graph_create");
+    if (st == ILU_OK) {
+        if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+            st = hip_fail(e, "ilu_apply_graph_create: begin capture");
+        } else {
+            ilu_status st2 = ilu_apply(h, b, x, nrhs, ld, fac_prec, vec_prec, flags, cs);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(cs, &graph);
+            if (st2 != ILU_OK) st = st2;
+            else if (e != hipSuccess) st = hip_fail(e, "ilu_apply_graph_create: end capture");
+            g->graph = graph;
+            if (st == ILU_OK && (e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0)) != hipSuccess)
+                st = hip_fail(e, "ilu_apply_graph_create: instantiate");
+        }
+    }
+    h->prof.enabled = prof;
+    (void)hipStreamSynchronize(cs);
+    (void)hipStreamDestroy(cs);
+    if (st != ILU_OK) return st;
+    g->h = h;
+    *out = g.release();
+    return ILU_OK;
+}
+
+extern "C" ilu_status ilu_graph_launch(ilu_graph g, hipStream_t s) {
+    if (!g || !g->exec) return fail(ILU_ERR_ARG, "ilu_graph_launch: NULL graph");
+    hipError_t e = hipGraphLaunch(g->exec, s);
+    if (e != hipSuccess) return hip_fail(e, "ilu_graph_launch");
+    return ILU_OK;
+}
+
+extern "C" ilu_status ilu_graph_destroy(ilu_graph g) {
+    delete g;
+    return ILU_OK;
 }
 
 // spmv
@@ -832,6 +897,26 @@ extern "C" ilu_status ilu_get_schedule(ilu_handle h, int32_t *factor_sched, int3
     if (lanes_factor) *lanes_factor = h->lanes_factor;
     if (lanes_solve) *lanes_solve = h->lanes_solve;
     return ILU_OK;
+}
+
+extern "C" ilu_status ilu_set_tuning(ilu_handle h, const char *key, int64_t value) {
+    if (!h || !key) return fail(ILU_ERR_ARG, "ilu_set_tuning: NULL argument");
+    const std::string k(key);
+    if (k == "poll_sleep") {
+        if (value < 0 || value > 64) return fail(ILU_ERR_ARG, "ilu_set_tuning: poll_sleep must be in [0, 64]");
+        h->poll_sleep = (int32_t)value;
+        return ILU_OK;
+    }
+    return fail(ILU_ERR_ARG, "ilu_set_tuning: unknown key " + k);
+}
+
+extern "C" ilu_status ilu_get_tuning(ilu_handle h, const char *key, int64_t *value) {
+    if (!h || !key || !value) return fail(ILU_ERR_ARG, "ilu_get_tuning: NULL argument");
+    const std::string k(key);
+    if (k == "poll_sleep") { *value = h->poll_sleep; return ILU_OK; }
+    if (k == "nstreams") { *value = h->nstreams; return ILU_OK; }
+    if (k == "factor_tcap") { *value = h->factor_tcap; return ILU_OK; }
+    return fail(ILU_ERR_ARG, "ilu_get_tuning: unknown key " + k);
 }
 
 // -------------------------------------------------------------------------------------

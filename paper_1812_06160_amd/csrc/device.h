@@ -63,6 +63,7 @@ struct FactorArgs {
     Claims claims;
     int32_t nstreams;
     int32_t tcap;         // LDS entries per group for the dependency rows (0: no staging)
+    int32_t poll_sleep;   // s_sleep(1) steps between polls of a pending value
 };
 
 struct SolveArgs {
@@ -71,8 +72,8 @@ struct SolveArgs {
     const void *val;          // TV[nnz]
     const int32_t *rows;      // row list (nullptr: identity)
     const int32_t *perm;      // nullptr: permuted space
-    const void *b;            // TX[n][ld]  (forward input)
-    void *x;                  // TX[n][ld]  (backward output)
+    const void *b;            // [n][ld] double or float (forward input)
+    void *x;                  // [n][ld] double or float (backward output)
     void *y;                  // TA[n][cap] forward intermediate (published)
     void *z;                  // TA[n][cap] backward intermediate (published)
     void *y_out;              // optional copy of y (TA) [n][ld], level ordering
@@ -80,11 +81,13 @@ struct SolveArgs {
     int64_t ld;
     int32_t cap;              // columns of the y/z buffers
     int32_t nrhs;
+    int32_t vec_f32;          // b and x are float (1) or double (0)
     int32_t unit_diag;        // forward: 1 (L), 0 (U^T); backward: 1 (L^T) or 0 (U)
     int32_t *info;
     int32_t row_begin, row_end;   // level-launch range over `rows` positions
     Claims claims;
     int32_t nstreams;
+    int32_t poll_sleep;
     const int32_t *vmap;      // optional value gather map (transposed views): val[vmap[p]]
 };
 

@@ -83,6 +83,7 @@ struct ilu_handle_s {
     bool counters_dirty[jv::kPasses] = {false, false, false, false, false};
     int32_t factor_tcap = 0;           // LDS staging entries per factor row (0: unstaged)
     int32_t nstreams = 1;              // task streams (one per XCD)
+    int32_t poll_sleep = 1;            // s_sleep(1) steps between polls (tunable)
     int8_t *d_xcc_stream = nullptr;    // XCC id -> stream
     std::vector<void *> allocs;
 

@@ -59,12 +59,12 @@ __device__ __forceinline__ int aborted(int32_t *info) {
 
 // Bounded wait until *p differs from the pending pattern.  On expiry (or when
 // another wave has expired) returns a quiet NaN; the host reports ILU_ERR_TIMEOUT.
-__device__ uint64_t wait_u64(const uint64_t *p, int32_t *info) {
+__device__ uint64_t wait_u64(const uint64_t *p, int32_t *info, int sleep) {
     uint64_t v = ld_acq_u64(p);
     if (v != kPending64) return v;
     int spins = 0;
     for (;;) {
-        __builtin_amdgcn_s_sleep(1);
+        for (int k = 0; k < sleep; ++k) __builtin_amdgcn_s_sleep(1);
         v = ld_acq_u64(p);
         if (v != kPending64) return v;
         if ((++spins & 31) == 0) {
@@ -77,12 +77,12 @@ __device__ uint64_t wait_u64(const uint64_t *p, int32_t *info) {
     }
 }
 
-__device__ uint32_t wait_u32(const uint32_t *p, int32_t *info) {
+__device__ uint32_t wait_u32(const uint32_t *p, int32_t *info, int sleep) {
     uint32_t v = ld_acq_u32(p);
     if (v != kPending32) return v;
     int spins = 0;
     for (;;) {
-        __builtin_amdgcn_s_sleep(1);
+        for (int k = 0; k < sleep; ++k) __builtin_amdgcn_s_sleep(1);
         v = ld_acq_u32(p);
         if (v != kPending32) return v;
         if ((++spins & 31) == 0) {
@@ -113,8 +113,8 @@ __device__ __forceinline__ T group_sum(T v) {
 // ---------------------------------------------------------------------------------
 template <typename TA> struct Pub;
 template <> struct Pub<double> {
-    __device__ static double wait(const double *p, int32_t *info) {
-        return __longlong_as_double((long long)wait_u64(reinterpret_cast<const uint64_t *>(p), info));
+    __device__ static double wait(const double *p, int32_t *info, int sleep) {
+        return __longlong_as_double((long long)wait_u64(reinterpret_cast<const uint64_t *>(p), info, sleep));
     }
     __device__ static void publish(double *p, double v) {
         uint64_t b = (uint64_t)__double_as_longlong(v);
@@ -124,8 +124,8 @@ template <> struct Pub<double> {
     __device__ static double pending() { return __longlong_as_double((long long)kPending64); }
 };
 template <> struct Pub<float> {
-    __device__ static float wait(const float *p, int32_t *info) {
-        return __uint_as_float(wait_u32(reinterpret_cast<const uint32_t *>(p), info));
+    __device__ static float wait(const float *p, int32_t *info, int sleep) {
+        return __uint_as_float(wait_u32(reinterpret_cast<const uint32_t *>(p), info, sleep));
     }
     __device__ static void publish(float *p, float v) {
         uint32_t b = __float_as_uint(v);
@@ -344,7 +344,7 @@ __device__ __forceinline__ void factor_row(const FactorArgs &A, int r, int t, in
             const int q = dc + t;
             ucol = A.ci[q];
             uabs = (A.use_flev && A.flev[q] > A.k) ? 1 : 0;
-            if constexpr (SF) uv = Pub<double>::wait(&A.lu[q], A.info);
+            if constexpr (SF) uv = Pub<double>::wait(&A.lu[q], A.info, A.poll_sleep);
             else uv = A.lu[q];
         }
         const double piv = __shfl(uv, 0, G);
@@ -405,7 +405,7 @@ __device__ __forceinline__ void factor_row_staged(const FactorArgs &A, int r, in
         const int q = sdc[e] + (j - soff[e]);
         sc[j] = (A.use_flev && A.flev[q] > A.k) ? -1 : A.ci[q];
         double uv;
-        if constexpr (SF) uv = Pub<double>::wait(&A.lu[q], A.info);
+        if constexpr (SF) uv = Pub<double>::wait(&A.lu[q], A.info, A.poll_sleep);
         else uv = A.lu[q];
         sv[j] = uv;
     }
@@ -486,8 +486,22 @@ __global__ __launch_bounds__(kBlock) void k_factor_syncfree(FactorArgs A) {
 // Backward: z_r = (y_r - sum_{c>r} a_rc z_c) [/ a_rr unless unit]; x = P^T z.
 // The y and z buffers keep the invariant "all pending" between applies: the
 // forward pass re-arms z[r], the backward pass re-arms y[r] after reading it.
-template <int G, typename TV, typename TX, typename TA, bool SF, bool FWD>
+template <typename TA>
+__device__ __forceinline__ TA load_vec(const void *v, int f32, int64_t i) {
+    return f32 ? (TA) static_cast<const float *>(v)[i] : (TA) static_cast<const double *>(v)[i];
+}
+template <typename TA>
+__device__ __forceinline__ void store_vec(void *v, int f32, int64_t i, TA x) {
+    if (f32) static_cast<float *>(v)[i] = (float)x;
+    else static_cast<double *>(v)[i] = (double)x;
+}
+
+// NR right-hand sides per pass: every lane accumulates all NR sums over its
+// entries (the NR values of one dependency row are adjacent in the [n][cap]
+// buffers), then lane t finishes right-hand sides t, t + G, ... of the batch.
+template <int G, int NR, typename TV, typename TA, bool SF, bool FWD>
 __device__ __forceinline__ void solve_row(const SolveArgs &A, int r, int t) {
+    constexpr int RPL = (NR + G - 1) / G;   // right-hand sides finished per lane
     const TV *val = static_cast<const TV *>(A.val);
     TA *y = static_cast<TA *>(A.y);
     TA *z = static_cast<TA *>(A.z);
@@ -497,49 +511,71 @@ __device__ __forceinline__ void solve_row(const SolveArgs &A, int r, int t) {
     TA *dep = FWD ? y : z;
     const int64_t cap = A.cap;
     const int out_row = A.perm ? A.perm[r] : r;
-    for (int s = 0; s < A.nrhs; ++s) {
-        TA acc = 0;
+    // everything that does not depend on other rows is loaded before the waits
+    const TA inv_piv = A.unit_diag ? (TA)1 : (TA)load_val(val, A.vmap ? A.vmap[d] : d);
+    for (int s0 = 0; s0 < A.nrhs; s0 += NR) {
+        const int nr = A.nrhs - s0 < NR ? A.nrhs - s0 : NR;
+        TA rhs[RPL];
+#pragma unroll
+        for (int m = 0; m < RPL; ++m) {
+            const int k = t + m * G;
+            rhs[m] = 0;
+            if (k < nr) {
+                if constexpr (FWD) rhs[m] = load_vec<TA>(A.b, A.vec_f32, (int64_t)out_row * A.ld + s0 + k);
+                else rhs[m] = y[(int64_t)r * cap + s0 + k];
+            }
+        }
+        TA acc[NR];
+#pragma unroll
+        for (int k = 0; k < NR; ++k) acc[k] = 0;
         for (int p = lo + t; p < hi; p += G) {
             const int c = A.ci[p];
             const TA a = (TA)load_val(val, A.vmap ? A.vmap[p] : p);
-            TA xc;
-            if constexpr (SF) xc = Pub<TA>::wait(&dep[(int64_t)c * cap + s], A.info);
-            else xc = dep[(int64_t)c * cap + s];
-            const TA prod = a * xc;
-            acc = acc + prod;
+            const TA *dc = dep + (int64_t)c * cap + s0;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                if (k < nr) {
+                    TA xc;
+                    if constexpr (SF) xc = Pub<TA>::wait(dc + k, A.info, A.poll_sleep);
+                    else xc = dc[k];
+                    const TA prod = a * xc;
+                    acc[k] = acc[k] + prod;
+                }
+            }
         }
-        acc = group_sum<G>(acc);
-        if (t == 0) {
-            TA rhs;
-            if constexpr (FWD) rhs = (TA)static_cast<const TX *>(A.b)[(int64_t)out_row * A.ld + s];
-            else rhs = y[(int64_t)r * cap + s];
-            TA v = rhs - acc;
-            if (!A.unit_diag) v = v / (TA)load_val(val, A.vmap ? A.vmap[d] : d);
-            if constexpr (FWD) {
-                if constexpr (SF) Pub<TA>::publish(&y[(int64_t)r * cap + s], v);
-                else y[(int64_t)r * cap + s] = v;
-                z[(int64_t)r * cap + s] = Pub<TA>::pending();
-                if (A.y_out) static_cast<TA *>(A.y_out)[(int64_t)r * A.ld + s] = v;
-            } else {
-                if constexpr (SF) Pub<TA>::publish(&z[(int64_t)r * cap + s], v);
-                else z[(int64_t)r * cap + s] = v;
-                y[(int64_t)r * cap + s] = Pub<TA>::pending();
-                static_cast<TX *>(A.x)[(int64_t)out_row * A.ld + s] = (TX)v;
-                if (A.z_out) static_cast<TA *>(A.z_out)[(int64_t)r * A.ld + s] = v;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            const TA sum = group_sum<G>(acc[k]);
+            if (k < nr && (k % G) == t) {
+                TA v = rhs[k / G] - sum;
+                if (!A.unit_diag) v = v / inv_piv;
+                const int64_t o = (int64_t)r * cap + s0 + k;
+                if constexpr (FWD) {
+                    if constexpr (SF) Pub<TA>::publish(&y[o], v);
+                    else y[o] = v;
+                    z[o] = Pub<TA>::pending();
+                    if (A.y_out) static_cast<TA *>(A.y_out)[(int64_t)r * A.ld + s0 + k] = v;
+                } else {
+                    if constexpr (SF) Pub<TA>::publish(&z[o], v);
+                    else z[o] = v;
+                    y[o] = Pub<TA>::pending();
+                    store_vec<TA>(A.x, A.vec_f32, (int64_t)out_row * A.ld + s0 + k, v);
+                    if (A.z_out) static_cast<TA *>(A.z_out)[(int64_t)r * A.ld + s0 + k] = v;
+                }
             }
         }
     }
 }
 
-template <int G, typename TV, typename TX, typename TA, bool FWD>
+template <int G, int NR, typename TV, typename TA, bool FWD>
 __global__ __launch_bounds__(kBlock) void k_solve_level(SolveArgs A) {
     const int pos = A.row_begin + (blockIdx.x * blockDim.x + threadIdx.x) / G;
     if (pos >= A.row_end) return;
     const int r = A.rows ? A.rows[pos] : pos;
-    solve_row<G, TV, TX, TA, false, FWD>(A, r, threadIdx.x % G);
+    solve_row<G, NR, TV, TA, false, FWD>(A, r, threadIdx.x % G);
 }
 
-template <int G, typename TV, typename TX, typename TA, bool FWD>
+template <int G, int NR, typename TV, typename TA, bool FWD>
 __global__ __launch_bounds__(kBlock) void k_solve_syncfree(SolveArgs A) {
     const int t = threadIdx.x % G;
     const int gi = (threadIdx.x & 63) / G;
@@ -547,7 +583,7 @@ __global__ __launch_bounds__(kBlock) void k_solve_syncfree(SolveArgs A) {
         const int pos = A.claims.task_ptr[task] + gi;
         if (pos < A.claims.task_ptr[task + 1]) {
             const int r = A.rows ? A.rows[pos] : pos;
-            solve_row<G, TV, TX, TA, true, FWD>(A, r, t);
+            solve_row<G, NR, TV, TA, true, FWD>(A, r, t);
         }
     });
 }
@@ -743,46 +779,48 @@ hipError_t probe_xcc_ids(int blocks, int32_t *host_ids) {
     return e;
 }
 
-template <int G, typename TV, typename TX, typename TA>
+template <int G, int NR, typename TV, typename TA>
 static hipError_t solve_dispatch3(const SolveArgs &A, bool fwd, bool syncfree, int grid, hipStream_t s) {
     if (syncfree) {
-        if (fwd) hipLaunchKernelGGL((k_solve_syncfree<G, TV, TX, TA, true>), dim3(grid), dim3(kBlock), 0, s, A);
-        else hipLaunchKernelGGL((k_solve_syncfree<G, TV, TX, TA, false>), dim3(grid), dim3(kBlock), 0, s, A);
+        if (fwd) hipLaunchKernelGGL((k_solve_syncfree<G, NR, TV, TA, true>), dim3(grid), dim3(kBlock), 0, s, A);
+        else hipLaunchKernelGGL((k_solve_syncfree<G, NR, TV, TA, false>), dim3(grid), dim3(kBlock), 0, s, A);
     } else {
         int64_t rows = A.row_end - A.row_begin;
         if (rows <= 0) return hipSuccess;
         dim3 g(grid_for(rows * G, kBlock));
-        if (fwd) hipLaunchKernelGGL((k_solve_level<G, TV, TX, TA, true>), g, dim3(kBlock), 0, s, A);
-        else hipLaunchKernelGGL((k_solve_level<G, TV, TX, TA, false>), g, dim3(kBlock), 0, s, A);
+        if (fwd) hipLaunchKernelGGL((k_solve_level<G, NR, TV, TA, true>), g, dim3(kBlock), 0, s, A);
+        else hipLaunchKernelGGL((k_solve_level<G, NR, TV, TA, false>), g, dim3(kBlock), 0, s, A);
     }
     return hipGetLastError();
 }
 
 template <int G, typename TV, typename TA>
-static hipError_t solve_dispatch2(const SolveArgs &A, bool fwd, int vec, bool syncfree, int grid, hipStream_t s) {
-    if (vec == 0) return solve_dispatch3<G, TV, double, TA>(A, fwd, syncfree, grid, s);
-    return solve_dispatch3<G, TV, float, TA>(A, fwd, syncfree, grid, s);
+static hipError_t solve_dispatch2(const SolveArgs &A, bool fwd, bool syncfree, int grid, hipStream_t s) {
+    if (A.nrhs == 1) return solve_dispatch3<G, 1, TV, TA>(A, fwd, syncfree, grid, s);
+    if (A.nrhs <= 4) return solve_dispatch3<G, 4, TV, TA>(A, fwd, syncfree, grid, s);
+    return solve_dispatch3<G, 16, TV, TA>(A, fwd, syncfree, grid, s);
 }
 
 template <int G>
-static hipError_t solve_dispatch1(const SolveArgs &A, bool fwd, int prec, int vec, bool syncfree, int grid,
-                                  hipStream_t s) {
+static hipError_t solve_dispatch1(const SolveArgs &A, bool fwd, int prec, bool syncfree, int grid, hipStream_t s) {
     switch (prec) {
-        case 0: return solve_dispatch2<G, double, double>(A, fwd, vec, syncfree, grid, s);
-        case 1: return solve_dispatch2<G, float, float>(A, fwd, vec, syncfree, grid, s);
-        case 2: return solve_dispatch2<G, uint16_t, float>(A, fwd, vec, syncfree, grid, s);
+        case 0: return solve_dispatch2<G, double, double>(A, fwd, syncfree, grid, s);
+        case 1: return solve_dispatch2<G, float, float>(A, fwd, syncfree, grid, s);
+        case 2: return solve_dispatch2<G, uint16_t, float>(A, fwd, syncfree, grid, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_solve(const SolveArgs &A, bool forward, int prec, int vec, int lanes, bool syncfree, int grid,
                         hipStream_t s) {
+    SolveArgs B = A;
+    B.vec_f32 = vec;
     switch (lanes) {
-        case 4: return solve_dispatch1<4>(A, forward, prec, vec, syncfree, grid, s);
-        case 8: return solve_dispatch1<8>(A, forward, prec, vec, syncfree, grid, s);
-        case 16: return solve_dispatch1<16>(A, forward, prec, vec, syncfree, grid, s);
-        case 32: return solve_dispatch1<32>(A, forward, prec, vec, syncfree, grid, s);
-        case 64: return solve_dispatch1<64>(A, forward, prec, vec, syncfree, grid, s);
+        case 4: return solve_dispatch1<4>(B, forward, prec, syncfree, grid, s);
+        case 8: return solve_dispatch1<8>(B, forward, prec, syncfree, grid, s);
+        case 16: return solve_dispatch1<16>(B, forward, prec, syncfree, grid, s);
+        case 32: return solve_dispatch1<32>(B, forward, prec, syncfree, grid, s);
+        case 64: return solve_dispatch1<64>(B, forward, prec, syncfree, grid, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -127,6 +127,14 @@ class Ilu:
         return dict(factor=inv[v[0].value], solve=inv[v[1].value], lanes_factor=v[2].value,
                     lanes_solve=v[3].value)
 
+    def set_tuning(self, key, value):
+        L.check(self.lib.ilu_set_tuning(self.h, key.encode(), int(value)), "ilu_set_tuning")
+
+    def get_tuning(self, key):
+        v = C.c_int64()
+        L.check(self.lib.ilu_get_tuning(self.h, key.encode(), C.byref(v)), "ilu_get_tuning")
+        return v.value
+
     # ---------------------------------------------------------------- numerics
     def factor(self, a_val: torch.Tensor, k=None, tau=0.0, casts=("f32", "bf16")):
         """ILU(k, tau) from device values in input order.  Raises IluError on failure
@@ -172,6 +180,10 @@ class Ilu:
         L.check(self.lib.ilu_apply(self.h, _ptr(b), _ptr(x), nrhs, ld, _PREC[prec], vec,
                                    L.PERMUTED_SPACE if permuted else 0, _stream()), "ilu_apply")
         return x
+
+    def apply_graph(self, b, x, prec="f64", permuted=False):
+        """An ApplyGraph replaying x = M^{-1} b (fixed tensors b and x)."""
+        return ApplyGraph(self, b, x, prec, permuted)
 
     def apply_ex(self, b, lu_val=None, want_y=True, permuted=False):
         nrhs, ld = _rhs_shape(b)
@@ -239,3 +251,30 @@ class Ilu:
         L.check(self.lib.ilu_tune(self.h, _ptr(a_val), int(reps), _np_ptr(res), 64, C.byref(nres), _stream()),
                 "ilu_tune")
         return res[:nres.value], self.get_schedule()
+
+
+class ApplyGraph:
+    """One captured ilu_apply (its launches in a HIP graph); launch() replays it on
+    the current stream.  Keeps b, x and the handle alive."""
+
+    def __init__(self, ilu, b, x, prec="f64", permuted=False):
+        self.ilu, self.b, self.x = ilu, b, x
+        nrhs, ld = _rhs_shape(b)
+        vec = L.PREC_F64 if b.dtype == torch.float64 else L.PREC_F32
+        self.g = C.c_void_p()
+        torch.cuda.current_stream().synchronize()
+        L.check(ilu.lib.ilu_apply_graph_create(ilu.h, _ptr(b), _ptr(x), nrhs, ld, _PREC[prec], vec,
+                                               L.PERMUTED_SPACE if permuted else 0, C.byref(self.g)),
+                "ilu_apply_graph_create")
+
+    def launch(self):
+        L.check(self.ilu.lib.ilu_graph_launch(self.g, _stream()), "ilu_graph_launch")
+        return self.x
+
+    def __del__(self):
+        try:
+            if self.g:
+                self.ilu.lib.ilu_graph_destroy(self.g)
+                self.g = C.c_void_p()
+        except Exception:
+            pass

@@ -1,0 +1,92 @@
+"""Full-size GPU parity in the launch configuration bench.py times (sync-free
+schedule, default lanes): the whole factor against the oracle bit for bit and
+whole solves against the oracle, on the BASELINE workloads."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def relerr(x, ref):
+    x = np.asarray(x).reshape(len(x), -1)
+    ref = np.asarray(ref).reshape(len(ref), -1)
+    return float(max(np.abs(x[:, s] - ref[:, s]).max() / np.abs(ref[:, s]).max() for s in range(ref.shape[1])))
+
+
+def test_laplace3d_128_full(jv):
+    A, b = synth.workload(2)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
+    ilu.factor(dev(A.val), casts=("f32",))
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    f = O.factor(an, A.val)
+    lu, st = ilu.factor_values()
+    assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
+    bp = np.ascontiguousarray(b[an.perm])
+    x = ilu.apply(dev(bp), permuted=True).cpu().numpy()
+    assert relerr(x, O.apply(an, f.val, bp, permuted=True)) <= 1e-12
+    y = ilu.spmv(dev(bp), permuted=True).cpu().numpy()
+    assert relerr(y, O.spmv(A.n, an.b_rp, an.b_ci, O.b_values(an, A.val), bp)) <= 1e-12
+    x, info = ilu.pcg(dev(b), rtol=1e-10)
+    assert info["true_relres"] <= 1e-10
+
+
+def test_convdiff3d_96_ilu1_full(jv):
+    A, b = synth.workload(3)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=1)
+    ilu.factor(dev(A.val), k=1, tau=1e-3, casts=("f32", "bf16"))
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=1)
+    f = O.factor(an, A.val, k=1, tau=1e-3)
+    lu, st = ilu.factor_values()
+    np.testing.assert_array_equal(st, f.stat)
+    assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
+    x = ilu.apply(dev(b)).cpu().numpy()
+    assert relerr(x, O.apply(an, f.val, b)) <= 1e-12
+    for prec in ("f64", "f32", "bf16"):
+        x, info = ilu.gmres(dev(b), rtol=1e-10, restart=30, prec=prec)
+        assert info["true_relres"] <= 1e-10, (prec, info)
+
+
+def test_random_1m_16rhs_full(jv):
+    A, B = synth.workload(4)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
+    ilu.factor(dev(A.val), casts=("f32",))
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    f = O.factor(an, A.val)
+    lu, _ = ilu.factor_values()
+    assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
+    # 4 of the 16 right-hand sides through the FP64 oracle (one oracle solve each)
+    x = ilu.apply(dev(B)).cpu().numpy()
+    cols = [0, 5, 10, 15]
+    xr = O.apply(an, f.val, np.ascontiguousarray(B[:, cols]))
+    assert relerr(x[:, cols], xr) <= 1e-12
+    B32 = B.astype(np.float32)
+    x32 = ilu.apply(dev(B32), prec="f32").cpu().numpy().astype(np.float64)
+    xr32 = O.apply(an, O.cast_f32(f.val), np.ascontiguousarray(B32[:, cols]).astype(np.float64), prec="f32")
+    assert relerr(x32[:, cols], xr32) <= 2.0 ** -12
+
+
+def test_batch512_full(jv):
+    mats, rhs = synth.workload(5)
+    hb = jv.Ilu.batched(mats)
+    vals = np.concatenate([m.val for m in mats])
+    hb.factor(dev(vals), casts=("f32",))
+    ro, _ = hb.batch_offsets()
+    b = np.concatenate(rhs)
+    x = hb.apply(dev(b)).cpu().numpy()
+    x32 = hb.apply(dev(b.astype(np.float32)), prec="f32").cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(0)
+    for i in sorted(rng.choice(len(mats), 12, replace=False)):
+        M = mats[i]
+        an = O.analyze(M.n, M.row_ptr, M.col_idx)
+        f = O.factor(an, M.val)
+        assert relerr(x[ro[i]:ro[i + 1]], O.apply(an, f.val, rhs[i])) <= 1e-12
+        xr32 = O.apply(an, O.cast_f32(f.val), rhs[i].astype(np.float32).astype(np.float64), prec="f32")
+        assert relerr(x32[ro[i]:ro[i + 1]], xr32) <= 2.0 ** -12

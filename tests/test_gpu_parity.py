@@ -388,3 +388,49 @@ def test_profile_counts(jv):
     p = ilu.profile_read()
     assert p["factor"][1] == 1 and p["forward"][1] == 1 and p["backward"][1] == 1 and p["spmv"][1] == 1
     assert all(v[0] > 0 for v in p.values())
+
+
+def test_multi_rhs_16_low_precision_vectors(jv):
+    # 16 right-hand sides, FP32 factor and FP32 vectors (the random-matrix workload recipe)
+    A = synth.random_banded(6000, rng=np.random.default_rng(18))
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
+    ilu.factor(dev(A.val), casts=("f32",))
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    f = O.factor(an, A.val)
+    b = np.random.default_rng(19).uniform(-1, 1, (A.n, 16)).astype(np.float32)
+    x = ilu.apply(dev(b), prec="f32").cpu().numpy().astype(np.float64)
+    xr = O.apply(an, O.cast_f32(f.val), b.astype(np.float64), prec="f32")
+    assert relerr(x, xr) <= 2.0 ** -17
+    x64 = ilu.apply(dev(b.astype(np.float64))).cpu().numpy()
+    assert relerr(x64, O.apply(an, f.val, b.astype(np.float64))) <= 1e-12
+    # 20 right-hand sides: one full batch of 16 and a partial one
+    b20 = np.random.default_rng(20).uniform(-1, 1, (A.n, 20))
+    assert relerr(ilu.apply(dev(b20)).cpu().numpy(), O.apply(an, f.val, b20)) <= 1e-12
+
+
+@pytest.mark.parametrize("sched", SCHEDS, ids=lambda s: s[0])
+def test_apply_graph_replays(jv, sched):
+    # a captured apply replayed several times, with eager work and new inputs between
+    # replays; every replay is checked against the eager result
+    mats, rhs = synth.workload(5, scale=0.1)
+    mats, rhs = mats[:16], rhs[:16]
+    hb = jv.Ilu.batched(mats)
+    hb.set_schedule(*sched)
+    vals = np.concatenate([m.val for m in mats])
+    hb.factor(dev(vals), casts=("f32",))
+    b0 = np.concatenate(rhs).astype(np.float32)
+    bt = dev(b0)
+    xt = torch.empty_like(bt)
+    g = hb.apply_graph(bt, xt, prec="f32")
+    rng = np.random.default_rng(21)
+    for it in range(4):
+        bnew = rng.uniform(-1, 1, b0.shape).astype(np.float32)
+        bt.copy_(dev(bnew))
+        g.launch()
+        torch.cuda.synchronize()
+        got = xt.cpu().numpy().copy()
+        want = hb.apply(dev(bnew), prec="f32").cpu().numpy()      # eager, in between replays
+        hb.spmv(dev(bnew.astype(np.float64)))                      # unrelated eager work
+        torch.cuda.synchronize()
+        assert np.array_equal(got, want), it
+    del g
