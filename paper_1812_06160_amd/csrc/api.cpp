@@ -475,6 +475,7 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
     A.row_tau = h->d_row_tau;
     A.info = h->d_info;
     A.tcap = factor_lds_bytes(lanes, h->factor_tcap) ? h->factor_tcap : 0;
+    A.max_lower = H.max_lower_lu;
     if (sf) {
         const TaskList *tl = h->task_list(kTasksForward, lanes);
         if (!tl) return fail(ILU_ERR_NOMEM, "ilu_factor: task list");

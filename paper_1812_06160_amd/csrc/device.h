@@ -24,8 +24,10 @@ enum : int {
     kInfoSlots = 8
 };
 
-// Bound on a single dependency wait (loop iterations, each >= one memory round trip).
-constexpr int kSpinLimit = 1 << 22;
+// Bound on a single dependency wait: 10 s of the 100 MHz realtime counter.  A
+// wait that long means a value that will never be published (the device abort
+// flag then stops every wait and the call reports ILU_ERR_TIMEOUT).
+constexpr uint64_t kWaitTicks = 1000000000ull;
 
 // Sync-free kernels take their work from task streams, one per XCD.  Each level's
 // tasks are cut into contiguous slices, slice x of every level going to stream x,
@@ -63,6 +65,7 @@ struct FactorArgs {
     Claims claims;
     int32_t nstreams;
     int32_t tcap;         // LDS entries per group for the dependency rows (0: no staging)
+    int32_t max_lower;    // longest strictly lower part of a row
     int32_t poll_sleep;   // s_sleep(1) steps between polls of a pending value
 };
 

@@ -23,7 +23,7 @@
 // or have finished; blocks claim slots when they start, so the smallest
 // unfinished task is always held by a running wave or claimed by the next block
 // that starts on its XCD, whatever the number of resident blocks.  Every wait
-// is bounded (kSpinLimit) and raises a device abort flag that stops all waits.
+// is bounded in time (kWaitTicks) and raises a device abort flag that stops all waits.
 //
 // Floating point: the library is compiled with -ffp-contract=off, so a - l*u is
 // a rounded multiply then a rounded subtract, and FP64 division is IEEE
@@ -57,19 +57,31 @@ __device__ __forceinline__ int aborted(int32_t *info) {
     return __hip_atomic_load(&info[kInfoAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Wall-clock bound of one wait: kWaitTicks of the 100 MHz realtime counter; the
+// first call starts the clock.
+__device__ __forceinline__ bool expired(uint64_t &t0) {
+    const uint64_t now = __builtin_amdgcn_s_memrealtime();
+    if (t0 == 0) {
+        t0 = now;
+        return false;
+    }
+    return now - t0 > kWaitTicks;
+}
+
 // Bounded wait until *p differs from the pending pattern.  On expiry (or when
 // another wave has expired) returns a quiet NaN; the host reports ILU_ERR_TIMEOUT.
 __device__ uint64_t wait_u64(const uint64_t *p, int32_t *info, int sleep) {
     uint64_t v = ld_acq_u64(p);
     if (v != kPending64) return v;
     int spins = 0;
+    uint64_t t0 = 0;
     for (;;) {
         for (int k = 0; k < sleep; ++k) __builtin_amdgcn_s_sleep(1);
         v = ld_acq_u64(p);
         if (v != kPending64) return v;
-        if ((++spins & 31) == 0) {
+        if ((++spins & 63) == 0) {
             if (aborted(info)) return kQNaN64;
-            if (spins > kSpinLimit) {
+            if (expired(t0)) {
                 __hip_atomic_store(&info[kInfoAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 return kQNaN64;
             }
@@ -81,13 +93,14 @@ __device__ uint32_t wait_u32(const uint32_t *p, int32_t *info, int sleep) {
     uint32_t v = ld_acq_u32(p);
     if (v != kPending32) return v;
     int spins = 0;
+    uint64_t t0 = 0;
     for (;;) {
         for (int k = 0; k < sleep; ++k) __builtin_amdgcn_s_sleep(1);
         v = ld_acq_u32(p);
         if (v != kPending32) return v;
-        if ((++spins & 31) == 0) {
+        if ((++spins & 63) == 0) {
             if (aborted(info)) return kQNaN32;
-            if (spins > kSpinLimit) {
+            if (expired(t0)) {
                 __hip_atomic_store(&info[kInfoAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 return kQNaN32;
             }
@@ -113,6 +126,10 @@ __device__ __forceinline__ T group_sum(T v) {
 // ---------------------------------------------------------------------------------
 template <typename TA> struct Pub;
 template <> struct Pub<double> {
+    using U = uint64_t;
+    static constexpr uint64_t kPend = kPending64;
+    __device__ static U load(const double *p) { return ld_acq_u64(reinterpret_cast<const uint64_t *>(p)); }
+    __device__ static double from(U b) { return __longlong_as_double((long long)b); }
     __device__ static double wait(const double *p, int32_t *info, int sleep) {
         return __longlong_as_double((long long)wait_u64(reinterpret_cast<const uint64_t *>(p), info, sleep));
     }
@@ -124,6 +141,10 @@ template <> struct Pub<double> {
     __device__ static double pending() { return __longlong_as_double((long long)kPending64); }
 };
 template <> struct Pub<float> {
+    using U = uint32_t;
+    static constexpr uint32_t kPend = kPending32;
+    __device__ static U load(const float *p) { return ld_acq_u32(reinterpret_cast<const uint32_t *>(p)); }
+    __device__ static float from(U b) { return __uint_as_float(b); }
     __device__ static float wait(const float *p, int32_t *info, int sleep) {
         return __uint_as_float(wait_u32(reinterpret_cast<const uint32_t *>(p), info, sleep));
     }
@@ -367,7 +388,15 @@ __device__ __forceinline__ void factor_row(const FactorArgs &A, int r, int t, in
     factor_finish<G, SF>(A, r, t, gi, p, act, col, absent, dropped, v, tr, d - rs);
 }
 
-template <int G, bool SF>
+// Staged row with the elimination split in three phases:
+//  gather  all dependency rows' upper parts (diagonal first) into LDS, with the
+//          loads of every lane issued together and re-polled together while pending;
+//  match   (no chain) lane t looks up, for every dependency e, the upper entry of
+//          row c_e in its own column and keeps it in a register (MAXL of them);
+//  chain   for e ascending: lane e divides by its pivot, the multiplier is
+//          broadcast, every lane with a match subtracts l * u -- the same
+//          operations in the same order as the unstaged form.
+template <int G, int MAXL, bool SF>
 __device__ __forceinline__ void factor_row_staged(const FactorArgs &A, int r, int t, int gi, double *sv, int *sc,
                                                   int *soff, int *sdc) {
     const int rs = A.rp[r], re = A.rp[r + 1], d = A.diag[r];
@@ -399,7 +428,51 @@ __device__ __forceinline__ void factor_row_staged(const FactorArgs &A, int r, in
         sdc[t] = dc;
     }
     wave_sync_lds();
-    for (int j = t; j < total; j += G) {
+    // ---- gather: JM values per lane in one polling round, the rest one by one ----
+    constexpr int JM = 4;
+    uint64_t raw[JM];
+    int qs[JM];
+#pragma unroll
+    for (int m = 0; m < JM; ++m) {
+        const int j = t + m * G;
+        qs[m] = -1;
+        raw[m] = 0;
+        if (j < total) {
+            int e = 0;
+            while (e + 1 < nL && soff[e + 1] <= j) ++e;
+            const int q = sdc[e] + (j - soff[e]);
+            qs[m] = q;
+            sc[j] = (A.use_flev && A.flev[q] > A.k) ? -1 : A.ci[q];
+            if constexpr (SF) raw[m] = ld_acq_u64(reinterpret_cast<const uint64_t *>(&A.lu[q]));
+            else raw[m] = (uint64_t)__double_as_longlong(A.lu[q]);
+        }
+    }
+    if constexpr (SF) {
+        int spins = 0;
+        uint64_t t0 = 0;
+        for (;;) {
+            bool pending = false;
+#pragma unroll
+            for (int m = 0; m < JM; ++m) pending |= (qs[m] >= 0 && raw[m] == kPending64);
+            if (!pending) break;
+            for (int k = 0; k < A.poll_sleep; ++k) __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+            for (int m = 0; m < JM; ++m)
+                if (qs[m] >= 0 && raw[m] == kPending64)
+                    raw[m] = ld_acq_u64(reinterpret_cast<const uint64_t *>(&A.lu[qs[m]]));
+            if ((++spins & 63) == 0) {
+                if (aborted(A.info)) break;
+                if (expired(t0)) {
+                    __hip_atomic_store(&A.info[kInfoAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < JM; ++m)
+        if (qs[m] >= 0) sv[t + m * G] = __longlong_as_double((long long)raw[m]);
+    for (int j = t + JM * G; j < total; j += G) {
         int e = 0;
         while (e + 1 < nL && soff[e + 1] <= j) ++e;
         const int q = sdc[e] + (j - soff[e]);
@@ -410,27 +483,56 @@ __device__ __forceinline__ void factor_row_staged(const FactorArgs &A, int r, in
         sv[j] = uv;
     }
     wave_sync_lds();
-    for (int e = 0; e < nL; ++e) {
-        const int le = __shfl(len, e, G);
-        if (le == 0) continue;   // absent dependency (a kept one always holds its diagonal)
-        const int o = soff[e];
-        const double piv = sv[o];
-        if (t == e) {
-            v = v / piv;
-            if (A.use_tau && fabs(v) < tr) dropped = 1;
-        }
-        if (__shfl(dropped, e, G)) continue;
-        const double l = __shfl(v, e, G);
-        for (int j = 1; j < le; ++j) {
-            const int uc = sc[o + j];
-            const double uu = sv[o + j];
-            if (uc >= 0 && (uint64_t)__double_as_longlong(uu) != kDropped64 && col == uc && !absent) {
-                const double prod = l * uu;
-                v = v - prod;
+    // ---- match: off the elimination chain ----
+    const double mypiv = (t < nL && len > 0) ? sv[off] : 1.0;
+    double wv[MAXL];
+    uint64_t mmask = 0;
+#pragma unroll
+    for (int e = 0; e < MAXL; ++e) {
+        wv[e] = 0.0;
+        if (e < nL && act && !absent) {
+            const int oe = soff[e];
+            const int le = (e + 1 < nL ? soff[e + 1] : total) - oe;
+            // columns of U(c_e) ascend: binary search for this lane's column in [oe + 1, oe + le)
+            int lo = oe + 1, hi = oe + le;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (sc[mid] < col && sc[mid] >= 0) lo = mid + 1;
+                else if (sc[mid] < 0) {
+                    // absent entries keep their column order; read the true column
+                    const int q = sdc[e] + (mid - oe);
+                    if (A.ci[q] < col) lo = mid + 1;
+                    else hi = mid;
+                } else hi = mid;
+            }
+            if (lo < oe + le && sc[lo] == col) {
+                const double u = sv[lo];
+                if ((uint64_t)__double_as_longlong(u) != kDropped64) {
+                    wv[e] = u;
+                    mmask |= 1ull << e;
+                }
             }
         }
     }
     wave_sync_lds();   // the slice is reused by the group's next row
+    // ---- chain ----
+#pragma unroll
+    for (int e = 0; e < MAXL; ++e) {
+        if (e < nL) {                                   // uniform across the group
+            if (__shfl(len, e, G) != 0) {               // kept dependency
+                if (t == e) {
+                    v = v / mypiv;
+                    if (A.use_tau && fabs(v) < tr) dropped = 1;
+                }
+                const int de = __shfl(dropped, e, G);
+                const double l = __shfl(v, e, G);
+                if (!de && ((mmask >> e) & 1ull)) {
+                    const double prod = l * wv[e];
+                    v = v - prod;
+                }
+            }
+        }
+    }
     factor_finish<G, SF>(A, r, t, gi, p, act, col, absent, dropped, v, tr, d - rs);
 }
 
@@ -447,33 +549,34 @@ __device__ __forceinline__ void group_slices(int tcap, double *&sv, int *&sc, in
     sdc = soff + G;
 }
 
-template <int G, bool STAGE>
+// MAXL > 0: staged rows with at most MAXL strictly lower entries; MAXL == 0: unstaged
+template <int G, int MAXL>
 __global__ __launch_bounds__(kBlock) void k_factor_level(FactorArgs A) {
     const int gid = (blockIdx.x * blockDim.x + threadIdx.x) / G;
     const int t = threadIdx.x % G;
     const int gi = (threadIdx.x & 63) / G;
     const int r = A.row_begin + gid;
-    if constexpr (STAGE) {
+    if constexpr (MAXL > 0) {
         double *sv;
         int *sc, *soff, *sdc;
         group_slices<G>(A.tcap, sv, sc, soff, sdc);
-        if (r < A.row_end) factor_row_staged<G, false>(A, r, t, gi, sv, sc, soff, sdc);
+        if (r < A.row_end) factor_row_staged<G, MAXL, false>(A, r, t, gi, sv, sc, soff, sdc);
     } else {
         if (r < A.row_end) factor_row<G, false>(A, r, t, gi);
     }
 }
 
-template <int G, bool STAGE>
+template <int G, int MAXL>
 __global__ __launch_bounds__(kBlock) void k_factor_syncfree(FactorArgs A) {
     const int t = threadIdx.x % G;
     const int gi = (threadIdx.x & 63) / G;
     double *sv = nullptr;
     int *sc = nullptr, *soff = nullptr, *sdc = nullptr;
-    if constexpr (STAGE) group_slices<G>(A.tcap, sv, sc, soff, sdc);
+    if constexpr (MAXL > 0) group_slices<G>(A.tcap, sv, sc, soff, sdc);
     claim_task(A.claims, A.nstreams, [&](int task) {
         const int r = A.claims.task_ptr[task] + gi;
         if (r < A.claims.task_ptr[task + 1]) {
-            if constexpr (STAGE) factor_row_staged<G, true>(A, r, t, gi, sv, sc, soff, sdc);
+            if constexpr (MAXL > 0) factor_row_staged<G, MAXL, true>(A, r, t, gi, sv, sc, soff, sdc);
             else factor_row<G, true>(A, r, t, gi);
         }
     });
@@ -532,14 +635,27 @@ __device__ __forceinline__ void solve_row(const SolveArgs &A, int r, int t) {
             const int c = A.ci[p];
             const TA a = (TA)load_val(val, A.vmap ? A.vmap[p] : p);
             const TA *dc = dep + (int64_t)c * cap + s0;
+            if constexpr (SF) {
+                // all loads of the batch first, then wait only on values still pending
+                typename Pub<TA>::U raw[NR];
 #pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                if (k < nr) {
-                    TA xc;
-                    if constexpr (SF) xc = Pub<TA>::wait(dc + k, A.info, A.poll_sleep);
-                    else xc = dc[k];
-                    const TA prod = a * xc;
-                    acc[k] = acc[k] + prod;
+                for (int k = 0; k < NR; ++k) raw[k] = k < nr ? Pub<TA>::load(dc + k) : 0;
+#pragma unroll
+                for (int k = 0; k < NR; ++k) {
+                    if (k < nr) {
+                        TA xc = Pub<TA>::from(raw[k]);
+                        if (raw[k] == Pub<TA>::kPend) xc = Pub<TA>::wait(dc + k, A.info, A.poll_sleep);
+                        const TA prod = a * xc;
+                        acc[k] = acc[k] + prod;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < NR; ++k) {
+                    if (k < nr) {
+                        const TA prod = a * dc[k];
+                        acc[k] = acc[k] + prod;
+                    }
                 }
             }
         }
@@ -741,20 +857,28 @@ size_t factor_lds_bytes(int lanes, int tcap) {
     return b <= 48 * 1024 ? b : 0;
 }
 
-template <int G>
-static hipError_t factor_dispatch(const FactorArgs &A, bool syncfree, int grid, hipStream_t s) {
-    const size_t lds = A.tcap > 0 ? lds_bytes_g<G>(A.tcap) : 0;
+template <int G, int MAXL>
+static hipError_t factor_launch(const FactorArgs &A, bool syncfree, int grid, size_t lds, hipStream_t s) {
     if (syncfree) {
-        if (lds) hipLaunchKernelGGL((k_factor_syncfree<G, true>), dim3(grid), dim3(kBlock), lds, s, A);
-        else hipLaunchKernelGGL((k_factor_syncfree<G, false>), dim3(grid), dim3(kBlock), 0, s, A);
+        hipLaunchKernelGGL((k_factor_syncfree<G, MAXL>), dim3(grid), dim3(kBlock), lds, s, A);
     } else {
         int64_t rows = A.row_end - A.row_begin;
         if (rows <= 0) return hipSuccess;
-        dim3 g(grid_for(rows * G, kBlock));
-        if (lds) hipLaunchKernelGGL((k_factor_level<G, true>), g, dim3(kBlock), lds, s, A);
-        else hipLaunchKernelGGL((k_factor_level<G, false>), g, dim3(kBlock), 0, s, A);
+        hipLaunchKernelGGL((k_factor_level<G, MAXL>), dim3(grid_for(rows * G, kBlock)), dim3(kBlock), lds, s, A);
     }
     return hipGetLastError();
+}
+
+template <int G>
+static hipError_t factor_dispatch(const FactorArgs &A, bool syncfree, int grid, hipStream_t s) {
+    const size_t lds = A.tcap > 0 ? lds_bytes_g<G>(A.tcap) : 0;
+    const int ml = A.max_lower;
+    if (!lds || ml > 32) return factor_launch<G, 0>(A, syncfree, grid, 0, s);
+    if (ml <= 4) return factor_launch<G, 4>(A, syncfree, grid, lds, s);
+    if constexpr (G >= 8) if (ml <= 8) return factor_launch<G, 8>(A, syncfree, grid, lds, s);
+    if constexpr (G >= 16) if (ml <= 16) return factor_launch<G, 16>(A, syncfree, grid, lds, s);
+    if constexpr (G >= 32) return factor_launch<G, 32>(A, syncfree, grid, lds, s);
+    return factor_launch<G, 0>(A, syncfree, grid, 0, s);
 }
 
 hipError_t launch_factor(const FactorArgs &A, int lanes, bool syncfree, int grid, hipStream_t s) {
