@@ -197,6 +197,13 @@ def main():
                     launches=dom_cnt, avg_us=round(dom_ms * 1e3, 2),
                     bytes_per_launch=int(per_launch))
 
+    from paper_1812_06160_amd.calibrate import calibrate
+    calib = calibrate(1 << 30)
+    roofline["measured_read_gbs"] = calib["read_gbs"]
+    roofline["frac_of_measured"] = round(achieved / calib["read_gbs"], 4)
+    roofline["hop_ns"] = calib["hop_ns_same_xcd"]
+    roofline["latency_floor_us"] = round((info["n_levels"] if dom == "forward" else info["n_ulevels"])
+                                         * calib["hop_ns_same_xcd"] * 1e-3, 1) if dom in ("forward", "backward") else None
     out = dict(
         metric=METRIC, value=round(value, 2), unit="GB/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
         ms_per_step=round(1e3 * t_total / args.steps, 3), higher_is_better=True, scaling="weak",
@@ -218,6 +225,7 @@ def main():
                  f32_factor=dict(seconds=round(float(np.median([p[0] for p in pcg32])), 5),
                                  iters=pcg32[-1][1]["iters"], true_relres=pcg32[-1][1]["true_relres"])),
         analyze_s=round(t_analyze, 3),
+        calibration=calib,
     )
     out["pcg"]["speedup_f32_over_f64"] = round(out["pcg"]["f64"]["seconds"] / out["pcg"]["f32_factor"]["seconds"], 3)
     if not args.no_cpu_baseline:

@@ -305,6 +305,17 @@ ilu_status ilu_profile_enable(ilu_handle h, int32_t enable, int32_t capacity);
 ilu_status ilu_profile_read(ilu_handle h, double *ms, int64_t *launches);
 
 /* ---------------------------------------------------------------------------- */
+/* Calibration.                                                                   */
+/* ---------------------------------------------------------------------------- */
+
+/* Measures the floors of the current device (allocates and frees two buffers of
+ * `bytes`, 0 = 2 GiB; synchronous): results[0] stream-read GB/s, [1] copy GB/s
+ * (read + write bytes), [2] one published-value hop in ns between two blocks on
+ * one XCD, [3] the same across XCDs (-1 if a bounded wait expired), [4] cost of
+ * an empty kernel launch in us.  Up to `cap` values are written. */
+ilu_status ilu_calibrate(int64_t bytes, double *results, int32_t cap);
+
+/* ---------------------------------------------------------------------------- */
 /* Lifetime and diagnostics.                                                      */
 /* ---------------------------------------------------------------------------- */
 

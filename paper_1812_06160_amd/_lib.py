@@ -27,7 +27,7 @@ SYMBOLS = [
     "ilu_analyze", "ilu_analyze_batched", "ilu_batch_offsets", "ilu_get_info", "ilu_copy_schedule",
     "ilu_factor", "ilu_factor_values", "ilu_copy_factor", "ilu_copy_factor_prec", "ilu_apply", "ilu_apply_ex",
     "ilu_apply_adjoint", "ilu_apply_graph_create", "ilu_graph_launch", "ilu_graph_destroy", "ilu_spmv", "ilu_set_values", "ilu_solve_pcg", "ilu_solve_gmres",
-    "ilu_set_schedule", "ilu_get_schedule", "ilu_set_tuning", "ilu_get_tuning", "ilu_tune", "ilu_profile_enable", "ilu_profile_read",
+    "ilu_set_schedule", "ilu_get_schedule", "ilu_set_tuning", "ilu_get_tuning", "ilu_tune", "ilu_profile_enable", "ilu_profile_read", "ilu_calibrate",
     "ilu_destroy", "ilu_version",
     "ilu_status_str", "ilu_last_error",
 ]
@@ -100,6 +100,7 @@ def load(path: str = LIB_PATH):
         "ilu_tune": [H, vp, i32, vp, i32, vp, vp],
         "ilu_profile_enable": [H, i32, i32],
         "ilu_profile_read": [H, vp, vp],
+        "ilu_calibrate": [i64, vp, i32],
         "ilu_destroy": [H],
         "ilu_version": [],
         "ilu_status_str": [i32],
