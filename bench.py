@@ -31,6 +31,24 @@ sys.path.insert(0, ROOT)
 METRIC = "ILU factor + L/U apply GB/s & GMRES time to 1e-10, FP64 vs FP32-factor form"
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the solve kernels per launch on this workload, from two rocprofv3
+# --pmc passes (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) over one bench step,
+# scaled by what the same counters read for the calibration copy kernels.  Valid
+# only for the kernel source it was taken with: a different hash reports null.
+PMC_TRAFFIC = dict(
+    kernels_sha256="aa83d12660e54a44a8bab2e44da0ed1c0cd47e0ca86ce1869a0aec8469e23d91",
+    fetch_scale=1.9986, write_scale=0.9943,
+    forward=dict(f64=(129327, 35109), f32=(92342, 19516)),
+    backward=dict(f64=(133830, 51523), f32=(92480, 35930)),
+)
+
+
+def kernels_sha256():
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1812_06160_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -192,8 +210,14 @@ def main():
     else:
         per_launch = B64[dom]
     achieved = per_launch / (dom_ms * 1e-3) / 1e9
+    traffic = None
+    if dom in ("forward", "backward") and kernels_sha256() == PMC_TRAFFIC["kernels_sha256"]:
+        def scaled(fw):
+            return 1024.0 * (fw[0] * PMC_TRAFFIC["fetch_scale"] + fw[1] * PMC_TRAFFIC["write_scale"])
+        t = PMC_TRAFFIC[dom]
+        traffic = int((c64 * scaled(t["f64"]) + c32 * scaled(t["f32"])) / max(c64 + c32, 1))
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, kernel=dom,
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=dom,
                     launches=dom_cnt, avg_us=round(dom_ms * 1e3, 2),
                     bytes_per_launch=int(per_launch))
 
