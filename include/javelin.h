@@ -66,7 +66,10 @@ enum {
 enum {
     ILU_SCHED_AUTO = 0,       /* the handle's current choice (sync-free unless tuned otherwise) */
     ILU_SCHED_LEVEL = 1,      /* one kernel launch per level: the launch boundary is the barrier */
-    ILU_SCHED_SYNCFREE = 2    /* one launch for all levels; rows wait on per-row published values */
+    ILU_SCHED_SYNCFREE = 2,   /* one launch for all levels; rows wait on per-row published values */
+    ILU_SCHED_TILED = 3       /* solves only: one launch; rows grouped into tiles, one workgroup per
+                                 tile, dependencies inside a tile resolved in LDS (Sec. III's
+                                 point-to-point waits, kept on-chip where the tile allows) */
 };
 
 typedef struct ilu_handle_s *ilu_handle;
@@ -85,7 +88,8 @@ typedef struct {
     int32_t host_only;        /* 1: analysis on the host only, nothing uploaded (inspection and
                                  planning without a device); numeric calls then fail with
                                  ILU_ERR_STATE */
-    int32_t reserved[5];      /* must be 0 */
+    int32_t tile_rows;        /* rows per tile of the tiled solves (0 = default 4096; else 16..65536) */
+    int32_t reserved[4];      /* must be 0 */
 } ilu_analyze_opts;
 
 typedef struct {
@@ -99,7 +103,11 @@ typedef struct {
     int32_t level_min, level_max;   /* rows per forward level */
     double level_median;
     int32_t batch_count;      /* matrices in a batched handle (1 otherwise) */
-    int32_t reserved[7];
+    int32_t n_tiles;          /* tiles of the forward (L) tiled solve */
+    int32_t n_utiles;         /* tiles of the backward (U) tiled solve */
+    int32_t tile_rows;        /* rows per tile requested */
+    int32_t max_tile;         /* largest padded tile of either direction (LDS slots) */
+    int32_t reserved[3];
 } ilu_info;
 
 typedef struct {
@@ -152,6 +160,17 @@ ilu_status ilu_copy_schedule(ilu_handle h, int32_t *level_ptr, int32_t *perm, in
                              int32_t *lu_col_idx, int32_t *diag_pos, int32_t *ulevel_ptr,
                              int32_t *ulevel_rows, int8_t *fill_lev, int32_t *lu_src,
                              int32_t *b_row_ptr, int32_t *b_col_idx);
+
+/* Copies the tiles of one solve direction (dir 0: L, 1: U) to host arrays; any
+ * pointer may be NULL.  Tiles are numbered in a topological order of that
+ * direction's dependency graph; tile t holds positions [tile_ptr[t],
+ * tile_ptr[t+1]) of tile_row (rows in the level ordering sorted by local level
+ * inside the tile, -1 for padding that aligns each local level to 16 positions).
+ * sci (nnz_lu entries, shared by both directions) encodes each off-diagonal
+ * factor entry (r, c): the position of c inside r's tile when c lies in the same
+ * tile of the direction that reads it, else ~c; diagonal entries hold ~r.
+ * Sizes: tile_ptr n_tiles+1 (n_utiles+1 for dir 1), tile_row tile_ptr[last]. */
+ilu_status ilu_copy_tiles(ilu_handle h, int32_t dir, int32_t *tile_ptr, int32_t *tile_row, int32_t *sci);
 
 /* ---------------------------------------------------------------------------- */
 /* Numeric factor (Sec. III, Fig. 1).                                            */
@@ -268,7 +287,9 @@ ilu_status ilu_get_schedule(ilu_handle h, int32_t *factor_sched, int32_t *solve_
                             int32_t *lanes_factor, int32_t *lanes_solve);
 
 /* Named tuning knobs.  Settable: "poll_sleep" (0..64, pause steps of about 64
- * clocks between polls of a value that is still pending).  Readable as well:
+ * clocks between polls of a value that is still pending), "tile_rows" (16..65536,
+ * rebuilds the tiles of the tiled solves on the host and uploads them;
+ * synchronous).  Readable as well:
  * "nstreams" (task streams = XCDs found), "factor_tcap" (LDS entries staged per
  * factor row).  Unknown keys give ILU_ERR_ARG. */
 ilu_status ilu_set_tuning(ilu_handle h, const char *key, int64_t value);

@@ -18,13 +18,13 @@ ERR_NOCONV, ERR_BREAKDOWN, ERR_STATE, ERR_UNSUPPORTED, ERR_TIMEOUT = 7, 8, 9, 10
 PATTERN_LOWER_SYM, PATTERN_LOWER_A = 0, 1
 PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
 PERMUTED_SPACE = 1
-SCHED_AUTO, SCHED_LEVEL, SCHED_SYNCFREE = 0, 1, 2
+SCHED_AUTO, SCHED_LEVEL, SCHED_SYNCFREE, SCHED_TILED = 0, 1, 2, 3
 STAGE_FACTOR, STAGE_FORWARD, STAGE_BACKWARD, STAGE_SPMV, STAGE_COUNT = 0, 1, 2, 3, 4
 STAGES = ["factor", "forward", "backward", "spmv"]
 
 # exported symbols that include/javelin.h declares
 SYMBOLS = [
-    "ilu_analyze", "ilu_analyze_batched", "ilu_batch_offsets", "ilu_get_info", "ilu_copy_schedule",
+    "ilu_analyze", "ilu_analyze_batched", "ilu_batch_offsets", "ilu_get_info", "ilu_copy_schedule", "ilu_copy_tiles",
     "ilu_factor", "ilu_factor_values", "ilu_copy_factor", "ilu_copy_factor_prec", "ilu_apply", "ilu_apply_ex",
     "ilu_apply_adjoint", "ilu_apply_graph_create", "ilu_graph_launch", "ilu_graph_destroy", "ilu_spmv", "ilu_set_values", "ilu_solve_pcg", "ilu_solve_gmres",
     "ilu_set_schedule", "ilu_get_schedule", "ilu_set_tuning", "ilu_get_tuning", "ilu_tune", "ilu_profile_enable", "ilu_profile_read", "ilu_calibrate",
@@ -39,14 +39,16 @@ class Csr(C.Structure):
 
 class AnalyzeOpts(C.Structure):
     _fields_ = [("k_max", C.c_int32), ("pattern", C.c_int32), ("host_only", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("tile_rows", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 class Info(C.Structure):
     _fields_ = [("n", C.c_int32), ("n_levels", C.c_int32), ("n_ulevels", C.c_int32),
                 ("max_row_lu", C.c_int32), ("nnz_a", C.c_int64), ("nnz_lu", C.c_int64),
                 ("nnz_b", C.c_int64), ("level_min", C.c_int32), ("level_max", C.c_int32),
-                ("level_median", C.c_double), ("batch_count", C.c_int32), ("reserved", C.c_int32 * 7)]
+                ("level_median", C.c_double), ("batch_count", C.c_int32), ("n_tiles", C.c_int32),
+                ("n_utiles", C.c_int32), ("tile_rows", C.c_int32), ("max_tile", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class FactorInfo(C.Structure):
@@ -79,6 +81,7 @@ def load(path: str = LIB_PATH):
         "ilu_batch_offsets": [H, vp, vp],
         "ilu_get_info": [H, C.POINTER(Info)],
         "ilu_copy_schedule": [H] + [vp] * 11,
+        "ilu_copy_tiles": [H, i32, vp, vp, vp],
         "ilu_factor": [H, vp, i32, f64, i32, C.POINTER(FactorInfo), vp],
         "ilu_factor_values": [H, i32, C.POINTER(vp)],
         "ilu_copy_factor": [H, vp, vp],

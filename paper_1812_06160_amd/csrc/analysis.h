@@ -45,6 +45,29 @@ struct HostAnalysis {
     std::vector<int32_t> tlevel_ptr, tlevel_rows, tulevel_ptr, tulevel_rows;
 };
 
+// Tiles of one triangular-solve direction (dir 0: L, columns < r; dir 1: U,
+// columns > r).  A tile is a set of rows that one workgroup solves with its
+// values held in LDS; tiles are numbered in a topological order of the
+// direction's dependency graph (every dependency of a row lies in an earlier tile
+// or in the same tile).  Inside a tile, rows are sorted by local level (longest
+// path over dependencies inside the tile) and every local level is padded with -1
+// to a multiple of `unit` positions, so no run of `unit` consecutive positions
+// mixes two local levels.
+struct TileSet {
+    int32_t cap = 0;                   // rows per tile requested (last tile may be smaller)
+    int32_t unit = 0;                  // positions per wave chunk
+    int32_t ntiles = 0;
+    int32_t max_tile = 0;              // largest padded tile (LDS slots)
+    std::vector<int32_t> ptr;          // [ntiles + 1] padded positions
+    std::vector<int32_t> row;          // row (level ordering) at each position, -1 for padding
+};
+
+// Builds both directions' tiles and the solve column encoding: for every factor
+// entry p = (r, c) with c != r, sci[p] = slot of c inside r's tile (c in the same
+// tile of that direction) or ~c.  Diagonal entries get ~r.
+void build_tiles(const HostAnalysis &H, int32_t cap, int32_t unit, TileSet *fwd, TileSet *bwd,
+                 std::vector<int32_t> *sci);
+
 // Returns ILU_OK or an error status with a message in *err.
 ilu_status analyze_host(int32_t n, const int32_t *rp, const int32_t *ci, int64_t nnz, int32_t k_max,
                         int32_t pattern, HostAnalysis *out, std::string *err);

@@ -198,7 +198,8 @@ hipError_t ilu_handle_s::reset_info(hipStream_t s) {
     return hipMemcpyAsync(d_info, init, sizeof(init), hipMemcpyHostToDevice, s);
 }
 
-static const int kComplement[kPasses] = {-1, kPassBackward, kPassForward, kPassTBackward, kPassTForward};
+static const int kComplement[kPasses] = {-1,          kPassBackward, kPassForward, kPassTBackward,
+                                         kPassTForward, kPassTileB,   kPassTileF};
 
 hipError_t ilu_handle_s::prepare_claims(int pass, const TaskList *tl, Claims *c, hipStream_t s) {
     int32_t *mine = d_counters + (size_t)pass * kStreams * kCounterStride;
@@ -216,6 +217,51 @@ hipError_t ilu_handle_s::prepare_claims(int pass, const TaskList *tl, Claims *c,
     counters_dirty[pass] = true;
     if (comp >= 0) counters_dirty[comp] = false;
     return hipSuccess;
+}
+
+hipError_t ilu_handle_s::prepare_tile_claims(int pass, TileArgs *t, hipStream_t s) {
+    int32_t *mine = d_counters + (size_t)pass * kStreams * kCounterStride;
+    if (counters_dirty[pass]) {
+        hipError_t e = launch_zero_counters(mine, s);
+        if (e != hipSuccess) return e;
+    }
+    const int comp = kComplement[pass];
+    t->counter = mine;
+    t->zero_counter = comp >= 0 ? d_counters + (size_t)comp * kStreams * kCounterStride : nullptr;
+    counters_dirty[pass] = true;
+    if (comp >= 0) counters_dirty[comp] = false;
+    return hipSuccess;
+}
+
+ilu_status ilu_handle_s::make_tiles(int32_t rows) {
+    try {
+        build_tiles(H, rows, kTileUnit, &tiles[0], &tiles[1], &sci);
+    } catch (const std::bad_alloc &) {
+        return fail(ILU_ERR_NOMEM, "tiles: out of host memory");
+    }
+    tile_rows = rows;
+    if (host_only) return ILU_OK;
+    auto drop = [&](int32_t *&d) {
+        if (d) {
+            (void)hipFree(d);
+            allocs_erase(this, d);
+            d = nullptr;
+        }
+    };
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "tiles: synchronize");
+    for (int dir = 0; dir < 2; ++dir) {
+        drop(d_tile_ptr[dir]);
+        drop(d_tile_row[dir]);
+        if ((e = upload(&d_tile_ptr[dir], tiles[dir].ptr)) != hipSuccess) return hip_fail(e, "tiles: upload");
+        if (d_tile_ptr[dir]) allocs.push_back(d_tile_ptr[dir]);
+        if ((e = upload(&d_tile_row[dir], tiles[dir].row)) != hipSuccess) return hip_fail(e, "tiles: upload");
+        if (d_tile_row[dir]) allocs.push_back(d_tile_row[dir]);
+    }
+    drop(d_sci);
+    if ((e = upload(&d_sci, sci)) != hipSuccess) return hip_fail(e, "tiles: upload");
+    if (d_sci) allocs.push_back(d_sci);
+    return ILU_OK;
 }
 
 // XCC ids present on the current device (one probe per process): id -> stream
@@ -322,8 +368,10 @@ extern "C" ilu_status ilu_analyze(const ilu_csr *A, const ilu_analyze_opts *opts
     *out = nullptr;
     ilu_analyze_opts o{};
     if (opts) o = *opts;
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 4; ++i)
         if (o.reserved[i]) return fail(ILU_ERR_ARG, "ilu_analyze: reserved option fields must be 0");
+    if (o.tile_rows != 0 && (o.tile_rows < 16 || o.tile_rows > 65536))
+        return fail(ILU_ERR_ARG, "ilu_analyze: tile_rows must be 0 or in [16, 65536]");
     if (o.host_only != 0 && o.host_only != 1) return fail(ILU_ERR_ARG, "ilu_analyze: host_only must be 0 or 1");
     if (A->n <= 0 || A->n >= (1 << 30)) return fail(ILU_ERR_ARG, "ilu_analyze: n must be in [1, 2^30)");
     std::unique_ptr<ilu_handle_s> h(new (std::nothrow) ilu_handle_s());
@@ -340,6 +388,7 @@ extern "C" ilu_status ilu_analyze(const ilu_csr *A, const ilu_analyze_opts *opts
     h->nnz_off = {0, A->nnz};
     h->host_only = o.host_only != 0;
     if (!h->host_only && (st = finish_analysis(h.get())) != ILU_OK) return st;
+    if ((st = h->make_tiles(o.tile_rows ? o.tile_rows : 4096)) != ILU_OK) return st;
     *out = h.release();
     return ILU_OK;
 }
@@ -406,6 +455,10 @@ extern "C" ilu_status ilu_get_info(ilu_handle h, ilu_info *out) {
     const size_t m = sizes.size();
     I.level_median = (m % 2) ? sizes[m / 2] : 0.5 * ((double)sizes[m / 2 - 1] + sizes[m / 2]);
     I.batch_count = h->batch_count;
+    I.n_tiles = h->tiles[0].ntiles;
+    I.n_utiles = h->tiles[1].ntiles;
+    I.tile_rows = h->tile_rows;
+    I.max_tile = std::max(h->tiles[0].max_tile, h->tiles[1].max_tile);
     *out = I;
     return ILU_OK;
 }
@@ -430,6 +483,16 @@ extern "C" ilu_status ilu_copy_schedule(ilu_handle h, int32_t *level_ptr, int32_
     cp(lu_src, H.lu_src);
     cp(b_row_ptr, H.b_rp);
     cp(b_col_idx, H.b_ci);
+    return ILU_OK;
+}
+
+extern "C" ilu_status ilu_copy_tiles(ilu_handle h, int32_t dir, int32_t *tile_ptr, int32_t *tile_row, int32_t *sci) {
+    if (!h) return fail(ILU_ERR_ARG, "ilu_copy_tiles: NULL handle");
+    if (dir != 0 && dir != 1) return fail(ILU_ERR_ARG, "ilu_copy_tiles: dir must be 0 or 1");
+    const TileSet &T = h->tiles[dir];
+    if (tile_ptr) std::copy(T.ptr.begin(), T.ptr.end(), tile_ptr);
+    if (tile_row) std::copy(T.row.begin(), T.row.end(), tile_row);
+    if (sci) std::copy(h->sci.begin(), h->sci.end(), sci);
     return ILU_OK;
 }
 
@@ -662,7 +725,24 @@ ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int 
             which = fwd ? kTasksTForward : kTasksTBackward;
             lptr = fwd ? &H.tlevel_ptr : &H.tulevel_ptr;
         }
-        if (sf) {
+        if (view == 0 && h->sched_solve == ILU_SCHED_TILED) {
+            const TileSet &T = h->tiles[fwd ? 0 : 1];
+            TileArgs ta{};
+            ta.tile_ptr = h->d_tile_ptr[fwd ? 0 : 1];
+            ta.tile_row = h->d_tile_row[fwd ? 0 : 1];
+            ta.sci = h->d_sci;
+            ta.ntiles = T.ntiles;
+            ta.lds_slots = T.max_tile;
+            if ((e = h->prepare_tile_claims(fwd ? kPassTileF : kPassTileB, &ta, s)) != hipSuccess)
+                return hip_fail(e, "tile claims");
+            A.poll_sleep = h->poll_sleep;
+            h->prof.begin(fwd ? ILU_STAGE_FORWARD : ILU_STAGE_BACKWARD, s);
+            e = launch_solve_tiled(A, ta, fwd, prec, vec, s);
+            h->prof.end(s);
+            if (e == hipErrorInvalidValue)
+                return fail(ILU_ERR_UNSUPPORTED, "tiled solve: the largest tile does not fit LDS (lower tile_rows)");
+            if (e != hipSuccess) return hip_fail(e, "tiled solve launch");
+        } else if (sf) {
             const TaskList *tl = h->task_list(which, lanes);
             if (!tl) return fail(ILU_ERR_NOMEM, "task list");
             const int pass = view == 0 ? (fwd ? kPassForward : kPassBackward) : (fwd ? kPassTForward : kPassTBackward);
@@ -876,7 +956,7 @@ static bool valid_lanes(int l) { return l == 0 || l == 4 || l == 8 || l == 16 ||
 extern "C" ilu_status ilu_set_schedule(ilu_handle h, int32_t factor_sched, int32_t solve_sched, int32_t lanes_factor,
                                        int32_t lanes_solve) {
     if (!h) return fail(ILU_ERR_ARG, "ilu_set_schedule: NULL handle");
-    if (factor_sched < 0 || factor_sched > 2 || solve_sched < 0 || solve_sched > 2 || !valid_lanes(lanes_factor) ||
+    if (factor_sched < 0 || factor_sched > 2 || solve_sched < 0 || solve_sched > 3 || !valid_lanes(lanes_factor) ||
         !valid_lanes(lanes_solve))
         return fail(ILU_ERR_ARG, "ilu_set_schedule: bad value");
     if (factor_sched) h->sched_factor = factor_sched;
@@ -908,6 +988,10 @@ extern "C" ilu_status ilu_set_tuning(ilu_handle h, const char *key, int64_t valu
         h->poll_sleep = (int32_t)value;
         return ILU_OK;
     }
+    if (k == "tile_rows") {
+        if (value < 16 || value > 65536) return fail(ILU_ERR_ARG, "ilu_set_tuning: tile_rows must be in [16, 65536]");
+        return h->make_tiles((int32_t)value);
+    }
     return fail(ILU_ERR_ARG, "ilu_set_tuning: unknown key " + k);
 }
 
@@ -917,6 +1001,7 @@ extern "C" ilu_status ilu_get_tuning(ilu_handle h, const char *key, int64_t *val
     if (k == "poll_sleep") { *value = h->poll_sleep; return ILU_OK; }
     if (k == "nstreams") { *value = h->nstreams; return ILU_OK; }
     if (k == "factor_tcap") { *value = h->factor_tcap; return ILU_OK; }
+    if (k == "tile_rows") { *value = h->tile_rows; return ILU_OK; }
     return fail(ILU_ERR_ARG, "ilu_get_tuning: unknown key " + k);
 }
 

@@ -94,6 +94,25 @@ struct SolveArgs {
     const int32_t *vmap;      // optional value gather map (transposed views): val[vmap[p]]
 };
 
+// Tiled solve: one workgroup per tile, tiles claimed in start order (tile order is
+// topological, so a block only waits on tiles of blocks that started earlier).
+// Values of rows inside the block's own tile go through LDS, others through the
+// published y/z buffers.
+struct TileArgs {
+    const int32_t *tile_ptr;  // [ntiles + 1] padded positions
+    const int32_t *tile_row;  // row at each position, -1 for padding
+    const int32_t *sci;       // per factor entry: LDS slot of the dependency (>= 0) or ~column
+    int32_t ntiles;
+    int32_t lds_slots;        // largest padded tile
+    int32_t *counter;         // claim counter of this pass
+    int32_t *zero_counter;    // counter of the complementary pass, cleared at launch (may be null)
+};
+
+// Rows per wave chunk of the tiled solve (64 lanes / kTileLanes lanes per row).
+constexpr int kTileLanes = 4;
+constexpr int kTileUnit = 64 / kTileLanes;
+constexpr int kTileLdsMax = 65536;    // dynamic LDS bytes a tiled launch may use
+
 struct SpmvArgs {
     int32_t n;
     const int32_t *rp, *ci;
@@ -123,6 +142,9 @@ hipError_t launch_cast_bf16(int64_t m, const double *x, uint16_t *y, hipStream_t
 hipError_t launch_solve(const SolveArgs &A, bool forward, int prec, int vec, int lanes, bool syncfree,
                         int grid, hipStream_t s);
 hipError_t launch_spmv(const SpmvArgs &A, int lanes, hipStream_t s);
+// tiled solve; returns hipErrorInvalidValue when no right-hand-side blocking fits LDS
+hipError_t launch_solve_tiled(const SolveArgs &A, const TileArgs &T, bool forward, int prec, int vec,
+                              hipStream_t s);
 // adjoint outer products on the factor pattern: for entry p = (i, j) of row i,
 // glu[p] = -sum_s W[i][s] x[perm[j]][s] (j >= i) or -sum_s Bp[i][s] y[j][s] (j < i)
 hipError_t launch_outer(int32_t n, const int32_t *rp, const int32_t *ci, const int32_t *perm, const double *W,

@@ -36,7 +36,10 @@ struct TaskList {
 };
 
 // claim-counter sets of the persistent passes
-enum { kPassFactor = 0, kPassForward = 1, kPassBackward = 2, kPassTForward = 3, kPassTBackward = 4, kPasses = 5 };
+enum {
+    kPassFactor = 0, kPassForward = 1, kPassBackward = 2, kPassTForward = 3, kPassTBackward = 4,
+    kPassTileF = 5, kPassTileB = 6, kPasses = 7
+};
 
 ilu_status fail(ilu_status s, const std::string &msg);
 ilu_status hip_fail(hipError_t e, const char *what);
@@ -78,9 +81,15 @@ struct ilu_handle_s {
     double *d_kry = nullptr;
 
     std::map<int, jv::TaskList> tasks;
+
+    // tiles of the tiled solves (direction 0: L, 1: U) and the solve column encoding
+    jv::TileSet tiles[2];
+    std::vector<int32_t> sci;
+    int32_t tile_rows = 4096;
+    int32_t *d_tile_ptr[2] = {nullptr, nullptr}, *d_tile_row[2] = {nullptr, nullptr}, *d_sci = nullptr;
     jv::Profiler prof;
     int32_t *d_counters = nullptr;     // kPasses sets of claim counters
-    bool counters_dirty[jv::kPasses] = {false, false, false, false, false};
+    bool counters_dirty[jv::kPasses] = {false, false, false, false, false, false, false};
     int32_t factor_tcap = 0;           // LDS staging entries per factor row (0: unstaged)
     int32_t nstreams = 1;              // task streams (one per XCD)
     int32_t poll_sleep = 1;            // s_sleep(1) steps between polls (tunable)
@@ -104,6 +113,10 @@ struct ilu_handle_s {
     hipError_t prepare_claims(int pass, const jv::TaskList *tl, jv::Claims *c, hipStream_t s);
     // blocks of a sync-free launch: every stream's slots plus one spare per stream
     int grid_syncfree(const jv::TaskList *tl) const { return nstreams * (tl->max_slots + 1); }
+    // (re)builds the tiles on the host and, unless host-only, uploads them
+    ilu_status make_tiles(int32_t rows);
+    // claim counter of a tiled pass (launching a counter reset when needed)
+    hipError_t prepare_tile_claims(int pass, jv::TileArgs *t, hipStream_t s);
 };
 
 inline void allocs_erase(ilu_handle_s *h, void *p) {

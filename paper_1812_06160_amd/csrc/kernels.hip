@@ -705,6 +705,170 @@ __global__ __launch_bounds__(kBlock) void k_solve_syncfree(SolveArgs A) {
 }
 
 // ---------------------------------------------------------------------------------
+// Tiled sync-free solve: one workgroup per tile, tile-local values in LDS
+// ---------------------------------------------------------------------------------
+// The value of every row of the block's tile lives in LDS slot (position in the
+// tile) until the tile is done; a row waits on the LDS word of a dependency in its
+// own tile and on the published y/z word of any other dependency.  Each LDS word
+// starts as the pending pattern, so (as in global memory) the value is its own
+// flag.  Wave w takes the chunks w, w + 4, ... of kTileUnit positions; a chunk
+// holds rows of one local level, and every dependency inside the tile sits in an
+// earlier chunk, so the lowest unfinished chunk can always proceed.
+
+template <typename TA>
+__device__ __forceinline__ typename Pub<TA>::U lds_ld(typename Pub<TA>::U *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename TA>
+__device__ __forceinline__ void lds_st(typename Pub<TA>::U *p, typename Pub<TA>::U v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename TA>
+__device__ __forceinline__ typename Pub<TA>::U bits_of(TA v);
+template <>
+__device__ __forceinline__ uint64_t bits_of<double>(double v) {
+    return v != v ? kQNaN64 : (uint64_t)__double_as_longlong(v);
+}
+template <>
+__device__ __forceinline__ uint32_t bits_of<float>(float v) {
+    return v != v ? kQNaN32 : __float_as_uint(v);
+}
+
+// Bounded wait on an LDS word (same expiry rule as the global waits).
+template <typename TA>
+__device__ TA lds_wait(typename Pub<TA>::U *p, int32_t *info) {
+    using U = typename Pub<TA>::U;
+    int spins = 0;
+    uint64_t t0 = 0;
+    for (;;) {
+        __builtin_amdgcn_s_sleep(1);
+        const U v = lds_ld<TA>(p);
+        if (v != Pub<TA>::kPend) return Pub<TA>::from(v);
+        if ((++spins & 63) == 0) {
+            if (aborted(info)) return Pub<TA>::from(sizeof(U) == 8 ? (U)kQNaN64 : (U)kQNaN32);
+            if (expired(t0)) {
+                __hip_atomic_store(&info[kInfoAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return Pub<TA>::from(sizeof(U) == 8 ? (U)kQNaN64 : (U)kQNaN32);
+            }
+        }
+    }
+}
+
+template <int G, int NR, typename TV, typename TA, bool FWD>
+__device__ __forceinline__ void tiled_row(const SolveArgs &A, const int32_t *__restrict__ sci,
+                                          typename Pub<TA>::U *lds, int r, int slot, int t, int s0, int nr) {
+    using U = typename Pub<TA>::U;
+    constexpr int RPL = (NR + G - 1) / G;
+    const TV *val = static_cast<const TV *>(A.val);
+    TA *y = static_cast<TA *>(A.y);
+    TA *z = static_cast<TA *>(A.z);
+    const int rs = A.rp[r], re = A.rp[r + 1], d = A.diag[r];
+    const int lo = FWD ? rs : d + 1;
+    const int hi = FWD ? d : re;
+    TA *dep = FWD ? y : z;
+    const int64_t cap = A.cap;
+    const int out_row = A.perm ? A.perm[r] : r;
+    const TA piv = A.unit_diag ? (TA)1 : (TA)load_val(val, d);
+    TA rhs[RPL];
+#pragma unroll
+    for (int m = 0; m < RPL; ++m) {
+        const int k = t + m * G;
+        rhs[m] = 0;
+        if (k < nr) {
+            if constexpr (FWD) rhs[m] = load_vec<TA>(A.b, A.vec_f32, (int64_t)out_row * A.ld + s0 + k);
+            else rhs[m] = y[(int64_t)r * cap + s0 + k];
+        }
+    }
+    TA acc[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) acc[k] = 0;
+    for (int p = lo + t; p < hi; p += G) {
+        const int enc = sci[p];
+        const TA a = (TA)load_val(val, p);
+        U raw[NR];
+        if (enc >= 0) {
+            U *src = lds + (int64_t)enc * NR;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) raw[k] = k < nr ? lds_ld<TA>(src + k) : 0;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                if (k < nr) {
+                    TA xc = Pub<TA>::from(raw[k]);
+                    if (raw[k] == Pub<TA>::kPend) xc = lds_wait<TA>(src + k, A.info);
+                    const TA prod = a * xc;
+                    acc[k] = acc[k] + prod;
+                }
+            }
+        } else {
+            const TA *dc = dep + (int64_t)(~enc) * cap + s0;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) raw[k] = k < nr ? Pub<TA>::load(dc + k) : 0;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                if (k < nr) {
+                    TA xc = Pub<TA>::from(raw[k]);
+                    if (raw[k] == Pub<TA>::kPend) xc = Pub<TA>::wait(dc + k, A.info, A.poll_sleep);
+                    const TA prod = a * xc;
+                    acc[k] = acc[k] + prod;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const TA sum = group_sum<G>(acc[k]);
+        if (k < nr && (k % G) == t) {
+            TA v = rhs[k / G] - sum;
+            if (!A.unit_diag) v = v / piv;
+            lds_st<TA>(lds + (int64_t)slot * NR + k, bits_of<TA>(v));
+            const int64_t o = (int64_t)r * cap + s0 + k;
+            if constexpr (FWD) {
+                Pub<TA>::publish(&y[o], v);
+                z[o] = Pub<TA>::pending();
+                if (A.y_out) static_cast<TA *>(A.y_out)[(int64_t)r * A.ld + s0 + k] = v;
+            } else {
+                Pub<TA>::publish(&z[o], v);
+                y[o] = Pub<TA>::pending();
+                store_vec<TA>(A.x, A.vec_f32, (int64_t)out_row * A.ld + s0 + k, v);
+                if (A.z_out) static_cast<TA *>(A.z_out)[(int64_t)r * A.ld + s0 + k] = v;
+            }
+        }
+    }
+}
+
+template <int NR, typename TV, typename TA, bool FWD>
+__global__ __launch_bounds__(kBlock) void k_solve_tiled(SolveArgs A, TileArgs T) {
+    using U = typename Pub<TA>::U;
+    constexpr int G = kTileLanes;
+    extern __shared__ __align__(16) unsigned char tile_smem[];
+    U *lds = reinterpret_cast<U *>(tile_smem);
+    __shared__ int s_tile;
+    if (threadIdx.x == 0) {
+        if (T.zero_counter && blockIdx.x == 0) T.zero_counter[0] = 0;
+        s_tile = __hip_atomic_fetch_add(T.counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const int tile = s_tile;
+    if (tile >= T.ntiles) return;
+    const int base = T.tile_ptr[tile];
+    const int cnt = T.tile_ptr[tile + 1] - base;   // a multiple of kTileUnit, <= lds_slots
+    const int wave = threadIdx.x >> 6;
+    const int gi = (threadIdx.x & 63) / G;
+    const int t = threadIdx.x % G;
+    for (int s0 = 0; s0 < A.nrhs; s0 += NR) {
+        const int nr = A.nrhs - s0 < NR ? A.nrhs - s0 : NR;
+        for (int i = threadIdx.x; i < cnt * NR; i += kBlock) lds[i] = Pub<TA>::kPend;
+        __syncthreads();
+        for (int c0 = wave * kTileUnit; c0 < cnt; c0 += (kBlock / 64) * kTileUnit) {
+            const int q = c0 + gi;
+            const int r = T.tile_row[base + q];
+            if (r >= 0) tiled_row<G, NR, TV, TA, FWD>(A, T.sci, lds, r, q, t, s0, nr);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------
 // spmv y = alpha A x + beta y (paper Sec. I-II), one row per group
 // ---------------------------------------------------------------------------------
 template <int G, bool PERM>
@@ -945,6 +1109,36 @@ hipError_t launch_solve(const SolveArgs &A, bool forward, int prec, int vec, int
         case 16: return solve_dispatch1<16>(B, forward, prec, syncfree, grid, s);
         case 32: return solve_dispatch1<32>(B, forward, prec, syncfree, grid, s);
         case 64: return solve_dispatch1<64>(B, forward, prec, syncfree, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int NR, typename TV, typename TA>
+static hipError_t tiled_launch(const SolveArgs &A, const TileArgs &T, bool fwd, hipStream_t s) {
+    const size_t lds = (size_t)T.lds_slots * NR * sizeof(TA);
+    if (lds > (size_t)kTileLdsMax) return hipErrorInvalidValue;
+    if (T.ntiles <= 0) return hipSuccess;
+    if (fwd) hipLaunchKernelGGL((k_solve_tiled<NR, TV, TA, true>), dim3(T.ntiles), dim3(kBlock), lds, s, A, T);
+    else hipLaunchKernelGGL((k_solve_tiled<NR, TV, TA, false>), dim3(T.ntiles), dim3(kBlock), lds, s, A, T);
+    return hipGetLastError();
+}
+
+// right-hand sides per pass: 4 when that blocking fits LDS, else 1
+template <typename TV, typename TA>
+static hipError_t tiled_dispatch(const SolveArgs &A, const TileArgs &T, bool fwd, hipStream_t s) {
+    if (A.nrhs > 1 && (size_t)T.lds_slots * 4 * sizeof(TA) <= (size_t)kTileLdsMax)
+        return tiled_launch<4, TV, TA>(A, T, fwd, s);
+    return tiled_launch<1, TV, TA>(A, T, fwd, s);
+}
+
+hipError_t launch_solve_tiled(const SolveArgs &A, const TileArgs &T, bool forward, int prec, int vec,
+                              hipStream_t s) {
+    SolveArgs B = A;
+    B.vec_f32 = vec;
+    switch (prec) {
+        case 0: return tiled_dispatch<double, double>(B, T, forward, s);
+        case 1: return tiled_dispatch<float, float>(B, T, forward, s);
+        case 2: return tiled_dispatch<uint16_t, float>(B, T, forward, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -1,0 +1,152 @@
+// Tiles of the triangular solves: greedy topological growth (host).
+//
+// The sync-free solve pays one global-memory hop (publish, then a poll on
+// another compute unit) for every dependency on its critical path.  Grouping rows
+// into tiles that one workgroup solves lets the dependencies inside a tile go
+// through LDS instead.  Tiles are grown by Kahn's algorithm on the direction's
+// dependency graph: the next row placed is the ready row with the most
+// dependencies already in the open tile (ties: lower level, then lower index),
+// or, when no ready row touches the open tile, the ready row of lowest level.  A
+// tile closes at `cap` rows.  Placement order is topological, so tile order is
+// too, which is what the kernel's start-ordered tile claims need to be free of
+// deadlock.  On grids in natural order the tiles come out as compact blocks
+// (cubes of side 8 or 16 for cap 512 or 4096 on 3D 7-point stencils) without any
+// coordinate information.
+#include <algorithm>
+#include <queue>
+#include <tuple>
+#include <vector>
+
+#include "analysis.h"
+
+namespace jv {
+
+namespace {
+
+void tiles_one(const HostAnalysis &H, int dir, int32_t cap, int32_t unit, TileSet *T, std::vector<int32_t> *sci) {
+    const int32_t n = H.n;
+    const std::vector<int32_t> &rp = H.lu_rp, &ci = H.lu_ci, &dg = H.diag;
+    auto dbeg = [&](int32_t r) { return dir == 0 ? rp[r] : dg[r] + 1; };
+    auto dend = [&](int32_t r) { return dir == 0 ? dg[r] : rp[r + 1]; };
+
+    // level of every row in this direction
+    std::vector<int32_t> lev(n, 0);
+    if (dir == 0) {
+        for (int32_t l = 0; l < H.n_levels; ++l)
+            for (int32_t q = H.level_ptr[l]; q < H.level_ptr[l + 1]; ++q) lev[q] = l;
+    } else {
+        for (int32_t l = 0; l < H.n_ulevels; ++l)
+            for (int32_t q = H.ulevel_ptr[l]; q < H.ulevel_ptr[l + 1]; ++q) lev[H.ulevel_rows[q]] = l;
+    }
+    // successor lists
+    std::vector<int32_t> sp(n + 1, 0), indeg(n, 0);
+    for (int32_t r = 0; r < n; ++r) {
+        indeg[r] = dend(r) - dbeg(r);
+        for (int32_t p = dbeg(r); p < dend(r); ++p) ++sp[ci[p] + 1];
+    }
+    for (int32_t i = 0; i < n; ++i) sp[i + 1] += sp[i];
+    std::vector<int32_t> sv(sp[n]), fill(sp.begin(), sp.end() - 1);
+    for (int32_t r = 0; r < n; ++r)
+        for (int32_t p = dbeg(r); p < dend(r); ++p) sv[fill[ci[p]]++] = r;
+
+    using Seed = std::pair<int32_t, int32_t>;                       // (level, row), smallest first
+    std::priority_queue<Seed, std::vector<Seed>, std::greater<Seed>> seed;
+    using Hot = std::tuple<int32_t, int32_t, int32_t>;              // (score, -level, -row), largest first
+    std::priority_queue<Hot> hot;
+    std::vector<int32_t> score(n, 0), touched, tile_of(n, -1), order;
+    std::vector<char> placed(n, 0);
+    order.reserve(n);
+    for (int32_t r = 0; r < n; ++r)
+        if (indeg[r] == 0) seed.push({lev[r], r});
+    int32_t cur = 0, size = 0;
+    while ((int32_t)order.size() < n) {
+        int32_t r = -1;
+        while (!hot.empty()) {
+            const int32_t x = -std::get<2>(hot.top());
+            hot.pop();
+            if (!placed[x]) {
+                r = x;
+                break;
+            }
+        }
+        while (r < 0) {   // the graph is acyclic, so an unplaced ready row exists
+            const int32_t x = seed.top().second;
+            seed.pop();
+            if (!placed[x]) r = x;
+        }
+        placed[r] = 1;
+        tile_of[r] = cur;
+        order.push_back(r);
+        ++size;
+        for (int32_t q = sp[r]; q < sp[r + 1]; ++q) {
+            const int32_t s = sv[q];
+            if (score[s]++ == 0) touched.push_back(s);
+            if (--indeg[s] == 0) {
+                seed.push({lev[s], s});
+                hot.push({score[s], -lev[s], -s});
+            }
+        }
+        if (size == cap) {
+            ++cur;
+            size = 0;
+            for (int32_t s : touched) score[s] = 0;
+            touched.clear();
+            hot = std::priority_queue<Hot>();
+        }
+    }
+    const int32_t ntiles = cur + (size > 0 ? 1 : 0);
+
+    // local levels (placement order is topological)
+    std::vector<int32_t> llev(n, 0);
+    for (int32_t r : order)
+        for (int32_t p = dbeg(r); p < dend(r); ++p) {
+            const int32_t c = ci[p];
+            if (tile_of[c] == tile_of[r]) llev[r] = std::max(llev[r], llev[c] + 1);
+        }
+    // per tile: rows by local level (stable in placement order), each level padded
+    T->cap = cap;
+    T->unit = unit;
+    T->ntiles = ntiles;
+    T->max_tile = 0;
+    T->ptr.assign(1, 0);
+    T->row.clear();
+    std::vector<int32_t> slot(n, -1);
+    size_t a = 0;
+    for (int32_t t = 0; t < ntiles; ++t) {
+        size_t b = a;
+        while (b < order.size() && tile_of[order[b]] == t) ++b;
+        std::vector<int32_t> rows(order.begin() + a, order.begin() + b);
+        std::stable_sort(rows.begin(), rows.end(), [&](int32_t x, int32_t y) { return llev[x] < llev[y]; });
+        const size_t base = T->row.size();
+        for (size_t i = 0; i < rows.size();) {
+            size_t j = i;
+            while (j < rows.size() && llev[rows[j]] == llev[rows[i]]) ++j;
+            for (size_t k = i; k < j; ++k) {
+                slot[rows[k]] = (int32_t)(T->row.size() - base);
+                T->row.push_back(rows[k]);
+            }
+            while ((T->row.size() - base) % unit) T->row.push_back(-1);
+            i = j;
+        }
+        T->ptr.push_back((int32_t)T->row.size());
+        T->max_tile = std::max<int32_t>(T->max_tile, (int32_t)(T->row.size() - base));
+        a = b;
+    }
+    for (int32_t r = 0; r < n; ++r)
+        for (int32_t p = dbeg(r); p < dend(r); ++p) {
+            const int32_t c = ci[p];
+            (*sci)[p] = tile_of[c] == tile_of[r] ? slot[c] : ~c;
+        }
+}
+
+}  // namespace
+
+void build_tiles(const HostAnalysis &H, int32_t cap, int32_t unit, TileSet *fwd, TileSet *bwd,
+                 std::vector<int32_t> *sci) {
+    sci->assign(H.lu_ci.size(), 0);
+    for (int32_t r = 0; r < H.n; ++r) (*sci)[H.diag[r]] = ~r;
+    tiles_one(H, 0, cap, unit, fwd, sci);
+    tiles_one(H, 1, cap, unit, bwd, sci);
+}
+
+}  // namespace jv

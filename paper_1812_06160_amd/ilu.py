@@ -27,7 +27,7 @@ def _np_ptr(a):
 
 
 _PREC = {"f64": L.PREC_F64, "f32": L.PREC_F32, "bf16": L.PREC_BF16}
-_SCHED = {"auto": L.SCHED_AUTO, "level": L.SCHED_LEVEL, "syncfree": L.SCHED_SYNCFREE}
+_SCHED = {"auto": L.SCHED_AUTO, "level": L.SCHED_LEVEL, "syncfree": L.SCHED_SYNCFREE, "tiled": L.SCHED_TILED}
 
 
 def _rhs_shape(t):
@@ -42,7 +42,7 @@ class Ilu:
     """Analysis handle: ILU(k_max) pattern, level schedule and permuted structure of A."""
 
     def __init__(self, n=None, row_ptr=None, col_idx=None, k_max=0, pattern="sym", host_only=False,
-                 _handle=None):
+                 tile_rows=0, _handle=None):
         self.lib = L.load()
         self.h = C.c_void_p()
         if _handle is not None:
@@ -52,7 +52,7 @@ class Ilu:
             ci = np.ascontiguousarray(col_idx, dtype=np.int32)
             csr = L.Csr(int(n), int(rp[-1]), _np_ptr(rp), _np_ptr(ci))
             opts = L.AnalyzeOpts(int(k_max), L.PATTERN_LOWER_SYM if pattern == "sym" else L.PATTERN_LOWER_A,
-                                 1 if host_only else 0)
+                                 1 if host_only else 0, int(tile_rows))
             L.check(self.lib.ilu_analyze(C.byref(csr), C.byref(opts), C.byref(self.h)), "ilu_analyze")
         self._info = L.Info()
         L.check(self.lib.ilu_get_info(self.h, C.byref(self._info)), "ilu_get_info")
@@ -93,7 +93,8 @@ class Ilu:
         I = self._info
         return dict(n=I.n, n_levels=I.n_levels, n_ulevels=I.n_ulevels, max_row_lu=I.max_row_lu,
                     nnz_a=I.nnz_a, nnz_lu=I.nnz_lu, nnz_b=I.nnz_b, level_min=I.level_min,
-                    level_max=I.level_max, level_median=I.level_median, batch_count=I.batch_count)
+                    level_max=I.level_max, level_median=I.level_median, batch_count=I.batch_count,
+                    n_tiles=I.n_tiles, n_utiles=I.n_utiles, tile_rows=I.tile_rows, max_tile=I.max_tile)
 
     def schedule(self):
         I = self._info
@@ -109,6 +110,18 @@ class Ilu:
         L.check(self.lib.ilu_copy_schedule(self.h, *[_np_ptr(out[k]) for k in keys]), "ilu_copy_schedule")
         return out
 
+    def tiles(self, direction=0):
+        """Tiles of the tiled solve of one direction (0: L, 1: U): (tile_ptr, tile_row, sci)."""
+        I = self._info
+        nt = I.n_tiles if direction == 0 else I.n_utiles
+        ptr = np.empty(nt + 1, np.int32)
+        L.check(self.lib.ilu_copy_tiles(self.h, int(direction), _np_ptr(ptr), None, None), "ilu_copy_tiles")
+        row = np.empty(int(ptr[-1]), np.int32)
+        sci = np.empty(I.nnz_lu, np.int32)
+        L.check(self.lib.ilu_copy_tiles(self.h, int(direction), _np_ptr(ptr), _np_ptr(row), _np_ptr(sci)),
+                "ilu_copy_tiles")
+        return ptr, row, sci
+
     def batch_offsets(self):
         cnt = self._info.batch_count
         ro = np.empty(cnt + 1, np.int64)
@@ -123,12 +136,13 @@ class Ilu:
     def get_schedule(self):
         v = [C.c_int32() for _ in range(4)]
         L.check(self.lib.ilu_get_schedule(self.h, *[C.byref(x) for x in v]), "ilu_get_schedule")
-        inv = {1: "level", 2: "syncfree"}
+        inv = {1: "level", 2: "syncfree", 3: "tiled"}
         return dict(factor=inv[v[0].value], solve=inv[v[1].value], lanes_factor=v[2].value,
                     lanes_solve=v[3].value)
 
     def set_tuning(self, key, value):
         L.check(self.lib.ilu_set_tuning(self.h, key.encode(), int(value)), "ilu_set_tuning")
+        L.check(self.lib.ilu_get_info(self.h, C.byref(self._info)), "ilu_get_info")
 
     def get_tuning(self, key):
         v = C.c_int64()

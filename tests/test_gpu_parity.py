@@ -14,6 +14,9 @@ import synth
 pytestmark = pytest.mark.gpu
 
 SCHEDS = [("level", "level"), ("syncfree", "syncfree")]
+# solve schedules: the factor schedule is irrelevant to the apply; the tiled solve
+# is built with small tiles so that test matrices span several tiles (ragged last)
+SOLVE_SCHEDS = SCHEDS + [("syncfree", "tiled")]
 
 
 def dev(x):
@@ -27,8 +30,8 @@ def relerr(x, ref):
                      for s in range(ref.shape[1])))
 
 
-def make(jv, A, k_max=0, sym=True, sched=("syncfree", "syncfree")):
-    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=k_max, pattern="sym" if sym else "a")
+def make(jv, A, k_max=0, sym=True, sched=("syncfree", "syncfree"), tile_rows=256):
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=k_max, pattern="sym" if sym else "a", tile_rows=tile_rows)
     ilu.set_schedule(*sched)
     return ilu
 
@@ -147,7 +150,7 @@ APPLY_CASES = [
 ]
 
 
-@pytest.mark.parametrize("sched", SCHEDS, ids=lambda s: s[0])
+@pytest.mark.parametrize("sched", SOLVE_SCHEDS, ids=lambda s: s[1])
 @pytest.mark.parametrize("name,mk,k,tau", APPLY_CASES, ids=[c[0] for c in APPLY_CASES])
 @pytest.mark.parametrize("nrhs", [1, 3, 16])
 def test_apply_f64(jv, name, mk, k, tau, sched, nrhs):
@@ -173,7 +176,7 @@ def test_apply_f64(jv, name, mk, k, tau, sched, nrhs):
         assert relerr(ilu.apply(dev(b)).cpu().numpy(), xr) <= 1e-12
 
 
-@pytest.mark.parametrize("sched", SCHEDS, ids=lambda s: s[0])
+@pytest.mark.parametrize("sched", SOLVE_SCHEDS, ids=lambda s: s[1])
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 @pytest.mark.parametrize("vec", ["f64", "f32"])
 def test_apply_low_precision(jv, sched, prec, vec):
@@ -230,7 +233,7 @@ def test_spmv(jv, name, mk, k, tau):
     assert np.array_equal(ilu.spmv(dev(xi)).cpu().numpy(), O.spmv(A.n, A.row_ptr, A.col_idx, Ai, xi))
 
 
-@pytest.mark.parametrize("sched", SCHEDS, ids=lambda s: s[0])
+@pytest.mark.parametrize("sched", SOLVE_SCHEDS, ids=lambda s: s[1])
 def test_apply_integer_exact(jv, sched):
     rng = np.random.default_rng(12)
     A = synth.integer_unit_lower(400, 0.01, rng)
@@ -243,7 +246,7 @@ def test_apply_integer_exact(jv, sched):
     assert np.array_equal(x, O.apply(an, f.val, b))
 
 
-@pytest.mark.parametrize("sched", SCHEDS, ids=lambda s: s[0])
+@pytest.mark.parametrize("sched", SOLVE_SCHEDS, ids=lambda s: s[1])
 def test_pcg_and_gmres(jv, sched):
     A, b = synth.workload(1)
     ilu = make(jv, A, sched=sched)
@@ -408,7 +411,7 @@ def test_multi_rhs_16_low_precision_vectors(jv):
     assert relerr(ilu.apply(dev(b20)).cpu().numpy(), O.apply(an, f.val, b20)) <= 1e-12
 
 
-@pytest.mark.parametrize("sched", SCHEDS, ids=lambda s: s[0])
+@pytest.mark.parametrize("sched", SOLVE_SCHEDS, ids=lambda s: s[1])
 def test_apply_graph_replays(jv, sched):
     # a captured apply replayed several times, with eager work and new inputs between
     # replays; every replay is checked against the eager result
@@ -434,3 +437,48 @@ def test_apply_graph_replays(jv, sched):
         torch.cuda.synchronize()
         assert np.array_equal(got, want), it
     del g
+
+
+@pytest.mark.parametrize("tile_rows", [16, 100, 256, 4096])
+@pytest.mark.parametrize("name,mk,k,sym", [
+    ("laplace3d_20", lambda: synth.laplace3d(20), 0, True),
+    ("convdiff3d_12_ilu1", lambda: synth.convdiff3d(12), 1, True),
+    ("random_2500_lower_a", lambda: synth.random_banded(2500, rng=np.random.default_rng(9)), 0, False),
+    ("tridiag_777", lambda: synth.tridiag(777), 0, True),
+], ids=lambda v: v if isinstance(v, (str, int)) else "")
+def test_apply_tiled_tile_sizes(jv, name, mk, k, sym, tile_rows):
+    # tiles from 16 rows (most dependencies cross tiles) to one tile for the whole
+    # matrix (every dependency in LDS); FP64, one and five right-hand sides
+    A = mk()
+    ilu = make(jv, A, k, sym, ("syncfree", "tiled"), tile_rows=tile_rows)
+    ilu.factor(dev(A.val), k=k)
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k, sym=sym)
+    f = O.factor(an, A.val, k=k)
+    rng = np.random.default_rng(tile_rows)
+    for nrhs in (1, 5):
+        b = rng.uniform(-1, 1, (A.n, nrhs)) if nrhs > 1 else rng.uniform(-1, 1, A.n)
+        xr = O.apply(an, f.val, b)
+        for _ in range(2):
+            assert relerr(ilu.apply(dev(b)).cpu().numpy(), xr) <= 1e-12
+
+
+def test_apply_tiled_retune_and_lds_limit(jv):
+    A = synth.laplace3d(20)
+    ilu = make(jv, A, 0, True, ("syncfree", "tiled"), tile_rows=512)
+    ilu.factor(dev(A.val))
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    f = O.factor(an, A.val)
+    b = np.random.default_rng(17).uniform(-1, 1, A.n)
+    xr = O.apply(an, f.val, b)
+    assert relerr(ilu.apply(dev(b)).cpu().numpy(), xr) <= 1e-12
+    for t in (64, 8000):
+        ilu.set_tuning("tile_rows", t)
+        assert ilu.get_tuning("tile_rows") == t and ilu.info()["tile_rows"] == t
+        assert relerr(ilu.apply(dev(b)).cpu().numpy(), xr) <= 1e-12
+    # a tile whose values do not fit the LDS budget is refused, not run
+    big = synth.laplace3d(48)
+    ilu = make(jv, big, 0, True, ("syncfree", "tiled"), tile_rows=65536)
+    ilu.factor(dev(big.val))
+    with pytest.raises(jv.IluError) as e:
+        ilu.apply(dev(np.ones(big.n)))
+    assert e.value.code == 10   # ILU_ERR_UNSUPPORTED
