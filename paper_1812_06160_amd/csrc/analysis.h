@@ -57,14 +57,16 @@ struct TileSet {
     int32_t cap = 0;                   // rows per tile requested (last tile may be smaller)
     int32_t unit = 0;                  // positions per wave chunk
     int32_t ntiles = 0;
-    int32_t max_tile = 0;              // largest padded tile (LDS slots)
+    int32_t max_tile = 0;              // most rows in one tile (LDS slots)
     std::vector<int32_t> ptr;          // [ntiles + 1] padded positions
     std::vector<int32_t> row;          // row (level ordering) at each position, -1 for padding
+    std::vector<int32_t> rs;           // (row, slot) pairs per position, slot -1 for padding
 };
 
 // Builds both directions' tiles and the solve column encoding: for every factor
 // entry p = (r, c) with c != r, sci[p] = slot of c inside r's tile (c in the same
-// tile of that direction) or ~c.  Diagonal entries get ~r.
+// tile of that direction) or ~c.  Diagonal entries get ~r.  Slots number the
+// real rows of a tile in position order (padding takes no slot).
 void build_tiles(const HostAnalysis &H, int32_t cap, int32_t unit, TileSet *fwd, TileSet *bwd,
                  std::vector<int32_t> *sci);
 

@@ -252,11 +252,11 @@ ilu_status ilu_handle_s::make_tiles(int32_t rows) {
     if (e != hipSuccess) return hip_fail(e, "tiles: synchronize");
     for (int dir = 0; dir < 2; ++dir) {
         drop(d_tile_ptr[dir]);
-        drop(d_tile_row[dir]);
+        drop(d_tile_rs[dir]);
         if ((e = upload(&d_tile_ptr[dir], tiles[dir].ptr)) != hipSuccess) return hip_fail(e, "tiles: upload");
         if (d_tile_ptr[dir]) allocs.push_back(d_tile_ptr[dir]);
-        if ((e = upload(&d_tile_row[dir], tiles[dir].row)) != hipSuccess) return hip_fail(e, "tiles: upload");
-        if (d_tile_row[dir]) allocs.push_back(d_tile_row[dir]);
+        if ((e = upload(&d_tile_rs[dir], tiles[dir].rs)) != hipSuccess) return hip_fail(e, "tiles: upload");
+        if (d_tile_rs[dir]) allocs.push_back(d_tile_rs[dir]);
     }
     drop(d_sci);
     if ((e = upload(&d_sci, sci)) != hipSuccess) return hip_fail(e, "tiles: upload");
@@ -729,7 +729,7 @@ ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int 
             const TileSet &T = h->tiles[fwd ? 0 : 1];
             TileArgs ta{};
             ta.tile_ptr = h->d_tile_ptr[fwd ? 0 : 1];
-            ta.tile_row = h->d_tile_row[fwd ? 0 : 1];
+            ta.tile_rs = reinterpret_cast<const int2 *>(h->d_tile_rs[fwd ? 0 : 1]);
             ta.sci = h->d_sci;
             ta.ntiles = T.ntiles;
             ta.lds_slots = T.max_tile;

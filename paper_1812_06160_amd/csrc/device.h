@@ -100,10 +100,10 @@ struct SolveArgs {
 // published y/z buffers.
 struct TileArgs {
     const int32_t *tile_ptr;  // [ntiles + 1] padded positions
-    const int32_t *tile_row;  // row at each position, -1 for padding
+    const int2 *tile_rs;      // (row, LDS slot) at each position, (-1, -1) for padding
     const int32_t *sci;       // per factor entry: LDS slot of the dependency (>= 0) or ~column
     int32_t ntiles;
-    int32_t lds_slots;        // largest padded tile
+    int32_t lds_slots;        // most rows in one tile
     int32_t *counter;         // claim counter of this pass
     int32_t *zero_counter;    // counter of the complementary pass, cleared at launch (may be null)
 };

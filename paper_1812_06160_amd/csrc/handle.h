@@ -86,7 +86,7 @@ struct ilu_handle_s {
     jv::TileSet tiles[2];
     std::vector<int32_t> sci;
     int32_t tile_rows = 4096;
-    int32_t *d_tile_ptr[2] = {nullptr, nullptr}, *d_tile_row[2] = {nullptr, nullptr}, *d_sci = nullptr;
+    int32_t *d_tile_ptr[2] = {nullptr, nullptr}, *d_tile_rs[2] = {nullptr, nullptr}, *d_sci = nullptr;
     jv::Profiler prof;
     int32_t *d_counters = nullptr;     // kPasses sets of claim counters
     bool counters_dirty[jv::kPasses] = {false, false, false, false, false, false, false};

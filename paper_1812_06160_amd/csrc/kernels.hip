@@ -851,18 +851,17 @@ __global__ __launch_bounds__(kBlock) void k_solve_tiled(SolveArgs A, TileArgs T)
     const int tile = s_tile;
     if (tile >= T.ntiles) return;
     const int base = T.tile_ptr[tile];
-    const int cnt = T.tile_ptr[tile + 1] - base;   // a multiple of kTileUnit, <= lds_slots
+    const int cnt = T.tile_ptr[tile + 1] - base;   // positions: a multiple of kTileUnit
     const int wave = threadIdx.x >> 6;
     const int gi = (threadIdx.x & 63) / G;
     const int t = threadIdx.x % G;
     for (int s0 = 0; s0 < A.nrhs; s0 += NR) {
         const int nr = A.nrhs - s0 < NR ? A.nrhs - s0 : NR;
-        for (int i = threadIdx.x; i < cnt * NR; i += kBlock) lds[i] = Pub<TA>::kPend;
+        for (int i = threadIdx.x; i < T.lds_slots * NR; i += kBlock) lds[i] = Pub<TA>::kPend;
         __syncthreads();
         for (int c0 = wave * kTileUnit; c0 < cnt; c0 += (kBlock / 64) * kTileUnit) {
-            const int q = c0 + gi;
-            const int r = T.tile_row[base + q];
-            if (r >= 0) tiled_row<G, NR, TV, TA, FWD>(A, T.sci, lds, r, q, t, s0, nr);
+            const int2 rs = T.tile_rs[base + c0 + gi];
+            if (rs.x >= 0) tiled_row<G, NR, TV, TA, FWD>(A, T.sci, lds, rs.x, rs.y, t, s0, nr);
         }
         __syncthreads();
     }

@@ -110,6 +110,7 @@ void tiles_one(const HostAnalysis &H, int dir, int32_t cap, int32_t unit, TileSe
     T->max_tile = 0;
     T->ptr.assign(1, 0);
     T->row.clear();
+    T->rs.clear();
     std::vector<int32_t> slot(n, -1);
     size_t a = 0;
     for (int32_t t = 0; t < ntiles; ++t) {
@@ -118,18 +119,25 @@ void tiles_one(const HostAnalysis &H, int dir, int32_t cap, int32_t unit, TileSe
         std::vector<int32_t> rows(order.begin() + a, order.begin() + b);
         std::stable_sort(rows.begin(), rows.end(), [&](int32_t x, int32_t y) { return llev[x] < llev[y]; });
         const size_t base = T->row.size();
+        int32_t nslot = 0;
         for (size_t i = 0; i < rows.size();) {
             size_t j = i;
             while (j < rows.size() && llev[rows[j]] == llev[rows[i]]) ++j;
             for (size_t k = i; k < j; ++k) {
-                slot[rows[k]] = (int32_t)(T->row.size() - base);
+                slot[rows[k]] = nslot;
                 T->row.push_back(rows[k]);
+                T->rs.push_back(rows[k]);
+                T->rs.push_back(nslot++);
             }
-            while ((T->row.size() - base) % unit) T->row.push_back(-1);
+            while ((T->row.size() - base) % unit) {
+                T->row.push_back(-1);
+                T->rs.push_back(-1);
+                T->rs.push_back(-1);
+            }
             i = j;
         }
         T->ptr.push_back((int32_t)T->row.size());
-        T->max_tile = std::max<int32_t>(T->max_tile, (int32_t)(T->row.size() - base));
+        T->max_tile = std::max<int32_t>(T->max_tile, nslot);
         a = b;
     }
     for (int32_t r = 0; r < n; ++r)
