@@ -88,7 +88,8 @@ typedef struct {
     int32_t host_only;        /* 1: analysis on the host only, nothing uploaded (inspection and
                                  planning without a device); numeric calls then fail with
                                  ILU_ERR_STATE */
-    int32_t tile_rows;        /* rows per tile of the tiled solves (0 = default 4096; else 16..65536) */
+    int32_t tile_rows;        /* rows per tile of the tiled solves (0 = default: 512, halved until a
+                                 tile fits the LDS budget; else 16..65536, used as given) */
     int32_t reserved[4];      /* must be 0 */
 } ilu_analyze_opts;
 
@@ -106,7 +107,7 @@ typedef struct {
     int32_t n_tiles;          /* tiles of the forward (L) tiled solve */
     int32_t n_utiles;         /* tiles of the backward (U) tiled solve */
     int32_t tile_rows;        /* rows per tile requested */
-    int32_t max_tile;         /* most rows in one tile of either direction (LDS slots) */
+    int32_t max_tile;         /* most rows in one tile of either direction */
     int32_t reserved[3];
 } ilu_info;
 
@@ -167,9 +168,10 @@ ilu_status ilu_copy_schedule(ilu_handle h, int32_t *level_ptr, int32_t *perm, in
  * tile_ptr[t+1]) of tile_row (rows in the level ordering sorted by local level
  * inside the tile, -1 for padding that aligns each local level to 16 positions).
  * sci (nnz_lu entries, shared by both directions) encodes each off-diagonal
- * factor entry (r, c): the LDS slot of c (its rank among the real rows of the
- * tile, in position order) when c lies in r's tile of the direction that reads
- * it, else ~c; diagonal entries hold ~r.
+ * factor entry (r, c) by the LDS slot of c in r's tile of the direction that
+ * reads it: the slots of a tile are its rows in position order, then its imports
+ * (the distinct columns read from other tiles, in order of first use); diagonal
+ * entries hold -1.
  * Sizes: tile_ptr n_tiles+1 (n_utiles+1 for dir 1), tile_row tile_ptr[last]. */
 ilu_status ilu_copy_tiles(ilu_handle h, int32_t dir, int32_t *tile_ptr, int32_t *tile_row, int32_t *sci);
 

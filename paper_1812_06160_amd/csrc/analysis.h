@@ -53,20 +53,29 @@ struct HostAnalysis {
 // path over dependencies inside the tile) and every local level is padded with -1
 // to a multiple of `unit` positions, so no run of `unit` consecutive positions
 // mixes two local levels.
+//
+// LDS slots of a tile: its real rows in position order (0 .. rows-1), then its
+// imports (the distinct dependencies that lie in other tiles).  Every
+// off-diagonal entry of the direction is encoded by the slot of its column.
 struct TileSet {
     int32_t cap = 0;                   // rows per tile requested (last tile may be smaller)
     int32_t unit = 0;                  // positions per wave chunk
     int32_t ntiles = 0;
-    int32_t max_tile = 0;              // most rows in one tile (LDS slots)
+    int32_t max_rows = 0;              // most rows in one tile
+    int32_t max_slots = 0;             // most rows + imports in one tile
+    int32_t max_pos = 0;               // most positions (rows + padding) in one tile
+    int32_t kmax = 0;                  // longest dependency list of a row
     std::vector<int32_t> ptr;          // [ntiles + 1] padded positions
     std::vector<int32_t> row;          // row (level ordering) at each position, -1 for padding
-    std::vector<int32_t> rs;           // (row, slot) pairs per position, slot -1 for padding
+    std::vector<int32_t> rows_ptr;     // [ntiles + 1] offsets of each tile's rows in slot order
+    std::vector<int32_t> rows;         // rows of each tile in slot order
+    std::vector<int32_t> imp_ptr;      // [ntiles + 1] offsets of each tile's imports
+    std::vector<int32_t> imp;          // imported rows (slot rows + i holds imp[imp_ptr[t] + i])
 };
 
 // Builds both directions' tiles and the solve column encoding: for every factor
-// entry p = (r, c) with c != r, sci[p] = slot of c inside r's tile (c in the same
-// tile of that direction) or ~c.  Diagonal entries get ~r.  Slots number the
-// real rows of a tile in position order (padding takes no slot).
+// entry p = (r, c) with c != r, sci[p] = LDS slot of c in r's tile of the
+// direction that reads the entry; diagonal entries get -1.
 void build_tiles(const HostAnalysis &H, int32_t cap, int32_t unit, TileSet *fwd, TileSet *bwd,
                  std::vector<int32_t> *sci);
 

@@ -198,6 +198,8 @@ hipError_t ilu_handle_s::reset_info(hipStream_t s) {
     return hipMemcpyAsync(d_info, init, sizeof(init), hipMemcpyHostToDevice, s);
 }
 
+static const int32_t kDefaultTileRows = 512;
+
 static const int kComplement[kPasses] = {-1,          kPassBackward, kPassForward, kPassTBackward,
                                          kPassTForward, kPassTileB,   kPassTileF};
 
@@ -233,9 +235,18 @@ hipError_t ilu_handle_s::prepare_tile_claims(int pass, TileArgs *t, hipStream_t 
     return hipSuccess;
 }
 
-ilu_status ilu_handle_s::make_tiles(int32_t rows) {
+static bool tiles_fit(const TileSet &T) {
+    return tile_lds_bytes(T.max_rows, T.max_slots, T.max_pos, T.kmax, 1, 8) <= (size_t)kTileLdsMax &&
+           T.max_slots + 1 <= 65535 && T.max_pos <= 32767;
+}
+
+ilu_status ilu_handle_s::make_tiles(int32_t rows, bool shrink) {
     try {
-        build_tiles(H, rows, kTileUnit, &tiles[0], &tiles[1], &sci);
+        for (;;) {
+            build_tiles(H, rows, kTileUnit, &tiles[0], &tiles[1], &sci);
+            if (!shrink || rows <= 16 || (tiles_fit(tiles[0]) && tiles_fit(tiles[1]))) break;
+            rows /= 2;
+        }
     } catch (const std::bad_alloc &) {
         return fail(ILU_ERR_NOMEM, "tiles: out of host memory");
     }
@@ -248,19 +259,28 @@ ilu_status ilu_handle_s::make_tiles(int32_t rows) {
             d = nullptr;
         }
     };
+    auto put = [&](int32_t *&d, const std::vector<int32_t> &v) -> hipError_t {
+        drop(d);
+        hipError_t e = upload(&d, v);
+        if (e == hipSuccess && d) allocs.push_back(d);
+        return e;
+    };
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "tiles: synchronize");
     for (int dir = 0; dir < 2; ++dir) {
-        drop(d_tile_ptr[dir]);
-        drop(d_tile_rs[dir]);
-        if ((e = upload(&d_tile_ptr[dir], tiles[dir].ptr)) != hipSuccess) return hip_fail(e, "tiles: upload");
-        if (d_tile_ptr[dir]) allocs.push_back(d_tile_ptr[dir]);
-        if ((e = upload(&d_tile_rs[dir], tiles[dir].rs)) != hipSuccess) return hip_fail(e, "tiles: upload");
-        if (d_tile_rs[dir]) allocs.push_back(d_tile_rs[dir]);
+        const TileSet &T = tiles[dir];
+        std::vector<int32_t> pslot(T.row.size());
+        for (int32_t t = 0; t < T.ntiles; ++t) {
+            int32_t k = 0;
+            for (int32_t q = T.ptr[t]; q < T.ptr[t + 1]; ++q) pslot[q] = T.row[q] >= 0 ? k++ : -1;
+        }
+        DevTiles &D = dtiles[dir];
+        if ((e = put(D.ptr, T.ptr)) != hipSuccess || (e = put(D.pslot, pslot)) != hipSuccess ||
+            (e = put(D.rows_ptr, T.rows_ptr)) != hipSuccess || (e = put(D.rows, T.rows)) != hipSuccess ||
+            (e = put(D.imp_ptr, T.imp_ptr)) != hipSuccess || (e = put(D.imp, T.imp)) != hipSuccess)
+            return hip_fail(e, "tiles: upload");
     }
-    drop(d_sci);
-    if ((e = upload(&d_sci, sci)) != hipSuccess) return hip_fail(e, "tiles: upload");
-    if (d_sci) allocs.push_back(d_sci);
+    if ((e = put(d_sci, sci)) != hipSuccess) return hip_fail(e, "tiles: upload");
     return ILU_OK;
 }
 
@@ -388,7 +408,7 @@ extern "C" ilu_status ilu_analyze(const ilu_csr *A, const ilu_analyze_opts *opts
     h->nnz_off = {0, A->nnz};
     h->host_only = o.host_only != 0;
     if (!h->host_only && (st = finish_analysis(h.get())) != ILU_OK) return st;
-    if ((st = h->make_tiles(o.tile_rows ? o.tile_rows : 4096)) != ILU_OK) return st;
+    if ((st = h->make_tiles(o.tile_rows ? o.tile_rows : kDefaultTileRows, o.tile_rows == 0)) != ILU_OK) return st;
     *out = h.release();
     return ILU_OK;
 }
@@ -458,7 +478,7 @@ extern "C" ilu_status ilu_get_info(ilu_handle h, ilu_info *out) {
     I.n_tiles = h->tiles[0].ntiles;
     I.n_utiles = h->tiles[1].ntiles;
     I.tile_rows = h->tile_rows;
-    I.max_tile = std::max(h->tiles[0].max_tile, h->tiles[1].max_tile);
+    I.max_tile = std::max(h->tiles[0].max_rows, h->tiles[1].max_rows);
     *out = I;
     return ILU_OK;
 }
@@ -727,12 +747,20 @@ ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int 
         }
         if (view == 0 && h->sched_solve == ILU_SCHED_TILED) {
             const TileSet &T = h->tiles[fwd ? 0 : 1];
+            const ilu_handle_s::DevTiles &D = h->dtiles[fwd ? 0 : 1];
             TileArgs ta{};
-            ta.tile_ptr = h->d_tile_ptr[fwd ? 0 : 1];
-            ta.tile_rs = reinterpret_cast<const int2 *>(h->d_tile_rs[fwd ? 0 : 1]);
+            ta.tile_ptr = D.ptr;
+            ta.pslot = D.pslot;
+            ta.rows_ptr = D.rows_ptr;
+            ta.rows = D.rows;
+            ta.imp_ptr = D.imp_ptr;
+            ta.imp = D.imp;
             ta.sci = h->d_sci;
             ta.ntiles = T.ntiles;
-            ta.lds_slots = T.max_tile;
+            ta.max_rows = T.max_rows;
+            ta.max_slots = T.max_slots;
+            ta.max_pos = T.max_pos;
+            ta.kmax = T.kmax;
             if ((e = h->prepare_tile_claims(fwd ? kPassTileF : kPassTileB, &ta, s)) != hipSuccess)
                 return hip_fail(e, "tile claims");
             A.poll_sleep = h->poll_sleep;
@@ -990,7 +1018,7 @@ extern "C" ilu_status ilu_set_tuning(ilu_handle h, const char *key, int64_t valu
     }
     if (k == "tile_rows") {
         if (value < 16 || value > 65536) return fail(ILU_ERR_ARG, "ilu_set_tuning: tile_rows must be in [16, 65536]");
-        return h->make_tiles((int32_t)value);
+        return h->make_tiles((int32_t)value, false);
     }
     return fail(ILU_ERR_ARG, "ilu_set_tuning: unknown key " + k);
 }

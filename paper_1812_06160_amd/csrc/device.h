@@ -96,22 +96,35 @@ struct SolveArgs {
 
 // Tiled solve: one workgroup per tile, tiles claimed in start order (tile order is
 // topological, so a block only waits on tiles of blocks that started earlier).
-// Values of rows inside the block's own tile go through LDS, others through the
-// published y/z buffers.
+// A block stages its tile (rows, dependency slots and values, pivots, right-hand
+// sides) into LDS, one poller wave copies the tile's imports (dependencies in
+// other tiles) from the published y/z buffers into their LDS slots as they
+// appear, and the compute waves solve the tile's rows reading LDS only.
 struct TileArgs {
-    const int32_t *tile_ptr;  // [ntiles + 1] padded positions
-    const int2 *tile_rs;      // (row, LDS slot) at each position, (-1, -1) for padding
-    const int32_t *sci;       // per factor entry: LDS slot of the dependency (>= 0) or ~column
+    const int32_t *tile_ptr;  // [ntiles + 1] positions (rows + padding)
+    const int32_t *pslot;     // LDS slot of each position, -1 for padding
+    const int32_t *rows_ptr;  // [ntiles + 1] offsets into rows
+    const int32_t *rows;      // rows of each tile in slot order
+    const int32_t *imp_ptr;   // [ntiles + 1] offsets into imp
+    const int32_t *imp;       // imported rows (slot = tile rows + index)
+    const int32_t *sci;       // per factor entry: LDS slot of the dependency
     int32_t ntiles;
-    int32_t lds_slots;        // most rows in one tile
+    int32_t max_rows, max_slots, max_pos, kmax;
+    // LDS carve-up (bytes), set by the launcher
+    int32_t off_rhs, off_piv, off_eval, off_eslot, off_rowid, off_pslot, lds_bytes;
     int32_t *counter;         // claim counter of this pass
     int32_t *zero_counter;    // counter of the complementary pass, cleared at launch (may be null)
 };
 
-// Rows per wave chunk of the tiled solve (64 lanes / kTileLanes lanes per row).
+// Lanes per row and rows per wave chunk of the tiled solve; block = 4 compute
+// waves + 1 poller wave.
 constexpr int kTileLanes = 4;
 constexpr int kTileUnit = 64 / kTileLanes;
+constexpr int kTileComputeWaves = 4;
+constexpr int kTileBlock = 64 * (kTileComputeWaves + 1);
 constexpr int kTileLdsMax = 65536;    // dynamic LDS bytes a tiled launch may use
+// LDS a tiling needs with `nr` right-hand sides per pass of `acc_bytes` each
+size_t tile_lds_bytes(int max_rows, int max_slots, int max_pos, int kmax, int nr, int acc_bytes);
 
 struct SpmvArgs {
     int32_t n;

@@ -85,8 +85,12 @@ struct ilu_handle_s {
     // tiles of the tiled solves (direction 0: L, 1: U) and the solve column encoding
     jv::TileSet tiles[2];
     std::vector<int32_t> sci;
-    int32_t tile_rows = 4096;
-    int32_t *d_tile_ptr[2] = {nullptr, nullptr}, *d_tile_rs[2] = {nullptr, nullptr}, *d_sci = nullptr;
+    int32_t tile_rows = 0;             // rows per tile of the current tiles
+    struct DevTiles {
+        int32_t *ptr = nullptr, *pslot = nullptr, *rows_ptr = nullptr, *rows = nullptr, *imp_ptr = nullptr,
+                *imp = nullptr;
+    } dtiles[2];
+    int32_t *d_sci = nullptr;
     jv::Profiler prof;
     int32_t *d_counters = nullptr;     // kPasses sets of claim counters
     bool counters_dirty[jv::kPasses] = {false, false, false, false, false, false, false};
@@ -113,8 +117,9 @@ struct ilu_handle_s {
     hipError_t prepare_claims(int pass, const jv::TaskList *tl, jv::Claims *c, hipStream_t s);
     // blocks of a sync-free launch: every stream's slots plus one spare per stream
     int grid_syncfree(const jv::TaskList *tl) const { return nstreams * (tl->max_slots + 1); }
-    // (re)builds the tiles on the host and, unless host-only, uploads them
-    ilu_status make_tiles(int32_t rows);
+    // (re)builds the tiles on the host and, unless host-only, uploads them; with
+    // shrink, halves the tile size until the tiles fit the LDS budget
+    ilu_status make_tiles(int32_t rows, bool shrink);
     // claim counter of a tiled pass (launching a counter reset when needed)
     hipError_t prepare_tile_claims(int pass, jv::TileArgs *t, hipStream_t s);
 };

@@ -705,15 +705,17 @@ __global__ __launch_bounds__(kBlock) void k_solve_syncfree(SolveArgs A) {
 }
 
 // ---------------------------------------------------------------------------------
-// Tiled sync-free solve: one workgroup per tile, tile-local values in LDS
+// Tiled sync-free solve: one workgroup per tile, everything the tile reads in LDS
 // ---------------------------------------------------------------------------------
-// The value of every row of the block's tile lives in LDS slot (position in the
-// tile) until the tile is done; a row waits on the LDS word of a dependency in its
-// own tile and on the published y/z word of any other dependency.  Each LDS word
-// starts as the pending pattern, so (as in global memory) the value is its own
-// flag.  Wave w takes the chunks w, w + 4, ... of kTileUnit positions; a chunk
-// holds rows of one local level, and every dependency inside the tile sits in an
-// earlier chunk, so the lowest unfinished chunk can always proceed.
+// LDS of a block: the value slots (tile rows, then imports, then one slot that
+// holds 0 for padded entries), the staged rows (dependency slots and factor
+// values packed kmax per row, pivot, right-hand side, row id) and the position ->
+// slot map.  Every value slot starts as the pending pattern, so the value is its
+// own flag.  The poller wave copies imports from the published y/z buffers as
+// they appear.  Compute wave w takes the chunks w, w + 4, ... of kTileUnit
+// positions; a chunk holds rows of one local level and every dependency inside
+// the tile sits in an earlier chunk, so the lowest unfinished chunk can always
+// proceed, and imports only come from earlier tiles.
 
 template <typename TA>
 __device__ __forceinline__ typename Pub<TA>::U lds_ld(typename Pub<TA>::U *p) {
@@ -733,6 +735,10 @@ template <>
 __device__ __forceinline__ uint32_t bits_of<float>(float v) {
     return v != v ? kQNaN32 : __float_as_uint(v);
 }
+template <typename TA>
+__device__ __forceinline__ TA qnan_of() {
+    return Pub<TA>::from(sizeof(TA) == 8 ? (typename Pub<TA>::U)kQNaN64 : (typename Pub<TA>::U)kQNaN32);
+}
 
 // Bounded wait on an LDS word (same expiry rule as the global waits).
 template <typename TA>
@@ -745,103 +751,85 @@ __device__ TA lds_wait(typename Pub<TA>::U *p, int32_t *info) {
         const U v = lds_ld<TA>(p);
         if (v != Pub<TA>::kPend) return Pub<TA>::from(v);
         if ((++spins & 63) == 0) {
-            if (aborted(info)) return Pub<TA>::from(sizeof(U) == 8 ? (U)kQNaN64 : (U)kQNaN32);
+            if (aborted(info)) return qnan_of<TA>();
             if (expired(t0)) {
                 __hip_atomic_store(&info[kInfoAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                return Pub<TA>::from(sizeof(U) == 8 ? (U)kQNaN64 : (U)kQNaN32);
+                return qnan_of<TA>();
             }
         }
     }
 }
 
-template <int G, int NR, typename TV, typename TA, bool FWD>
-__device__ __forceinline__ void tiled_row(const SolveArgs &A, const int32_t *__restrict__ sci,
-                                          typename Pub<TA>::U *lds, int r, int slot, int t, int s0, int nr) {
+// Poller: copies the tile's imports (right-hand sides s0 .. s0 + nr - 1) from
+// the published buffer into LDS slots `first` .. as they appear.  Loads are
+// issued kPollBatch at a time per lane; a round re-polls only what is still
+// pending.  Bounded like every wait.
+constexpr int kPollBatch = 8;
+template <int NR, typename TA>
+__device__ void tile_poll(const int32_t *__restrict__ imp, int nimp, const TA *dep, int64_t cap, int s0, int nr,
+                          typename Pub<TA>::U *vals, int first, int32_t *info, int sleep) {
     using U = typename Pub<TA>::U;
-    constexpr int RPL = (NR + G - 1) / G;
-    const TV *val = static_cast<const TV *>(A.val);
-    TA *y = static_cast<TA *>(A.y);
-    TA *z = static_cast<TA *>(A.z);
-    const int rs = A.rp[r], re = A.rp[r + 1], d = A.diag[r];
-    const int lo = FWD ? rs : d + 1;
-    const int hi = FWD ? d : re;
-    TA *dep = FWD ? y : z;
-    const int64_t cap = A.cap;
-    const int out_row = A.perm ? A.perm[r] : r;
-    const TA piv = A.unit_diag ? (TA)1 : (TA)load_val(val, d);
-    TA rhs[RPL];
+    const int lane = threadIdx.x & 63;
+    const int total = nimp * nr;
+    int spins = 0;
+    uint64_t t0 = 0;
+    for (;;) {
+        bool left = false;
+        for (int i0 = lane; i0 < total; i0 += 64 * kPollBatch) {
+            U raw[kPollBatch];
+            int slot[kPollBatch];
 #pragma unroll
-    for (int m = 0; m < RPL; ++m) {
-        const int k = t + m * G;
-        rhs[m] = 0;
-        if (k < nr) {
-            if constexpr (FWD) rhs[m] = load_vec<TA>(A.b, A.vec_f32, (int64_t)out_row * A.ld + s0 + k);
-            else rhs[m] = y[(int64_t)r * cap + s0 + k];
-        }
-    }
-    TA acc[NR];
-#pragma unroll
-    for (int k = 0; k < NR; ++k) acc[k] = 0;
-    for (int p = lo + t; p < hi; p += G) {
-        const int enc = sci[p];
-        const TA a = (TA)load_val(val, p);
-        U raw[NR];
-        if (enc >= 0) {
-            U *src = lds + (int64_t)enc * NR;
-#pragma unroll
-            for (int k = 0; k < NR; ++k) raw[k] = k < nr ? lds_ld<TA>(src + k) : 0;
-#pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                if (k < nr) {
-                    TA xc = Pub<TA>::from(raw[k]);
-                    if (raw[k] == Pub<TA>::kPend) xc = lds_wait<TA>(src + k, A.info);
-                    const TA prod = a * xc;
-                    acc[k] = acc[k] + prod;
+            for (int b = 0; b < kPollBatch; ++b) {
+                const int i = i0 + b * 64;
+                slot[b] = -1;
+                raw[b] = Pub<TA>::kPend;
+                if (i < total) {
+                    const int m = i / nr, k = i - m * nr;
+                    const int sl = (first + m) * NR + k;
+                    if (lds_ld<TA>(vals + sl) == Pub<TA>::kPend) {
+                        slot[b] = sl;
+                        raw[b] = Pub<TA>::load(dep + (int64_t)imp[m] * cap + s0 + k);
+                    }
                 }
             }
-        } else {
-            const TA *dc = dep + (int64_t)(~enc) * cap + s0;
 #pragma unroll
-            for (int k = 0; k < NR; ++k) raw[k] = k < nr ? Pub<TA>::load(dc + k) : 0;
-#pragma unroll
-            for (int k = 0; k < NR; ++k) {
-                if (k < nr) {
-                    TA xc = Pub<TA>::from(raw[k]);
-                    if (raw[k] == Pub<TA>::kPend) xc = Pub<TA>::wait(dc + k, A.info, A.poll_sleep);
-                    const TA prod = a * xc;
-                    acc[k] = acc[k] + prod;
+            for (int b = 0; b < kPollBatch; ++b) {
+                if (slot[b] >= 0) {
+                    if (raw[b] != Pub<TA>::kPend) lds_st<TA>(vals + slot[b], raw[b]);
+                    else left = true;
                 }
             }
         }
-    }
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-        const TA sum = group_sum<G>(acc[k]);
-        if (k < nr && (k % G) == t) {
-            TA v = rhs[k / G] - sum;
-            if (!A.unit_diag) v = v / piv;
-            lds_st<TA>(lds + (int64_t)slot * NR + k, bits_of<TA>(v));
-            const int64_t o = (int64_t)r * cap + s0 + k;
-            if constexpr (FWD) {
-                Pub<TA>::publish(&y[o], v);
-                z[o] = Pub<TA>::pending();
-                if (A.y_out) static_cast<TA *>(A.y_out)[(int64_t)r * A.ld + s0 + k] = v;
-            } else {
-                Pub<TA>::publish(&z[o], v);
-                y[o] = Pub<TA>::pending();
-                store_vec<TA>(A.x, A.vec_f32, (int64_t)out_row * A.ld + s0 + k, v);
-                if (A.z_out) static_cast<TA *>(A.z_out)[(int64_t)r * A.ld + s0 + k] = v;
+        if (!__any(left)) return;
+        for (int k = 0; k < sleep; ++k) __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 15) == 0) {
+            if (aborted(info)) break;
+            if (expired(t0)) {
+                __hip_atomic_store(&info[kInfoAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
             }
         }
+    }
+    // aborted: release every waiter of this block with a quiet NaN
+    for (int i = lane; i < total; i += 64) {
+        const int m = i / nr, k = i - m * nr;
+        U *p = vals + (first + m) * NR + k;
+        if (lds_ld<TA>(p) == Pub<TA>::kPend) lds_st<TA>(p, bits_of<TA>(qnan_of<TA>()));
     }
 }
 
 template <int NR, typename TV, typename TA, bool FWD>
-__global__ __launch_bounds__(kBlock) void k_solve_tiled(SolveArgs A, TileArgs T) {
+__global__ __launch_bounds__(kTileBlock) void k_solve_tiled(SolveArgs A, TileArgs T) {
     using U = typename Pub<TA>::U;
     constexpr int G = kTileLanes;
     extern __shared__ __align__(16) unsigned char tile_smem[];
-    U *lds = reinterpret_cast<U *>(tile_smem);
+    U *vals = reinterpret_cast<U *>(tile_smem);
+    TA *rhs = reinterpret_cast<TA *>(tile_smem + T.off_rhs);
+    TA *piv = reinterpret_cast<TA *>(tile_smem + T.off_piv);
+    TA *ev = reinterpret_cast<TA *>(tile_smem + T.off_eval);
+    uint16_t *es = reinterpret_cast<uint16_t *>(tile_smem + T.off_eslot);
+    int32_t *rowid = reinterpret_cast<int32_t *>(tile_smem + T.off_rowid);
+    int16_t *ps = reinterpret_cast<int16_t *>(tile_smem + T.off_pslot);
     __shared__ int s_tile;
     if (threadIdx.x == 0) {
         if (T.zero_counter && blockIdx.x == 0) T.zero_counter[0] = 0;
@@ -850,18 +838,105 @@ __global__ __launch_bounds__(kBlock) void k_solve_tiled(SolveArgs A, TileArgs T)
     __syncthreads();
     const int tile = s_tile;
     if (tile >= T.ntiles) return;
-    const int base = T.tile_ptr[tile];
-    const int cnt = T.tile_ptr[tile + 1] - base;   // positions: a multiple of kTileUnit
+    const int pbase = T.tile_ptr[tile], npos = T.tile_ptr[tile + 1] - pbase;
+    const int rbase = T.rows_ptr[tile], nrows = T.rows_ptr[tile + 1] - rbase;
+    const int ibase = T.imp_ptr[tile], nimp = T.imp_ptr[tile + 1] - ibase;
+    const int K = T.kmax;
+    const int zero = T.max_slots;   // the slot that always holds 0
+    const TV *val = static_cast<const TV *>(A.val);
+    TA *y = static_cast<TA *>(A.y);
+    TA *z = static_cast<TA *>(A.z);
+    const int64_t cap = A.cap;
+    const int t = threadIdx.x % G;
+
+    // stage the tile: position -> slot, then per row its dependency slots and values
+    for (int q = threadIdx.x; q < npos; q += kTileBlock) ps[q] = (int16_t)T.pslot[pbase + q];
+    for (int sl = threadIdx.x / G; sl < nrows; sl += kTileBlock / G) {
+        const int r = T.rows[rbase + sl];
+        const int d = A.diag[r];
+        const int lo = FWD ? A.rp[r] : d + 1;
+        const int hi = FWD ? d : A.rp[r + 1];
+        if (t == 0) {
+            rowid[sl] = r;
+            piv[sl] = A.unit_diag ? (TA)1 : (TA)load_val(val, d);
+        }
+        for (int j = t; j < K; j += G) {
+            const int p = lo + j;
+            const bool on = p < hi;
+            es[sl * K + j] = (uint16_t)(on ? T.sci[p] : zero);
+            ev[sl * K + j] = on ? (TA)load_val(val, p) : (TA)0;
+        }
+    }
+    __syncthreads();
     const int wave = threadIdx.x >> 6;
     const int gi = (threadIdx.x & 63) / G;
-    const int t = threadIdx.x % G;
     for (int s0 = 0; s0 < A.nrhs; s0 += NR) {
         const int nr = A.nrhs - s0 < NR ? A.nrhs - s0 : NR;
-        for (int i = threadIdx.x; i < T.lds_slots * NR; i += kBlock) lds[i] = Pub<TA>::kPend;
+        for (int i = threadIdx.x; i < (nrows + nimp) * NR; i += kTileBlock) vals[i] = Pub<TA>::kPend;
+        if (threadIdx.x < NR) vals[zero * NR + threadIdx.x] = bits_of<TA>((TA)0);
+        for (int i = threadIdx.x; i < nrows * nr; i += kTileBlock) {
+            const int sl = i / nr, k = i - sl * nr;
+            const int r = rowid[sl];
+            TA b;
+            if constexpr (FWD) {
+                const int orow = A.perm ? A.perm[r] : r;
+                b = load_vec<TA>(A.b, A.vec_f32, (int64_t)orow * A.ld + s0 + k);
+            } else {
+                b = y[(int64_t)r * cap + s0 + k];
+            }
+            rhs[sl * NR + k] = b;
+        }
         __syncthreads();
-        for (int c0 = wave * kTileUnit; c0 < cnt; c0 += (kBlock / 64) * kTileUnit) {
-            const int2 rs = T.tile_rs[base + c0 + gi];
-            if (rs.x >= 0) tiled_row<G, NR, TV, TA, FWD>(A, T.sci, lds, rs.x, rs.y, t, s0, nr);
+        if (wave == kTileComputeWaves) {
+            tile_poll<NR, TA>(T.imp + ibase, nimp, FWD ? y : z, cap, s0, nr, vals, nrows, A.info, A.poll_sleep);
+        } else {
+            for (int c0 = wave * kTileUnit; c0 < npos; c0 += kTileComputeWaves * kTileUnit) {
+                const int sl = ps[c0 + gi];
+                if (sl < 0) continue;
+                TA acc[NR];
+#pragma unroll
+                for (int k = 0; k < NR; ++k) acc[k] = 0;
+                for (int j = t; j < K; j += G) {
+                    const int dsl = es[sl * K + j];
+                    const TA a = ev[sl * K + j];
+                    U *src = vals + dsl * NR;
+                    U raw[NR];
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) raw[k] = k < nr ? lds_ld<TA>(src + k) : 0;
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) {
+                        if (k < nr) {
+                            TA xc = Pub<TA>::from(raw[k]);
+                            if (raw[k] == Pub<TA>::kPend) xc = lds_wait<TA>(src + k, A.info);
+                            const TA prod = a * xc;
+                            acc[k] = acc[k] + prod;
+                        }
+                    }
+                }
+                const int r = rowid[sl];
+                const TA pv = piv[sl];
+#pragma unroll
+                for (int k = 0; k < NR; ++k) {
+                    const TA sum = group_sum<G>(acc[k]);
+                    if (k < nr && (k % G) == t) {
+                        TA v = rhs[sl * NR + k] - sum;
+                        if (!A.unit_diag) v = v / pv;
+                        lds_st<TA>(vals + sl * NR + k, bits_of<TA>(v));
+                        const int64_t o = (int64_t)r * cap + s0 + k;
+                        if constexpr (FWD) {
+                            Pub<TA>::publish(&y[o], v);
+                            z[o] = Pub<TA>::pending();
+                            if (A.y_out) static_cast<TA *>(A.y_out)[(int64_t)r * A.ld + s0 + k] = v;
+                        } else {
+                            Pub<TA>::publish(&z[o], v);
+                            y[o] = Pub<TA>::pending();
+                            const int orow = A.perm ? A.perm[r] : r;
+                            store_vec<TA>(A.x, A.vec_f32, (int64_t)orow * A.ld + s0 + k, v);
+                            if (A.z_out) static_cast<TA *>(A.z_out)[(int64_t)r * A.ld + s0 + k] = v;
+                        }
+                    }
+                }
+            }
         }
         __syncthreads();
     }
@@ -1112,20 +1187,60 @@ hipError_t launch_solve(const SolveArgs &A, bool forward, int prec, int vec, int
     }
 }
 
+static size_t align8(size_t x) { return (x + 7) & ~(size_t)7; }
+
+// LDS carve-up of a tiled launch: value slots (+1 zero slot), right-hand sides,
+// pivots, packed entry values, packed entry slots, row ids, position -> slot map
+static size_t tile_layout(const TileArgs &T, int nr, int acc, TileArgs *out) {
+    size_t o = align8((size_t)(T.max_slots + 1) * nr * acc);
+    const size_t rhs = o;
+    o = align8(o + (size_t)T.max_rows * nr * acc);
+    const size_t pv = o;
+    o = align8(o + (size_t)T.max_rows * acc);
+    const size_t evl = o;
+    o = align8(o + (size_t)T.max_rows * T.kmax * acc);
+    const size_t esl = o;
+    o = align8(o + (size_t)T.max_rows * T.kmax * 2);
+    const size_t rid = o;
+    o = align8(o + (size_t)T.max_rows * 4);
+    const size_t psl = o;
+    o = align8(o + (size_t)T.max_pos * 2);
+    if (out) {
+        out->off_rhs = (int32_t)rhs;
+        out->off_piv = (int32_t)pv;
+        out->off_eval = (int32_t)evl;
+        out->off_eslot = (int32_t)esl;
+        out->off_rowid = (int32_t)rid;
+        out->off_pslot = (int32_t)psl;
+        out->lds_bytes = (int32_t)o;
+    }
+    return o;
+}
+
+size_t tile_lds_bytes(int max_rows, int max_slots, int max_pos, int kmax, int nr, int acc_bytes) {
+    TileArgs T{};
+    T.max_rows = max_rows;
+    T.max_slots = max_slots;
+    T.max_pos = max_pos;
+    T.kmax = kmax;
+    return tile_layout(T, nr, acc_bytes, nullptr);
+}
+
 template <int NR, typename TV, typename TA>
-static hipError_t tiled_launch(const SolveArgs &A, const TileArgs &T, bool fwd, hipStream_t s) {
-    const size_t lds = (size_t)T.lds_slots * NR * sizeof(TA);
-    if (lds > (size_t)kTileLdsMax) return hipErrorInvalidValue;
+static hipError_t tiled_launch(const SolveArgs &A, const TileArgs &T0, bool fwd, hipStream_t s) {
+    TileArgs T = T0;
+    const size_t lds = tile_layout(T, NR, sizeof(TA), &T);
+    if (lds > (size_t)kTileLdsMax || T.max_slots + 1 > 65535 || T.max_pos > 32767) return hipErrorInvalidValue;
     if (T.ntiles <= 0) return hipSuccess;
-    if (fwd) hipLaunchKernelGGL((k_solve_tiled<NR, TV, TA, true>), dim3(T.ntiles), dim3(kBlock), lds, s, A, T);
-    else hipLaunchKernelGGL((k_solve_tiled<NR, TV, TA, false>), dim3(T.ntiles), dim3(kBlock), lds, s, A, T);
+    if (fwd) hipLaunchKernelGGL((k_solve_tiled<NR, TV, TA, true>), dim3(T.ntiles), dim3(kTileBlock), lds, s, A, T);
+    else hipLaunchKernelGGL((k_solve_tiled<NR, TV, TA, false>), dim3(T.ntiles), dim3(kTileBlock), lds, s, A, T);
     return hipGetLastError();
 }
 
 // right-hand sides per pass: 4 when that blocking fits LDS, else 1
 template <typename TV, typename TA>
 static hipError_t tiled_dispatch(const SolveArgs &A, const TileArgs &T, bool fwd, hipStream_t s) {
-    if (A.nrhs > 1 && (size_t)T.lds_slots * 4 * sizeof(TA) <= (size_t)kTileLdsMax)
+    if (A.nrhs > 1 && tile_layout(T, 4, sizeof(TA), nullptr) <= (size_t)kTileLdsMax)
         return tiled_launch<4, TV, TA>(A, T, fwd, s);
     return tiled_launch<1, TV, TA>(A, T, fwd, s);
 }

@@ -103,15 +103,21 @@ void tiles_one(const HostAnalysis &H, int dir, int32_t cap, int32_t unit, TileSe
             const int32_t c = ci[p];
             if (tile_of[c] == tile_of[r]) llev[r] = std::max(llev[r], llev[c] + 1);
         }
-    // per tile: rows by local level (stable in placement order), each level padded
+    // per tile: rows by local level (stable in placement order), each level padded;
+    // slots: rows in position order, then the tile's imports
     T->cap = cap;
     T->unit = unit;
     T->ntiles = ntiles;
-    T->max_tile = 0;
+    T->max_rows = T->max_slots = T->max_pos = 0;
+    T->kmax = 0;
     T->ptr.assign(1, 0);
     T->row.clear();
-    T->rs.clear();
-    std::vector<int32_t> slot(n, -1);
+    T->rows_ptr.assign(1, 0);
+    T->rows.clear();
+    T->imp_ptr.assign(1, 0);
+    T->imp.clear();
+    for (int32_t r = 0; r < n; ++r) T->kmax = std::max(T->kmax, dend(r) - dbeg(r));
+    std::vector<int32_t> slot(n, -1), imp_slot(n, -1);
     size_t a = 0;
     for (int32_t t = 0; t < ntiles; ++t) {
         size_t b = a;
@@ -124,35 +130,44 @@ void tiles_one(const HostAnalysis &H, int dir, int32_t cap, int32_t unit, TileSe
             size_t j = i;
             while (j < rows.size() && llev[rows[j]] == llev[rows[i]]) ++j;
             for (size_t k = i; k < j; ++k) {
-                slot[rows[k]] = nslot;
+                slot[rows[k]] = nslot++;
                 T->row.push_back(rows[k]);
-                T->rs.push_back(rows[k]);
-                T->rs.push_back(nslot++);
+                T->rows.push_back(rows[k]);
             }
-            while ((T->row.size() - base) % unit) {
-                T->row.push_back(-1);
-                T->rs.push_back(-1);
-                T->rs.push_back(-1);
-            }
+            while ((T->row.size() - base) % unit) T->row.push_back(-1);
             i = j;
         }
+        // imports, in order of first use
+        const size_t ibase = T->imp.size();
+        for (int32_t r : rows)
+            for (int32_t p = dbeg(r); p < dend(r); ++p) {
+                const int32_t c = ci[p];
+                if (tile_of[c] != t && imp_slot[c] < 0) {
+                    imp_slot[c] = nslot + (int32_t)(T->imp.size() - ibase);
+                    T->imp.push_back(c);
+                }
+            }
+        for (int32_t r : rows)
+            for (int32_t p = dbeg(r); p < dend(r); ++p) {
+                const int32_t c = ci[p];
+                (*sci)[p] = tile_of[c] == t ? slot[c] : imp_slot[c];
+            }
+        for (size_t i = ibase; i < T->imp.size(); ++i) imp_slot[T->imp[i]] = -1;
         T->ptr.push_back((int32_t)T->row.size());
-        T->max_tile = std::max<int32_t>(T->max_tile, nslot);
+        T->rows_ptr.push_back((int32_t)T->rows.size());
+        T->imp_ptr.push_back((int32_t)T->imp.size());
+        T->max_rows = std::max<int32_t>(T->max_rows, nslot);
+        T->max_slots = std::max<int32_t>(T->max_slots, nslot + (int32_t)(T->imp.size() - ibase));
+        T->max_pos = std::max<int32_t>(T->max_pos, (int32_t)(T->row.size() - base));
         a = b;
     }
-    for (int32_t r = 0; r < n; ++r)
-        for (int32_t p = dbeg(r); p < dend(r); ++p) {
-            const int32_t c = ci[p];
-            (*sci)[p] = tile_of[c] == tile_of[r] ? slot[c] : ~c;
-        }
 }
 
 }  // namespace
 
 void build_tiles(const HostAnalysis &H, int32_t cap, int32_t unit, TileSet *fwd, TileSet *bwd,
                  std::vector<int32_t> *sci) {
-    sci->assign(H.lu_ci.size(), 0);
-    for (int32_t r = 0; r < H.n; ++r) (*sci)[H.diag[r]] = ~r;
+    sci->assign(H.lu_ci.size(), -1);
     tiles_one(H, 0, cap, unit, fwd, sci);
     tiles_one(H, 1, cap, unit, bwd, sci);
 }
