@@ -439,7 +439,7 @@ def test_apply_graph_replays(jv, sched):
     del g
 
 
-@pytest.mark.parametrize("tile_rows", [16, 100, 256, 768])
+@pytest.mark.parametrize("tile_rows", [16, 100, 256, 0])
 @pytest.mark.parametrize("name,mk,k,sym", [
     ("laplace3d_20", lambda: synth.laplace3d(20), 0, True),
     ("convdiff3d_12_ilu1", lambda: synth.convdiff3d(12), 1, True),
