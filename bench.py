@@ -91,7 +91,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--scale", type=float, default=1.0, help="grid scale (1.0 = 128^3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sched", default="syncfree", choices=["syncfree", "level"])
+    ap.add_argument("--sched", default="syncfree", choices=["syncfree", "level"],
+                    help="launch scheme of the factor")
+    ap.add_argument("--solve-sched", default="tiled", choices=["tiled", "syncfree", "level"],
+                    help="launch scheme of the triangular solves")
     ap.add_argument("--workload", default="laplace3d_128",
                     choices=["laplace3d_128", "convdiff3d_96", "random_1m", "batch512"])
     args = ap.parse_args()
@@ -117,7 +120,7 @@ def main():
     t0 = time.perf_counter()
     ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
     t_analyze = time.perf_counter() - t0
-    ilu.set_schedule(args.sched, args.sched)
+    ilu.set_schedule(args.sched, args.solve_sched)
     info = ilu.info()
     sched = ilu.schedule()
     nnz_l = int((sched["diag_pos"] - sched["lu_row_ptr"][:-1]).sum())
@@ -234,7 +237,8 @@ def main():
         vs_baseline=None, dtype="f64", data="synthetic",
         config=dict(workload="laplace3d_128: 3D 7-point Laplacian, 128^3 grid, natural ordering, FP64 CSR, "
                              "ILU(0), b ~ U[-1,1]",
-                    n=n, nnz=A.nnz, nnz_lu=info["nnz_lu"], levels=info["n_levels"], schedule=args.sched),
+                    n=n, nnz=A.nnz, nnz_lu=info["nnz_lu"], levels=info["n_levels"], schedule=args.sched,
+                    solve_schedule=args.solve_sched),
         roofline=roofline,
         stages_us=dict(factor=round(1e3 * t_factor, 2), forward_f64=round(1e3 * t_fwd64, 2),
                        backward_f64=round(1e3 * t_bwd64, 2), forward_f32=round(1e3 * t_fwd32, 2),

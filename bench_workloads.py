@@ -53,11 +53,11 @@ def run(args):
     torch.cuda.set_device(0)
     jv.load()
     wl = args.workload
-    out = dict(workload=wl, data="synthetic", n_gpus=1)
+    out = dict(workload=wl, data="synthetic", n_gpus=1, schedule=args.sched, solve_schedule=args.solve_sched)
     if wl == "convdiff3d_96":
         A, b = synth.workload(3)
         ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=1)
-        ilu.set_schedule(args.sched, args.sched)
+        ilu.set_schedule(args.sched, args.solve_sched)
         a = _dev(A.val)
         bt = _dev(b)
         ilu.factor(a, k=1, tau=1e-3, casts=("f32", "bf16"))
@@ -91,7 +91,7 @@ def run(args):
     elif wl == "random_1m":
         A, Bm = synth.workload(4)
         ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
-        ilu.set_schedule(args.sched, args.sched)
+        ilu.set_schedule(args.sched, args.solve_sched)
         a = _dev(A.val)
         ilu.factor(a, casts=("f32",))
         ilu.profile(True, 1 << 16)
@@ -121,7 +121,7 @@ def run(args):
         t0 = time.perf_counter()
         hb = jv.Ilu.batched(mats)
         t_an = time.perf_counter() - t0
-        hb.set_schedule(args.sched, args.sched)
+        hb.set_schedule(args.sched, args.solve_sched)
         vals = _dev(np.concatenate([m.val for m in mats]))
         hb.factor(vals, casts=("f32",))
         b = np.concatenate(rhs)

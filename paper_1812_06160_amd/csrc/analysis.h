@@ -75,8 +75,10 @@ struct TileSet {
 
 // Builds both directions' tiles and the solve column encoding: for every factor
 // entry p = (r, c) with c != r, sci[p] = LDS slot of c in r's tile of the
-// direction that reads the entry; diagonal entries get -1.
-void build_tiles(const HostAnalysis &H, int32_t cap, int32_t unit, TileSet *fwd, TileSet *bwd,
+// direction that reads the entry; diagonal entries get -1.  A direction whose
+// rows have at most short_row dependencies is padded to chunks of 64 positions
+// (one lane per row), otherwise to chunks of 16 (four lanes per row).
+void build_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, TileSet *fwd, TileSet *bwd,
                  std::vector<int32_t> *sci);
 
 // Returns ILU_OK or an error status with a message in *err.

@@ -237,13 +237,14 @@ hipError_t ilu_handle_s::prepare_tile_claims(int pass, TileArgs *t, hipStream_t 
 
 static bool tiles_fit(const TileSet &T) {
     return tile_lds_bytes(T.max_rows, T.max_slots, T.max_pos, T.kmax, 1, 8) <= (size_t)kTileLdsMax &&
-           T.max_slots + 1 <= 65535 && T.max_pos <= 32767;
+           T.max_slots + 1 <= 65535 && T.max_pos <= 32767 &&
+           T.kmax <= (T.unit == 64 ? kTileShortRow : 4 * kTileLongJ);
 }
 
 ilu_status ilu_handle_s::make_tiles(int32_t rows, bool shrink) {
     try {
         for (;;) {
-            build_tiles(H, rows, kTileUnit, &tiles[0], &tiles[1], &sci);
+            build_tiles(H, rows, kTileShortRow, &tiles[0], &tiles[1], &sci);
             if (!shrink || rows <= 16 || (tiles_fit(tiles[0]) && tiles_fit(tiles[1]))) break;
             rows /= 2;
         }
@@ -253,6 +254,13 @@ ilu_status ilu_handle_s::make_tiles(int32_t rows, bool shrink) {
     tile_rows = rows;
     if (host_only) return ILU_OK;
     auto drop = [&](int32_t *&d) {
+        if (d) {
+            (void)hipFree(d);
+            allocs_erase(this, d);
+            d = nullptr;
+        }
+    };
+    auto drop16 = [&](int16_t *&d) {
         if (d) {
             (void)hipFree(d);
             allocs_erase(this, d);
@@ -269,14 +277,25 @@ ilu_status ilu_handle_s::make_tiles(int32_t rows, bool shrink) {
     if (e != hipSuccess) return hip_fail(e, "tiles: synchronize");
     for (int dir = 0; dir < 2; ++dir) {
         const TileSet &T = tiles[dir];
-        std::vector<int32_t> pslot(T.row.size());
+        std::vector<int16_t> pslot(T.row.size());
         for (int32_t t = 0; t < T.ntiles; ++t) {
             int32_t k = 0;
-            for (int32_t q = T.ptr[t]; q < T.ptr[t + 1]; ++q) pslot[q] = T.row[q] >= 0 ? k++ : -1;
+            for (int32_t q = T.ptr[t]; q < T.ptr[t + 1]; ++q) pslot[q] = (int16_t)(T.row[q] >= 0 ? k++ : -1);
+        }
+        std::vector<int32_t> meta(T.rows.size() * 4);
+        for (size_t i = 0; i < T.rows.size(); ++i) {
+            const int32_t r = T.rows[i], d = H.diag[r];
+            meta[4 * i] = r;
+            meta[4 * i + 1] = dir == 0 ? H.lu_rp[r] : d + 1;
+            meta[4 * i + 2] = dir == 0 ? d : H.lu_rp[r + 1];
+            meta[4 * i + 3] = d;
         }
         DevTiles &D = dtiles[dir];
-        if ((e = put(D.ptr, T.ptr)) != hipSuccess || (e = put(D.pslot, pslot)) != hipSuccess ||
-            (e = put(D.rows_ptr, T.rows_ptr)) != hipSuccess || (e = put(D.rows, T.rows)) != hipSuccess ||
+        drop16(D.pslot);
+        if ((e = upload(&D.pslot, pslot)) != hipSuccess) return hip_fail(e, "tiles: upload");
+        if (D.pslot) allocs.push_back(D.pslot);
+        if ((e = put(D.ptr, T.ptr)) != hipSuccess ||
+            (e = put(D.rows_ptr, T.rows_ptr)) != hipSuccess || (e = put(D.meta, meta)) != hipSuccess ||
             (e = put(D.imp_ptr, T.imp_ptr)) != hipSuccess || (e = put(D.imp, T.imp)) != hipSuccess)
             return hip_fail(e, "tiles: upload");
     }
@@ -752,7 +771,7 @@ ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int 
             ta.tile_ptr = D.ptr;
             ta.pslot = D.pslot;
             ta.rows_ptr = D.rows_ptr;
-            ta.rows = D.rows;
+            ta.meta = reinterpret_cast<const int4 *>(D.meta);
             ta.imp_ptr = D.imp_ptr;
             ta.imp = D.imp;
             ta.sci = h->d_sci;
@@ -761,6 +780,7 @@ ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int 
             ta.max_slots = T.max_slots;
             ta.max_pos = T.max_pos;
             ta.kmax = T.kmax;
+            ta.unit = T.unit;
             if ((e = h->prepare_tile_claims(fwd ? kPassTileF : kPassTileB, &ta, s)) != hipSuccess)
                 return hip_fail(e, "tile claims");
             A.poll_sleep = h->poll_sleep;

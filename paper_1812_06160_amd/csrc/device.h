@@ -102,25 +102,30 @@ struct SolveArgs {
 // appear, and the compute waves solve the tile's rows reading LDS only.
 struct TileArgs {
     const int32_t *tile_ptr;  // [ntiles + 1] positions (rows + padding)
-    const int32_t *pslot;     // LDS slot of each position, -1 for padding
-    const int32_t *rows_ptr;  // [ntiles + 1] offsets into rows
-    const int32_t *rows;      // rows of each tile in slot order
+    const int16_t *pslot;     // LDS slot of each position, -1 for padding
+    const int32_t *rows_ptr;  // [ntiles + 1] offsets into meta
+    const int4 *meta;         // per row of each tile in slot order: row, first and end entry of the
+                              // direction's part of the row, diagonal entry
     const int32_t *imp_ptr;   // [ntiles + 1] offsets into imp
     const int32_t *imp;       // imported rows (slot = tile rows + index)
     const int32_t *sci;       // per factor entry: LDS slot of the dependency
     int32_t ntiles;
     int32_t max_rows, max_slots, max_pos, kmax;
+    int32_t unit;             // positions per chunk (64: one lane per row, 16: four)
     // LDS carve-up (bytes), set by the launcher
-    int32_t off_rhs, off_piv, off_eval, off_eslot, off_rowid, off_pslot, lds_bytes;
+    int32_t off_rhs, off_piv, off_eval, off_eslot, off_rowid, off_pslot, off_imp, off_orow, lds_bytes;
     int32_t *counter;         // claim counter of this pass
     int32_t *zero_counter;    // counter of the complementary pass, cleared at launch (may be null)
 };
 
-// Lanes per row and rows per wave chunk of the tiled solve; block = 4 compute
-// waves + 1 poller wave.
-constexpr int kTileLanes = 4;
-constexpr int kTileUnit = 64 / kTileLanes;
-constexpr int kTileComputeWaves = 4;
+// Tiled solve blocks: kTileComputeWaves compute waves and 1 poller wave (imports);
+// all of them stage the tile.  A tile
+// whose rows have at most kTileShortRow dependencies is solved with one lane per
+// row (chunks of 64 positions); longer rows get 4 lanes each (chunks of 16, at
+// most 4 * kTileLongJ dependencies).  The chunk size is fixed by the tiling.
+constexpr int kTileComputeWaves = 8;
+constexpr int kTileShortRow = 1;
+constexpr int kTileLongJ = 8;
 constexpr int kTileBlock = 64 * (kTileComputeWaves + 1);
 constexpr int kTileLdsMax = 65536;    // dynamic LDS bytes a tiled launch may use
 // LDS a tiling needs with `nr` right-hand sides per pass of `acc_bytes` each

@@ -87,8 +87,8 @@ struct ilu_handle_s {
     std::vector<int32_t> sci;
     int32_t tile_rows = 0;             // rows per tile of the current tiles
     struct DevTiles {
-        int32_t *ptr = nullptr, *pslot = nullptr, *rows_ptr = nullptr, *rows = nullptr, *imp_ptr = nullptr,
-                *imp = nullptr;
+        int32_t *ptr = nullptr, *rows_ptr = nullptr, *meta = nullptr, *imp_ptr = nullptr, *imp = nullptr;
+        int16_t *pslot = nullptr;
     } dtiles[2];
     int32_t *d_sci = nullptr;
     jv::Profiler prof;

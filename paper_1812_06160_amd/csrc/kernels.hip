@@ -114,10 +114,39 @@ __device__ __forceinline__ uint64_t group_bits(uint64_t ballot, int gi) {
     else return (ballot >> (gi * G)) & ((1ull << G) - 1ull);
 }
 
+// Cross-lane moves inside rows of 16 lanes (DPP): quad permutations and mirrors
+// execute in the vector pipeline, where a general shuffle would be an LDS-unit
+// permute with LDS latency.
+enum : int {
+    kDppQuadXor1 = 0xB1,     // quad_perm [1, 0, 3, 2]
+    kDppQuadXor2 = 0x4E,     // quad_perm [2, 3, 0, 1]
+    kDppHalfMirror = 0x141,  // lane i <- lane 7 - i within each 8 lanes
+    kDppMirror = 0x140       // lane i <- lane 15 - i within each 16 lanes
+};
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the G lanes of an aligned lane group, returned in every lane of the
+// group.  Lanes pair in the same order at every width, and each pairwise sum is
+// commutative, so all lanes of a group hold identical bits.
 template <int G, typename T>
 __device__ __forceinline__ T group_sum(T v) {
+    if constexpr (G >= 2) {
+        if constexpr (G >= 4) v += dpp_mov<kDppQuadXor2>(v);
+        v += dpp_mov<kDppQuadXor1>(v);
+    }
+    if constexpr (G >= 8) v += dpp_mov<kDppHalfMirror>(v);
+    if constexpr (G >= 16) v += dpp_mov<kDppMirror>(v);
 #pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+    for (int off = 16; off < G; off <<= 1) v += __shfl_xor(v, off, G);
     return v;
 }
 
@@ -740,9 +769,13 @@ __device__ __forceinline__ TA qnan_of() {
     return Pub<TA>::from(sizeof(TA) == 8 ? (typename Pub<TA>::U)kQNaN64 : (typename Pub<TA>::U)kQNaN32);
 }
 
-// Bounded wait on an LDS word (same expiry rule as the global waits).
+// Bounded wait of a compute wave on an LDS word.  It never touches global memory
+// except to raise the device abort flag: a global load here would make the wave
+// wait for its own outstanding global stores before the load's result is used
+// (stores and loads share one counter), which would put a store round trip on
+// every step.  The poller mirrors the device abort flag into *lds_abort.
 template <typename TA>
-__device__ TA lds_wait(typename Pub<TA>::U *p, int32_t *info) {
+__device__ TA lds_wait(typename Pub<TA>::U *p, int *lds_abort, int32_t *info) {
     using U = typename Pub<TA>::U;
     int spins = 0;
     uint64_t t0 = 0;
@@ -751,9 +784,10 @@ __device__ TA lds_wait(typename Pub<TA>::U *p, int32_t *info) {
         const U v = lds_ld<TA>(p);
         if (v != Pub<TA>::kPend) return Pub<TA>::from(v);
         if ((++spins & 63) == 0) {
-            if (aborted(info)) return qnan_of<TA>();
+            if (__hip_atomic_load(lds_abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return qnan_of<TA>();
             if (expired(t0)) {
                 __hip_atomic_store(&info[kInfoAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(lds_abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 return qnan_of<TA>();
             }
         }
@@ -761,46 +795,59 @@ __device__ TA lds_wait(typename Pub<TA>::U *p, int32_t *info) {
 }
 
 // Poller: copies the tile's imports (right-hand sides s0 .. s0 + nr - 1) from
-// the published buffer into LDS slots `first` .. as they appear.  Loads are
-// issued kPollBatch at a time per lane; a round re-polls only what is still
-// pending.  Bounded like every wait.
-constexpr int kPollBatch = 8;
+// the published buffer into LDS slots `first` .. as they appear.  The imported
+// rows are staged in LDS with the tile, so a round costs one global load per
+// pending import.  Imports are numbered in order of first use; the poller works
+// on a window of kPollBatch rows of 64 imports starting at the first unresolved
+// row, which moves on once that row is resolved, and rounds that find nothing new
+// back off up to kPollMaxSleep pause steps.  Bounded like every wait.
+constexpr int kPollBatch = 2;
+constexpr int kPollMaxSleep = 8;
+constexpr int kStageRows = 4;   // rows per lane group per staging step
+constexpr int kStageCopy = 8;   // elements per thread per staging copy step
+
 template <int NR, typename TA>
-__device__ void tile_poll(const int32_t *__restrict__ imp, int nimp, const TA *dep, int64_t cap, int s0, int nr,
-                          typename Pub<TA>::U *vals, int first, int32_t *info, int sleep) {
+__device__ void tile_poll(const int32_t *imp, int nimp, const TA *dep, int64_t cap, int s0, int nr,
+                          typename Pub<TA>::U *vals, int first, int32_t *info, int sleep0,
+                          int *lds_abort) {
     using U = typename Pub<TA>::U;
     const int lane = threadIdx.x & 63;
     const int total = nimp * nr;
-    int spins = 0;
+    int head = 0, sleep = 0, spins = 0;
     uint64_t t0 = 0;
-    for (;;) {
-        bool left = false;
-        for (int i0 = lane; i0 < total; i0 += 64 * kPollBatch) {
-            U raw[kPollBatch];
-            int slot[kPollBatch];
+    while (head < total) {
+        U raw[kPollBatch];
+        int sl[kPollBatch];
 #pragma unroll
-            for (int b = 0; b < kPollBatch; ++b) {
-                const int i = i0 + b * 64;
-                slot[b] = -1;
-                raw[b] = Pub<TA>::kPend;
-                if (i < total) {
-                    const int m = i / nr, k = i - m * nr;
-                    const int sl = (first + m) * NR + k;
-                    if (lds_ld<TA>(vals + sl) == Pub<TA>::kPend) {
-                        slot[b] = sl;
-                        raw[b] = Pub<TA>::load(dep + (int64_t)imp[m] * cap + s0 + k);
-                    }
-                }
-            }
-#pragma unroll
-            for (int b = 0; b < kPollBatch; ++b) {
-                if (slot[b] >= 0) {
-                    if (raw[b] != Pub<TA>::kPend) lds_st<TA>(vals + slot[b], raw[b]);
-                    else left = true;
+        for (int b = 0; b < kPollBatch; ++b) {
+            const int i = head + 64 * b + lane;
+            sl[b] = -1;
+            raw[b] = Pub<TA>::kPend;
+            if (i < total) {
+                const int m = i / nr, k = i - m * nr;
+                const int q = (first + m) * NR + k;
+                if (lds_ld<TA>(vals + q) == Pub<TA>::kPend) {
+                    sl[b] = q;
+                    raw[b] = Pub<TA>::load(dep + (int64_t)imp[m] * cap + s0 + k);
                 }
             }
         }
-        if (!__any(left)) return;
+        bool got = false, pend0 = false;
+#pragma unroll
+        for (int b = 0; b < kPollBatch; ++b) {
+            if (sl[b] < 0) continue;
+            if (raw[b] != Pub<TA>::kPend) {
+                lds_st<TA>(vals + sl[b], raw[b]);
+                got = true;
+            } else if (b == 0) {
+                pend0 = true;
+            }
+        }
+        if (!__any(pend0)) {   // the first window row is resolved: move on
+            head += 64;
+            continue;
+        }
+        sleep = __any(got) ? sleep0 : (sleep * 2 + 1 < kPollMaxSleep ? sleep * 2 + 1 : kPollMaxSleep);
         for (int k = 0; k < sleep; ++k) __builtin_amdgcn_s_sleep(1);
         if ((++spins & 15) == 0) {
             if (aborted(info)) break;
@@ -810,7 +857,9 @@ __device__ void tile_poll(const int32_t *__restrict__ imp, int nimp, const TA *d
             }
         }
     }
+    if (head >= total) return;
     // aborted: release every waiter of this block with a quiet NaN
+    if (lane == 0) __hip_atomic_store(lds_abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     for (int i = lane; i < total; i += 64) {
         const int m = i / nr, k = i - m * nr;
         U *p = vals + (first + m) * NR + k;
@@ -818,10 +867,138 @@ __device__ void tile_poll(const int32_t *__restrict__ imp, int nimp, const TA *d
     }
 }
 
-template <int NR, typename TV, typename TA, bool FWD>
+// Global stores of one solved value: publish it, re-arm the other buffer, write
+// the outputs.
+template <typename TA, bool FWD>
+__device__ __forceinline__ void tile_store(const SolveArgs &A, int r, int orow, int col, TA v) {
+    TA *y = static_cast<TA *>(A.y);
+    TA *z = static_cast<TA *>(A.z);
+    const int64_t o = (int64_t)r * A.cap + col;
+    if constexpr (FWD) {
+        Pub<TA>::publish(&y[o], v);
+        z[o] = Pub<TA>::pending();
+        if (A.y_out) static_cast<TA *>(A.y_out)[(int64_t)r * A.ld + col] = v;
+    } else {
+        Pub<TA>::publish(&z[o], v);
+        y[o] = Pub<TA>::pending();
+        store_vec<TA>(A.x, A.vec_f32, (int64_t)orow * A.ld + col, v);
+        if (A.z_out) static_cast<TA *>(A.z_out)[(int64_t)r * A.ld + col] = v;
+    }
+}
+
+// Copies n elements from global memory into LDS, every thread issuing U loads
+// before storing any.
+template <int U, typename T>
+__device__ __forceinline__ void lds_copy(T *dst, const T *__restrict__ src, int n) {
+    for (int i0 = threadIdx.x; i0 < n; i0 += kTileBlock * U) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * kTileBlock;
+            if (i < n) v[u] = src[i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * kTileBlock;
+            if (i < n) dst[i] = v[u];
+        }
+    }
+}
+
+// The staged data of one row of a chunk, loaded one chunk ahead: with G = 1 a lane
+// holds all (at most J) dependencies of its row, with G > 1 lane t of the row's
+// group holds entries t, t + G, ... (at most J of them).
+template <int J, int NR, typename TA>
+struct TileRow {
+    int sl;              // LDS slot of the row (-1: padding)
+    int dsl[J];
+    TA a[J];
+    int r;
+    TA pv;
+    TA rhs[NR];
+};
+
+template <int G, int J, int NR, typename TA>
+__device__ __forceinline__ void tile_row_load(TileRow<J, NR, TA> &R, const int16_t *ps, const TA *ev,
+                                              const uint16_t *es, const int32_t *rowid, const TA *piv, const TA *rhs,
+                                              int K, int pos, int t, int nr) {
+    R.sl = ps[pos];
+    if (R.sl < 0) return;
+#pragma unroll
+    for (int jj = 0; jj < J; ++jj) {
+        const int j = t + jj * G;
+        R.dsl[jj] = j < K ? es[R.sl * K + j] : -1;
+        R.a[jj] = j < K ? ev[R.sl * K + j] : (TA)0;
+    }
+    R.r = rowid[R.sl];
+    R.pv = piv[R.sl];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) R.rhs[k] = k < nr ? rhs[R.sl * NR + k] : (TA)0;
+}
+
+// Compute waves: wave w solves the chunks w, w + kTileComputeWaves, ... of the
+// tile (a chunk is 64 / G positions of one local level), writing each value only
+// to its LDS slot and publishing it.  The next chunk's staged row data is loaded
+// while the current one waits and computes, and all dependency values of a row
+// are read at once, so one LDS round trip plus the arithmetic separates one local
+// level from the next.  The wave issues no global load: the bounded waits only
+// look at LDS (a global load would make the wave wait for its outstanding
+// stores before using the result).  Every row of the tile has
+// at most J * G dependencies (the launcher checks).  With G = 1 a lane sums its
+// row's products in column order; with G > 1 the lanes of a group sum their
+// entries and the group adds them up.
+template <int G, int J, int NR, typename TA, bool FWD>
+__device__ __forceinline__ void tile_compute(const SolveArgs &A, typename Pub<TA>::U *vals, const TA *ev,
+                                             const uint16_t *es, const int16_t *ps, const int32_t *rowid,
+                                             const int32_t *orows, const TA *piv, const TA *rhs, int K, int npos,
+                                             int wave, int gi, int t, int s0, int nr, int *lds_abort) {
+    using U = typename Pub<TA>::U;
+    constexpr int UNIT = 64 / G;
+    constexpr int STEP = kTileComputeWaves * UNIT;
+    TileRow<J, NR, TA> cur;
+    int c0 = wave * UNIT;
+    cur.sl = -1;
+    if (c0 < npos) tile_row_load<G, J, NR, TA>(cur, ps, ev, es, rowid, piv, rhs, K, c0 + gi, t, nr);
+    for (; c0 < npos; c0 += STEP) {
+        TileRow<J, NR, TA> nxt;
+        nxt.sl = -1;
+        if (c0 + STEP < npos) tile_row_load<G, J, NR, TA>(nxt, ps, ev, es, rowid, piv, rhs, K, c0 + STEP + gi, t, nr);
+        if (cur.sl >= 0) {
+            U raw[J][NR];
+#pragma unroll
+            for (int jj = 0; jj < J; ++jj)
+#pragma unroll
+                for (int k = 0; k < NR; ++k)
+                    raw[jj][k] = (cur.dsl[jj] >= 0 && k < nr) ? lds_ld<TA>(vals + cur.dsl[jj] * NR + k) : 0;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                TA acc = 0;
+#pragma unroll
+                for (int jj = 0; jj < J; ++jj) {
+                    if (cur.dsl[jj] >= 0 && k < nr) {
+                        TA xc = Pub<TA>::from(raw[jj][k]);
+                        if (raw[jj][k] == Pub<TA>::kPend)
+                            xc = lds_wait<TA>(vals + cur.dsl[jj] * NR + k, lds_abort, A.info);
+                        const TA prod = cur.a[jj] * xc;
+                        acc = acc + prod;
+                    }
+                }
+                const TA sum = group_sum<G>(acc);
+                if (k < nr && (k % G) == t) {
+                    TA v = cur.rhs[k] - sum;
+                    if (!A.unit_diag) v = v / cur.pv;
+                    lds_st<TA>(vals + cur.sl * NR + k, bits_of<TA>(v));
+                    tile_store<TA, FWD>(A, cur.r, orows[cur.sl], s0 + k, v);
+                }
+            }
+        }
+        cur = nxt;
+    }
+}
+
+template <int G, int J, int NR, typename TV, typename TA, bool FWD>
 __global__ __launch_bounds__(kTileBlock) void k_solve_tiled(SolveArgs A, TileArgs T) {
     using U = typename Pub<TA>::U;
-    constexpr int G = kTileLanes;
     extern __shared__ __align__(16) unsigned char tile_smem[];
     U *vals = reinterpret_cast<U *>(tile_smem);
     TA *rhs = reinterpret_cast<TA *>(tile_smem + T.off_rhs);
@@ -830,10 +1007,14 @@ __global__ __launch_bounds__(kTileBlock) void k_solve_tiled(SolveArgs A, TileArg
     uint16_t *es = reinterpret_cast<uint16_t *>(tile_smem + T.off_eslot);
     int32_t *rowid = reinterpret_cast<int32_t *>(tile_smem + T.off_rowid);
     int16_t *ps = reinterpret_cast<int16_t *>(tile_smem + T.off_pslot);
+    int32_t *impl = reinterpret_cast<int32_t *>(tile_smem + T.off_imp);
+    int32_t *orows = reinterpret_cast<int32_t *>(tile_smem + T.off_orow);
     __shared__ int s_tile;
+    __shared__ int s_abort;
     if (threadIdx.x == 0) {
         if (T.zero_counter && blockIdx.x == 0) T.zero_counter[0] = 0;
         s_tile = __hip_atomic_fetch_add(T.counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_abort = 0;
     }
     __syncthreads();
     const int tile = s_tile;
@@ -849,22 +1030,77 @@ __global__ __launch_bounds__(kTileBlock) void k_solve_tiled(SolveArgs A, TileArg
     const int64_t cap = A.cap;
     const int t = threadIdx.x % G;
 
-    // stage the tile: position -> slot, then per row its dependency slots and values
-    for (int q = threadIdx.x; q < npos; q += kTileBlock) ps[q] = (int16_t)T.pslot[pbase + q];
-    for (int sl = threadIdx.x / G; sl < nrows; sl += kTileBlock / G) {
-        const int r = T.rows[rbase + sl];
-        const int d = A.diag[r];
-        const int lo = FWD ? A.rp[r] : d + 1;
-        const int hi = FWD ? d : A.rp[r + 1];
-        if (t == 0) {
-            rowid[sl] = r;
-            piv[sl] = A.unit_diag ? (TA)1 : (TA)load_val(val, d);
+    // stage the tile (every thread issues all loads of a step before it uses any):
+    // position -> slot, imports, then per row its id, pivot, dependency slots and
+    // values
+    lds_copy<kStageCopy>(ps, T.pslot + pbase, npos);
+    lds_copy<kStageCopy>(impl, T.imp + ibase, nimp);
+    constexpr int SR = kStageRows;
+    constexpr int SJ = G == 1 ? 4 : 2;   // entries per lane fetched with the batched loads
+    constexpr int GROUPS = kTileBlock / G;
+    for (int s0r = threadIdx.x / G; s0r < nrows; s0r += GROUPS * SR) {
+        int4 mt[SR];
+#pragma unroll
+        for (int u = 0; u < SR; ++u) {
+            const int sl = s0r + u * GROUPS;
+            mt[u] = sl < nrows ? T.meta[rbase + sl] : make_int4(-1, 0, 0, 0);
         }
-        for (int j = t; j < K; j += G) {
-            const int p = lo + j;
-            const bool on = p < hi;
-            es[sl * K + j] = (uint16_t)(on ? T.sci[p] : zero);
-            ev[sl * K + j] = on ? (TA)load_val(val, p) : (TA)0;
+        TA pv[SR];
+        int es_r[SR][SJ];
+        TA ev_r[SR][SJ];
+#pragma unroll
+        for (int u = 0; u < SR; ++u) {
+            pv[u] = (mt[u].x >= 0 && !A.unit_diag) ? (TA)load_val(val, mt[u].w) : (TA)1;
+#pragma unroll
+            for (int jj = 0; jj < SJ; ++jj) {
+                const int p = mt[u].y + t + jj * G;
+                const bool on = mt[u].x >= 0 && p < mt[u].z;
+                es_r[u][jj] = on ? T.sci[p] : zero;
+                ev_r[u][jj] = on ? (TA)load_val(val, p) : (TA)0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SR; ++u) {
+            const int sl = s0r + u * GROUPS;
+            if (sl >= nrows) continue;
+            if (t == 0) {
+                rowid[sl] = mt[u].x;
+                piv[sl] = pv[u];
+                if constexpr (!FWD) orows[sl] = mt[u].x;
+            }
+#pragma unroll
+            for (int jj = 0; jj < SJ; ++jj) {
+                const int j = t + jj * G;
+                if (j < K) {
+                    es[sl * K + j] = (uint16_t)es_r[u][jj];
+                    ev[sl * K + j] = ev_r[u][jj];
+                }
+            }
+            // longer rows: the rest one by one
+            for (int j = t + SJ * G; j < K; j += G) {
+                const int p = mt[u].y + j;
+                const bool on = p < mt[u].z;
+                es[sl * K + j] = (uint16_t)(on ? T.sci[p] : zero);
+                ev[sl * K + j] = on ? (TA)load_val(val, p) : (TA)0;
+            }
+        }
+    }
+    if constexpr (!FWD) {
+        if (A.perm) {
+            __syncthreads();
+            for (int i0 = threadIdx.x; i0 < nrows; i0 += kTileBlock * kStageCopy) {
+                int o[kStageCopy];
+#pragma unroll
+                for (int u = 0; u < kStageCopy; ++u) {
+                    const int i = i0 + u * kTileBlock;
+                    if (i < nrows) o[u] = A.perm[rowid[i]];
+                }
+#pragma unroll
+                for (int u = 0; u < kStageCopy; ++u) {
+                    const int i = i0 + u * kTileBlock;
+                    if (i < nrows) orows[i] = o[u];
+                }
+            }
         }
     }
     __syncthreads();
@@ -874,70 +1110,52 @@ __global__ __launch_bounds__(kTileBlock) void k_solve_tiled(SolveArgs A, TileArg
         const int nr = A.nrhs - s0 < NR ? A.nrhs - s0 : NR;
         for (int i = threadIdx.x; i < (nrows + nimp) * NR; i += kTileBlock) vals[i] = Pub<TA>::kPend;
         if (threadIdx.x < NR) vals[zero * NR + threadIdx.x] = bits_of<TA>((TA)0);
-        for (int i = threadIdx.x; i < nrows * nr; i += kTileBlock) {
-            const int sl = i / nr, k = i - sl * nr;
-            const int r = rowid[sl];
-            TA b;
-            if constexpr (FWD) {
-                const int orow = A.perm ? A.perm[r] : r;
-                b = load_vec<TA>(A.b, A.vec_f32, (int64_t)orow * A.ld + s0 + k);
-            } else {
-                b = y[(int64_t)r * cap + s0 + k];
+        for (int i0 = threadIdx.x; i0 < nrows * nr; i0 += kTileBlock * kStageCopy) {
+            int64_t at[kStageCopy];
+#pragma unroll
+            for (int u = 0; u < kStageCopy; ++u) {
+                const int i = i0 + u * kTileBlock;
+                at[u] = -1;
+                if (i < nrows * nr) {
+                    const int sl = i / nr, k = i - sl * nr;
+                    const int r = rowid[sl];
+                    if constexpr (FWD) at[u] = (int64_t)r * A.ld + s0 + k;   // permuted below if needed
+                    else at[u] = (int64_t)r * cap + s0 + k;
+                }
             }
-            rhs[sl * NR + k] = b;
+            if constexpr (FWD) {
+                if (A.perm) {
+#pragma unroll
+                    for (int u = 0; u < kStageCopy; ++u) {
+                        const int i = i0 + u * kTileBlock;
+                        if (at[u] >= 0) {
+                            const int sl = i / nr, k = i - sl * nr;
+                            at[u] = (int64_t)A.perm[rowid[sl]] * A.ld + s0 + k;
+                        }
+                    }
+                }
+            }
+            TA bv[kStageCopy];
+#pragma unroll
+            for (int u = 0; u < kStageCopy; ++u) {
+                if (at[u] < 0) continue;
+                if constexpr (FWD) bv[u] = load_vec<TA>(A.b, A.vec_f32, at[u]);
+                else bv[u] = y[at[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kStageCopy; ++u) {
+                const int i = i0 + u * kTileBlock;
+                if (at[u] < 0) continue;
+                const int sl = i / nr, k = i - sl * nr;
+                rhs[sl * NR + k] = bv[u];
+            }
         }
         __syncthreads();
-        if (wave == kTileComputeWaves) {
-            tile_poll<NR, TA>(T.imp + ibase, nimp, FWD ? y : z, cap, s0, nr, vals, nrows, A.info, A.poll_sleep);
-        } else {
-            for (int c0 = wave * kTileUnit; c0 < npos; c0 += kTileComputeWaves * kTileUnit) {
-                const int sl = ps[c0 + gi];
-                if (sl < 0) continue;
-                TA acc[NR];
-#pragma unroll
-                for (int k = 0; k < NR; ++k) acc[k] = 0;
-                for (int j = t; j < K; j += G) {
-                    const int dsl = es[sl * K + j];
-                    const TA a = ev[sl * K + j];
-                    U *src = vals + dsl * NR;
-                    U raw[NR];
-#pragma unroll
-                    for (int k = 0; k < NR; ++k) raw[k] = k < nr ? lds_ld<TA>(src + k) : 0;
-#pragma unroll
-                    for (int k = 0; k < NR; ++k) {
-                        if (k < nr) {
-                            TA xc = Pub<TA>::from(raw[k]);
-                            if (raw[k] == Pub<TA>::kPend) xc = lds_wait<TA>(src + k, A.info);
-                            const TA prod = a * xc;
-                            acc[k] = acc[k] + prod;
-                        }
-                    }
-                }
-                const int r = rowid[sl];
-                const TA pv = piv[sl];
-#pragma unroll
-                for (int k = 0; k < NR; ++k) {
-                    const TA sum = group_sum<G>(acc[k]);
-                    if (k < nr && (k % G) == t) {
-                        TA v = rhs[sl * NR + k] - sum;
-                        if (!A.unit_diag) v = v / pv;
-                        lds_st<TA>(vals + sl * NR + k, bits_of<TA>(v));
-                        const int64_t o = (int64_t)r * cap + s0 + k;
-                        if constexpr (FWD) {
-                            Pub<TA>::publish(&y[o], v);
-                            z[o] = Pub<TA>::pending();
-                            if (A.y_out) static_cast<TA *>(A.y_out)[(int64_t)r * A.ld + s0 + k] = v;
-                        } else {
-                            Pub<TA>::publish(&z[o], v);
-                            y[o] = Pub<TA>::pending();
-                            const int orow = A.perm ? A.perm[r] : r;
-                            store_vec<TA>(A.x, A.vec_f32, (int64_t)orow * A.ld + s0 + k, v);
-                            if (A.z_out) static_cast<TA *>(A.z_out)[(int64_t)r * A.ld + s0 + k] = v;
-                        }
-                    }
-                }
-            }
-        }
+        if (wave == kTileComputeWaves)
+            tile_poll<NR, TA>(impl, nimp, FWD ? y : z, cap, s0, nr, vals, nrows, A.info, A.poll_sleep, &s_abort);
+        else
+            tile_compute<G, J, NR, TA, FWD>(A, vals, ev, es, ps, rowid, orows, piv, rhs, K, npos, wave, gi, t, s0, nr,
+                                            &s_abort);
         __syncthreads();
     }
 }
@@ -1205,7 +1423,13 @@ static size_t tile_layout(const TileArgs &T, int nr, int acc, TileArgs *out) {
     o = align8(o + (size_t)T.max_rows * 4);
     const size_t psl = o;
     o = align8(o + (size_t)T.max_pos * 2);
+    const size_t imp = o;
+    o = align8(o + (size_t)(T.max_slots - T.max_rows > 0 ? T.max_slots : 0) * 4);
+    const size_t orw = o;
+    o = align8(o + (size_t)T.max_rows * 4);
     if (out) {
+        out->off_imp = (int32_t)imp;
+        out->off_orow = (int32_t)orw;
         out->off_rhs = (int32_t)rhs;
         out->off_piv = (int32_t)pv;
         out->off_eval = (int32_t)evl;
@@ -1226,23 +1450,39 @@ size_t tile_lds_bytes(int max_rows, int max_slots, int max_pos, int kmax, int nr
     return tile_layout(T, nr, acc_bytes, nullptr);
 }
 
-template <int NR, typename TV, typename TA>
+template <int G, int J, int NR, typename TV, typename TA>
 static hipError_t tiled_launch(const SolveArgs &A, const TileArgs &T0, bool fwd, hipStream_t s) {
     TileArgs T = T0;
     const size_t lds = tile_layout(T, NR, sizeof(TA), &T);
     if (lds > (size_t)kTileLdsMax || T.max_slots + 1 > 65535 || T.max_pos > 32767) return hipErrorInvalidValue;
     if (T.ntiles <= 0) return hipSuccess;
-    if (fwd) hipLaunchKernelGGL((k_solve_tiled<NR, TV, TA, true>), dim3(T.ntiles), dim3(kTileBlock), lds, s, A, T);
-    else hipLaunchKernelGGL((k_solve_tiled<NR, TV, TA, false>), dim3(T.ntiles), dim3(kTileBlock), lds, s, A, T);
+    if (fwd)
+        hipLaunchKernelGGL((k_solve_tiled<G, J, NR, TV, TA, true>), dim3(T.ntiles), dim3(kTileBlock), lds, s, A, T);
+    else
+        hipLaunchKernelGGL((k_solve_tiled<G, J, NR, TV, TA, false>), dim3(T.ntiles), dim3(kTileBlock), lds, s, A, T);
     return hipGetLastError();
 }
 
-// right-hand sides per pass: 4 when that blocking fits LDS, else 1
+// lanes per row from the tiling's chunk size; right-hand sides per pass: 4 when
+// that blocking fits LDS, else 1
+template <int NR, typename TV, typename TA>
+static hipError_t tiled_lanes(const SolveArgs &A, const TileArgs &T, bool fwd, hipStream_t s) {
+    if (T.unit == 64) {
+        if (T.kmax > kTileShortRow) return hipErrorInvalidValue;
+        return tiled_launch<1, kTileShortRow, NR, TV, TA>(A, T, fwd, s);
+    }
+    if (T.unit == 16) {
+        if (T.kmax > 4 * kTileLongJ) return hipErrorInvalidValue;
+        return tiled_launch<4, kTileLongJ, NR, TV, TA>(A, T, fwd, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 template <typename TV, typename TA>
 static hipError_t tiled_dispatch(const SolveArgs &A, const TileArgs &T, bool fwd, hipStream_t s) {
     if (A.nrhs > 1 && tile_layout(T, 4, sizeof(TA), nullptr) <= (size_t)kTileLdsMax)
-        return tiled_launch<4, TV, TA>(A, T, fwd, s);
-    return tiled_launch<1, TV, TA>(A, T, fwd, s);
+        return tiled_lanes<4, TV, TA>(A, T, fwd, s);
+    return tiled_lanes<1, TV, TA>(A, T, fwd, s);
 }
 
 hipError_t launch_solve_tiled(const SolveArgs &A, const TileArgs &T, bool forward, int prec, int vec,

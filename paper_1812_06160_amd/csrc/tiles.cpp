@@ -23,7 +23,7 @@ namespace jv {
 
 namespace {
 
-void tiles_one(const HostAnalysis &H, int dir, int32_t cap, int32_t unit, TileSet *T, std::vector<int32_t> *sci) {
+void tiles_one(const HostAnalysis &H, int dir, int32_t cap, int32_t short_row, TileSet *T, std::vector<int32_t> *sci) {
     const int32_t n = H.n;
     const std::vector<int32_t> &rp = H.lu_rp, &ci = H.lu_ci, &dg = H.diag;
     auto dbeg = [&](int32_t r) { return dir == 0 ? rp[r] : dg[r] + 1; };
@@ -105,18 +105,19 @@ void tiles_one(const HostAnalysis &H, int dir, int32_t cap, int32_t unit, TileSe
         }
     // per tile: rows by local level (stable in placement order), each level padded;
     // slots: rows in position order, then the tile's imports
+    T->kmax = 0;
+    for (int32_t r = 0; r < n; ++r) T->kmax = std::max(T->kmax, dend(r) - dbeg(r));
+    const int32_t unit = T->kmax <= short_row ? 64 : 16;
     T->cap = cap;
     T->unit = unit;
     T->ntiles = ntiles;
     T->max_rows = T->max_slots = T->max_pos = 0;
-    T->kmax = 0;
     T->ptr.assign(1, 0);
     T->row.clear();
     T->rows_ptr.assign(1, 0);
     T->rows.clear();
     T->imp_ptr.assign(1, 0);
     T->imp.clear();
-    for (int32_t r = 0; r < n; ++r) T->kmax = std::max(T->kmax, dend(r) - dbeg(r));
     std::vector<int32_t> slot(n, -1), imp_slot(n, -1);
     size_t a = 0;
     for (int32_t t = 0; t < ntiles; ++t) {
@@ -165,11 +166,11 @@ void tiles_one(const HostAnalysis &H, int dir, int32_t cap, int32_t unit, TileSe
 
 }  // namespace
 
-void build_tiles(const HostAnalysis &H, int32_t cap, int32_t unit, TileSet *fwd, TileSet *bwd,
+void build_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, TileSet *fwd, TileSet *bwd,
                  std::vector<int32_t> *sci) {
     sci->assign(H.lu_ci.size(), -1);
-    tiles_one(H, 0, cap, unit, fwd, sci);
-    tiles_one(H, 1, cap, unit, bwd, sci);
+    tiles_one(H, 0, cap, short_row, fwd, sci);
+    tiles_one(H, 1, cap, short_row, bwd, sci);
 }
 
 }  // namespace jv

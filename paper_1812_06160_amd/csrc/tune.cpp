@@ -1,6 +1,7 @@
 // Autotuner: times the launch schemes (one launch per level vs one persistent
-// sync-free launch) and the lanes per row of the factor and of the FP64 apply on
-// the handle's own matrix, and keeps the fastest.  The factor is deterministic, so
+// sync-free launch, and for the apply also the tiled launch) and the lanes per
+// row of the factor and of the FP64 apply on the handle's own matrix, and keeps
+// the fastest.  The factor is deterministic, so
 // re-running it with the same values reproduces the same factor bits.
 #include <hip/hip_runtime.h>
 
@@ -115,6 +116,25 @@ extern "C" ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, 
                 best_ls = lanes;
             }
         }
+    {   // tiled (one candidate: the handle's current tiles); not every tiling fits
+        h->sched_solve = ILU_SCHED_TILED;
+        double us = 0;
+        ilu_status st = time_it(
+            [&]() { return ilu_apply(h, b, x, 1, 1, ILU_PREC_F64, ILU_PREC_F64, ILU_PERMUTED_SPACE, s); }, &us);
+        if (st == ILU_OK) {
+            rows.insert(rows.end(), {1.0, (double)ILU_SCHED_TILED, 0.0, us});
+            if (us < best) {
+                best = us;
+                best_ss = ILU_SCHED_TILED;
+                best_ls = save_ls;
+            }
+        } else if (st != ILU_ERR_UNSUPPORTED) {
+            (void)hipFree(buf);
+            h->sched_solve = save_ss;
+            h->lanes_solve = save_ls;
+            return st;
+        }
+    }
     (void)hipStreamSynchronize(s);
     (void)hipFree(buf);
     h->sched_solve = best_ss;
