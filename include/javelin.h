@@ -64,7 +64,8 @@ enum {
 
 /* Scheduling of the factor and the triangular solves. */
 enum {
-    ILU_SCHED_AUTO = 0,       /* the handle's current choice (sync-free unless tuned otherwise) */
+    ILU_SCHED_AUTO = 0,       /* the handle's current choice: after analysis the factor is sync-free
+                                 and the solves are tiled when the tiles fit LDS (else sync-free) */
     ILU_SCHED_LEVEL = 1,      /* one kernel launch per level: the launch boundary is the barrier */
     ILU_SCHED_SYNCFREE = 2,   /* one launch for all levels; rows wait on per-row published values */
     ILU_SCHED_TILED = 3       /* solves only: one launch; rows grouped into tiles, one workgroup per

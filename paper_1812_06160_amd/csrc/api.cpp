@@ -428,6 +428,8 @@ extern "C" ilu_status ilu_analyze(const ilu_csr *A, const ilu_analyze_opts *opts
     h->host_only = o.host_only != 0;
     if (!h->host_only && (st = finish_analysis(h.get())) != ILU_OK) return st;
     if ((st = h->make_tiles(o.tile_rows ? o.tile_rows : kDefaultTileRows, o.tile_rows == 0)) != ILU_OK) return st;
+    // the solves default to the tiled launch wherever the tiles fit LDS
+    h->sched_solve = tiles_fit(h->tiles[0]) && tiles_fit(h->tiles[1]) ? ILU_SCHED_TILED : ILU_SCHED_SYNCFREE;
     *out = h.release();
     return ILU_OK;
 }
