@@ -36,10 +36,10 @@ HBM_PEAK_GBS = 8000.0
 # scaled by what the same counters read for the calibration copy kernels.  Valid
 # only for the kernel source it was taken with: a different hash reports null.
 PMC_TRAFFIC = dict(
-    kernels_sha256="aa83d12660e54a44a8bab2e44da0ed1c0cd47e0ca86ce1869a0aec8469e23d91",
-    fetch_scale=1.9986, write_scale=0.9943,
-    forward=dict(f64=(129327, 35109), f32=(92342, 19516)),
-    backward=dict(f64=(133830, 51523), f32=(92480, 35930)),
+    kernels_sha256="6e051b5056454a543d0e5d9d8fd32e710ee5297d5fb8b5dd9a482f54d79aecf9",
+    fetch_scale=1.9987, write_scale=0.9941,
+    forward=dict(f64=(187438, 66160), f32=(155403, 51191)),
+    backward=dict(f64=(189269, 93862), f32=(149057, 78535)),
 )
 
 
