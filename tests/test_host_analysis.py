@@ -136,3 +136,97 @@ def test_numeric_calls_on_host_only_handle_report_state():
     assert lib.ilu_set_schedule(h.h, 1, 2, 0, 8) == L.OK
     assert lib.ilu_set_schedule(h.h, 5, 0, 0, 0) == L.ERR_ARG
     assert lib.ilu_set_schedule(h.h, 0, 0, 3, 0) == L.ERR_ARG
+
+
+# ---------------------------------------------------------------------------------
+# Tiles of the tiled triangular solves (host side)
+# ---------------------------------------------------------------------------------
+
+def _check_tiles(h, n):
+    """Every row once per direction; tile order topological; no dependency inside a
+    run of 16 positions; slot encoding of every off-diagonal entry."""
+    sch = h.schedule()
+    rp, ci, dg = sch["lu_row_ptr"], sch["lu_col_idx"], sch["diag_pos"]
+    for d in (0, 1):
+        ptr, row, sci = h.tiles(d)
+        assert ptr[0] == 0 and np.all(np.diff(ptr) > 0) and np.all(np.diff(ptr) % 16 == 0)
+        real = row[row >= 0]
+        assert len(real) == n and len(np.unique(real)) == n
+        tile_of = np.empty(n, np.int64)
+        pos = np.empty(n, np.int64)
+        slot = np.empty(n, np.int64)
+        nrows = np.empty(len(ptr) - 1, np.int64)
+        for t in range(len(ptr) - 1):
+            seg = row[ptr[t]:ptr[t + 1]]
+            m = seg >= 0
+            tile_of[seg[m]] = t
+            pos[seg[m]] = np.nonzero(m)[0]
+            slot[seg[m]] = np.arange(m.sum())
+            nrows[t] = m.sum()
+        imports = {}
+        for r in range(n):
+            lo, hi = (rp[r], dg[r]) if d == 0 else (dg[r] + 1, rp[r + 1])
+            t = tile_of[r]
+            for p in range(lo, hi):
+                c = ci[p]
+                assert tile_of[c] <= t
+                if tile_of[c] == t:
+                    assert sci[p] == slot[c]
+                    assert pos[c] // 16 < pos[r] // 16
+                else:
+                    assert sci[p] >= nrows[t]
+                    assert imports.setdefault((t, c), sci[p]) == sci[p]
+            assert sci[dg[r]] == -1
+        per_tile = {}
+        for (t, c), s in imports.items():
+            per_tile.setdefault(t, []).append(s)
+        for t, sl in per_tile.items():   # import slots of a tile are distinct and contiguous
+            assert sorted(sl) == list(range(nrows[t], nrows[t] + len(sl)))
+
+
+@pytest.mark.parametrize("name,mk,k,sym,tile_rows", [
+    ("laplace3d_12", lambda: synth.laplace3d(12), 0, True, 256),
+    ("laplace2d_30", lambda: synth.laplace2d(30), 0, True, 100),
+    ("convdiff3d_8_ilu1", lambda: synth.convdiff3d(8), 1, True, 128),
+    ("random_1500_lower_a", lambda: synth.random_banded(1500, rng=np.random.default_rng(21)), 0, False, 200),
+    ("random_sparse_ilu2", lambda: synth.random_sparse(300, 0.015, np.random.default_rng(7)), 2, False, 64),
+    ("tridiag_200", lambda: synth.tridiag(200), 0, True, 16),
+    ("one_tile", lambda: synth.laplace2d(10), 0, True, 4096),
+], ids=lambda v: v if isinstance(v, str) else "")
+def test_tiles_invariants(name, mk, k, sym, tile_rows):
+    A = mk()
+    h = jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=k, pattern="sym" if sym else "a", host_only=True,
+               tile_rows=tile_rows)
+    info = h.info()
+    assert info["tile_rows"] == tile_rows and info["max_tile"] <= tile_rows
+    _check_tiles(h, A.n)
+
+
+def test_tiles_are_cubes_on_grids():
+    # greedy growth gives compact blocks without coordinates: 8^3 cubes at 512 rows
+    # on a 3D 7-point grid, 16 x 16 squares at 256 rows on a 2D 5-point grid
+    for A, m, t, side, dims in [(synth.laplace3d(16), 16, 512, 8, 3), (synth.laplace2d(64), 64, 256, 16, 2)]:
+        h = jv.Ilu(A.n, A.row_ptr, A.col_idx, host_only=True, tile_rows=t)
+        perm = h.schedule()["perm"]
+        for d in (0, 1):
+            ptr, row, _ = h.tiles(d)
+            assert len(ptr) - 1 == A.n // t
+            for q in range(len(ptr) - 1):
+                o = perm[row[ptr[q]:ptr[q + 1]][row[ptr[q]:ptr[q + 1]] >= 0]]
+                coords = [(o // m ** a) % m // side for a in range(dims)]
+                assert len(o) == t and all(len(np.unique(c)) == 1 for c in coords)
+
+
+def test_tiles_default_fits_and_retile():
+    A = synth.laplace3d(10)
+    h = jv.Ilu(A.n, A.row_ptr, A.col_idx, host_only=True)
+    assert h.info()["tile_rows"] == 512 and h.get_schedule()["solve"] == "tiled"
+    h.set_tuning("tile_rows", 64)
+    assert h.get_tuning("tile_rows") == 64 and h.info()["tile_rows"] == 64
+    _check_tiles(h, A.n)
+    with pytest.raises(jv.IluError):
+        h.set_tuning("tile_rows", 8)
+    # rows longer than any tiled launch handles: the default tiles are not used
+    D = synth.dense_pattern(40, np.random.default_rng(3))
+    hd = jv.Ilu(D.n, D.row_ptr, D.col_idx, host_only=True)
+    assert hd.get_schedule()["solve"] == "syncfree"
