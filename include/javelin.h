@@ -64,12 +64,12 @@ enum {
 
 /* Scheduling of the factor and the triangular solves. */
 enum {
-    ILU_SCHED_AUTO = 0,       /* the handle's current choice: after analysis the factor is sync-free
-                                 and the solves are tiled when the tiles fit LDS (else sync-free) */
+    ILU_SCHED_AUTO = 0,       /* the handle's current choice: after analysis the factor and the
+                                 solves are tiled where their tiles fit LDS, else sync-free */
     ILU_SCHED_LEVEL = 1,      /* one kernel launch per level: the launch boundary is the barrier */
     ILU_SCHED_SYNCFREE = 2,   /* one launch for all levels; rows wait on per-row published values */
-    ILU_SCHED_TILED = 3       /* solves only: one launch; rows grouped into tiles, one workgroup per
-                                 tile, dependencies inside a tile resolved in LDS (Sec. III's
+    ILU_SCHED_TILED = 3       /* one launch; rows grouped into tiles, one workgroup per tile,
+                                 dependencies inside a tile resolved in LDS (Sec. III's
                                  point-to-point waits, kept on-chip where the tile allows) */
 };
 
@@ -282,7 +282,9 @@ ilu_status ilu_solve_gmres(ilu_handle h, const double *b, double *x, double rtol
 /* Scheduling and tuning.                                                         */
 /* ---------------------------------------------------------------------------- */
 
-/* Chooses the launch scheme of the factor and of the solves (ILU_SCHED_*) and the
+/* Chooses the launch scheme of the factor and of the solves (ILU_SCHED_*; the
+ * tiled factor runs plain ILU only -- k = k_max and tau = 0 -- and otherwise the
+ * call runs the sync-free factor) and the
  * lanes per row (0 = automatic from the longest row; else 4, 8, 16, 32 or 64;
  * factor lanes must cover the longest factor row). */
 ilu_status ilu_set_schedule(ilu_handle h, int32_t factor_sched, int32_t solve_sched,
@@ -295,7 +297,9 @@ ilu_status ilu_get_schedule(ilu_handle h, int32_t *factor_sched, int32_t *solve_
  * rebuilds the tiles of the tiled solves on the host and uploads them;
  * synchronous).  Readable as well:
  * "nstreams" (task streams = XCDs found), "factor_tcap" (LDS entries staged per
- * factor row).  Unknown keys give ILU_ERR_ARG. */
+ * factor row), "factor_tiled" (1 if the tiled factor can run on this handle:
+ * rows of at most 16 entries and tiles that fit LDS).  Unknown keys give
+ * ILU_ERR_ARG. */
 ilu_status ilu_set_tuning(ilu_handle h, const char *key, int64_t value);
 ilu_status ilu_get_tuning(ilu_handle h, const char *key, int64_t *value);
 

@@ -64,6 +64,7 @@ struct TileSet {
     int32_t max_rows = 0;              // most rows in one tile
     int32_t max_slots = 0;             // most rows + imports in one tile
     int32_t max_pos = 0;               // most positions (rows + padding) in one tile
+    int32_t max_imps = 0;              // most imports of one tile
     int32_t kmax = 0;                  // longest dependency list of a row
     std::vector<int32_t> ptr;          // [ntiles + 1] padded positions
     std::vector<int32_t> row;          // row (level ordering) at each position, -1 for padding
@@ -80,6 +81,31 @@ struct TileSet {
 // (one lane per row), otherwise to chunks of 16 (four lanes per row).
 void build_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, TileSet *fwd, TileSet *bwd,
                  std::vector<int32_t> *sci);
+
+// Data of the tiled factor on the forward tiles.  LDS of a tile: the value area
+// (the tile's rows' entries in slot order, then the U parts -- diagonal first -- of
+// its imports) and one ready flag per tile row and per import.  Per tile row:
+// meta (row, first entry, end entry, diagonal entry) and (value-area offset,
+// offset of its first L entry among the tile's L entries).  Per L entry
+// (r, c) in tile order: the value-area location of U(c)'s diagonal, the ready
+// flag of c, and for each lane t < lanes the index j >= 1 in U(c) of the column
+// of entry t of row r (-1 if that column is not in U(c)).  Per import: the factor
+// entry of its diagonal, the length of its U part, its value-area offset.
+struct FactorTiles {
+    int32_t lanes = 0;                 // lanes per row (>= longest row)
+    int32_t max_vals = 0;              // largest value area (entries)
+    int32_t max_lents = 0;             // most L entries in one tile
+    std::vector<int32_t> meta;         // 4 per tile row (slot order, tiles concatenated)
+    std::vector<int32_t> off;          // 2 per tile row: value-area offset, L-entry offset
+    std::vector<int32_t> lptr;         // [ntiles + 1] offsets of each tile's L entries
+    std::vector<int32_t> dloc, dflag;  // per L entry
+    std::vector<int8_t> match;         // lanes per L entry
+    std::vector<int32_t> imp;          // 4 per import: diagonal entry, U length, value-area offset, 0
+};
+
+// Builds the tiled-factor data from the forward tiles; lanes = power of two >= the
+// longest factor row (the caller checks it is at most 16).
+void build_factor_tiles(const HostAnalysis &H, const TileSet &fwd, int32_t lanes, FactorTiles *F);
 
 // Returns ILU_OK or an error status with a message in *err.
 ilu_status analyze_host(int32_t n, const int32_t *rp, const int32_t *ci, int64_t nnz, int32_t k_max,

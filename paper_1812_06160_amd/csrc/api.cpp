@@ -201,7 +201,7 @@ hipError_t ilu_handle_s::reset_info(hipStream_t s) {
 static const int32_t kDefaultTileRows = 512;
 
 static const int kComplement[kPasses] = {-1,          kPassBackward, kPassForward, kPassTBackward,
-                                         kPassTForward, kPassTileB,   kPassTileF};
+                                         kPassTForward, kPassTileB,   kPassTileF,   -1};
 
 hipError_t ilu_handle_s::prepare_claims(int pass, const TaskList *tl, Claims *c, hipStream_t s) {
     int32_t *mine = d_counters + (size_t)pass * kStreams * kCounterStride;
@@ -300,6 +300,51 @@ ilu_status ilu_handle_s::make_tiles(int32_t rows, bool shrink) {
             return hip_fail(e, "tiles: upload");
     }
     if ((e = put(d_sci, sci)) != hipSuccess) return hip_fail(e, "tiles: upload");
+    return make_factor_tiles();
+}
+
+// The tiled factor needs the forward tiles, rows of at most kFactorMaxLanes
+// entries and a tile image that fits LDS.
+ilu_status ilu_handle_s::make_factor_tiles() {
+    ftiles_ok = false;
+    if (H.max_row_lu > kFactorMaxLanes || tiles[0].ntiles == 0) return ILU_OK;
+    const int32_t lanes = H.max_row_lu <= 8 ? 8 : 16;
+    try {
+        build_factor_tiles(H, tiles[0], lanes, &ftiles);
+    } catch (const std::bad_alloc &) {
+        return fail(ILU_ERR_NOMEM, "factor tiles: out of host memory");
+    }
+    FactorTileArgs T{};
+    T.max_rows = tiles[0].max_rows;
+    T.max_vals = ftiles.max_vals;
+    T.max_lents = ftiles.max_lents;
+    T.max_pos = tiles[0].max_pos;
+    T.max_imps = tiles[0].max_imps;
+    if (factor_tile_lds_bytes(T, lanes) > (size_t)kFactorTileLdsMax) return ILU_OK;
+    if (host_only) {
+        ftiles_ok = true;
+        return ILU_OK;
+    }
+    auto drop = [&](auto *&d) {
+        if (d) {
+            (void)hipFree(d);
+            allocs_erase(this, d);
+            d = nullptr;
+        }
+    };
+    auto put = [&](auto *&d, const auto &v) -> hipError_t {
+        drop(d);
+        hipError_t e = upload(&d, v);
+        if (e == hipSuccess && d) allocs.push_back(d);
+        return e;
+    };
+    hipError_t e;
+    if ((e = put(dft.meta, ftiles.meta)) != hipSuccess || (e = put(dft.off, ftiles.off)) != hipSuccess ||
+        (e = put(dft.lptr, ftiles.lptr)) != hipSuccess || (e = put(dft.dloc, ftiles.dloc)) != hipSuccess ||
+        (e = put(dft.dflag, ftiles.dflag)) != hipSuccess || (e = put(dft.match, ftiles.match)) != hipSuccess ||
+        (e = put(dft.imp, ftiles.imp)) != hipSuccess)
+        return hip_fail(e, "factor tiles: upload");
+    ftiles_ok = true;
     return ILU_OK;
 }
 
@@ -430,6 +475,7 @@ extern "C" ilu_status ilu_analyze(const ilu_csr *A, const ilu_analyze_opts *opts
     if ((st = h->make_tiles(o.tile_rows ? o.tile_rows : kDefaultTileRows, o.tile_rows == 0)) != ILU_OK) return st;
     // the solves default to the tiled launch wherever the tiles fit LDS
     h->sched_solve = tiles_fit(h->tiles[0]) && tiles_fit(h->tiles[1]) ? ILU_SCHED_TILED : ILU_SCHED_SYNCFREE;
+    h->sched_factor = h->ftiles_ok ? ILU_SCHED_TILED : ILU_SCHED_SYNCFREE;
     *out = h.release();
     return ILU_OK;
 }
@@ -580,7 +626,40 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
     A.info = h->d_info;
     A.tcap = factor_lds_bytes(lanes, h->factor_tcap) ? h->factor_tcap : 0;
     A.max_lower = H.max_lower_lu;
-    if (sf) {
+    // the tiled factor covers plain ILU (every pattern entry kept, no dropping);
+    // anything else runs the sync-free factor
+    bool tiled = h->sched_factor == ILU_SCHED_TILED && h->ftiles_ok && !use_tau && !A.use_flev;
+    if (tiled) {
+        const TileSet &T0 = h->tiles[0];
+        const ilu_handle_s::DevTiles &D = h->dtiles[0];
+        FactorTileArgs T{};
+        T.tile_ptr = D.ptr;
+        T.pslot = D.pslot;
+        T.rows_ptr = D.rows_ptr;
+        T.meta = reinterpret_cast<const int4 *>(h->dft.meta);
+        T.off = reinterpret_cast<const int2 *>(h->dft.off);
+        T.lptr = h->dft.lptr;
+        T.dloc = h->dft.dloc;
+        T.dflag = h->dft.dflag;
+        T.match = h->dft.match;
+        T.imp_ptr = D.imp_ptr;
+        T.imp = reinterpret_cast<const int4 *>(h->dft.imp);
+        T.ntiles = T0.ntiles;
+        T.max_rows = T0.max_rows;
+        T.max_vals = h->ftiles.max_vals;
+        T.max_lents = h->ftiles.max_lents;
+        T.max_pos = T0.max_pos;
+        T.max_imps = T0.max_imps;
+        T.counter = h->d_counters + (size_t)kPassFactorTile * kStreams * kCounterStride;
+        A.poll_sleep = h->poll_sleep;
+        if ((e = launch_fill_u64((uint64_t *)h->d_lu, kPending64, H.lu_rp[H.n], s)) != hipSuccess)
+            return hip_fail(e, "ilu_factor: arm");
+        if ((e = launch_zero_counters(T.counter, s)) != hipSuccess) return hip_fail(e, "ilu_factor: claims");
+        h->prof.begin(ILU_STAGE_FACTOR, s);
+        e = launch_factor_tiled(A, T, h->ftiles.lanes, s);
+        h->prof.end(s);
+        if (e != hipSuccess) return hip_fail(e, "ilu_factor: tiled launch");
+    } else if (sf) {
         const TaskList *tl = h->task_list(kTasksForward, lanes);
         if (!tl) return fail(ILU_ERR_NOMEM, "ilu_factor: task list");
         if ((e = launch_fill_u64((uint64_t *)h->d_lu, kPending64, H.lu_rp[H.n], s)) != hipSuccess)
@@ -1006,7 +1085,7 @@ static bool valid_lanes(int l) { return l == 0 || l == 4 || l == 8 || l == 16 ||
 extern "C" ilu_status ilu_set_schedule(ilu_handle h, int32_t factor_sched, int32_t solve_sched, int32_t lanes_factor,
                                        int32_t lanes_solve) {
     if (!h) return fail(ILU_ERR_ARG, "ilu_set_schedule: NULL handle");
-    if (factor_sched < 0 || factor_sched > 2 || solve_sched < 0 || solve_sched > 3 || !valid_lanes(lanes_factor) ||
+    if (factor_sched < 0 || factor_sched > 3 || solve_sched < 0 || solve_sched > 3 || !valid_lanes(lanes_factor) ||
         !valid_lanes(lanes_solve))
         return fail(ILU_ERR_ARG, "ilu_set_schedule: bad value");
     if (factor_sched) h->sched_factor = factor_sched;
@@ -1052,6 +1131,7 @@ extern "C" ilu_status ilu_get_tuning(ilu_handle h, const char *key, int64_t *val
     if (k == "nstreams") { *value = h->nstreams; return ILU_OK; }
     if (k == "factor_tcap") { *value = h->factor_tcap; return ILU_OK; }
     if (k == "tile_rows") { *value = h->tile_rows; return ILU_OK; }
+    if (k == "factor_tiled") { *value = h->ftiles_ok ? 1 : 0; return ILU_OK; }
     return fail(ILU_ERR_ARG, "ilu_get_tuning: unknown key " + k);
 }
 

@@ -127,9 +127,30 @@ constexpr int kTileComputeWaves = 8;
 constexpr int kTileShortRow = 1;
 constexpr int kTileLongJ = 8;
 constexpr int kTileBlock = 64 * (kTileComputeWaves + 1);
-constexpr int kTileLdsMax = 65536;    // dynamic LDS bytes a tiled launch may use
+constexpr int kTileLdsMax = 65536;    // dynamic LDS bytes a tiled solve may use
+constexpr int kFactorTileLdsMax = 163840;   // the whole LDS of a compute unit (opt-in above 64 KB)
+constexpr int kFactorMaxLanes = 16;         // longest factor row of the tiled factor
 // LDS a tiling needs with `nr` right-hand sides per pass of `acc_bytes` each
 size_t tile_lds_bytes(int max_rows, int max_slots, int max_pos, int kmax, int nr, int acc_bytes);
+
+// Tiled factor (plain ILU: every pattern entry kept, no dropping) on the forward
+// tiles; see FactorTiles in analysis.h for the data.
+struct FactorTileArgs {
+    const int32_t *tile_ptr;  // [ntiles + 1] positions (forward tiles)
+    const int16_t *pslot;     // slot of each position, -1 for padding
+    const int32_t *rows_ptr;  // [ntiles + 1] offsets into meta / off
+    const int4 *meta;         // per tile row: row, first entry, end entry, diagonal entry
+    const int2 *off;          // per tile row: value-area offset, L-entry offset
+    const int32_t *lptr;      // [ntiles + 1] offsets into the L-entry arrays
+    const int32_t *dloc, *dflag;
+    const int8_t *match;      // lanes per L entry
+    const int32_t *imp_ptr;   // [ntiles + 1] offsets into imp
+    const int4 *imp;          // per import: diagonal entry, U length, value-area offset
+    int32_t ntiles, max_rows, max_vals, max_lents, max_pos, max_imps;
+    // LDS carve-up (bytes), set by the launcher
+    int32_t off_flags, off_meta, off_off, off_dloc, off_dflag, off_match, off_imp, off_pslot, lds_bytes;
+    int32_t *counter;         // claim counter (zero at launch)
+};
 
 struct SpmvArgs {
     int32_t n;
@@ -160,6 +181,10 @@ hipError_t launch_cast_bf16(int64_t m, const double *x, uint16_t *y, hipStream_t
 hipError_t launch_solve(const SolveArgs &A, bool forward, int prec, int vec, int lanes, bool syncfree,
                         int grid, hipStream_t s);
 hipError_t launch_spmv(const SpmvArgs &A, int lanes, hipStream_t s);
+// tiled factor with `lanes` (8 or 16) lanes per row; hipErrorInvalidValue when it
+// does not fit LDS
+hipError_t launch_factor_tiled(const FactorArgs &A, const FactorTileArgs &T, int lanes, hipStream_t s);
+size_t factor_tile_lds_bytes(const FactorTileArgs &T, int lanes);
 // tiled solve; returns hipErrorInvalidValue when no right-hand-side blocking fits LDS
 hipError_t launch_solve_tiled(const SolveArgs &A, const TileArgs &T, bool forward, int prec, int vec,
                               hipStream_t s);

@@ -38,7 +38,7 @@ struct TaskList {
 // claim-counter sets of the persistent passes
 enum {
     kPassFactor = 0, kPassForward = 1, kPassBackward = 2, kPassTForward = 3, kPassTBackward = 4,
-    kPassTileF = 5, kPassTileB = 6, kPasses = 7
+    kPassTileF = 5, kPassTileB = 6, kPassFactorTile = 7, kPasses = 8
 };
 
 ilu_status fail(ilu_status s, const std::string &msg);
@@ -91,9 +91,17 @@ struct ilu_handle_s {
         int16_t *pslot = nullptr;
     } dtiles[2];
     int32_t *d_sci = nullptr;
+    // tiled factor (plain ILU) on the forward tiles
+    jv::FactorTiles ftiles;
+    bool ftiles_ok = false;            // built and fits LDS
+    struct DevFactorTiles {
+        int32_t *meta = nullptr, *off = nullptr, *lptr = nullptr, *dloc = nullptr, *dflag = nullptr,
+                *imp = nullptr;
+        int8_t *match = nullptr;
+    } dft;
     jv::Profiler prof;
     int32_t *d_counters = nullptr;     // kPasses sets of claim counters
-    bool counters_dirty[jv::kPasses] = {false, false, false, false, false, false, false};
+    bool counters_dirty[jv::kPasses] = {false, false, false, false, false, false, false, false};
     int32_t factor_tcap = 0;           // LDS staging entries per factor row (0: unstaged)
     int32_t nstreams = 1;              // task streams (one per XCD)
     int32_t poll_sleep = 1;            // s_sleep(1) steps between polls (tunable)
@@ -120,6 +128,7 @@ struct ilu_handle_s {
     // (re)builds the tiles on the host and, unless host-only, uploads them; with
     // shrink, halves the tile size until the tiles fit the LDS budget
     ilu_status make_tiles(int32_t rows, bool shrink);
+    ilu_status make_factor_tiles();
     // claim counter of a tiled pass (launching a counter reset when needed)
     hipError_t prepare_tile_claims(int pass, jv::TileArgs *t, hipStream_t s);
 };

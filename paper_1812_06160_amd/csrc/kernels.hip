@@ -1161,6 +1161,212 @@ __global__ __launch_bounds__(kTileBlock) void k_solve_tiled(SolveArgs A, TileArg
 }
 
 // ---------------------------------------------------------------------------------
+// Tiled factor (plain ILU on the forward tiles): rows and imported U rows in LDS
+// ---------------------------------------------------------------------------------
+// The block of a tile stages, into LDS, the tile's rows (their input values), the
+// per-L-entry data (where U(c) sits in LDS, its ready flag, and each lane's index
+// into U(c)), and reserves room for the U parts of its imports, which the poller
+// wave copies from the factor buffer as they are published.  A compute wave
+// factors one chunk (64/G rows of one local level) at a time, G lanes per row,
+// lane t holding entry t: for the L entries in ascending column order, the lane of
+// the entry divides by u_cc, the multiplier is broadcast, and every lane whose
+// column is in U(c) subtracts l * u_cj -- the serial up-looking algorithm's
+// operations in its order (Sec. III, Fig. 1), so the result is bit for bit the
+// serial one.  A row then writes its values to LDS, raises its ready flag and
+// publishes its values to the factor buffer for other tiles.
+
+__device__ __forceinline__ int lds_wait_flag(int *f, int *lds_abort, int32_t *info) {
+    int spins = 0;
+    uint64_t t0 = 0;
+    for (;;) {
+        if (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) return 1;
+        __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 63) == 0) {
+            if (__hip_atomic_load(lds_abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return 0;
+            if (expired(t0)) {
+                __hip_atomic_store(&info[kInfoAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(lds_abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                return 0;
+            }
+        }
+    }
+}
+
+// (Ready flags guard values at other LDS addresses: they are raised with release
+// and polled with acquire semantics at workgroup scope.)
+//
+// Poller of the tiled factor: lane l holds imports l, l + 64 of the window (in
+// order of first use); each round loads every still-missing U value of a held
+// import, copies the published ones into LDS and raises the import's ready flag
+// once its whole U part is there.  The window moves by 64 when its first 64
+// imports are complete.  Bounded like every wait.
+__device__ void factor_poll(const int4 *imp, int nimp, const double *lu, double *vals, int *flags, int nrows,
+                            int32_t *info, int sleep0, int *lds_abort) {
+    const int lane = threadIdx.x & 63;
+    int head = 0, sleep = 0, spins = 0;
+    uint64_t t0 = 0;
+    uint32_t have[2] = {0u, 0u};   // U values already copied, per held import
+    while (head < nimp) {
+        bool got = false, left0 = false;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int i = head + 64 * b + lane;
+            if (i >= nimp) continue;
+            const int4 m = imp[i];
+            const uint32_t all = m.y >= 32 ? 0xFFFFFFFFu : ((1u << m.y) - 1u);
+            if (have[b] == all) continue;
+            uint64_t raw[kFactorMaxLanes];
+#pragma unroll
+            for (int j = 0; j < kFactorMaxLanes; ++j)
+                raw[j] = (j < m.y && !(have[b] >> j & 1u)) ? ld_acq_u64(reinterpret_cast<const uint64_t *>(lu + m.x + j))
+                                                           : kPending64;
+#pragma unroll
+            for (int j = 0; j < kFactorMaxLanes; ++j) {
+                if (j < m.y && !(have[b] >> j & 1u) && raw[j] != kPending64) {
+                    reinterpret_cast<uint64_t *>(vals)[m.z + j] = raw[j];
+                    have[b] |= 1u << j;
+                    got = true;
+                }
+            }
+            if (have[b] == all) __hip_atomic_store(&flags[nrows + i], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            else if (b == 0) left0 = true;
+        }
+        if (!__any(left0)) {
+            head += 64;
+            have[0] = have[1];
+            have[1] = 0u;
+            continue;
+        }
+        sleep = __any(got) ? sleep0 : (sleep * 2 + 1 < kPollMaxSleep ? sleep * 2 + 1 : kPollMaxSleep);
+        for (int k = 0; k < sleep; ++k) __builtin_amdgcn_s_sleep(1);
+        if ((++spins & 15) == 0) {
+            if (aborted(info)) break;
+            if (expired(t0)) {
+                __hip_atomic_store(&info[kInfoAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+    }
+    if (head >= nimp) return;
+    // aborted: release every waiter of this block
+    if (lane == 0) __hip_atomic_store(lds_abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <int G>
+__global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, FactorTileArgs T) {
+    extern __shared__ __align__(16) unsigned char fsmem[];
+    double *vals = reinterpret_cast<double *>(fsmem);
+    int *flags = reinterpret_cast<int *>(fsmem + T.off_flags);
+    int4 *meta = reinterpret_cast<int4 *>(fsmem + T.off_meta);
+    int2 *off = reinterpret_cast<int2 *>(fsmem + T.off_off);
+    int32_t *dloc = reinterpret_cast<int32_t *>(fsmem + T.off_dloc);
+    int32_t *dflag = reinterpret_cast<int32_t *>(fsmem + T.off_dflag);
+    int8_t *match = reinterpret_cast<int8_t *>(fsmem + T.off_match);
+    int4 *imp = reinterpret_cast<int4 *>(fsmem + T.off_imp);
+    int16_t *ps = reinterpret_cast<int16_t *>(fsmem + T.off_pslot);
+    __shared__ int s_tile, s_abort;
+    if (threadIdx.x == 0) {
+        s_tile = __hip_atomic_fetch_add(T.counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_abort = 0;
+    }
+    __syncthreads();
+    const int tile = s_tile;
+    if (tile >= T.ntiles) return;
+    const int pbase = T.tile_ptr[tile], npos = T.tile_ptr[tile + 1] - pbase;
+    const int rbase = T.rows_ptr[tile], nrows = T.rows_ptr[tile + 1] - rbase;
+    const int lbase = T.lptr[tile], nl = T.lptr[tile + 1] - lbase;
+    const int ibase = T.imp_ptr[tile], nimp = T.imp_ptr[tile + 1] - ibase;
+    const int t = threadIdx.x % G;
+
+    // stage the tile's tables
+    lds_copy<kStageCopy>(ps, T.pslot + pbase, npos);
+    lds_copy<kStageCopy>(reinterpret_cast<int *>(meta), reinterpret_cast<const int *>(T.meta + rbase), nrows * 4);
+    lds_copy<kStageCopy>(reinterpret_cast<int *>(off), reinterpret_cast<const int *>(T.off + rbase), nrows * 2);
+    lds_copy<kStageCopy>(dloc, T.dloc + lbase, nl);
+    lds_copy<kStageCopy>(dflag, T.dflag + lbase, nl);
+    lds_copy<kStageCopy>(reinterpret_cast<int *>(match), reinterpret_cast<const int *>(T.match + (int64_t)lbase * G),
+                         nl * G / 4);
+    lds_copy<kStageCopy>(reinterpret_cast<int *>(imp), reinterpret_cast<const int *>(T.imp + ibase), nimp * 4);
+    for (int i = threadIdx.x; i < nrows + nimp; i += kTileBlock) flags[i] = 0;
+    __syncthreads();
+    // input values of the tile's rows (fill entries start at 0); imported U parts pending
+    for (int i = threadIdx.x; i < nimp; i += kTileBlock) {
+        const int4 m = imp[i];
+        for (int j = 0; j < m.y; ++j) reinterpret_cast<uint64_t *>(vals)[m.z + j] = kPending64;
+    }
+    constexpr int SR = kStageRows;
+    constexpr int GROUPS = kTileBlock / G;
+    for (int s0r = threadIdx.x / G; s0r < nrows; s0r += GROUPS * SR) {
+        int src[SR];
+        int dst[SR];
+#pragma unroll
+        for (int u = 0; u < SR; ++u) {
+            const int sl = s0r + u * GROUPS;
+            src[u] = -1;
+            dst[u] = -1;
+            if (sl < nrows) {
+                const int4 m = meta[sl];
+                if (m.y + t < m.z) {
+                    dst[u] = off[sl].x + t;
+                    src[u] = A.src[m.y + t];
+                }
+            }
+        }
+        double a[SR];
+#pragma unroll
+        for (int u = 0; u < SR; ++u) a[u] = src[u] >= 0 ? A.a[src[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < SR; ++u)
+            if (dst[u] >= 0) vals[dst[u]] = a[u];
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    const int gi = (threadIdx.x & 63) / G;
+    if (wave == kTileComputeWaves) {
+        factor_poll(imp, nimp, A.lu, vals, flags, nrows, A.info, A.poll_sleep, &s_abort);
+        return;
+    }
+    constexpr int UNIT = 64 / G;
+    for (int c0 = wave * UNIT; c0 < npos; c0 += kTileComputeWaves * UNIT) {
+        const int sl = ps[c0 + gi];
+        if (sl < 0) continue;
+        const int4 m = meta[sl];
+        const int2 o = off[sl];
+        const int len = m.z - m.y, K = m.w - m.y;
+        const bool act = t < len;
+        double v = act ? vals[o.x + t] : 0.0;
+        for (int e = 0; e < K; ++e) {
+            const int li = o.y + e;
+            const int loc = dloc[li];
+            const int ok = lds_wait_flag(&flags[dflag[li]], &s_abort, A.info);
+            const double piv = ok ? vals[loc] : __longlong_as_double((long long)kQNaN64);
+            if (t == e) v = v / piv;
+            const double l = __shfl(v, e, G);
+            const int j = match[li * G + t];
+            if (j > 0) {
+                const double u = vals[loc + j];
+                const double prod = l * u;
+                v = v - prod;
+            }
+        }
+        // pivot and finiteness checks, as in the sync-free factor
+        const double pv = __shfl(v, K, G);
+        const bool nonfinite = act && !isfinite(v);
+        const uint64_t nfm = group_bits<G>(__ballot(nonfinite), gi);
+        if (t == 0) {
+            if (pv == 0.0) atomicMin(&A.info[kInfoBadKey], 2 * m.x);
+            else if (nfm) atomicMin(&A.info[kInfoBadKey], 2 * m.x + 1);
+        }
+        if (act) {
+            vals[o.x + t] = v;
+            const uint64_t bits = (v != v) ? kQNaN64 : (uint64_t)__double_as_longlong(v);
+            st_pub_u64(reinterpret_cast<uint64_t *>(&A.lu[m.y + t]), bits);
+        }
+        if (t == 0) __hip_atomic_store(&flags[sl], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
+// ---------------------------------------------------------------------------------
 // spmv y = alpha A x + beta y (paper Sec. I-II), one row per group
 // ---------------------------------------------------------------------------------
 template <int G, bool PERM>
@@ -1483,6 +1689,64 @@ static hipError_t tiled_dispatch(const SolveArgs &A, const TileArgs &T, bool fwd
     if (A.nrhs > 1 && tile_layout(T, 4, sizeof(TA), nullptr) <= (size_t)kTileLdsMax)
         return tiled_lanes<4, TV, TA>(A, T, fwd, s);
     return tiled_lanes<1, TV, TA>(A, T, fwd, s);
+}
+
+// LDS carve-up of a tiled factor launch
+static size_t factor_tile_layout(const FactorTileArgs &T, int G, FactorTileArgs *out) {
+    size_t o = align8((size_t)T.max_vals * 8);
+    const size_t fl = o;
+    o = align8(o + (size_t)(T.max_rows + T.max_imps) * 4);
+    const size_t me = o;
+    o = align8(o + (size_t)T.max_rows * 16);
+    const size_t of = o;
+    o = align8(o + (size_t)T.max_rows * 8);
+    const size_t dl = o;
+    o = align8(o + (size_t)T.max_lents * 4);
+    const size_t df = o;
+    o = align8(o + (size_t)T.max_lents * 4);
+    const size_t ma = o;
+    o = align8(o + (size_t)T.max_lents * G);
+    const size_t im = o;
+    o = align8(o + (size_t)T.max_imps * 16);
+    const size_t psl = o;
+    o = align8(o + (size_t)T.max_pos * 2);
+    if (out) {
+        out->off_flags = (int32_t)fl;
+        out->off_meta = (int32_t)me;
+        out->off_off = (int32_t)of;
+        out->off_dloc = (int32_t)dl;
+        out->off_dflag = (int32_t)df;
+        out->off_match = (int32_t)ma;
+        out->off_imp = (int32_t)im;
+        out->off_pslot = (int32_t)psl;
+        out->lds_bytes = (int32_t)o;
+    }
+    return o;
+}
+
+size_t factor_tile_lds_bytes(const FactorTileArgs &T, int lanes) { return factor_tile_layout(T, lanes, nullptr); }
+
+template <int G>
+static hipError_t factor_tiled_launch(const FactorArgs &A, const FactorTileArgs &T0, hipStream_t s) {
+    FactorTileArgs T = T0;
+    const size_t lds = factor_tile_layout(T, G, &T);
+    if (lds > (size_t)kFactorTileLdsMax) return hipErrorInvalidValue;
+    if (T.ntiles <= 0) return hipSuccess;
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute((const void *)k_factor_tiled<G>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_factor_tiled<G>), dim3(T.ntiles), dim3(kTileBlock), lds, s, A, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_factor_tiled(const FactorArgs &A, const FactorTileArgs &T, int lanes, hipStream_t s) {
+    switch (lanes) {
+        case 8: return factor_tiled_launch<8>(A, T, s);
+        case 16: return factor_tiled_launch<16>(A, T, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_solve_tiled(const SolveArgs &A, const TileArgs &T, bool forward, int prec, int vec,

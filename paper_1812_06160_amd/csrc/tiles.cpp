@@ -111,7 +111,7 @@ void tiles_one(const HostAnalysis &H, int dir, int32_t cap, int32_t short_row, T
     T->cap = cap;
     T->unit = unit;
     T->ntiles = ntiles;
-    T->max_rows = T->max_slots = T->max_pos = 0;
+    T->max_rows = T->max_slots = T->max_pos = T->max_imps = 0;
     T->ptr.assign(1, 0);
     T->row.clear();
     T->rows_ptr.assign(1, 0);
@@ -160,6 +160,7 @@ void tiles_one(const HostAnalysis &H, int dir, int32_t cap, int32_t short_row, T
         T->max_rows = std::max<int32_t>(T->max_rows, nslot);
         T->max_slots = std::max<int32_t>(T->max_slots, nslot + (int32_t)(T->imp.size() - ibase));
         T->max_pos = std::max<int32_t>(T->max_pos, (int32_t)(T->row.size() - base));
+        T->max_imps = std::max<int32_t>(T->max_imps, (int32_t)(T->imp.size() - ibase));
         a = b;
     }
 }
@@ -171,6 +172,75 @@ void build_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, TileSet 
     sci->assign(H.lu_ci.size(), -1);
     tiles_one(H, 0, cap, short_row, fwd, sci);
     tiles_one(H, 1, cap, short_row, bwd, sci);
+}
+
+void build_factor_tiles(const HostAnalysis &H, const TileSet &T, int32_t lanes, FactorTiles *F) {
+    const std::vector<int32_t> &rp = H.lu_rp, &ci = H.lu_ci, &dg = H.diag;
+    F->lanes = lanes;
+    F->max_vals = F->max_lents = 0;
+    F->meta.clear();
+    F->off.clear();
+    F->lptr.assign(1, 0);
+    F->dloc.clear();
+    F->dflag.clear();
+    F->match.clear();
+    F->imp.clear();
+    std::vector<int32_t> slot_of(H.n, -1), imp_of(H.n, -1), iloc(H.n, -1);
+    for (int32_t t = 0; t < T.ntiles; ++t) {
+        const int32_t r0 = T.rows_ptr[t], r1 = T.rows_ptr[t + 1];
+        const int32_t nrows = r1 - r0;
+        // value area: rows in slot order, then imports' U parts
+        int32_t va = 0, la = 0;
+        for (int32_t q = r0; q < r1; ++q) {
+            const int32_t r = T.rows[q];
+            slot_of[r] = q - r0;
+            F->meta.insert(F->meta.end(), {r, rp[r], rp[r + 1], dg[r]});
+            F->off.insert(F->off.end(), {va, la});
+            va += rp[r + 1] - rp[r];
+            la += dg[r] - rp[r];
+        }
+        for (int32_t i = T.imp_ptr[t]; i < T.imp_ptr[t + 1]; ++i) {
+            const int32_t c = T.imp[i];
+            imp_of[c] = i - T.imp_ptr[t];
+            iloc[c] = va;
+            F->imp.insert(F->imp.end(), {dg[c], rp[c + 1] - dg[c], va, 0});
+            va += rp[c + 1] - dg[c];
+        }
+        F->max_vals = std::max(F->max_vals, va);
+        F->max_lents = std::max(F->max_lents, la);
+        // L entries
+        for (int32_t q = r0; q < r1; ++q) {
+            const int32_t r = T.rows[q];
+            for (int32_t p = rp[r]; p < dg[r]; ++p) {
+                const int32_t c = ci[p];
+                if (slot_of[c] >= 0) {
+                    F->dloc.push_back(F->off[2 * (r0 + slot_of[c])] + (dg[c] - rp[c]));
+                    F->dflag.push_back(slot_of[c]);
+                } else {
+                    F->dloc.push_back(iloc[c]);
+                    F->dflag.push_back(nrows + imp_of[c]);
+                }
+                // U(c) columns, diagonal first; both rows are sorted: merge
+                for (int32_t l = 0; l < lanes; ++l) {
+                    int8_t m = -1;
+                    const int32_t pe = rp[r] + l;
+                    if (pe < rp[r + 1]) {
+                        const int32_t col = ci[pe];
+                        const int32_t *b = ci.data() + dg[c] + 1, *e = ci.data() + rp[c + 1];
+                        const int32_t *f = std::lower_bound(b, e, col);
+                        if (f != e && *f == col) m = (int8_t)(f - (ci.data() + dg[c]));
+                    }
+                    F->match.push_back(m);
+                }
+            }
+        }
+        F->lptr.push_back((int32_t)F->dloc.size());
+        for (int32_t q = r0; q < r1; ++q) slot_of[T.rows[q]] = -1;
+        for (int32_t i = T.imp_ptr[t]; i < T.imp_ptr[t + 1]; ++i) {
+            imp_of[T.imp[i]] = -1;
+            iloc[T.imp[i]] = -1;
+        }
+    }
 }
 
 }  // namespace jv

@@ -17,6 +17,9 @@ SCHEDS = [("level", "level"), ("syncfree", "syncfree")]
 # solve schedules: the factor schedule is irrelevant to the apply; the tiled solve
 # is built with small tiles so that test matrices span several tiles (ragged last)
 SOLVE_SCHEDS = SCHEDS + [("syncfree", "tiled")]
+# factor schedules: the tiled factor covers plain ILU (k = k_max, tau = 0, rows of at
+# most 16 entries) and falls back to the sync-free factor otherwise
+FACTOR_SCHEDS = SCHEDS + [("tiled", "tiled")]
 
 
 def dev(x):
@@ -49,7 +52,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("sched", SCHEDS, ids=lambda s: s[0])
+@pytest.mark.parametrize("sched", FACTOR_SCHEDS, ids=lambda s: s[0])
 @pytest.mark.parametrize("name,mk,k,tau", CASES, ids=[c[0] for c in CASES])
 def test_factor_bit_exact(jv, name, mk, k, tau, sched):
     A = mk()
@@ -74,7 +77,7 @@ def test_factor_bit_exact(jv, name, mk, k, tau, sched):
         assert info["n_dropped"] == int((f.stat == 1).sum())
 
 
-@pytest.mark.parametrize("sched", SCHEDS, ids=lambda s: s[0])
+@pytest.mark.parametrize("sched", FACTOR_SCHEDS, ids=lambda s: s[0])
 def test_factor_k_below_kmax(jv, sched):
     A = synth.convdiff3d(10)
     ilu = make(jv, A, 2, True, sched)
@@ -87,7 +90,7 @@ def test_factor_k_below_kmax(jv, sched):
         assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
 
 
-@pytest.mark.parametrize("sched", SCHEDS, ids=lambda s: s[0])
+@pytest.mark.parametrize("sched", FACTOR_SCHEDS, ids=lambda s: s[0])
 @pytest.mark.parametrize("lanes", [0, 16, 64])
 def test_factor_lane_counts_same_bits(jv, sched, lanes):
     A = synth.random_banded(2000, rng=np.random.default_rng(8))
@@ -100,7 +103,7 @@ def test_factor_lane_counts_same_bits(jv, sched, lanes):
     assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
 
 
-@pytest.mark.parametrize("sched", SCHEDS, ids=lambda s: s[0])
+@pytest.mark.parametrize("sched", FACTOR_SCHEDS, ids=lambda s: s[0])
 def test_factor_errors(jv, sched):
     # zero pivot in the first row, zero pivot later, non-finite value
     A = synth.csr_from_coo(3, [0, 0, 1, 1, 2, 2], [0, 1, 0, 1, 1, 2], [0.0, 1, 1, 2, 1, 3])
@@ -482,3 +485,26 @@ def test_apply_tiled_retune_and_lds_limit(jv):
     with pytest.raises(jv.IluError) as e:
         ilu.apply(dev(np.ones(big.n)))
     assert e.value.code == 10   # ILU_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("tile_rows", [16, 100, 512])
+@pytest.mark.parametrize("name,mk,k,sym", [
+    ("laplace3d_20", lambda: synth.laplace3d(20), 0, True),
+    ("convdiff3d_12_ilu1", lambda: synth.convdiff3d(12), 1, True),
+    ("laplace2d_40_lower_a", lambda: synth.laplace2d(40), 0, False),
+    ("tridiag_777", lambda: synth.tridiag(777), 0, True),
+    ("random_sparse_300", lambda: synth.random_sparse(300, 0.01, np.random.default_rng(23)), 0, False),
+], ids=lambda v: v if isinstance(v, (str, int)) else "")
+def test_factor_tiled_bit_exact(jv, name, mk, k, sym, tile_rows):
+    # the tiled factor on tiles from 16 rows (most dependencies imported) to whole
+    # matrices; bit for bit the serial factor, twice in a row (re-armed buffers)
+    A = mk()
+    ilu = make(jv, A, k, sym, ("tiled", "tiled"), tile_rows=tile_rows)
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k, sym=sym)
+    f = O.factor(an, A.val, k=k)
+    if np.diff(an.lu_rp).max() <= 16:
+        assert ilu.get_tuning("factor_tiled") == 1
+    for _ in range(2):
+        ilu.factor(dev(A.val), k=k)
+        lu, _ = ilu.factor_values()
+        assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64)), f"max diff {np.abs(lu - f.val).max()}"
