@@ -91,7 +91,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--scale", type=float, default=1.0, help="grid scale (1.0 = 128^3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sched", default="syncfree", choices=["syncfree", "level"],
+    ap.add_argument("--sched", default="tiled", choices=["tiled", "syncfree", "level"],
                     help="launch scheme of the factor")
     ap.add_argument("--solve-sched", default="tiled", choices=["tiled", "syncfree", "level"],
                     help="launch scheme of the triangular solves")
