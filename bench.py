@@ -36,10 +36,11 @@ HBM_PEAK_GBS = 8000.0
 # scaled by what the same counters read for the calibration copy kernels.  Valid
 # only for the kernel source it was taken with: a different hash reports null.
 PMC_TRAFFIC = dict(
-    kernels_sha256="6e051b5056454a543d0e5d9d8fd32e710ee5297d5fb8b5dd9a482f54d79aecf9",
-    fetch_scale=1.9987, write_scale=0.9941,
-    forward=dict(f64=(187438, 66160), f32=(155403, 51191)),
-    backward=dict(f64=(189269, 93862), f32=(149057, 78535)),
+    kernels_sha256="009d02652b0d6ca1c0f04fccb71571f9a4275d5c010e25759983feb3192e2532",
+    fetch_scale=1.9986, write_scale=0.9941,
+    forward=dict(f64=(187231, 66199), f32=(155425, 51145)),
+    backward=dict(f64=(189242, 93897), f32=(149264, 78569)),
+    factor=(279327, 146456),
 )
 
 
@@ -214,11 +215,14 @@ def main():
         per_launch = B64[dom]
     achieved = per_launch / (dom_ms * 1e-3) / 1e9
     traffic = None
-    if dom in ("forward", "backward") and kernels_sha256() == PMC_TRAFFIC["kernels_sha256"]:
+    if dom in ("forward", "backward", "factor") and kernels_sha256() == PMC_TRAFFIC["kernels_sha256"]:
         def scaled(fw):
             return 1024.0 * (fw[0] * PMC_TRAFFIC["fetch_scale"] + fw[1] * PMC_TRAFFIC["write_scale"])
         t = PMC_TRAFFIC[dom]
-        traffic = int((c64 * scaled(t["f64"]) + c32 * scaled(t["f32"])) / max(c64 + c32, 1))
+        if dom == "factor":
+            traffic = int(scaled(t))
+        else:
+            traffic = int((c64 * scaled(t["f64"]) + c32 * scaled(t["f32"])) / max(c64 + c32, 1))
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=dom,
                     launches=dom_cnt, avg_us=round(dom_ms * 1e3, 2),
