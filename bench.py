@@ -168,6 +168,28 @@ def main():
         torch.cuda.synchronize()
         stage[name] = ilu.profile_read()
 
+    # per-call distributions, warm and cold (the 256 MB MALL flushed by a 1 GiB
+    # write before each call): p10 / median / p90 of 20 calls per stage
+    flush = torch.zeros(1 << 28, dtype=torch.float32, device="cuda")
+    dist = {}
+    for name, fn, keys in (("factor", lambda: ilu.factor(a_d, casts=()), ("factor",)),
+                           ("apply_f64", lambda: ilu.apply(bp_d, x=x_d, permuted=True), ("forward", "backward")),
+                           ("spmv", lambda: ilu.spmv(bp_d, y=y_d, permuted=True), ("spmv",))):
+        for mode in ("warm", "cold"):
+            vals = []
+            for _ in range(20):
+                if mode == "cold":
+                    flush.add_(1.0)
+                torch.cuda.synchronize()
+                ilu.profile_read()
+                fn()
+                torch.cuda.synchronize()
+                p = ilu.profile_read()
+                vals.append(1e3 * sum(p[k][0] for k in keys))
+            q = np.percentile(vals, [10, 50, 90])
+            dist.setdefault(name, {})[mode] = [round(float(v), 2) for v in q]
+    del flush
+
     # timed steps (events stay on: they are the live per-kernel durations)
     log(f"timing {args.steps} steps ...")
     ilu.profile_read()
@@ -252,6 +274,7 @@ def main():
                         apply_f32=round(B32["apply"] / t_apply32 / 1e6, 1),
                         spmv=round(B64["spmv"] / t_spmv / 1e6, 1)),
         rows_per_s=dict(factor=round(n / (t_factor * 1e-3), 1)),
+        calls_us_p10_p50_p90=dist,
         pcg=dict(f64=dict(seconds=round(float(np.median([p[0] for p in pcg64])), 5),
                           iters=pcg64[-1][1]["iters"], true_relres=pcg64[-1][1]["true_relres"]),
                  f32_factor=dict(seconds=round(float(np.median([p[0] for p in pcg32])), 5),

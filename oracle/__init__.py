@@ -63,8 +63,8 @@ def lib():
         L.orc_row_tau.restype = None
         L.orc_row_tau.argtypes = [C.c_int, _i32p, _f64p, _i32p, C.c_double, _f64p]
         L.orc_factor.restype = C.c_int
-        L.orc_factor.argtypes = [C.c_int, _i32p, _i32p, _i32p, _i32p, _f64p, C.c_int, _f64p, _i8p,
-                                 C.POINTER(C.c_int)]
+        L.orc_factor.argtypes = [C.c_int, _i32p, _i32p, _i32p, _i32p, _f64p, C.c_int, _f64p, C.c_int,
+                                 _i8p, C.POINTER(C.c_int)]
         L.orc_cast_f32.restype = None
         L.orc_cast_f32.argtypes = [C.c_long, _f64p, _f32p]
         L.orc_cast_bf16.restype = None
@@ -274,15 +274,16 @@ def row_tau(an: Analysis, a_val_input, tau):
     return out
 
 
-def factor(an: Analysis, a_val_input, k=None, tau=0.0) -> Factor:
-    """Up-looking ILU(k, tau) on P S P^T (Sec. III, Fig. 1)."""
+def factor(an: Analysis, a_val_input, k=None, tau=0.0, milu=False) -> Factor:
+    """Up-looking ILU(k, tau) on P S P^T (Sec. III, Fig. 1); milu: modified ILU
+    (what a row loses goes to its diagonal; Sec. I, Sec. III)."""
     k = an.k_max if k is None else int(k)
     val = gather(an.lu_src, a_val_input)
     rt = row_tau(an, a_val_input, tau)
     stat = np.empty(an.nnz_lu, np.int8)
     bad = C.c_int(-1)
-    st = lib().orc_factor(an.n, an.lu_rp, an.lu_ci, an.lu_lev, an.diag_pos, val, k, rt, stat,
-                          C.byref(bad))
+    st = lib().orc_factor(an.n, an.lu_rp, an.lu_ci, an.lu_lev, an.diag_pos, val, k, rt, 1 if milu else 0,
+                          stat, C.byref(bad))
     return Factor(val=val, stat=stat, status=st, bad_row=bad.value)
 
 

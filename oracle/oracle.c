@@ -314,12 +314,19 @@ void orc_row_tau(int n, const int *arp, const double *av, const int *perm, doubl
 /* Then U entries of row r right of the diagonal with |a_rj| < tau_r are    */
 /* dropped.  Entries whose fill level exceeds k are absent (stat 2, 0.0);    */
 /* they neither update nor receive updates.  The diagonal is never dropped.  */
+/* Modified ILU (milu != 0; Sec. I and Sec. III name it as an option without */
+/* defining it; the textbook rule is taken): whatever row r loses is added to */
+/* its diagonal at the moment it is lost, so the row sums of L*U equal those */
+/* of A.  An update l*u_cj whose target (r, j) is outside the kept pattern   */
+/* (not stored, or absent) is subtracted from a_rr; a dropped multiplier     */
+/* gives back its value before the division (a_rr += a_rc); a dropped U      */
+/* entry gives back its value (a_rr += a_rj), in ascending column order.     */
 /* No pivoting (Sec. III): the first row with a_rr == 0 gives ZERO_PIVOT,    */
 /* the first row with any non-finite value gives NONFINITE; the oracle stops */
 /* there and reports the row in *bad_row.                                    */
 /* ------------------------------------------------------------------------ */
 int orc_factor(int n, const int *rp, const int *ci, const int *flev, const int *diag_pos,
-               double *val, int k, const double *row_tau, signed char *stat, int *bad_row) {
+               double *val, int k, const double *row_tau, int milu, signed char *stat, int *bad_row) {
     int *pos = (int *)malloc(sizeof(int) * (size_t)n);
     if (!pos) return ORC_ERR_NOMEM;
     for (int j = 0; j < n; ++j) pos[j] = -1;
@@ -332,25 +339,35 @@ int orc_factor(int n, const int *rp, const int *ci, const int *flev, const int *
     for (int r = 0; r < n; ++r) {
         double tr = row_tau ? row_tau[r] : 0.0;
         for (int p = rp[r]; p < rp[r + 1]; ++p) pos[ci[p]] = p;
+        int dr = diag_pos[r];
         for (int p = rp[r]; p < rp[r + 1] && ci[p] < r; ++p) {
             if (stat[p] != 0) continue;
             int c = ci[p];
+            double before = val[p];
             val[p] = val[p] / val[diag_pos[c]];
             if (fabs(val[p]) < tr) {
                 val[p] = 0.0;
                 stat[p] = 1;
+                if (milu) val[dr] = val[dr] + before;
                 continue;
             }
             for (int q = diag_pos[c] + 1; q < rp[c + 1]; ++q) {
                 if (stat[q] != 0) continue;
                 int t = pos[ci[q]];
-                if (t < 0 || stat[t] != 0) continue;
+                if (t < 0 || stat[t] != 0) {
+                    if (milu) {
+                        double lost = val[p] * val[q];
+                        val[dr] = val[dr] - lost;
+                    }
+                    continue;
+                }
                 double prod = val[p] * val[q];
                 val[t] = val[t] - prod;
             }
         }
-        for (int p = diag_pos[r] + 1; p < rp[r + 1]; ++p) {
+        for (int p = dr + 1; p < rp[r + 1]; ++p) {
             if (stat[p] == 0 && fabs(val[p]) < tr) {
+                if (milu) val[dr] = val[dr] + val[p];
                 val[p] = 0.0;
                 stat[p] = 1;
             }

@@ -225,6 +225,80 @@ def test_k_restriction_matches_pattern_subset():
 
 
 # --------------------------------------------------------------------------------------
+# Modified ILU (Sec. I and Sec. III name it; the rule is the textbook one: what a row
+# loses goes to its diagonal)
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(10))
+def test_milu_row_sums_and_offdiagonal_identity(seed):
+    # The modified factor is characterised by two facts: every kept off-diagonal
+    # entry of LU equals A's (as for plain ILU), and every row sum of LU equals the
+    # row sum of A (what is lost is given back on the diagonal).  With tau drops the
+    # row sums still hold.  Row by row the two fix L, the off-diagonal U and the
+    # diagonal uniquely.
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(8, 60))
+    k_max = int(seed % 3)
+    k = k_max if seed % 5 else max(k_max - 1, 0)
+    tau = 0.0 if seed < 6 else float(rng.choice([1e-3, 1e-2]))
+    A = synth.random_sparse(n, float(rng.uniform(0.05, 0.2)), rng, symmetric_pattern=bool(seed % 2))
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k_max, sym=bool(seed % 3 == 0))
+    f = O.factor(an, A.val, k=k, tau=tau, milu=True)
+    assert f.status == O.OK
+    Lm, Um = O.dense_factors(an, f.val)
+    D = dense(A)[np.ix_(an.perm, an.perm)]
+    LU = Lm @ Um
+    scale = np.abs(D).max() * max(1.0, np.abs(LU).max() / np.abs(D).max())
+    assert np.abs(LU.sum(axis=1) - D.sum(axis=1)).max() <= 1e-12 * scale * n
+    kept_off = np.zeros((n, n), bool)
+    for r in range(n):
+        for p in range(an.lu_rp[r], an.lu_rp[r + 1]):
+            if f.stat[p] == 0 and an.lu_ci[p] != r:
+                kept_off[r, an.lu_ci[p]] = True
+    assert np.abs((LU - D)[kept_off]).max() <= 1e-12 * scale
+    # something was lost, so the diagonal differs from plain ILU's
+    g = O.factor(an, A.val, k=k, tau=tau)
+    dg = an.diag_pos
+    assert not np.array_equal(f.val[dg], g.val[dg]) or np.array_equal(f.val, g.val)
+
+
+def test_milu_5point_diagonal_recurrence():
+    # 5-point Laplacian (4 on the diagonal, -1 to each neighbour), natural ordering:
+    # eliminating the south neighbour (i, j-1) loses its east entry (i+1, j-1) and
+    # eliminating the west neighbour (i-1, j) loses its north entry (i-1, j+1), each
+    # worth (-1/d)(-1), so d_ij = 4 - (1 + [i+1 < nx]) / d_{i,j-1} - (1 + [j+1 < ny]) / d_{i-1,j}.
+    # Plain ILU(0) has d_ij = 4 - 1/d_{i,j-1} - 1/d_{i-1,j}.
+    nx, ny = 9, 7
+    A = synth.laplace2d(nx, ny)
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    for milu in (True, False):
+        f = O.factor(an, A.val, milu=milu)
+        d = np.zeros((nx, ny))
+        for j in range(ny):
+            for i in range(nx):
+                v = 4.0
+                if j > 0:
+                    v -= (1 + (milu and i + 1 < nx)) / d[i, j - 1]
+                if i > 0:
+                    v -= (1 + (milu and j + 1 < ny)) / d[i - 1, j]
+                d[i, j] = v
+        got = f.val[an.diag_pos][an.iperm]       # original row order
+        np.testing.assert_allclose(got, d.T.ravel(), rtol=1e-14)
+
+
+def test_milu_equals_ilu_when_nothing_is_lost():
+    # Tridiagonal ILU(0), a dense pattern and a lower-triangular matrix lose no
+    # update, so the modified factor is the plain one bit for bit.
+    rng = np.random.default_rng(31)
+    mats = [synth.tridiag(40), synth.integer_unit_lower(30, 0.2, rng), synth.dense_pattern(12, rng)]
+    for A in mats:
+        an = O.analyze(A.n, A.row_ptr, A.col_idx)
+        f = O.factor(an, A.val, milu=True)
+        g = O.factor(an, A.val)
+        assert f.status == O.OK and np.array_equal(f.val, g.val)
+
+
+# --------------------------------------------------------------------------------------
 # Errors (no pivoting, Sec. III)
 # --------------------------------------------------------------------------------------
 
