@@ -180,19 +180,32 @@ ilu_status ilu_copy_tiles(ilu_handle h, int32_t dir, int32_t *tile_ptr, int32_t 
 /* Numeric factor (Sec. III, Fig. 1).                                            */
 /* ---------------------------------------------------------------------------- */
 
+/* flags of ilu_factor */
+enum {
+    ILU_CAST_F32 = 1,             /* also store an FP32 copy (round to nearest even) */
+    ILU_CAST_BF16 = 2,            /* also store a BF16 copy (FP64 -> FP32 -> BF16, each RNE) */
+    ILU_FACTOR_MODIFIED = 0x100   /* modified ILU (named as an option in Sec. I and Sec. III) */
+};
+
 /* ILU(k, tau) with 0 <= k <= k_max on the analysed pattern.  a_val: device, the
  * values of A in the input entry order (length nnz_a).  Entries with fill level
  * above k are absent; with tau > 0, a multiplier l_rc with |l_rc| < tau_r after
  * its division, and a U entry with |u_rj| < tau_r at the end of its row, are
  * dropped (set to 0 and marked), where tau_r = tau * ||A(row,:)||_2; the
- * diagonal is never dropped.  The FP64 factor is kept; `casts` (bit 1 = FP32,
- * bit 2 = BF16) also stores rounded copies for ILU_PREC_F32/BF16 applies.
+ * diagonal is never dropped.  The FP64 factor is kept; flags ILU_CAST_F32 /
+ * ILU_CAST_BF16 also store rounded copies for ILU_PREC_F32/BF16 applies.
+ * ILU_FACTOR_MODIFIED: whatever row r loses is added to u_rr when it is lost --
+ * an update l_rc * u_cj whose target (r, j) is not a kept entry is subtracted
+ * from u_rr, a dropped multiplier adds back its value before the division, a
+ * dropped U entry adds back its value (ascending column) -- so the row sums of
+ * L*U equal those of A.  The tiled factor covers the modified form of plain
+ * ILU(k) too; with tau > 0 or k < k_max it runs sync-free (or level launches).
  * Also loads the values of the permuted copy of A used by ilu_spmv.
  * Synchronises `stream` to read the status word.  info may be NULL.
- * Errors: ILU_ERR_STATE, ILU_ERR_ARG (k > k_max, tau < 0 or NaN),
- * ILU_ERR_ZERO_PIVOT, ILU_ERR_NONFINITE (first failing row in level order),
- * ILU_ERR_TIMEOUT, ILU_ERR_HIP. */
-ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, double tau, int32_t casts,
+ * Errors: ILU_ERR_STATE, ILU_ERR_ARG (k > k_max, tau < 0 or NaN, unknown flag
+ * bits), ILU_ERR_ZERO_PIVOT, ILU_ERR_NONFINITE (first failing row in level
+ * order), ILU_ERR_TIMEOUT, ILU_ERR_HIP. */
+ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, double tau, int32_t flags,
                       ilu_factor_info *info, hipStream_t stream);
 
 /* Device pointer to the factor values in factor order (L strictly lower with unit
@@ -295,7 +308,9 @@ ilu_status ilu_get_schedule(ilu_handle h, int32_t *factor_sched, int32_t *solve_
 /* Named tuning knobs.  Settable: "poll_sleep" (0..64, pause steps of about 64
  * clocks between polls of a value that is still pending), "tile_rows" (16..65536,
  * rebuilds the tiles of the tiled solves on the host and uploads them;
- * synchronous).  Readable as well:
+ * synchronous), "factor_staged" (1, the default: the sync-free and level factors
+ * gather a row's dependency rows into LDS when they fit; 0: each dependency row
+ * is read from global memory when its turn comes; same results).  Readable as well:
  * "nstreams" (task streams = XCDs found), "factor_tcap" (LDS entries staged per
  * factor row), "factor_tiled" (1 if the tiled factor can run on this handle:
  * rows of at most 16 entries and tiles that fit LDS).  Unknown keys give

@@ -19,6 +19,7 @@ PATTERN_LOWER_SYM, PATTERN_LOWER_A = 0, 1
 PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
 PERMUTED_SPACE = 1
 SCHED_AUTO, SCHED_LEVEL, SCHED_SYNCFREE, SCHED_TILED = 0, 1, 2, 3
+CAST_F32, CAST_BF16, FACTOR_MODIFIED = 1, 2, 0x100
 STAGE_FACTOR, STAGE_FORWARD, STAGE_BACKWARD, STAGE_SPMV, STAGE_COUNT = 0, 1, 2, 3, 4
 STAGES = ["factor", "forward", "backward", "spmv"]
 

@@ -100,6 +100,9 @@ struct FactorTiles {
     std::vector<int32_t> lptr;         // [ntiles + 1] offsets of each tile's L entries
     std::vector<int32_t> dloc, dflag;  // per L entry
     std::vector<int8_t> match;         // lanes per L entry
+    std::vector<uint32_t> cmask;       // per L entry (r, c): bit j set for each position j >= 1 of U(c)
+                                       // whose update goes to u_rr in modified ILU (column r, or a
+                                       // column that row r does not hold)
     std::vector<int32_t> imp;          // 4 per import: diagonal entry, U length, value-area offset, 0
 };
 

@@ -304,7 +304,7 @@ ilu_status ilu_handle_s::make_tiles(int32_t rows, bool shrink) {
 }
 
 // The tiled factor needs the forward tiles, rows of at most kFactorMaxLanes
-// entries and a tile image that fits LDS.
+// entries and a tile image that fits LDS (the modified form's masks included).
 ilu_status ilu_handle_s::make_factor_tiles() {
     ftiles_ok = false;
     if (H.max_row_lu > kFactorMaxLanes || tiles[0].ntiles == 0) return ILU_OK;
@@ -320,7 +320,7 @@ ilu_status ilu_handle_s::make_factor_tiles() {
     T.max_lents = ftiles.max_lents;
     T.max_pos = tiles[0].max_pos;
     T.max_imps = tiles[0].max_imps;
-    if (factor_tile_lds_bytes(T, lanes) > (size_t)kFactorTileLdsMax) return ILU_OK;
+    if (factor_tile_lds_bytes(T, lanes, true) > (size_t)kFactorTileLdsMax) return ILU_OK;
     if (host_only) {
         ftiles_ok = true;
         return ILU_OK;
@@ -342,7 +342,7 @@ ilu_status ilu_handle_s::make_factor_tiles() {
     if ((e = put(dft.meta, ftiles.meta)) != hipSuccess || (e = put(dft.off, ftiles.off)) != hipSuccess ||
         (e = put(dft.lptr, ftiles.lptr)) != hipSuccess || (e = put(dft.dloc, ftiles.dloc)) != hipSuccess ||
         (e = put(dft.dflag, ftiles.dflag)) != hipSuccess || (e = put(dft.match, ftiles.match)) != hipSuccess ||
-        (e = put(dft.imp, ftiles.imp)) != hipSuccess)
+        (e = put(dft.imp, ftiles.imp)) != hipSuccess || (e = put(dft.cmask, ftiles.cmask)) != hipSuccess)
         return hip_fail(e, "factor tiles: upload");
     ftiles_ok = true;
     return ILU_OK;
@@ -594,7 +594,9 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
     if (!a_val && h->H.nnz_in > 0) return fail(ILU_ERR_ARG, "ilu_factor: NULL values");
     if (k < 0 || k > h->H.k_max) return fail(ILU_ERR_ARG, "ilu_factor: k must be in [0, k_max]");
     if (!(tau >= 0.0)) return fail(ILU_ERR_ARG, "ilu_factor: tau must be >= 0");
-    if (casts & ~3) return fail(ILU_ERR_ARG, "ilu_factor: unknown cast bits");
+    if (casts & ~(ILU_CAST_F32 | ILU_CAST_BF16 | ILU_FACTOR_MODIFIED))
+        return fail(ILU_ERR_ARG, "ilu_factor: unknown flag bits");
+    const bool milu = (casts & ILU_FACTOR_MODIFIED) != 0;
     const HostAnalysis &H = h->H;
     if (H.max_row_lu > 64)
         return fail(ILU_ERR_UNSUPPORTED, "ilu_factor: factor rows longer than 64 entries are not supported");
@@ -620,11 +622,12 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
     A.k = k;
     A.use_flev = k < H.k_max;
     A.use_tau = use_tau;
+    A.milu = milu;
     A.a = a_val;
     A.lu = h->d_lu;
     A.row_tau = h->d_row_tau;
     A.info = h->d_info;
-    A.tcap = factor_lds_bytes(lanes, h->factor_tcap) ? h->factor_tcap : 0;
+    A.tcap = (h->factor_staged && factor_lds_bytes(lanes, h->factor_tcap)) ? h->factor_tcap : 0;
     A.max_lower = H.max_lower_lu;
     // the tiled factor covers plain ILU (every pattern entry kept, no dropping);
     // anything else runs the sync-free factor
@@ -642,6 +645,7 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
         T.dloc = h->dft.dloc;
         T.dflag = h->dft.dflag;
         T.match = h->dft.match;
+        T.cmask = h->dft.cmask;
         T.imp_ptr = D.imp_ptr;
         T.imp = reinterpret_cast<const int4 *>(h->dft.imp);
         T.ntiles = T0.ntiles;
@@ -1121,6 +1125,11 @@ extern "C" ilu_status ilu_set_tuning(ilu_handle h, const char *key, int64_t valu
         if (value < 16 || value > 65536) return fail(ILU_ERR_ARG, "ilu_set_tuning: tile_rows must be in [16, 65536]");
         return h->make_tiles((int32_t)value, false);
     }
+    if (k == "factor_staged") {
+        if (value != 0 && value != 1) return fail(ILU_ERR_ARG, "ilu_set_tuning: factor_staged must be 0 or 1");
+        h->factor_staged = value != 0;
+        return ILU_OK;
+    }
     return fail(ILU_ERR_ARG, "ilu_set_tuning: unknown key " + k);
 }
 
@@ -1132,6 +1141,7 @@ extern "C" ilu_status ilu_get_tuning(ilu_handle h, const char *key, int64_t *val
     if (k == "factor_tcap") { *value = h->factor_tcap; return ILU_OK; }
     if (k == "tile_rows") { *value = h->tile_rows; return ILU_OK; }
     if (k == "factor_tiled") { *value = h->ftiles_ok ? 1 : 0; return ILU_OK; }
+    if (k == "factor_staged") { *value = h->factor_staged ? 1 : 0; return ILU_OK; }
     return fail(ILU_ERR_ARG, "ilu_get_tuning: unknown key " + k);
 }
 

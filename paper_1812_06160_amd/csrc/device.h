@@ -56,6 +56,7 @@ struct FactorArgs {
     int32_t k;
     int32_t use_flev;     // k < k_max: entries with fill level > k are absent
     int32_t use_tau;
+    int32_t milu;         // modified ILU: what a row loses is added to its diagonal
     const double *a;      // input values (input entry order)
     double *lu;           // factor values (factor order)
     const double *row_tau;
@@ -144,11 +145,12 @@ struct FactorTileArgs {
     const int32_t *lptr;      // [ntiles + 1] offsets into the L-entry arrays
     const int32_t *dloc, *dflag;
     const int8_t *match;      // lanes per L entry
+    const uint32_t *cmask;    // per L entry: U(c) positions whose update goes to the diagonal (modified ILU)
     const int32_t *imp_ptr;   // [ntiles + 1] offsets into imp
     const int4 *imp;          // per import: diagonal entry, U length, value-area offset
     int32_t ntiles, max_rows, max_vals, max_lents, max_pos, max_imps;
     // LDS carve-up (bytes), set by the launcher
-    int32_t off_flags, off_meta, off_off, off_dloc, off_dflag, off_match, off_imp, off_pslot, lds_bytes;
+    int32_t off_flags, off_meta, off_off, off_dloc, off_dflag, off_match, off_cmask, off_imp, off_pslot, lds_bytes;
     int32_t *counter;         // claim counter (zero at launch)
 };
 
@@ -184,7 +186,7 @@ hipError_t launch_spmv(const SpmvArgs &A, int lanes, hipStream_t s);
 // tiled factor with `lanes` (8 or 16) lanes per row; hipErrorInvalidValue when it
 // does not fit LDS
 hipError_t launch_factor_tiled(const FactorArgs &A, const FactorTileArgs &T, int lanes, hipStream_t s);
-size_t factor_tile_lds_bytes(const FactorTileArgs &T, int lanes);
+size_t factor_tile_lds_bytes(const FactorTileArgs &T, int lanes, bool milu);
 // tiled solve; returns hipErrorInvalidValue when no right-hand-side blocking fits LDS
 hipError_t launch_solve_tiled(const SolveArgs &A, const TileArgs &T, bool forward, int prec, int vec,
                               hipStream_t s);

@@ -98,11 +98,13 @@ struct ilu_handle_s {
         int32_t *meta = nullptr, *off = nullptr, *lptr = nullptr, *dloc = nullptr, *dflag = nullptr,
                 *imp = nullptr;
         int8_t *match = nullptr;
+        uint32_t *cmask = nullptr;
     } dft;
     jv::Profiler prof;
     int32_t *d_counters = nullptr;     // kPasses sets of claim counters
     bool counters_dirty[jv::kPasses] = {false, false, false, false, false, false, false, false};
     int32_t factor_tcap = 0;           // LDS staging entries per factor row (0: unstaged)
+    bool factor_staged = true;         // stage dependency rows in LDS when they fit
     int32_t nstreams = 1;              // task streams (one per XCD)
     int32_t poll_sleep = 1;            // s_sleep(1) steps between polls (tunable)
     int8_t *d_xcc_stream = nullptr;    // XCC id -> stream

@@ -349,6 +349,13 @@ template <int G, bool SF>
 __device__ __forceinline__ void factor_finish(const FactorArgs &A, int r, int t, int gi, int p, bool act, int col,
                                               int absent, int dropped, double v, double tr, int diag_lane) {
     if (A.use_tau && act && !absent && col > r && fabs(v) < tr) dropped = 1;
+    if (A.milu && A.use_tau) {
+        // modified ILU: dropped U entries go back to the diagonal, ascending column
+        for (int j = diag_lane + 1; j < G; ++j) {
+            const double dv = __shfl(v, j, G);
+            if (__shfl(dropped, j, G) && t == diag_lane) v = v + dv;
+        }
+    }
     const double pv = __shfl(v, diag_lane, G);
     const bool nonfinite = act && !absent && !dropped && !isfinite(v);
     const uint64_t nfm = group_bits<G>(__ballot(nonfinite), gi);
@@ -369,7 +376,7 @@ __device__ __forceinline__ void factor_finish(const FactorArgs &A, int r, int t,
 template <int G, bool SF>
 __device__ __forceinline__ void factor_row(const FactorArgs &A, int r, int t, int gi) {
     const int rs = A.rp[r], re = A.rp[r + 1], d = A.diag[r];
-    const int nL = d - rs;
+    const int nL = d - rs, dl = d - rs;
     const int p = rs + t;
     const bool act = p < re;
     const int col = act ? A.ci[p] : INT_MAX;
@@ -398,17 +405,36 @@ __device__ __forceinline__ void factor_row(const FactorArgs &A, int r, int t, in
             else uv = A.lu[q];
         }
         const double piv = __shfl(uv, 0, G);
+        double before = 0.0;
         if (t == e) {
+            before = v;
             v = v / piv;
             if (A.use_tau && fabs(v) < tr) dropped = 1;
         }
-        if (__shfl(dropped, e, G)) continue;
+        if (__shfl(dropped, e, G)) {
+            if (A.milu) {
+                // modified ILU: a dropped multiplier gives back its value before the division
+                const double bv = __shfl(before, e, G);
+                if (t == dl) v = v + bv;
+            }
+            continue;
+        }
         const double l = __shfl(v, e, G);
         for (int j = 1; j < lenU; ++j) {
             const int uc = __shfl(ucol, j, G);
             const double uu = __shfl(uv, j, G);
             const int ua = __shfl(uabs, j, G);
-            if (!ua && (uint64_t)__double_as_longlong(uu) != kDropped64 && col == uc && !absent) {
+            const bool kept = !ua && (uint64_t)__double_as_longlong(uu) != kDropped64;
+            const bool mine = kept && col == uc && !absent;
+            // modified ILU: an update whose target is not a kept entry of row r is
+            // subtracted from the diagonal instead, in U(c)'s column order
+            const bool taken = A.milu && group_bits<G>(__ballot(mine && t != dl), gi) != 0;
+            if (A.milu && t == dl) {
+                if (kept && !taken) {
+                    const double lost = l * uu;
+                    v = v - lost;
+                }
+            } else if (mine) {
                 const double prod = l * uu;
                 v = v - prod;
             }
@@ -428,8 +454,9 @@ __device__ __forceinline__ void factor_row(const FactorArgs &A, int r, int t, in
 template <int G, int MAXL, bool SF>
 __device__ __forceinline__ void factor_row_staged(const FactorArgs &A, int r, int t, int gi, double *sv, int *sc,
                                                   int *soff, int *sdc) {
+    constexpr int kTaken = -2;   // column slot of a U(c) entry that a lane of the row took
     const int rs = A.rp[r], re = A.rp[r + 1], d = A.diag[r];
-    const int nL = d - rs;
+    const int nL = d - rs, dl = d - rs;
     const int p = rs + t;
     const bool act = p < re;
     const int col = act ? A.ci[p] : INT_MAX;
@@ -539,29 +566,54 @@ __device__ __forceinline__ void factor_row_staged(const FactorArgs &A, int r, in
                 if ((uint64_t)__double_as_longlong(u) != kDropped64) {
                     wv[e] = u;
                     mmask |= 1ull << e;
+                    // modified ILU: positions another lane takes are marked for the
+                    // diagonal lane, which gives back the rest (the search of this
+                    // region has ended for every lane of the group)
+                    if (A.milu && t != dl) sc[lo] = kTaken;
                 }
             }
         }
     }
-    wave_sync_lds();   // the slice is reused by the group's next row
+    wave_sync_lds();   // the slice is reused by the group's next row (or, in the
+                       // modified form, read by the diagonal lane in the chain)
     // ---- chain ----
 #pragma unroll
     for (int e = 0; e < MAXL; ++e) {
         if (e < nL) {                                   // uniform across the group
             if (__shfl(len, e, G) != 0) {               // kept dependency
+                double before = 0.0;
                 if (t == e) {
+                    before = v;
                     v = v / mypiv;
                     if (A.use_tau && fabs(v) < tr) dropped = 1;
                 }
                 const int de = __shfl(dropped, e, G);
                 const double l = __shfl(v, e, G);
-                if (!de && ((mmask >> e) & 1ull)) {
+                const double bv = A.milu ? __shfl(before, e, G) : 0.0;
+                if (A.milu && t == dl) {
+                    if (de) {
+                        v = v + bv;
+                    } else {
+                        // U(c_e) in column order: kept entries no other lane took
+                        const int oe = soff[e];
+                        const int le = (e + 1 < nL ? soff[e + 1] : total) - oe;
+                        for (int j = oe + 1; j < oe + le; ++j) {
+                            const int cj = sc[j];
+                            const double u = sv[j];
+                            if (cj >= 0 && (uint64_t)__double_as_longlong(u) != kDropped64) {
+                                const double lost = l * u;
+                                v = v - lost;
+                            }
+                        }
+                    }
+                } else if (!de && ((mmask >> e) & 1ull)) {
                     const double prod = l * wv[e];
                     v = v - prod;
                 }
             }
         }
     }
+    if (A.milu) wave_sync_lds();   // the diagonal lane's reads end before the next row's gather
     factor_finish<G, SF>(A, r, t, gi, p, act, col, absent, dropped, v, tr, d - rs);
 }
 
@@ -1262,6 +1314,7 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
     int32_t *dloc = reinterpret_cast<int32_t *>(fsmem + T.off_dloc);
     int32_t *dflag = reinterpret_cast<int32_t *>(fsmem + T.off_dflag);
     int8_t *match = reinterpret_cast<int8_t *>(fsmem + T.off_match);
+    uint32_t *cmask = reinterpret_cast<uint32_t *>(fsmem + T.off_cmask);
     int4 *imp = reinterpret_cast<int4 *>(fsmem + T.off_imp);
     int16_t *ps = reinterpret_cast<int16_t *>(fsmem + T.off_pslot);
     __shared__ int s_tile, s_abort;
@@ -1286,6 +1339,8 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
     lds_copy<kStageCopy>(dflag, T.dflag + lbase, nl);
     lds_copy<kStageCopy>(reinterpret_cast<int *>(match), reinterpret_cast<const int *>(T.match + (int64_t)lbase * G),
                          nl * G / 4);
+    if (A.milu)
+        lds_copy<kStageCopy>(reinterpret_cast<int *>(cmask), reinterpret_cast<const int *>(T.cmask + lbase), nl);
     lds_copy<kStageCopy>(reinterpret_cast<int *>(imp), reinterpret_cast<const int *>(T.imp + ibase), nimp * 4);
     for (int i = threadIdx.x; i < nrows + nimp; i += kTileBlock) flags[i] = 0;
     __syncthreads();
@@ -1342,11 +1397,23 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
             const double piv = ok ? vals[loc] : __longlong_as_double((long long)kQNaN64);
             if (t == e) v = v / piv;
             const double l = __shfl(v, e, G);
-            const int j = match[li * G + t];
-            if (j > 0) {
-                const double u = vals[loc + j];
-                const double prod = l * u;
-                v = v - prod;
+            if (A.milu && t == K) {
+                // modified ILU: the diagonal takes its own update and every update
+                // whose target row r does not hold, in U(c)'s column order
+                uint32_t mk = cmask[li];
+                while (mk) {
+                    const int jj = __builtin_ctz(mk);
+                    mk &= mk - 1;
+                    const double lost = l * vals[loc + jj];
+                    v = v - lost;
+                }
+            } else {
+                const int j = match[li * G + t];
+                if (j > 0) {
+                    const double u = vals[loc + j];
+                    const double prod = l * u;
+                    v = v - prod;
+                }
             }
         }
         // pivot and finiteness checks, as in the sync-free factor
@@ -1692,7 +1759,7 @@ static hipError_t tiled_dispatch(const SolveArgs &A, const TileArgs &T, bool fwd
 }
 
 // LDS carve-up of a tiled factor launch
-static size_t factor_tile_layout(const FactorTileArgs &T, int G, FactorTileArgs *out) {
+static size_t factor_tile_layout(const FactorTileArgs &T, int G, bool milu, FactorTileArgs *out) {
     size_t o = align8((size_t)T.max_vals * 8);
     const size_t fl = o;
     o = align8(o + (size_t)(T.max_rows + T.max_imps) * 4);
@@ -1706,6 +1773,8 @@ static size_t factor_tile_layout(const FactorTileArgs &T, int G, FactorTileArgs 
     o = align8(o + (size_t)T.max_lents * 4);
     const size_t ma = o;
     o = align8(o + (size_t)T.max_lents * G);
+    const size_t cm = o;
+    if (milu) o = align8(o + (size_t)T.max_lents * 4);
     const size_t im = o;
     o = align8(o + (size_t)T.max_imps * 16);
     const size_t psl = o;
@@ -1717,6 +1786,7 @@ static size_t factor_tile_layout(const FactorTileArgs &T, int G, FactorTileArgs 
         out->off_dloc = (int32_t)dl;
         out->off_dflag = (int32_t)df;
         out->off_match = (int32_t)ma;
+        out->off_cmask = (int32_t)cm;
         out->off_imp = (int32_t)im;
         out->off_pslot = (int32_t)psl;
         out->lds_bytes = (int32_t)o;
@@ -1724,12 +1794,14 @@ static size_t factor_tile_layout(const FactorTileArgs &T, int G, FactorTileArgs 
     return o;
 }
 
-size_t factor_tile_lds_bytes(const FactorTileArgs &T, int lanes) { return factor_tile_layout(T, lanes, nullptr); }
+size_t factor_tile_lds_bytes(const FactorTileArgs &T, int lanes, bool milu) {
+    return factor_tile_layout(T, lanes, milu, nullptr);
+}
 
 template <int G>
 static hipError_t factor_tiled_launch(const FactorArgs &A, const FactorTileArgs &T0, hipStream_t s) {
     FactorTileArgs T = T0;
-    const size_t lds = factor_tile_layout(T, G, &T);
+    const size_t lds = factor_tile_layout(T, G, A.milu != 0, &T);
     if (lds > (size_t)kFactorTileLdsMax) return hipErrorInvalidValue;
     if (T.ntiles <= 0) return hipSuccess;
     if (lds > 65536) {

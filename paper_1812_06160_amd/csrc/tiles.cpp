@@ -184,6 +184,7 @@ void build_factor_tiles(const HostAnalysis &H, const TileSet &T, int32_t lanes, 
     F->dloc.clear();
     F->dflag.clear();
     F->match.clear();
+    F->cmask.clear();
     F->imp.clear();
     std::vector<int32_t> slot_of(H.n, -1), imp_of(H.n, -1), iloc(H.n, -1);
     for (int32_t t = 0; t < T.ntiles; ++t) {
@@ -232,6 +233,13 @@ void build_factor_tiles(const HostAnalysis &H, const TileSet &T, int32_t lanes, 
                     }
                     F->match.push_back(m);
                 }
+                uint32_t cm = 0;
+                for (int32_t j = 1; j < rp[c + 1] - dg[c]; ++j) {
+                    const int32_t col = ci[dg[c] + j];
+                    if (col == r || !std::binary_search(ci.data() + rp[r], ci.data() + rp[r + 1], col))
+                        cm |= 1u << j;
+                }
+                F->cmask.push_back(cm);
             }
         }
         F->lptr.push_back((int32_t)F->dloc.size());

@@ -150,12 +150,15 @@ class Ilu:
         return v.value
 
     # ---------------------------------------------------------------- numerics
-    def factor(self, a_val: torch.Tensor, k=None, tau=0.0, casts=("f32", "bf16")):
-        """ILU(k, tau) from device values in input order.  Raises IluError on failure
-        (the exception carries .code and the FactorInfo as .info)."""
+    def factor(self, a_val: torch.Tensor, k=None, tau=0.0, casts=("f32", "bf16"), milu=False):
+        """ILU(k, tau) from device values in input order; milu: modified ILU (what a
+        row loses goes to its diagonal).  Raises IluError on failure (the exception
+        carries .code and the FactorInfo as .info)."""
         assert a_val.is_cuda and a_val.dtype == torch.float64 and a_val.is_contiguous()
         k = 0 if k is None else int(k)
-        cbits = (1 if "f32" in casts else 0) | (2 if "bf16" in casts else 0)
+        cbits = (L.CAST_F32 if "f32" in casts else 0) | (L.CAST_BF16 if "bf16" in casts else 0)
+        if milu:
+            cbits |= L.FACTOR_MODIFIED
         fi = L.FactorInfo()
         code = self.lib.ilu_factor(self.h, _ptr(a_val), k, float(tau), cbits, C.byref(fi), _stream())
         info = dict(bad_row=fi.bad_row, bad_row_original=fi.bad_row_original, bad_matrix=fi.bad_matrix,

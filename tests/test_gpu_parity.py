@@ -17,8 +17,8 @@ SCHEDS = [("level", "level"), ("syncfree", "syncfree")]
 # solve schedules: the factor schedule is irrelevant to the apply; the tiled solve
 # is built with small tiles so that test matrices span several tiles (ragged last)
 SOLVE_SCHEDS = SCHEDS + [("syncfree", "tiled")]
-# factor schedules: the tiled factor covers plain ILU (k = k_max, tau = 0, rows of at
-# most 16 entries) and falls back to the sync-free factor otherwise
+# factor schedules: the tiled factor covers ILU(k) and modified ILU(k) with k = k_max,
+# tau = 0 and rows of at most 16 entries, and falls back to the sync-free factor otherwise
 FACTOR_SCHEDS = SCHEDS + [("tiled", "tiled")]
 
 
@@ -75,6 +75,63 @@ def test_factor_bit_exact(jv, name, mk, k, tau, sched):
         assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64)), \
             f"max diff {np.abs(lu - f.val).max()}"
         assert info["n_dropped"] == int((f.stat == 1).sum())
+
+
+MILU_CASES = [
+    ("laplace2d_64", lambda: synth.workload(1)[0], 0, 0.0),
+    ("laplace3d_16", lambda: synth.laplace3d(16), 0, 0.0),
+    ("convdiff3d_12_ilu1", lambda: synth.convdiff3d(12), 1, 0.0),
+    ("convdiff3d_12_ilu1_tau", lambda: synth.convdiff3d(12), 1, 1e-3),
+    ("random_sparse_ilu1_tau", lambda: synth.random_sparse(300, 0.02, np.random.default_rng(9)), 1, 1e-2),
+    ("random_banded_1500", lambda: synth.random_banded(1500, rng=np.random.default_rng(10)), 0, 0.0),
+]
+
+
+@pytest.mark.parametrize("sched", FACTOR_SCHEDS, ids=lambda s: s[0])
+@pytest.mark.parametrize("staged", [1, 0], ids=["staged", "unstaged"])
+@pytest.mark.parametrize("name,mk,k,tau", MILU_CASES, ids=[c[0] for c in MILU_CASES])
+def test_factor_modified_bit_exact(jv, name, mk, k, tau, staged, sched):
+    # modified ILU: every lost update, dropped multiplier and dropped U entry goes to
+    # the diagonal in the oracle's order, so the factor is bit for bit the oracle's
+    A = mk()
+    for sym in (True, False):
+        an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k, sym=sym)
+        ilu = make(jv, A, k, sym, sched)
+        ilu.set_tuning("factor_staged", staged)
+        f = O.factor(an, A.val, k=k, tau=tau, milu=True)
+        if f.status != O.OK:
+            with pytest.raises(jv.IluError) as e:
+                ilu.factor(dev(A.val), k=k, tau=tau, milu=True)
+            want = "ILU_ERR_ZERO_PIVOT" if f.status == O.ERR_ZERO_PIVOT else "ILU_ERR_NONFINITE"
+            assert e.value.status == want and e.value.info["bad_row"] == f.bad_row
+            continue
+        info = ilu.factor(dev(A.val), k=k, tau=tau, milu=True)
+        lu, st = ilu.factor_values()
+        np.testing.assert_array_equal(st, f.stat)
+        assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64)), \
+            f"max diff {np.abs(lu - f.val).max()}"
+        assert info["n_dropped"] == int((f.stat == 1).sum())
+        # and the plain factor afterwards on the same handle is the plain one
+        ilu.factor(dev(A.val), k=k, tau=tau)
+        g = O.factor(an, A.val, k=k, tau=tau)
+        lu2, _ = ilu.factor_values()
+        assert np.array_equal(lu2.view(np.uint64), g.val.view(np.uint64))
+
+
+@pytest.mark.parametrize("staged", [1, 0], ids=["staged", "unstaged"])
+def test_factor_modified_k_below_kmax(jv, staged):
+    # entries above fill level k are outside the kept pattern: their updates go to
+    # the diagonal too
+    A = synth.convdiff3d(10)
+    ilu = make(jv, A, 2, True, ("syncfree", "syncfree"))
+    ilu.set_tuning("factor_staged", staged)
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=2)
+    for k, tau in ((0, 0.0), (1, 1e-2), (2, 0.0)):
+        ilu.factor(dev(A.val), k=k, tau=tau, milu=True)
+        f = O.factor(an, A.val, k=k, tau=tau, milu=True)
+        lu, st = ilu.factor_values()
+        np.testing.assert_array_equal(st, f.stat)
+        assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
 
 
 @pytest.mark.parametrize("sched", FACTOR_SCHEDS, ids=lambda s: s[0])
@@ -497,14 +554,16 @@ def test_apply_tiled_retune_and_lds_limit(jv):
 ], ids=lambda v: v if isinstance(v, (str, int)) else "")
 def test_factor_tiled_bit_exact(jv, name, mk, k, sym, tile_rows):
     # the tiled factor on tiles from 16 rows (most dependencies imported) to whole
-    # matrices; bit for bit the serial factor, twice in a row (re-armed buffers)
+    # matrices; bit for bit the serial factor, twice in a row (re-armed buffers),
+    # plain and modified, alternating on one handle
     A = mk()
     ilu = make(jv, A, k, sym, ("tiled", "tiled"), tile_rows=tile_rows)
     an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k, sym=sym)
-    f = O.factor(an, A.val, k=k)
+    want = {milu: O.factor(an, A.val, k=k, milu=milu) for milu in (False, True)}
     if np.diff(an.lu_rp).max() <= 16:
         assert ilu.get_tuning("factor_tiled") == 1
-    for _ in range(2):
-        ilu.factor(dev(A.val), k=k)
+    for milu in (False, True, True, False):
+        f = want[milu]
+        ilu.factor(dev(A.val), k=k, milu=milu)
         lu, _ = ilu.factor_values()
         assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64)), f"max diff {np.abs(lu - f.val).max()}"
