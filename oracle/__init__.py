@@ -62,6 +62,8 @@ def lib():
         L.orc_upper_levels.argtypes = [C.c_int, _i32p, _i32p, _i32p]
         L.orc_row_tau.restype = None
         L.orc_row_tau.argtypes = [C.c_int, _i32p, _f64p, _i32p, C.c_double, _f64p]
+        L.orc_rcm.restype = C.c_int
+        L.orc_rcm.argtypes = [C.c_int, _i32p, _i32p, _i32p]
         L.orc_factor.restype = C.c_int
         L.orc_factor.argtypes = [C.c_int, _i32p, _i32p, _i32p, _i32p, _f64p, C.c_int, _f64p, C.c_int,
                                  _i8p, C.POINTER(C.c_int)]
@@ -209,6 +211,7 @@ class Analysis:
     n_ulevels: int
     ulevel_rows: np.ndarray
     ulevel_ptr: np.ndarray
+    order: np.ndarray | None = None   # RCM preorder (new -> input), when one was applied
     extra: dict = field(default_factory=dict)
 
     @property
@@ -221,8 +224,42 @@ class Analysis:
                     median=float(np.median(sizes)))
 
 
-def analyze(n, row_ptr, col_idx, k_max=0, sym=True) -> Analysis:
-    """Pattern, level schedule and permuted structure of ILU(k_max) (Sec. III)."""
+def rcm(n, row_ptr, col_idx):
+    """Reverse Cuthill-McKee order of the graph of A + A^T: order[i] is the input
+    vertex that becomes vertex i (Sec. VII's RCM preordering)."""
+    order = np.empty(n, np.int32)
+    st = lib().orc_rcm(n, np.ascontiguousarray(row_ptr, dtype=np.int32),
+                       np.ascontiguousarray(col_idx, dtype=np.int32), order)
+    if st != OK:
+        raise OracleError(st)
+    return order
+
+
+def analyze(n, row_ptr, col_idx, k_max=0, sym=True, rcm_order=False) -> Analysis:
+    """Pattern, level schedule and permuted structure of ILU(k_max) (Sec. III).
+
+    rcm_order: preorder A by reverse Cuthill-McKee first (Sec. VII); the pattern and
+    levels then belong to Q A Q^T, and perm / the entry maps are composed so that
+    they still refer to the input ordering and input entries."""
+    if rcm_order:
+        canonical(n, row_ptr, col_idx)          # validates A
+        q = rcm(n, row_ptr, col_idx)
+        iq = np.empty(n, np.int32)
+        iq[q] = np.arange(n, dtype=np.int32)
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        qrp, qci, qsrc, _ = permute(n, rp, ci, q, iq)
+        an = analyze(n, qrp, qci, k_max, sym)
+        # compose: Q A Q^T entries -> input entries, level rows -> input rows
+        an.lu_src = np.where(an.lu_src >= 0, qsrc[np.maximum(an.lu_src, 0)], -1)
+        an.b_src = np.where(an.b_src >= 0, qsrc[np.maximum(an.b_src, 0)], -1)
+        an.perm = q[an.perm].astype(np.int32)
+        an.iperm = np.empty(n, np.int32)
+        an.iperm[an.perm] = np.arange(n, dtype=np.int32)
+        # tau row norms are taken over the input rows, in input entry order
+        an.a_rp, an.a_ci, _, an.a_src = canonical(n, row_ptr, col_idx)
+        an.order = q
+        return an
     a_rp, a_ci, _, a_src = canonical(n, row_ptr, col_idx, None)
     s_rp, s_ci, s_lev = symbolic(n, a_rp, a_ci, k_max)
     level, nlev = levels(n, s_rp, s_ci, sym)

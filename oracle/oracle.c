@@ -212,6 +212,153 @@ void orc_sort_by_key(int n, const int *key, int nkey, int *perm, int *iperm, int
 }
 
 /* ------------------------------------------------------------------------ */
+/* Reverse Cuthill-McKee preordering (Sec. VII compares it with the natural  */
+/* and nested-dissection orderings without stating the algorithm; this is   */
+/* the textbook one).  Graph: the pattern of A + A^T without the diagonal;   */
+/* deg(v) = number of distinct neighbours.  Components are taken in order of */
+/* their smallest vertex.  Start vertex of a component: pseudo-peripheral    */
+/* search (George and Liu) from the vertex of least degree (ties: smaller    */
+/* index): build the BFS level structure from r, take x = the vertex of      */
+/* least degree (ties: smaller index) in its last level; if the structure    */
+/* from x is deeper, r = x and repeat, else keep r.  Cuthill-McKee visit:    */
+/* breadth first from the start, each vertex's unvisited neighbours queued   */
+/* in order of (degree, index).  The whole visit order is then reversed:     */
+/* order[i] is the input vertex that becomes vertex i.                       */
+/* ------------------------------------------------------------------------ */
+/* Breadth-first level structure of the component of root: queue receives  */
+/* the component in visit order; returns the depth (levels - 1), with the    */
+/* component size in *size and the queue position of the last level's first */
+/* vertex in *last_lo.                                                       */
+static int rcm_bfs(const int *ap, const int *aj, int root, int *mark, int stamp, int *queue, int *size,
+                   int *last_lo) {
+    int head = 0, tail = 0, depth = 0, lo = 0, hi = 1;
+    queue[tail++] = root;
+    mark[root] = stamp;
+    while (head < tail) {
+        if (head == hi) {   /* every vertex of the current level is expanded */
+            ++depth;
+            lo = hi;
+            hi = tail;
+        }
+        int u = queue[head++];
+        for (int p = ap[u]; p < ap[u + 1]; ++p) {
+            int w = aj[p];
+            if (mark[w] != stamp) {
+                mark[w] = stamp;
+                queue[tail++] = w;
+            }
+        }
+    }
+    *size = tail;
+    *last_lo = lo;
+    return depth;
+}
+
+static int rcm_less(const int *deg, int a, int b) { return deg[a] < deg[b] || (deg[a] == deg[b] && a < b); }
+
+int orc_rcm(int n, const int *rp, const int *ci, int *order) {
+    int *ap = (int *)malloc(sizeof(int) * ((size_t)n + 1));
+    int *cnt = (int *)calloc((size_t)n + 1, sizeof(int));
+    int *deg = (int *)malloc(sizeof(int) * ((size_t)n + 1));
+    int *mark = (int *)malloc(sizeof(int) * ((size_t)n + 1));
+    int *visited = (int *)calloc((size_t)n + 1, sizeof(int));
+    int *queue = (int *)malloc(sizeof(int) * ((size_t)n + 1));
+    int *cm = (int *)malloc(sizeof(int) * ((size_t)n + 1));
+    if (!ap || !cnt || !deg || !mark || !visited || !queue || !cm) return ORC_ERR_NOMEM;
+    /* adjacency of A + A^T without the diagonal: both directions of every entry */
+    for (int i = 0; i < n; ++i)
+        for (int p = rp[i]; p < rp[i + 1]; ++p)
+            if (ci[p] != i) {
+                cnt[i + 1]++;
+                cnt[ci[p] + 1]++;
+            }
+    for (int i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+    int *aj = (int *)malloc(sizeof(int) * ((size_t)cnt[n] + 1));
+    if (!aj) return ORC_ERR_NOMEM;
+    for (int i = 0; i < n; ++i) mark[i] = cnt[i];   /* next free place of row i */
+    for (int i = 0; i < n; ++i)
+        for (int p = rp[i]; p < rp[i + 1]; ++p)
+            if (ci[p] != i) {
+                aj[mark[i]++] = ci[p];
+                aj[mark[ci[p]]++] = i;
+            }
+    /* sort each row (insertion sort) and squeeze out repeated neighbours */
+    ap[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        int lo = cnt[i], hi = cnt[i + 1];
+        for (int a = lo + 1; a < hi; ++a) {
+            int v = aj[a], b = a;
+            while (b > lo && aj[b - 1] > v) {
+                aj[b] = aj[b - 1];
+                --b;
+            }
+            aj[b] = v;
+        }
+        int len = 0;
+        for (int a = lo; a < hi; ++a)
+            if (len == 0 || aj[ap[i] + len - 1] != aj[a]) aj[ap[i] + len++] = aj[a];
+        ap[i + 1] = ap[i] + len;
+        deg[i] = len;
+    }
+    for (int i = 0; i < n; ++i) mark[i] = 0;
+    int stamp = 0, ncm = 0;
+    for (int v = 0; v < n; ++v) {
+        if (visited[v]) continue;
+        /* the vertex of least degree of v's component */
+        int size, lo;
+        rcm_bfs(ap, aj, v, mark, ++stamp, queue, &size, &lo);
+        int r = v;
+        for (int a = 0; a < size; ++a)
+            if (rcm_less(deg, queue[a], r)) r = queue[a];
+        /* pseudo-peripheral search */
+        int depth = rcm_bfs(ap, aj, r, mark, ++stamp, queue, &size, &lo);
+        for (;;) {
+            int x = queue[lo];
+            for (int a = lo + 1; a < size; ++a)
+                if (rcm_less(deg, queue[a], x)) x = queue[a];
+            int sx, lx;
+            int dx = rcm_bfs(ap, aj, x, mark, ++stamp, queue, &sx, &lx);
+            if (dx <= depth) break;
+            r = x;
+            depth = dx;
+            size = sx;
+            lo = lx;
+        }
+        /* Cuthill-McKee visit from r: each vertex's unvisited neighbours in
+           (degree, index) order */
+        int head = ncm;
+        cm[ncm++] = r;
+        visited[r] = 1;
+        while (head < ncm) {
+            int u = cm[head++];
+            int first = ncm;
+            for (int p = ap[u]; p < ap[u + 1]; ++p) {
+                int w = aj[p];
+                if (visited[w]) continue;
+                visited[w] = 1;
+                int b = ncm++;
+                while (b > first && rcm_less(deg, w, cm[b - 1])) {
+                    cm[b] = cm[b - 1];
+                    --b;
+                }
+                cm[b] = w;
+            }
+        }
+    }
+    /* reverse */
+    for (int i = 0; i < n; ++i) order[i] = cm[n - 1 - i];
+    free(ap);
+    free(cnt);
+    free(deg);
+    free(mark);
+    free(visited);
+    free(queue);
+    free(cm);
+    free(aj);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Symmetric permutation P S P^T of a pattern with an integer tag per entry  */
 /* (Sec. III: A is copied into the CSR of L and U in level order).  Row r of */
 /* the result is the original row perm[r] with each column j renamed         */

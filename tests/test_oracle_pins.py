@@ -299,6 +299,141 @@ def test_milu_equals_ilu_when_nothing_is_lost():
 
 
 # --------------------------------------------------------------------------------------
+# Reverse Cuthill-McKee preordering (Sec. VII compares orderings; textbook algorithm)
+# --------------------------------------------------------------------------------------
+
+def _sym_adj(A):
+    D = dense(A) != 0
+    G = (D | D.T)
+    np.fill_diagonal(G, False)
+    return [np.flatnonzero(G[i]) for i in range(A.n)]
+
+
+def _bandwidth(adj, order):
+    pos = np.empty(len(order), np.int64)
+    pos[order] = np.arange(len(order))
+    return max((abs(pos[i] - pos[j]) for i in range(len(adj)) for j in adj[i]), default=0)
+
+
+def _bfs_depths(adj, root):
+    d = {root: 0}
+    frontier = [root]
+    while frontier:
+        nxt = []
+        for u in frontier:
+            for w in adj[u]:
+                if w not in d:
+                    d[w] = d[u] + 1
+                    nxt.append(w)
+        frontier = nxt
+    return d
+
+
+def _scramble(A, rng):
+    p = rng.permutation(A.n)
+    D = dense(A)[np.ix_(p, p)]
+    r, c = np.nonzero(D)
+    return synth.csr_from_coo(A.n, r, c, D[r, c])
+
+
+def test_rcm_recovers_a_scrambled_path():
+    rng = np.random.default_rng(41)
+    B = _scramble(synth.tridiag(60), rng)
+    order = O.rcm(B.n, B.row_ptr, B.col_idx)
+    assert sorted(order) == list(range(B.n))
+    assert _bandwidth(_sym_adj(B), order) == 1
+
+
+@pytest.mark.parametrize("nx,ny", [(7, 11), (12, 5), (9, 9)])
+def test_rcm_scrambled_grid_bandwidth(nx, ny):
+    # from a corner the visit runs along anti-diagonals of at most min(nx, ny)
+    # vertices, so no edge spans more than two of them
+    B = _scramble(synth.laplace2d(nx, ny), np.random.default_rng(nx * ny))
+    order = O.rcm(B.n, B.row_ptr, B.col_idx)
+    adj = _sym_adj(B)
+    assert _bandwidth(adj, order) <= 2 * min(nx, ny)
+    assert len(adj[order[-1]]) == 2            # the visit starts at a corner
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_rcm_cuthill_mckee_properties(seed):
+    rng = np.random.default_rng(700 + seed)
+    n = int(rng.integers(20, 80))
+    A = synth.random_sparse(n, float(rng.uniform(0.01, 0.06)), rng, symmetric_pattern=bool(seed % 2))
+    adj = _sym_adj(A)
+    deg = np.array([len(a) for a in adj])
+    order = O.rcm(A.n, A.row_ptr, A.col_idx)
+    assert sorted(order) == list(range(n))
+    cm = list(order[::-1])
+    pos = {v: i for i, v in enumerate(cm)}
+    # components: contiguous, in order of their smallest vertex
+    starts, seen_min = [], -1
+    i = 0
+    while i < n:
+        comp = _bfs_depths(adj, cm[i])
+        seg = cm[i:i + len(comp)]
+        assert set(seg) == set(comp)
+        assert min(comp) > seen_min
+        seen_min = min(comp)
+        starts.append((cm[i], comp))
+        i += len(comp)
+    for s0, comp in starts:
+        # breadth first: every vertex after the start has its first-placed neighbour
+        # (its parent) earlier, parents are non-decreasing, and siblings come in
+        # (degree, index) order
+        seg = sorted(comp, key=lambda v: pos[v])
+        par = [min(pos[w] for w in adj[v]) for v in seg[1:]]
+        assert all(par[k] < pos[seg[k + 1]] for k in range(len(par)))
+        assert all(par[k] <= par[k + 1] for k in range(len(par) - 1))
+        for k in range(len(par) - 1):
+            if par[k] == par[k + 1]:
+                a, b = seg[k + 1], seg[k + 2]
+                assert (deg[a], a) < (deg[b], b)
+        # the start ends the pseudo-peripheral search: the least-degree vertex of its
+        # last level is no deeper, and the start is the search's seed (least degree,
+        # smallest index) or deeper than it
+        d = _bfs_depths(adj, s0)
+        ecc = max(d.values())
+        last = [v for v in comp if d[v] == ecc]
+        x = min(last, key=lambda v: (deg[v], v))
+        assert max(_bfs_depths(adj, x).values()) <= ecc
+        m = min(comp, key=lambda v: (deg[v], v))
+        assert s0 == m or ecc > max(_bfs_depths(adj, m).values())
+
+
+def test_rcm_bandwidth_close_to_scipy():
+    # a library RCM (different tie rules) as a yardstick on scrambled grids and bands
+    import scipy.sparse.csgraph as csg
+    rng = np.random.default_rng(77)
+    for A in (synth.laplace2d(15, 9), synth.laplace3d(6), synth.banded(80, 3, rng)):
+        B = _scramble(A, rng)
+        adj = _sym_adj(B)
+        ours = _bandwidth(adj, O.rcm(B.n, B.row_ptr, B.col_idx))
+        M = scipy.sparse.csr_matrix((np.ones(B.nnz), B.col_idx, B.row_ptr), shape=(B.n, B.n))
+        ref = _bandwidth(adj, csg.reverse_cuthill_mckee(M, symmetric_mode=False))
+        assert ours <= 1.5 * ref + 1
+
+
+def test_analyze_with_rcm_is_analysis_of_permuted_matrix():
+    # the composed analysis equals the plain analysis of Q A Q^T, and the factor
+    # reaches the same values through the composed entry maps
+    rng = np.random.default_rng(55)
+    A = synth.random_sparse(70, 0.05, rng, symmetric_pattern=True)
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=1, rcm_order=True)
+    q = an.order
+    D = dense(A)[np.ix_(q, q)]
+    r, c = np.nonzero(D)
+    Bq = synth.csr_from_coo(A.n, r, c, D[r, c])
+    bn = O.analyze(Bq.n, Bq.row_ptr, Bq.col_idx, k_max=1)
+    assert np.array_equal(an.lu_rp, bn.lu_rp) and np.array_equal(an.lu_ci, bn.lu_ci)
+    assert np.array_equal(an.perm, q[bn.perm])
+    fa = O.factor(an, A.val, tau=1e-3)
+    fb = O.factor(bn, Bq.val, tau=1e-3)
+    assert np.array_equal(fa.stat, fb.stat)
+    np.testing.assert_allclose(fa.val, fb.val, rtol=1e-13, atol=1e-15)
+
+
+# --------------------------------------------------------------------------------------
 # Errors (no pivoting, Sec. III)
 # --------------------------------------------------------------------------------------
 
