@@ -8,6 +8,10 @@ random_1m      n = 1e6 random unsymmetric rows (8 banded + 8 scattered off-diago
 batch512       512 variable-coefficient 2D diffusion matrices in one block-diagonal
                handle: factor, FP32 apply of 4 right-hand sides each through a
                captured graph, FP64 forward + adjoint.
+ordering       natural vs reverse Cuthill-McKee preorder (both under the level
+               ordering): levels, factor and apply times, Krylov iterations and time
+               on the 128^3 Laplacian (as given and scrambled by a random symmetric
+               permutation), convdiff3d_96 and random_1m.
 """
 import json
 import sys
@@ -118,6 +122,63 @@ def run(args):
                    apply16_f64_us=round(1e3 * t64, 1), apply16_f64_gbs=round(B64["apply"] / t64 / 1e6, 1),
                    apply1_f64_us=round(1e3 * t1, 1),
                    us_per_level_apply1=round(1e3 * t1 / (info["n_levels"] + info["n_ulevels"]), 3))
+    elif wl == "ordering":
+        rows = []
+
+        def scrambled(A, seed):
+            # P A P^T for a random permutation P: row i of the result is row p[i]
+            p = np.random.default_rng(seed).permutation(A.n)
+            ip = np.empty(A.n, np.int64)
+            ip[p] = np.arange(A.n)
+            lens = np.diff(A.row_ptr)[p]
+            rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+            starts = A.row_ptr[p]
+            src = np.repeat(starts - rp[:-1], lens) + np.arange(rp[-1])
+            cols = ip[A.col_idx[src]]
+            vals = A.val[src]
+            key = np.repeat(np.arange(A.n, dtype=np.int64), lens) * A.n + cols
+            o = np.argsort(key, kind="stable")
+            return synth.CSR(A.n, rp, cols[o].astype(np.int32), vals[o])
+
+        A2, b2 = synth.workload(2)
+        A3, b3 = synth.workload(3)
+        A4, _ = synth.workload(4)
+        b4 = np.ascontiguousarray(synth.rhs(A4.n, 1, np.random.default_rng([4, 2]))).reshape(-1)
+        cases = [("laplace3d_128", A2, b2, 0, 0.0, "sym", "pcg"),
+                 ("laplace3d_128_scrambled", scrambled(A2, 7), b2, 0, 0.0, "sym", "pcg"),
+                 ("convdiff3d_96", A3, b3, 1, 1e-3, "sym", "gmres"),
+                 ("random_1m", A4, b4, 0, 0.0, "sym", "gmres")]
+        for name, A, b, k, tau, pat, kry in cases:
+            for order in ("natural", "rcm"):
+                t0 = time.perf_counter()
+                ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=k, pattern=pat, ordering=order)
+                t_an = time.perf_counter() - t0
+                ilu.set_schedule(args.sched, args.solve_sched)
+                info = ilu.info()
+                vals = _dev(A.val)
+                bd = _dev(b)
+                ilu.profile(True, 1 << 16)
+                st = _stage_times(ilu, lambda: ilu.factor(vals, k=k, tau=tau, casts=()), 3)
+                pa = _stage_times(ilu, lambda: ilu.apply(bd), 5)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                if kry == "pcg":
+                    _, si = ilu.pcg(bd, rtol=1e-10, prec="f64", raise_on_fail=False)
+                else:
+                    _, si = ilu.gmres(bd, rtol=1e-10, restart=30, prec="f64", raise_on_fail=False)
+                torch.cuda.synchronize()
+                t_k = time.perf_counter() - t1
+                row = dict(matrix=name, ordering=order, analyze_s=round(t_an, 2), levels=info["n_levels"],
+                           ulevels=info["n_ulevels"], level_median=info["level_median"],
+                           factor_us=round(1e3 * st["factor"][0], 1),
+                           apply_us=round(1e3 * (pa["forward"][0] + pa["backward"][0]), 1),
+                           krylov=kry, iters=si["iters"], seconds=round(t_k, 4),
+                           true_relres=si["true_relres"])
+                log(json.dumps(row))
+                rows.append(row)
+                del ilu
+                torch.cuda.empty_cache()
+        out.update(rows=rows)
     elif wl == "batch512":
         mats, rhs = synth.workload(5)
         t0 = time.perf_counter()

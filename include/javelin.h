@@ -91,8 +91,20 @@ typedef struct {
                                  ILU_ERR_STATE */
     int32_t tile_rows;        /* rows per tile of the tiled solves (0 = default: 512, halved until a
                                  tile fits the LDS budget; else 16..65536, used as given) */
-    int32_t reserved[4];      /* must be 0 */
+    int32_t ordering;         /* ILU_ORDER_NATURAL (default: A as given) or ILU_ORDER_RCM */
+    int32_t reserved[3];      /* must be 0 */
 } ilu_analyze_opts;
+
+/* Preorderings applied before the analysis (Sec. VII compares orderings; the
+ * method itself only imposes the level ordering).  ILU_ORDER_RCM: reverse
+ * Cuthill-McKee on the graph of A + A^T -- components in order of their smallest
+ * vertex, each started from a pseudo-peripheral vertex (George-Liu search seeded
+ * with the vertex of least degree, ties to the smaller index), neighbours queued
+ * by (degree, index), the whole sweep reversed.  The levels are then those of
+ * Q A Q^T; perm (ilu_copy_schedule) and every call keep using the input ordering,
+ * so callers see no difference except the schedule and the factor.  Not
+ * available for batched handles (ILU_ERR_UNSUPPORTED). */
+enum { ILU_ORDER_NATURAL = 0, ILU_ORDER_RCM = 1 };
 
 typedef struct {
     int32_t n;

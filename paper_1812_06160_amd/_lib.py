@@ -20,6 +20,7 @@ PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
 PERMUTED_SPACE = 1
 SCHED_AUTO, SCHED_LEVEL, SCHED_SYNCFREE, SCHED_TILED = 0, 1, 2, 3
 CAST_F32, CAST_BF16, FACTOR_MODIFIED = 1, 2, 0x100
+ORDER_NATURAL, ORDER_RCM = 0, 1
 STAGE_FACTOR, STAGE_FORWARD, STAGE_BACKWARD, STAGE_SPMV, STAGE_COUNT = 0, 1, 2, 3, 4
 STAGES = ["factor", "forward", "backward", "spmv"]
 
@@ -40,7 +41,7 @@ class Csr(C.Structure):
 
 class AnalyzeOpts(C.Structure):
     _fields_ = [("k_max", C.c_int32), ("pattern", C.c_int32), ("host_only", C.c_int32),
-                ("tile_rows", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("tile_rows", C.c_int32), ("ordering", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class Info(C.Structure):

@@ -76,9 +76,10 @@ void triangular_deps(int32_t n, const std::vector<int32_t> &rp, const std::vecto
 
 }  // namespace
 
-ilu_status analyze_host(int32_t n, const int32_t *rp, const int32_t *ci, int64_t nnz, int32_t k_max,
-                        int32_t pattern, HostAnalysis *out, std::string *err) {
-    if (n <= 0 || !rp || !ci || !out) { *err = "analyze: n <= 0 or NULL array"; return ILU_ERR_ARG; }
+// Arguments and CSR intake: monotone row pointers, sorted unique in-range columns.
+static ilu_status check_input(int32_t n, const int32_t *rp, const int32_t *ci, int64_t nnz, int32_t k_max,
+                              int32_t pattern, std::string *err) {
+    if (n <= 0 || !rp || !ci) { *err = "analyze: n <= 0 or NULL array"; return ILU_ERR_ARG; }
     if (k_max < 0 || k_max > 100) { *err = "analyze: k_max must be in [0, 100]"; return ILU_ERR_ARG; }
     if (pattern != ILU_PATTERN_LOWER_SYM && pattern != ILU_PATTERN_LOWER_A) {
         *err = "analyze: unknown dependency pattern";
@@ -97,6 +98,14 @@ ilu_status analyze_host(int32_t n, const int32_t *rp, const int32_t *ci, int64_t
             if (p > rp[i] && ci[p] <= ci[p - 1]) { *err = "analyze: columns unsorted or duplicated in row " + std::to_string(i); return ILU_ERR_CSR; }
         }
     }
+    return ILU_OK;
+}
+
+static ilu_status analyze_natural(int32_t n, const int32_t *rp, const int32_t *ci, int64_t nnz, int32_t k_max,
+                                  int32_t pattern, HostAnalysis *out, std::string *err) {
+    if (!out) { *err = "analyze: NULL output"; return ILU_ERR_ARG; }
+    ilu_status st0 = check_input(n, rp, ci, nnz, k_max, pattern, err);
+    if (st0 != ILU_OK) return st0;
     HostAnalysis &H = *out;
     H = HostAnalysis();
     H.n = n;
@@ -290,6 +299,142 @@ ilu_status analyze_host(int32_t n, const int32_t *rp, const int32_t *ci, int64_t
         H.n_tulevels = peel(n, sp, succ, indeg, H.tulevel_rows, H.tulevel_ptr, nullptr);
         if (H.n_tlevels < 0 || H.n_tulevels < 0) { *err = "analyze: transposed schedule cycle (internal error)"; return ILU_ERR_ARG; }
     }
+    return ILU_OK;
+}
+
+
+// Reverse Cuthill-McKee order of the graph of A + A^T (diagonal ignored), the
+// preordering that Sec. VII sets against nested dissection.  Components in order
+// of their smallest vertex; each starts from a pseudo-peripheral vertex found by
+// the George-Liu search seeded with the component's vertex of least (degree,
+// index); the Cuthill-McKee sweep queues each vertex's unvisited neighbours by
+// (degree, index); the concatenated sweep is reversed.  order[i] = input vertex
+// that becomes vertex i.
+std::vector<int32_t> rcm_order(int32_t n, const int32_t *rp, const int32_t *ci) {
+    // symmetric adjacency from the sorted, de-duplicated list of both directions
+    std::vector<int64_t> arcs;
+    arcs.reserve((size_t)rp[n] * 2);
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t p = rp[i]; p < rp[i + 1]; ++p)
+            if (ci[p] != i) {
+                arcs.push_back((int64_t)i * n + ci[p]);
+                arcs.push_back((int64_t)ci[p] * n + i);
+            }
+    std::sort(arcs.begin(), arcs.end());
+    arcs.erase(std::unique(arcs.begin(), arcs.end()), arcs.end());
+    std::vector<int32_t> gp((size_t)n + 1, 0), gj(arcs.size());
+    for (size_t e = 0; e < arcs.size(); ++e) {
+        gp[arcs[e] / n + 1]++;
+        gj[e] = (int32_t)(arcs[e] % n);
+    }
+    for (int32_t i = 0; i < n; ++i) gp[i + 1] += gp[i];
+    auto deg = [&](int32_t v) { return gp[v + 1] - gp[v]; };
+    auto before = [&](int32_t a, int32_t b) { return deg(a) != deg(b) ? deg(a) < deg(b) : a < b; };
+
+    // breadth-first level structure: returns its depth; `bfs` holds the reached
+    // vertices in visit order and `last` the start of the deepest level
+    std::vector<int32_t> seen(n, -1), bfs;
+    bfs.reserve(n);
+    int32_t epoch = 0;
+    auto levels = [&](int32_t root, size_t &last) {
+        ++epoch;
+        bfs.clear();
+        bfs.push_back(root);
+        seen[root] = epoch;
+        size_t level_begin = 0, level_end = 1;
+        int32_t depth = 0;
+        while (true) {
+            for (size_t k = level_begin; k < level_end; ++k)
+                for (int32_t e = gp[bfs[k]]; e < gp[bfs[k] + 1]; ++e)
+                    if (seen[gj[e]] != epoch) {
+                        seen[gj[e]] = epoch;
+                        bfs.push_back(gj[e]);
+                    }
+            if (bfs.size() == level_end) break;
+            level_begin = level_end;
+            level_end = bfs.size();
+            ++depth;
+        }
+        last = level_begin;
+        return depth;
+    };
+
+    std::vector<char> placed(n, 0);
+    std::vector<int32_t> sweep;
+    sweep.reserve(n);
+    std::vector<int32_t> kids;
+    for (int32_t v = 0; v < n; ++v) {
+        if (placed[v]) continue;
+        size_t last = 0;
+        levels(v, last);
+        int32_t start = *std::min_element(bfs.begin(), bfs.end(), before);
+        int32_t depth = levels(start, last);
+        while (true) {
+            const int32_t x = *std::min_element(bfs.begin() + (std::ptrdiff_t)last, bfs.end(), before);
+            size_t xlast = 0;
+            const int32_t dx = levels(x, xlast);
+            if (dx <= depth) break;
+            start = x;
+            depth = dx;
+            last = xlast;
+        }
+        size_t head = sweep.size();
+        sweep.push_back(start);
+        placed[start] = 1;
+        while (head < sweep.size()) {
+            const int32_t u = sweep[head++];
+            kids.clear();
+            for (int32_t e = gp[u]; e < gp[u + 1]; ++e)
+                if (!placed[gj[e]]) {
+                    placed[gj[e]] = 1;
+                    kids.push_back(gj[e]);
+                }
+            std::sort(kids.begin(), kids.end(), before);
+            sweep.insert(sweep.end(), kids.begin(), kids.end());
+        }
+    }
+    std::reverse(sweep.begin(), sweep.end());
+    return sweep;
+}
+
+ilu_status analyze_host(int32_t n, const int32_t *rp, const int32_t *ci, int64_t nnz, int32_t k_max,
+                        int32_t pattern, int32_t ordering, HostAnalysis *out, std::string *err) {
+    if (ordering == ILU_ORDER_NATURAL) return analyze_natural(n, rp, ci, nnz, k_max, pattern, out, err);
+    if (ordering != ILU_ORDER_RCM) {
+        *err = "analyze: unknown ordering";
+        return ILU_ERR_ARG;
+    }
+    // validate A as given, then analyse Q A Q^T and compose the maps back
+    ilu_status st = check_input(n, rp, ci, nnz, k_max, pattern, err);
+    if (st != ILU_OK) return st;
+    if (!out) { *err = "analyze: NULL output"; return ILU_ERR_ARG; }
+    const std::vector<int32_t> q = rcm_order(n, rp, ci);
+    std::vector<int32_t> iq(n);
+    for (int32_t i = 0; i < n; ++i) iq[q[i]] = i;
+    std::vector<int32_t> qrp((size_t)n + 1, 0), qci((size_t)nnz), qsrc((size_t)nnz);
+    std::vector<std::pair<int32_t, int32_t>> row;
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t o = q[i];
+        row.clear();
+        for (int32_t p = rp[o]; p < rp[o + 1]; ++p) row.emplace_back(iq[ci[p]], p);
+        std::sort(row.begin(), row.end());
+        qrp[i + 1] = qrp[i] + (int32_t)row.size();
+        for (size_t k = 0; k < row.size(); ++k) {
+            qci[qrp[i] + k] = row[k].first;
+            qsrc[qrp[i] + k] = row[k].second;
+        }
+    }
+    st = analyze_natural(n, qrp.data(), qci.data(), nnz, k_max, pattern, out, err);
+    if (st != ILU_OK) return st;
+    HostAnalysis &H = *out;
+    for (auto &s : H.lu_src)
+        if (s >= 0) s = qsrc[s];
+    for (auto &s : H.b_src)
+        if (s >= 0) s = qsrc[s];
+    for (int32_t r = 0; r < n; ++r) H.perm[r] = q[H.perm[r]];
+    for (int32_t r = 0; r < n; ++r) H.iperm[H.perm[r]] = r;
+    H.in_rp.assign(rp, rp + n + 1);   // tau row norms: input rows, input entry order
+    H.order = q;
     return ILU_OK;
 }
 

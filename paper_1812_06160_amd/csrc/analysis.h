@@ -23,6 +23,7 @@ struct HostAnalysis {
     std::vector<int32_t> level_ptr;    // [n_levels + 1], rows of level l are [ptr[l], ptr[l+1])
     std::vector<int32_t> perm;         // level ordering -> input ordering
     std::vector<int32_t> iperm;        // input ordering -> level ordering
+    std::vector<int32_t> order;        // preordering applied before the analysis (empty: none)
 
     // factor structure P S P^T in level order
     std::vector<int32_t> lu_rp, lu_ci, diag, lu_src;
@@ -110,8 +111,13 @@ struct FactorTiles {
 // longest factor row (the caller checks it is at most 16).
 void build_factor_tiles(const HostAnalysis &H, const TileSet &fwd, int32_t lanes, FactorTiles *F);
 
-// Returns ILU_OK or an error status with a message in *err.
+// Returns ILU_OK or an error status with a message in *err.  ordering:
+// ILU_ORDER_NATURAL (A as given) or ILU_ORDER_RCM (A preordered by reverse
+// Cuthill-McKee; perm and the entry maps then refer to the input ordering).
 ilu_status analyze_host(int32_t n, const int32_t *rp, const int32_t *ci, int64_t nnz, int32_t k_max,
-                        int32_t pattern, HostAnalysis *out, std::string *err);
+                        int32_t pattern, int32_t ordering, HostAnalysis *out, std::string *err);
+
+// Reverse Cuthill-McKee order of the graph of A + A^T: order[i] = input vertex i'.
+std::vector<int32_t> rcm_order(int32_t n, const int32_t *rp, const int32_t *ci);
 
 }  // namespace jv

@@ -452,7 +452,7 @@ extern "C" ilu_status ilu_analyze(const ilu_csr *A, const ilu_analyze_opts *opts
     *out = nullptr;
     ilu_analyze_opts o{};
     if (opts) o = *opts;
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 3; ++i)
         if (o.reserved[i]) return fail(ILU_ERR_ARG, "ilu_analyze: reserved option fields must be 0");
     if (o.tile_rows != 0 && (o.tile_rows < 16 || o.tile_rows > 65536))
         return fail(ILU_ERR_ARG, "ilu_analyze: tile_rows must be 0 or in [16, 65536]");
@@ -463,7 +463,7 @@ extern "C" ilu_status ilu_analyze(const ilu_csr *A, const ilu_analyze_opts *opts
     std::string err;
     ilu_status st;
     try {
-        st = analyze_host(A->n, A->row_ptr, A->col_idx, A->nnz, o.k_max, o.pattern, &h->H, &err);
+        st = analyze_host(A->n, A->row_ptr, A->col_idx, A->nnz, o.k_max, o.pattern, o.ordering, &h->H, &err);
     } catch (const std::bad_alloc &) {
         return fail(ILU_ERR_NOMEM, "ilu_analyze: out of host memory");
     }
@@ -486,6 +486,8 @@ extern "C" ilu_status ilu_analyze_batched(int32_t count, const ilu_csr *As, cons
     *out = nullptr;
     ilu_analyze_opts o{};
     if (opts) o = *opts;
+    if (o.ordering != ILU_ORDER_NATURAL)
+        return fail(ILU_ERR_UNSUPPORTED, "ilu_analyze_batched: a preordering would mix the matrices' rows");
     std::vector<int64_t> roff(count + 1, 0), zoff(count + 1, 0);
     for (int i = 0; i < count; ++i) {
         if (As[i].n <= 0 || !As[i].row_ptr || !As[i].col_idx) return fail(ILU_ERR_ARG, "ilu_analyze_batched: bad matrix");

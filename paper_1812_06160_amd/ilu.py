@@ -42,7 +42,7 @@ class Ilu:
     """Analysis handle: ILU(k_max) pattern, level schedule and permuted structure of A."""
 
     def __init__(self, n=None, row_ptr=None, col_idx=None, k_max=0, pattern="sym", host_only=False,
-                 tile_rows=0, _handle=None):
+                 tile_rows=0, ordering="natural", _handle=None):
         self.lib = L.load()
         self.h = C.c_void_p()
         if _handle is not None:
@@ -52,7 +52,8 @@ class Ilu:
             ci = np.ascontiguousarray(col_idx, dtype=np.int32)
             csr = L.Csr(int(n), int(rp[-1]), _np_ptr(rp), _np_ptr(ci))
             opts = L.AnalyzeOpts(int(k_max), L.PATTERN_LOWER_SYM if pattern == "sym" else L.PATTERN_LOWER_A,
-                                 1 if host_only else 0, int(tile_rows))
+                                 1 if host_only else 0, int(tile_rows),
+                                 {"natural": L.ORDER_NATURAL, "rcm": L.ORDER_RCM}[ordering])
             L.check(self.lib.ilu_analyze(C.byref(csr), C.byref(opts), C.byref(self.h)), "ilu_analyze")
         self._info = L.Info()
         L.check(self.lib.ilu_get_info(self.h, C.byref(self._info)), "ilu_get_info")

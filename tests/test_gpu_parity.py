@@ -134,6 +134,42 @@ def test_factor_modified_k_below_kmax(jv, staged):
         assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
 
 
+RCM_CASES = [
+    ("random_banded_3000", lambda: synth.random_banded(3000, rng=np.random.default_rng(31)), 0, 0.0, True),
+    ("convdiff3d_12_ilu1_tau", lambda: synth.convdiff3d(12), 1, 1e-3, True),
+    ("random_sparse_ragged_lower_a", lambda: synth.random_sparse(500, 0.01, np.random.default_rng(32)), 0, 0.0,
+     False),
+]
+
+
+@pytest.mark.parametrize("sched", FACTOR_SCHEDS, ids=lambda s: s[0])
+@pytest.mark.parametrize("name,mk,k,tau,sym", RCM_CASES, ids=[c[0] for c in RCM_CASES])
+def test_rcm_preorder_factor_apply_krylov(jv, name, mk, k, tau, sym, sched):
+    # reverse Cuthill-McKee preorder: schedule, factor bits and applies equal the
+    # oracle's composed analysis; callers keep the input ordering throughout
+    A = mk()
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k, sym=sym, rcm_order=True)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=k, pattern="sym" if sym else "a", ordering="rcm")
+    ilu.set_schedule(*sched)
+    s = ilu.schedule()
+    np.testing.assert_array_equal(s["perm"], an.perm)
+    np.testing.assert_array_equal(s["lu_col_idx"], an.lu_ci)
+    f = O.factor(an, A.val, k=k, tau=tau)
+    assert f.status == O.OK
+    ilu.factor(dev(A.val), k=k, tau=tau)
+    lu, st = ilu.factor_values()
+    np.testing.assert_array_equal(st, f.stat)
+    assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
+    b = synth.rhs(A.n, 3, np.random.default_rng(33))
+    x = ilu.apply(dev(b)).cpu().numpy()
+    assert relerr(x, O.apply(an, f.val, b)) <= 1e-12
+    y = ilu.spmv(dev(b)).cpu().numpy()
+    assert relerr(y, synth.csr_to_dense(A) @ b) <= 1e-12
+    rhs = dev(b[:, 0].copy())
+    xs, info = ilu.gmres(rhs, rtol=1e-10, restart=30, prec="f64")
+    assert info["true_relres"] <= 1e-10
+
+
 @pytest.mark.parametrize("sched", FACTOR_SCHEDS, ids=lambda s: s[0])
 def test_factor_k_below_kmax(jv, sched):
     A = synth.convdiff3d(10)

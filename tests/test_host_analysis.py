@@ -24,13 +24,14 @@ def test_library_exports_every_declared_symbol():
     assert lib.ilu_status_str(5) == b"ILU_ERR_ZERO_PIVOT"
 
 
-def host_ilu(A, k_max=0, sym=True):
-    return jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=k_max, pattern="sym" if sym else "a", host_only=True)
+def host_ilu(A, k_max=0, sym=True, ordering="natural"):
+    return jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=k_max, pattern="sym" if sym else "a", host_only=True,
+                  ordering=ordering)
 
 
-def compare_schedule(A, k_max, sym):
-    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k_max, sym=sym)
-    h = host_ilu(A, k_max, sym)
+def compare_schedule(A, k_max, sym, ordering="natural"):
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k_max, sym=sym, rcm_order=ordering == "rcm")
+    h = host_ilu(A, k_max, sym, ordering)
     s = h.schedule()
     assert h.info()["n_levels"] == an.n_levels
     assert h.info()["n_ulevels"] == an.n_ulevels
@@ -64,6 +65,37 @@ def test_host_analysis_bit_exact_workloads_small(wid, k):
     compare_schedule(A, k_max=k, sym=False)
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_host_analysis_rcm_bit_exact(seed):
+    # the library's reverse Cuthill-McKee preorder and the composed analysis equal
+    # the oracle's (several components, missing diagonals, both patterns, k <= 2)
+    rng = np.random.default_rng(1300 + seed)
+    n = int(rng.integers(2, 300))
+    A = synth.random_sparse(n, float(rng.uniform(0.002, 0.05)), rng, symmetric_pattern=bool(seed % 3 == 0),
+                            drop_diag_frac=0.2 if seed % 4 == 1 else 0.0)
+    compare_schedule(A, k_max=seed % 3, sym=bool(seed % 2), ordering="rcm")
+
+
+@pytest.mark.parametrize("wid,k", [(1, 0), (2, 0), (3, 1), (4, 0)])
+def test_host_analysis_rcm_workloads_small(wid, k):
+    A, _ = synth.workload(wid, scale=0.1 if wid != 4 else 0.002)
+    compare_schedule(A, k_max=k, sym=True, ordering="rcm")
+
+
+def test_rcm_option_errors():
+    # an unknown ordering is an argument error; a batched handle refuses a preorder
+    A = synth.laplace2d(5)
+    assert _analyze_raw(A.n, A.row_ptr, A.col_idx, ordering=7) == L.ERR_ARG
+    assert _analyze_raw(A.n, A.row_ptr, A.col_idx, ordering=L.ORDER_RCM) == L.OK
+    lib = jv.load()
+    rp = np.ascontiguousarray(A.row_ptr, np.int32)
+    ci = np.ascontiguousarray(A.col_idx, np.int32)
+    arr = (L.Csr * 1)(L.Csr(A.n, int(rp[-1]), rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p)))
+    opts = L.AnalyzeOpts(0, 0, 1, 0, L.ORDER_RCM)
+    h = C.c_void_p()
+    assert lib.ilu_analyze_batched(1, arr, C.byref(opts), C.byref(h)) == L.ERR_UNSUPPORTED
+
+
 def test_host_analysis_batched_is_block_diagonal():
     mats, _ = synth.workload(5, scale=0.06)
     mats = mats[:6]
@@ -91,12 +123,12 @@ def test_host_analysis_full_laplace3d():
     assert I["nnz_lu"] == 14_581_760
 
 
-def _analyze_raw(n, rp, ci, k_max=0, pattern=0, host_only=1, reserved=0):
+def _analyze_raw(n, rp, ci, k_max=0, pattern=0, host_only=1, reserved=0, ordering=0):
     lib = jv.load()
     rp = np.ascontiguousarray(rp, np.int32)
     ci = np.ascontiguousarray(ci, np.int32)
     csr = L.Csr(n, int(rp[-1]) if rp.size else 0, rp.ctypes.data_as(C.c_void_p), ci.ctypes.data_as(C.c_void_p))
-    opts = L.AnalyzeOpts(k_max, pattern, host_only)
+    opts = L.AnalyzeOpts(k_max, pattern, host_only, 0, ordering)
     opts.reserved[0] = reserved
     h = C.c_void_p()
     code = lib.ilu_analyze(C.byref(csr), C.byref(opts), C.byref(h))
