@@ -307,11 +307,14 @@ ilu_status ilu_solve_gmres(ilu_handle h, const double *b, double *x, double rtol
 /* Scheduling and tuning.                                                         */
 /* ---------------------------------------------------------------------------- */
 
-/* Chooses the launch scheme of the factor and of the solves (ILU_SCHED_*; the
- * tiled factor runs plain ILU only -- k = k_max and tau = 0 -- and otherwise the
- * call runs the sync-free factor) and the
+/* Chooses the launch scheme of the factor and of the solves (ILU_SCHED_*) and the
  * lanes per row (0 = automatic from the longest row; else 4, 8, 16, 32 or 64;
- * factor lanes must cover the longest factor row). */
+ * factor lanes must cover the longest factor row).  The tiled factor runs ILU(k)
+ * and modified ILU(k) with k = k_max, tau = 0 and rows of at most 16 entries;
+ * otherwise the call runs the sync-free factor.  A solve direction whose rows have
+ * more than 32 dependencies runs sync-free under the tiled schedule.  Factor rows
+ * longer than 64 entries (up to 4096) run with one wave per row and the row in
+ * LDS, whatever the lanes; longer rows give ILU_ERR_UNSUPPORTED. */
 ilu_status ilu_set_schedule(ilu_handle h, int32_t factor_sched, int32_t solve_sched,
                             int32_t lanes_factor, int32_t lanes_solve);
 ilu_status ilu_get_schedule(ilu_handle h, int32_t *factor_sched, int32_t *solve_sched,

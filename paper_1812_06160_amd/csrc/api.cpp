@@ -235,10 +235,12 @@ hipError_t ilu_handle_s::prepare_tile_claims(int pass, TileArgs *t, hipStream_t 
     return hipSuccess;
 }
 
+// rows the tiled solve can take at all (dependencies per row), whatever the tile size
+static bool tile_rows_ok(const TileSet &T) { return T.kmax <= (T.unit == 64 ? kTileShortRow : 4 * kTileLongJ); }
+
 static bool tiles_fit(const TileSet &T) {
     return tile_lds_bytes(T.max_rows, T.max_slots, T.max_pos, T.kmax, 1, 8) <= (size_t)kTileLdsMax &&
-           T.max_slots + 1 <= 65535 && T.max_pos <= 32767 &&
-           T.kmax <= (T.unit == 64 ? kTileShortRow : 4 * kTileLongJ);
+           T.max_slots + 1 <= 65535 && T.max_pos <= 32767 && tile_rows_ok(T);
 }
 
 ilu_status ilu_handle_s::make_tiles(int32_t rows, bool shrink) {
@@ -600,9 +602,11 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
         return fail(ILU_ERR_ARG, "ilu_factor: unknown flag bits");
     const bool milu = (casts & ILU_FACTOR_MODIFIED) != 0;
     const HostAnalysis &H = h->H;
-    if (H.max_row_lu > 64)
-        return fail(ILU_ERR_UNSUPPORTED, "ilu_factor: factor rows longer than 64 entries are not supported");
-    const int lanes = h->lanes_factor;
+    if (H.max_row_lu > kFactorLongMax)
+        return fail(ILU_ERR_UNSUPPORTED, "ilu_factor: factor rows longer than 4096 entries are not supported");
+    // rows longer than 64 entries: one wave per row with the row in LDS
+    const bool long_rows = H.max_row_lu > 64;
+    const int lanes = long_rows ? 64 : h->lanes_factor;
     const bool sf = h->sched_factor != ILU_SCHED_LEVEL;
     hipError_t e;
     h->factored = false;
@@ -631,6 +635,7 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
     A.info = h->d_info;
     A.tcap = (h->factor_staged && factor_lds_bytes(lanes, h->factor_tcap)) ? h->factor_tcap : 0;
     A.max_lower = H.max_lower_lu;
+    A.lcap = long_rows ? H.max_row_lu : 0;
     // the tiled factor covers plain ILU (every pattern entry kept, no dropping);
     // anything else runs the sync-free factor
     bool tiled = h->sched_factor == ILU_SCHED_TILED && h->ftiles_ok && !use_tau && !A.use_flev;
@@ -674,7 +679,8 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
         A.nstreams = h->nstreams;
         A.poll_sleep = h->poll_sleep;
         h->prof.begin(ILU_STAGE_FACTOR, s);
-        e = launch_factor(A, lanes, true, h->grid_syncfree(tl), s);
+        e = long_rows ? launch_factor_long(A, true, h->grid_syncfree(tl), s)
+                      : launch_factor(A, lanes, true, h->grid_syncfree(tl), s);
         h->prof.end(s);
         if (e != hipSuccess) return hip_fail(e, "ilu_factor: launch");
     } else {
@@ -682,7 +688,8 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
         for (int l = 0; l < H.n_levels; ++l) {
             A.row_begin = H.level_ptr[l];
             A.row_end = H.level_ptr[l + 1];
-            if ((e = launch_factor(A, lanes, false, 0, s)) != hipSuccess) return hip_fail(e, "ilu_factor: launch");
+            e = long_rows ? launch_factor_long(A, false, 0, s) : launch_factor(A, lanes, false, 0, s);
+            if (e != hipSuccess) return hip_fail(e, "ilu_factor: launch");
         }
         h->prof.end(s);
     }
@@ -851,7 +858,8 @@ ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int 
             which = fwd ? kTasksTForward : kTasksTBackward;
             lptr = fwd ? &H.tlevel_ptr : &H.tulevel_ptr;
         }
-        if (view == 0 && h->sched_solve == ILU_SCHED_TILED) {
+        // the tiled schedule; a direction whose rows are too long for it runs sync-free
+        if (view == 0 && h->sched_solve == ILU_SCHED_TILED && tile_rows_ok(h->tiles[fwd ? 0 : 1])) {
             const TileSet &T = h->tiles[fwd ? 0 : 1];
             const ilu_handle_s::DevTiles &D = h->dtiles[fwd ? 0 : 1];
             TileArgs ta{};

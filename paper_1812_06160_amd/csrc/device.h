@@ -68,6 +68,7 @@ struct FactorArgs {
     int32_t tcap;         // LDS entries per group for the dependency rows (0: no staging)
     int32_t max_lower;    // longest strictly lower part of a row
     int32_t poll_sleep;   // s_sleep(1) steps between polls of a pending value
+    int32_t lcap;         // long rows (more than 64 entries): LDS entries per wave (0: not used)
 };
 
 struct SolveArgs {
@@ -174,6 +175,11 @@ hipError_t launch_row_tau(int32_t n, const int32_t *in_rp, const double *a, cons
                           double *row_tau, hipStream_t s);
 hipError_t launch_gather(int64_t m, const int32_t *src, const double *a, double *out, hipStream_t s);
 hipError_t launch_factor(const FactorArgs &A, int lanes, bool syncfree, int grid, hipStream_t s);
+// factor with one wave per row and the row's values in LDS (A.lcap entries per wave),
+// for patterns with rows longer than 64 entries; hipErrorInvalidValue when the rows
+// do not fit LDS
+hipError_t launch_factor_long(const FactorArgs &A, bool syncfree, int grid, hipStream_t s);
+constexpr int kFactorLongMax = 4096;   // longest factor row of the long-row factor
 hipError_t launch_factor_fixup(int64_t nnz, double *lu, const int8_t *flev, int32_t k, int32_t use_flev,
                                int8_t *stat, int32_t *info, hipStream_t s);
 hipError_t launch_cast_f32(int64_t m, const double *x, float *y, hipStream_t s);

@@ -617,6 +617,136 @@ __device__ __forceinline__ void factor_row_staged(const FactorArgs &A, int r, in
     factor_finish<G, SF>(A, r, t, gi, p, act, col, absent, dropped, v, tr, d - rs);
 }
 
+// Long rows (more than 64 entries): one wave per row, the row's values in an LDS
+// buffer.  For each kept L entry c in ascending column order every lane computes
+// l = a_rc / u_cc (the same operation, the same result); lane 0 keeps it.  The
+// U(c) entries are then taken 64 at a time, lane j finding its column in row r
+// by binary search and updating that entry -- each target is hit at most once per
+// c, so every entry sees the serial algorithm's updates in its order (Sec. III,
+// Fig. 1).  Updates that land on the diagonal (its own, and in the modified form
+// the ones whose target row r does not hold) are applied by lane 0 in U(c)'s
+// column order.
+template <bool SF>
+__device__ void factor_row_long(const FactorArgs &A, int r, int lane, double *rv) {
+    const int rs = A.rp[r], re = A.rp[r + 1], d = A.diag[r];
+    const int len = re - rs, dl = d - rs;
+    const double tr = A.use_tau ? A.row_tau[r] : 0.0;
+    for (int k = lane; k < len; k += 64) {
+        const int p = rs + k;
+        const bool absent = A.use_flev && A.flev[p] > A.k;
+        const int s = A.src[p];
+        rv[k] = (s >= 0 && !absent) ? A.a[s] : 0.0;
+    }
+    wave_sync_lds();
+    for (int e = 0; e < dl; ++e) {
+        const int p = rs + e;
+        if (A.use_flev && A.flev[p] > A.k) continue;   // absent L entry
+        const int c = A.ci[p];
+        const int dc = A.diag[c], ec = A.rp[c + 1];
+        double piv;
+        if constexpr (SF) piv = Pub<double>::wait(&A.lu[dc], A.info, A.poll_sleep);
+        else piv = A.lu[dc];
+        const double before = rv[e];
+        const double l = before / piv;
+        if (A.use_tau && fabs(l) < tr) {
+            if (lane == 0) {
+                rv[e] = __longlong_as_double((long long)kDropped64);
+                if (A.milu) rv[dl] = rv[dl] + before;
+            }
+            wave_sync_lds();
+            continue;
+        }
+        if (lane == 0) rv[e] = l;
+        for (int j0 = dc + 1; j0 < ec; j0 += 64) {
+            const int j = j0 + lane;
+            const bool act = j < ec;
+            int pos = -1;
+            bool kept = false;
+            double u = 0.0;
+            if (act) {
+                const bool uabs = A.use_flev && A.flev[j] > A.k;
+                if (!uabs) {
+                    if constexpr (SF) u = Pub<double>::wait(&A.lu[j], A.info, A.poll_sleep);
+                    else u = A.lu[j];
+                    kept = (uint64_t)__double_as_longlong(u) != kDropped64;
+                }
+                if (kept) {
+                    const int col = A.ci[j];
+                    int lo = rs, hi = re;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (A.ci[mid] < col) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    if (lo < re && A.ci[lo] == col && !(A.use_flev && A.flev[lo] > A.k)) pos = lo - rs;
+                }
+            }
+            const double prod = l * u;
+            if (pos >= 0 && pos != dl) rv[pos] = rv[pos] - prod;
+            // diagonal updates in column order
+            uint64_t dm = __ballot(kept && (pos == dl || (A.milu && pos < 0)));
+            while (dm) {
+                const int b = __builtin_ctzll(dm);
+                dm &= dm - 1;
+                const double q = __shfl(prod, b, 64);
+                if (lane == 0) rv[dl] = rv[dl] - q;
+            }
+        }
+        wave_sync_lds();
+    }
+    // U entries below the drop threshold at the end of the row, in column order
+    if (A.use_tau && lane == 0) {
+        for (int k = dl + 1; k < len; ++k) {
+            if (A.use_flev && A.flev[rs + k] > A.k) continue;
+            const double v = rv[k];
+            if (fabs(v) < tr) {
+                if (A.milu) rv[dl] = rv[dl] + v;
+                rv[k] = __longlong_as_double((long long)kDropped64);
+            }
+        }
+    }
+    wave_sync_lds();
+    const double pv = rv[dl];
+    bool bad = false;
+    for (int k = lane; k < len; k += 64) {
+        const int p = rs + k;
+        const bool absent = A.use_flev && A.flev[p] > A.k;
+        const double v = rv[k];
+        const uint64_t raw = (uint64_t)__double_as_longlong(v);
+        uint64_t bits;
+        if (absent) bits = 0;
+        else if (raw == kDropped64) bits = kDropped64;
+        else {
+            if (!isfinite(v)) bad = true;
+            bits = (v != v) ? kQNaN64 : raw;
+        }
+        if constexpr (SF) st_pub_u64(reinterpret_cast<uint64_t *>(&A.lu[p]), bits);
+        else A.lu[p] = __longlong_as_double((long long)bits);
+    }
+    const bool any_bad = __ballot(bad) != 0;
+    if (lane == 0) {
+        if (pv == 0.0) atomicMin(&A.info[kInfoBadKey], 2 * r);
+        else if (any_bad) atomicMin(&A.info[kInfoBadKey], 2 * r + 1);
+    }
+    wave_sync_lds();   // the buffer is reused by the wave's next row
+}
+
+template <bool SF>
+__global__ __launch_bounds__(kBlock) void k_factor_long(FactorArgs A) {
+    extern __shared__ double lds_f[];
+    const int lane = threadIdx.x & 63;
+    double *rv = lds_f + (size_t)(threadIdx.x >> 6) * A.lcap;
+    if constexpr (SF) {
+        claim_task(A.claims, A.nstreams, [&](int task) {
+            const int r = A.claims.task_ptr[task];
+            if (r < A.claims.task_ptr[task + 1]) factor_row_long<true>(A, r, lane, rv);
+        });
+    } else {
+        const int r = A.row_begin + (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
+        if (r < A.row_end) factor_row_long<false>(A, r, lane, rv);
+    }
+}
+
 // per-group LDS slices: [ngroups][tcap] doubles, then per group tcap + 2G ints
 template <int G>
 __device__ __forceinline__ void group_slices(int tcap, double *&sv, int *&sc, int *&soff, int *&sdc) {
@@ -1619,6 +1749,24 @@ hipError_t launch_factor(const FactorArgs &A, int lanes, bool syncfree, int grid
         case 64: return factor_dispatch<64>(A, syncfree, grid, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_factor_long(const FactorArgs &A, bool syncfree, int grid, hipStream_t s) {
+    const size_t lds = (size_t)(kBlock / 64) * A.lcap * 8;
+    if (A.lcap <= 0 || lds > (size_t)kFactorTileLdsMax) return hipErrorInvalidValue;
+    const void *fn = syncfree ? (const void *)k_factor_long<true> : (const void *)k_factor_long<false>;
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    if (syncfree) {
+        hipLaunchKernelGGL((k_factor_long<true>), dim3(grid), dim3(kBlock), lds, s, A);
+    } else {
+        const int64_t rows = A.row_end - A.row_begin;
+        if (rows <= 0) return hipSuccess;
+        hipLaunchKernelGGL((k_factor_long<false>), dim3(grid_for(rows * 64, kBlock)), dim3(kBlock), lds, s, A);
+    }
+    return hipGetLastError();
 }
 
 hipError_t probe_xcc_ids(int blocks, int32_t *host_ids) {

@@ -198,6 +198,43 @@ def random_banded(n: int, band: int = 8, rnd: int = 8, halfwidth: int = 64,
     return CSR(n, row_ptr, cols.ravel(), vals.ravel())
 
 
+def heavy_rows(n: int, light: int = 4, halfwidth: int = 16, heavy_frac: float = 0.01,
+               heavy_len: tuple = (256, 2048), rng: np.random.Generator | None = None) -> CSR:
+    """Irregular rows: every row couples to ``light`` distinct columns drawn uniformly
+    from [i-halfwidth, i+halfwidth] minus {i}; a fraction ``heavy_frac`` of the rows
+    (each row independently) also gets L ~ U[heavy_len] columns uniform over [0, n)
+    (repeats merged), the long rows of circuit-like matrices.  Off-diagonal values
+    N(0,1); diagonal 1.2 * sum |off| + 1 (strict row dominance)."""
+    rng = np.random.default_rng(0) if rng is None else rng
+    offsets = np.concatenate([np.arange(-halfwidth, 0), np.arange(1, halfwidth + 1)])
+    rows_i = np.arange(n, dtype=np.int64)
+    cand = rows_i[:, None] + offsets[None, :]
+    keys = rng.random(cand.shape, dtype=np.float32)
+    keys[(cand < 0) | (cand >= n)] = np.inf
+    k = min(light, 2 * halfwidth)
+    pick = np.argpartition(keys, k - 1, axis=1)[:, :k]
+    lc = np.take_along_axis(cand, pick, axis=1)
+    ok = np.isfinite(np.take_along_axis(keys, pick, axis=1))
+    r_parts = [np.repeat(rows_i, k)[ok.ravel()]]
+    c_parts = [lc.ravel()[ok.ravel()]]
+    heavy = np.flatnonzero(rng.random(n) < heavy_frac)
+    lens = rng.integers(heavy_len[0], heavy_len[1] + 1, size=heavy.size)
+    lens = np.minimum(lens, n - 1)
+    r_parts.append(np.repeat(heavy, lens))
+    c_parts.append(rng.integers(0, n, size=int(lens.sum()), dtype=np.int64))
+    r = np.concatenate(r_parts)
+    c = np.concatenate(c_parts)
+    off = r != c
+    key = np.unique(r[off] * n + c[off])
+    r, c = key // n, key % n
+    v = rng.standard_normal(r.size)
+    dsum = np.bincount(r, weights=np.abs(v), minlength=n)
+    r = np.concatenate([r, rows_i])
+    c = np.concatenate([c, rows_i])
+    v = np.concatenate([v, 1.2 * dsum + 1.0])
+    return csr_from_coo(n, r, c, v)
+
+
 # --------------------------------------------------------------------------------------
 # Variable-coefficient diffusion (finite volume) and its batch
 # --------------------------------------------------------------------------------------

@@ -134,6 +134,61 @@ def test_factor_modified_k_below_kmax(jv, staged):
         assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
 
 
+def _heavy(n, seed, lo=100, hi=400):
+    return synth.heavy_rows(n, heavy_len=(lo, hi), heavy_frac=0.02, rng=np.random.default_rng(seed))
+
+
+LONG_CASES = [
+    ("heavy_2000_ilu0", lambda: _heavy(2000, 3), 0, 0, 0.0, False, True),
+    ("heavy_2000_ilu0_tau_modified", lambda: _heavy(2000, 3), 0, 0, 1e-3, True, True),
+    ("heavy_2000_ilu1_k0", lambda: _heavy(2000, 4), 1, 0, 0.0, False, True),
+    ("heavy_2000_ilu1_tau", lambda: _heavy(2000, 4), 1, 1, 1e-3, False, True),
+    ("heavy_1500_lower_a_modified", lambda: _heavy(1500, 5, 300, 900), 0, 0, 0.0, True, False),
+]
+
+
+@pytest.mark.parametrize("sched", FACTOR_SCHEDS, ids=lambda s: s[0])
+@pytest.mark.parametrize("name,mk,kmax,k,tau,milu,sym", LONG_CASES, ids=[c[0] for c in LONG_CASES])
+def test_factor_long_rows_bit_exact(jv, name, mk, kmax, k, tau, milu, sym, sched):
+    # rows of more than 64 entries: one wave per row with the row in LDS; bit for
+    # bit the oracle's factor, then applies, spmv and FGMRES on it
+    A = mk()
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=kmax, sym=sym)
+    assert np.diff(an.lu_rp).max() > 64
+    ilu = make(jv, A, kmax, sym, sched)
+    f = O.factor(an, A.val, k=k, tau=tau, milu=milu)
+    assert f.status == O.OK
+    info = ilu.factor(dev(A.val), k=k, tau=tau, milu=milu)
+    lu, st = ilu.factor_values()
+    np.testing.assert_array_equal(st, f.stat)
+    assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64)), f"max diff {np.abs(lu - f.val).max()}"
+    assert info["n_dropped"] == int((f.stat == 1).sum())
+    b = synth.rhs(A.n, 2, np.random.default_rng(8))
+    x = ilu.apply(dev(b)).cpu().numpy()
+    assert relerr(x, O.apply(an, f.val, b)) <= 1e-12
+    y = ilu.spmv(dev(b)).cpu().numpy()
+    assert relerr(y, synth.csr_to_dense(A) @ b) <= 1e-12
+    _, si = ilu.gmres(dev(b[:, 0].copy()), rtol=1e-10, restart=30, prec="f64")
+    assert si["true_relres"] <= 1e-10
+
+
+def test_factor_rows_beyond_long_limit_unsupported(jv):
+    # one row of 5000 entries: beyond the long-row factor's LDS row buffer
+    n = 5000
+    A = synth.heavy_rows(n, heavy_frac=0.0, rng=np.random.default_rng(9))
+    rows = np.repeat(np.arange(n), np.diff(A.row_ptr))
+    keep = rows != 7
+    r = np.concatenate([rows[keep], np.full(n, 7)])
+    c = np.concatenate([A.col_idx[keep], np.arange(n)])
+    v = np.concatenate([A.val[keep], np.where(np.arange(n) == 7, float(n), 0.5)])
+    B = synth.csr_from_coo(n, r, c, v)
+    assert np.diff(B.row_ptr)[7] == n
+    ilu = jv.Ilu(B.n, B.row_ptr, B.col_idx)
+    with pytest.raises(jv.IluError) as e:
+        ilu.factor(dev(B.val))
+    assert e.value.status == "ILU_ERR_UNSUPPORTED"
+
+
 RCM_CASES = [
     ("random_banded_3000", lambda: synth.random_banded(3000, rng=np.random.default_rng(31)), 0, 0.0, True),
     ("convdiff3d_12_ilu1_tau", lambda: synth.convdiff3d(12), 1, 1e-3, True),
