@@ -8,6 +8,9 @@ random_1m      n = 1e6 random unsymmetric rows (8 banded + 8 scattered off-diago
 batch512       512 variable-coefficient 2D diffusion matrices in one block-diagonal
                handle: factor, FP32 apply of 4 right-hand sides each through a
                captured graph, FP64 forward + adjoint.
+heavy_1m       n = 1e6 irregular rows (4 local couplings per row, 1% of the rows with
+               256..2048 scattered entries): ILU(0) with the long-row factor, applies,
+               spmv (with its per-row-length split), FGMRES(30).
 ordering       natural vs reverse Cuthill-McKee preorder (both under the level
                ordering): levels, factor and apply times, Krylov iterations and time
                on the 128^3 Laplacian (as given and scrambled by a random symmetric
@@ -122,6 +125,56 @@ def run(args):
                    apply16_f64_us=round(1e3 * t64, 1), apply16_f64_gbs=round(B64["apply"] / t64 / 1e6, 1),
                    apply1_f64_us=round(1e3 * t1, 1),
                    us_per_level_apply1=round(1e3 * t1 / (info["n_levels"] + info["n_ulevels"]), 3))
+    elif wl == "heavy_1m":
+        A = synth.heavy_rows(1_000_000, rng=np.random.default_rng([6, 0]))
+        b = np.ascontiguousarray(synth.rhs(A.n, 1, np.random.default_rng([6, 1]))).reshape(-1)
+        t0 = time.perf_counter()
+        ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
+        t_an = time.perf_counter() - t0
+        ilu.set_schedule(args.sched, args.solve_sched)
+        info = ilu.info()
+        vals = _dev(A.val)
+        bd = _dev(b)
+        yd = torch.empty_like(bd)
+        ilu.profile(True, 1 << 16)
+        st = _stage_times(ilu, lambda: ilu.factor(vals, casts=()), 3)
+        pa = _stage_times(ilu, lambda: ilu.apply(bd), 5)
+        ps = _stage_times(ilu, lambda: ilu.spmv(bd, y=yd), 20)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, si = ilu.gmres(bd, rtol=1e-10, restart=30, prec="f64", raise_on_fail=False)
+        torch.cuda.synchronize()
+        t_k = time.perf_counter() - t1
+        nl = _nnz_l(ilu)
+        B = _bytes(A.n, info["nnz_lu"], nl, info["nnz_b"])
+        rl = np.diff(A.row_ptr)
+        out.update(n=A.n, nnz=A.nnz, max_row=int(rl.max()), rows_over_64=int((rl > 64).sum()),
+                   levels=info["n_levels"], ulevels=info["n_ulevels"], analyze_s=round(t_an, 2),
+                   factor_us=round(1e3 * st["factor"][0], 1),
+                   factor_gbs=round(B["factor"] / st["factor"][0] / 1e6, 1),
+                   apply_us=round(1e3 * (pa["forward"][0] + pa["backward"][0]), 1),
+                   spmv_us=round(1e3 * ps["spmv"][0], 1), spmv_gbs=round(B["spmv"] / ps["spmv"][0] / 1e6, 1),
+                   gmres30=dict(iters=si["iters"], seconds=round(t_k, 4), true_relres=si["true_relres"]))
+        # the same matrix under the reverse Cuthill-McKee preorder
+        del ilu
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx, ordering="rcm")
+        t_an = time.perf_counter() - t0
+        ilu.set_schedule(args.sched, args.solve_sched)
+        info = ilu.info()
+        ilu.profile(True, 1 << 16)
+        st = _stage_times(ilu, lambda: ilu.factor(vals, casts=()), 3)
+        pa = _stage_times(ilu, lambda: ilu.apply(bd), 5)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, si = ilu.gmres(bd, rtol=1e-10, restart=30, prec="f64", raise_on_fail=False)
+        torch.cuda.synchronize()
+        t_k = time.perf_counter() - t1
+        out["rcm"] = dict(levels=info["n_levels"], ulevels=info["n_ulevels"], analyze_s=round(t_an, 2),
+                          factor_us=round(1e3 * st["factor"][0], 1),
+                          apply_us=round(1e3 * (pa["forward"][0] + pa["backward"][0]), 1),
+                          gmres30=dict(iters=si["iters"], seconds=round(t_k, 4), true_relres=si["true_relres"]))
     elif wl == "ordering":
         rows = []
 

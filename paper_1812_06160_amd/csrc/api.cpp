@@ -442,10 +442,28 @@ static ilu_status finish_analysis(ilu_handle_s *h) {
         tcap = std::max(tcap, t);
     }
     h->factor_tcap = (int32_t)std::min<int64_t>(tcap, 1 << 20);
-#undef UPLOAD_ONE
     h->lanes_factor = pow2_lanes(H.max_row_lu, 4, 64);
     h->lanes_solve = pow2_lanes(std::max(H.max_lower_lu, H.max_upper_lu), 4, 64);
-    h->lanes_spmv = pow2_lanes(std::max(1, (int)((H.b_rp[H.n] + H.n - 1) / H.n)), 4, 64);
+    // spmv: rows longer than one wave go to a one-wave-per-row pass; the lanes of the
+    // rest follow their mean length
+    {
+        constexpr int32_t kHeavy = 64;
+        std::vector<int32_t> heavy;
+        int64_t light_nnz = 0;
+        for (int32_t r = 0; r < H.n; ++r) {
+            const int32_t len = H.b_rp[r + 1] - H.b_rp[r];
+            if (len > kHeavy) heavy.push_back(r);
+            else light_nnz += len;
+        }
+        const int64_t light_rows = std::max<int64_t>(1, H.n - (int64_t)heavy.size());
+        h->lanes_spmv = pow2_lanes((int)std::max<int64_t>(1, (light_nnz + light_rows - 1) / light_rows), 4, 64);
+        if (!heavy.empty()) {
+            UPLOAD_ONE(h->d_spmv_heavy, heavy);
+            h->n_spmv_heavy = (int32_t)heavy.size();
+            h->spmv_heavy_min = kHeavy;
+        }
+    }
+#undef UPLOAD_ONE
     return ILU_OK;
 }
 
@@ -1038,6 +1056,9 @@ extern "C" ilu_status ilu_spmv(ilu_handle h, double alpha, const double *x, doub
     A.beta = beta;
     A.ld = ld;
     A.nrhs = nrhs;
+    A.heavy_min = h->spmv_heavy_min;
+    A.heavy = h->d_spmv_heavy;
+    A.nheavy = h->n_spmv_heavy;
     h->prof.begin(ILU_STAGE_SPMV, s);
     hipError_t e = launch_spmv(A, h->lanes_spmv, s);
     h->prof.end(s);

@@ -165,6 +165,11 @@ struct SpmvArgs {
     double alpha, beta;
     int64_t ld;
     int32_t nrhs;
+    // rows with more than heavy_min entries are left to a second pass with one wave
+    // per row over the list heavy[0 .. nheavy) (load balance for long rows)
+    int32_t heavy_min;
+    const int32_t *heavy;
+    int32_t nheavy;
 };
 
 // launchers (kernels.hip); all return hipError_t of the launch

@@ -1572,6 +1572,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs A) {
     const int t = threadIdx.x % G;
     if (r >= A.n) return;
     const int rs = A.rp[r], re = A.rp[r + 1];
+    if (re - rs > A.heavy_min) return;   // a long row: the one-wave pass takes it
     const int yr = PERM ? A.perm[r] : r;
     for (int s = 0; s < A.nrhs; ++s) {
         double acc = 0.0;
@@ -1989,15 +1990,50 @@ static hipError_t spmv_dispatch(const SpmvArgs &A, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Long rows of the spmv: one wave per listed row, lanes striding over its entries,
+// the wave's partial sums added by the butterfly.
+template <bool PERM>
+__global__ __launch_bounds__(kBlock) void k_spmv_heavy(SpmvArgs A) {
+    const int w = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (w >= A.nheavy) return;
+    const int r = A.heavy[w];
+    const int rs = A.rp[r], re = A.rp[r + 1];
+    const int yr = PERM ? A.perm[r] : r;
+    for (int s = 0; s < A.nrhs; ++s) {
+        double acc = 0.0;
+        for (int p = rs + lane; p < re; p += 64) {
+            const int c = PERM ? A.perm[A.ci[p]] : A.ci[p];
+            const double prod = A.val[p] * A.x[(int64_t)c * A.ld + s];
+            acc = acc + prod;
+        }
+        acc = group_sum<64>(acc);
+        if (lane == 0) {
+            double out = A.alpha * acc;
+            if (A.beta != 0.0) {
+                const double by = A.beta * A.y[(int64_t)yr * A.ld + s];
+                out = out + by;
+            }
+            A.y[(int64_t)yr * A.ld + s] = out;
+        }
+    }
+}
+
 hipError_t launch_spmv(const SpmvArgs &A, int lanes, hipStream_t s) {
+    hipError_t e;
     switch (lanes) {
-        case 4: return spmv_dispatch<4>(A, s);
-        case 8: return spmv_dispatch<8>(A, s);
-        case 16: return spmv_dispatch<16>(A, s);
-        case 32: return spmv_dispatch<32>(A, s);
-        case 64: return spmv_dispatch<64>(A, s);
+        case 4: e = spmv_dispatch<4>(A, s); break;
+        case 8: e = spmv_dispatch<8>(A, s); break;
+        case 16: e = spmv_dispatch<16>(A, s); break;
+        case 32: e = spmv_dispatch<32>(A, s); break;
+        case 64: e = spmv_dispatch<64>(A, s); break;
         default: return hipErrorInvalidValue;
     }
+    if (e != hipSuccess || A.nheavy <= 0) return e;
+    dim3 g(grid_for((int64_t)A.nheavy * 64, kBlock));
+    if (A.perm) hipLaunchKernelGGL((k_spmv_heavy<true>), g, dim3(kBlock), 0, s, A);
+    else hipLaunchKernelGGL((k_spmv_heavy<false>), g, dim3(kBlock), 0, s, A);
+    return hipGetLastError();
 }
 
 }  // namespace jv
