@@ -1894,6 +1894,9 @@ static hipError_t tiled_lanes(const SolveArgs &A, const TileArgs &T, bool fwd, h
         return tiled_launch<1, kTileShortRow, NR, TV, TA>(A, T, fwd, s);
     }
     if (T.unit == 16) {
+        // entries per lane: as few as the tiling's longest row needs
+        if (T.kmax <= 4) return tiled_launch<4, 1, NR, TV, TA>(A, T, fwd, s);
+        if (T.kmax <= 8) return tiled_launch<4, 2, NR, TV, TA>(A, T, fwd, s);
         if (T.kmax > 4 * kTileLongJ) return hipErrorInvalidValue;
         return tiled_launch<4, kTileLongJ, NR, TV, TA>(A, T, fwd, s);
     }
