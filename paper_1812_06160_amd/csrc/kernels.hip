@@ -1168,7 +1168,9 @@ __device__ __forceinline__ void tile_compute(const SolveArgs &A, typename Pub<TA
                 const TA sum = group_sum<G>(acc);
                 if (k < nr && (k % G) == t) {
                     TA v = cur.rhs[k] - sum;
-                    if (!A.unit_diag) v = v / cur.pv;
+                    // forward: L has a unit diagonal; backward: multiply by the
+                    // reciprocal of u_rr taken at staging, off the dependency chain
+                    if constexpr (!FWD) v = v * cur.pv;
                     lds_st<TA>(vals + cur.sl * NR + k, bits_of<TA>(v));
                     tile_store<TA, FWD>(A, cur.r, orows[cur.sl], s0 + k, v);
                 }
@@ -1247,7 +1249,7 @@ __global__ __launch_bounds__(kTileBlock) void k_solve_tiled(SolveArgs A, TileArg
             if (sl >= nrows) continue;
             if (t == 0) {
                 rowid[sl] = mt[u].x;
-                piv[sl] = pv[u];
+                piv[sl] = FWD ? pv[u] : (TA)1 / pv[u];
                 if constexpr (!FWD) orows[sl] = mt[u].x;
             }
 #pragma unroll
