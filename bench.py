@@ -36,11 +36,11 @@ HBM_PEAK_GBS = 8000.0
 # scaled by what the same counters read for the calibration copy kernels.  Valid
 # only for the kernel source it was taken with: a different hash reports null.
 PMC_TRAFFIC = dict(
-    kernels_sha256="009d02652b0d6ca1c0f04fccb71571f9a4275d5c010e25759983feb3192e2532",
-    fetch_scale=1.9986, write_scale=0.9941,
-    forward=dict(f64=(187231, 66199), f32=(155425, 51145)),
-    backward=dict(f64=(189242, 93897), f32=(149264, 78569)),
-    factor=(279327, 146456),
+    kernels_sha256="a27aa9c2473984918edae9818db43e908645b6a239f612db14faedc2d9874461",
+    fetch_scale=1.9986, write_scale=0.9944,
+    forward=dict(f64=(189241, 65777), f32=(157539, 50714)),
+    backward=dict(f64=(190276, 92815), f32=(151550, 77799)),
+    factor=(279953, 146456),
 )
 
 
