@@ -27,6 +27,21 @@
 #define ORC_ERR_NOCONV 7
 #define ORC_ERR_BREAKDOWN 8
 
+/* qsort comparators: ints ascending; (key, tag) pairs by key then tag.       */
+static int cmp_int(const void *a, const void *b) {
+    int x = *(const int *)a, y = *(const int *)b;
+    return (x > y) - (x < y);
+}
+typedef struct {
+    long key;
+    long tag;
+} orc_pair;
+static int cmp_pair(const void *a, const void *b) {
+    const orc_pair *x = (const orc_pair *)a, *y = (const orc_pair *)b;
+    if (x->key != y->key) return (x->key > y->key) - (x->key < y->key);
+    return (x->tag > y->tag) - (x->tag < y->tag);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Canonical CSR.  The method takes A in conventional CSR (Sec. I, Sec. II    */
 /* "Sparse matrix-vector multiplication and triangular solve").  Columns must */
@@ -264,7 +279,8 @@ int orc_rcm(int n, const int *rp, const int *ci, int *order) {
     int *visited = (int *)calloc((size_t)n + 1, sizeof(int));
     int *queue = (int *)malloc(sizeof(int) * ((size_t)n + 1));
     int *cm = (int *)malloc(sizeof(int) * ((size_t)n + 1));
-    if (!ap || !cnt || !deg || !mark || !visited || !queue || !cm) return ORC_ERR_NOMEM;
+    orc_pair *kids = (orc_pair *)malloc(sizeof(orc_pair) * ((size_t)n + 1));
+    if (!ap || !cnt || !deg || !mark || !visited || !queue || !cm || !kids) return ORC_ERR_NOMEM;
     /* adjacency of A + A^T without the diagonal: both directions of every entry */
     for (int i = 0; i < n; ++i)
         for (int p = rp[i]; p < rp[i + 1]; ++p)
@@ -282,18 +298,11 @@ int orc_rcm(int n, const int *rp, const int *ci, int *order) {
                 aj[mark[i]++] = ci[p];
                 aj[mark[ci[p]]++] = i;
             }
-    /* sort each row (insertion sort) and squeeze out repeated neighbours */
+    /* sort each row and squeeze out repeated neighbours */
     ap[0] = 0;
     for (int i = 0; i < n; ++i) {
         int lo = cnt[i], hi = cnt[i + 1];
-        for (int a = lo + 1; a < hi; ++a) {
-            int v = aj[a], b = a;
-            while (b > lo && aj[b - 1] > v) {
-                aj[b] = aj[b - 1];
-                --b;
-            }
-            aj[b] = v;
-        }
+        qsort(aj + lo, (size_t)(hi - lo), sizeof(int), cmp_int);
         int len = 0;
         for (int a = lo; a < hi; ++a)
             if (len == 0 || aj[ap[i] + len - 1] != aj[a]) aj[ap[i] + len++] = aj[a];
@@ -331,18 +340,17 @@ int orc_rcm(int n, const int *rp, const int *ci, int *order) {
         visited[r] = 1;
         while (head < ncm) {
             int u = cm[head++];
-            int first = ncm;
+            int nk = 0;
             for (int p = ap[u]; p < ap[u + 1]; ++p) {
                 int w = aj[p];
                 if (visited[w]) continue;
                 visited[w] = 1;
-                int b = ncm++;
-                while (b > first && rcm_less(deg, w, cm[b - 1])) {
-                    cm[b] = cm[b - 1];
-                    --b;
-                }
-                cm[b] = w;
+                kids[nk].key = (long)deg[w] * n + w;   /* (degree, index) order */
+                kids[nk].tag = w;
+                ++nk;
             }
+            qsort(kids, (size_t)nk, sizeof(orc_pair), cmp_pair);
+            for (int k = 0; k < nk; ++k) cm[ncm++] = (int)kids[k].tag;
         }
     }
     /* reverse */
@@ -354,6 +362,7 @@ int orc_rcm(int n, const int *rp, const int *ci, int *order) {
     free(visited);
     free(queue);
     free(cm);
+    free(kids);
     free(aj);
     return ORC_OK;
 }
@@ -362,7 +371,7 @@ int orc_rcm(int n, const int *rp, const int *ci, int *order) {
 /* Symmetric permutation P S P^T of a pattern with an integer tag per entry  */
 /* (Sec. III: A is copied into the CSR of L and U in level order).  Row r of */
 /* the result is the original row perm[r] with each column j renamed         */
-/* iperm[j], sorted ascending (insertion sort).  src[p] is the index of the */
+/* iperm[j], sorted ascending (qsort).          src[p] is the index of the */
 /* source entry; diag_pos[r] is the position of column r (or -1).            */
 /* ------------------------------------------------------------------------ */
 void orc_permute(int n, const int *rp, const int *ci, const int *perm, const int *iperm,
@@ -373,26 +382,28 @@ void orc_permute(int n, const int *rp, const int *ci, const int *perm, const int
         int len = rp[i + 1] - rp[i];
         prp[r + 1] = prp[r] + len;
     }
+    int maxlen = 0;
+    for (int i = 0; i < n; ++i)
+        if (rp[i + 1] - rp[i] > maxlen) maxlen = rp[i + 1] - rp[i];
+    orc_pair *row = (orc_pair *)malloc(sizeof(orc_pair) * ((size_t)maxlen + 1));
     for (int r = 0; r < n; ++r) {
         int i = perm[r];
         int base = prp[r];
-        int len = 0;
+        int len = rp[i + 1] - rp[i];
         for (int p = rp[i]; p < rp[i + 1]; ++p) {
-            int c = iperm[ci[p]];
-            int t = base + len;
-            while (t > base && pci[t - 1] > c) {
-                pci[t] = pci[t - 1];
-                src[t] = src[t - 1];
-                --t;
-            }
-            pci[t] = c;
-            src[t] = p;
-            ++len;
+            row[p - rp[i]].key = iperm[ci[p]];
+            row[p - rp[i]].tag = p;
+        }
+        qsort(row, (size_t)len, sizeof(orc_pair), cmp_pair);
+        for (int k = 0; k < len; ++k) {
+            pci[base + k] = (int)row[k].key;
+            src[base + k] = row[k].tag;
         }
         diag_pos[r] = -1;
         for (int p = base; p < base + len; ++p)
             if (pci[p] == r) diag_pos[r] = p;
     }
+    free(row);
 }
 
 /* Values of A placed on the pattern S (both canonical and sorted by row):   */
