@@ -1,6 +1,8 @@
-"""Full-size GPU parity in the launch configuration bench.py times (sync-free
-schedule, default lanes): the whole factor against the oracle bit for bit and
-whole solves against the oracle, on the BASELINE workloads."""
+"""Full-size GPU parity in the launch configuration bench.py times (the default
+schedules -- tiled where they apply -- and default lanes): the whole factor against
+the oracle bit for bit and whole solves against the oracle, on the full-size
+workloads, and the modified factor, the RCM preorder and the long-row factor at
+full size."""
 import numpy as np
 import pytest
 import torch
@@ -90,3 +92,59 @@ def test_batch512_full(jv):
         assert relerr(x[ro[i]:ro[i + 1]], O.apply(an, f.val, rhs[i])) <= 1e-12
         xr32 = O.apply(an, O.cast_f32(f.val), rhs[i].astype(np.float32).astype(np.float64), prec="f32")
         assert relerr(x32[ro[i]:ro[i + 1]], xr32) <= 2.0 ** -12
+
+
+def test_laplace3d_128_modified_full(jv):
+    # modified ILU(0) at full size: bit-exact with the oracle, and since L U has A's
+    # row sums, M^{-1} (A 1) is the vector of ones up to rounding
+    A, b = synth.workload(2)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
+    ilu.factor(dev(A.val), casts=(), milu=True)
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    f = O.factor(an, A.val, milu=True)
+    lu, _ = ilu.factor_values()
+    assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
+    ones = torch.ones(A.n, dtype=torch.float64, device="cuda")
+    x = ilu.apply(ilu.spmv(ones)).cpu().numpy()
+    assert np.abs(x - 1.0).max() <= 1e-9
+    _, info = ilu.pcg(dev(b), rtol=1e-10)
+    assert info["true_relres"] <= 1e-10 and info["iters"] < 120
+
+
+def test_random_1m_rcm_full(jv):
+    # the reverse Cuthill-McKee preorder at full size: the library's permutation and
+    # factor equal the oracle's composed analysis; FGMRES converges in the input ordering
+    A, B = synth.workload(4)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx, ordering="rcm")
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, rcm_order=True)
+    s = ilu.schedule()
+    np.testing.assert_array_equal(s["perm"], an.perm)
+    np.testing.assert_array_equal(s["level_ptr"], an.level_ptr)
+    ilu.factor(dev(A.val), casts=())
+    f = O.factor(an, A.val)
+    lu, _ = ilu.factor_values()
+    assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
+    b = np.ascontiguousarray(B[:, 3])
+    x = ilu.apply(dev(b)).cpu().numpy()
+    assert relerr(x, O.apply(an, f.val, b)) <= 1e-12
+    _, info = ilu.gmres(dev(b), rtol=1e-10, restart=30)
+    assert info["true_relres"] <= 1e-10
+
+
+def test_heavy_1m_long_rows_full(jv):
+    # 10^6 irregular rows, 1% of them with 256..2048 entries: the long-row factor bit
+    # for bit, the applies and the split spmv against the oracle
+    A = synth.heavy_rows(1_000_000, rng=np.random.default_rng([6, 0]))
+    b = np.ascontiguousarray(synth.rhs(A.n, 1, np.random.default_rng([6, 1]))).reshape(-1)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx, ordering="rcm")
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, rcm_order=True)
+    assert np.diff(an.lu_rp).max() > 64
+    ilu.factor(dev(A.val), casts=())
+    f = O.factor(an, A.val)
+    lu, _ = ilu.factor_values()
+    assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
+    x = ilu.apply(dev(b)).cpu().numpy()
+    assert relerr(x, O.apply(an, f.val, b)) <= 1e-12
+    y = ilu.spmv(dev(b)).cpu().numpy()
+    yr = O.spmv(A.n, A.row_ptr, A.col_idx, A.val, b)
+    assert relerr(y, yr) <= 1e-12
