@@ -86,8 +86,10 @@ void build_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, TileSet 
 // Data of the tiled factor on the forward tiles.  LDS of a tile: the value area
 // (the tile's rows' entries in slot order, then the U parts -- diagonal first -- of
 // its imports) and one ready flag per tile row and per import.  Per tile row:
-// meta (row, first entry, end entry, diagonal entry) and (value-area offset,
-// offset of its first L entry among the tile's L entries).  Per L entry
+// meta (row, first entry, end entry, diagonal entry; the row is stored as ~row
+// when its L entries never update one another, so that its multipliers are
+// independent) and (value-area offset, offset of its first L entry among the
+// tile's L entries).  Per L entry
 // (r, c) in tile order: the value-area location of U(c)'s diagonal, the ready
 // flag of c, and for each lane t < lanes the index j >= 1 in U(c) of the column
 // of entry t of row r (-1 if that column is not in U(c)).  Per import: the factor

@@ -1520,14 +1520,29 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
         const int4 m = meta[sl];
         const int2 o = off[sl];
         const int len = m.z - m.y, K = m.w - m.y;
+        const bool flat = m.x < 0;             // L entries independent of one another
+        const int row = flat ? ~m.x : m.x;
         const bool act = t < len;
         double v = act ? vals[o.x + t] : 0.0;
+        if (flat) {
+            // every multiplier at once: lane t < K waits for its own dependency and
+            // divides; the updates below then only reach U entries
+            if (t < K) {
+                const int li = o.y + t;
+                const int ok = lds_wait_flag(&flags[dflag[li]], &s_abort, A.info);
+                const double piv = ok ? vals[dloc[li]] : __longlong_as_double((long long)kQNaN64);
+                v = v / piv;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
         for (int e = 0; e < K; ++e) {
             const int li = o.y + e;
             const int loc = dloc[li];
-            const int ok = lds_wait_flag(&flags[dflag[li]], &s_abort, A.info);
-            const double piv = ok ? vals[loc] : __longlong_as_double((long long)kQNaN64);
-            if (t == e) v = v / piv;
+            if (!flat) {
+                const int ok = lds_wait_flag(&flags[dflag[li]], &s_abort, A.info);
+                const double piv = ok ? vals[loc] : __longlong_as_double((long long)kQNaN64);
+                if (t == e) v = v / piv;
+            }
             const double l = __shfl(v, e, G);
             if (A.milu && t == K) {
                 // modified ILU: the diagonal takes its own update and every update
@@ -1553,8 +1568,8 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
         const bool nonfinite = act && !isfinite(v);
         const uint64_t nfm = group_bits<G>(__ballot(nonfinite), gi);
         if (t == 0) {
-            if (pv == 0.0) atomicMin(&A.info[kInfoBadKey], 2 * m.x);
-            else if (nfm) atomicMin(&A.info[kInfoBadKey], 2 * m.x + 1);
+            if (pv == 0.0) atomicMin(&A.info[kInfoBadKey], 2 * row);
+            else if (nfm) atomicMin(&A.info[kInfoBadKey], 2 * row + 1);
         }
         if (act) {
             vals[o.x + t] = v;

@@ -212,6 +212,7 @@ void build_factor_tiles(const HostAnalysis &H, const TileSet &T, int32_t lanes, 
         // L entries
         for (int32_t q = r0; q < r1; ++q) {
             const int32_t r = T.rows[q];
+            const size_t lfirst = F->dloc.size();
             for (int32_t p = rp[r]; p < dg[r]; ++p) {
                 const int32_t c = ci[p];
                 if (slot_of[c] >= 0) {
@@ -241,6 +242,18 @@ void build_factor_tiles(const HostAnalysis &H, const TileSet &T, int32_t lanes, 
                 }
                 F->cmask.push_back(cm);
             }
+            // a row whose L entries never update one another (no L entry's column
+            // lies in U(c) of an earlier L entry c) has independent multipliers:
+            // its row id is stored complemented to say so
+            const int32_t nl = dg[r] - rp[r];
+            bool flat = true;
+            for (int32_t e1 = 0; e1 < nl && flat; ++e1)
+                for (int32_t e2 = e1 + 1; e2 < nl; ++e2)
+                    if (F->match[(lfirst + e1) * lanes + e2] > 0) {
+                        flat = false;
+                        break;
+                    }
+            if (flat) F->meta[4 * (size_t)q] = ~r;
         }
         F->lptr.push_back((int32_t)F->dloc.size());
         for (int32_t q = r0; q < r1; ++q) slot_of[T.rows[q]] = -1;
