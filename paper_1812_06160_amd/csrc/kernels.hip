@@ -1893,8 +1893,17 @@ template <int G, int J, int NR, typename TV, typename TA>
 static hipError_t tiled_launch(const SolveArgs &A, const TileArgs &T0, bool fwd, hipStream_t s) {
     TileArgs T = T0;
     const size_t lds = tile_layout(T, NR, sizeof(TA), &T);
-    if (lds > (size_t)kTileLdsMax || T.max_slots + 1 > 65535 || T.max_pos > 32767) return hipErrorInvalidValue;
+    // one right-hand side per pass keeps to 64 KB (three blocks per CU); several
+    // per pass may take the whole LDS of a CU
+    const size_t cap = NR == 1 ? (size_t)kTileLdsMax : (size_t)kFactorTileLdsMax;
+    if (lds > cap || T.max_slots + 1 > 65535 || T.max_pos > 32767) return hipErrorInvalidValue;
     if (T.ntiles <= 0) return hipSuccess;
+    if (lds > 65536) {
+        const void *fn = fwd ? (const void *)k_solve_tiled<G, J, NR, TV, TA, true>
+                             : (const void *)k_solve_tiled<G, J, NR, TV, TA, false>;
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
     if (fwd)
         hipLaunchKernelGGL((k_solve_tiled<G, J, NR, TV, TA, true>), dim3(T.ntiles), dim3(kTileBlock), lds, s, A, T);
     else
@@ -1922,7 +1931,7 @@ static hipError_t tiled_lanes(const SolveArgs &A, const TileArgs &T, bool fwd, h
 
 template <typename TV, typename TA>
 static hipError_t tiled_dispatch(const SolveArgs &A, const TileArgs &T, bool fwd, hipStream_t s) {
-    if (A.nrhs > 1 && tile_layout(T, 4, sizeof(TA), nullptr) <= (size_t)kTileLdsMax)
+    if (A.nrhs > 1 && tile_layout(T, 4, sizeof(TA), nullptr) <= (size_t)kFactorTileLdsMax)
         return tiled_lanes<4, TV, TA>(A, T, fwd, s);
     return tiled_lanes<1, TV, TA>(A, T, fwd, s);
 }
