@@ -210,8 +210,8 @@ enum {
  * an update l_rc * u_cj whose target (r, j) is not a kept entry is subtracted
  * from u_rr, a dropped multiplier adds back its value before the division, a
  * dropped U entry adds back its value (ascending column) -- so the row sums of
- * L*U equal those of A.  The tiled factor covers the modified form of plain
- * ILU(k) too; with tau > 0 or k < k_max it runs sync-free (or level launches).
+ * L*U equal those of A.  The tiled factor covers the modified form too; with
+ * k < k_max it runs sync-free (or level launches).
  * Also loads the values of the permuted copy of A used by ilu_spmv.
  * Synchronises `stream` to read the status word.  info may be NULL.
  * Errors: ILU_ERR_STATE, ILU_ERR_ARG (k > k_max, tau < 0 or NaN, unknown flag
@@ -309,8 +309,8 @@ ilu_status ilu_solve_gmres(ilu_handle h, const double *b, double *x, double rtol
 
 /* Chooses the launch scheme of the factor and of the solves (ILU_SCHED_*) and the
  * lanes per row (0 = automatic from the longest row; else 4, 8, 16, 32 or 64;
- * factor lanes must cover the longest factor row).  The tiled factor runs ILU(k)
- * and modified ILU(k) with k = k_max, tau = 0 and rows of at most 16 entries;
+ * factor lanes must cover the longest factor row).  The tiled factor runs ILU(k,
+ * tau) and modified ILU(k, tau) with k = k_max and rows of at most 16 entries;
  * otherwise the call runs the sync-free factor.  A solve direction whose rows have
  * more than 32 dependencies runs sync-free under the tiled schedule.  Factor rows
  * longer than 64 entries (up to 4096) run with one wave per row and the row in

@@ -83,6 +83,10 @@ struct TileSet {
 void build_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, TileSet *fwd, TileSet *bwd,
                  std::vector<int32_t> *sci);
 
+// Forward tiles only (a tiling of its own for the factor when the solves' tiles
+// are too large for its LDS image).
+void build_forward_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, TileSet *fwd);
+
 // Data of the tiled factor on the forward tiles.  LDS of a tile: the value area
 // (the tile's rows' entries in slot order, then the U parts -- diagonal first -- of
 // its imports) and one ready flag per tile row and per import.  Per tile row:

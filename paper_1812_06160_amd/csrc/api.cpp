@@ -243,6 +243,16 @@ static bool tiles_fit(const TileSet &T) {
            T.max_slots + 1 <= 65535 && T.max_pos <= 32767 && tile_rows_ok(T);
 }
 
+// LDS slot of every position of a tiling (-1 for padding)
+static std::vector<int16_t> position_slots(const TileSet &T) {
+    std::vector<int16_t> pslot(T.row.size());
+    for (int32_t t = 0; t < T.ntiles; ++t) {
+        int32_t k = 0;
+        for (int32_t q = T.ptr[t]; q < T.ptr[t + 1]; ++q) pslot[q] = (int16_t)(T.row[q] >= 0 ? k++ : -1);
+    }
+    return pslot;
+}
+
 ilu_status ilu_handle_s::make_tiles(int32_t rows, bool shrink) {
     try {
         for (;;) {
@@ -254,7 +264,7 @@ ilu_status ilu_handle_s::make_tiles(int32_t rows, bool shrink) {
         return fail(ILU_ERR_NOMEM, "tiles: out of host memory");
     }
     tile_rows = rows;
-    if (host_only) return ILU_OK;
+    if (host_only) return make_factor_tiles();
     auto drop = [&](int32_t *&d) {
         if (d) {
             (void)hipFree(d);
@@ -279,11 +289,7 @@ ilu_status ilu_handle_s::make_tiles(int32_t rows, bool shrink) {
     if (e != hipSuccess) return hip_fail(e, "tiles: synchronize");
     for (int dir = 0; dir < 2; ++dir) {
         const TileSet &T = tiles[dir];
-        std::vector<int16_t> pslot(T.row.size());
-        for (int32_t t = 0; t < T.ntiles; ++t) {
-            int32_t k = 0;
-            for (int32_t q = T.ptr[t]; q < T.ptr[t + 1]; ++q) pslot[q] = (int16_t)(T.row[q] >= 0 ? k++ : -1);
-        }
+        const std::vector<int16_t> pslot = position_slots(T);
         std::vector<int32_t> meta(T.rows.size() * 4);
         for (size_t i = 0; i < T.rows.size(); ++i) {
             const int32_t r = T.rows[i], d = H.diag[r];
@@ -309,20 +315,31 @@ ilu_status ilu_handle_s::make_tiles(int32_t rows, bool shrink) {
 // entries and a tile image that fits LDS (the modified form's masks included).
 ilu_status ilu_handle_s::make_factor_tiles() {
     ftiles_ok = false;
+    ftset_own = false;
     if (H.max_row_lu > kFactorMaxLanes || tiles[0].ntiles == 0) return ILU_OK;
     const int32_t lanes = H.max_row_lu <= 8 ? 8 : 16;
+    auto fits = [&](const TileSet &S) {
+        build_factor_tiles(H, S, lanes, &ftiles);
+        FactorTileArgs T{};
+        T.max_rows = S.max_rows;
+        T.max_vals = ftiles.max_vals;
+        T.max_lents = ftiles.max_lents;
+        T.max_pos = S.max_pos;
+        T.max_imps = S.max_imps;
+        return factor_tile_lds_bytes(T, lanes, true) <= (size_t)kFactorTileLdsMax;
+    };
     try {
-        build_factor_tiles(H, tiles[0], lanes, &ftiles);
+        bool ok = fits(tiles[0]);
+        // too large an LDS image: a forward tiling of its own, halving the tile size
+        for (int32_t rows = tile_rows / 2; !ok && rows >= 16; rows /= 2) {
+            build_forward_tiles(H, rows, kTileShortRow, &ftset);
+            ok = fits(ftset);
+            ftset_own = ok;
+        }
+        if (!ok) return ILU_OK;
     } catch (const std::bad_alloc &) {
         return fail(ILU_ERR_NOMEM, "factor tiles: out of host memory");
     }
-    FactorTileArgs T{};
-    T.max_rows = tiles[0].max_rows;
-    T.max_vals = ftiles.max_vals;
-    T.max_lents = ftiles.max_lents;
-    T.max_pos = tiles[0].max_pos;
-    T.max_imps = tiles[0].max_imps;
-    if (factor_tile_lds_bytes(T, lanes, true) > (size_t)kFactorTileLdsMax) return ILU_OK;
     if (host_only) {
         ftiles_ok = true;
         return ILU_OK;
@@ -346,6 +363,11 @@ ilu_status ilu_handle_s::make_factor_tiles() {
         (e = put(dft.dflag, ftiles.dflag)) != hipSuccess || (e = put(dft.match, ftiles.match)) != hipSuccess ||
         (e = put(dft.imp, ftiles.imp)) != hipSuccess || (e = put(dft.cmask, ftiles.cmask)) != hipSuccess)
         return hip_fail(e, "factor tiles: upload");
+    if (ftset_own) {
+        if ((e = put(dftset.pslot, position_slots(ftset))) != hipSuccess || (e = put(dftset.ptr, ftset.ptr)) != hipSuccess ||
+            (e = put(dftset.rows_ptr, ftset.rows_ptr)) != hipSuccess || (e = put(dftset.imp_ptr, ftset.imp_ptr)) != hipSuccess)
+            return hip_fail(e, "factor tiles: upload");
+    }
     ftiles_ok = true;
     return ILU_OK;
 }
@@ -654,12 +676,12 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
     A.tcap = (h->factor_staged && factor_lds_bytes(lanes, h->factor_tcap)) ? h->factor_tcap : 0;
     A.max_lower = H.max_lower_lu;
     A.lcap = long_rows ? H.max_row_lu : 0;
-    // the tiled factor covers plain ILU (every pattern entry kept, no dropping);
-    // anything else runs the sync-free factor
-    bool tiled = h->sched_factor == ILU_SCHED_TILED && h->ftiles_ok && !use_tau && !A.use_flev;
+    // the tiled factor covers ILU(k, tau), plain or modified, at k = k_max (no
+    // absent entries); anything else runs the sync-free factor
+    bool tiled = h->sched_factor == ILU_SCHED_TILED && h->ftiles_ok && !A.use_flev;
     if (tiled) {
-        const TileSet &T0 = h->tiles[0];
-        const ilu_handle_s::DevTiles &D = h->dtiles[0];
+        const TileSet &T0 = h->ftset_own ? h->ftset : h->tiles[0];
+        const ilu_handle_s::DevTiles &D = h->ftset_own ? h->dftset : h->dtiles[0];
         FactorTileArgs T{};
         T.tile_ptr = D.ptr;
         T.pslot = D.pslot;

@@ -94,6 +94,11 @@ struct ilu_handle_s {
     // tiled factor (plain ILU) on the forward tiles
     jv::FactorTiles ftiles;
     bool ftiles_ok = false;            // built and fits LDS
+    // the factor's own forward tiling, when the solves' tiles make too large an LDS
+    // image for it (ftset_own); otherwise the factor uses tiles[0] / dtiles[0]
+    jv::TileSet ftset;
+    bool ftset_own = false;
+    DevTiles dftset;
     struct DevFactorTiles {
         int32_t *meta = nullptr, *off = nullptr, *lptr = nullptr, *dloc = nullptr, *dflag = nullptr,
                 *imp = nullptr;

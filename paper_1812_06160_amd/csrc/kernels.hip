@@ -1345,7 +1345,8 @@ __global__ __launch_bounds__(kTileBlock) void k_solve_tiled(SolveArgs A, TileArg
 }
 
 // ---------------------------------------------------------------------------------
-// Tiled factor (plain ILU on the forward tiles): rows and imported U rows in LDS
+// Tiled factor (ILU(k, tau) at k = k_max on the forward tiles): rows and imported
+// U rows in LDS
 // ---------------------------------------------------------------------------------
 // The block of a tile stages, into LDS, the tile's rows (their input values), the
 // per-L-entry data (where U(c) sits in LDS, its ready flag, and each lane's index
@@ -1523,7 +1524,10 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
         const bool flat = m.x < 0;             // L entries independent of one another
         const int row = flat ? ~m.x : m.x;
         const bool act = t < len;
+        const double tr = A.use_tau ? A.row_tau[row] : 0.0;
         double v = act ? vals[o.x + t] : 0.0;
+        double before = 0.0;                   // an L entry's value before its division
+        int dropped = 0;
         if (flat) {
             // every multiplier at once: lane t < K waits for its own dependency and
             // divides; the updates below then only reach U entries
@@ -1531,7 +1535,9 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
                 const int li = o.y + t;
                 const int ok = lds_wait_flag(&flags[dflag[li]], &s_abort, A.info);
                 const double piv = ok ? vals[dloc[li]] : __longlong_as_double((long long)kQNaN64);
+                before = v;
                 v = v / piv;
+                if (A.use_tau && fabs(v) < tr) dropped = 1;
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         }
@@ -1541,9 +1547,20 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
             if (!flat) {
                 const int ok = lds_wait_flag(&flags[dflag[li]], &s_abort, A.info);
                 const double piv = ok ? vals[loc] : __longlong_as_double((long long)kQNaN64);
-                if (t == e) v = v / piv;
+                if (t == e) {
+                    before = v;
+                    v = v / piv;
+                    if (A.use_tau && fabs(v) < tr) dropped = 1;
+                }
             }
             const double l = __shfl(v, e, G);
+            if (A.use_tau && __shfl(dropped, e, G)) {
+                // a dropped multiplier updates nothing; the modified form gives its
+                // value before the division back to the diagonal
+                const double bv = __shfl(before, e, G);
+                if (A.milu && t == K) v = v + bv;
+                continue;
+            }
             if (A.milu && t == K) {
                 // modified ILU: the diagonal takes its own update and every update
                 // whose target row r does not hold, in U(c)'s column order
@@ -1551,29 +1568,43 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
                 while (mk) {
                     const int jj = __builtin_ctz(mk);
                     mk &= mk - 1;
-                    const double lost = l * vals[loc + jj];
+                    const double u = vals[loc + jj];
+                    if ((uint64_t)__double_as_longlong(u) == kDropped64) continue;
+                    const double lost = l * u;
                     v = v - lost;
                 }
             } else {
                 const int j = match[li * G + t];
                 if (j > 0) {
                     const double u = vals[loc + j];
-                    const double prod = l * u;
-                    v = v - prod;
+                    if ((uint64_t)__double_as_longlong(u) != kDropped64) {
+                        const double prod = l * u;
+                        v = v - prod;
+                    }
                 }
             }
         }
-        // pivot and finiteness checks, as in the sync-free factor
+        // U entries below the threshold at the end of the row (the modified form adds
+        // them to the diagonal in column order), then the checks of the sync-free factor
+        if (A.use_tau) {
+            if (act && t > K && fabs(v) < tr) dropped = 1;
+            if (A.milu) {
+                for (int j = K + 1; j < G; ++j) {
+                    const double dv = __shfl(v, j, G);
+                    if (__shfl(dropped, j, G) && t == K) v = v + dv;
+                }
+            }
+        }
         const double pv = __shfl(v, K, G);
-        const bool nonfinite = act && !isfinite(v);
+        const bool nonfinite = act && !dropped && !isfinite(v);
         const uint64_t nfm = group_bits<G>(__ballot(nonfinite), gi);
         if (t == 0) {
             if (pv == 0.0) atomicMin(&A.info[kInfoBadKey], 2 * row);
             else if (nfm) atomicMin(&A.info[kInfoBadKey], 2 * row + 1);
         }
         if (act) {
-            vals[o.x + t] = v;
-            const uint64_t bits = (v != v) ? kQNaN64 : (uint64_t)__double_as_longlong(v);
+            const uint64_t bits = dropped ? kDropped64 : (v != v) ? kQNaN64 : (uint64_t)__double_as_longlong(v);
+            reinterpret_cast<uint64_t *>(vals)[o.x + t] = bits;
             st_pub_u64(reinterpret_cast<uint64_t *>(&A.lu[m.y + t]), bits);
         }
         if (t == 0) __hip_atomic_store(&flags[sl], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);

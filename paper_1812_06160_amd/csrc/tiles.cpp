@@ -174,6 +174,11 @@ void build_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, TileSet 
     tiles_one(H, 1, cap, short_row, bwd, sci);
 }
 
+void build_forward_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, TileSet *fwd) {
+    std::vector<int32_t> sci(H.lu_ci.size(), -1);
+    tiles_one(H, 0, cap, short_row, fwd, &sci);
+}
+
 void build_factor_tiles(const HostAnalysis &H, const TileSet &T, int32_t lanes, FactorTiles *F) {
     const std::vector<int32_t> &rp = H.lu_rp, &ci = H.lu_ci, &dg = H.diag;
     F->lanes = lanes;

@@ -17,8 +17,8 @@ SCHEDS = [("level", "level"), ("syncfree", "syncfree")]
 # solve schedules: the factor schedule is irrelevant to the apply; the tiled solve
 # is built with small tiles so that test matrices span several tiles (ragged last)
 SOLVE_SCHEDS = SCHEDS + [("syncfree", "tiled")]
-# factor schedules: the tiled factor covers ILU(k) and modified ILU(k) with k = k_max,
-# tau = 0 and rows of at most 16 entries, and falls back to the sync-free factor otherwise
+# factor schedules: the tiled factor covers ILU(k, tau) and modified ILU(k, tau) with
+# k = k_max and rows of at most 16 entries, and falls back to the sync-free factor otherwise
 FACTOR_SCHEDS = SCHEDS + [("tiled", "tiled")]
 
 
@@ -650,11 +650,14 @@ def test_factor_tiled_bit_exact(jv, name, mk, k, sym, tile_rows):
     A = mk()
     ilu = make(jv, A, k, sym, ("tiled", "tiled"), tile_rows=tile_rows)
     an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k, sym=sym)
-    want = {milu: O.factor(an, A.val, k=k, milu=milu) for milu in (False, True)}
+    cases = [(False, 0.0), (True, 0.0), (True, 1e-2), (False, 1e-2), (False, 0.0)]
+    want = {c: O.factor(an, A.val, k=k, milu=c[0], tau=c[1]) for c in set(cases)}
     if np.diff(an.lu_rp).max() <= 16:
         assert ilu.get_tuning("factor_tiled") == 1
-    for milu in (False, True, True, False):
-        f = want[milu]
-        ilu.factor(dev(A.val), k=k, milu=milu)
-        lu, _ = ilu.factor_values()
+    for milu, tau in cases:
+        f = want[(milu, tau)]
+        info = ilu.factor(dev(A.val), k=k, milu=milu, tau=tau)
+        lu, st = ilu.factor_values()
+        np.testing.assert_array_equal(st, f.stat)
         assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64)), f"max diff {np.abs(lu - f.val).max()}"
+        assert info["n_dropped"] == int((f.stat == 1).sum())
