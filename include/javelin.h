@@ -310,7 +310,7 @@ ilu_status ilu_solve_gmres(ilu_handle h, const double *b, double *x, double rtol
 /* Chooses the launch scheme of the factor and of the solves (ILU_SCHED_*) and the
  * lanes per row (0 = automatic from the longest row; else 4, 8, 16, 32 or 64;
  * factor lanes must cover the longest factor row).  The tiled factor runs ILU(k,
- * tau) and modified ILU(k, tau) with k = k_max and rows of at most 16 entries;
+ * tau) and modified ILU(k, tau) with k = k_max and rows of at most 32 entries;
  * otherwise the call runs the sync-free factor.  A solve direction whose rows have
  * more than 32 dependencies runs sync-free under the tiled schedule.  Factor rows
  * longer than 64 entries (up to 4096) run with one wave per row and the row in
@@ -328,7 +328,7 @@ ilu_status ilu_get_schedule(ilu_handle h, int32_t *factor_sched, int32_t *solve_
  * is read from global memory when its turn comes; same results).  Readable as well:
  * "nstreams" (task streams = XCDs found), "factor_tcap" (LDS entries staged per
  * factor row), "factor_tiled" (1 if the tiled factor can run on this handle:
- * rows of at most 16 entries and tiles that fit LDS).  Unknown keys give
+ * rows of at most 32 entries and tiles that fit LDS).  Unknown keys give
  * ILU_ERR_ARG. */
 ilu_status ilu_set_tuning(ilu_handle h, const char *key, int64_t value);
 ilu_status ilu_get_tuning(ilu_handle h, const char *key, int64_t *value);

@@ -317,7 +317,7 @@ ilu_status ilu_handle_s::make_factor_tiles() {
     ftiles_ok = false;
     ftset_own = false;
     if (H.max_row_lu > kFactorMaxLanes || tiles[0].ntiles == 0) return ILU_OK;
-    const int32_t lanes = H.max_row_lu <= 8 ? 8 : 16;
+    const int32_t lanes = H.max_row_lu <= 8 ? 8 : H.max_row_lu <= 16 ? 16 : 32;
     auto fits = [&](const TileSet &S) {
         build_factor_tiles(H, S, lanes, &ftiles);
         FactorTileArgs T{};

@@ -131,7 +131,7 @@ constexpr int kTileLongJ = 8;
 constexpr int kTileBlock = 64 * (kTileComputeWaves + 1);
 constexpr int kTileLdsMax = 65536;    // dynamic LDS bytes a tiled solve may use
 constexpr int kFactorTileLdsMax = 163840;   // the whole LDS of a compute unit (opt-in above 64 KB)
-constexpr int kFactorMaxLanes = 16;         // longest factor row of the tiled factor
+constexpr int kFactorMaxLanes = 32;         // longest factor row of the tiled factor
 // LDS a tiling needs with `nr` right-hand sides per pass of `acc_bytes` each
 size_t tile_lds_bytes(int max_rows, int max_slots, int max_pos, int kmax, int nr, int acc_bytes);
 
@@ -194,7 +194,7 @@ hipError_t launch_cast_bf16(int64_t m, const double *x, uint16_t *y, hipStream_t
 hipError_t launch_solve(const SolveArgs &A, bool forward, int prec, int vec, int lanes, bool syncfree,
                         int grid, hipStream_t s);
 hipError_t launch_spmv(const SpmvArgs &A, int lanes, hipStream_t s);
-// tiled factor with `lanes` (8 or 16) lanes per row; hipErrorInvalidValue when it
+// tiled factor with `lanes` (8, 16 or 32) lanes per row; hipErrorInvalidValue when it
 // does not fit LDS
 hipError_t launch_factor_tiled(const FactorArgs &A, const FactorTileArgs &T, int lanes, hipStream_t s);
 size_t factor_tile_lds_bytes(const FactorTileArgs &T, int lanes, bool milu);

@@ -1385,6 +1385,7 @@ __device__ __forceinline__ int lds_wait_flag(int *f, int *lds_abort, int32_t *in
 // import, copies the published ones into LDS and raises the import's ready flag
 // once its whole U part is there.  The window moves by 64 when its first 64
 // imports are complete.  Bounded like every wait.
+template <int G>
 __device__ void factor_poll(const int4 *imp, int nimp, const double *lu, double *vals, int *flags, int nrows,
                             int32_t *info, int sleep0, int *lds_abort) {
     const int lane = threadIdx.x & 63;
@@ -1400,13 +1401,13 @@ __device__ void factor_poll(const int4 *imp, int nimp, const double *lu, double 
             const int4 m = imp[i];
             const uint32_t all = m.y >= 32 ? 0xFFFFFFFFu : ((1u << m.y) - 1u);
             if (have[b] == all) continue;
-            uint64_t raw[kFactorMaxLanes];
+            uint64_t raw[G];   // a U part has at most G entries
 #pragma unroll
-            for (int j = 0; j < kFactorMaxLanes; ++j)
+            for (int j = 0; j < G; ++j)
                 raw[j] = (j < m.y && !(have[b] >> j & 1u)) ? ld_acq_u64(reinterpret_cast<const uint64_t *>(lu + m.x + j))
                                                            : kPending64;
 #pragma unroll
-            for (int j = 0; j < kFactorMaxLanes; ++j) {
+            for (int j = 0; j < G; ++j) {
                 if (j < m.y && !(have[b] >> j & 1u) && raw[j] != kPending64) {
                     reinterpret_cast<uint64_t *>(vals)[m.z + j] = raw[j];
                     have[b] |= 1u << j;
@@ -1511,7 +1512,7 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
     const int wave = threadIdx.x >> 6;
     const int gi = (threadIdx.x & 63) / G;
     if (wave == kTileComputeWaves) {
-        factor_poll(imp, nimp, A.lu, vals, flags, nrows, A.info, A.poll_sleep, &s_abort);
+        factor_poll<G>(imp, nimp, A.lu, vals, flags, nrows, A.info, A.poll_sleep, &s_abort);
         return;
     }
     constexpr int UNIT = 64 / G;
@@ -1962,7 +1963,13 @@ static hipError_t tiled_lanes(const SolveArgs &A, const TileArgs &T, bool fwd, h
 
 template <typename TV, typename TA>
 static hipError_t tiled_dispatch(const SolveArgs &A, const TileArgs &T, bool fwd, hipStream_t s) {
-    if (A.nrhs > 1 && tile_layout(T, 4, sizeof(TA), nullptr) <= (size_t)kFactorTileLdsMax)
+    // several right-hand sides per pass: within 64 KB always; up to the whole LDS of
+    // a CU only for tiles with few imports (the one poller wave walks every
+    // import's right-hand sides in turn, so import-heavy tiles do better with
+    // single-right-hand-side passes at higher occupancy)
+    const size_t l4 = tile_layout(T, 4, sizeof(TA), nullptr);
+    const bool few_imports = T.max_slots <= 2 * T.max_rows;
+    if (A.nrhs > 1 && (l4 <= (size_t)kTileLdsMax || (few_imports && l4 <= (size_t)kFactorTileLdsMax)))
         return tiled_lanes<4, TV, TA>(A, T, fwd, s);
     return tiled_lanes<1, TV, TA>(A, T, fwd, s);
 }
@@ -2026,6 +2033,7 @@ hipError_t launch_factor_tiled(const FactorArgs &A, const FactorTileArgs &T, int
     switch (lanes) {
         case 8: return factor_tiled_launch<8>(A, T, s);
         case 16: return factor_tiled_launch<16>(A, T, s);
+        case 32: return factor_tiled_launch<32>(A, T, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -18,7 +18,7 @@ SCHEDS = [("level", "level"), ("syncfree", "syncfree")]
 # is built with small tiles so that test matrices span several tiles (ragged last)
 SOLVE_SCHEDS = SCHEDS + [("syncfree", "tiled")]
 # factor schedules: the tiled factor covers ILU(k, tau) and modified ILU(k, tau) with
-# k = k_max and rows of at most 16 entries, and falls back to the sync-free factor otherwise
+# k = k_max and rows of at most 32 entries, and falls back to the sync-free factor otherwise
 FACTOR_SCHEDS = SCHEDS + [("tiled", "tiled")]
 
 
