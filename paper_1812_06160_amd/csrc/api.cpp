@@ -239,7 +239,7 @@ hipError_t ilu_handle_s::prepare_tile_claims(int pass, TileArgs *t, hipStream_t 
 static bool tile_rows_ok(const TileSet &T) { return T.kmax <= (T.unit == 64 ? kTileShortRow : 4 * kTileLongJ); }
 
 static bool tiles_fit(const TileSet &T) {
-    return tile_lds_bytes(T.max_rows, T.max_slots, T.max_pos, T.kmax, 1, 8) <= (size_t)kTileLdsMax &&
+    return tile_lds_bytes(T.max_rows, T.max_slots, T.max_pos, T.max_imps, T.kmax, 1, 8) <= (size_t)kTileLdsMax &&
            T.max_slots + 1 <= 65535 && T.max_pos <= 32767 && tile_rows_ok(T);
 }
 
@@ -513,6 +513,7 @@ extern "C" ilu_status ilu_analyze(const ilu_csr *A, const ilu_analyze_opts *opts
     h->row_off = {0, (int64_t)A->n};
     h->nnz_off = {0, A->nnz};
     h->host_only = o.host_only != 0;
+    h->pattern_sym = h->H.t_rp == h->H.lu_rp && h->H.t_ci == h->H.lu_ci;
     if (!h->host_only && (st = finish_analysis(h.get())) != ILU_OK) return st;
     if ((st = h->make_tiles(o.tile_rows ? o.tile_rows : kDefaultTileRows, o.tile_rows == 0)) != ILU_OK) return st;
     // the solves default to the tiled launch wherever the tiles fit LDS
@@ -898,8 +899,9 @@ ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int 
             which = fwd ? kTasksTForward : kTasksTBackward;
             lptr = fwd ? &H.tlevel_ptr : &H.tulevel_ptr;
         }
-        // the tiled schedule; a direction whose rows are too long for it runs sync-free
-        if (view == 0 && h->sched_solve == ILU_SCHED_TILED && tile_rows_ok(h->tiles[fwd ? 0 : 1])) {
+        // the tiled schedule; a direction whose rows are too long for it runs
+        // sync-free, and so do the transposed views of an unsymmetric pattern
+        if ((view == 0 || h->pattern_sym) && h->sched_solve == ILU_SCHED_TILED && tile_rows_ok(h->tiles[fwd ? 0 : 1])) {
             const TileSet &T = h->tiles[fwd ? 0 : 1];
             const ilu_handle_s::DevTiles &D = h->dtiles[fwd ? 0 : 1];
             TileArgs ta{};
@@ -914,6 +916,7 @@ ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int 
             ta.max_rows = T.max_rows;
             ta.max_slots = T.max_slots;
             ta.max_pos = T.max_pos;
+            ta.max_imps = T.max_imps;
             ta.kmax = T.kmax;
             ta.unit = T.unit;
             if ((e = h->prepare_tile_claims(fwd ? kPassTileF : kPassTileB, &ta, s)) != hipSuccess)

@@ -112,7 +112,7 @@ struct TileArgs {
     const int32_t *imp;       // imported rows (slot = tile rows + index)
     const int32_t *sci;       // per factor entry: LDS slot of the dependency
     int32_t ntiles;
-    int32_t max_rows, max_slots, max_pos, kmax;
+    int32_t max_rows, max_slots, max_pos, max_imps, kmax;
     int32_t unit;             // positions per chunk (64: one lane per row, 16: four)
     // LDS carve-up (bytes), set by the launcher
     int32_t off_rhs, off_piv, off_eval, off_eslot, off_rowid, off_pslot, off_imp, off_orow, lds_bytes;
@@ -133,7 +133,7 @@ constexpr int kTileLdsMax = 65536;    // dynamic LDS bytes a tiled solve may use
 constexpr int kFactorTileLdsMax = 163840;   // the whole LDS of a compute unit (opt-in above 64 KB)
 constexpr int kFactorMaxLanes = 32;         // longest factor row of the tiled factor
 // LDS a tiling needs with `nr` right-hand sides per pass of `acc_bytes` each
-size_t tile_lds_bytes(int max_rows, int max_slots, int max_pos, int kmax, int nr, int acc_bytes);
+size_t tile_lds_bytes(int max_rows, int max_slots, int max_pos, int max_imps, int kmax, int nr, int acc_bytes);
 
 // Tiled factor (plain ILU: every pattern entry kept, no dropping) on the forward
 // tiles; see FactorTiles in analysis.h for the data.

@@ -86,6 +86,8 @@ struct ilu_handle_s {
     jv::TileSet tiles[2];
     std::vector<int32_t> sci;
     int32_t tile_rows = 0;             // rows per tile of the current tiles
+    bool pattern_sym = false;          // factor pattern symmetric: the transposed views (adjoint)
+                                       // have the same rows and columns and use the same tiles
     struct DevTiles {
         int32_t *ptr = nullptr, *rows_ptr = nullptr, *meta = nullptr, *imp_ptr = nullptr, *imp = nullptr;
         int16_t *pslot = nullptr;

@@ -1168,9 +1168,10 @@ __device__ __forceinline__ void tile_compute(const SolveArgs &A, typename Pub<TA
                 const TA sum = group_sum<G>(acc);
                 if (k < nr && (k % G) == t) {
                     TA v = cur.rhs[k] - sum;
-                    // forward: L has a unit diagonal; backward: multiply by the
-                    // reciprocal of u_rr taken at staging, off the dependency chain
-                    if constexpr (!FWD) v = v * cur.pv;
+                    // a unit diagonal (L, or L^T of the adjoint) needs nothing; else
+                    // multiply by the reciprocal of the pivot taken at staging, off
+                    // the dependency chain
+                    if (!A.unit_diag) v = v * cur.pv;
                     lds_st<TA>(vals + cur.sl * NR + k, bits_of<TA>(v));
                     tile_store<TA, FWD>(A, cur.r, orows[cur.sl], s0 + k, v);
                 }
@@ -1234,13 +1235,14 @@ __global__ __launch_bounds__(kTileBlock) void k_solve_tiled(SolveArgs A, TileArg
         TA ev_r[SR][SJ];
 #pragma unroll
         for (int u = 0; u < SR; ++u) {
-            pv[u] = (mt[u].x >= 0 && !A.unit_diag) ? (TA)load_val(val, mt[u].w) : (TA)1;
+            // values through the view's gather map (transposed views) when there is one
+            pv[u] = (mt[u].x >= 0 && !A.unit_diag) ? (TA)load_val(val, A.vmap ? A.vmap[mt[u].w] : mt[u].w) : (TA)1;
 #pragma unroll
             for (int jj = 0; jj < SJ; ++jj) {
                 const int p = mt[u].y + t + jj * G;
                 const bool on = mt[u].x >= 0 && p < mt[u].z;
                 es_r[u][jj] = on ? T.sci[p] : zero;
-                ev_r[u][jj] = on ? (TA)load_val(val, p) : (TA)0;
+                ev_r[u][jj] = on ? (TA)load_val(val, A.vmap ? A.vmap[p] : p) : (TA)0;
             }
         }
 #pragma unroll
@@ -1249,7 +1251,7 @@ __global__ __launch_bounds__(kTileBlock) void k_solve_tiled(SolveArgs A, TileArg
             if (sl >= nrows) continue;
             if (t == 0) {
                 rowid[sl] = mt[u].x;
-                piv[sl] = FWD ? pv[u] : (TA)1 / pv[u];
+                piv[sl] = A.unit_diag ? (TA)1 : (TA)1 / pv[u];
                 if constexpr (!FWD) orows[sl] = mt[u].x;
             }
 #pragma unroll
@@ -1265,7 +1267,7 @@ __global__ __launch_bounds__(kTileBlock) void k_solve_tiled(SolveArgs A, TileArg
                 const int p = mt[u].y + j;
                 const bool on = p < mt[u].z;
                 es[sl * K + j] = (uint16_t)(on ? T.sci[p] : zero);
-                ev[sl * K + j] = on ? (TA)load_val(val, p) : (TA)0;
+                ev[sl * K + j] = on ? (TA)load_val(val, A.vmap ? A.vmap[p] : p) : (TA)0;
             }
         }
     }
@@ -1895,7 +1897,7 @@ static size_t tile_layout(const TileArgs &T, int nr, int acc, TileArgs *out) {
     const size_t psl = o;
     o = align8(o + (size_t)T.max_pos * 2);
     const size_t imp = o;
-    o = align8(o + (size_t)(T.max_slots - T.max_rows > 0 ? T.max_slots : 0) * 4);
+    o = align8(o + (size_t)T.max_imps * 4);   // the import list of the tile with the most imports
     const size_t orw = o;
     o = align8(o + (size_t)T.max_rows * 4);
     if (out) {
@@ -1912,11 +1914,12 @@ static size_t tile_layout(const TileArgs &T, int nr, int acc, TileArgs *out) {
     return o;
 }
 
-size_t tile_lds_bytes(int max_rows, int max_slots, int max_pos, int kmax, int nr, int acc_bytes) {
+size_t tile_lds_bytes(int max_rows, int max_slots, int max_pos, int max_imps, int kmax, int nr, int acc_bytes) {
     TileArgs T{};
     T.max_rows = max_rows;
     T.max_slots = max_slots;
     T.max_pos = max_pos;
+    T.max_imps = max_imps;
     T.kmax = kmax;
     return tile_layout(T, nr, acc_bytes, nullptr);
 }

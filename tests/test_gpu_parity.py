@@ -461,6 +461,35 @@ def test_adjoint_against_oracle(jv, sched):
         assert np.abs(g - glur).max() <= 1e-12 * np.abs(glur).max()
 
 
+@pytest.mark.parametrize("tile_rows", [16, 100, 0])
+@pytest.mark.parametrize("name,mk,k", [
+    ("laplace2d_30", lambda: synth.laplace2d(30), 0),
+    ("convdiff3d_8_ilu1", lambda: synth.convdiff3d(8), 1),
+    ("random_sym_400", lambda: synth.random_sparse(400, 0.015, np.random.default_rng(17), symmetric_pattern=True), 0),
+], ids=lambda v: v if isinstance(v, (str, int)) else "")
+def test_adjoint_tiled_symmetric_pattern(jv, name, mk, k, tile_rows):
+    # a symmetric factor pattern: the transposed solves of the adjoint run on the
+    # forward and backward tiles, values through the transposed view's map
+    A = mk()
+    rng = np.random.default_rng(18)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=k, tile_rows=tile_rows)
+    ilu.set_schedule("syncfree", "tiled")
+    ilu.factor(dev(A.val), k=k)
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k)
+    f = O.factor(an, A.val, k=k)
+    for nrhs in (1, 3):
+        b = rng.uniform(-1, 1, (A.n, nrhs))
+        gx = rng.uniform(-1, 1, (A.n, nrhs))
+        x, y = ilu.apply_ex(dev(b))
+        xr, yr = O.apply(an, f.val, b, want_y=True)
+        assert relerr(x.cpu().numpy(), xr) <= 1e-12
+        gb, glu = ilu.adjoint(dev(gx), x, y)
+        gbr, glur = O.adjoint(an, f.val, gx, xr, yr)
+        assert relerr(gb.cpu().numpy(), gbr) <= 1e-12
+        g = glu.cpu().numpy()
+        assert np.abs(g - glur).max() <= 1e-12 * np.abs(glur).max()
+
+
 def test_autograd_finite_differences(jv):
     rng = np.random.default_rng(16)
     A = synth.convdiff3d(6)
@@ -596,6 +625,9 @@ def test_apply_graph_replays(jv, sched):
     ("convdiff3d_12_ilu1", lambda: synth.convdiff3d(12), 1, True),
     ("random_2500_lower_a", lambda: synth.random_banded(2500, rng=np.random.default_rng(9)), 0, False),
     ("tridiag_777", lambda: synth.tridiag(777), 0, True),
+    # two tiles: the larger (512 rows) imports nothing, the other does -- the LDS
+    # room for the import list must follow the most imports of any tile
+    ("laplace2d_30", lambda: synth.laplace2d(30), 0, True),
 ], ids=lambda v: v if isinstance(v, (str, int)) else "")
 def test_apply_tiled_tile_sizes(jv, name, mk, k, sym, tile_rows):
     # tiles from 16 rows (most dependencies cross tiles) to one tile for the whole
