@@ -1966,14 +1966,12 @@ static hipError_t tiled_lanes(const SolveArgs &A, const TileArgs &T, bool fwd, h
 
 template <typename TV, typename TA>
 static hipError_t tiled_dispatch(const SolveArgs &A, const TileArgs &T, bool fwd, hipStream_t s) {
-    // several right-hand sides per pass: within 64 KB always; up to the whole LDS of
-    // a CU only for tiles with few imports (the one poller wave walks every
-    // import's right-hand sides in turn, so import-heavy tiles do better with
-    // single-right-hand-side passes at higher occupancy)
+    // several right-hand sides per pass (up to the whole LDS of a CU) only for tiles
+    // with few imports: the one poller wave walks every import's right-hand sides
+    // in turn, so import-heavy tiles do better with single-right-hand-side passes
     const size_t l4 = tile_layout(T, 4, sizeof(TA), nullptr);
     const bool few_imports = T.max_slots <= 2 * T.max_rows;
-    if (A.nrhs > 1 && (l4 <= (size_t)kTileLdsMax || (few_imports && l4 <= (size_t)kFactorTileLdsMax)))
-        return tiled_lanes<4, TV, TA>(A, T, fwd, s);
+    if (A.nrhs > 1 && few_imports && l4 <= (size_t)kFactorTileLdsMax) return tiled_lanes<4, TV, TA>(A, T, fwd, s);
     return tiled_lanes<1, TV, TA>(A, T, fwd, s);
 }
 
