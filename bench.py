@@ -97,7 +97,8 @@ def main():
     ap.add_argument("--solve-sched", default="tiled", choices=["tiled", "syncfree", "level"],
                     help="launch scheme of the triangular solves")
     ap.add_argument("--workload", default="laplace3d_128",
-                    choices=["laplace3d_128", "convdiff3d_96", "random_1m", "batch512", "heavy_1m", "ordering"])
+                    choices=["laplace3d_128", "laplace2d_64", "convdiff3d_96", "random_1m", "batch512", "heavy_1m",
+                             "ordering"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)

@@ -1,5 +1,7 @@
 """Measurements of the other workloads (bench.py --workload ...): one JSON line each.
 
+laplace2d_64   64x64 5-point Laplacian (n = 4096): ILU(0) factor, one apply, PCG to 1e-10
+               -- a latency case (the working set fits in L2), reported in microseconds.
 convdiff3d_96  96^3 upwind convection-diffusion, ILU(1, tau=1e-3): factor, applies,
                FGMRES(30) to 1e-10 with FP64, FP32 and BF16 factors.
 random_1m      n = 1e6 random unsymmetric rows (8 banded + 8 scattered off-diagonals),
@@ -61,7 +63,30 @@ def run(args):
     jv.load()
     wl = args.workload
     out = dict(workload=wl, data="synthetic", n_gpus=1, schedule=args.sched, solve_schedule=args.solve_sched)
-    if wl == "convdiff3d_96":
+    if wl == "laplace2d_64":
+        A, b = synth.workload(1)
+        ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
+        ilu.set_schedule(args.sched, args.solve_sched)
+        vals = _dev(A.val)
+        bd = _dev(b)
+        ilu.factor(vals)
+        ilu.profile(True, 1 << 16)
+        st = _stage_times(ilu, lambda: ilu.factor(vals, casts=()), 20)
+        pa = _stage_times(ilu, lambda: ilu.apply(bd), 20)
+        for _ in range(2):
+            ilu.pcg(bd, rtol=1e-10)
+        torch.cuda.synchronize()
+        reps = 10
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, si = ilu.pcg(bd, rtol=1e-10)
+        torch.cuda.synchronize()
+        t_cg = (time.perf_counter() - t0) / reps
+        info = ilu.info()
+        out.update(n=A.n, nnz=A.nnz, levels=info["n_levels"], factor_us=round(1e3 * st["factor"][0], 2),
+                   apply_us=round(1e3 * (pa["forward"][0] + pa["backward"][0]), 2),
+                   pcg=dict(iters=si["iters"], us=round(1e6 * t_cg, 1), true_relres=si["true_relres"]))
+    elif wl == "convdiff3d_96":
         A, b = synth.workload(3)
         ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=1)
         ilu.set_schedule(args.sched, args.solve_sched)
