@@ -129,7 +129,7 @@ constexpr int kTileComputeWaves = 8;
 constexpr int kTileShortRow = 1;
 constexpr int kTileLongJ = 8;
 constexpr int kTileBlock = 64 * (kTileComputeWaves + 1);
-constexpr int kTileLdsMax = 65536;    // dynamic LDS bytes a tiled solve may use
+constexpr int kTileLdsMax = 163840;   // dynamic LDS bytes a tiled solve may use (the whole LDS of a CU)
 constexpr int kFactorTileLdsMax = 163840;   // the whole LDS of a compute unit (opt-in above 64 KB)
 constexpr int kFactorMaxLanes = 32;         // longest factor row of the tiled factor
 // LDS a tiling needs with `nr` right-hand sides per pass of `acc_bytes` each

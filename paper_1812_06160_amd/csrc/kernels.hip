@@ -1928,9 +1928,10 @@ template <int G, int J, int NR, typename TV, typename TA>
 static hipError_t tiled_launch(const SolveArgs &A, const TileArgs &T0, bool fwd, hipStream_t s) {
     TileArgs T = T0;
     const size_t lds = tile_layout(T, NR, sizeof(TA), &T);
-    // one right-hand side per pass keeps to 64 KB (three blocks per CU); several
-    // per pass may take the whole LDS of a CU
-    const size_t cap = NR == 1 ? (size_t)kTileLdsMax : (size_t)kFactorTileLdsMax;
+    // a tile may take the whole LDS of a CU (opt-in above 64 KB): grid tiles stay
+    // far below (three blocks per CU), import-heavy tiles trade blocks for fewer
+    // crossings
+    const size_t cap = (size_t)kTileLdsMax;
     if (lds > cap || T.max_slots + 1 > 65535 || T.max_pos > 32767) return hipErrorInvalidValue;
     if (T.ntiles <= 0) return hipSuccess;
     if (lds > 65536) {
@@ -1971,7 +1972,7 @@ static hipError_t tiled_dispatch(const SolveArgs &A, const TileArgs &T, bool fwd
     // in turn, so import-heavy tiles do better with single-right-hand-side passes
     const size_t l4 = tile_layout(T, 4, sizeof(TA), nullptr);
     const bool few_imports = T.max_slots <= 2 * T.max_rows;
-    if (A.nrhs > 1 && few_imports && l4 <= (size_t)kFactorTileLdsMax) return tiled_lanes<4, TV, TA>(A, T, fwd, s);
+    if (A.nrhs > 1 && few_imports && l4 <= (size_t)kTileLdsMax) return tiled_lanes<4, TV, TA>(A, T, fwd, s);
     return tiled_lanes<1, TV, TA>(A, T, fwd, s);
 }
 
