@@ -36,11 +36,11 @@ HBM_PEAK_GBS = 8000.0
 # scaled by what the same counters read for the calibration copy kernels.  Valid
 # only for the kernel source it was taken with: a different hash reports null.
 PMC_TRAFFIC = dict(
-    kernels_sha256="a27aa9c2473984918edae9818db43e908645b6a239f612db14faedc2d9874461",
-    fetch_scale=1.9986, write_scale=0.9944,
-    forward=dict(f64=(189241, 65777), f32=(157539, 50714)),
-    backward=dict(f64=(190276, 92815), f32=(151550, 77799)),
-    factor=(279953, 146456),
+    kernels_sha256="a41bbf6a727db4faca572d6f3603d0e38326c15abe18de3d9d36c844315a386f",
+    fetch_scale=1.9986, write_scale=0.9945,
+    forward=dict(f64=(189426, 65757), f32=(157542, 50705)),
+    backward=dict(f64=(189245, 92804), f32=(149680, 77510)),
+    factor=(284234, 146456),
 )
 
 
