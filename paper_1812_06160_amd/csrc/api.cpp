@@ -238,9 +238,20 @@ hipError_t ilu_handle_s::prepare_tile_claims(int pass, TileArgs *t, hipStream_t 
 // rows the tiled solve can take at all (dependencies per row), whatever the tile size
 static bool tile_rows_ok(const TileSet &T) { return T.kmax <= (T.unit == 64 ? kTileShortRow : 4 * kTileLongJ); }
 
-static bool tiles_fit(const TileSet &T) {
-    return tile_lds_bytes(T.max_rows, T.max_slots, T.max_pos, T.max_imps, T.kmax, 1, 8) <= (size_t)kTileLdsMax &&
+static bool tiles_fit(const TileSet &T, size_t budget = kTileLdsMax) {
+    return tile_lds_bytes(T.max_rows, T.max_slots, T.max_pos, T.max_imps, T.kmax, 1, 8) <= budget &&
            T.max_slots + 1 <= 65535 && T.max_pos <= 32767 && tile_rows_ok(T);
+}
+
+// LDS budget of the default tile size.  Narrow levels (median under 256 rows) leave
+// little parallelism per level, and large tiles -- fewer crossings -- win even at
+// one block per CU; wide levels want three blocks per CU (64 KB).
+static size_t default_tile_budget(const HostAnalysis &H) {
+    std::vector<int32_t> sizes(H.n_levels);
+    for (int32_t l = 0; l < H.n_levels; ++l) sizes[l] = H.level_ptr[l + 1] - H.level_ptr[l];
+    if (sizes.empty()) return 65536;
+    std::nth_element(sizes.begin(), sizes.begin() + sizes.size() / 2, sizes.end());
+    return sizes[sizes.size() / 2] < 256 ? (size_t)kTileLdsMax : (size_t)65536;
 }
 
 // LDS slot of every position of a tiling (-1 for padding)
@@ -255,9 +266,10 @@ static std::vector<int16_t> position_slots(const TileSet &T) {
 
 ilu_status ilu_handle_s::make_tiles(int32_t rows, bool shrink) {
     try {
+        const size_t budget = default_tile_budget(H);
         for (;;) {
             build_tiles(H, rows, kTileShortRow, &tiles[0], &tiles[1], &sci);
-            if (!shrink || rows <= 16 || (tiles_fit(tiles[0]) && tiles_fit(tiles[1]))) break;
+            if (!shrink || rows <= 16 || (tiles_fit(tiles[0], budget) && tiles_fit(tiles[1], budget))) break;
             rows /= 2;
         }
     } catch (const std::bad_alloc &) {
