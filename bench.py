@@ -36,11 +36,11 @@ HBM_PEAK_GBS = 8000.0
 # scaled by what the same counters read for the calibration copy kernels.  Valid
 # only for the kernel source it was taken with: a different hash reports null.
 PMC_TRAFFIC = dict(
-    kernels_sha256="a41bbf6a727db4faca572d6f3603d0e38326c15abe18de3d9d36c844315a386f",
+    kernels_sha256="16cc77b9ddc2a76b3ffea06fb2ed69c29d36c3a04a493996633c29378ad971c1",
     fetch_scale=1.9986, write_scale=0.9945,
-    forward=dict(f64=(189426, 65757), f32=(157542, 50705)),
-    backward=dict(f64=(189245, 92804), f32=(149680, 77510)),
-    factor=(284234, 146456),
+    forward=dict(f64=(189744, 65773), f32=(157919, 50706)),
+    backward=dict(f64=(189811, 93017), f32=(149804, 77532)),
+    factor=(281781, 146456),
 )
 
 

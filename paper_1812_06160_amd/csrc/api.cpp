@@ -338,7 +338,7 @@ ilu_status ilu_handle_s::make_factor_tiles() {
         T.max_lents = ftiles.max_lents;
         T.max_pos = S.max_pos;
         T.max_imps = S.max_imps;
-        return factor_tile_lds_bytes(T, lanes, true) <= (size_t)kFactorTileLdsMax;
+        return factor_tile_lds_bytes(T, lanes, true, true) <= (size_t)kFactorTileLdsMax;
     };
     try {
         bool ok = fits(tiles[0]);

@@ -151,7 +151,8 @@ struct FactorTileArgs {
     const int4 *imp;          // per import: diagonal entry, U length, value-area offset
     int32_t ntiles, max_rows, max_vals, max_lents, max_pos, max_imps;
     // LDS carve-up (bytes), set by the launcher
-    int32_t off_flags, off_meta, off_off, off_dloc, off_dflag, off_match, off_cmask, off_imp, off_pslot, lds_bytes;
+    int32_t off_flags, off_meta, off_off, off_dloc, off_dflag, off_match, off_cmask, off_imp, off_pslot, off_tau,
+        lds_bytes;
     int32_t *counter;         // claim counter (zero at launch)
 };
 
@@ -197,7 +198,7 @@ hipError_t launch_spmv(const SpmvArgs &A, int lanes, hipStream_t s);
 // tiled factor with `lanes` (8, 16 or 32) lanes per row; hipErrorInvalidValue when it
 // does not fit LDS
 hipError_t launch_factor_tiled(const FactorArgs &A, const FactorTileArgs &T, int lanes, hipStream_t s);
-size_t factor_tile_lds_bytes(const FactorTileArgs &T, int lanes, bool milu);
+size_t factor_tile_lds_bytes(const FactorTileArgs &T, int lanes, bool milu, bool tau);
 // tiled solve; returns hipErrorInvalidValue when no right-hand-side blocking fits LDS
 hipError_t launch_solve_tiled(const SolveArgs &A, const TileArgs &T, bool forward, int prec, int vec,
                               hipStream_t s);

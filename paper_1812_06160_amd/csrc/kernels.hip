@@ -1337,11 +1337,16 @@ __global__ __launch_bounds__(kTileBlock) void k_solve_tiled(SolveArgs A, TileArg
             }
         }
         __syncthreads();
-        if (wave == kTileComputeWaves)
+        if (wave == kTileComputeWaves) {
             tile_poll<NR, TA>(impl, nimp, FWD ? y : z, cap, s0, nr, vals, nrows, A.info, A.poll_sleep, &s_abort);
-        else
+        } else {
+            // Nothing is outstanding here but this wave's stores.  Saying so keeps
+            // the compiler from waiting on them inside the compute loop (its
+            // bookkeeping otherwise carries the poller's loads around the pass loop).
+            __builtin_amdgcn_s_waitcnt(0);
             tile_compute<G, J, NR, TA, FWD>(A, vals, ev, es, ps, rowid, orows, piv, rhs, K, npos, wave, gi, t, s0, nr,
                                             &s_abort);
+        }
         __syncthreads();
     }
 }
@@ -1453,6 +1458,7 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
     uint32_t *cmask = reinterpret_cast<uint32_t *>(fsmem + T.off_cmask);
     int4 *imp = reinterpret_cast<int4 *>(fsmem + T.off_imp);
     int16_t *ps = reinterpret_cast<int16_t *>(fsmem + T.off_pslot);
+    double *tau = reinterpret_cast<double *>(fsmem + T.off_tau);
     __shared__ int s_tile, s_abort;
     if (threadIdx.x == 0) {
         s_tile = __hip_atomic_fetch_add(T.counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1484,6 +1490,13 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
     for (int i = threadIdx.x; i < nimp; i += kTileBlock) {
         const int4 m = imp[i];
         for (int j = 0; j < m.y; ++j) reinterpret_cast<uint64_t *>(vals)[m.z + j] = kPending64;
+    }
+    // the rows' drop thresholds, so that the compute waves issue no global load
+    if (A.use_tau) {
+        for (int i = threadIdx.x; i < nrows; i += kTileBlock) {
+            const int mx = meta[i].x;
+            tau[i] = A.row_tau[mx < 0 ? ~mx : mx];
+        }
     }
     constexpr int SR = kStageRows;
     constexpr int GROUPS = kTileBlock / G;
@@ -1517,6 +1530,9 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
         factor_poll<G>(imp, nimp, A.lu, vals, flags, nrows, A.info, A.poll_sleep, &s_abort);
         return;
     }
+    // Every staging load has landed.  Saying so keeps the compiler from waiting
+    // on the stores of earlier rows inside the loop, which has no global load.
+    __builtin_amdgcn_s_waitcnt(0);
     constexpr int UNIT = 64 / G;
     for (int c0 = wave * UNIT; c0 < npos; c0 += kTileComputeWaves * UNIT) {
         const int sl = ps[c0 + gi];
@@ -1527,7 +1543,7 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
         const bool flat = m.x < 0;             // L entries independent of one another
         const int row = flat ? ~m.x : m.x;
         const bool act = t < len;
-        const double tr = A.use_tau ? A.row_tau[row] : 0.0;
+        const double tr = A.use_tau ? tau[sl] : 0.0;
         double v = act ? vals[o.x + t] : 0.0;
         double before = 0.0;                   // an L entry's value before its division
         int dropped = 0;
@@ -1977,7 +1993,7 @@ static hipError_t tiled_dispatch(const SolveArgs &A, const TileArgs &T, bool fwd
 }
 
 // LDS carve-up of a tiled factor launch
-static size_t factor_tile_layout(const FactorTileArgs &T, int G, bool milu, FactorTileArgs *out) {
+static size_t factor_tile_layout(const FactorTileArgs &T, int G, bool milu, bool tau, FactorTileArgs *out) {
     size_t o = align8((size_t)T.max_vals * 8);
     const size_t fl = o;
     o = align8(o + (size_t)(T.max_rows + T.max_imps) * 4);
@@ -1997,7 +2013,10 @@ static size_t factor_tile_layout(const FactorTileArgs &T, int G, bool milu, Fact
     o = align8(o + (size_t)T.max_imps * 16);
     const size_t psl = o;
     o = align8(o + (size_t)T.max_pos * 2);
+    const size_t ta = o;
+    if (tau) o = align8(o + (size_t)T.max_rows * 8);
     if (out) {
+        out->off_tau = (int32_t)ta;
         out->off_flags = (int32_t)fl;
         out->off_meta = (int32_t)me;
         out->off_off = (int32_t)of;
@@ -2012,14 +2031,14 @@ static size_t factor_tile_layout(const FactorTileArgs &T, int G, bool milu, Fact
     return o;
 }
 
-size_t factor_tile_lds_bytes(const FactorTileArgs &T, int lanes, bool milu) {
-    return factor_tile_layout(T, lanes, milu, nullptr);
+size_t factor_tile_lds_bytes(const FactorTileArgs &T, int lanes, bool milu, bool tau) {
+    return factor_tile_layout(T, lanes, milu, tau, nullptr);
 }
 
 template <int G>
 static hipError_t factor_tiled_launch(const FactorArgs &A, const FactorTileArgs &T0, hipStream_t s) {
     FactorTileArgs T = T0;
-    const size_t lds = factor_tile_layout(T, G, A.milu != 0, &T);
+    const size_t lds = factor_tile_layout(T, G, A.milu != 0, A.use_tau != 0, &T);
     if (lds > (size_t)kFactorTileLdsMax) return hipErrorInvalidValue;
     if (T.ntiles <= 0) return hipSuccess;
     if (lds > 65536) {
