@@ -129,6 +129,13 @@ constexpr int kTileComputeWaves = 8;
 constexpr int kTileShortRow = 1;
 constexpr int kTileLongJ = 8;
 constexpr int kTileBlock = 64 * (kTileComputeWaves + 1);
+// Compute waves of a tiled solve block by accumulate type.  Seven for FP64 gives
+// eight-wave blocks, two waves on every SIMD; FP32 (fewer registers per lane)
+// measured faster with eight.
+template <typename TA>
+constexpr int solve_waves() { return sizeof(TA) == 8 ? 7 : 8; }
+template <typename TA>
+constexpr int solve_block() { return 64 * (solve_waves<TA>() + 1); }
 constexpr int kTileLdsMax = 163840;   // dynamic LDS bytes a tiled solve may use (the whole LDS of a CU)
 constexpr int kFactorTileLdsMax = 163840;   // the whole LDS of a compute unit (opt-in above 64 KB)
 constexpr int kFactorMaxLanes = 32;         // longest factor row of the tiled factor

@@ -1070,18 +1070,18 @@ __device__ __forceinline__ void tile_store(const SolveArgs &A, int r, int orow, 
 
 // Copies n elements from global memory into LDS, every thread issuing U loads
 // before storing any.
-template <int U, typename T>
+template <int U, int B = kTileBlock, typename T>
 __device__ __forceinline__ void lds_copy(T *dst, const T *__restrict__ src, int n) {
-    for (int i0 = threadIdx.x; i0 < n; i0 += kTileBlock * U) {
+    for (int i0 = threadIdx.x; i0 < n; i0 += B * U) {
         T v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * kTileBlock;
+            const int i = i0 + u * B;
             if (i < n) v[u] = src[i];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int i = i0 + u * kTileBlock;
+            const int i = i0 + u * B;
             if (i < n) dst[i] = v[u];
         }
     }
@@ -1118,7 +1118,7 @@ __device__ __forceinline__ void tile_row_load(TileRow<J, NR, TA> &R, const int16
     for (int k = 0; k < NR; ++k) R.rhs[k] = k < nr ? rhs[R.sl * NR + k] : (TA)0;
 }
 
-// Compute waves: wave w solves the chunks w, w + kTileComputeWaves, ... of the
+// Compute waves: wave w solves the chunks w, w + solve_waves<TA>(), ... of the
 // tile (a chunk is 64 / G positions of one local level), writing each value only
 // to its LDS slot and publishing it.  The next chunk's staged row data is loaded
 // while the current one waits and computes, and all dependency values of a row
@@ -1136,7 +1136,7 @@ __device__ __forceinline__ void tile_compute(const SolveArgs &A, typename Pub<TA
                                              int wave, int gi, int t, int s0, int nr, int *lds_abort) {
     using U = typename Pub<TA>::U;
     constexpr int UNIT = 64 / G;
-    constexpr int STEP = kTileComputeWaves * UNIT;
+    constexpr int STEP = solve_waves<TA>() * UNIT;
     TileRow<J, NR, TA> cur;
     int c0 = wave * UNIT;
     cur.sl = -1;
@@ -1182,7 +1182,8 @@ __device__ __forceinline__ void tile_compute(const SolveArgs &A, typename Pub<TA
 }
 
 template <int G, int J, int NR, typename TV, typename TA, bool FWD>
-__global__ __launch_bounds__(kTileBlock) void k_solve_tiled(SolveArgs A, TileArgs T) {
+__global__ __launch_bounds__(solve_block<TA>()) void k_solve_tiled(SolveArgs A, TileArgs T) {
+    constexpr int B = solve_block<TA>();
     using U = typename Pub<TA>::U;
     extern __shared__ __align__(16) unsigned char tile_smem[];
     U *vals = reinterpret_cast<U *>(tile_smem);
@@ -1218,11 +1219,11 @@ __global__ __launch_bounds__(kTileBlock) void k_solve_tiled(SolveArgs A, TileArg
     // stage the tile (every thread issues all loads of a step before it uses any):
     // position -> slot, imports, then per row its id, pivot, dependency slots and
     // values
-    lds_copy<kStageCopy>(ps, T.pslot + pbase, npos);
-    lds_copy<kStageCopy>(impl, T.imp + ibase, nimp);
+    lds_copy<kStageCopy, B>(ps, T.pslot + pbase, npos);
+    lds_copy<kStageCopy, B>(impl, T.imp + ibase, nimp);
     constexpr int SR = kStageRows;
     constexpr int SJ = G == 1 ? 4 : 2;   // entries per lane fetched with the batched loads
-    constexpr int GROUPS = kTileBlock / G;
+    constexpr int GROUPS = B / G;
     for (int s0r = threadIdx.x / G; s0r < nrows; s0r += GROUPS * SR) {
         int4 mt[SR];
 #pragma unroll
@@ -1274,16 +1275,16 @@ __global__ __launch_bounds__(kTileBlock) void k_solve_tiled(SolveArgs A, TileArg
     if constexpr (!FWD) {
         if (A.perm) {
             __syncthreads();
-            for (int i0 = threadIdx.x; i0 < nrows; i0 += kTileBlock * kStageCopy) {
+            for (int i0 = threadIdx.x; i0 < nrows; i0 += B * kStageCopy) {
                 int o[kStageCopy];
 #pragma unroll
                 for (int u = 0; u < kStageCopy; ++u) {
-                    const int i = i0 + u * kTileBlock;
+                    const int i = i0 + u * B;
                     if (i < nrows) o[u] = A.perm[rowid[i]];
                 }
 #pragma unroll
                 for (int u = 0; u < kStageCopy; ++u) {
-                    const int i = i0 + u * kTileBlock;
+                    const int i = i0 + u * B;
                     if (i < nrows) orows[i] = o[u];
                 }
             }
@@ -1294,13 +1295,13 @@ __global__ __launch_bounds__(kTileBlock) void k_solve_tiled(SolveArgs A, TileArg
     const int gi = (threadIdx.x & 63) / G;
     for (int s0 = 0; s0 < A.nrhs; s0 += NR) {
         const int nr = A.nrhs - s0 < NR ? A.nrhs - s0 : NR;
-        for (int i = threadIdx.x; i < (nrows + nimp) * NR; i += kTileBlock) vals[i] = Pub<TA>::kPend;
+        for (int i = threadIdx.x; i < (nrows + nimp) * NR; i += B) vals[i] = Pub<TA>::kPend;
         if (threadIdx.x < NR) vals[zero * NR + threadIdx.x] = bits_of<TA>((TA)0);
-        for (int i0 = threadIdx.x; i0 < nrows * nr; i0 += kTileBlock * kStageCopy) {
+        for (int i0 = threadIdx.x; i0 < nrows * nr; i0 += B * kStageCopy) {
             int64_t at[kStageCopy];
 #pragma unroll
             for (int u = 0; u < kStageCopy; ++u) {
-                const int i = i0 + u * kTileBlock;
+                const int i = i0 + u * B;
                 at[u] = -1;
                 if (i < nrows * nr) {
                     const int sl = i / nr, k = i - sl * nr;
@@ -1313,7 +1314,7 @@ __global__ __launch_bounds__(kTileBlock) void k_solve_tiled(SolveArgs A, TileArg
                 if (A.perm) {
 #pragma unroll
                     for (int u = 0; u < kStageCopy; ++u) {
-                        const int i = i0 + u * kTileBlock;
+                        const int i = i0 + u * B;
                         if (at[u] >= 0) {
                             const int sl = i / nr, k = i - sl * nr;
                             at[u] = (int64_t)A.perm[rowid[sl]] * A.ld + s0 + k;
@@ -1330,14 +1331,14 @@ __global__ __launch_bounds__(kTileBlock) void k_solve_tiled(SolveArgs A, TileArg
             }
 #pragma unroll
             for (int u = 0; u < kStageCopy; ++u) {
-                const int i = i0 + u * kTileBlock;
+                const int i = i0 + u * B;
                 if (at[u] < 0) continue;
                 const int sl = i / nr, k = i - sl * nr;
                 rhs[sl * NR + k] = bv[u];
             }
         }
         __syncthreads();
-        if (wave == kTileComputeWaves) {
+        if (wave == solve_waves<TA>()) {
             tile_poll<NR, TA>(impl, nimp, FWD ? y : z, cap, s0, nr, vals, nrows, A.info, A.poll_sleep, &s_abort);
         } else {
             // Nothing is outstanding here but this wave's stores.  Saying so keeps
@@ -1957,9 +1958,9 @@ static hipError_t tiled_launch(const SolveArgs &A, const TileArgs &T0, bool fwd,
         if (e != hipSuccess) return e;
     }
     if (fwd)
-        hipLaunchKernelGGL((k_solve_tiled<G, J, NR, TV, TA, true>), dim3(T.ntiles), dim3(kTileBlock), lds, s, A, T);
+        hipLaunchKernelGGL((k_solve_tiled<G, J, NR, TV, TA, true>), dim3(T.ntiles), dim3(solve_block<TA>()), lds, s, A, T);
     else
-        hipLaunchKernelGGL((k_solve_tiled<G, J, NR, TV, TA, false>), dim3(T.ntiles), dim3(kTileBlock), lds, s, A, T);
+        hipLaunchKernelGGL((k_solve_tiled<G, J, NR, TV, TA, false>), dim3(T.ntiles), dim3(solve_block<TA>()), lds, s, A, T);
     return hipGetLastError();
 }
 
