@@ -36,11 +36,11 @@ HBM_PEAK_GBS = 8000.0
 # scaled by what the same counters read for the calibration copy kernels.  Valid
 # only for the kernel source it was taken with: a different hash reports null.
 PMC_TRAFFIC = dict(
-    kernels_sha256="e20153ce18581786c854980f12582f94e24c689791e0e94dd8c97985607d50e2",
-    fetch_scale=1.9986, write_scale=0.9944,
-    forward=dict(f64=(208997, 66128), f32=(157593, 50675)),
-    backward=dict(f64=(211047, 94264), f32=(150090, 77577)),
-    factor=(281772, 146456),
+    kernels_sha256="b136f002ce897dd123c272786faeda185782d3eab4750d69cd244a416bc9dc32",
+    fetch_scale=1.9987, write_scale=0.9945,
+    forward=dict(f64=(209072, 66171), f32=(159291, 50766)),
+    backward=dict(f64=(211735, 94306), f32=(150668, 77626)),
+    factor=(281816, 146456),
 )
 
 

@@ -1219,8 +1219,24 @@ __global__ __launch_bounds__(solve_block<TA>()) void k_solve_tiled(SolveArgs A, 
     // stage the tile (every thread issues all loads of a step before it uses any):
     // position -> slot, imports, then per row its id, pivot, dependency slots and
     // values
-    lds_copy<kStageCopy, B>(ps, T.pslot + pbase, npos);
-    lds_copy<kStageCopy, B>(impl, T.imp + ibase, nimp);
+    // position and import tables: when each fits one step of the block, their loads
+    // are issued here and stored after the row loop has issued its own, so the
+    // three chains share one memory latency
+    constexpr int PC = 2;   // elements per thread of each table in that case
+    const bool one_step = npos <= B * PC && nimp <= B * PC;
+    int16_t pv_pos[PC];
+    int32_t pv_imp[PC];
+    if (one_step) {
+#pragma unroll
+        for (int u = 0; u < PC; ++u) {
+            const int i = threadIdx.x + u * B;
+            pv_pos[u] = i < npos ? T.pslot[pbase + i] : (int16_t)0;
+            pv_imp[u] = i < nimp ? T.imp[ibase + i] : 0;
+        }
+    } else {
+        lds_copy<kStageCopy, B>(ps, T.pslot + pbase, npos);
+        lds_copy<kStageCopy, B>(impl, T.imp + ibase, nimp);
+    }
     constexpr int SR = kStageRows;
     constexpr int SJ = G == 1 ? 4 : 2;   // entries per lane fetched with the batched loads
     constexpr int GROUPS = B / G;
@@ -1270,6 +1286,14 @@ __global__ __launch_bounds__(solve_block<TA>()) void k_solve_tiled(SolveArgs A, 
                 es[sl * K + j] = (uint16_t)(on ? T.sci[p] : zero);
                 ev[sl * K + j] = on ? (TA)load_val(val, A.vmap ? A.vmap[p] : p) : (TA)0;
             }
+        }
+    }
+    if (one_step) {
+#pragma unroll
+        for (int u = 0; u < PC; ++u) {
+            const int i = threadIdx.x + u * B;
+            if (i < npos) ps[i] = pv_pos[u];
+            if (i < nimp) impl[i] = pv_imp[u];
         }
     }
     if constexpr (!FWD) {
