@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 # scaled by what the same counters read for the calibration copy kernels.  Valid
 # only for the kernel source it was taken with: a different hash reports null.
 PMC_TRAFFIC = dict(
-    kernels_sha256="b136f002ce897dd123c272786faeda185782d3eab4750d69cd244a416bc9dc32",
+    kernels_sha256="a9eee54bbd52941742d98d9ad40a00e2d4778a8832d729e5a085bc9e9ac1763b",
     fetch_scale=1.9987, write_scale=0.9945,
     forward=dict(f64=(209072, 66171), f32=(159291, 50766)),
     backward=dict(f64=(211735, 94306), f32=(150668, 77626)),

@@ -1218,10 +1218,9 @@ __global__ __launch_bounds__(solve_block<TA>()) void k_solve_tiled(SolveArgs A, 
 
     // stage the tile (every thread issues all loads of a step before it uses any):
     // position -> slot, imports, then per row its id, pivot, dependency slots and
-    // values
-    // position and import tables: when each fits one step of the block, their loads
-    // are issued here and stored after the row loop has issued its own, so the
-    // three chains share one memory latency
+    // values.  When the position and import tables each fit one step of the block,
+    // their loads are issued here and stored after the row loop has issued its
+    // own, so the three chains share one memory latency.
     constexpr int PC = 2;   // elements per thread of each table in that case
     const bool one_step = npos <= B * PC && nimp <= B * PC;
     int16_t pv_pos[PC];
@@ -1365,9 +1364,11 @@ __global__ __launch_bounds__(solve_block<TA>()) void k_solve_tiled(SolveArgs A, 
         if (wave == solve_waves<TA>()) {
             tile_poll<NR, TA>(impl, nimp, FWD ? y : z, cap, s0, nr, vals, nrows, A.info, A.poll_sleep, &s_abort);
         } else {
-            // Nothing is outstanding here but this wave's stores.  Saying so keeps
-            // the compiler from waiting on them inside the compute loop (its
-            // bookkeeping otherwise carries the poller's loads around the pass loop).
+            // One wait per pass for all this wave has outstanding (the staging
+            // loads have landed; at most the previous pass's stores remain).  It
+            // clears the compiler's bookkeeping, which otherwise carries the
+            // poller's loads around the pass loop and waits on the wave's own
+            // stores inside the compute loop, once per chunk.
             __builtin_amdgcn_s_waitcnt(0);
             tile_compute<G, J, NR, TA, FWD>(A, vals, ev, es, ps, rowid, orows, piv, rhs, K, npos, wave, gi, t, s0, nr,
                                             &s_abort);
