@@ -182,6 +182,40 @@ def test_tau_dropping_bounds(seed):
     assert (f.stat == 1).any() or tau < 1e-2
 
 
+def load_tau_cases():
+    with open(os.path.join(GOLDEN, "tau_norm.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", load_tau_cases(), ids=lambda c: c["name"])
+def test_tau_norm_hand_worked(case):
+    # tau_r = tau * ||A(row,:)||_2 (reading of Sec. I's ILU(tau)); each case sits where
+    # the 1-norm, the infinity norm or a pivot-only test would decide the other way.
+    n = case["n"]
+    rp = np.array(case["row_ptr"], np.int32)
+    ci = np.array(case["col_idx"], np.int32)
+    val = np.array(case["val"], np.float64)
+    an = O.analyze(n, rp, ci)
+    assert an.perm.tolist() == case["perm"]
+    f = O.factor(an, val, tau=case["tau"])
+    assert f.status == O.OK
+    assert f.stat.tolist() == case["state"]
+    expect = np.array([float(Fraction(s)) for s in case["lu_val"]])
+    np.testing.assert_allclose(f.val, expect, rtol=4e-16, atol=0)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_row_tau_is_two_norm_of_the_original_row(seed):
+    # the threshold of permuted row r is tau times the Euclidean norm of row perm[r] of A
+    # as given (LAPACK's norm, not a sum re-typed here)
+    rng = np.random.default_rng(900 + seed)
+    A = synth.random_sparse(int(rng.integers(20, 60)), 0.12, rng)
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    tau = float(rng.uniform(1e-3, 1e-1))
+    expect = tau * np.linalg.norm(dense(A)[an.perm], axis=1)
+    np.testing.assert_allclose(O.row_tau(an, A.val, tau), expect, rtol=1e-15, atol=0)
+
+
 def test_tau_infinite_is_jacobi():
     rng = np.random.default_rng(7)
     A = synth.random_sparse(40, 0.1, rng)
@@ -708,6 +742,85 @@ def test_apply_lowp_bounds():
         x = O.apply(an, low, b, prec=prec)
         xr = O.apply(an, widen(low), b)
         assert np.abs(x - xr).max() <= 1e-5 * np.abs(xr).max()
+
+
+def _exact_vec(strs, shape):
+    return np.array([float(Fraction(s)) for s in strs], np.float64).reshape(shape)
+
+
+def load_lowp_cases():
+    with open(os.path.join(GOLDEN, "lowp_apply.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("case", load_lowp_cases(), ids=lambda c: c["name"])
+def test_apply_lowp_hand_worked(case, prec):
+    # FP32 arithmetic in ascending column order and a true FP32 division, bit for bit
+    n, nrhs = case["n"], case["nrhs"]
+    val = np.array([float(Fraction(s)) for s in case["val"]])
+    an = O.analyze(n, np.array(case["row_ptr"], np.int32), np.array(case["col_idx"], np.int32))
+    f = O.factor(an, val)
+    assert f.status == O.OK
+    low = O.cast_f32(f.val) if prec == "f32" else O.cast_bf16(f.val)
+    b = _exact_vec(case["b"], (n, nrhs))
+    x = O.apply(an, low, b if nrhs > 1 else b[:, 0], prec=prec).reshape(n, nrhs)
+    expect = _exact_vec(case["x_f32"], (n, nrhs))
+    assert np.array_equal(x.view(np.uint64), expect.view(np.uint64)), (x, expect)
+    if "x_f64" in case:
+        x64 = O.apply(an, f.val, b if nrhs > 1 else b[:, 0]).reshape(n, nrhs)
+        assert np.array_equal(x64, _exact_vec(case["x_f64"], (n, nrhs)))
+        assert not np.array_equal(x64, x)   # the case separates FP32 from FP64 arithmetic
+
+
+def _serial_f32_apply(an, low32, b):
+    # textbook forward and back substitution on numpy float32 scalars (every product,
+    # sum and division rounded to FP32), columns ascending, in the level ordering
+    n = an.n
+    f = np.float32
+    y = [f(0)] * n
+    z = [f(0)] * n
+    bp = b[an.perm]
+    for r in range(n):
+        acc = f(0)
+        for p in range(an.lu_rp[r], an.diag_pos[r]):
+            acc = f(acc + f(low32[p] * y[an.lu_ci[p]]))
+        y[r] = f(f(bp[r]) - acc)
+    for r in range(n - 1, -1, -1):
+        acc = f(0)
+        for p in range(an.diag_pos[r] + 1, an.lu_rp[r + 1]):
+            acc = f(acc + f(low32[p] * z[an.lu_ci[p]]))
+        z[r] = f(f(y[r] - acc) / low32[an.diag_pos[r]])
+    x = np.empty(n, np.float64)
+    x[an.perm] = np.array(z, np.float32).astype(np.float64)
+    return x
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_apply_lowp_serial_float32(seed):
+    # n <= 64: the oracle's FP32/BF16 apply equals a serial numpy.float32 substitution
+    # bit for bit, on inputs with wide value ranges where FP32 and FP64 arithmetic
+    # give visibly different results
+    rng = np.random.default_rng(950 + seed)
+    n = int(rng.integers(20, 65))
+    A = synth.random_sparse(n, 0.15, rng)
+    A.val[:] = A.val * np.exp(rng.uniform(-6, 6, A.nnz))
+    for i in range(n):   # keep it factorable: dominant diagonal
+        s, e = A.row_ptr[i], A.row_ptr[i + 1]
+        d = s + int(np.searchsorted(A.col_idx[s:e], i))
+        A.val[d] = 1.5 * np.abs(A.val[s:e]).sum() + 1.0
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    f = O.factor(an, A.val)
+    assert f.status == O.OK
+    b = rng.uniform(-1, 1, n) * np.exp(rng.uniform(-8, 8, n))
+    for prec in ("f32", "bf16"):
+        low = O.cast_f32(f.val) if prec == "f32" else O.cast_bf16(f.val)
+        w32 = low if prec == "f32" else (low.astype(np.uint32) << 16).view(np.float32)
+        x = O.apply(an, low, b, prec=prec)
+        xr = _serial_f32_apply(an, w32, b)
+        assert np.array_equal(x.view(np.uint64), xr.view(np.uint64))
+        x64 = O.apply(an, w32.astype(np.float64), b)
+        assert np.abs(x64 - x).max() > 0.0   # FP64 arithmetic would be told apart
 
 
 def test_spmv_library_and_integer_exact():
