@@ -47,7 +47,8 @@ enum {
     ILU_ERR_BREAKDOWN = 8,    /* Krylov breakdown (zero curvature) */
     ILU_ERR_STATE = 9,        /* call out of order (e.g. apply before factor) */
     ILU_ERR_UNSUPPORTED = 10, /* size or row length beyond what the kernels support */
-    ILU_ERR_TIMEOUT = 11      /* a dependency wait in a persistent kernel exceeded its bound */
+    ILU_ERR_TIMEOUT = 11      /* a dependency wait in a persistent kernel exceeded its bound (or a
+                                 test raised the abort flag through "force_abort") */
 };
 
 /* Dependency pattern used to build level sets (Sec. III; Sec. VII recommends the
@@ -241,9 +242,19 @@ ilu_status ilu_copy_factor_prec(ilu_handle h, int32_t prec, void *host);
  * ILU_PREC_F32 (float).  fac_prec selects the stored factor: F64 computes in
  * FP64; F32/BF16 compute in FP32 (b rounded to FP32, x rounded to vec_prec).
  * x may alias b.  Asynchronous.  Errors: ILU_ERR_STATE (no factor / cast),
- * ILU_ERR_ARG. */
+ * ILU_ERR_ARG, ILU_ERR_UNSUPPORTED (a user tile size whose tiles do not fit LDS).
+ * A dependency wait that expires on the device (ILU_ERR_TIMEOUT) cannot be
+ * returned by this asynchronous call: its outputs hold NaNs, the next call on the
+ * handle re-arms the intermediates, and ilu_get_status (or the Krylov driver
+ * that made the call) reports ILU_ERR_TIMEOUT. */
 ilu_status ilu_apply(ilu_handle h, const void *b, void *x, int32_t nrhs, int64_t ld,
                      int32_t fac_prec, int32_t vec_prec, int32_t flags, hipStream_t stream);
+
+/* Synchronises `stream` and reports whether an apply on h (ilu_apply,
+ * ilu_apply_ex, ilu_apply_adjoint, graph replays) has timed out since the last
+ * query: ILU_ERR_TIMEOUT (after re-arming the handle's intermediates and clearing
+ * the record), else ILU_OK. */
+ilu_status ilu_get_status(ilu_handle h, hipStream_t stream);
 
 /* FP64 apply with explicit factor values and the forward intermediate:
  * lu_val (device, nnz_lu, may be NULL = the handle's factor), y_out (device,
@@ -291,14 +302,17 @@ ilu_status ilu_set_values(ilu_handle h, const double *a_val, hipStream_t stream)
  * fac_prec; stops when the recursive residual norm / ||b|| <= rtol, then checks
  * the true residual (restarting the recurrence from it if it misses).
  * b, x device [n] (original ordering unless ILU_PERMUTED_SPACE).  Synchronous.
- * info may be NULL.  Returns ILU_OK, ILU_ERR_NOCONV or ILU_ERR_BREAKDOWN. */
+ * info may be NULL.  Returns ILU_OK, ILU_ERR_NOCONV or ILU_ERR_BREAKDOWN, or
+ * ILU_ERR_TIMEOUT when an apply inside it timed out (checked at every scalar
+ * readback). */
 ilu_status ilu_solve_pcg(ilu_handle h, const double *b, double *x, double rtol, int32_t maxit,
                          int32_t fac_prec, int32_t flags, ilu_solve_info *info, hipStream_t stream);
 
 /* Right-preconditioned flexible GMRES(restart) with modified Gram-Schmidt and
  * Givens rotations, x0 = 0; a cycle ends at |g_{j+1}| / ||b|| <= rtol, happy
  * breakdown or `restart` steps; the true residual decides whether to restart.
- * maxit bounds the total Arnoldi steps.  Synchronous. */
+ * maxit bounds the total Arnoldi steps.  Synchronous.  ILU_ERR_TIMEOUT as for
+ * ilu_solve_pcg. */
 ilu_status ilu_solve_gmres(ilu_handle h, const double *b, double *x, double rtol, int32_t restart,
                            int32_t maxit, int32_t fac_prec, int32_t flags, ilu_solve_info *info,
                            hipStream_t stream);
@@ -328,17 +342,26 @@ ilu_status ilu_get_schedule(ilu_handle h, int32_t *factor_sched, int32_t *solve_
  * is read from global memory when its turn comes; same results).  Readable as well:
  * "nstreams" (task streams = XCDs found), "factor_tcap" (LDS entries staged per
  * factor row), "factor_tiled" (1 if the tiled factor can run on this handle:
- * rows of at most 32 entries and tiles that fit LDS).  Unknown keys give
+ * rows of at most 32 entries and tiles that fit LDS).  "force_abort" (set only;
+ * failure-path tests): 1 raises the device abort flag now, as an apply that timed
+ * out and was not yet reported leaves it; 2 raises it inside the next apply, after
+ * that apply's guard, so its kernels leave through their bounded waits (outputs
+ * NaN, ilu_get_status then reports ILU_ERR_TIMEOUT).  Unknown keys give
  * ILU_ERR_ARG. */
 ilu_status ilu_set_tuning(ilu_handle h, const char *key, int64_t value);
 ilu_status ilu_get_tuning(ilu_handle h, const char *key, int64_t *value);
 
-/* Times the candidate schedules (level vs sync-free, lanes per row) of the factor
- * (when a_val, device values in input order, is given; re-run with tau = 0 and the
- * last k) and of the FP64 apply on this handle's matrix, and keeps the fastest.
- * Requires a factor; leaves a factor of a_val in the handle.  Synchronous.
- * results (may be NULL) receives up to `cap` rows of {stage (0 factor, 1 apply),
- * sched, lanes, microseconds} as doubles; *n_results the row count. */
+/* Times the candidate schedules of the FP64 apply and, when a_val (device values
+ * in input order) is given, of the factor on this handle's matrix, and keeps the
+ * fastest: level launches and sync-free launches with 1x and 2x the lanes per row
+ * the rows need, and tiled launches at tile sizes 128, 256, 512 and 1024 rows (and
+ * the current size).  The tile size is the level-merge threshold (a tile merges
+ * consecutive levels of up to that many rows into one workgroup); one tiling serves
+ * both stages, chosen by the apply.  The factor is re-run with the last call's k,
+ * tau and flags, so the handle keeps the same factor (every schedule gives the same
+ * bits).  Requires a factor.  Synchronous.  results (may be NULL) receives up to
+ * `cap` rows of {stage (0 factor, 1 apply), sched, lanes or tile rows (tiled),
+ * microseconds} as doubles; *n_results the row count. */
 ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, double *results, int32_t cap,
                     int32_t *n_results, hipStream_t stream);
 
@@ -352,12 +375,17 @@ enum {
     ILU_STAGE_FORWARD = 1,    /* forward triangular-solve kernel(s) (L, or U^T in the adjoint) */
     ILU_STAGE_BACKWARD = 2,   /* backward triangular-solve kernel(s) (U, or L^T in the adjoint) */
     ILU_STAGE_SPMV = 3,       /* spmv kernel */
-    ILU_STAGE_COUNT = 4
+    ILU_STAGE_FACTOR_CALL = 4,/* everything one ilu_factor call launches: guard, status reset, row
+                                 thresholds, arming, the factor kernel(s), drop fix-up, the spmv
+                                 value gather and the casts (not the status readback) */
+    ILU_STAGE_APPLY_CALL = 5, /* everything one apply (or adjoint solve pair) launches: guard and
+                                 both triangular solves */
+    ILU_STAGE_COUNT = 6
 };
 
 /* While enabled, every stage launch on this handle is bracketed by a pair of HIP
  * events recorded on the launch's own stream (pool of `capacity` pairs; launches
- * beyond it are not timed).  ilu_profile_read synchronises the events, adds the
+ * beyond it are not timed); the *_CALL stages bracket whole calls around them.  ilu_profile_read synchronises the events, adds the
  * elapsed times per stage into ms[ILU_STAGE_COUNT] (milliseconds) and
  * launches[ILU_STAGE_COUNT], and clears the record.  Either output may be NULL. */
 ilu_status ilu_profile_enable(ilu_handle h, int32_t enable, int32_t capacity);

@@ -21,13 +21,15 @@ PERMUTED_SPACE = 1
 SCHED_AUTO, SCHED_LEVEL, SCHED_SYNCFREE, SCHED_TILED = 0, 1, 2, 3
 CAST_F32, CAST_BF16, FACTOR_MODIFIED = 1, 2, 0x100
 ORDER_NATURAL, ORDER_RCM = 0, 1
-STAGE_FACTOR, STAGE_FORWARD, STAGE_BACKWARD, STAGE_SPMV, STAGE_COUNT = 0, 1, 2, 3, 4
-STAGES = ["factor", "forward", "backward", "spmv"]
+STAGE_FACTOR, STAGE_FORWARD, STAGE_BACKWARD, STAGE_SPMV, STAGE_FACTOR_CALL, STAGE_APPLY_CALL = 0, 1, 2, 3, 4, 5
+STAGE_COUNT = 6
+STAGES = ["factor", "forward", "backward", "spmv", "factor_call", "apply_call"]
 
 # exported symbols that include/javelin.h declares
 SYMBOLS = [
     "ilu_analyze", "ilu_analyze_batched", "ilu_batch_offsets", "ilu_get_info", "ilu_copy_schedule", "ilu_copy_tiles",
-    "ilu_factor", "ilu_factor_values", "ilu_copy_factor", "ilu_copy_factor_prec", "ilu_apply", "ilu_apply_ex",
+    "ilu_factor", "ilu_factor_values", "ilu_copy_factor", "ilu_copy_factor_prec", "ilu_apply", "ilu_get_status",
+    "ilu_apply_ex",
     "ilu_apply_adjoint", "ilu_apply_graph_create", "ilu_graph_launch", "ilu_graph_destroy", "ilu_spmv", "ilu_set_values", "ilu_solve_pcg", "ilu_solve_gmres",
     "ilu_set_schedule", "ilu_get_schedule", "ilu_set_tuning", "ilu_get_tuning", "ilu_tune", "ilu_profile_enable", "ilu_profile_read", "ilu_calibrate",
     "ilu_destroy", "ilu_version",
@@ -89,6 +91,7 @@ def load(path: str = LIB_PATH):
         "ilu_copy_factor": [H, vp, vp],
         "ilu_copy_factor_prec": [H, i32, vp],
         "ilu_apply": [H, vp, vp, i32, i64, i32, i32, i32, vp],
+        "ilu_get_status": [H, vp],
         "ilu_apply_ex": [H, vp, vp, vp, vp, i32, i64, i32, vp],
         "ilu_apply_adjoint": [H, vp, vp, vp, vp, vp, vp, i32, i64, vp],
         "ilu_apply_graph_create": [H, vp, vp, i32, i64, i32, i32, i32, C.POINTER(vp)],

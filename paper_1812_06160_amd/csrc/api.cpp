@@ -59,25 +59,24 @@ std::vector<int32_t> make_tasks(const std::vector<int32_t> &level_ptr, int per) 
     return t;
 }
 
-void Profiler::begin(int st, hipStream_t s) {
-    if (!enabled || 2 * (used + 1) > pool.size()) return;
-    if (hipEventRecord(pool[2 * used], s) != hipSuccess) return;
+int Profiler::begin(int st, hipStream_t s) {
+    if (!enabled || 2 * (used + 1) > pool.size()) return -1;
+    if (hipEventRecord(pool[2 * used], s) != hipSuccess) return -1;
     stage.push_back(st);
+    closed.push_back(0);
+    return (int)used++;
 }
 
-void Profiler::end(hipStream_t s) {
-    if (!enabled || stage.size() != used + 1) return;
-    if (hipEventRecord(pool[2 * used + 1], s) != hipSuccess) {
-        stage.pop_back();
-        return;
-    }
-    ++used;
+void Profiler::end(int pair, hipStream_t s) {
+    if (pair < 0 || (size_t)pair >= used) return;
+    if (hipEventRecord(pool[2 * pair + 1], s) == hipSuccess) closed[pair] = 1;
 }
 
 void Profiler::release() {
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
     pool.clear();
     stage.clear();
+    closed.clear();
     used = 0;
     enabled = false;
 }
@@ -193,9 +192,33 @@ hipError_t ilu_handle_s::rearm(hipStream_t s) {
     return e;
 }
 
+// resets the factor's slots (bad row, abort, drop count); the timeout count and
+// the guard's counter are left alone
 hipError_t ilu_handle_s::reset_info(hipStream_t s) {
-    static const int32_t init[kInfoSlots] = {INT_MAX, 0, 0, 0, 0, 0, 0, 0};
+    static const int32_t init[kInfoTimeouts] = {INT_MAX, 0, 0, 0};
     return hipMemcpyAsync(d_info, init, sizeof(init), hipMemcpyHostToDevice, s);
+}
+
+hipError_t ilu_handle_s::guard(hipStream_t s) {
+    return launch_solve_guard(d_info, (uint64_t *)y64, (uint64_t *)z64, (int64_t)H.n * cap64, (uint32_t *)y32,
+                              (uint32_t *)z32, (int64_t)H.n * cap32, s);
+}
+
+// Reads the abort flag and the timeout count (synchronises s).  Either one set:
+// re-arms the intermediates, clears both and returns ILU_ERR_TIMEOUT.
+ilu_status ilu_handle_s::take_timeout(hipStream_t s, const char *who) {
+    int32_t w[kInfoSlots];
+    hipError_t e = hipMemcpyAsync(w, d_info, sizeof(w), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, who);
+    if (!w[kInfoAbort] && !w[kInfoTimeouts]) return ILU_OK;
+    static const int32_t zero2[2] = {0, 0};
+    e = rearm(s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&d_info[kInfoAbort], zero2, 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&d_info[kInfoTimeouts], zero2, 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, who);
+    return fail(ILU_ERR_TIMEOUT, std::string(who) + ": a dependency wait of an apply expired (its outputs are invalid)");
 }
 
 static const int32_t kDefaultTileRows = 512;
@@ -456,6 +479,7 @@ static ilu_status finish_analysis(ilu_handle_s *h) {
     h->d_row_tau = (double *)p;
     if ((e = h->alloc_bytes(&p, kInfoSlots * 4)) != hipSuccess) return hip_fail(e, "alloc info");
     h->d_info = (int32_t *)p;
+    if ((e = hipMemset(h->d_info, 0, kInfoSlots * 4)) != hipSuccess) return hip_fail(e, "zero info");
     if ((e = h->alloc_bytes(&p, kDotParts * 8 + 64 * 8)) != hipSuccess) return hip_fail(e, "alloc dot work");
     h->d_dotwork = (double *)p;
     const size_t cbytes = (size_t)kPasses * kStreams * kCounterStride * 4;
@@ -667,6 +691,10 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
         info->bad_row = info->bad_row_original = info->bad_matrix = -1;
         info->n_dropped = 0;
     }
+    // an apply that timed out and was never reported leaves its intermediates
+    // half published: re-arm them before the factor clears the abort flag
+    const int pcall = h->prof.begin(ILU_STAGE_FACTOR_CALL, s);
+    if ((e = h->guard(s)) != hipSuccess) return hip_fail(e, "ilu_factor: guard");
     if ((e = h->reset_info(s)) != hipSuccess) return hip_fail(e, "ilu_factor: info reset");
     const bool use_tau = tau > 0.0;
     if (use_tau && (e = launch_row_tau(H.n, h->d_in_rp, a_val, h->d_perm, tau, h->d_row_tau, s)) != hipSuccess)
@@ -719,9 +747,9 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
         if ((e = launch_fill_u64((uint64_t *)h->d_lu, kPending64, H.lu_rp[H.n], s)) != hipSuccess)
             return hip_fail(e, "ilu_factor: arm");
         if ((e = launch_zero_counters(T.counter, s)) != hipSuccess) return hip_fail(e, "ilu_factor: claims");
-        h->prof.begin(ILU_STAGE_FACTOR, s);
+        const int pp_ = h->prof.begin(ILU_STAGE_FACTOR, s);
         e = launch_factor_tiled(A, T, h->ftiles.lanes, s);
-        h->prof.end(s);
+        h->prof.end(pp_, s);
         if (e != hipSuccess) return hip_fail(e, "ilu_factor: tiled launch");
     } else if (sf) {
         const TaskList *tl = h->task_list(kTasksForward, lanes);
@@ -731,20 +759,20 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
         if ((e = h->prepare_claims(kPassFactor, tl, &A.claims, s)) != hipSuccess) return hip_fail(e, "ilu_factor: claims");
         A.nstreams = h->nstreams;
         A.poll_sleep = h->poll_sleep;
-        h->prof.begin(ILU_STAGE_FACTOR, s);
+        const int pp_ = h->prof.begin(ILU_STAGE_FACTOR, s);
         e = long_rows ? launch_factor_long(A, true, h->grid_syncfree(tl), s)
                       : launch_factor(A, lanes, true, h->grid_syncfree(tl), s);
-        h->prof.end(s);
+        h->prof.end(pp_, s);
         if (e != hipSuccess) return hip_fail(e, "ilu_factor: launch");
     } else {
-        h->prof.begin(ILU_STAGE_FACTOR, s);
+        const int pp_ = h->prof.begin(ILU_STAGE_FACTOR, s);
         for (int l = 0; l < H.n_levels; ++l) {
             A.row_begin = H.level_ptr[l];
             A.row_end = H.level_ptr[l + 1];
             e = long_rows ? launch_factor_long(A, false, 0, s) : launch_factor(A, lanes, false, 0, s);
             if (e != hipSuccess) return hip_fail(e, "ilu_factor: launch");
         }
-        h->prof.end(s);
+        h->prof.end(pp_, s);
     }
     h->tracked = use_tau || A.use_flev;
     if (h->tracked) {
@@ -775,6 +803,7 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
         }
         if ((e = launch_cast_bf16(H.lu_rp[H.n], h->d_lu, h->d_lu16, s)) != hipSuccess) return hip_fail(e, "cast bf16");
     }
+    h->prof.end(pcall, s);
     int32_t hinfo[kInfoSlots];
     if ((e = hipMemcpyAsync(hinfo, h->d_info, sizeof(hinfo), hipMemcpyDeviceToHost, s)) != hipSuccess)
         return hip_fail(e, "ilu_factor: info readback");
@@ -782,6 +811,8 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
     h->has32 = casts & 1;
     h->has16 = (casts & 2) != 0;
     h->k_used = k;
+    h->tau_used = tau;
+    h->flags_used = casts;
     int64_t dropped = 0;
     std::memcpy(&dropped, &hinfo[kInfoDropLo], 8);
     if (info) info->n_dropped = dropped;
@@ -867,11 +898,42 @@ namespace jv {
 // One forward + backward pass.  view: 0 = the factor (L then U), 1 = the
 // transposed factor (U^T then L^T, adjoint).
 ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int vec, const void *b, void *x,
-                      void *y_out, void *z_out, int nrhs, int64_t ld, int flags, hipStream_t s) {
+                      void *y_out, void *z_out, int nrhs, int64_t ld, int flags, hipStream_t s, const SolveWork *ws) {
     const HostAnalysis &H = h->H;
     const int pc = prec == ILU_PREC_F64 ? 0 : 1;
     hipError_t e;
-    if ((e = h->ensure_workspace(nrhs, pc, s)) != hipSuccess) return hip_fail(e, "workspace");
+    if (!ws && (e = h->ensure_workspace(nrhs, pc, s)) != hipSuccess) return hip_fail(e, "workspace");
+    const int pcall = h->prof.begin(ILU_STAGE_APPLY_CALL, s);
+    // an earlier apply that timed out: re-arm, clear and count it (reported by
+    // ilu_get_status and the Krylov drivers)
+    if ((e = h->guard(s)) != hipSuccess) return hip_fail(e, "solve guard");
+    if (ws && ws->fill) {
+        // caller-provided intermediates start all pending
+        const int64_t cnt = (int64_t)H.n * ws->cap;
+        e = pc == 0 ? launch_fill_u64((uint64_t *)ws->y, kPending64, cnt, s)
+                    : launch_fill_u32((uint32_t *)ws->y, kPending32, cnt, s);
+        if (e == hipSuccess)
+            e = pc == 0 ? launch_fill_u64((uint64_t *)ws->z, kPending64, cnt, s)
+                        : launch_fill_u32((uint32_t *)ws->z, kPending32, cnt, s);
+        if (e != hipSuccess) return hip_fail(e, "solve workspace fill");
+    }
+    if (h->force_abort) {
+        h->force_abort = false;
+        if ((e = launch_raise_abort(h->d_info, s)) != hipSuccess) return hip_fail(e, "raise abort");
+    }
+    // after a completed forward pass, an error leaves y published: re-arm it
+    auto after_fwd = [&](ilu_status st, int pass) -> ilu_status {
+        if (pass == 1) {
+            if (ws) {
+                const int64_t cnt = (int64_t)H.n * ws->cap;
+                (void)(pc == 0 ? launch_fill_u64((uint64_t *)ws->y, kPending64, cnt, s)
+                               : launch_fill_u32((uint32_t *)ws->y, kPending32, cnt, s));
+            } else {
+                (void)h->rearm(s);
+            }
+        }
+        return st;
+    };
     const bool sf = h->sched_solve != ILU_SCHED_LEVEL;
     const int lanes = h->lanes_solve;
     SolveArgs A{};
@@ -880,12 +942,12 @@ ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int 
     A.perm = (flags & ILU_PERMUTED_SPACE) ? nullptr : h->d_perm;
     A.b = b;
     A.x = x;
-    A.y = pc == 0 ? h->y64 : h->y32;
-    A.z = pc == 0 ? h->z64 : h->z32;
+    A.y = ws ? ws->y : (pc == 0 ? h->y64 : h->y32);
+    A.z = ws ? ws->z : (pc == 0 ? h->z64 : h->z32);
     A.y_out = y_out;
     A.z_out = z_out;
     A.ld = ld;
-    A.cap = pc == 0 ? h->cap64 : h->cap32;
+    A.cap = ws ? ws->cap : (pc == 0 ? h->cap64 : h->cap32);
     A.nrhs = nrhs;
     A.info = h->d_info;
     for (int pass = 0; pass < 2; ++pass) {
@@ -932,36 +994,42 @@ ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int 
             ta.kmax = T.kmax;
             ta.unit = T.unit;
             if ((e = h->prepare_tile_claims(fwd ? kPassTileF : kPassTileB, &ta, s)) != hipSuccess)
-                return hip_fail(e, "tile claims");
+                return after_fwd(hip_fail(e, "tile claims"), pass);
             A.poll_sleep = h->poll_sleep;
-            h->prof.begin(fwd ? ILU_STAGE_FORWARD : ILU_STAGE_BACKWARD, s);
+            const int pp_ = h->prof.begin(fwd ? ILU_STAGE_FORWARD : ILU_STAGE_BACKWARD, s);
             e = launch_solve_tiled(A, ta, fwd, prec, vec, s);
-            h->prof.end(s);
+            h->prof.end(pp_, s);
             if (e == hipErrorInvalidValue)
-                return fail(ILU_ERR_UNSUPPORTED, "tiled solve: the largest tile does not fit LDS (lower tile_rows)");
-            if (e != hipSuccess) return hip_fail(e, "tiled solve launch");
+                return after_fwd(fail(ILU_ERR_UNSUPPORTED, "tiled solve: the largest tile does not fit LDS (lower tile_rows)"),
+                                 pass);
+            if (e != hipSuccess) return after_fwd(hip_fail(e, "tiled solve launch"), pass);
         } else if (sf) {
-            const TaskList *tl = h->task_list(which, lanes);
-            if (!tl) return fail(ILU_ERR_NOMEM, "task list");
-            const int pass = view == 0 ? (fwd ? kPassForward : kPassBackward) : (fwd ? kPassTForward : kPassTBackward);
-            if ((e = h->prepare_claims(pass, tl, &A.claims, s)) != hipSuccess) return hip_fail(e, "solve claims");
+            const TaskList *tl = ws ? h->cached_task_list(which, lanes) : h->task_list(which, lanes);
+            if (!tl)
+                return after_fwd(ws ? fail(ILU_ERR_STATE, "solve: the sync-free task list is built by a first ilu_apply")
+                                    : fail(ILU_ERR_NOMEM, "task list"),
+                                 pass);
+            const int cpass = view == 0 ? (fwd ? kPassForward : kPassBackward) : (fwd ? kPassTForward : kPassTBackward);
+            if ((e = h->prepare_claims(cpass, tl, &A.claims, s)) != hipSuccess)
+                return after_fwd(hip_fail(e, "solve claims"), pass);
             A.nstreams = h->nstreams;
             A.poll_sleep = h->poll_sleep;
-            h->prof.begin(fwd ? ILU_STAGE_FORWARD : ILU_STAGE_BACKWARD, s);
+            const int pp_ = h->prof.begin(fwd ? ILU_STAGE_FORWARD : ILU_STAGE_BACKWARD, s);
             e = launch_solve(A, fwd, prec, vec, lanes, true, h->grid_syncfree(tl), s);
-            h->prof.end(s);
-            if (e != hipSuccess) return hip_fail(e, "solve launch");
+            h->prof.end(pp_, s);
+            if (e != hipSuccess) return after_fwd(hip_fail(e, "solve launch"), pass);
         } else {
-            h->prof.begin(fwd ? ILU_STAGE_FORWARD : ILU_STAGE_BACKWARD, s);
+            const int pp_ = h->prof.begin(fwd ? ILU_STAGE_FORWARD : ILU_STAGE_BACKWARD, s);
             for (size_t l = 0; l + 1 < lptr->size(); ++l) {
                 A.row_begin = (*lptr)[l];
                 A.row_end = (*lptr)[l + 1];
                 if ((e = launch_solve(A, fwd, prec, vec, lanes, false, 0, s)) != hipSuccess)
-                    return hip_fail(e, "solve launch");
+                    return after_fwd(hip_fail(e, "solve launch"), pass);
             }
-            h->prof.end(s);
+            h->prof.end(pp_, s);
         }
     }
+    h->prof.end(pcall, s);
     return ILU_OK;
 }
 
@@ -989,6 +1057,12 @@ extern "C" ilu_status ilu_apply(ilu_handle h, const void *b, void *x, int32_t nr
     }
     return run_solves(h, 0, val, fac_prec, vec_prec == ILU_PREC_F64 ? 0 : 1, b, x, nullptr, nullptr, nrhs, ld, flags,
                       s);
+}
+
+extern "C" ilu_status ilu_get_status(ilu_handle h, hipStream_t s) {
+    if (!h) return fail(ILU_ERR_ARG, "ilu_get_status: NULL handle");
+    if (h->host_only) return ILU_OK;
+    return h->take_timeout(s, "ilu_get_status");
 }
 
 extern "C" ilu_status ilu_apply_ex(ilu_handle h, const double *lu_val, const double *b, double *x, double *y_out,
@@ -1096,9 +1170,9 @@ extern "C" ilu_status ilu_spmv(ilu_handle h, double alpha, const double *x, doub
     A.heavy_min = h->spmv_heavy_min;
     A.heavy = h->d_spmv_heavy;
     A.nheavy = h->n_spmv_heavy;
-    h->prof.begin(ILU_STAGE_SPMV, s);
+    const int pp_ = h->prof.begin(ILU_STAGE_SPMV, s);
     hipError_t e = launch_spmv(A, h->lanes_spmv, s);
-    h->prof.end(s);
+    h->prof.end(pp_, s);
     if (e != hipSuccess) return hip_fail(e, "ilu_spmv");
     return ILU_OK;
 }
@@ -1198,6 +1272,20 @@ extern "C" ilu_status ilu_set_tuning(ilu_handle h, const char *key, int64_t valu
         h->factor_staged = value != 0;
         return ILU_OK;
     }
+    if (k == "force_abort") {
+        // failure-path tests: 1 raises the abort flag now (as an apply that timed
+        // out and was not reported would leave it); 2 raises it inside the next
+        // apply, after its guard, so its kernels leave through their bounded waits
+        if (value != 1 && value != 2) return fail(ILU_ERR_ARG, "ilu_set_tuning: force_abort must be 1 or 2");
+        if (h->host_only) return fail(ILU_ERR_STATE, "ilu_set_tuning: host-only analysis");
+        if (value == 2) {
+            h->force_abort = true;
+            return ILU_OK;
+        }
+        hipError_t e = launch_raise_abort(h->d_info, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        return e == hipSuccess ? ILU_OK : hip_fail(e, "ilu_set_tuning: force_abort");
+    }
     return fail(ILU_ERR_ARG, "ilu_set_tuning: unknown key " + k);
 }
 
@@ -1237,6 +1325,7 @@ extern "C" ilu_status ilu_profile_enable(ilu_handle h, int32_t enable, int32_t c
         }
     }
     h->prof.stage.clear();
+    h->prof.closed.clear();
     h->prof.used = 0;
     h->prof.enabled = true;
     return ILU_OK;
@@ -1247,6 +1336,7 @@ extern "C" ilu_status ilu_profile_read(ilu_handle h, double *ms, int64_t *launch
     double acc[ILU_STAGE_COUNT] = {0};
     int64_t cnt[ILU_STAGE_COUNT] = {0};
     for (size_t i = 0; i < h->prof.used; ++i) {
+        if (!h->prof.closed[i]) continue;
         hipError_t e = hipEventSynchronize(h->prof.pool[2 * i + 1]);
         if (e != hipSuccess) return hip_fail(e, "ilu_profile_read");
         float t = 0.f;
@@ -1256,6 +1346,7 @@ extern "C" ilu_status ilu_profile_read(ilu_handle h, double *ms, int64_t *launch
         cnt[h->prof.stage[i]] += 1;
     }
     h->prof.stage.clear();
+    h->prof.closed.clear();
     h->prof.used = 0;
     for (int i = 0; i < ILU_STAGE_COUNT; ++i) {
         if (ms) ms[i] = acc[i];

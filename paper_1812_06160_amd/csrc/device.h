@@ -21,6 +21,8 @@ enum : int {
     kInfoBadKey = 0,      // atomicMin of 2*row + (0 zero pivot | 1 non-finite); INT32_MAX if none
     kInfoAbort = 1,       // a bounded wait expired: every persistent kernel stops
     kInfoDropLo = 2,      // dropped-entry count (uint64 in slots 2-3)
+    kInfoTimeouts = 4,    // applies whose start found the abort flag raised (cleared by a status query)
+    kInfoGuardDone = 5,   // blocks of the solve guard that have finished re-arming
     kInfoSlots = 8
 };
 
@@ -184,6 +186,15 @@ struct SpmvArgs {
 hipError_t launch_fill_u64(uint64_t *p, uint64_t value, int64_t count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, int64_t count, hipStream_t s);
 hipError_t launch_zero_counters(int32_t *counters, hipStream_t s);
+// Start of every apply: when the device abort flag is raised (a bounded wait of an
+// earlier call expired), re-arms the published intermediates (y/z of both
+// precision classes: n64 FP64 and n32 FP32 elements each), clears the flag and
+// counts the event in info[kInfoTimeouts]; otherwise every block returns at once.
+hipError_t launch_solve_guard(int32_t *info, uint64_t *y64, uint64_t *z64, int64_t n64, uint32_t *y32, uint32_t *z32,
+                              int64_t n32, hipStream_t s);
+// Raises the device abort flag from the stream (failure-path tests: every wait of
+// the kernels that follow gives up within its next 64 polls).
+hipError_t launch_raise_abort(int32_t *info, hipStream_t s);
 hipError_t launch_row_tau(int32_t n, const int32_t *in_rp, const double *a, const int32_t *perm, double tau,
                           double *row_tau, hipStream_t s);
 hipError_t launch_gather(int64_t m, const int32_t *src, const double *a, double *out, hipStream_t s);

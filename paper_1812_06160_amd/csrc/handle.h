@@ -16,14 +16,16 @@ namespace jv {
 
 enum { kTasksForward = 0, kTasksBackward = 1, kTasksTForward = 2, kTasksTBackward = 3 };
 
-// Event pairs around stage launches (ilu_profile_*).
+// Event pairs around stage launches (ilu_profile_*).  Pairs may nest: a whole
+// call is bracketed around the brackets of its kernels.
 struct Profiler {
     bool enabled = false;
     std::vector<hipEvent_t> pool;      // 2 * capacity events
-    std::vector<int> stage;            // stage of each recorded pair
-    size_t used = 0;
-    void begin(int st, hipStream_t s);
-    void end(hipStream_t s);
+    std::vector<int> stage;            // stage of each pair handed out
+    std::vector<char> closed;          // its end event was recorded
+    size_t used = 0;                   // pairs handed out
+    int begin(int st, hipStream_t s);  // pair index, -1 when not recording
+    void end(int pair, hipStream_t s);
     void release();
 };
 
@@ -122,7 +124,10 @@ struct ilu_handle_s {
     // state
     bool host_only = false;
     bool factored = false, factor_ok = false, tracked = false, bvals = false, has32 = false, has16 = false;
-    int32_t k_used = 0;
+    bool force_abort = false;          // raise the abort flag inside the next apply (tests)
+    int32_t k_used = 0;                // k, tau and flags of the last factor (the tuner re-runs it)
+    double tau_used = 0.0;
+    int32_t flags_used = 0;
     int32_t sched_factor = ILU_SCHED_SYNCFREE, sched_solve = ILU_SCHED_SYNCFREE;
     int32_t lanes_factor = 8, lanes_solve = 4, lanes_spmv = 8;
 
@@ -132,6 +137,16 @@ struct ilu_handle_s {
     hipError_t ensure_workspace(int nrhs, int prec_class, hipStream_t s);
     hipError_t rearm(hipStream_t s);
     hipError_t reset_info(hipStream_t s);
+    // launches the solve guard over the handle's intermediates (see launch_solve_guard)
+    hipError_t guard(hipStream_t s);
+    // synchronous check of the abort flag and the timeout count (ILU_ERR_TIMEOUT
+    // after re-arming and clearing them)
+    ilu_status take_timeout(hipStream_t s, const char *who);
+    // the task list if it has been built already (no allocation), else nullptr
+    const jv::TaskList *cached_task_list(int which, int lanes) const {
+        auto it = tasks.find(which * 1000 + lanes);
+        return it == tasks.end() ? nullptr : &it->second;
+    }
     // fills the claims of one sync-free pass (launching a counter reset when needed)
     hipError_t prepare_claims(int pass, const jv::TaskList *tl, jv::Claims *c, hipStream_t s);
     // blocks of a sync-free launch: every stream's slots plus one spare per stream
@@ -150,6 +165,14 @@ inline void allocs_erase(ilu_handle_s *h, void *p) {
 }
 
 namespace jv {
+// Published intermediates supplied by the caller instead of the handle's: y and z
+// of [n][cap] elements of the accumulate type; fill: arm them at the start.
+struct SolveWork {
+    void *y, *z;
+    int32_t cap;
+    bool fill;
+};
 ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int vec, const void *b, void *x,
-                      void *y_out, void *z_out, int nrhs, int64_t ld, int flags, hipStream_t s);
+                      void *y_out, void *z_out, int nrhs, int64_t ld, int flags, hipStream_t s,
+                      const SolveWork *ws = nullptr);
 }

@@ -209,6 +209,37 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t value, int64_t count) {
     for (; i < count; i += stride) p[i] = value;
 }
 
+// Re-arms the solve intermediates when the abort flag is up; the last block to
+// finish clears the flag and counts the timeout.  Nothing else writes the flag
+// while this kernel runs (stream order), so every block reads the same value and
+// either all blocks take part or none does.
+__global__ void k_solve_guard(int32_t *info, uint64_t *y64, uint64_t *z64, int64_t n64, uint32_t *y32,
+                              uint32_t *z32, int64_t n32) {
+    if (!aborted(info)) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n64; i += stride) {
+        y64[i] = kPending64;
+        z64[i] = kPending64;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n32; i += stride) {
+        y32[i] = kPending32;
+        z32[i] = kPending32;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&info[kInfoGuardDone], 1) == (int)gridDim.x - 1) {
+            info[kInfoGuardDone] = 0;
+            atomicAdd(&info[kInfoTimeouts], 1);
+            __hip_atomic_store(&info[kInfoAbort], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+__global__ void k_raise_abort(int32_t *info) {
+    if (threadIdx.x == 0) __hip_atomic_store(&info[kInfoAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // tau_r = tau * ||A(perm[r], :)||_2, squares summed in the input order of the row
 __global__ void k_row_tau(int32_t n, const int32_t *__restrict__ in_rp, const double *__restrict__ a,
                           const int32_t *__restrict__ perm, double tau, double *__restrict__ row_tau) {
@@ -1733,6 +1764,18 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t value, int64_t count, hipStream
 
 hipError_t launch_zero_counters(int32_t *counters, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, s, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_guard(int32_t *info, uint64_t *y64, uint64_t *z64, int64_t n64, uint32_t *y32, uint32_t *z32,
+                              int64_t n32, hipStream_t s) {
+    hipLaunchKernelGGL(k_solve_guard, dim3(256), dim3(kBlock), 0, s, info, y64, z64, y64 ? n64 : 0, y32, z32,
+                       y32 ? n32 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_raise_abort(int32_t *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_raise_abort, dim3(1), dim3(64), 0, s, info);
     return hipGetLastError();
 }
 

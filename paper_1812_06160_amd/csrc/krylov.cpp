@@ -62,10 +62,17 @@ ilu_status spmv(Ctx &c, double alpha, const double *x, double beta, double *y) {
     return ilu_spmv(c.h, alpha, x, beta, y, 1, 1, ILU_PERMUTED_SPACE, c.s);
 }
 
+// Reads `count` device scalars, and with them the abort flag and the timeout
+// count of the applies: a preconditioner apply whose wait expired makes the
+// iterate meaningless, so the driver stops with ILU_ERR_TIMEOUT.
 ilu_status readback(Ctx &c, const double *dev, double *host, int count) {
+    int32_t w[kInfoSlots];
     hipError_t e = hipMemcpyAsync(host, dev, sizeof(double) * count, hipMemcpyDeviceToHost, c.s);
+    if (e == hipSuccess) e = hipMemcpyAsync(w, c.h->d_info, sizeof(w), hipMemcpyDeviceToHost, c.s);
     if (e == hipSuccess) e = hipStreamSynchronize(c.s);
-    return e == hipSuccess ? ILU_OK : hip_fail(e, "krylov readback");
+    if (e != hipSuccess) return hip_fail(e, "krylov readback");
+    if (w[kInfoAbort] || w[kInfoTimeouts]) return c.h->take_timeout(c.s, "krylov");
+    return ILU_OK;
 }
 
 #define CHK(x)                          \

@@ -1,8 +1,15 @@
-// Autotuner: times the launch schemes (one launch per level vs one persistent
-// sync-free launch, and for the apply also the tiled launch) and the lanes per
-// row of the factor and of the FP64 apply on the handle's own matrix, and keeps
-// the fastest.  The factor is deterministic, so
-// re-running it with the same values reproduces the same factor bits.
+// Autotuner: times the launch schemes of the factor and of the FP64 apply on the
+// handle's own matrix and keeps the fastest.  The candidates are one launch per
+// level and one persistent sync-free launch (each with 1x and 2x the lanes per
+// row the longest row needs), and the tiled launch at tile sizes of 128, 256,
+// 512 and 1024 rows (and the handle's own size).  The tile size is this design's
+// level-merge threshold: a tile merges consecutive levels of up to that many rows
+// into one workgroup whose dependencies go through LDS.  One tiling serves the
+// factor and the solves, so the apply -- called many times per factor -- picks
+// it; the factor then picks its scheme with that tiling in place.  Every
+// schedule computes the same bits (the factor reproduces the serial up-looking
+// order on all of them), so re-running the caller's factor -- same k, tau and
+// flags -- leaves the handle with the factor it had.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,18 +36,29 @@ struct Timer {
     }
 };
 
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
 }  // namespace
 
 extern "C" ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, double *results, int32_t cap,
                                int32_t *n_results, hipStream_t s) {
     if (!h) return fail(ILU_ERR_ARG, "ilu_tune: NULL handle");
+    if (h->host_only) return fail(ILU_ERR_STATE, "ilu_tune: host-only analysis");
     if (!h->factored) return fail(ILU_ERR_STATE, "ilu_tune: requires a factor");
     if (reps < 1) reps = 3;
     const HostAnalysis &H = h->H;
     const int32_t save_fs = h->sched_factor, save_ss = h->sched_solve;
     const int32_t save_lf = h->lanes_factor, save_ls = h->lanes_solve;
+    const int32_t save_tr = h->tile_rows;
+    // the caller's factor: same k, tau and flags (casts, modified form)
     const int32_t k = h->k_used;
-    const int32_t casts = (h->has32 ? 1 : 0) | (h->has16 ? 2 : 0);
+    const double tau = h->tau_used;
+    const int32_t fflags = h->flags_used;
     std::vector<double> rows;
     Timer T;
     auto time_it = [&](auto &&fn, double *us) -> ilu_status {
@@ -57,23 +75,107 @@ extern "C" ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, 
         *us = 1e3 * ms / reps;
         return ILU_OK;
     };
-    // ---- factor ----
-    int best_fs = save_fs, best_lf = save_lf;
+    auto restore = [&](ilu_status st) {
+        h->sched_factor = save_fs;
+        h->sched_solve = save_ss;
+        h->lanes_factor = save_lf;
+        h->lanes_solve = save_ls;
+        if (h->tile_rows != save_tr) (void)h->make_tiles(save_tr, false);
+        return st;
+    };
+    auto factor = [&]() { return ilu_factor(h, a_val, k, tau, fflags, nullptr, s); };
+    DevBuf buf;
+    hipError_t e = hipMalloc(&buf.p, (size_t)H.n * 16);
+    if (e != hipSuccess) return hip_fail(e, "ilu_tune: buffers");
+    double *b = (double *)buf.p, *x = b + H.n;
+    if ((e = launch_fill_u64((uint64_t *)b, 0x3FF0000000000000ull, H.n, s)) != hipSuccess)   // b = 1
+        return hip_fail(e, "ilu_tune: fill");
+    auto apply = [&]() { return ilu_apply(h, b, x, 1, 1, ILU_PREC_F64, ILU_PREC_F64, ILU_PERMUTED_SPACE, s); };
+
+    // ---- tiled: tile sizes (the level-merge threshold), apply and factor ----
+    std::vector<int32_t> sizes = {128, 256, 512, 1024};
+    if (std::find(sizes.begin(), sizes.end(), save_tr) == sizes.end()) sizes.push_back(save_tr);
+    struct TileRes {
+        int32_t rows;
+        double apply_us, factor_us;
+    };
+    std::vector<TileRes> tres;
+    for (int32_t tr : sizes) {
+        if (tr > std::max<int32_t>(H.n, 16) && tr != save_tr) continue;
+        ilu_status st = h->make_tiles(tr, false);
+        if (st != ILU_OK) return restore(st);
+        TileRes r{tr, -1.0, -1.0};
+        h->sched_solve = ILU_SCHED_TILED;
+        st = time_it(apply, &r.apply_us);
+        if (st == ILU_ERR_UNSUPPORTED) r.apply_us = -1.0;   // tiles beyond LDS
+        else if (st != ILU_OK) return restore(st);
+        if (a_val && h->ftiles_ok && k == H.k_max) {
+            h->sched_factor = ILU_SCHED_TILED;
+            st = time_it(factor, &r.factor_us);
+            if (st != ILU_OK) return restore(st);
+        }
+        if (r.apply_us >= 0) rows.insert(rows.end(), {1.0, (double)ILU_SCHED_TILED, (double)tr, r.apply_us});
+        if (r.factor_us >= 0) rows.insert(rows.end(), {0.0, (double)ILU_SCHED_TILED, (double)tr, r.factor_us});
+        tres.push_back(r);
+    }
+    h->sched_factor = save_fs;
+    // ---- level and sync-free applies, lanes per row ----
+    double best_apply = 1e300;
+    int best_ss = save_ss, best_ls = save_ls;
+    int32_t best_tr = save_tr;
+    for (const TileRes &r : tres)
+        if (r.apply_us >= 0 && r.apply_us < best_apply) {
+            best_apply = r.apply_us;
+            best_ss = ILU_SCHED_TILED;
+            best_tr = r.rows;
+        }
+    for (int sched = ILU_SCHED_LEVEL; sched <= ILU_SCHED_SYNCFREE; ++sched)
+        for (int lanes = 4; lanes <= 64; lanes *= 2) {
+            h->sched_solve = sched;
+            h->lanes_solve = lanes;
+            double us = 0;
+            ilu_status st = time_it(apply, &us);
+            if (st != ILU_OK) return restore(st);
+            rows.insert(rows.end(), {1.0, (double)sched, (double)lanes, us});
+            if (us < best_apply) {
+                best_apply = us;
+                best_ss = sched;
+                best_ls = lanes;
+            }
+        }
+    h->sched_solve = best_ss;
+    h->lanes_solve = best_ss == ILU_SCHED_TILED ? save_ls : best_ls;
+    // the tiling of the chosen apply (or, when the apply is not tiled, the one the
+    // tiled factor liked best)
+    if (best_ss != ILU_SCHED_TILED) {
+        double bf = 1e300;
+        for (const TileRes &r : tres)
+            if (r.factor_us >= 0 && r.factor_us < bf) {
+                bf = r.factor_us;
+                best_tr = r.rows;
+            }
+    }
+    if (h->tile_rows != best_tr) {
+        ilu_status st = h->make_tiles(best_tr, false);
+        if (st != ILU_OK) return restore(st);
+    }
+    // ---- factor: tiled on the chosen tiling vs sync-free and level launches ----
     if (a_val) {
         double best = 1e300;
-        const int lmin = std::max(4, save_lf);
+        int best_fs = save_fs, best_lf = save_lf;
+        for (const TileRes &r : tres)
+            if (r.rows == best_tr && r.factor_us >= 0) {
+                best = r.factor_us;
+                best_fs = ILU_SCHED_TILED;
+            }
+        const int lmin = std::max(4, std::min(save_lf, 64));
         for (int sched = ILU_SCHED_LEVEL; sched <= ILU_SCHED_SYNCFREE; ++sched)
             for (int lanes = lmin; lanes <= 64 && lanes <= 2 * lmin; lanes *= 2) {
                 h->sched_factor = sched;
                 h->lanes_factor = lanes;
                 double us = 0;
-                ilu_status st =
-                    time_it([&]() { return ilu_factor(h, a_val, k, 0.0, casts, nullptr, s); }, &us);
-                if (st != ILU_OK) {
-                    h->sched_factor = save_fs;
-                    h->lanes_factor = save_lf;
-                    return st;
-                }
+                ilu_status st = time_it(factor, &us);
+                if (st != ILU_OK) return restore(st);
                 rows.insert(rows.end(), {0.0, (double)sched, (double)lanes, us});
                 if (us < best) {
                     best = us;
@@ -82,63 +184,12 @@ extern "C" ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, 
                 }
             }
         h->sched_factor = best_fs;
-        h->lanes_factor = best_lf;
-        // leave a factor equal to the caller's (tau = 0 and the handle's k)
+        h->lanes_factor = best_fs == ILU_SCHED_TILED ? save_lf : best_lf;
+        // leave the caller's factor computed on the chosen schedule
+        ilu_status st = factor();
+        if (st != ILU_OK) return restore(st);
     }
-    // ---- apply (FP64, one right-hand side, permuted space) ----
-    void *buf = nullptr;
-    hipError_t e = hipMalloc(&buf, (size_t)H.n * 16);
-    if (e != hipSuccess) return hip_fail(e, "ilu_tune: buffers");
-    double *b = (double *)buf, *x = b + H.n;
-    if ((e = launch_fill_u64((uint64_t *)b, 0x3FF0000000000000ull, H.n, s)) != hipSuccess) {   // b = 1
-        (void)hipFree(buf);
-        return hip_fail(e, "ilu_tune: fill");
-    }
-    double best = 1e300;
-    int best_ss = save_ss, best_ls = save_ls;
-    for (int sched = ILU_SCHED_LEVEL; sched <= ILU_SCHED_SYNCFREE; ++sched)
-        for (int lanes = 4; lanes <= 64; lanes *= 2) {
-            h->sched_solve = sched;
-            h->lanes_solve = lanes;
-            double us = 0;
-            ilu_status st = time_it(
-                [&]() { return ilu_apply(h, b, x, 1, 1, ILU_PREC_F64, ILU_PREC_F64, ILU_PERMUTED_SPACE, s); }, &us);
-            if (st != ILU_OK) {
-                (void)hipFree(buf);
-                h->sched_solve = save_ss;
-                h->lanes_solve = save_ls;
-                return st;
-            }
-            rows.insert(rows.end(), {1.0, (double)sched, (double)lanes, us});
-            if (us < best) {
-                best = us;
-                best_ss = sched;
-                best_ls = lanes;
-            }
-        }
-    {   // tiled (one candidate: the handle's current tiles); not every tiling fits
-        h->sched_solve = ILU_SCHED_TILED;
-        double us = 0;
-        ilu_status st = time_it(
-            [&]() { return ilu_apply(h, b, x, 1, 1, ILU_PREC_F64, ILU_PREC_F64, ILU_PERMUTED_SPACE, s); }, &us);
-        if (st == ILU_OK) {
-            rows.insert(rows.end(), {1.0, (double)ILU_SCHED_TILED, 0.0, us});
-            if (us < best) {
-                best = us;
-                best_ss = ILU_SCHED_TILED;
-                best_ls = save_ls;
-            }
-        } else if (st != ILU_ERR_UNSUPPORTED) {
-            (void)hipFree(buf);
-            h->sched_solve = save_ss;
-            h->lanes_solve = save_ls;
-            return st;
-        }
-    }
-    (void)hipStreamSynchronize(s);
-    (void)hipFree(buf);
-    h->sched_solve = best_ss;
-    h->lanes_solve = best_ls;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "ilu_tune: synchronize");
     const int nr = (int)(rows.size() / 4);
     if (n_results) *n_results = nr;
     if (results && cap > 0) std::memcpy(results, rows.data(), sizeof(double) * 4 * std::min(cap, nr));

@@ -199,6 +199,11 @@ class Ilu:
                                    L.PERMUTED_SPACE if permuted else 0, _stream()), "ilu_apply")
         return x
 
+    def status(self):
+        """Synchronises the current stream; raises IluError (ILU_ERR_TIMEOUT) if an
+        apply on this handle timed out since the last query."""
+        L.check(self.lib.ilu_get_status(self.h, _stream()), "ilu_get_status")
+
     def apply_graph(self, b, x, prec="f64", permuted=False):
         """An ApplyGraph replaying x = M^{-1} b (fixed tensors b and x)."""
         return ApplyGraph(self, b, x, prec, permuted)

@@ -94,6 +94,39 @@ def test_batch512_full(jv):
         assert relerr(x32[ro[i]:ro[i + 1]], xr32) <= 2.0 ** -12
 
 
+def test_batch512_adjoint_full(jv):
+    # the backward of the 512-matrix batch: b-bar and the L/U-value gradients of 12
+    # sampled matrices against the oracle's adjoint of each matrix alone (4 RHS)
+    mats, rhs = synth.workload(5)
+    hb = jv.Ilu.batched(mats)
+    vals = np.concatenate([m.val for m in mats])
+    hb.factor(dev(vals), casts=())
+    ro, _ = hb.batch_offsets()
+    b = np.concatenate(rhs)
+    gx = np.random.default_rng(31).uniform(-1, 1, b.shape)
+    x, y = hb.apply_ex(dev(b))
+    gb, glu = hb.adjoint(dev(gx), x, y)
+    x, y, gb, glu = (t.cpu().numpy() for t in (x, y, gb, glu))
+    sb = hb.schedule()
+    perm, rp = sb["perm"], sb["lu_row_ptr"]
+    rng = np.random.default_rng(0)
+    for i in sorted(rng.choice(len(mats), 12, replace=False)):
+        M = mats[i]
+        an = O.analyze(M.n, M.row_ptr, M.col_idx)
+        f = O.factor(an, M.val)
+        xr, yr = O.apply(an, f.val, rhs[i], want_y=True)
+        assert relerr(x[ro[i]:ro[i + 1]], xr) <= 1e-12
+        gbr, glur = O.adjoint(an, f.val, gx[ro[i]:ro[i + 1]], xr, yr)
+        assert relerr(gb[ro[i]:ro[i + 1]], gbr) <= 1e-12
+        # the batch keeps each matrix's rows (in its level order) and their entries
+        rows = np.nonzero((perm >= ro[i]) & (perm < ro[i + 1]))[0]
+        loc = an.iperm[perm[rows] - ro[i]]
+        assert relerr(y[rows], yr[loc]) <= 1e-12
+        got = np.concatenate([glu[rp[r]:rp[r + 1]] for r in rows])
+        want = np.concatenate([glur[an.lu_rp[q]:an.lu_rp[q + 1]] for q in loc])
+        assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+
+
 def test_laplace3d_128_modified_full(jv):
     # modified ILU(0) at full size: bit-exact with the oracle, and since L U has A's
     # row sums, M^{-1} (A 1) is the vector of ones up to rounding
