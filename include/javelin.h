@@ -256,6 +256,22 @@ ilu_status ilu_apply(ilu_handle h, const void *b, void *x, int32_t nrhs, int64_t
  * the record), else ILU_OK. */
 ilu_status ilu_get_status(ilu_handle h, hipStream_t stream);
 
+/* ilu_apply for callers that cannot allocate device memory during the call (code
+ * under graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results (bit for bit), with the published intermediates y and z
+ * ([n][nrhs] each, of the accumulate type: 8 bytes per element for F64 factors, 4
+ * for F32/BF16) in a static device workspace of 64 MiB that the library holds on
+ * every device it runs on until the process ends, instead of the buffers
+ * ilu_apply allocates on first use.  Calls no hipMalloc/hipFree.  The workspace is
+ * shared by every call on a device: calls that overlap on one device (any
+ * handle, any stream) race; it is re-armed at the start of each call.  The
+ * sync-free schedule needs the task list a first ilu_apply of the handle built
+ * (ILU_ERR_STATE otherwise); the tiled and level schedules need nothing.
+ * Errors: as ilu_apply, and ILU_ERR_ARG when 2 * n * nrhs * element size exceeds
+ * 64 MiB (n * nrhs above 4,194,304 with F64 factors, 8,388,608 with F32/BF16). */
+ilu_status ilu_apply_noalloc(ilu_handle h, const void *b, void *x, int32_t nrhs, int64_t ld,
+                             int32_t fac_prec, int32_t vec_prec, int32_t flags, hipStream_t stream);
+
 /* FP64 apply with explicit factor values and the forward intermediate:
  * lu_val (device, nnz_lu, may be NULL = the handle's factor), y_out (device,
  * [n][ld] in the level ordering, may be NULL) receives y = L^{-1} P b. */

@@ -29,7 +29,7 @@ STAGES = ["factor", "forward", "backward", "spmv", "factor_call", "apply_call"]
 SYMBOLS = [
     "ilu_analyze", "ilu_analyze_batched", "ilu_batch_offsets", "ilu_get_info", "ilu_copy_schedule", "ilu_copy_tiles",
     "ilu_factor", "ilu_factor_values", "ilu_copy_factor", "ilu_copy_factor_prec", "ilu_apply", "ilu_get_status",
-    "ilu_apply_ex",
+    "ilu_apply_noalloc", "ilu_apply_ex",
     "ilu_apply_adjoint", "ilu_apply_graph_create", "ilu_graph_launch", "ilu_graph_destroy", "ilu_spmv", "ilu_set_values", "ilu_solve_pcg", "ilu_solve_gmres",
     "ilu_set_schedule", "ilu_get_schedule", "ilu_set_tuning", "ilu_get_tuning", "ilu_tune", "ilu_profile_enable", "ilu_profile_read", "ilu_calibrate",
     "ilu_destroy", "ilu_version",
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH):
         "ilu_copy_factor_prec": [H, i32, vp],
         "ilu_apply": [H, vp, vp, i32, i64, i32, i32, i32, vp],
         "ilu_get_status": [H, vp],
+        "ilu_apply_noalloc": [H, vp, vp, i32, i64, i32, i32, i32, vp],
         "ilu_apply_ex": [H, vp, vp, vp, vp, i32, i64, i32, vp],
         "ilu_apply_adjoint": [H, vp, vp, vp, vp, vp, vp, i32, i64, vp],
         "ilu_apply_graph_create": [H, vp, vp, i32, i64, i32, i32, i32, C.POINTER(vp)],
