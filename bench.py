@@ -135,6 +135,8 @@ def main():
                     help="launch scheme of the factor")
     ap.add_argument("--solve-sched", default="tiled", choices=["tiled", "syncfree", "level"],
                     help="launch scheme of the triangular solves")
+    ap.add_argument("--tune", action="append", default=[], metavar="KEY=VALUE",
+                    help="a tuning knob of the handles (ilu_set_tuning), repeatable")
     ap.add_argument("--workload", default="laplace3d_128",
                     choices=["laplace3d_128", "laplace2d_64", "convdiff3d_96", "random_1m", "batch512", "heavy_1m",
                              "ordering"])
@@ -162,6 +164,9 @@ def main():
     ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
     t_analyze = time.perf_counter() - t0
     ilu.set_schedule(args.sched, args.solve_sched)
+    for kv in args.tune:
+        key, val = kv.split("=")
+        ilu.set_tuning(key, int(val))
     info = ilu.info()
     sched = ilu.schedule()
     nnz_l = int((sched["diag_pos"] - sched["lu_row_ptr"][:-1]).sum())
@@ -178,6 +183,9 @@ def main():
     A3, b3 = synth.workload(3)
     log(f"convdiff3d_96: n={A3.n} nnz={A3.nnz}; analysis ...")
     cd = jv.Ilu(A3.n, A3.row_ptr, A3.col_idx, k_max=1)
+    for kv in args.tune:
+        key, val = kv.split("=")
+        cd.set_tuning(key, int(val))
     a3_d = torch.from_numpy(A3.val).cuda()
     b3_d = torch.from_numpy(b3).cuda()
     cd_info = cd.info()

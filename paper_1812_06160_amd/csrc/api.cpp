@@ -85,6 +85,7 @@ void Profiler::release() {
 
 ilu_handle_s::~ilu_handle_s() {
     prof.release();
+
     for (void *p : allocs) (void)hipFree(p);
     for (auto &kv : tasks) {
         (void)hipFree(kv.second.ptr);
@@ -350,6 +351,7 @@ ilu_status ilu_handle_s::make_tiles(int32_t rows, bool shrink) {
 // entries and a tile image that fits LDS (the modified form's masks included).
 ilu_status ilu_handle_s::make_factor_tiles() {
     ftiles_ok = false;
+    arm_built = false;
     ftset_own = false;
     if (H.max_row_lu > kFactorMaxLanes || tiles[0].ntiles == 0) return ILU_OK;
     const int32_t lanes = H.max_row_lu <= 8 ? 8 : H.max_row_lu <= 16 ? 16 : 32;
@@ -393,6 +395,21 @@ ilu_status ilu_handle_s::make_factor_tiles() {
         return e;
     };
     hipError_t e;
+    {   // the U parts other tiles import (diagonal entry, length), once each
+        std::vector<std::pair<int32_t, int32_t>> ranges;
+        for (size_t i = 0; i + 3 < ftiles.imp.size(); i += 4) ranges.push_back({ftiles.imp[i], ftiles.imp[i + 1]});
+        std::sort(ranges.begin(), ranges.end());
+        ranges.erase(std::unique(ranges.begin(), ranges.end()), ranges.end());
+        std::vector<int32_t> flat;
+        flat.reserve(2 * ranges.size());
+        for (const auto &r : ranges) {
+            flat.push_back(r.first);
+            flat.push_back(r.second);
+        }
+        if ((e = put(d_arm, flat)) != hipSuccess) return hip_fail(e, "factor tiles: upload");
+        n_arm = (int32_t)ranges.size();
+        arm_built = true;
+    }
     if ((e = put(dft.meta, ftiles.meta)) != hipSuccess || (e = put(dft.off, ftiles.off)) != hipSuccess ||
         (e = put(dft.lptr, ftiles.lptr)) != hipSuccess || (e = put(dft.dloc, ftiles.dloc)) != hipSuccess ||
         (e = put(dft.dflag, ftiles.dflag)) != hipSuccess || (e = put(dft.match, ftiles.match)) != hipSuccess ||
@@ -486,6 +503,9 @@ static ilu_status finish_analysis(ilu_handle_s *h) {
     if ((e = h->alloc_bytes(&p, cbytes)) != hipSuccess) return hip_fail(e, "alloc counters");
     h->d_counters = (int32_t *)p;
     if ((e = hipMemset(h->d_counters, 0, cbytes)) != hipSuccess) return hip_fail(e, "zero counters");
+    // the permuted copy of A has the factor's pattern when there is no fill (the
+    // tiled factor then writes its values)
+    h->b_same = H.b_rp == H.lu_rp && H.b_ci == H.lu_ci;
     std::vector<int8_t> xmap;
     if ((e = xcc_streams(&xmap, &h->nstreams)) != hipSuccess) return hip_fail(e, "xcc probe");
     UPLOAD_ONE(h->d_xcc_stream, xmap);
@@ -691,12 +711,30 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
         info->bad_row = info->bad_row_original = info->bad_matrix = -1;
         info->n_dropped = 0;
     }
-    // an apply that timed out and was never reported leaves its intermediates
-    // half published: re-arm them before the factor clears the abort flag
-    const int pcall = h->prof.begin(ILU_STAGE_FACTOR_CALL, s);
-    if ((e = h->guard(s)) != hipSuccess) return hip_fail(e, "ilu_factor: guard");
-    if ((e = h->reset_info(s)) != hipSuccess) return hip_fail(e, "ilu_factor: info reset");
     const bool use_tau = tau > 0.0;
+    // the tiled factor covers ILU(k, tau), plain or modified, at k = k_max (no
+    // absent entries); anything else runs the sync-free factor
+    const bool tiled = h->sched_factor == ILU_SCHED_TILED && h->ftiles_ok && k == H.k_max;
+    // storage copies are allocated before the first launch of the call
+    void *p;
+    if ((casts & ILU_CAST_F32) && !h->d_lu32) {
+        if ((e = h->alloc_bytes(&p, (size_t)H.lu_rp[H.n] * 4)) != hipSuccess) return hip_fail(e, "alloc f32");
+        h->d_lu32 = (float *)p;
+    }
+    if ((casts & ILU_CAST_BF16) && !h->d_lu16) {
+        if ((e = h->alloc_bytes(&p, (size_t)H.lu_rp[H.n] * 2)) != hipSuccess) return hip_fail(e, "alloc bf16");
+        h->d_lu16 = (uint16_t *)p;
+    }
+    int32_t *tile_counter = h->d_counters + (size_t)kPassFactorTile * kStreams * kCounterStride;
+    const int pcall = h->prof.begin(ILU_STAGE_FACTOR_CALL, s);
+    // an apply that timed out and was never reported leaves its intermediates
+    // half published: the prologue re-arms them before the abort flag is cleared,
+    // resets the status slots and the tiled factor's claim counter
+    if ((e = launch_factor_prologue(h->d_info, (uint64_t *)h->y64, (uint64_t *)h->z64, (int64_t)H.n * h->cap64,
+                                    (uint32_t *)h->y32, (uint32_t *)h->z32, (int64_t)H.n * h->cap32,
+                                    tiled ? tile_counter : nullptr, s)) != hipSuccess)
+        return hip_fail(e, "ilu_factor: prologue");
+
     if (use_tau && (e = launch_row_tau(H.n, h->d_in_rp, a_val, h->d_perm, tau, h->d_row_tau, s)) != hipSuccess)
         return hip_fail(e, "ilu_factor: row tau");
     FactorArgs A{};
@@ -717,9 +755,6 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
     A.tcap = (h->factor_staged && factor_lds_bytes(lanes, h->factor_tcap)) ? h->factor_tcap : 0;
     A.max_lower = H.max_lower_lu;
     A.lcap = long_rows ? H.max_row_lu : 0;
-    // the tiled factor covers ILU(k, tau), plain or modified, at k = k_max (no
-    // absent entries); anything else runs the sync-free factor
-    bool tiled = h->sched_factor == ILU_SCHED_TILED && h->ftiles_ok && !A.use_flev;
     if (tiled) {
         const TileSet &T0 = h->ftset_own ? h->ftset : h->tiles[0];
         const ilu_handle_s::DevTiles &D = h->ftset_own ? h->dftset : h->dtiles[0];
@@ -742,11 +777,17 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
         T.max_lents = h->ftiles.max_lents;
         T.max_pos = T0.max_pos;
         T.max_imps = T0.max_imps;
-        T.counter = h->d_counters + (size_t)kPassFactorTile * kStreams * kCounterStride;
+        T.counter = tile_counter;
         A.poll_sleep = h->poll_sleep;
-        if ((e = launch_fill_u64((uint64_t *)h->d_lu, kPending64, H.lu_rp[H.n], s)) != hipSuccess)
-            return hip_fail(e, "ilu_factor: arm");
-        if ((e = launch_zero_counters(T.counter, s)) != hipSuccess) return hip_fail(e, "ilu_factor: claims");
+        // only U parts that other tiles import are polled: arm just those
+        e = h->arm_built ? launch_arm_ranges((uint64_t *)h->d_lu, reinterpret_cast<const int2 *>(h->d_arm), h->n_arm, s)
+                     : launch_fill_u64((uint64_t *)h->d_lu, kPending64, H.lu_rp[H.n], s);
+        if (e != hipSuccess) return hip_fail(e, "ilu_factor: arm");
+        // the storage copies are written as each row is published, the spmv
+        // operand as the rows' input values are staged
+        A.lu32 = (casts & ILU_CAST_F32) ? h->d_lu32 : nullptr;
+        A.lu16 = (casts & ILU_CAST_BF16) ? h->d_lu16 : nullptr;
+        A.bval = h->b_same ? h->d_bval : nullptr;
         const int pp_ = h->prof.begin(ILU_STAGE_FACTOR, s);
         e = launch_factor_tiled(A, T, h->ftiles.lanes, s);
         h->prof.end(pp_, s);
@@ -785,24 +826,15 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
             hipSuccess)
             return hip_fail(e, "ilu_factor: fixup");
     }
-    if ((e = launch_gather(H.b_rp[H.n], h->d_b_src, a_val, h->d_bval, s)) != hipSuccess)
+    if ((!tiled || !h->b_same) && (e = launch_gather(H.b_rp[H.n], h->d_b_src, a_val, h->d_bval, s)) != hipSuccess)
         return hip_fail(e, "ilu_factor: spmv values");
     h->bvals = true;
-    void *p;
-    if (casts & 1) {
-        if (!h->d_lu32) {
-            if ((e = h->alloc_bytes(&p, (size_t)H.lu_rp[H.n] * 4)) != hipSuccess) return hip_fail(e, "alloc f32");
-            h->d_lu32 = (float *)p;
-        }
-        if ((e = launch_cast_f32(H.lu_rp[H.n], h->d_lu, h->d_lu32, s)) != hipSuccess) return hip_fail(e, "cast f32");
-    }
-    if (casts & 2) {
-        if (!h->d_lu16) {
-            if ((e = h->alloc_bytes(&p, (size_t)H.lu_rp[H.n] * 2)) != hipSuccess) return hip_fail(e, "alloc bf16");
-            h->d_lu16 = (uint16_t *)p;
-        }
-        if ((e = launch_cast_bf16(H.lu_rp[H.n], h->d_lu, h->d_lu16, s)) != hipSuccess) return hip_fail(e, "cast bf16");
-    }
+    if (!tiled && (casts & ILU_CAST_F32) &&
+        (e = launch_cast_f32(H.lu_rp[H.n], h->d_lu, h->d_lu32, s)) != hipSuccess)
+        return hip_fail(e, "cast f32");
+    if (!tiled && (casts & ILU_CAST_BF16) &&
+        (e = launch_cast_bf16(H.lu_rp[H.n], h->d_lu, h->d_lu16, s)) != hipSuccess)
+        return hip_fail(e, "cast bf16");
     h->prof.end(pcall, s);
     int32_t hinfo[kInfoSlots];
     if ((e = hipMemcpyAsync(hinfo, h->d_info, sizeof(hinfo), hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -898,7 +930,8 @@ namespace jv {
 // One forward + backward pass.  view: 0 = the factor (L then U), 1 = the
 // transposed factor (U^T then L^T, adjoint).
 ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int vec, const void *b, void *x,
-                      void *y_out, void *z_out, int nrhs, int64_t ld, int flags, hipStream_t s, const SolveWork *ws) {
+                      void *y_out, void *z_out, int nrhs, int64_t ld, int flags, hipStream_t s, const SolveWork *ws,
+                      bool guard) {
     const HostAnalysis &H = h->H;
     const int pc = prec == ILU_PREC_F64 ? 0 : 1;
     hipError_t e;
@@ -906,7 +939,7 @@ ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int 
     const int pcall = h->prof.begin(ILU_STAGE_APPLY_CALL, s);
     // an earlier apply that timed out: re-arm, clear and count it (reported by
     // ilu_get_status and the Krylov drivers)
-    if ((e = h->guard(s)) != hipSuccess) return hip_fail(e, "solve guard");
+    if (guard && (e = h->guard(s)) != hipSuccess) return hip_fail(e, "solve guard");
     if (ws && ws->fill) {
         // caller-provided intermediates start all pending
         const int64_t cnt = (int64_t)H.n * ws->cap;

@@ -71,6 +71,10 @@ struct FactorArgs {
     int32_t max_lower;    // longest strictly lower part of a row
     int32_t poll_sleep;   // s_sleep(1) steps between polls of a pending value
     int32_t lcap;         // long rows (more than 64 entries): LDS entries per wave (0: not used)
+    float *lu32;          // tiled factor: FP32 copy written with each published row (may be null)
+    uint16_t *lu16;       // tiled factor: BF16 copy written with each published row (may be null)
+    double *bval;         // tiled factor, when the permuted copy of A has the factor's pattern:
+                          // A's values written into it as each row starts (may be null)
 };
 
 struct SolveArgs {
@@ -192,6 +196,14 @@ hipError_t launch_zero_counters(int32_t *counters, hipStream_t s);
 // counts the event in info[kInfoTimeouts]; otherwise every block returns at once.
 hipError_t launch_solve_guard(int32_t *info, uint64_t *y64, uint64_t *z64, int64_t n64, uint32_t *y32, uint32_t *z32,
                               int64_t n32, hipStream_t s);
+// The guard of a factor call, which also resets the factor's status slots (bad row,
+// drop count; the abort flag is clear after the guard) and, when `counters` is not
+// null, zeroes that pass's claim counters -- one launch instead of three.
+hipError_t launch_factor_prologue(int32_t *info, uint64_t *y64, uint64_t *z64, int64_t n64, uint32_t *y32,
+                                  uint32_t *z32, int64_t n32, int32_t *counters, hipStream_t s);
+// Writes the pending pattern into `count` ranges of the factor buffer: range i is
+// entries [ranges[i].x, ranges[i].x + ranges[i].y) (the U parts other tiles import).
+hipError_t launch_arm_ranges(uint64_t *lu, const int2 *ranges, int32_t count, hipStream_t s);
 // Raises the device abort flag from the stream (failure-path tests: every wait of
 // the kernels that follow gives up within its next 64 polls).
 hipError_t launch_raise_abort(int32_t *info, hipStream_t s);

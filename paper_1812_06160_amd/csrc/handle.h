@@ -109,6 +109,10 @@ struct ilu_handle_s {
         int8_t *match = nullptr;
         uint32_t *cmask = nullptr;
     } dft;
+    int32_t *d_arm = nullptr;          // tiled factor: (diagonal entry, U length) of every imported row
+    int32_t n_arm = 0;
+    bool arm_built = false;            // d_arm / n_arm describe the current factor tiles
+    bool b_same = false;               // the permuted copy of A has the factor's pattern
     jv::Profiler prof;
     int32_t *d_counters = nullptr;     // kPasses sets of claim counters
     bool counters_dirty[jv::kPasses] = {false, false, false, false, false, false, false, false};
@@ -174,5 +178,5 @@ struct SolveWork {
 };
 ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int vec, const void *b, void *x,
                       void *y_out, void *z_out, int nrhs, int64_t ld, int flags, hipStream_t s,
-                      const SolveWork *ws = nullptr);
+                      const SolveWork *ws = nullptr, bool guard = true);
 }

@@ -236,6 +236,45 @@ __global__ void k_solve_guard(int32_t *info, uint64_t *y64, uint64_t *z64, int64
     }
 }
 
+__global__ void k_factor_prologue(int32_t *info, uint64_t *y64, uint64_t *z64, int64_t n64, uint32_t *y32,
+                                  uint32_t *z32, int64_t n32, int32_t *counters) {
+    if (blockIdx.x == 0) {
+        if (counters && threadIdx.x < kStreams) counters[threadIdx.x * kCounterStride] = 0;
+        if (threadIdx.x == 0) {
+            info[kInfoBadKey] = INT_MAX;
+            info[kInfoDropLo] = 0;
+            info[kInfoDropLo + 1] = 0;
+        }
+    }
+    if (!aborted(info)) return;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n64; i += stride) {
+        y64[i] = kPending64;
+        z64[i] = kPending64;
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n32; i += stride) {
+        y32[i] = kPending32;
+        z32[i] = kPending32;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&info[kInfoGuardDone], 1) == (int)gridDim.x - 1) {
+            info[kInfoGuardDone] = 0;
+            atomicAdd(&info[kInfoTimeouts], 1);
+            __hip_atomic_store(&info[kInfoAbort], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// one thread per range; ranges are a few entries long (the U part of one row)
+__global__ void k_arm_ranges(uint64_t *lu, const int2 *__restrict__ ranges, int32_t count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int2 r = ranges[i];
+    for (int j = 0; j < r.y; ++j) lu[r.x + j] = kPending64;
+}
+
 __global__ void k_raise_abort(int32_t *info) {
     if (threadIdx.x == 0) __hip_atomic_store(&info[kInfoAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -1602,6 +1641,9 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
         const bool act = t < len;
         const double tr = A.use_tau ? tau[sl] : 0.0;
         double v = act ? vals[o.x + t] : 0.0;
+        // the spmv operand (same pattern as the factor): A's value in the permuted
+        // copy, a store issued here so that no wait on it sits in the staging
+        if (A.bval && act) A.bval[m.y + t] = v;
         double before = 0.0;                   // an L entry's value before its division
         int dropped = 0;
         if (flat) {
@@ -1682,6 +1724,11 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
             const uint64_t bits = dropped ? kDropped64 : (v != v) ? kQNaN64 : (uint64_t)__double_as_longlong(v);
             reinterpret_cast<uint64_t *>(vals)[o.x + t] = bits;
             st_pub_u64(reinterpret_cast<uint64_t *>(&A.lu[m.y + t]), bits);
+            // the storage copies of the final value (a dropped entry is 0): the same
+            // roundings as the cast kernels, written while the row is at hand
+            const float f = dropped ? 0.0f : (float)__longlong_as_double((long long)bits);
+            if (A.lu32) A.lu32[m.y + t] = f;
+            if (A.lu16) A.lu16[m.y + t] = to_bf16(f);
         }
         if (t == 0) __hip_atomic_store(&flags[sl], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
@@ -1771,6 +1818,19 @@ hipError_t launch_solve_guard(int32_t *info, uint64_t *y64, uint64_t *z64, int64
                               int64_t n32, hipStream_t s) {
     hipLaunchKernelGGL(k_solve_guard, dim3(256), dim3(kBlock), 0, s, info, y64, z64, y64 ? n64 : 0, y32, z32,
                        y32 ? n32 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_factor_prologue(int32_t *info, uint64_t *y64, uint64_t *z64, int64_t n64, uint32_t *y32,
+                                  uint32_t *z32, int64_t n32, int32_t *counters, hipStream_t s) {
+    hipLaunchKernelGGL(k_factor_prologue, dim3(256), dim3(kBlock), 0, s, info, y64, z64, y64 ? n64 : 0, y32, z32,
+                       y32 ? n32 : 0, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_arm_ranges(uint64_t *lu, const int2 *ranges, int32_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_arm_ranges, dim3(grid_for(count, kBlock)), dim3(kBlock), 0, s, lu, ranges, count);
     return hipGetLastError();
 }
 

@@ -53,9 +53,11 @@ struct Ctx {
     double *work;   // dot partials
 };
 
+// Applies inside a driver skip the per-call guard: the driver runs it once at its
+// start and checks the abort flag at every readback, so each apply starts clear.
 ilu_status apply(Ctx &c, const double *in, double *out) {
     return run_solves(c.h, 0, factor_ptr(c.h, c.prec), c.prec, 0, in, out, nullptr, nullptr, 1, 1,
-                      ILU_PERMUTED_SPACE, c.s);
+                      ILU_PERMUTED_SPACE, c.s, nullptr, false);
 }
 
 ilu_status spmv(Ctx &c, double alpha, const double *x, double beta, double *y) {
@@ -103,6 +105,8 @@ extern "C" ilu_status ilu_solve_pcg(ilu_handle h, const double *b, double *x, do
     CHK(check_common(h, b, x, rtol, fac_prec, flags));
     const int64_t n = h->H.n;
     CHK(ensure_kry(h, sizeof(double) * (size_t)n * 6, s));
+    CHK(h->ensure_workspace(1, fac_prec == ILU_PREC_F64 ? 0 : 1, s) == hipSuccess ? ILU_OK : fail(ILU_ERR_HIP, "pcg workspace"));
+    HCHK(h->guard(s), "pcg guard");
     double *bp = h->d_kry, *xp = bp + n, *r = xp + n, *z = r + n, *p = z + n, *q = p + n;
     Ctx c{h, n, fac_prec, s, h->d_dotwork + kDotParts, h->d_dotwork};
     double *S = c.scal;   // 0 bnorm^2, 1 rz, 2 rz_new, 3 pq, 4 rr
@@ -181,6 +185,8 @@ extern "C" ilu_status ilu_solve_gmres(ilu_handle h, const double *b, double *x, 
     const int m = restart;
     const int64_t n = h->H.n;
     CHK(ensure_kry(h, sizeof(double) * (size_t)n * (size_t)(2 * m + 4), s));
+    CHK(h->ensure_workspace(1, fac_prec == ILU_PREC_F64 ? 0 : 1, s) == hipSuccess ? ILU_OK : fail(ILU_ERR_HIP, "gmres workspace"));
+    HCHK(h->guard(s), "gmres guard");
     double *bp = h->d_kry, *xp = bp + n, *w = xp + n, *V = w + n, *Z = V + (size_t)n * (m + 1);
     Ctx c{h, n, fac_prec, s, h->d_dotwork + kDotParts, h->d_dotwork};
     double *S = c.scal;  // 0..m: current Hessenberg column, m+1: beta, m+2..: y coefficients (<= 30)

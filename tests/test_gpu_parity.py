@@ -349,13 +349,53 @@ def test_apply_low_precision(jv, sched, prec, vec):
     assert relerr(x, xr) <= 2.0 ** -17
 
 
-def test_casts_bit_exact(jv):
-    A = synth.random_banded(3000, rng=np.random.default_rng(10))
-    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
-    ilu.factor(dev(A.val), casts=("f32", "bf16"))
-    lu, _ = ilu.factor_values()
-    assert np.array_equal(ilu.factor_values_prec("f32").view(np.uint32), O.cast_f32(lu).view(np.uint32))
-    assert np.array_equal(ilu.factor_values_prec("bf16"), O.cast_bf16(lu))
+@pytest.mark.parametrize("sched", FACTOR_SCHEDS, ids=lambda s: s[0])
+@pytest.mark.parametrize("name,mk,k,tau,milu", [
+    ("random_3000", lambda: synth.random_banded(3000, rng=np.random.default_rng(10)), 0, 0.0, False),
+    ("convdiff3d_14_ilu1_tau", lambda: synth.convdiff3d(14), 1, 1e-3, False),
+    ("laplace3d_20_modified", lambda: synth.laplace3d(20), 0, 0.0, True),
+], ids=lambda v: v if isinstance(v, str) else "")
+def test_casts_bit_exact(jv, name, mk, k, tau, milu, sched):
+    # the FP32 and BF16 storage copies are the oracle's roundings of the oracle's
+    # factor (dropped entries 0), whether cast kernels or the tiled factor write them
+    A = mk()
+    ilu = make(jv, A, k, True, sched, tile_rows=128)
+    for rep in range(2):
+        ilu.factor(dev(A.val), k=k, tau=tau, casts=("f32", "bf16"), milu=milu)
+        an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k)
+        f = O.factor(an, A.val, k=k, tau=tau, milu=milu)
+        lu, _ = ilu.factor_values()
+        assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
+        assert np.array_equal(ilu.factor_values_prec("f32").view(np.uint32), O.cast_f32(f.val).view(np.uint32))
+        assert np.array_equal(ilu.factor_values_prec("bf16"), O.cast_bf16(f.val))
+
+
+@pytest.mark.parametrize("sched", FACTOR_SCHEDS, ids=lambda s: s[0])
+@pytest.mark.parametrize("name,mk,k", [
+    ("laplace3d_20", lambda: synth.laplace3d(20), 0),
+    ("convdiff3d_12_ilu1", lambda: synth.convdiff3d(12), 1),
+    ("random_sparse_missing_diag", lambda: synth.random_sparse(333, 0.02, np.random.default_rng(6),
+                                                               drop_diag_frac=0.1), 0),
+], ids=lambda v: v if isinstance(v, str) else "")
+def test_spmv_values_from_factor(jv, name, mk, k, sched):
+    # the spmv operand loaded by ilu_factor (the tiled factor writes it while it
+    # stages the rows; other schedules gather it): equal to the oracle's copy
+    A = mk()
+    rng = np.random.default_rng(12)
+    ilu = make(jv, A, k, True, sched, tile_rows=128)
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k)
+    for rep in range(2):
+        try:
+            ilu.factor(dev(A.val * (1.0 + rep)), k=k)
+        except jv.IluError as e:   # an inserted zero diagonal may be a zero pivot; the values are loaded
+            assert e.status in ("ILU_ERR_ZERO_PIVOT", "ILU_ERR_NONFINITE")
+        x = rng.integers(-4, 5, (A.n, 2)).astype(np.float64)
+        want = O.spmv(A.n, an.b_rp, an.b_ci, O.b_values(an, A.val * (1.0 + rep)), x)
+        got = ilu.spmv(dev(x), permuted=True).cpu().numpy()
+        assert relerr(got, want) <= 1e-12
+        xo = rng.uniform(-1, 1, A.n)
+        yo = O.spmv(A.n, A.row_ptr, A.col_idx, A.val * (1.0 + rep), xo)
+        assert relerr(ilu.spmv(dev(xo)).cpu().numpy(), yo) <= 1e-12
 
 
 @pytest.mark.parametrize("name,mk,k,tau", APPLY_CASES, ids=[c[0] for c in APPLY_CASES])
