@@ -150,6 +150,21 @@ def run(args):
                    apply16_f64_us=round(1e3 * t64, 1), apply16_f64_gbs=round(B64["apply"] / t64 / 1e6, 1),
                    apply1_f64_us=round(1e3 * t1, 1),
                    us_per_level_apply1=round(1e3 * t1 / (info["n_levels"] + info["n_ulevels"]), 3))
+        # the lower stage (Sec. III-B): levels of fewer than 64 rows at the end of each
+        # direction streamed by one workgroup per right-hand side
+        ilu.set_tuning("tail_min_rows", 64)
+        ti = ilu.info()
+        q64 = _stage_times(ilu, lambda: ilu.apply(b64), 5)
+        q32 = _stage_times(ilu, lambda: ilu.apply(b32, prec="f32"), 5)
+        q1 = _stage_times(ilu, lambda: ilu.apply(b1), 5)
+        u64 = q64["forward"][0] + q64["backward"][0]
+        u32 = q32["forward"][0] + q32["backward"][0]
+        u1 = q1["forward"][0] + q1["backward"][0]
+        out["tail"] = dict(min_rows=64, rows=ti["tail_rows"], urows=ti["tail_urows"],
+                           apply16_f32_us=round(1e3 * u32, 1), apply16_f32_gbs=round(B16["apply"] / u32 / 1e6, 1),
+                           apply16_f64_us=round(1e3 * u64, 1), apply16_f64_gbs=round(B64["apply"] / u64 / 1e6, 1),
+                           apply1_f64_us=round(1e3 * u1, 1),
+                           us_per_level_apply1=round(1e3 * u1 / (info["n_levels"] + info["n_ulevels"]), 3))
     elif wl == "heavy_1m":
         A = synth.heavy_rows(1_000_000, rng=np.random.default_rng([6, 0]))
         b = np.ascontiguousarray(synth.rhs(A.n, 1, np.random.default_rng([6, 1]))).reshape(-1)
@@ -180,6 +195,18 @@ def run(args):
                    apply_us=round(1e3 * (pa["forward"][0] + pa["backward"][0]), 1),
                    spmv_us=round(1e3 * ps["spmv"][0], 1), spmv_gbs=round(B["spmv"] / ps["spmv"][0] / 1e6, 1),
                    gmres30=dict(iters=si["iters"], seconds=round(t_k, 4), true_relres=si["true_relres"]))
+        # natural order with the lower stage (its long rows split over steps of one wave)
+        ilu.set_tuning("tail_min_rows", 64)
+        ti = ilu.info()
+        pa = _stage_times(ilu, lambda: ilu.apply(bd), 5)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, si = ilu.gmres(bd, rtol=1e-10, restart=30, prec="f64", raise_on_fail=False)
+        torch.cuda.synchronize()
+        t_k = time.perf_counter() - t1
+        out["tail"] = dict(min_rows=64, rows=ti["tail_rows"], urows=ti["tail_urows"],
+                           apply_us=round(1e3 * (pa["forward"][0] + pa["backward"][0]), 1),
+                           gmres30=dict(iters=si["iters"], seconds=round(t_k, 4), true_relres=si["true_relres"]))
         # the same matrix under the reverse Cuthill-McKee preorder
         del ilu
         torch.cuda.empty_cache()

@@ -93,7 +93,12 @@ typedef struct {
     int32_t tile_rows;        /* rows per tile of the tiled solves (0 = default: 512, halved until a
                                  tile fits the LDS budget; else 16..65536, used as given) */
     int32_t ordering;         /* ILU_ORDER_NATURAL (default: A as given) or ILU_ORDER_RCM */
-    int32_t reserved[3];      /* must be 0 */
+    int32_t tail_min_rows;    /* lower stage of the triangular solves (Sec. III-B, "Lower Stage";
+                                 Fig. 7): 0 = none; M > 0: in each direction the longest suffix of
+                                 the level order whose levels all hold fewer than M rows (at least
+                                 64 levels) is solved by one streaming workgroup per right-hand
+                                 side after the rows before it */
+    int32_t reserved[2];      /* must be 0 */
 } ilu_analyze_opts;
 
 /* Preorderings applied before the analysis (Sec. VII compares orderings; the
@@ -122,7 +127,9 @@ typedef struct {
     int32_t n_utiles;         /* tiles of the backward (U) tiled solve */
     int32_t tile_rows;        /* rows per tile requested */
     int32_t max_tile;         /* most rows in one tile of either direction */
-    int32_t reserved[3];
+    int32_t tail_rows;        /* rows in the lower stage of the forward solve (0: none) */
+    int32_t tail_urows;       /* rows in the lower stage of the backward solve (0: none) */
+    int32_t reserved[1];
 } ilu_info;
 
 typedef struct {
@@ -188,6 +195,19 @@ ilu_status ilu_copy_schedule(ilu_handle h, int32_t *level_ptr, int32_t *perm, in
  * entries hold -1.
  * Sizes: tile_ptr n_tiles+1 (n_utiles+1 for dir 1), tile_row tile_ptr[last]. */
 ilu_status ilu_copy_tiles(ilu_handle h, int32_t dir, int32_t *tile_ptr, int32_t *tile_row, int32_t *sci);
+
+/* Copies the lower stage ("tail") of one solve direction (dir 0: L, 1: U; see
+ * ilu_analyze_opts.tail_min_rows) to host arrays; any pointer may be NULL.
+ * sizes[4] = {first tail level (-1: none), first tail position, steps, record
+ * words}.  hdr (4 * (steps + 1)): per step its record offset, nrows | nlanes << 8
+ * | log2(largest lane group) << 16 | flags << 24 (1: adds the previous step's
+ * partial sum, 2: finishes its rows), entries, 0.  rec: per step, 4 words per row
+ * (row in the level ordering, ring slot, input-ordering row, diagonal entry), one
+ * word per lane (row in the step | log2 of its lane group << 8 | group leader <<
+ * 16), then per entry (entry (lane, j) at j * nlanes + lane) its factor entry (-1:
+ * none) and the source of its dependency value (a ring slot below 2048, 2048 + row
+ * for the published buffer, -1: none).  For inspection and tests. */
+ilu_status ilu_copy_tail(ilu_handle h, int32_t dir, int32_t *sizes, int32_t *hdr, int32_t *rec);
 
 /* ---------------------------------------------------------------------------- */
 /* Numeric factor (Sec. III, Fig. 1).                                            */
@@ -358,7 +378,9 @@ ilu_status ilu_get_schedule(ilu_handle h, int32_t *factor_sched, int32_t *solve_
  * is read from global memory when its turn comes; same results).  Readable as well:
  * "nstreams" (task streams = XCDs found), "factor_tcap" (LDS entries staged per
  * factor row), "factor_tiled" (1 if the tiled factor can run on this handle:
- * rows of at most 32 entries and tiles that fit LDS).  "force_abort" (set only;
+ * rows of at most 32 entries and tiles that fit LDS).  "tail_min_rows" (0 or
+ * 1..65536: rebuilds the lower stage of both solve directions as with the
+ * analysis option of that name; synchronous).  "force_abort" (set only;
  * failure-path tests): 1 raises the device abort flag now, as an apply that timed
  * out and was not yet reported leaves it; 2 raises it inside the next apply, after
  * that apply's guard, so its kernels leave through their bounded waits (outputs
@@ -375,8 +397,10 @@ ilu_status ilu_get_tuning(ilu_handle h, const char *key, int64_t *value);
  * consecutive levels of up to that many rows into one workgroup); one tiling serves
  * both stages, chosen by the apply.  The factor is re-run with the last call's k,
  * tau and flags, so the handle keeps the same factor (every schedule gives the same
- * bits).  Requires a factor.  Synchronous.  results (may be NULL) receives up to
- * `cap` rows of {stage (0 factor, 1 apply), sched, lanes or tile rows (tiled),
+ * bits).  The apply also tries the lower stage (tail_min_rows 64, or the handle's
+ * own value) and keeps it if faster.  Requires a factor.  Synchronous.  results
+ * (may be NULL) receives up to `cap` rows of {stage (0 factor, 1 apply), sched (10:
+ * lower stage), lanes or tile rows (tiled) or tail_min_rows (lower stage),
  * microseconds} as doubles; *n_results the row count. */
 ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, double *results, int32_t cap,
                     int32_t *n_results, hipStream_t stream);

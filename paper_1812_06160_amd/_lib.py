@@ -28,6 +28,7 @@ STAGES = ["factor", "forward", "backward", "spmv", "factor_call", "apply_call"]
 # exported symbols that include/javelin.h declares
 SYMBOLS = [
     "ilu_analyze", "ilu_analyze_batched", "ilu_batch_offsets", "ilu_get_info", "ilu_copy_schedule", "ilu_copy_tiles",
+    "ilu_copy_tail",
     "ilu_factor", "ilu_factor_values", "ilu_copy_factor", "ilu_copy_factor_prec", "ilu_apply", "ilu_get_status",
     "ilu_apply_noalloc", "ilu_apply_ex",
     "ilu_apply_adjoint", "ilu_apply_graph_create", "ilu_graph_launch", "ilu_graph_destroy", "ilu_spmv", "ilu_set_values", "ilu_solve_pcg", "ilu_solve_gmres",
@@ -43,7 +44,8 @@ class Csr(C.Structure):
 
 class AnalyzeOpts(C.Structure):
     _fields_ = [("k_max", C.c_int32), ("pattern", C.c_int32), ("host_only", C.c_int32),
-                ("tile_rows", C.c_int32), ("ordering", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("tile_rows", C.c_int32), ("ordering", C.c_int32), ("tail_min_rows", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class Info(C.Structure):
@@ -52,7 +54,7 @@ class Info(C.Structure):
                 ("nnz_b", C.c_int64), ("level_min", C.c_int32), ("level_max", C.c_int32),
                 ("level_median", C.c_double), ("batch_count", C.c_int32), ("n_tiles", C.c_int32),
                 ("n_utiles", C.c_int32), ("tile_rows", C.c_int32), ("max_tile", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("tail_rows", C.c_int32), ("tail_urows", C.c_int32), ("reserved", C.c_int32 * 1)]
 
 
 class FactorInfo(C.Structure):
@@ -86,6 +88,7 @@ def load(path: str = LIB_PATH):
         "ilu_get_info": [H, C.POINTER(Info)],
         "ilu_copy_schedule": [H] + [vp] * 11,
         "ilu_copy_tiles": [H, i32, vp, vp, vp],
+        "ilu_copy_tail": [H, i32, vp, vp, vp],
         "ilu_factor": [H, vp, i32, f64, i32, C.POINTER(FactorInfo), vp],
         "ilu_factor_values": [H, i32, C.POINTER(vp)],
         "ilu_copy_factor": [H, vp, vp],

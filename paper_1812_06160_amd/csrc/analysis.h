@@ -87,6 +87,38 @@ void build_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, TileSet 
 // are too large for its LDS image).
 void build_forward_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, TileSet *fwd);
 
+// Lower stage ("tail") of one triangular-solve direction: the longest suffix of
+// its level order whose levels hold fewer than min_rows rows, cut into steps (rows
+// of one level solved together by one wave; a row with more than 64 * kTailJ
+// dependencies gets consecutive steps of its own whose partial sums carry over).
+constexpr int kTailJ = 2;        // dependencies per lane
+constexpr int kTailQ = 24;       // steps staged ahead (LDS buffers)
+constexpr int kTailW = 2048;     // ring of recent results (power of two; at least 64 steps of 32 rows,
+                                 // so that values not in the ring are kTailQ or more steps old)
+constexpr int kTailRows = 32;    // most rows in one step
+constexpr int kTailCarryIn = 1;  // step flag: add the previous step's partial sum
+constexpr int kTailEmit = 2;     // step flag: the step finishes its rows
+struct TailPlan {
+    int32_t level0 = -1;         // first tail level (-1: no tail)
+    int32_t pos0 = 0;            // first tail position in the direction's order
+    int32_t nsteps = 0;
+    int32_t max_rows = 0, max_lanes = 0;
+    // 4 per step (+ a sentinel): record offset in `rec`,
+    // nrows | nlanes << 8 | log2(largest lane group) << 16 | flags << 24, entries, 0
+    std::vector<int32_t> hdr;
+    // per step (starting at a multiple of 4 words): per row 4 words (row in the
+    // level ordering, its ring slot, its input-ordering row, its diagonal entry),
+    // lanes (row in the step | log2 group << 8 | leader << 16) [nlanes], then per entry
+    // (lane-major, entry (lane, j) at j * nlanes + lane) the factor entry [nent]
+    // (-1: none) and the source of the dependency value [nent]: a ring slot
+    // (< kTailW; no row written since holds the same slot), kTailW + row (read
+    // from the published buffer), or -1 (none)
+    std::vector<int32_t> rec;
+};
+// dir 0: forward (L), 1: backward (U).  No tail when min_rows <= 0 or the suffix
+// has fewer than min_levels levels.
+void build_tail(const HostAnalysis &H, int dir, int32_t min_rows, int32_t min_levels, TailPlan *T);
+
 // Data of the tiled factor on the forward tiles.  LDS of a tile: the value area
 // (the tile's rows' entries in slot order, then the U parts -- diagonal first -- of
 // its imports) and one ready flag per tile row and per import.  Per tile row:

@@ -102,8 +102,8 @@ hipError_t ilu_handle_s::alloc_bytes(void **p, size_t bytes) {
     return e;
 }
 
-const TaskList *ilu_handle_s::task_list(int which, int lanes) {
-    const int key = which * 1000 + lanes;
+const TaskList *ilu_handle_s::task_list(int which, int lanes, int32_t levels) {
+    const int64_t key = task_key(which, lanes, levels);
     auto it = tasks.find(key);
     if (it != tasks.end()) return &it->second;
     const std::vector<int32_t> *ptr = nullptr;
@@ -119,7 +119,8 @@ const TaskList *ilu_handle_s::task_list(int which, int lanes) {
     const int S = nstreams;
     std::vector<int32_t> t;
     std::vector<std::vector<int32_t>> streams(S);
-    for (size_t l = 0; l + 1 < ptr->size(); ++l) {
+    const size_t nl = levels < 0 ? ptr->size() - 1 : std::min<size_t>((size_t)levels, ptr->size() - 1);
+    for (size_t l = 0; l < nl; ++l) {
         const int32_t t0 = (int32_t)t.size();
         for (int32_t p = (*ptr)[l]; p < (*ptr)[l + 1]; p += per) t.push_back(p);
         const int32_t t1 = (int32_t)t.size();
@@ -129,7 +130,7 @@ const TaskList *ilu_handle_s::task_list(int which, int lanes) {
             for (int32_t k = a; k < b; ++k) streams[x].push_back(k);
         }
     }
-    t.push_back(ptr->empty() ? 0 : ptr->back());
+    t.push_back(ptr->empty() ? 0 : (*ptr)[nl]);
     std::vector<int32_t> st, sp(S + 1, 0);
     int32_t max_slots = 0;
     const int wpb = 4;   // waves per block: one task each
@@ -424,6 +425,35 @@ ilu_status ilu_handle_s::make_factor_tiles() {
     return ILU_OK;
 }
 
+ilu_status ilu_handle_s::make_tail(int32_t min_rows) {
+    constexpr int32_t kTailMinLevels = 64;
+    try {
+        build_tail(H, 0, min_rows, kTailMinLevels, &tail[0]);
+        build_tail(H, 1, min_rows, kTailMinLevels, &tail[1]);
+    } catch (const std::bad_alloc &) {
+        return fail(ILU_ERR_NOMEM, "tail: out of host memory");
+    }
+    tail_min_rows = min_rows;
+    if (host_only) return ILU_OK;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "tail: synchronize");
+    for (int d = 0; d < 2; ++d) {
+        for (int32_t **pp : {&dtail[d].hdr, &dtail[d].rec}) {
+            if (*pp) {
+                (void)hipFree(*pp);
+                allocs_erase(this, *pp);
+                *pp = nullptr;
+            }
+        }
+        if (tail[d].nsteps == 0) continue;
+        if ((e = upload(&dtail[d].hdr, tail[d].hdr)) != hipSuccess || (e = upload(&dtail[d].rec, tail[d].rec)) != hipSuccess)
+            return hip_fail(e, "tail: upload");
+        if (dtail[d].hdr) allocs.push_back(dtail[d].hdr);
+        if (dtail[d].rec) allocs.push_back(dtail[d].rec);
+    }
+    return ILU_OK;
+}
+
 // XCC ids present on the current device (one probe per process): id -> stream
 static hipError_t xcc_streams(std::vector<int8_t> *map, int *nstreams) {
     static std::vector<int8_t> cached;
@@ -550,8 +580,10 @@ extern "C" ilu_status ilu_analyze(const ilu_csr *A, const ilu_analyze_opts *opts
     *out = nullptr;
     ilu_analyze_opts o{};
     if (opts) o = *opts;
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 2; ++i)
         if (o.reserved[i]) return fail(ILU_ERR_ARG, "ilu_analyze: reserved option fields must be 0");
+    if (o.tail_min_rows < 0 || o.tail_min_rows > 65536)
+        return fail(ILU_ERR_ARG, "ilu_analyze: tail_min_rows must be in [0, 65536]");
     if (o.tile_rows != 0 && (o.tile_rows < 16 || o.tile_rows > 65536))
         return fail(ILU_ERR_ARG, "ilu_analyze: tile_rows must be 0 or in [16, 65536]");
     if (o.host_only != 0 && o.host_only != 1) return fail(ILU_ERR_ARG, "ilu_analyze: host_only must be 0 or 1");
@@ -572,6 +604,7 @@ extern "C" ilu_status ilu_analyze(const ilu_csr *A, const ilu_analyze_opts *opts
     h->pattern_sym = h->H.t_rp == h->H.lu_rp && h->H.t_ci == h->H.lu_ci;
     if (!h->host_only && (st = finish_analysis(h.get())) != ILU_OK) return st;
     if ((st = h->make_tiles(o.tile_rows ? o.tile_rows : kDefaultTileRows, o.tile_rows == 0)) != ILU_OK) return st;
+    if ((st = h->make_tail(o.tail_min_rows)) != ILU_OK) return st;
     // the solves default to the tiled launch wherever the tiles fit LDS
     h->sched_solve = tiles_fit(h->tiles[0]) && tiles_fit(h->tiles[1]) ? ILU_SCHED_TILED : ILU_SCHED_SYNCFREE;
     h->sched_factor = h->ftiles_ok ? ILU_SCHED_TILED : ILU_SCHED_SYNCFREE;
@@ -647,6 +680,8 @@ extern "C" ilu_status ilu_get_info(ilu_handle h, ilu_info *out) {
     I.n_utiles = h->tiles[1].ntiles;
     I.tile_rows = h->tile_rows;
     I.max_tile = std::max(h->tiles[0].max_rows, h->tiles[1].max_rows);
+    I.tail_rows = h->tail[0].nsteps ? H.n - h->tail[0].pos0 : 0;
+    I.tail_urows = h->tail[1].nsteps ? H.n - h->tail[1].pos0 : 0;
     *out = I;
     return ILU_OK;
 }
@@ -681,6 +716,21 @@ extern "C" ilu_status ilu_copy_tiles(ilu_handle h, int32_t dir, int32_t *tile_pt
     if (tile_ptr) std::copy(T.ptr.begin(), T.ptr.end(), tile_ptr);
     if (tile_row) std::copy(T.row.begin(), T.row.end(), tile_row);
     if (sci) std::copy(h->sci.begin(), h->sci.end(), sci);
+    return ILU_OK;
+}
+
+extern "C" ilu_status ilu_copy_tail(ilu_handle h, int32_t dir, int32_t *sizes, int32_t *hdr, int32_t *rec) {
+    if (!h) return fail(ILU_ERR_ARG, "ilu_copy_tail: NULL handle");
+    if (dir != 0 && dir != 1) return fail(ILU_ERR_ARG, "ilu_copy_tail: dir must be 0 or 1");
+    const TailPlan &T = h->tail[dir];
+    if (sizes) {
+        sizes[0] = T.level0;
+        sizes[1] = T.pos0;
+        sizes[2] = T.nsteps;
+        sizes[3] = (int32_t)T.rec.size();
+    }
+    if (hdr) std::copy(T.hdr.begin(), T.hdr.end(), hdr);
+    if (rec) std::copy(T.rec.begin(), T.rec.end(), rec);
     return ILU_OK;
 }
 
@@ -1006,6 +1056,41 @@ ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int 
             which = fwd ? kTasksTForward : kTasksTBackward;
             lptr = fwd ? &H.tlevel_ptr : &H.tulevel_ptr;
         }
+        // a lower stage: the levels before it sync-free (or one launch per level),
+        // then one streaming workgroup per right-hand side for the tail
+        const TailPlan &TP = h->tail[fwd ? 0 : 1];
+        if (view == 0 && TP.nsteps > 0) {
+            const int pp_ = h->prof.begin(fwd ? ILU_STAGE_FORWARD : ILU_STAGE_BACKWARD, s);
+            if (TP.level0 > 0 && h->sched_solve == ILU_SCHED_LEVEL) {
+                for (int32_t l = 0; l < TP.level0; ++l) {
+                    A.row_begin = (*lptr)[l];
+                    A.row_end = (*lptr)[l + 1];
+                    if ((e = launch_solve(A, fwd, prec, vec, lanes, false, 0, s)) != hipSuccess)
+                        return after_fwd(hip_fail(e, "solve launch"), pass);
+                }
+            } else if (TP.level0 > 0) {
+                const TaskList *tl = ws ? h->cached_task_list(which, lanes, TP.level0) : h->task_list(which, lanes, TP.level0);
+                if (!tl)
+                    return after_fwd(ws ? fail(ILU_ERR_STATE, "solve: the sync-free task list is built by a first ilu_apply")
+                                        : fail(ILU_ERR_NOMEM, "task list"),
+                                     pass);
+                if ((e = h->prepare_claims(fwd ? kPassForward : kPassBackward, tl, &A.claims, s)) != hipSuccess)
+                    return after_fwd(hip_fail(e, "solve claims"), pass);
+                A.nstreams = h->nstreams;
+                A.poll_sleep = h->poll_sleep;
+                if ((e = launch_solve(A, fwd, prec, vec, lanes, true, h->grid_syncfree(tl), s)) != hipSuccess)
+                    return after_fwd(hip_fail(e, "solve launch"), pass);
+            }
+            StreamArgs sa{};
+            sa.hdr = reinterpret_cast<const int4 *>(h->dtail[fwd ? 0 : 1].hdr);
+            sa.rec = h->dtail[fwd ? 0 : 1].rec;
+            sa.nsteps = TP.nsteps;
+            A.poll_sleep = h->poll_sleep;
+            e = launch_solve_stream(A, sa, fwd, prec, vec, s);
+            h->prof.end(pp_, s);
+            if (e != hipSuccess) return after_fwd(hip_fail(e, "tail launch"), pass);
+            continue;
+        }
         // the tiled schedule; a direction whose rows are too long for it runs
         // sync-free, and so do the transposed views of an unsymmetric pattern
         if ((view == 0 || h->pattern_sym) && h->sched_solve == ILU_SCHED_TILED && tile_rows_ok(h->tiles[fwd ? 0 : 1])) {
@@ -1305,6 +1390,10 @@ extern "C" ilu_status ilu_set_tuning(ilu_handle h, const char *key, int64_t valu
         h->factor_staged = value != 0;
         return ILU_OK;
     }
+    if (k == "tail_min_rows") {
+        if (value < 0 || value > 65536) return fail(ILU_ERR_ARG, "ilu_set_tuning: tail_min_rows must be in [0, 65536]");
+        return h->make_tail((int32_t)value);
+    }
     if (k == "force_abort") {
         // failure-path tests: 1 raises the abort flag now (as an apply that timed
         // out and was not reported would leave it); 2 raises it inside the next
@@ -1331,6 +1420,7 @@ extern "C" ilu_status ilu_get_tuning(ilu_handle h, const char *key, int64_t *val
     if (k == "tile_rows") { *value = h->tile_rows; return ILU_OK; }
     if (k == "factor_tiled") { *value = h->ftiles_ok ? 1 : 0; return ILU_OK; }
     if (k == "factor_staged") { *value = h->factor_staged ? 1 : 0; return ILU_OK; }
+    if (k == "tail_min_rows") { *value = h->tail_min_rows; return ILU_OK; }
     return fail(ILU_ERR_ARG, "ilu_get_tuning: unknown key " + k);
 }
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "analysis.h"
+
 namespace jv {
 
 // Bit patterns published into factor values and solve intermediates.  Both are
@@ -147,6 +149,22 @@ constexpr int kFactorTileLdsMax = 163840;   // the whole LDS of a compute unit (
 constexpr int kFactorMaxLanes = 32;         // longest factor row of the tiled factor
 // LDS a tiling needs with `nr` right-hand sides per pass of `acc_bytes` each
 size_t tile_lds_bytes(int max_rows, int max_slots, int max_pos, int max_imps, int kmax, int nr, int acc_bytes);
+
+// Lower stage (tail) of a solve direction, streamed by one workgroup per
+// right-hand side: wave 0 computes the steps in order, the other waves stage them
+// kTailQ steps ahead (see TailPlan in analysis.h for the record format).
+struct StreamArgs {
+    const int4 *hdr;          // [nsteps + 1] per step: record offset, packed counts, entries, 0
+    const int32_t *rec;       // step records
+    int32_t nsteps;
+    // LDS carve-up (bytes), set by the launcher
+    int32_t off_vals, off_a, off_c, off_lane, off_rhs, off_piv, off_hdr, off_sync, lds_bytes;
+};
+constexpr int kStreamStagers = 15;
+// The stream launch: A.nrhs blocks (block b solves right-hand side b of the
+// direction's tail); the direction's rows before the tail must be finished.
+hipError_t launch_solve_stream(const SolveArgs &A, const StreamArgs &T, bool forward, int prec, int vec,
+                               hipStream_t s);
 
 // Tiled factor (plain ILU: every pattern entry kept, no dropping) on the forward
 // tiles; see FactorTiles in analysis.h for the data.

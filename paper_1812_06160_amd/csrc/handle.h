@@ -82,7 +82,7 @@ struct ilu_handle_s {
     size_t kry_bytes = 0;
     double *d_kry = nullptr;
 
-    std::map<int, jv::TaskList> tasks;
+    std::map<int64_t, jv::TaskList> tasks;
 
     // tiles of the tiled solves (direction 0: L, 1: U) and the solve column encoding
     jv::TileSet tiles[2];
@@ -113,6 +113,12 @@ struct ilu_handle_s {
     int32_t n_arm = 0;
     bool arm_built = false;            // d_arm / n_arm describe the current factor tiles
     bool b_same = false;               // the permuted copy of A has the factor's pattern
+    // lower stage of each solve direction (0: L, 1: U) and its device copy
+    jv::TailPlan tail[2];
+    int32_t tail_min_rows = 0;
+    struct DevTail {
+        int32_t *hdr = nullptr, *rec = nullptr;
+    } dtail[2];
     jv::Profiler prof;
     int32_t *d_counters = nullptr;     // kPasses sets of claim counters
     bool counters_dirty[jv::kPasses] = {false, false, false, false, false, false, false, false};
@@ -137,7 +143,8 @@ struct ilu_handle_s {
 
     ~ilu_handle_s();
     hipError_t alloc_bytes(void **p, size_t bytes);
-    const jv::TaskList *task_list(int which, int lanes);
+    // task list of the first `levels` levels of a direction (-1: all)
+    const jv::TaskList *task_list(int which, int lanes, int32_t levels = -1);
     hipError_t ensure_workspace(int nrhs, int prec_class, hipStream_t s);
     hipError_t rearm(hipStream_t s);
     hipError_t reset_info(hipStream_t s);
@@ -147,8 +154,11 @@ struct ilu_handle_s {
     // after re-arming and clearing them)
     ilu_status take_timeout(hipStream_t s, const char *who);
     // the task list if it has been built already (no allocation), else nullptr
-    const jv::TaskList *cached_task_list(int which, int lanes) const {
-        auto it = tasks.find(which * 1000 + lanes);
+    static int64_t task_key(int which, int lanes, int32_t levels) {
+        return ((int64_t)(levels + 1) << 16) | (int64_t)(which << 8) | lanes;
+    }
+    const jv::TaskList *cached_task_list(int which, int lanes, int32_t levels = -1) const {
+        auto it = tasks.find(task_key(which, lanes, levels));
         return it == tasks.end() ? nullptr : &it->second;
     }
     // fills the claims of one sync-free pass (launching a counter reset when needed)
@@ -159,6 +169,8 @@ struct ilu_handle_s {
     // shrink, halves the tile size until the tiles fit the LDS budget
     ilu_status make_tiles(int32_t rows, bool shrink);
     ilu_status make_factor_tiles();
+    // (re)builds the lower stage of both solve directions (min_rows 0: none)
+    ilu_status make_tail(int32_t min_rows);
     // claim counter of a tiled pass (launching a counter reset when needed)
     hipError_t prepare_tile_claims(int pass, jv::TileArgs *t, hipStream_t s);
 };

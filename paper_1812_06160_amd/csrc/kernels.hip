@@ -1448,6 +1448,274 @@ __global__ __launch_bounds__(solve_block<TA>()) void k_solve_tiled(SolveArgs A, 
 }
 
 // ---------------------------------------------------------------------------------
+// Lower stage (tail) of a triangular solve: one workgroup streams the narrow
+// levels at the end of the level order (Sec. III-B, Fig. 7)
+// ---------------------------------------------------------------------------------
+// Wave 0 computes the steps in order.  For each step it reads the staged
+// coefficients and dependency values (a dependency computed a few steps earlier
+// is read from the ring of recent results, any other one was fetched by a stager
+// from the published buffer), sums each row's products over its lane group,
+// writes the result to the ring and publishes it.  Waves 1..kStreamStagers take
+// steps round-robin and stage step s into buffer s % kTailQ once wave 0 has
+// finished step s - kTailQ.  The lowest unstaged step only waits for steps at
+// least kTailQ earlier, which wave 0 can always finish, so the block cannot
+// deadlock; every wait is bounded and a raised abort flag releases all of them.
+constexpr int kStreamBlock = 64 * (1 + kStreamStagers);
+constexpr int kStreamEnt = 64 * kTailJ;   // entries of one step
+
+// Sum over each lane's aligned group of 2^gl lanes (gl differs between groups of a
+// wave; gmax is the largest); every lane of a group ends with the group's sum.
+template <typename T>
+__device__ __forceinline__ T seg_sum(T v, int gl, int gmax) {
+    if (gmax >= 1) {
+        const T w = dpp_mov<kDppQuadXor1>(v);
+        if (gl >= 1) v = v + w;
+    }
+    if (gmax >= 2) {
+        const T w = dpp_mov<kDppQuadXor2>(v);
+        if (gl >= 2) v = v + w;
+    }
+    if (gmax >= 3) {
+        const T w = dpp_mov<kDppHalfMirror>(v);
+        if (gl >= 3) v = v + w;
+    }
+    if (gmax >= 4) {
+        const T w = dpp_mov<kDppMirror>(v);
+        if (gl >= 4) v = v + w;
+    }
+    if (gmax >= 5) {
+        const T w = __shfl_xor(v, 16);
+        if (gl >= 5) v = v + w;
+    }
+    if (gmax >= 6) {
+        const T w = __shfl_xor(v, 32);
+        if (gl >= 6) v = v + w;
+    }
+    return v;
+}
+
+// Bounded wait until the LDS counter *p reaches v; false when the block gives up
+// (its abort word, the device abort flag when `global` allows a global load, or
+// the wall-clock bound).  With `backoff` the pause between polls doubles up to 8
+// steps (waves far ahead of the one they wait for poll LDS less).
+__device__ bool lds_wait_ge(int *p, int v, int *labort, int32_t *info, bool global, bool backoff = false) {
+    int spins = 0, pause = 1;
+    uint64_t t0 = 0;
+    for (;;) {
+        if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= v) return true;
+        for (int k = 0; k < pause; ++k) __builtin_amdgcn_s_sleep(1);
+        if (backoff && pause < 8) pause *= 2;
+        if ((++spins & 63) == 0) {
+            if (__hip_atomic_load(labort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return false;
+            if (global && aborted(info)) {
+                __hip_atomic_store(labort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                return false;
+            }
+            if (expired(t0)) {
+                __hip_atomic_store(&info[kInfoAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(labort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                return false;
+            }
+        }
+    }
+}
+
+// A step's record as a stager lane holds it, for the compute lane of the same
+// number (lane < nlanes): its lane word, the row of its lane group (4 words), and
+// its kTailJ entries (entry j * nlanes + lane of the record).  The row is read
+// only by a group's leader lane.
+template <int J>
+struct StreamRec {
+    int h, nent, nrows, nlanes;
+    int li;
+    int4 lr;
+    int p[J], code[J];
+};
+
+template <int J>
+__device__ __forceinline__ void stream_rec_load(StreamRec<J> &R, const StreamArgs &T, int4 hd, int lane) {
+    R.h = hd.y;
+    R.nent = hd.z;
+    R.nrows = hd.y & 255;
+    R.nlanes = (hd.y >> 8) & 255;
+    const int off = hd.x;
+    R.li = lane < R.nlanes ? T.rec[off + 4 * R.nrows + lane] : 0;
+    R.lr = (lane < R.nlanes && ((R.li >> 16) & 1))
+               ? *reinterpret_cast<const int4 *>(T.rec + off + 4 * (R.li & 255))
+               : make_int4(0, 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int e = j * R.nlanes + lane;
+        R.p[j] = lane < R.nlanes ? T.rec[off + 4 * R.nrows + R.nlanes + e] : -1;
+        R.code[j] = lane < R.nlanes ? T.rec[off + 4 * R.nrows + R.nlanes + R.nent + e] : -1;
+    }
+}
+
+template <typename TV, typename TA, bool FWD>
+__global__ __launch_bounds__(kStreamBlock) void k_solve_stream(SolveArgs A, StreamArgs T) {
+    using U = typename Pub<TA>::U;
+    constexpr int Q = kTailQ, E = kStreamEnt, W = kTailW, J = kTailJ, S = kStreamStagers;
+    extern __shared__ __align__(16) unsigned char st_smem[];
+    U *vals = reinterpret_cast<U *>(st_smem + T.off_vals);          // ring [W], staged old values [Q][E], zero
+    TA *sa = reinterpret_cast<TA *>(st_smem + T.off_a);             // [Q][J][64] coefficients
+    uint16_t *sc = reinterpret_cast<uint16_t *>(st_smem + T.off_c); // [Q][J][64] value slot of each entry
+    // [Q][64] per compute lane: log2 group | leader << 8, and for a leader its
+    // row's ring slot, row, output row; right-hand side and reciprocal pivot
+    int4 *slane = reinterpret_cast<int4 *>(st_smem + T.off_lane);
+    TA *srhs = reinterpret_cast<TA *>(st_smem + T.off_rhs);         // [Q][64]
+    TA *spiv = reinterpret_cast<TA *>(st_smem + T.off_piv);         // [Q][64]
+    int32_t *shdr = reinterpret_cast<int32_t *>(st_smem + T.off_hdr);     // [Q]
+    int32_t *ready = reinterpret_cast<int32_t *>(st_smem + T.off_sync);   // [Q]
+    int32_t *done = ready + Q;
+    int32_t *labort = ready + Q + 1;
+    const int zero = W + Q * E;
+    const int col = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < Q; i += kStreamBlock) ready[i] = -1;
+    if (threadIdx.x == 0) {
+        *done = -1;
+        *labort = 0;
+        vals[zero] = bits_of<TA>((TA)0);
+    }
+    __syncthreads();
+    const TV *val = static_cast<const TV *>(A.val);
+    TA *y = static_cast<TA *>(A.y);
+    TA *z = static_cast<TA *>(A.z);
+    const int64_t cap = A.cap;
+    if (wave == 0) {
+        // Everything a step needs is staged per compute lane, so the first LDS
+        // round trip of a step depends on nothing and is issued speculatively at
+        // the end of the previous step together with the read of the step's ready
+        // word (LDS serves one wave's reads in order, so data read after a ready
+        // word that shows the step is the staged data); only when the word shows
+        // an older step does the wave wait and read again.  The second round trip
+        // reads the dependency values; then the group sum, one ring write and the
+        // published stores.
+        TA carry = (TA)0;
+        int rdy, h, c[J];
+        int4 ln;
+        TA a[J], rhs, piv;
+        auto first_batch = [&](int slot) {
+            rdy = __hip_atomic_load(&ready[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            h = shdr[slot];
+            ln = slane[slot * 64 + lane];
+            rhs = srhs[slot * 64 + lane];
+            piv = spiv[slot * 64 + lane];
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                c[j] = sc[(slot * J + j) * 64 + lane];
+                a[j] = sa[(slot * J + j) * 64 + lane];
+            }
+        };
+        if (T.nsteps > 0) first_batch(0);
+        for (int s = 0; s < T.nsteps; ++s) {
+            if (rdy < s) {
+                if (!lds_wait_ge(&ready[s % Q], s, labort, A.info, false)) break;
+                first_batch(s % Q);
+            }
+            TA acc = (TA)0;
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const TA x = Pub<TA>::from(lds_ld<TA>(vals + c[j]));
+                const TA prod = a[j] * x;
+                acc = acc + prod;
+            }
+            acc = seg_sum(acc, ln.x & 255, (h >> 16) & 255);
+            const int flags = h >> 24;
+            if (flags & kTailCarryIn) acc = acc + carry;
+            if (!(flags & kTailEmit)) {
+                carry = acc;
+            } else if (ln.x >> 8) {
+                TA v = rhs - acc;
+                if (!A.unit_diag) v = v * piv;
+                lds_st<TA>(vals + ln.y, bits_of<TA>(v));
+                tile_store<TA, FWD>(A, ln.z, ln.w, col, v);
+            }
+            // the step's buffer is free: every read of it has returned (its values
+            // were used above), and LDS takes this write after them
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            if (lane == 0) __hip_atomic_store(done, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (s + 1 < T.nsteps) first_batch((s + 1) % Q);
+        }
+        return;
+    }
+    // Stagers: wave w stages steps w - 1, w - 1 + S, ...  Software pipeline over
+    // the wave's steps: the header two steps ahead, the record one ahead, the
+    // values it points at for the current step, issued before the wait for the
+    // step's buffer
+    const TA *dep = FWD ? y : z;
+    const int s0 = wave - 1;
+    if (s0 >= T.nsteps) return;
+    StreamRec<J> cur;
+    stream_rec_load<J>(cur, T, T.hdr[s0], lane);
+    int4 hd1 = s0 + S < T.nsteps ? T.hdr[s0 + S] : make_int4(0, 0, 0, 0);
+    for (int s = s0; s < T.nsteps; s += S) {
+        const int slot = s % Q;
+        // the values of step s; this lane stages compute lane `lane`, whose row
+        // is row k of the step (its lane word), for which it also reads the
+        // right-hand side and the pivot
+        TA a[J];
+        U xo[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            a[j] = cur.p[j] >= 0 ? (TA)load_val(val, cur.p[j]) : (TA)0;
+            xo[j] = cur.code[j] >= W ? Pub<TA>::load(dep + (int64_t)(cur.code[j] - W) * cap + col) : (U)0;
+        }
+        const bool lead = lane < cur.nlanes && ((cur.li >> 16) & 1);
+        TA rhs = (TA)0, pv = (TA)1;
+        int outr = 0;
+        if (lead) {
+            if constexpr (FWD) {
+                rhs = load_vec<TA>(A.b, A.vec_f32, (int64_t)(A.perm ? cur.lr.z : cur.lr.x) * A.ld + col);
+            } else {
+                rhs = y[(int64_t)cur.lr.x * cap + col];
+                if (!A.unit_diag) pv = (TA)load_val(val, cur.lr.w);
+            }
+            outr = A.perm ? cur.lr.z : cur.lr.x;
+        }
+        // the record of step s + S and the header of step s + 2S
+        StreamRec<J> nxt;
+        nxt.nrows = nxt.nlanes = nxt.nent = 0;
+        if (s + S < T.nsteps) stream_rec_load<J>(nxt, T, hd1, lane);
+        const int4 hd2 = s + 2 * S < T.nsteps ? T.hdr[s + 2 * S] : make_int4(0, 0, 0, 0);
+        // the buffer is free once step s - Q is done
+        if (s >= Q && !lds_wait_ge(done, s - Q, labort, A.info, true, true)) break;
+        // a dependency published but not yet visible is waited for (it was
+        // computed kTailQ or more steps ago)
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+            if (cur.code[j] >= W && xo[j] == Pub<TA>::kPend)
+                xo[j] = bits_of<TA>(Pub<TA>::wait(dep + (int64_t)(cur.code[j] - W) * cap + col, A.info, A.poll_sleep));
+        // entry j of compute lane `lane` to [slot][j][lane]; padding and lanes
+        // beyond the step's lanes read the zero slot with coefficient 0
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int q = slot * E + j * 64 + lane;
+            int idx = zero;
+            if (cur.code[j] >= W) {
+                idx = W + q;
+                lds_st<TA>(vals + idx, xo[j]);
+            } else if (cur.code[j] >= 0) {
+                idx = cur.code[j];
+            }
+            sc[q] = (uint16_t)idx;
+            sa[q] = a[j];
+        }
+        const int gl = lane < cur.nlanes ? (cur.li >> 8) & 255 : 0;
+        slane[slot * 64 + lane] = make_int4(gl | (lead ? 256 : 0), cur.lr.y, cur.lr.x, outr);
+        srhs[slot * 64 + lane] = rhs;
+        spiv[slot * 64 + lane] = (TA)1 / pv;
+        if (lane == 0) {
+            shdr[slot] = cur.h;
+            __hip_atomic_store(&ready[slot], s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        cur = nxt;
+        hd1 = hd2;
+    }
+}
+
+// ---------------------------------------------------------------------------------
 // Tiled factor (ILU(k, tau) at k = k_max on the forward tiles): rows and imported
 // U rows in LDS
 // ---------------------------------------------------------------------------------
@@ -2121,6 +2389,49 @@ static hipError_t tiled_dispatch(const SolveArgs &A, const TileArgs &T, bool fwd
     return tiled_lanes<1, TV, TA>(A, T, fwd, s);
 }
 
+// LDS carve-up of a stream launch
+static size_t stream_layout(StreamArgs *T, int acc_bytes) {
+    constexpr int Q = kTailQ, E = kStreamEnt;
+    size_t o = 0;
+    T->off_vals = 0;
+    o = align8((size_t)(kTailW + Q * E + 1) * acc_bytes);
+    T->off_a = (int32_t)o;
+    o = align8(o + (size_t)Q * E * acc_bytes);
+    T->off_c = (int32_t)o;
+    o = align8(o + (size_t)Q * E * 2);
+    o = (o + 15) & ~(size_t)15;
+    T->off_lane = (int32_t)o;
+    o = align8(o + (size_t)Q * 64 * 16);
+    T->off_rhs = (int32_t)o;
+    o = align8(o + (size_t)Q * 64 * acc_bytes);
+    T->off_piv = (int32_t)o;
+    o = align8(o + (size_t)Q * 64 * acc_bytes);
+    T->off_hdr = (int32_t)o;
+    o = align8(o + (size_t)Q * 4);
+    T->off_sync = (int32_t)o;
+    o = align8(o + (size_t)(Q + 2) * 4);
+    T->lds_bytes = (int32_t)o;
+    return o;
+}
+
+template <typename TV, typename TA>
+static hipError_t stream_launch(const SolveArgs &A, const StreamArgs &T0, bool fwd, hipStream_t s) {
+    StreamArgs T = T0;
+    const size_t lds = stream_layout(&T, sizeof(TA));
+    if (lds > (size_t)kTileLdsMax) return hipErrorInvalidValue;
+    if (T.nsteps <= 0 || A.nrhs <= 0) return hipSuccess;
+    const void *fn = fwd ? (const void *)k_solve_stream<TV, TA, true> : (const void *)k_solve_stream<TV, TA, false>;
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    if (fwd)
+        hipLaunchKernelGGL((k_solve_stream<TV, TA, true>), dim3(A.nrhs), dim3(kStreamBlock), lds, s, A, T);
+    else
+        hipLaunchKernelGGL((k_solve_stream<TV, TA, false>), dim3(A.nrhs), dim3(kStreamBlock), lds, s, A, T);
+    return hipGetLastError();
+}
+
 // LDS carve-up of a tiled factor launch
 static size_t factor_tile_layout(const FactorTileArgs &T, int G, bool milu, bool tau, FactorTileArgs *out) {
     size_t o = align8((size_t)T.max_vals * 8);
@@ -2196,6 +2507,18 @@ hipError_t launch_solve_tiled(const SolveArgs &A, const TileArgs &T, bool forwar
         case 0: return tiled_dispatch<double, double>(B, T, forward, s);
         case 1: return tiled_dispatch<float, float>(B, T, forward, s);
         case 2: return tiled_dispatch<uint16_t, float>(B, T, forward, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_solve_stream(const SolveArgs &A, const StreamArgs &T, bool forward, int prec, int vec,
+                               hipStream_t s) {
+    SolveArgs B = A;
+    B.vec_f32 = vec;
+    switch (prec) {
+        case 0: return stream_launch<double, double>(B, T, forward, s);
+        case 1: return stream_launch<float, float>(B, T, forward, s);
+        case 2: return stream_launch<uint16_t, float>(B, T, forward, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -4,7 +4,9 @@
 // row the longest row needs), and the tiled launch at tile sizes of 128, 256,
 // 512 and 1024 rows (and the handle's own size).  The tile size is this design's
 // level-merge threshold: a tile merges consecutive levels of up to that many rows
-// into one workgroup whose dependencies go through LDS.  One tiling serves the
+// into one workgroup whose dependencies go through LDS.  The apply also tries the
+// lower stage (narrow levels at the end of each direction streamed by one
+// workgroup, levels of fewer than 64 rows or the handle's own threshold).  One tiling serves the
 // factor and the solves, so the apply -- called many times per factor -- picks
 // it; the factor then picks its scheme with that tiling in place.  Every
 // schedule computes the same bits (the factor reproduces the serial up-looking
@@ -75,7 +77,9 @@ extern "C" ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, 
         *us = 1e3 * ms / reps;
         return ILU_OK;
     };
+    const int32_t save_tail = h->tail_min_rows;
     auto restore = [&](ilu_status st) {
+        if (h->tail_min_rows != save_tail) (void)h->make_tail(save_tail);
         h->sched_factor = save_fs;
         h->sched_solve = save_ss;
         h->lanes_factor = save_lf;
@@ -93,6 +97,12 @@ extern "C" ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, 
     auto apply = [&]() { return ilu_apply(h, b, x, 1, 1, ILU_PREC_F64, ILU_PREC_F64, ILU_PERMUTED_SPACE, s); };
 
     // ---- tiled: tile sizes (the level-merge threshold), apply and factor ----
+    // (without a lower stage; it is a candidate of its own below)
+    const int32_t tail_in = h->tail_min_rows;
+    if (tail_in != 0) {
+        ilu_status st = h->make_tail(0);
+        if (st != ILU_OK) return restore(st);
+    }
     std::vector<int32_t> sizes = {128, 256, 512, 1024};
     if (std::find(sizes.begin(), sizes.end(), save_tr) == sizes.end()) sizes.push_back(save_tr);
     struct TileRes {
@@ -119,7 +129,7 @@ extern "C" ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, 
         tres.push_back(r);
     }
     h->sched_factor = save_fs;
-    // ---- level and sync-free applies, lanes per row ----
+    // ---- level and sync-free applies, lanes per row (without a lower stage) ----
     double best_apply = 1e300;
     int best_ss = save_ss, best_ls = save_ls;
     int32_t best_tr = save_tr;
@@ -145,6 +155,25 @@ extern "C" ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, 
         }
     h->sched_solve = best_ss;
     h->lanes_solve = best_ss == ILU_SCHED_TILED ? save_ls : best_ls;
+    // the lower stage: narrow levels at the end of each direction streamed by one
+    // workgroup (levels of fewer than 64 rows), next to the best schedule so far
+    int32_t best_tail = 0;
+    for (int32_t m : {tail_in > 0 ? tail_in : 64}) {
+        ilu_status st = h->make_tail(m);
+        if (st != ILU_OK) return restore(st);
+        if (m > 0 && h->tail[0].nsteps == 0 && h->tail[1].nsteps == 0) continue;
+        double us = 0;
+        if ((st = time_it(apply, &us)) != ILU_OK) return restore(st);
+        rows.insert(rows.end(), {1.0, 10.0, (double)m, us});
+        if (us < best_apply) {
+            best_apply = us;
+            best_tail = m;
+        }
+    }
+    if (h->tail_min_rows != best_tail) {
+        ilu_status st = h->make_tail(best_tail);
+        if (st != ILU_OK) return restore(st);
+    }
     // the tiling of the chosen apply (or, when the apply is not tiled, the one the
     // tiled factor liked best)
     if (best_ss != ILU_SCHED_TILED) {

@@ -42,7 +42,7 @@ class Ilu:
     """Analysis handle: ILU(k_max) pattern, level schedule and permuted structure of A."""
 
     def __init__(self, n=None, row_ptr=None, col_idx=None, k_max=0, pattern="sym", host_only=False,
-                 tile_rows=0, ordering="natural", _handle=None):
+                 tile_rows=0, ordering="natural", tail_min_rows=0, _handle=None):
         self.lib = L.load()
         self.h = C.c_void_p()
         if _handle is not None:
@@ -53,7 +53,7 @@ class Ilu:
             csr = L.Csr(int(n), int(rp[-1]), _np_ptr(rp), _np_ptr(ci))
             opts = L.AnalyzeOpts(int(k_max), L.PATTERN_LOWER_SYM if pattern == "sym" else L.PATTERN_LOWER_A,
                                  1 if host_only else 0, int(tile_rows),
-                                 {"natural": L.ORDER_NATURAL, "rcm": L.ORDER_RCM}[ordering])
+                                 {"natural": L.ORDER_NATURAL, "rcm": L.ORDER_RCM}[ordering], int(tail_min_rows))
             L.check(self.lib.ilu_analyze(C.byref(csr), C.byref(opts), C.byref(self.h)), "ilu_analyze")
         self._info = L.Info()
         L.check(self.lib.ilu_get_info(self.h, C.byref(self._info)), "ilu_get_info")
@@ -95,7 +95,8 @@ class Ilu:
         return dict(n=I.n, n_levels=I.n_levels, n_ulevels=I.n_ulevels, max_row_lu=I.max_row_lu,
                     nnz_a=I.nnz_a, nnz_lu=I.nnz_lu, nnz_b=I.nnz_b, level_min=I.level_min,
                     level_max=I.level_max, level_median=I.level_median, batch_count=I.batch_count,
-                    n_tiles=I.n_tiles, n_utiles=I.n_utiles, tile_rows=I.tile_rows, max_tile=I.max_tile)
+                    n_tiles=I.n_tiles, n_utiles=I.n_utiles, tile_rows=I.tile_rows, max_tile=I.max_tile,
+                    tail_rows=I.tail_rows, tail_urows=I.tail_urows)
 
     def schedule(self):
         I = self._info
@@ -122,6 +123,15 @@ class Ilu:
         L.check(self.lib.ilu_copy_tiles(self.h, int(direction), _np_ptr(ptr), _np_ptr(row), _np_ptr(sci)),
                 "ilu_copy_tiles")
         return ptr, row, sci
+
+    def tail(self, direction=0):
+        """The lower stage of one solve direction: dict(level0, pos0, nsteps, hdr [nsteps+1][4], rec)."""
+        sz = np.zeros(4, np.int32)
+        L.check(self.lib.ilu_copy_tail(self.h, int(direction), _np_ptr(sz), None, None), "ilu_copy_tail")
+        hdr = np.zeros((int(sz[2]) + 1) * 4 if sz[2] > 0 else 0, np.int32)
+        rec = np.zeros(int(sz[3]), np.int32)
+        L.check(self.lib.ilu_copy_tail(self.h, int(direction), None, _np_ptr(hdr), _np_ptr(rec)), "ilu_copy_tail")
+        return dict(level0=int(sz[0]), pos0=int(sz[1]), nsteps=int(sz[2]), hdr=hdr.reshape(-1, 4), rec=rec)
 
     def batch_offsets(self):
         cnt = self._info.batch_count

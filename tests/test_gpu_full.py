@@ -75,6 +75,40 @@ def test_random_1m_16rhs_full(jv):
     assert relerr(x32[:, cols], xr32) <= 2.0 ** -12
 
 
+def test_random_1m_tail_full(jv):
+    # every level of random_1m holds fewer than 15 rows: the whole matrix is the
+    # lower stage, streamed by one workgroup per right-hand side (16 at once)
+    A, B = synth.workload(4)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx, tail_min_rows=64)
+    assert ilu.info()["tail_rows"] == A.n
+    ilu.factor(dev(A.val), casts=("f32",))
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    f = O.factor(an, A.val)
+    cols = [0, 7, 15]
+    x = ilu.apply(dev(B)).cpu().numpy()
+    assert relerr(x[:, cols], O.apply(an, f.val, np.ascontiguousarray(B[:, cols]))) <= 1e-12
+    B32 = B.astype(np.float32)
+    x32 = ilu.apply(dev(B32), prec="f32").cpu().numpy().astype(np.float64)
+    xr32 = O.apply(an, O.cast_f32(f.val), np.ascontiguousarray(B32[:, cols]).astype(np.float64), prec="f32")
+    assert relerr(x32[:, cols], xr32) <= 2.0 ** -12
+    ilu.status()
+
+
+def test_heavy_1m_natural_tail_full(jv):
+    # the irregular matrix in its natural order (322k forward levels): the lower
+    # stage with rows of up to 2053 entries split over steps of one wave
+    A = synth.heavy_rows(1_000_000, rng=np.random.default_rng([6, 0]))
+    b = np.ascontiguousarray(synth.rhs(A.n, 1, np.random.default_rng([6, 1]))).reshape(-1)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx, tail_min_rows=64)
+    assert ilu.info()["tail_rows"] > 0.9 * A.n
+    ilu.factor(dev(A.val), casts=())
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    f = O.factor(an, A.val)
+    x = ilu.apply(dev(b)).cpu().numpy()
+    assert relerr(x, O.apply(an, f.val, b)) <= 1e-12
+    ilu.status()
+
+
 def test_batch512_full(jv):
     mats, rhs = synth.workload(5)
     hb = jv.Ilu.batched(mats)

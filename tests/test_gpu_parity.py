@@ -349,6 +349,54 @@ def test_apply_low_precision(jv, sched, prec, vec):
     assert relerr(x, xr) <= 2.0 ** -17
 
 
+TAIL_CASES = [
+    ("random_banded_6000_all", lambda: synth.random_banded(6000, rng=np.random.default_rng(31)), 0, 65536),
+    ("laplace2d_150_tail65", lambda: synth.laplace2d(150), 0, 65),
+    ("heavy_4000_long_rows", lambda: synth.heavy_rows(4000, heavy_len=(150, 700), heavy_frac=0.03,
+                                                      rng=np.random.default_rng(32)), 0, 65536),
+    ("random_banded_3000_ilu1_all", lambda: synth.random_banded(3000, rng=np.random.default_rng(33)), 1, 65536),
+]
+
+
+@pytest.mark.parametrize("sched", ["tiled", "syncfree", "level"])
+@pytest.mark.parametrize("name,mk,k,M", TAIL_CASES, ids=[c[0] for c in TAIL_CASES])
+def test_tail_apply(jv, name, mk, k, M, sched):
+    # the lower stage: the levels before it on the handle's schedule (sync-free or
+    # level launches), the tail streamed by one workgroup per right-hand side
+    A = mk()
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k)
+    f = O.factor(an, A.val, k=k)
+    assert f.status == O.OK
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=k, tile_rows=128, tail_min_rows=M)
+    ilu.set_schedule("syncfree", sched)
+    info = ilu.info()
+    assert info["tail_rows"] > 0 and info["tail_urows"] > 0
+    ilu.factor(dev(A.val), k=k, casts=("f32",))
+    rng = np.random.default_rng(34)
+    for nrhs in (1, 3):
+        b = rng.uniform(-1, 1, (A.n, nrhs)) if nrhs > 1 else rng.uniform(-1, 1, A.n)
+        x = ilu.apply(dev(b)).cpu().numpy()
+        assert relerr(x, O.apply(an, f.val, b)) <= 1e-12
+        b32 = b.astype(np.float32)
+        x32 = ilu.apply(dev(b32), prec="f32").cpu().numpy().astype(np.float64)
+        xr32 = O.apply(an, O.cast_f32(f.val), b32.astype(np.float64), prec="f32")
+        assert relerr(x32, xr32) <= 2.0 ** -17
+    bp = rng.uniform(-1, 1, A.n)
+    xp = dev(bp)
+    ilu.apply(xp, x=xp, permuted=True)   # in place, level ordering
+    assert relerr(xp.cpu().numpy(), O.apply(an, f.val, bp, permuted=True)) <= 1e-12
+    ilu.status()
+    _, si = ilu.gmres(dev(rng.uniform(-1, 1, A.n)), rtol=1e-10, restart=30)
+    assert si["true_relres"] <= 1e-10
+    # and the same handle without the lower stage gives the same results
+    ilu.set_tuning("tail_min_rows", 0)
+    assert ilu.info()["tail_rows"] == 0
+    x0 = ilu.apply(dev(bp)).cpu().numpy()
+    ilu.set_tuning("tail_min_rows", M)
+    x1 = ilu.apply(dev(bp)).cpu().numpy()
+    assert relerr(x1, x0) <= 1e-12
+
+
 @pytest.mark.parametrize("sched", FACTOR_SCHEDS, ids=lambda s: s[0])
 @pytest.mark.parametrize("name,mk,k,tau,milu", [
     ("random_3000", lambda: synth.random_banded(3000, rng=np.random.default_rng(10)), 0, 0.0, False),
@@ -623,6 +671,26 @@ def test_tune_no_slower_and_same_factor(jv, name, mk, k, tau, milu):
     t_app1 = _stage_us(ilu, lambda: ilu.apply(b, permuted=True), 10, ("forward", "backward"))
     assert t_app1 <= 1.25 * t_app0 + 20.0, (t_app0, t_app1, chosen)
     assert t_fac1 <= 1.25 * t_fac0 + 20.0, (t_fac0, t_fac1, chosen)
+
+
+def test_tune_tries_the_lower_stage(jv):
+    # narrow levels everywhere: the tuner times the lower stage next to the other
+    # schedules, keeps whichever is faster, and the results stay the oracle's
+    A = synth.random_banded(6000, rng=np.random.default_rng(35))
+    a = dev(A.val)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
+    ilu.factor(a)
+    res, chosen = ilu.tune(a, reps=3)
+    assert (res[:, 1] == 10).any()
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    f = O.factor(an, A.val)
+    lu, _ = ilu.factor_values()
+    assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
+    b = np.random.default_rng(36).uniform(-1, 1, A.n)
+    assert relerr(ilu.apply(dev(b)).cpu().numpy(), O.apply(an, f.val, b)) <= 1e-12
+    tail_rows = res[res[:, 1] == 10]
+    best_other = res[(res[:, 0] == 1) & (res[:, 1] != 10)][:, 3].min()
+    assert (ilu.get_tuning("tail_min_rows") > 0) == (tail_rows[:, 3].min() < best_other)
 
 
 @pytest.mark.parametrize("sched", ["tiled", "syncfree", "level"])
