@@ -119,6 +119,32 @@ struct TailPlan {
 // has fewer than min_levels levels.
 void build_tail(const HostAnalysis &H, int dir, int32_t min_rows, int32_t min_levels, TailPlan *T);
 
+// Lower stage of the numeric factor: the same rows as the forward solve's tail,
+// cut into steps of rows of one level; each row has an aligned group of G >= its
+// length lanes, lane t holding entry t.  For every L entry e of a row (ascending)
+// and every lane t of it, the source of the U(c_e) value lane t needs: its pivot
+// u_cc when t == e, u_cj when the column of entry t is j of U(c_e), none
+// otherwise.  Sources are the ring of recent U parts in LDS (kFTailW rows of umax
+// entries) or the factor buffer.
+constexpr int kFTailK = 16;      // most L entries of a tail row
+constexpr int kFTailQ = 8;       // steps staged ahead
+constexpr int kFTailW = 512;     // ring of recent U parts (rows)
+struct FactorTailPlan {
+    int32_t pos0 = 0, nsteps = 0;
+    int32_t umax = 0;            // longest U part (diagonal included) of a tail row
+    // 4 per step (+ a sentinel): record offset, nrows | nlanes << 8 | kmax << 16, 0, 0
+    std::vector<int32_t> hdr;
+    // per step: per lane 4 words (row in the step | t << 8 | K << 16 | len << 24;
+    // factor entry of entry t (-1 past the row); input entry of it (-1: fill);
+    // ring index of entry t if it is in the U part, else -1), then per L entry e
+    // < kmax (e-major) and lane the source: -1 none, < kFTailW * umax a ring index,
+    // else kFTailW * umax + factor entry
+    std::vector<int32_t> rec;
+};
+// false (and no plan) when a tail row is longer than 64 entries, has more than
+// kFTailK L entries, or the forward solve has no tail
+bool build_factor_tail(const HostAnalysis &H, const TailPlan &fwd, FactorTailPlan *T);
+
 // Data of the tiled factor on the forward tiles.  LDS of a tile: the value area
 // (the tile's rows' entries in slot order, then the U parts -- diagonal first -- of
 // its imports) and one ready flag per tile row and per import.  Per tile row:
@@ -143,6 +169,23 @@ struct FactorTiles {
                                        // whose update goes to u_rr in modified ILU (column r, or a
                                        // column that row r does not hold)
     std::vector<int32_t> imp;          // 4 per import: diagonal entry, U length, value-area offset, 0
+    // What one tile stages, in one piece: per tile kFactorHdr words of header (see
+    // FactorHdr), its tables as one 16-byte aligned blob in the order and layout
+    // they take in LDS, and the input entry of each of its rows' value slots (-1:
+    // fill).  lds_need[tau + 2 * modified]: bytes of LDS the largest tile needs.
+    std::vector<int32_t> hdr;
+    std::vector<int32_t> blob;         // 16-byte units (4 words each)
+    std::vector<int32_t> vsrc;
+    size_t lds_need[4] = {0, 0, 0, 0};
+};
+
+// Header words of a factor tile: blob offset and size (16-byte units), rows,
+// imports, L entries, positions; byte offsets in the blob of the off, dloc,
+// dflag, match, imp and position-slot tables (meta at 0); first value-source
+// entry, row value slots, all value slots (imports included), first L entry.
+enum FactorHdr {
+    kFhBlob, kFhBlobSize, kFhRows, kFhImps, kFhLents, kFhPos, kFhOff, kFhDloc, kFhDflag, kFhMatch, kFhImp, kFhPs,
+    kFhVsrc, kFhRowVals, kFhVals, kFhL0, kFactorHdr
 };
 
 // Builds the tiled-factor data from the forward tiles; lanes = power of two >= the

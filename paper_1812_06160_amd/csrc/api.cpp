@@ -358,13 +358,7 @@ ilu_status ilu_handle_s::make_factor_tiles() {
     const int32_t lanes = H.max_row_lu <= 8 ? 8 : H.max_row_lu <= 16 ? 16 : 32;
     auto fits = [&](const TileSet &S) {
         build_factor_tiles(H, S, lanes, &ftiles);
-        FactorTileArgs T{};
-        T.max_rows = S.max_rows;
-        T.max_vals = ftiles.max_vals;
-        T.max_lents = ftiles.max_lents;
-        T.max_pos = S.max_pos;
-        T.max_imps = S.max_imps;
-        return factor_tile_lds_bytes(T, lanes, true, true) <= (size_t)kFactorTileLdsMax;
+        return ftiles.lds_need[3] <= (size_t)kFactorTileLdsMax;
     };
     try {
         bool ok = fits(tiles[0]);
@@ -411,16 +405,9 @@ ilu_status ilu_handle_s::make_factor_tiles() {
         n_arm = (int32_t)ranges.size();
         arm_built = true;
     }
-    if ((e = put(dft.meta, ftiles.meta)) != hipSuccess || (e = put(dft.off, ftiles.off)) != hipSuccess ||
-        (e = put(dft.lptr, ftiles.lptr)) != hipSuccess || (e = put(dft.dloc, ftiles.dloc)) != hipSuccess ||
-        (e = put(dft.dflag, ftiles.dflag)) != hipSuccess || (e = put(dft.match, ftiles.match)) != hipSuccess ||
-        (e = put(dft.imp, ftiles.imp)) != hipSuccess || (e = put(dft.cmask, ftiles.cmask)) != hipSuccess)
+    if ((e = put(dft.hdr, ftiles.hdr)) != hipSuccess || (e = put(dft.blob, ftiles.blob)) != hipSuccess ||
+        (e = put(dft.vsrc, ftiles.vsrc)) != hipSuccess || (e = put(dft.cmask, ftiles.cmask)) != hipSuccess)
         return hip_fail(e, "factor tiles: upload");
-    if (ftset_own) {
-        if ((e = put(dftset.pslot, position_slots(ftset))) != hipSuccess || (e = put(dftset.ptr, ftset.ptr)) != hipSuccess ||
-            (e = put(dftset.rows_ptr, ftset.rows_ptr)) != hipSuccess || (e = put(dftset.imp_ptr, ftset.imp_ptr)) != hipSuccess)
-            return hip_fail(e, "factor tiles: upload");
-    }
     ftiles_ok = true;
     return ILU_OK;
 }
@@ -807,26 +794,13 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
     A.lcap = long_rows ? H.max_row_lu : 0;
     if (tiled) {
         const TileSet &T0 = h->ftset_own ? h->ftset : h->tiles[0];
-        const ilu_handle_s::DevTiles &D = h->ftset_own ? h->dftset : h->dtiles[0];
         FactorTileArgs T{};
-        T.tile_ptr = D.ptr;
-        T.pslot = D.pslot;
-        T.rows_ptr = D.rows_ptr;
-        T.meta = reinterpret_cast<const int4 *>(h->dft.meta);
-        T.off = reinterpret_cast<const int2 *>(h->dft.off);
-        T.lptr = h->dft.lptr;
-        T.dloc = h->dft.dloc;
-        T.dflag = h->dft.dflag;
-        T.match = h->dft.match;
+        T.hdr = h->dft.hdr;
+        T.blob = reinterpret_cast<const int4 *>(h->dft.blob);
+        T.vsrc = h->dft.vsrc;
         T.cmask = h->dft.cmask;
-        T.imp_ptr = D.imp_ptr;
-        T.imp = reinterpret_cast<const int4 *>(h->dft.imp);
         T.ntiles = T0.ntiles;
-        T.max_rows = T0.max_rows;
-        T.max_vals = h->ftiles.max_vals;
-        T.max_lents = h->ftiles.max_lents;
-        T.max_pos = T0.max_pos;
-        T.max_imps = T0.max_imps;
+        T.lds_bytes = (int32_t)h->ftiles.lds_need[(use_tau ? 1 : 0) + (milu ? 2 : 0)];
         T.counter = tile_counter;
         A.poll_sleep = h->poll_sleep;
         // only U parts that other tiles import are polled: arm just those

@@ -168,22 +168,20 @@ hipError_t launch_solve_stream(const SolveArgs &A, const StreamArgs &T, bool for
 
 // Tiled factor (plain ILU: every pattern entry kept, no dropping) on the forward
 // tiles; see FactorTiles in analysis.h for the data.
+// One tile's tables live in a blob in the layout they take in LDS (FactorHdr
+// gives the offsets): per tile row meta (row, first entry, end entry, diagonal
+// entry; the row complemented when its L entries are independent) and off
+// (value-area offset, L-entry offset); per L entry the LDS location and ready
+// flag of its U row and, per lane, the position of the lane's column in that U
+// row; per import (diagonal entry, U length, value-area offset); per position
+// the row slot (-1: padding).
 struct FactorTileArgs {
-    const int32_t *tile_ptr;  // [ntiles + 1] positions (forward tiles)
-    const int16_t *pslot;     // slot of each position, -1 for padding
-    const int32_t *rows_ptr;  // [ntiles + 1] offsets into meta / off
-    const int4 *meta;         // per tile row: row, first entry, end entry, diagonal entry
-    const int2 *off;          // per tile row: value-area offset, L-entry offset
-    const int32_t *lptr;      // [ntiles + 1] offsets into the L-entry arrays
-    const int32_t *dloc, *dflag;
-    const int8_t *match;      // lanes per L entry
+    const int32_t *hdr;       // kFactorHdr words per tile
+    const int4 *blob;
+    const int32_t *vsrc;      // input entry of each row value slot, -1 for fill
     const uint32_t *cmask;    // per L entry: U(c) positions whose update goes to the diagonal (modified ILU)
-    const int32_t *imp_ptr;   // [ntiles + 1] offsets into imp
-    const int4 *imp;          // per import: diagonal entry, U length, value-area offset
-    int32_t ntiles, max_rows, max_vals, max_lents, max_pos, max_imps;
-    // LDS carve-up (bytes), set by the launcher
-    int32_t off_flags, off_meta, off_off, off_dloc, off_dflag, off_match, off_cmask, off_imp, off_pslot, off_tau,
-        lds_bytes;
+    int32_t ntiles;
+    int32_t lds_bytes;        // LDS of the largest tile image
     int32_t *counter;         // claim counter (zero at launch)
 };
 
@@ -246,7 +244,6 @@ hipError_t launch_spmv(const SpmvArgs &A, int lanes, hipStream_t s);
 // tiled factor with `lanes` (8, 16 or 32) lanes per row; hipErrorInvalidValue when it
 // does not fit LDS
 hipError_t launch_factor_tiled(const FactorArgs &A, const FactorTileArgs &T, int lanes, hipStream_t s);
-size_t factor_tile_lds_bytes(const FactorTileArgs &T, int lanes, bool milu, bool tau);
 // tiled solve; returns hipErrorInvalidValue when no right-hand-side blocking fits LDS
 hipError_t launch_solve_tiled(const SolveArgs &A, const TileArgs &T, bool forward, int prec, int vec,
                               hipStream_t s);

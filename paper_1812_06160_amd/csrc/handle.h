@@ -102,11 +102,8 @@ struct ilu_handle_s {
     // image for it (ftset_own); otherwise the factor uses tiles[0] / dtiles[0]
     jv::TileSet ftset;
     bool ftset_own = false;
-    DevTiles dftset;
     struct DevFactorTiles {
-        int32_t *meta = nullptr, *off = nullptr, *lptr = nullptr, *dloc = nullptr, *dflag = nullptr,
-                *imp = nullptr;
-        int8_t *match = nullptr;
+        int32_t *hdr = nullptr, *blob = nullptr, *vsrc = nullptr;
         uint32_t *cmask = nullptr;
     } dft;
     int32_t *d_arm = nullptr;          // tiled factor: (diagonal entry, U length) of every imported row

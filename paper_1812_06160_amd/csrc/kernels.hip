@@ -30,6 +30,7 @@
 // correctly rounded; with the columns of a row taken in ascending order the
 // factor reproduces a serial up-looking ILU bit for bit.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <climits>
 #include <cstdint>
 
@@ -1772,17 +1773,25 @@ __device__ void factor_poll(const int4 *imp, int nimp, const double *lu, double 
             const int4 m = imp[i];
             const uint32_t all = m.y >= 32 ? 0xFFFFFFFFu : ((1u << m.y) - 1u);
             if (have[b] == all) continue;
-            uint64_t raw[G];   // a U part has at most G entries
+            // a U part has at most G entries, fetched up to 8 at a time
+            constexpr int PJ = G < 8 ? G : 8;
+            for (int j0 = 0; j0 < m.y; j0 += PJ) {
+                uint64_t raw[PJ];
 #pragma unroll
-            for (int j = 0; j < G; ++j)
-                raw[j] = (j < m.y && !(have[b] >> j & 1u)) ? ld_acq_u64(reinterpret_cast<const uint64_t *>(lu + m.x + j))
-                                                           : kPending64;
+                for (int q = 0; q < PJ; ++q) {
+                    const int j = j0 + q;
+                    raw[q] = (j < m.y && !(have[b] >> j & 1u))
+                                 ? ld_acq_u64(reinterpret_cast<const uint64_t *>(lu + m.x + j))
+                                 : kPending64;
+                }
 #pragma unroll
-            for (int j = 0; j < G; ++j) {
-                if (j < m.y && !(have[b] >> j & 1u) && raw[j] != kPending64) {
-                    reinterpret_cast<uint64_t *>(vals)[m.z + j] = raw[j];
-                    have[b] |= 1u << j;
-                    got = true;
+                for (int q = 0; q < PJ; ++q) {
+                    const int j = j0 + q;
+                    if (j < m.y && !(have[b] >> j & 1u) && raw[q] != kPending64) {
+                        reinterpret_cast<uint64_t *>(vals)[m.z + j] = raw[q];
+                        have[b] |= 1u << j;
+                        got = true;
+                    }
                 }
             }
             if (have[b] == all) __hip_atomic_store(&flags[nrows + i], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1810,83 +1819,80 @@ __device__ void factor_poll(const int4 *imp, int nimp, const double *lu, double 
 }
 
 template <int G>
-__global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, FactorTileArgs T) {
-    extern __shared__ __align__(16) unsigned char fsmem[];
+__device__ __forceinline__ void factor_tile(const FactorArgs &A, const FactorTileArgs &T, int tile, unsigned char *fsmem,
+                                            int &s_abort) {
+    // The tile's header (uniform: scalar loads) and its LDS image: values, ready
+    // flags, the tables (one blob, copied as is), thresholds, modified-ILU masks.
+    const int32_t *th = T.hdr + (size_t)kFactorHdr * tile;
+    const int boff = th[kFhBlob], bsz = th[kFhBlobSize], nrows = th[kFhRows], nimp = th[kFhImps];
+    const int nl = th[kFhLents], npos = th[kFhPos], vbase = th[kFhVsrc], nvr = th[kFhRowVals];
+    const int nvals = th[kFhVals], l0 = th[kFhL0];
     double *vals = reinterpret_cast<double *>(fsmem);
-    int *flags = reinterpret_cast<int *>(fsmem + T.off_flags);
-    int4 *meta = reinterpret_cast<int4 *>(fsmem + T.off_meta);
-    int2 *off = reinterpret_cast<int2 *>(fsmem + T.off_off);
-    int32_t *dloc = reinterpret_cast<int32_t *>(fsmem + T.off_dloc);
-    int32_t *dflag = reinterpret_cast<int32_t *>(fsmem + T.off_dflag);
-    int8_t *match = reinterpret_cast<int8_t *>(fsmem + T.off_match);
-    uint32_t *cmask = reinterpret_cast<uint32_t *>(fsmem + T.off_cmask);
-    int4 *imp = reinterpret_cast<int4 *>(fsmem + T.off_imp);
-    int16_t *ps = reinterpret_cast<int16_t *>(fsmem + T.off_pslot);
-    double *tau = reinterpret_cast<double *>(fsmem + T.off_tau);
-    __shared__ int s_tile, s_abort;
-    if (threadIdx.x == 0) {
-        s_tile = __hip_atomic_fetch_add(T.counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_abort = 0;
-    }
-    __syncthreads();
-    const int tile = s_tile;
-    if (tile >= T.ntiles) return;
-    const int pbase = T.tile_ptr[tile], npos = T.tile_ptr[tile + 1] - pbase;
-    const int rbase = T.rows_ptr[tile], nrows = T.rows_ptr[tile + 1] - rbase;
-    const int lbase = T.lptr[tile], nl = T.lptr[tile + 1] - lbase;
-    const int ibase = T.imp_ptr[tile], nimp = T.imp_ptr[tile + 1] - ibase;
+    int *flags = reinterpret_cast<int *>(fsmem + ((nvals * 8 + 15) & ~15));
+    unsigned char *blob = reinterpret_cast<unsigned char *>(flags) + (((nrows + nimp) * 4 + 15) & ~15);
+    int4 *meta = reinterpret_cast<int4 *>(blob);
+    int2 *off = reinterpret_cast<int2 *>(blob + th[kFhOff]);
+    int32_t *dloc = reinterpret_cast<int32_t *>(blob + th[kFhDloc]);
+    int32_t *dflag = reinterpret_cast<int32_t *>(blob + th[kFhDflag]);
+    int8_t *match = reinterpret_cast<int8_t *>(blob + th[kFhMatch]);
+    int4 *imp = reinterpret_cast<int4 *>(blob + th[kFhImp]);
+    int16_t *ps = reinterpret_cast<int16_t *>(blob + th[kFhPs]);
+    double *tau = reinterpret_cast<double *>(blob + (size_t)bsz * 16);
+    uint32_t *cmask = reinterpret_cast<uint32_t *>(tau + (A.use_tau ? nrows : 0));
     const int t = threadIdx.x % G;
 
-    // stage the tile's tables
-    lds_copy<kStageCopy>(ps, T.pslot + pbase, npos);
-    lds_copy<kStageCopy>(reinterpret_cast<int *>(meta), reinterpret_cast<const int *>(T.meta + rbase), nrows * 4);
-    lds_copy<kStageCopy>(reinterpret_cast<int *>(off), reinterpret_cast<const int *>(T.off + rbase), nrows * 2);
-    lds_copy<kStageCopy>(dloc, T.dloc + lbase, nl);
-    lds_copy<kStageCopy>(dflag, T.dflag + lbase, nl);
-    lds_copy<kStageCopy>(reinterpret_cast<int *>(match), reinterpret_cast<const int *>(T.match + (int64_t)lbase * G),
-                         nl * G / 4);
-    if (A.milu)
-        lds_copy<kStageCopy>(reinterpret_cast<int *>(cmask), reinterpret_cast<const int *>(T.cmask + lbase), nl);
-    lds_copy<kStageCopy>(reinterpret_cast<int *>(imp), reinterpret_cast<const int *>(T.imp + ibase), nimp * 4);
-    for (int i = threadIdx.x; i < nrows + nimp; i += kTileBlock) flags[i] = 0;
-    __syncthreads();
-    // input values of the tile's rows (fill entries start at 0); imported U parts pending
-    for (int i = threadIdx.x; i < nimp; i += kTileBlock) {
-        const int4 m = imp[i];
-        for (int j = 0; j < m.y; ++j) reinterpret_cast<uint64_t *>(vals)[m.z + j] = kPending64;
+    // Staging in two memory round trips: the blob and the rows' value sources are
+    // loaded together, then the input values; the tables reach LDS meanwhile.
+    constexpr int UB = 4, UV = G <= 16 ? 8 : 4, B = kTileBlock;
+    const int4 *gblob = T.blob + boff;
+    int4 *lblob = reinterpret_cast<int4 *>(blob);
+    // (loads are unconditional, at clamped indices, so that they issue together;
+    // a tile has at least one row and one blob unit)
+    int vs[UV];
+    for (int b0 = 0;; b0 += B * UB) {
+        int4 v[UB];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) v[u] = gblob[min(b0 + (int)threadIdx.x + u * B, bsz - 1)];
+        if (b0 == 0) {
+#pragma unroll
+            for (int u = 0; u < UV; ++u) vs[u] = T.vsrc[vbase + min((int)threadIdx.x + u * B, nvr - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            const int i = b0 + threadIdx.x + u * B;
+            if (i < bsz) lblob[i] = v[u];
+        }
+        if (b0 + B * UB >= bsz) break;
     }
-    // the rows' drop thresholds, so that the compute waves issue no global load
-    if (A.use_tau) {
-        for (int i = threadIdx.x; i < nrows; i += kTileBlock) {
-            const int mx = meta[i].x;
-            tau[i] = A.row_tau[mx < 0 ? ~mx : mx];
+    for (int k0 = 0; k0 < nvr; k0 += B * UV) {
+        if (k0 > 0) {
+#pragma unroll
+            for (int u = 0; u < UV; ++u) vs[u] = T.vsrc[vbase + min(k0 + (int)threadIdx.x + u * B, nvr - 1)];
+        }
+        double a[UV];
+#pragma unroll
+        for (int u = 0; u < UV; ++u) a[u] = A.a[max(vs[u], 0)];
+#pragma unroll
+        for (int u = 0; u < UV; ++u) {
+            const int k = k0 + threadIdx.x + u * B;
+            if (k < nvr) vals[k] = vs[u] >= 0 ? a[u] : 0.0;   // fill entries start at 0
         }
     }
-    constexpr int SR = kStageRows;
-    constexpr int GROUPS = kTileBlock / G;
-    for (int s0r = threadIdx.x / G; s0r < nrows; s0r += GROUPS * SR) {
-        int src[SR];
-        int dst[SR];
-#pragma unroll
-        for (int u = 0; u < SR; ++u) {
-            const int sl = s0r + u * GROUPS;
-            src[u] = -1;
-            dst[u] = -1;
-            if (sl < nrows) {
-                const int4 m = meta[sl];
-                if (m.y + t < m.z) {
-                    dst[u] = off[sl].x + t;
-                    src[u] = A.src[m.y + t];
-                }
+    for (int i = threadIdx.x; i < nrows + nimp; i += B) flags[i] = 0;
+    if (A.use_tau || A.milu) {
+        __syncthreads();
+        // the rows' drop thresholds and the modified form's masks, so that the
+        // compute waves issue no global load
+        if (A.use_tau) {
+            for (int i = threadIdx.x; i < nrows; i += B) {
+                const int mx = meta[i].x;
+                tau[i] = A.row_tau[mx < 0 ? ~mx : mx];
             }
         }
-        double a[SR];
-#pragma unroll
-        for (int u = 0; u < SR; ++u) a[u] = src[u] >= 0 ? A.a[src[u]] : 0.0;
-#pragma unroll
-        for (int u = 0; u < SR; ++u)
-            if (dst[u] >= 0) vals[dst[u]] = a[u];
+        if (A.milu) lds_copy<kStageCopy>(cmask, T.cmask + l0, nl);
     }
+    // (imported U parts are read only after their ready flag: the poller raises it
+    // once it has copied the whole part)
     __syncthreads();
     const int wave = threadIdx.x >> 6;
     const int gi = (threadIdx.x & 63) / G;
@@ -1914,6 +1920,54 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
         if (A.bval && act) A.bval[m.y + t] = v;
         double before = 0.0;                   // an L entry's value before its division
         int dropped = 0;
+        if (flat && !A.milu && K > 0) {
+            // Independent L entries: lane t < K waits for its own dependency and
+            // divides; the multipliers then go to the U lanes four at a time, the
+            // U(c_e) values they meet read in one LDS round (positions read before
+            // the wait, every load unconditional so that none waits on another)
+            // and subtracted in ascending e as the serial loop does.
+            int uix[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int li = o.y + (q < K ? q : K - 1);
+                const int j = match[li * G + t], dl = dloc[li];
+                uix[q] = (q < K && j > 0) ? dl + j : -1;
+            }
+            const int lo = o.y + (t < K ? t : K - 1);
+            const int myflag = dflag[lo], myloc = dloc[lo];
+            if (t < K) {
+                const int ok = lds_wait_flag(&flags[myflag], &s_abort, A.info);
+                const double piv = ok ? vals[myloc] : __longlong_as_double((long long)kQNaN64);
+                v = v / piv;
+                if (A.use_tau && fabs(v) < tr) dropped = 1;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            const uint64_t dm = A.use_tau ? group_bits<G>(__ballot(dropped != 0), gi) : 0ull;
+            for (int e0 = 0;;) {
+                double u[4], l[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) u[q] = vals[uix[q] >= 0 ? uix[q] : 0];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) l[q] = __shfl(v, (e0 + q) & (G - 1), G);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const bool use = uix[q] >= 0 && !(dm >> (e0 + q) & 1ull) &&
+                                     (uint64_t)__double_as_longlong(u[q]) != kDropped64;
+                    const double prod = l[q] * u[q];
+                    const double nv = v - prod;
+                    v = use ? nv : v;
+                }
+                e0 += 4;
+                if (!__any(e0 < K)) break;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = e0 + q;
+                    const int li = o.y + (e < K ? e : K - 1);
+                    const int j = match[li * G + t], dl = dloc[li];
+                    uix[q] = (e < K && j > 0) ? dl + j : -1;
+                }
+            }
+        } else {
         if (flat) {
             // every multiplier at once: lane t < K waits for its own dependency and
             // divides; the updates below then only reach U entries
@@ -1970,6 +2024,7 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
                 }
             }
         }
+        }
         // U entries below the threshold at the end of the row (the modified form adds
         // them to the diagonal in column order), then the checks of the sync-free factor
         if (A.use_tau) {
@@ -1981,11 +2036,13 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
                 }
             }
         }
-        const double pv = __shfl(v, K, G);
+        // a zero pivot (lane K) or a non-finite kept entry, by ballot: no cross-lane
+        // move on the way to the ready flag
+        const uint64_t zpm = group_bits<G>(__ballot(t == K && v == 0.0), gi);
         const bool nonfinite = act && !dropped && !isfinite(v);
         const uint64_t nfm = group_bits<G>(__ballot(nonfinite), gi);
         if (t == 0) {
-            if (pv == 0.0) atomicMin(&A.info[kInfoBadKey], 2 * row);
+            if (zpm) atomicMin(&A.info[kInfoBadKey], 2 * row);
             else if (nfm) atomicMin(&A.info[kInfoBadKey], 2 * row + 1);
         }
         if (act) {
@@ -1999,6 +2056,25 @@ __global__ __launch_bounds__(kTileBlock) void k_factor_tiled(FactorArgs A, Facto
             if (A.lu16) A.lu16[m.y + t] = to_bf16(f);
         }
         if (t == 0) __hip_atomic_store(&flags[sl], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
+// Persistent blocks: each claims tiles in start order until none is left, so that
+// a finished tile's slot goes to the next tile without a new workgroup dispatch.
+// A tile waits only on tiles claimed before it, which are held by running blocks.
+template <int G>
+__global__ __launch_bounds__(kTileBlock, 5) void k_factor_tiled(FactorArgs A, FactorTileArgs T) {
+    extern __shared__ __align__(16) unsigned char fsmem[];
+    __shared__ int s_tile, s_abort;
+    if (threadIdx.x == 0) s_abort = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = __hip_atomic_fetch_add(T.counter, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int tile = s_tile;
+        if (tile >= T.ntiles || s_abort) return;
+        factor_tile<G>(A, T, tile, fsmem, s_abort);
+        // every wave is done with the tile's LDS image before the next one is staged
+        __syncthreads();
     }
 }
 
@@ -2432,53 +2508,9 @@ static hipError_t stream_launch(const SolveArgs &A, const StreamArgs &T0, bool f
     return hipGetLastError();
 }
 
-// LDS carve-up of a tiled factor launch
-static size_t factor_tile_layout(const FactorTileArgs &T, int G, bool milu, bool tau, FactorTileArgs *out) {
-    size_t o = align8((size_t)T.max_vals * 8);
-    const size_t fl = o;
-    o = align8(o + (size_t)(T.max_rows + T.max_imps) * 4);
-    const size_t me = o;
-    o = align8(o + (size_t)T.max_rows * 16);
-    const size_t of = o;
-    o = align8(o + (size_t)T.max_rows * 8);
-    const size_t dl = o;
-    o = align8(o + (size_t)T.max_lents * 4);
-    const size_t df = o;
-    o = align8(o + (size_t)T.max_lents * 4);
-    const size_t ma = o;
-    o = align8(o + (size_t)T.max_lents * G);
-    const size_t cm = o;
-    if (milu) o = align8(o + (size_t)T.max_lents * 4);
-    const size_t im = o;
-    o = align8(o + (size_t)T.max_imps * 16);
-    const size_t psl = o;
-    o = align8(o + (size_t)T.max_pos * 2);
-    const size_t ta = o;
-    if (tau) o = align8(o + (size_t)T.max_rows * 8);
-    if (out) {
-        out->off_tau = (int32_t)ta;
-        out->off_flags = (int32_t)fl;
-        out->off_meta = (int32_t)me;
-        out->off_off = (int32_t)of;
-        out->off_dloc = (int32_t)dl;
-        out->off_dflag = (int32_t)df;
-        out->off_match = (int32_t)ma;
-        out->off_cmask = (int32_t)cm;
-        out->off_imp = (int32_t)im;
-        out->off_pslot = (int32_t)psl;
-        out->lds_bytes = (int32_t)o;
-    }
-    return o;
-}
-
-size_t factor_tile_lds_bytes(const FactorTileArgs &T, int lanes, bool milu, bool tau) {
-    return factor_tile_layout(T, lanes, milu, tau, nullptr);
-}
-
 template <int G>
-static hipError_t factor_tiled_launch(const FactorArgs &A, const FactorTileArgs &T0, hipStream_t s) {
-    FactorTileArgs T = T0;
-    const size_t lds = factor_tile_layout(T, G, A.milu != 0, A.use_tau != 0, &T);
+static hipError_t factor_tiled_launch(const FactorArgs &A, const FactorTileArgs &T, hipStream_t s) {
+    const size_t lds = (size_t)T.lds_bytes;
     if (lds > (size_t)kFactorTileLdsMax) return hipErrorInvalidValue;
     if (T.ntiles <= 0) return hipSuccess;
     if (lds > 65536) {
@@ -2486,7 +2518,15 @@ static hipError_t factor_tiled_launch(const FactorArgs &A, const FactorTileArgs 
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_factor_tiled<G>), dim3(T.ntiles), dim3(kTileBlock), lds, s, A, T);
+    // as many blocks as fit the device at once (persistent)
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_factor_tiled<G>, kTileBlock, lds);
+    if (e != hipSuccess) return e;
+    const int grid = std::max(1, std::min(T.ntiles, cus * std::max(per_cu, 1)));
+    hipLaunchKernelGGL((k_factor_tiled<G>), dim3(grid), dim3(kTileBlock), lds, s, A, T);
     return hipGetLastError();
 }
 

@@ -175,4 +175,125 @@ void build_tail(const HostAnalysis &H, int dir, int32_t min_rows, int32_t min_le
     T->hdr.push_back(0);
 }
 
+
+// The factor's lower stage.  Row r of the tail is factored in one step: for its
+// L entries e ascending, lane e divides by the pivot of column c_e, the
+// multiplier goes to every lane of the row, and each lane whose column is in
+// U(c_e) subtracts multiplier * u -- the serial up-looking algorithm's operations
+// in its order (Sec. III, Fig. 1), hence its bits.  ER's "rows in parallel" part is
+// the rows before the tail, factored first; the corner is streamed.
+bool build_factor_tail(const HostAnalysis &H, const TailPlan &fwd, FactorTailPlan *T) {
+    *T = FactorTailPlan();
+    if (fwd.nsteps == 0) return false;
+    const int32_t n = H.n, pos0 = fwd.pos0;
+    int32_t umax = 1;
+    for (int32_t r = pos0; r < n; ++r) {
+        const int32_t len = H.lu_rp[r + 1] - H.lu_rp[r], K = H.diag[r] - H.lu_rp[r];
+        if (len > 64 || K > kFTailK) return false;
+        umax = std::max(umax, H.lu_rp[r + 1] - H.diag[r]);
+    }
+    const int32_t W = kFTailW, RW = kFTailW * umax;
+    // steps: rows of one level, groups of G >= len lanes packed largest first
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> steps;   // (row, log2 G)
+    std::vector<int32_t> step_level;
+    const int32_t nl = (int32_t)H.level_ptr.size() - 1, t0 = fwd.level0;
+    std::vector<int32_t> step_of(n - pos0, -1);
+    for (int32_t l = t0; l < nl; ++l) {
+        std::vector<std::pair<int32_t, int32_t>> rows;
+        for (int32_t r = H.level_ptr[l]; r < H.level_ptr[l + 1]; ++r) {
+            const int32_t len = H.lu_rp[r + 1] - H.lu_rp[r];
+            int32_t g = 0;
+            while ((1 << g) < len) ++g;
+            rows.push_back({r, g});
+        }
+        std::stable_sort(rows.begin(), rows.end(), [](const auto &a, const auto &b) { return a.second > b.second; });
+        std::vector<std::pair<int32_t, int32_t>> cur;
+        int32_t lanes = 0;
+        for (const auto &rg : rows) {
+            if (lanes + (1 << rg.second) > 64) {
+                steps.push_back(cur);
+                step_level.push_back(l);
+                cur.clear();
+                lanes = 0;
+            }
+            cur.push_back(rg);
+            lanes += 1 << rg.second;
+            step_of[rg.first - pos0] = (int32_t)steps.size();
+        }
+        if (!cur.empty()) {
+            steps.push_back(cur);
+            step_level.push_back(l);
+        }
+    }
+    T->pos0 = pos0;
+    T->umax = umax;
+    T->nsteps = (int32_t)steps.size();
+    for (int32_t s = 0; s < T->nsteps; ++s) {
+        const auto &S = steps[s];
+        int32_t nlanes = 0, kmax = 0;
+        for (const auto &rg : S) {
+            nlanes += 1 << rg.second;
+            kmax = std::max(kmax, H.diag[rg.first] - H.lu_rp[rg.first]);
+        }
+        T->hdr.push_back((int32_t)T->rec.size());
+        T->hdr.push_back((int32_t)S.size() | nlanes << 8 | kmax << 16);
+        T->hdr.push_back(0);
+        T->hdr.push_back(0);
+        // lanes
+        std::vector<int32_t> row_of(nlanes, -1), t_of(nlanes, 0);
+        for (int32_t k = 0, l0 = 0; k < (int32_t)S.size(); ++k) {
+            for (int32_t t = 0; t < (1 << S[k].second); ++t) {
+                row_of[l0 + t] = k;
+                t_of[l0 + t] = t;
+            }
+            l0 += 1 << S[k].second;
+        }
+        for (int32_t ln = 0; ln < nlanes; ++ln) {
+            const int32_t r = S[row_of[ln]].first, t = t_of[ln];
+            const int32_t len = H.lu_rp[r + 1] - H.lu_rp[r], K = H.diag[r] - H.lu_rp[r];
+            T->rec.push_back(row_of[ln] | t << 8 | K << 16 | len << 24);
+            const int32_t p = t < len ? H.lu_rp[r] + t : -1;
+            T->rec.push_back(p);
+            T->rec.push_back(p >= 0 ? H.lu_src[p] : -1);
+            T->rec.push_back(t >= K && t < len ? (r & (W - 1)) * umax + (t - K) : -1);
+        }
+        // sources of the U values each lane needs, L entry by L entry
+        for (int32_t e = 0; e < kmax; ++e)
+            for (int32_t ln = 0; ln < nlanes; ++ln) {
+                const int32_t r = S[row_of[ln]].first, t = t_of[ln];
+                const int32_t len = H.lu_rp[r + 1] - H.lu_rp[r], K = H.diag[r] - H.lu_rp[r];
+                int32_t src = -1;
+                if (e < K && t < len && t >= e) {
+                    const int32_t c = H.lu_ci[H.lu_rp[r] + e];
+                    int32_t j = -1;   // position of entry t's column in U(c)
+                    if (t == e) {
+                        j = 0;
+                    } else {
+                        const int32_t col = H.lu_ci[H.lu_rp[r] + t];
+                        const auto b = H.lu_ci.begin() + H.diag[c], en = H.lu_ci.begin() + H.lu_rp[c + 1];
+                        const auto it = std::lower_bound(b, en, col);
+                        if (it != en && *it == col) j = (int32_t)(it - b);
+                    }
+                    if (j >= 0) {
+                        src = RW + H.diag[c] + j;   // the factor buffer
+                        if (c >= pos0) {
+                            const int32_t sd = step_of[c - pos0];
+                            // in the ring when no row written since holds its slot:
+                            // rows written after c's step lie between the start of
+                            // its level and the end of the previous step's level
+                            if (sd < s && H.level_ptr[step_level[s - 1] + 1] - H.level_ptr[step_level[sd]] <= W)
+                                src = (c & (W - 1)) * umax + j;
+                        }
+                    }
+                }
+                T->rec.push_back(src);
+            }
+    }
+    T->hdr.push_back((int32_t)T->rec.size());
+    T->hdr.push_back(0);
+    T->hdr.push_back(0);
+    T->hdr.push_back(0);
+    return true;
+}
+
 }  // namespace jv

@@ -13,6 +13,7 @@
 // (cubes of side 8 or 16 for cap 512 or 4096 on 3D 7-point stencils) without any
 // coordinate information.
 #include <algorithm>
+#include <cstring>
 #include <queue>
 #include <tuple>
 #include <vector>
@@ -179,10 +180,77 @@ void build_forward_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, 
     tiles_one(H, 0, cap, short_row, fwd, &sci);
 }
 
+namespace {
+
+size_t a16(size_t b) { return (b + 15) & ~(size_t)15; }
+
+// Tile t's header, blob and value sources (its tables are the last ones appended
+// to F's per-entry arrays).
+void append_tile_blob(const HostAnalysis &H, const TileSet &T, int32_t t, int32_t lanes, FactorTiles *F) {
+    const int32_t r0 = T.rows_ptr[t], nrows = T.rows_ptr[t + 1] - r0;
+    const int32_t l0 = F->lptr[t], nl = F->lptr[t + 1] - l0;
+    const int32_t i0 = T.imp_ptr[t], nimp = T.imp_ptr[t + 1] - i0;
+    const int32_t p0 = T.ptr[t], npos = T.ptr[t + 1] - p0;
+    // sections: meta, off, dloc, dflag, match, imp, position slots
+    size_t o = 0;
+    const size_t o_meta = o;
+    o = a16(o + (size_t)nrows * 16);
+    const size_t o_off = o;
+    o = a16(o + (size_t)nrows * 8);
+    const size_t o_dloc = o;
+    o = a16(o + (size_t)nl * 4);
+    const size_t o_dflag = o;
+    o = a16(o + (size_t)nl * 4);
+    const size_t o_match = o;
+    o = a16(o + (size_t)nl * lanes);
+    const size_t o_imp = o;
+    o = a16(o + (size_t)nimp * 16);
+    const size_t o_ps = o;
+    o = a16(o + (size_t)npos * 2);
+    std::vector<unsigned char> b(o, 0);
+    std::memcpy(b.data() + o_meta, F->meta.data() + 4 * (size_t)r0, (size_t)nrows * 16);
+    std::memcpy(b.data() + o_off, F->off.data() + 2 * (size_t)r0, (size_t)nrows * 8);
+    std::memcpy(b.data() + o_dloc, F->dloc.data() + l0, (size_t)nl * 4);
+    std::memcpy(b.data() + o_dflag, F->dflag.data() + l0, (size_t)nl * 4);
+    std::memcpy(b.data() + o_match, F->match.data() + (size_t)l0 * lanes, (size_t)nl * lanes);
+    const size_t fi0 = F->imp.size() - 4 * (size_t)nimp;   // this tile's imports: the last appended
+    std::memcpy(b.data() + o_imp, F->imp.data() + fi0, (size_t)nimp * 16);
+    int16_t *ps = reinterpret_cast<int16_t *>(b.data() + o_ps);
+    for (int32_t q = 0, k = 0; q < npos; ++q) ps[q] = (int16_t)(T.row[p0 + q] >= 0 ? k++ : -1);
+    // value sources of the rows, in value-area order
+    const int32_t vbase = (int32_t)F->vsrc.size();
+    for (int32_t q = r0; q < r0 + nrows; ++q) {
+        const int32_t r = T.rows[q];
+        for (int32_t p = H.lu_rp[r]; p < H.lu_rp[r + 1]; ++p) F->vsrc.push_back(H.lu_src[p]);
+    }
+    const int32_t nvr = (int32_t)F->vsrc.size() - vbase;
+    int32_t nvals = nvr;
+    for (int32_t i = 0; i < nimp; ++i) nvals = std::max(nvals, F->imp[fi0 + 4 * i + 2] + F->imp[fi0 + 4 * i + 1]);
+    const int32_t boff = (int32_t)(F->blob.size() / 4);
+    F->blob.resize(F->blob.size() + o / 4);
+    std::memcpy(F->blob.data() + 4 * (size_t)boff, b.data(), o);
+    const int32_t h[kFactorHdr] = {boff, (int32_t)(o / 16), nrows, nimp, nl, npos, (int32_t)o_off, (int32_t)o_dloc,
+                                   (int32_t)o_dflag, (int32_t)o_match, (int32_t)o_imp, (int32_t)o_ps, vbase, nvr,
+                                   nvals, l0};
+    F->hdr.insert(F->hdr.end(), h, h + kFactorHdr);
+    // LDS: values, ready flags, the blob, then the thresholds and masks if used
+    const size_t base = a16((size_t)nvals * 8) + a16((size_t)(nrows + nimp) * 4) + o;
+    for (int v = 0; v < 4; ++v) {
+        const size_t need = base + ((v & 1) ? (size_t)nrows * 8 : 0) + ((v & 2) ? (size_t)nl * 4 : 0);
+        F->lds_need[v] = std::max(F->lds_need[v], need);
+    }
+}
+
+}  // namespace
+
 void build_factor_tiles(const HostAnalysis &H, const TileSet &T, int32_t lanes, FactorTiles *F) {
     const std::vector<int32_t> &rp = H.lu_rp, &ci = H.lu_ci, &dg = H.diag;
     F->lanes = lanes;
     F->max_vals = F->max_lents = 0;
+    F->hdr.clear();
+    F->blob.clear();
+    F->vsrc.clear();
+    for (size_t &x : F->lds_need) x = 0;
     F->meta.clear();
     F->off.clear();
     F->lptr.assign(1, 0);
@@ -261,6 +329,7 @@ void build_factor_tiles(const HostAnalysis &H, const TileSet &T, int32_t lanes, 
             if (flat) F->meta[4 * (size_t)q] = ~r;
         }
         F->lptr.push_back((int32_t)F->dloc.size());
+        append_tile_blob(H, T, t, lanes, F);
         for (int32_t q = r0; q < r1; ++q) slot_of[T.rows[q]] = -1;
         for (int32_t i = T.imp_ptr[t]; i < T.imp_ptr[t + 1]; ++i) {
             imp_of[T.imp[i]] = -1;
