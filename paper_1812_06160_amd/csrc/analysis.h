@@ -180,12 +180,18 @@ struct FactorTiles {
 };
 
 // Header words of a factor tile: blob offset and size (16-byte units), rows,
-// imports, L entries, positions; byte offsets in the blob of the off, dloc,
-// dflag, match, imp and position-slot tables (meta at 0); first value-source
+// imports, L entries, positions; byte offsets in the blob of the L-entry, match,
+// import and position-slot tables (the row table at 0); first value-source
 // entry, row value slots, all value slots (imports included), first L entry.
+// Blob tables: per row int4 (row, complemented when its L entries are
+// independent; first factor entry; value-area offset | length << 16 | L
+// entries << 24; first L entry of the tile's L table), per L entry the LDS
+// location of its U row | that row's ready slot << 16, per L entry and lane the
+// lane's column position in that U row (0: none), per import int4 (diagonal
+// entry, U length, value-area offset, 0), per position the row slot (-1: padding).
 enum FactorHdr {
-    kFhBlob, kFhBlobSize, kFhRows, kFhImps, kFhLents, kFhPos, kFhOff, kFhDloc, kFhDflag, kFhMatch, kFhImp, kFhPs,
-    kFhVsrc, kFhRowVals, kFhVals, kFhL0, kFactorHdr
+    kFhBlob, kFhBlobSize, kFhRows, kFhImps, kFhLents, kFhPos, kFhLent, kFhMatch, kFhImp, kFhPs,
+    kFhVsrc, kFhRowVals, kFhVals, kFhL0, kFactorHdr = 16
 };
 
 // Builds the tiled-factor data from the forward tiles; lanes = power of two >= the

@@ -1732,33 +1732,36 @@ __global__ __launch_bounds__(kStreamBlock) void k_solve_stream(SolveArgs A, Stre
 // serial one.  A row then writes its values to LDS, raises its ready flag and
 // publishes its values to the factor buffer for other tiles.
 
-__device__ __forceinline__ int lds_wait_flag(int *f, int *lds_abort, int32_t *info) {
+// A tiled-factor row (or import) is ready when its ready word holds its pivot
+// u_cc instead of the pending pattern; the word is written last, with release
+// semantics, so that the U part it guards is in LDS.  Returns the pivot, or a NaN
+// after an abort or an expired wait.
+__device__ __forceinline__ double lds_wait_pivot(const uint64_t *f, int *lds_abort, int32_t *info) {
     int spins = 0;
     uint64_t t0 = 0;
     for (;;) {
-        if (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) return 1;
+        const uint64_t b = __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (b != kPending64) return __longlong_as_double((long long)b);
         __builtin_amdgcn_s_sleep(1);
         if ((++spins & 63) == 0) {
-            if (__hip_atomic_load(lds_abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return 0;
+            if (__hip_atomic_load(lds_abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+                return __longlong_as_double((long long)kQNaN64);
             if (expired(t0)) {
                 __hip_atomic_store(&info[kInfoAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 __hip_atomic_store(lds_abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                return 0;
+                return __longlong_as_double((long long)kQNaN64);
             }
         }
     }
 }
 
-// (Ready flags guard values at other LDS addresses: they are raised with release
-// and polled with acquire semantics at workgroup scope.)
-//
 // Poller of the tiled factor: lane l holds imports l, l + 64 of the window (in
 // order of first use); each round loads every still-missing U value of a held
-// import, copies the published ones into LDS and raises the import's ready flag
-// once its whole U part is there.  The window moves by 64 when its first 64
+// import, copies the published ones into LDS and sets the import's ready word
+// to its pivot once its whole U part is there.  The window moves by 64 when its first 64
 // imports are complete.  Bounded like every wait.
 template <int G>
-__device__ void factor_poll(const int4 *imp, int nimp, const double *lu, double *vals, int *flags, int nrows,
+__device__ void factor_poll(const int4 *imp, int nimp, const double *lu, double *vals, uint64_t *rdy, int nrows,
                             int32_t *info, int sleep0, int *lds_abort) {
     const int lane = threadIdx.x & 63;
     int head = 0, sleep = 0, spins = 0;
@@ -1794,7 +1797,10 @@ __device__ void factor_poll(const int4 *imp, int nimp, const double *lu, double 
                     }
                 }
             }
-            if (have[b] == all) __hip_atomic_store(&flags[nrows + i], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (have[b] == all) {
+                const uint64_t pv = reinterpret_cast<const uint64_t *>(vals)[m.z];   // u_cc, copied above
+                __hip_atomic_store(&rdy[nrows + i], pv, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
             else if (b == 0) left0 = true;
         }
         if (!__any(left0)) {
@@ -1822,18 +1828,16 @@ template <int G>
 __device__ __forceinline__ void factor_tile(const FactorArgs &A, const FactorTileArgs &T, int tile, unsigned char *fsmem,
                                             int &s_abort) {
     // The tile's header (uniform: scalar loads) and its LDS image: values, ready
-    // flags, the tables (one blob, copied as is), thresholds, modified-ILU masks.
+    // words, the tables (one blob, copied as is), thresholds, modified-ILU masks.
     const int32_t *th = T.hdr + (size_t)kFactorHdr * tile;
     const int boff = th[kFhBlob], bsz = th[kFhBlobSize], nrows = th[kFhRows], nimp = th[kFhImps];
     const int nl = th[kFhLents], npos = th[kFhPos], vbase = th[kFhVsrc], nvr = th[kFhRowVals];
     const int nvals = th[kFhVals], l0 = th[kFhL0];
     double *vals = reinterpret_cast<double *>(fsmem);
-    int *flags = reinterpret_cast<int *>(fsmem + ((nvals * 8 + 15) & ~15));
-    unsigned char *blob = reinterpret_cast<unsigned char *>(flags) + (((nrows + nimp) * 4 + 15) & ~15);
-    int4 *meta = reinterpret_cast<int4 *>(blob);
-    int2 *off = reinterpret_cast<int2 *>(blob + th[kFhOff]);
-    int32_t *dloc = reinterpret_cast<int32_t *>(blob + th[kFhDloc]);
-    int32_t *dflag = reinterpret_cast<int32_t *>(blob + th[kFhDflag]);
+    uint64_t *rdy = reinterpret_cast<uint64_t *>(fsmem + ((nvals * 8 + 15) & ~15));
+    unsigned char *blob = reinterpret_cast<unsigned char *>(rdy) + (((nrows + nimp) * 8 + 15) & ~15);
+    const int4 *rmeta = reinterpret_cast<const int4 *>(blob);
+    const uint32_t *lent = reinterpret_cast<const uint32_t *>(blob + th[kFhLent]);
     int8_t *match = reinterpret_cast<int8_t *>(blob + th[kFhMatch]);
     int4 *imp = reinterpret_cast<int4 *>(blob + th[kFhImp]);
     int16_t *ps = reinterpret_cast<int16_t *>(blob + th[kFhPs]);
@@ -1878,26 +1882,26 @@ __device__ __forceinline__ void factor_tile(const FactorArgs &A, const FactorTil
             if (k < nvr) vals[k] = vs[u] >= 0 ? a[u] : 0.0;   // fill entries start at 0
         }
     }
-    for (int i = threadIdx.x; i < nrows + nimp; i += B) flags[i] = 0;
+    for (int i = threadIdx.x; i < nrows + nimp; i += B) rdy[i] = kPending64;
     if (A.use_tau || A.milu) {
         __syncthreads();
         // the rows' drop thresholds and the modified form's masks, so that the
         // compute waves issue no global load
         if (A.use_tau) {
             for (int i = threadIdx.x; i < nrows; i += B) {
-                const int mx = meta[i].x;
+                const int mx = rmeta[i].x;
                 tau[i] = A.row_tau[mx < 0 ? ~mx : mx];
             }
         }
         if (A.milu) lds_copy<kStageCopy>(cmask, T.cmask + l0, nl);
     }
-    // (imported U parts are read only after their ready flag: the poller raises it
+    // (imported U parts are read only after their ready word: the poller sets it
     // once it has copied the whole part)
     __syncthreads();
     const int wave = threadIdx.x >> 6;
     const int gi = (threadIdx.x & 63) / G;
     if (wave == kTileComputeWaves) {
-        factor_poll<G>(imp, nimp, A.lu, vals, flags, nrows, A.info, A.poll_sleep, &s_abort);
+        factor_poll<G>(imp, nimp, A.lu, vals, rdy, nrows, A.info, A.poll_sleep, &s_abort);
         return;
     }
     // Every staging load has landed.  Saying so keeps the compiler from waiting
@@ -1907,9 +1911,9 @@ __device__ __forceinline__ void factor_tile(const FactorArgs &A, const FactorTil
     for (int c0 = wave * UNIT; c0 < npos; c0 += kTileComputeWaves * UNIT) {
         const int sl = ps[c0 + gi];
         if (sl < 0) continue;
-        const int4 m = meta[sl];
-        const int2 o = off[sl];
-        const int len = m.z - m.y, K = m.w - m.y;
+        const int4 m = rmeta[sl];
+        const int2 o = make_int2(m.z & 0xFFFF, m.w);
+        const int len = (m.z >> 16) & 0xFF, K = (m.z >> 24) & 0xFF;
         const bool flat = m.x < 0;             // L entries independent of one another
         const int row = flat ? ~m.x : m.x;
         const bool act = t < len;
@@ -1930,14 +1934,12 @@ __device__ __forceinline__ void factor_tile(const FactorArgs &A, const FactorTil
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int li = o.y + (q < K ? q : K - 1);
-                const int j = match[li * G + t], dl = dloc[li];
+                const int j = match[li * G + t], dl = (int)(lent[li] & 0xFFFFu);
                 uix[q] = (q < K && j > 0) ? dl + j : -1;
             }
-            const int lo = o.y + (t < K ? t : K - 1);
-            const int myflag = dflag[lo], myloc = dloc[lo];
+            const int myrdy = (int)(lent[o.y + (t < K ? t : K - 1)] >> 16);
             if (t < K) {
-                const int ok = lds_wait_flag(&flags[myflag], &s_abort, A.info);
-                const double piv = ok ? vals[myloc] : __longlong_as_double((long long)kQNaN64);
+                const double piv = lds_wait_pivot(&rdy[myrdy], &s_abort, A.info);
                 v = v / piv;
                 if (A.use_tau && fabs(v) < tr) dropped = 1;
             }
@@ -1963,7 +1965,7 @@ __device__ __forceinline__ void factor_tile(const FactorArgs &A, const FactorTil
                 for (int q = 0; q < 4; ++q) {
                     const int e = e0 + q;
                     const int li = o.y + (e < K ? e : K - 1);
-                    const int j = match[li * G + t], dl = dloc[li];
+                    const int j = match[li * G + t], dl = (int)(lent[li] & 0xFFFFu);
                     uix[q] = (e < K && j > 0) ? dl + j : -1;
                 }
             }
@@ -1972,9 +1974,7 @@ __device__ __forceinline__ void factor_tile(const FactorArgs &A, const FactorTil
             // every multiplier at once: lane t < K waits for its own dependency and
             // divides; the updates below then only reach U entries
             if (t < K) {
-                const int li = o.y + t;
-                const int ok = lds_wait_flag(&flags[dflag[li]], &s_abort, A.info);
-                const double piv = ok ? vals[dloc[li]] : __longlong_as_double((long long)kQNaN64);
+                const double piv = lds_wait_pivot(&rdy[lent[o.y + t] >> 16], &s_abort, A.info);
                 before = v;
                 v = v / piv;
                 if (A.use_tau && fabs(v) < tr) dropped = 1;
@@ -1983,10 +1983,9 @@ __device__ __forceinline__ void factor_tile(const FactorArgs &A, const FactorTil
         }
         for (int e = 0; e < K; ++e) {
             const int li = o.y + e;
-            const int loc = dloc[li];
+            const int loc = (int)(lent[li] & 0xFFFFu);
             if (!flat) {
-                const int ok = lds_wait_flag(&flags[dflag[li]], &s_abort, A.info);
-                const double piv = ok ? vals[loc] : __longlong_as_double((long long)kQNaN64);
+                const double piv = lds_wait_pivot(&rdy[lent[li] >> 16], &s_abort, A.info);
                 if (t == e) {
                     before = v;
                     v = v / piv;
@@ -2045,8 +2044,8 @@ __device__ __forceinline__ void factor_tile(const FactorArgs &A, const FactorTil
             if (zpm) atomicMin(&A.info[kInfoBadKey], 2 * row);
             else if (nfm) atomicMin(&A.info[kInfoBadKey], 2 * row + 1);
         }
+        const uint64_t bits = dropped ? kDropped64 : (v != v) ? kQNaN64 : (uint64_t)__double_as_longlong(v);
         if (act) {
-            const uint64_t bits = dropped ? kDropped64 : (v != v) ? kQNaN64 : (uint64_t)__double_as_longlong(v);
             reinterpret_cast<uint64_t *>(vals)[o.x + t] = bits;
             st_pub_u64(reinterpret_cast<uint64_t *>(&A.lu[m.y + t]), bits);
             // the storage copies of the final value (a dropped entry is 0): the same
@@ -2055,7 +2054,8 @@ __device__ __forceinline__ void factor_tile(const FactorArgs &A, const FactorTil
             if (A.lu32) A.lu32[m.y + t] = f;
             if (A.lu16) A.lu16[m.y + t] = to_bf16(f);
         }
-        if (t == 0) __hip_atomic_store(&flags[sl], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        // the row's ready word: its pivot, after the U part (one LDS store above)
+        if (t == K) __hip_atomic_store(&rdy[sl], bits, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 }
 

@@ -13,6 +13,7 @@
 // (cubes of side 8 or 16 for cap 512 or 4096 on 3D 7-point stencils) without any
 // coordinate information.
 #include <algorithm>
+#include <cstdint>
 #include <cstring>
 #include <queue>
 #include <tuple>
@@ -185,21 +186,17 @@ namespace {
 size_t a16(size_t b) { return (b + 15) & ~(size_t)15; }
 
 // Tile t's header, blob and value sources (its tables are the last ones appended
-// to F's per-entry arrays).
+// to F's per-entry arrays).  A tile whose offsets do not fit the packed fields
+// makes the whole set unusable (lds_need beyond any LDS).
 void append_tile_blob(const HostAnalysis &H, const TileSet &T, int32_t t, int32_t lanes, FactorTiles *F) {
     const int32_t r0 = T.rows_ptr[t], nrows = T.rows_ptr[t + 1] - r0;
     const int32_t l0 = F->lptr[t], nl = F->lptr[t + 1] - l0;
     const int32_t i0 = T.imp_ptr[t], nimp = T.imp_ptr[t + 1] - i0;
     const int32_t p0 = T.ptr[t], npos = T.ptr[t + 1] - p0;
-    // sections: meta, off, dloc, dflag, match, imp, position slots
     size_t o = 0;
-    const size_t o_meta = o;
+    const size_t o_rows = o;
     o = a16(o + (size_t)nrows * 16);
-    const size_t o_off = o;
-    o = a16(o + (size_t)nrows * 8);
-    const size_t o_dloc = o;
-    o = a16(o + (size_t)nl * 4);
-    const size_t o_dflag = o;
+    const size_t o_lent = o;
     o = a16(o + (size_t)nl * 4);
     const size_t o_match = o;
     o = a16(o + (size_t)nl * lanes);
@@ -208,10 +205,23 @@ void append_tile_blob(const HostAnalysis &H, const TileSet &T, int32_t t, int32_
     const size_t o_ps = o;
     o = a16(o + (size_t)npos * 2);
     std::vector<unsigned char> b(o, 0);
-    std::memcpy(b.data() + o_meta, F->meta.data() + 4 * (size_t)r0, (size_t)nrows * 16);
-    std::memcpy(b.data() + o_off, F->off.data() + 2 * (size_t)r0, (size_t)nrows * 8);
-    std::memcpy(b.data() + o_dloc, F->dloc.data() + l0, (size_t)nl * 4);
-    std::memcpy(b.data() + o_dflag, F->dflag.data() + l0, (size_t)nl * 4);
+    bool packs = nrows + nimp <= 65536;
+    int32_t *rw = reinterpret_cast<int32_t *>(b.data() + o_rows);
+    for (int32_t k = 0; k < nrows; ++k) {
+        const int32_t *m = F->meta.data() + 4 * (size_t)(r0 + k), *of = F->off.data() + 2 * (size_t)(r0 + k);
+        const int32_t len = m[2] - m[1], K = m[3] - m[1];
+        packs = packs && of[0] < 65536 && len < 256 && K < 256;
+        rw[4 * k] = m[0];
+        rw[4 * k + 1] = m[1];
+        rw[4 * k + 2] = of[0] | len << 16 | K << 24;
+        rw[4 * k + 3] = of[1];
+    }
+    uint32_t *le = reinterpret_cast<uint32_t *>(b.data() + o_lent);
+    for (int32_t k = 0; k < nl; ++k) {
+        const int32_t dl = F->dloc[l0 + k], df = F->dflag[l0 + k];
+        packs = packs && dl < 65536;
+        le[k] = (uint32_t)dl | (uint32_t)df << 16;
+    }
     std::memcpy(b.data() + o_match, F->match.data() + (size_t)l0 * lanes, (size_t)nl * lanes);
     const size_t fi0 = F->imp.size() - 4 * (size_t)nimp;   // this tile's imports: the last appended
     std::memcpy(b.data() + o_imp, F->imp.data() + fi0, (size_t)nimp * 16);
@@ -226,17 +236,18 @@ void append_tile_blob(const HostAnalysis &H, const TileSet &T, int32_t t, int32_
     const int32_t nvr = (int32_t)F->vsrc.size() - vbase;
     int32_t nvals = nvr;
     for (int32_t i = 0; i < nimp; ++i) nvals = std::max(nvals, F->imp[fi0 + 4 * i + 2] + F->imp[fi0 + 4 * i + 1]);
+    packs = packs && nvals <= 65536;
     const int32_t boff = (int32_t)(F->blob.size() / 4);
     F->blob.resize(F->blob.size() + o / 4);
     std::memcpy(F->blob.data() + 4 * (size_t)boff, b.data(), o);
-    const int32_t h[kFactorHdr] = {boff, (int32_t)(o / 16), nrows, nimp, nl, npos, (int32_t)o_off, (int32_t)o_dloc,
-                                   (int32_t)o_dflag, (int32_t)o_match, (int32_t)o_imp, (int32_t)o_ps, vbase, nvr,
-                                   nvals, l0};
+    int32_t h[kFactorHdr] = {boff, (int32_t)(o / 16), nrows, nimp, nl, npos, (int32_t)o_lent, (int32_t)o_match,
+                             (int32_t)o_imp, (int32_t)o_ps, vbase, nvr, nvals, l0};
     F->hdr.insert(F->hdr.end(), h, h + kFactorHdr);
-    // LDS: values, ready flags, the blob, then the thresholds and masks if used
-    const size_t base = a16((size_t)nvals * 8) + a16((size_t)(nrows + nimp) * 4) + o;
+    // LDS: values, ready words, the blob, then the thresholds and masks if used
+    const size_t base = a16((size_t)nvals * 8) + a16((size_t)(nrows + nimp) * 8) + o;
     for (int v = 0; v < 4; ++v) {
-        const size_t need = base + ((v & 1) ? (size_t)nrows * 8 : 0) + ((v & 2) ? (size_t)nl * 4 : 0);
+        const size_t need = packs ? base + ((v & 1) ? (size_t)nrows * 8 : 0) + ((v & 2) ? (size_t)nl * 4 : 0)
+                                  : SIZE_MAX;
         F->lds_need[v] = std::max(F->lds_need[v], need);
     }
 }
