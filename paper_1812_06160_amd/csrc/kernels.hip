@@ -1919,9 +1919,7 @@ __device__ __forceinline__ void factor_tile(const FactorArgs &A, const FactorTil
         const bool act = t < len;
         const double tr = A.use_tau ? tau[sl] : 0.0;
         double v = act ? vals[o.x + t] : 0.0;
-        // the spmv operand (same pattern as the factor): A's value in the permuted
-        // copy, a store issued here so that no wait on it sits in the staging
-        if (A.bval && act) A.bval[m.y + t] = v;
+        const double vin = v;                  // the input value (the spmv operand, stored below)
         double before = 0.0;                   // an L entry's value before its division
         int dropped = 0;
         if (flat && !A.milu && K > 0) {
@@ -2035,8 +2033,24 @@ __device__ __forceinline__ void factor_tile(const FactorArgs &A, const FactorTil
                 }
             }
         }
-        // a zero pivot (lane K) or a non-finite kept entry, by ballot: no cross-lane
-        // move on the way to the ready flag
+        // The row in LDS, then its ready word (its pivot) for the rows of this tile;
+        // the global copies and the checks of the sync-free factor come after, off
+        // the path from one level to the next.
+        const uint64_t bits = dropped ? kDropped64 : (v != v) ? kQNaN64 : (uint64_t)__double_as_longlong(v);
+        if (act) reinterpret_cast<uint64_t *>(vals)[o.x + t] = bits;
+        if (t == K) __hip_atomic_store(&rdy[sl], bits, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (act) {
+            st_pub_u64(reinterpret_cast<uint64_t *>(&A.lu[m.y + t]), bits);
+            // the storage copies of the final value (a dropped entry is 0): the same
+            // roundings as the cast kernels, written while the row is at hand
+            const float f = dropped ? 0.0f : (float)__longlong_as_double((long long)bits);
+            if (A.lu32) A.lu32[m.y + t] = f;
+            if (A.lu16) A.lu16[m.y + t] = to_bf16(f);
+            // the spmv operand (same pattern as the factor): A's value in the
+            // permuted copy
+            if (A.bval) A.bval[m.y + t] = vin;
+        }
+        // a zero pivot (lane K) or a non-finite kept entry, by ballot
         const uint64_t zpm = group_bits<G>(__ballot(t == K && v == 0.0), gi);
         const bool nonfinite = act && !dropped && !isfinite(v);
         const uint64_t nfm = group_bits<G>(__ballot(nonfinite), gi);
@@ -2044,18 +2058,6 @@ __device__ __forceinline__ void factor_tile(const FactorArgs &A, const FactorTil
             if (zpm) atomicMin(&A.info[kInfoBadKey], 2 * row);
             else if (nfm) atomicMin(&A.info[kInfoBadKey], 2 * row + 1);
         }
-        const uint64_t bits = dropped ? kDropped64 : (v != v) ? kQNaN64 : (uint64_t)__double_as_longlong(v);
-        if (act) {
-            reinterpret_cast<uint64_t *>(vals)[o.x + t] = bits;
-            st_pub_u64(reinterpret_cast<uint64_t *>(&A.lu[m.y + t]), bits);
-            // the storage copies of the final value (a dropped entry is 0): the same
-            // roundings as the cast kernels, written while the row is at hand
-            const float f = dropped ? 0.0f : (float)__longlong_as_double((long long)bits);
-            if (A.lu32) A.lu32[m.y + t] = f;
-            if (A.lu16) A.lu16[m.y + t] = to_bf16(f);
-        }
-        // the row's ready word: its pivot, after the U part (one LDS store above)
-        if (t == K) __hip_atomic_store(&rdy[sl], bits, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 }
 
