@@ -380,7 +380,11 @@ ilu_status ilu_get_schedule(ilu_handle h, int32_t *factor_sched, int32_t *solve_
  * factor row), "factor_tiled" (1 if the tiled factor can run on this handle:
  * rows of at most 32 entries and tiles that fit LDS).  "tail_min_rows" (0 or
  * 1..65536: rebuilds the lower stage of both solve directions as with the
- * analysis option of that name; synchronous).  "force_abort" (set only;
+ * analysis option of that name; synchronous).  "solve_blocks_per_cu" (0..8, default
+ * 2: at most that many tiles of a tiled solve resident per compute unit, 0: as many
+ * as LDS and waves allow; fewer tiles in flight contend less for the compute
+ * unit's issue slots and LDS, which shortens each tile's level-to-level step;
+ * same results).  "force_abort" (set only;
  * failure-path tests): 1 raises the device abort flag now, as an apply that timed
  * out and was not yet reported leaves it; 2 raises it inside the next apply, after
  * that apply's guard, so its kernels leave through their bounded waits (outputs

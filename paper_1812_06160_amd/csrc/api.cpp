@@ -1085,6 +1085,7 @@ ilu_status run_solves(ilu_handle_s *h, int view, const void *val, int prec, int 
             ta.max_imps = T.max_imps;
             ta.kmax = T.kmax;
             ta.unit = T.unit;
+            ta.blocks_per_cu = h->solve_bpc;
             if ((e = h->prepare_tile_claims(fwd ? kPassTileF : kPassTileB, &ta, s)) != hipSuccess)
                 return after_fwd(hip_fail(e, "tile claims"), pass);
             A.poll_sleep = h->poll_sleep;
@@ -1359,6 +1360,11 @@ extern "C" ilu_status ilu_set_tuning(ilu_handle h, const char *key, int64_t valu
         if (value < 16 || value > 65536) return fail(ILU_ERR_ARG, "ilu_set_tuning: tile_rows must be in [16, 65536]");
         return h->make_tiles((int32_t)value, false);
     }
+    if (k == "solve_blocks_per_cu") {
+        if (value < 0 || value > 8) return fail(ILU_ERR_ARG, "ilu_set_tuning: solve_blocks_per_cu must be in [0, 8]");
+        h->solve_bpc = (int32_t)value;
+        return ILU_OK;
+    }
     if (k == "factor_staged") {
         if (value != 0 && value != 1) return fail(ILU_ERR_ARG, "ilu_set_tuning: factor_staged must be 0 or 1");
         h->factor_staged = value != 0;
@@ -1392,6 +1398,7 @@ extern "C" ilu_status ilu_get_tuning(ilu_handle h, const char *key, int64_t *val
     if (k == "nstreams") { *value = h->nstreams; return ILU_OK; }
     if (k == "factor_tcap") { *value = h->factor_tcap; return ILU_OK; }
     if (k == "tile_rows") { *value = h->tile_rows; return ILU_OK; }
+    if (k == "solve_blocks_per_cu") { *value = h->solve_bpc; return ILU_OK; }
     if (k == "factor_tiled") { *value = h->ftiles_ok ? 1 : 0; return ILU_OK; }
     if (k == "factor_staged") { *value = h->factor_staged ? 1 : 0; return ILU_OK; }
     if (k == "tail_min_rows") { *value = h->tail_min_rows; return ILU_OK; }

@@ -126,6 +126,7 @@ struct TileArgs {
     int32_t off_rhs, off_piv, off_eval, off_eslot, off_rowid, off_pslot, off_imp, off_orow, lds_bytes;
     int32_t *counter;         // claim counter of this pass
     int32_t *zero_counter;    // counter of the complementary pass, cleared at launch (may be null)
+    int32_t blocks_per_cu;    // at most this many tiles resident per CU (0: as many as fit)
 };
 
 // Tiled solve blocks: kTileComputeWaves compute waves and 1 poller wave (imports);

@@ -123,6 +123,7 @@ struct ilu_handle_s {
     bool factor_staged = true;         // stage dependency rows in LDS when they fit
     int32_t nstreams = 1;              // task streams (one per XCD)
     int32_t poll_sleep = 1;            // s_sleep(1) steps between polls (tunable)
+    int32_t solve_bpc = 2;             // tiled solves: resident tiles per CU cap (0: none; tunable)
     int8_t *d_xcc_stream = nullptr;    // XCC id -> stream
     int32_t *d_spmv_heavy = nullptr;   // rows of the permuted copy of A longer than spmv_heavy_min
     int32_t n_spmv_heavy = 0, spmv_heavy_min = INT32_MAX;

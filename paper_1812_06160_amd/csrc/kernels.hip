@@ -2418,7 +2418,12 @@ size_t tile_lds_bytes(int max_rows, int max_slots, int max_pos, int max_imps, in
 template <int G, int J, int NR, typename TV, typename TA>
 static hipError_t tiled_launch(const SolveArgs &A, const TileArgs &T0, bool fwd, hipStream_t s) {
     TileArgs T = T0;
-    const size_t lds = tile_layout(T, NR, sizeof(TA), &T);
+    size_t lds = tile_layout(T, NR, sizeof(TA), &T);
+    // a cap on resident tiles per CU is an LDS request that leaves room for no more
+    if (T.blocks_per_cu > 0 && lds <= (size_t)kTileLdsMax) {
+        const size_t floor_bytes = (size_t)kTileLdsMax / (size_t)(T.blocks_per_cu + 1) + 1024;
+        if (lds < floor_bytes) lds = std::min(floor_bytes, (size_t)kTileLdsMax / (size_t)T.blocks_per_cu);
+    }
     // a tile may take the whole LDS of a CU (opt-in above 64 KB): grid tiles stay
     // far below (three blocks per CU), import-heavy tiles trade blocks for fewer
     // crossings

@@ -895,6 +895,27 @@ def test_apply_tiled_retune_and_lds_limit(jv):
     assert e.value.code == 10   # ILU_ERR_UNSUPPORTED
 
 
+def test_apply_tiled_blocks_per_cu_same_bits(jv):
+    # the cap on resident tiles changes only how many run at once: every setting
+    # gives the same bits, in FP64 and with the FP32 factor
+    A = synth.laplace3d(24)
+    ilu = make(jv, A, 0, True, ("syncfree", "tiled"), tile_rows=512)
+    ilu.factor(dev(A.val))
+    assert ilu.get_tuning("solve_blocks_per_cu") == 2
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    f = O.factor(an, A.val)
+    b = np.random.default_rng(29).uniform(-1, 1, A.n)
+    xr = O.apply(an, f.val, b)
+    ref = {p: ilu.apply(dev(b), prec=p).cpu().numpy() for p in ("f64", "f32")}
+    assert relerr(ref["f64"], xr) <= 1e-12
+    for bpc in (0, 1, 3, 8):
+        ilu.set_tuning("solve_blocks_per_cu", bpc)
+        for p in ("f64", "f32"):
+            assert np.array_equal(ilu.apply(dev(b), prec=p).cpu().numpy().view(np.uint64), ref[p].view(np.uint64))
+    with pytest.raises(jv.IluError):
+        ilu.set_tuning("solve_blocks_per_cu", 9)
+
+
 @pytest.mark.parametrize("tile_rows", [16, 100, 512])
 @pytest.mark.parametrize("name,mk,k,sym", [
     ("laplace3d_20", lambda: synth.laplace3d(20), 0, True),
