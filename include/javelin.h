@@ -384,7 +384,12 @@ ilu_status ilu_get_schedule(ilu_handle h, int32_t *factor_sched, int32_t *solve_
  * 2: at most that many tiles of a tiled solve resident per compute unit, 0: as many
  * as LDS and waves allow; fewer tiles in flight contend less for the compute
  * unit's issue slots and LDS, which shortens each tile's level-to-level step;
- * same results).  "force_abort" (set only;
+ * same results).  "spmv_nz" (0 or 1; readable as 1 only when in use): the spmv
+ * of a matrix with rows longer than 64 entries (one right-hand side, no empty
+ * row) in nnz-balanced waves -- 16 consecutive entries per lane, row segments
+ * added across lanes by a segmented scan and across waves by a second kernel, in a
+ * fixed order -- instead of a lane group per row and one wave per long row; on by
+ * default when a row exceeds 4096 entries.  "force_abort" (set only;
  * failure-path tests): 1 raises the device abort flag now, as an apply that timed
  * out and was not yet reported leaves it; 2 raises it inside the next apply, after
  * that apply's guard, so its kernels leave through their bounded waits (outputs
@@ -402,9 +407,12 @@ ilu_status ilu_get_tuning(ilu_handle h, const char *key, int64_t *value);
  * both stages, chosen by the apply.  The factor is re-run with the last call's k,
  * tau and flags, so the handle keeps the same factor (every schedule gives the same
  * bits).  The apply also tries the lower stage (tail_min_rows 64, or the handle's
- * own value) and keeps it if faster.  Requires a factor.  Synchronous.  results
- * (may be NULL) receives up to `cap` rows of {stage (0 factor, 1 apply), sched (10:
- * lower stage), lanes or tile rows (tiled) or tail_min_rows (lower stage),
+ * own value) and keeps it if faster.  When the matrix has rows longer than 64
+ * entries and no empty row, the spmv's nnz-balanced pass is timed against the
+ * row-per-group pass ("spmv_nz") and the faster kept.  Requires a factor.
+ * Synchronous.  results (may be NULL) receives up to `cap` rows of {stage (0
+ * factor, 1 apply, 2 spmv), sched (10: lower stage; 20 spmv by rows, 21 spmv
+ * nnz-balanced), lanes or tile rows (tiled) or tail_min_rows (lower stage),
  * microseconds} as doubles; *n_results the row count. */
 ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, double *results, int32_t cap,
                     int32_t *n_results, hipStream_t stream);

@@ -557,6 +557,39 @@ static ilu_status finish_analysis(ilu_handle_s *h) {
             h->n_spmv_heavy = (int32_t)heavy.size();
             h->spmv_heavy_min = kHeavy;
         }
+        // with long rows, the nnz-balanced pass (every row must hold an entry)
+        bool nonempty = true;
+        for (int32_t r = 0; r < H.n && nonempty; ++r) nonempty = H.b_rp[r + 1] > H.b_rp[r];
+        const int64_t nnzb = H.b_rp[H.n];
+        if (!heavy.empty() && nonempty && nnzb > 0) {
+            const int32_t nw = (int32_t)((nnzb + kNzWave - 1) / kNzWave);
+            std::vector<int32_t> wrow(nw), span;
+            std::vector<uint16_t> bits((size_t)(nw + 1) * 64, 0);
+            for (int32_t r = 0; r < H.n; ++r) {
+                const int32_t p = H.b_rp[r];
+                bits[p / kNzLane] |= (uint16_t)(1u << (p % kNzLane));
+                const int32_t w0 = p / kNzWave, w1 = (H.b_rp[r + 1] - 1) / kNzWave;
+                if (w1 > w0) span.insert(span.end(), {r, w0, w1});
+            }
+            for (int32_t w = 0, r = 0; w < nw; ++w) {
+                while (H.b_rp[r + 1] <= (int64_t)w * kNzWave) ++r;
+                wrow[w] = r;
+            }
+            UPLOAD_ONE(h->d_nz_wrow, wrow);
+            UPLOAD_ONE(h->d_nz_bits, bits);
+            if (!span.empty()) UPLOAD_ONE(h->d_nz_span, span);
+            void *pp = nullptr;
+            if ((e = h->alloc_bytes(&pp, (size_t)2 * nw * sizeof(double))) != hipSuccess)
+                return hip_fail(e, "spmv pieces");
+            h->d_nz_part = (double *)pp;
+            h->nz_waves = nw;
+            h->nz_nspan = (int32_t)(span.size() / 3);
+            // by default only for rows so long that one wave per row would walk
+            // them for more than 64 rounds (the autotuner times both)
+            int32_t longest = 0;
+            for (int32_t r = 0; r < H.n; ++r) longest = std::max(longest, H.b_rp[r + 1] - H.b_rp[r]);
+            h->spmv_nz = longest > 4 * kNzWave;
+        }
     }
 #undef UPLOAD_ONE
     return ILU_OK;
@@ -1263,6 +1296,14 @@ extern "C" ilu_status ilu_spmv(ilu_handle h, double alpha, const double *x, doub
     A.heavy_min = h->spmv_heavy_min;
     A.heavy = h->d_spmv_heavy;
     A.nheavy = h->n_spmv_heavy;
+    if (h->spmv_nz) {
+        A.nz_waves = h->nz_waves;
+        A.nz_wrow = h->d_nz_wrow;
+        A.nz_bits = h->d_nz_bits;
+        A.nz_span = h->d_nz_span;
+        A.nz_nspan = h->nz_nspan;
+        A.nz_part = h->d_nz_part;
+    }
     const int pp_ = h->prof.begin(ILU_STAGE_SPMV, s);
     hipError_t e = launch_spmv(A, h->lanes_spmv, s);
     h->prof.end(pp_, s);
@@ -1360,6 +1401,11 @@ extern "C" ilu_status ilu_set_tuning(ilu_handle h, const char *key, int64_t valu
         if (value < 16 || value > 65536) return fail(ILU_ERR_ARG, "ilu_set_tuning: tile_rows must be in [16, 65536]");
         return h->make_tiles((int32_t)value, false);
     }
+    if (k == "spmv_nz") {
+        if (value != 0 && value != 1) return fail(ILU_ERR_ARG, "ilu_set_tuning: spmv_nz must be 0 or 1");
+        h->spmv_nz = value != 0;
+        return ILU_OK;
+    }
     if (k == "solve_blocks_per_cu") {
         if (value < 0 || value > 8) return fail(ILU_ERR_ARG, "ilu_set_tuning: solve_blocks_per_cu must be in [0, 8]");
         h->solve_bpc = (int32_t)value;
@@ -1399,6 +1445,7 @@ extern "C" ilu_status ilu_get_tuning(ilu_handle h, const char *key, int64_t *val
     if (k == "factor_tcap") { *value = h->factor_tcap; return ILU_OK; }
     if (k == "tile_rows") { *value = h->tile_rows; return ILU_OK; }
     if (k == "solve_blocks_per_cu") { *value = h->solve_bpc; return ILU_OK; }
+    if (k == "spmv_nz") { *value = (h->spmv_nz && h->nz_waves > 0) ? 1 : 0; return ILU_OK; }
     if (k == "factor_tiled") { *value = h->ftiles_ok ? 1 : 0; return ILU_OK; }
     if (k == "factor_staged") { *value = h->factor_staged ? 1 : 0; return ILU_OK; }
     if (k == "tail_min_rows") { *value = h->tail_min_rows; return ILU_OK; }

@@ -201,7 +201,21 @@ struct SpmvArgs {
     int32_t heavy_min;
     const int32_t *heavy;
     int32_t nheavy;
+    // nnz-balanced pass (one right-hand side, rows all nonempty): wave w takes
+    // entries [w * kNzWave, (w + 1) * kNzWave), 16 consecutive entries per lane;
+    // nz_bits marks the entries that start a row (16 bits per lane, one chunk of 64
+    // spare at the end), nz_wrow[w] is the row of the wave's first entry, and the
+    // rows whose entries reach over several waves (nz_span: row, first wave, last
+    // wave) are added up from the waves' pieces in nz_part by a second kernel
+    int32_t nz_waves;
+    const int32_t *nz_wrow;
+    const uint16_t *nz_bits;
+    const int32_t *nz_span;
+    int32_t nz_nspan;
+    double *nz_part;          // [2 * nz_waves]: closing piece, open piece of each wave
 };
+constexpr int kNzLane = 16;
+constexpr int kNzWave = 64 * kNzLane;
 
 // launchers (kernels.hip); all return hipError_t of the launch
 hipError_t launch_fill_u64(uint64_t *p, uint64_t value, int64_t count, hipStream_t s);

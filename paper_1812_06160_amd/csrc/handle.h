@@ -127,6 +127,13 @@ struct ilu_handle_s {
     int8_t *d_xcc_stream = nullptr;    // XCC id -> stream
     int32_t *d_spmv_heavy = nullptr;   // rows of the permuted copy of A longer than spmv_heavy_min
     int32_t n_spmv_heavy = 0, spmv_heavy_min = INT32_MAX;
+    // nnz-balanced spmv (when long rows exist and no row is empty): per wave its
+    // first entry's row, the row-start bits, the rows over several waves, pieces
+    int32_t *d_nz_wrow = nullptr, *d_nz_span = nullptr;
+    uint16_t *d_nz_bits = nullptr;
+    double *d_nz_part = nullptr;
+    int32_t nz_waves = 0, nz_nspan = 0;
+    bool spmv_nz = false;              // use it (when built; tunable)
     std::vector<void *> allocs;
 
     // state

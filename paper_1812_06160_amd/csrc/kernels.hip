@@ -2607,8 +2607,164 @@ __global__ __launch_bounds__(kBlock) void k_spmv_heavy(SpmvArgs A) {
     }
 }
 
+// nnz-balanced spmv (one right-hand side; CSR5-like partition of the entries,
+// Sec. II): each lane sums its 16 consecutive entries row segment by row segment
+// and writes the rows that start and end among them; a segmented scan over the
+// wave's lanes adds up the segments that cross lanes, and the lane (or the end of
+// the wave) that closes a segment writes it when it started in this wave.  The
+// pieces of rows that reach over a wave boundary go to nz_part (the closing piece
+// of the wave's first row, the open piece of its last row) for k_spmv_nz_span.
+// Every sum is taken in a fixed order, so the result does not vary between runs.
+template <bool PERM>
+__global__ __launch_bounds__(kBlock) void k_spmv_nz(SpmvArgs A) {
+    const int w = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (w >= A.nz_waves) return;
+    const int nnz = A.rp[A.n];
+    const int f = w * kNzWave + lane * kNzLane;
+    const uint32_t bits = A.nz_bits[(size_t)w * 64 + lane];
+    const int cnt = __popc(bits);
+    int inc = cnt;
+#pragma unroll
+    for (int d = 1; d < 64; d *= 2) {
+        const int o = __shfl_up(inc, d);
+        if (lane >= d) inc += o;
+    }
+    const int b0 = __shfl(bits, 0) & 1;
+    // the row of the lane's first entry
+    const int rf = A.nz_wrow[w] + (inc - cnt) - b0 + (int)(bits & 1);
+    auto put = [&](int row, double sum) {
+        const int yr = PERM ? A.perm[row] : row;
+        double out = A.alpha * sum;
+        if (A.beta != 0.0) {
+            const double by = A.beta * A.y[yr];
+            out = out + by;
+        }
+        A.y[yr] = out;
+    };
+    // every load of the lane's entries first (at clamped indices, so that they all
+    // issue before any result is needed), then the sums
+    double av[kNzLane], xv[kNzLane];
+    int cv[kNzLane];
+    if (f + kNzLane <= nnz) {
+        // 16-byte loads of the lane's 128 bytes of values and 64 bytes of columns
+        const double2 *vp = reinterpret_cast<const double2 *>(A.val + f);
+        const int4 *cp = reinterpret_cast<const int4 *>(A.ci + f);
+#pragma unroll
+        for (int i = 0; i < kNzLane / 2; ++i) {
+            const double2 v = vp[i];
+            av[2 * i] = v.x;
+            av[2 * i + 1] = v.y;
+        }
+#pragma unroll
+        for (int i = 0; i < kNzLane / 4; ++i) {
+            const int4 c = cp[i];
+            cv[4 * i] = c.x;
+            cv[4 * i + 1] = c.y;
+            cv[4 * i + 2] = c.z;
+            cv[4 * i + 3] = c.w;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < kNzLane; ++i) {
+            const int p = min(f + i, nnz - 1);
+            av[i] = A.val[p];
+            cv[i] = A.ci[p];
+        }
+    }
+    if constexpr (PERM) {
+#pragma unroll
+        for (int i = 0; i < kNzLane; ++i) cv[i] = A.perm[cv[i]];
+    }
+#pragma unroll
+    for (int i = 0; i < kNzLane; ++i) xv[i] = A.x[cv[i]];
+    int r = rf;
+    double cur = 0.0, head = 0.0;
+    bool started = bits & 1;
+#pragma unroll
+    for (int i = 0; i < kNzLane; ++i) {
+        if (f + i < nnz) {
+            if (i > 0 && (bits >> i & 1)) {
+                if (!started) {
+                    head = cur;
+                    started = true;
+                } else {
+                    put(r, cur);   // a row that starts and ends in this lane
+                }
+                cur = 0.0;
+                ++r;
+            }
+            const double prod = av[i] * xv[i];
+            cur = cur + prod;
+        }
+    }
+    // segmented inclusive scan of the open segments: s = sum from the segment's
+    // first lane to this one; seen = a segment starts at or before this lane
+    const bool has = bits != 0;
+    double sc = cur;
+    bool seen = has;
+#pragma unroll
+    for (int d = 1; d < 64; d *= 2) {
+        const double su = __shfl_up(sc, d);
+        const bool fu = __shfl_up((int)seen, d) != 0;
+        if (lane >= d && !seen) {
+            sc = su + sc;
+            seen = fu;
+        }
+    }
+    const double sprev = __shfl_up(sc, 1);
+    const bool fprev = __shfl_up((int)seen, 1) != 0 && lane > 0;
+    // a lane with a row start closes the segment open before it
+    if (has && !(lane == 0 && (bits & 1))) {
+        double total = lane > 0 ? sprev : 0.0;
+        if (!(bits & 1)) total = total + head;
+        const int row = rf - (int)(bits & 1);
+        if (fprev) put(row, total);
+        else A.nz_part[2 * w] = total;   // the end of a row that began in an earlier wave
+    }
+    if (lane == 63) {
+        const int e = (w + 1) * kNzWave;
+        const bool closes = e >= nnz || (A.nz_bits[(size_t)(w + 1) * 64] & 1);
+        if (closes) {
+            if (seen) put(r, sc);
+            else A.nz_part[2 * w] = sc;
+        } else {
+            A.nz_part[2 * w + 1] = sc;   // the row goes on in the next wave
+        }
+    }
+}
+
+// Rows over several waves: the open pieces of the waves before the last, then the
+// last wave's closing piece, in wave order.
+template <bool PERM>
+__global__ __launch_bounds__(kBlock) void k_spmv_nz_span(SpmvArgs A) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.nz_nspan) return;
+    const int row = A.nz_span[3 * i], w0 = A.nz_span[3 * i + 1], w1 = A.nz_span[3 * i + 2];
+    double sum = A.nz_part[2 * w0 + 1];
+    for (int w = w0 + 1; w < w1; ++w) sum = sum + A.nz_part[2 * w + 1];
+    sum = sum + A.nz_part[2 * w1];
+    const int yr = PERM ? A.perm[row] : row;
+    double out = A.alpha * sum;
+    if (A.beta != 0.0) {
+        const double by = A.beta * A.y[yr];
+        out = out + by;
+    }
+    A.y[yr] = out;
+}
+
 hipError_t launch_spmv(const SpmvArgs &A, int lanes, hipStream_t s) {
     hipError_t e;
+    if (A.nz_waves > 0 && A.nrhs == 1) {
+        dim3 g(grid_for((int64_t)A.nz_waves * 64, kBlock));
+        if (A.perm) hipLaunchKernelGGL((k_spmv_nz<true>), g, dim3(kBlock), 0, s, A);
+        else hipLaunchKernelGGL((k_spmv_nz<false>), g, dim3(kBlock), 0, s, A);
+        if ((e = hipGetLastError()) != hipSuccess || A.nz_nspan <= 0) return e;
+        dim3 g2(grid_for((int64_t)A.nz_nspan, kBlock));
+        if (A.perm) hipLaunchKernelGGL((k_spmv_nz_span<true>), g2, dim3(kBlock), 0, s, A);
+        else hipLaunchKernelGGL((k_spmv_nz_span<false>), g2, dim3(kBlock), 0, s, A);
+        return hipGetLastError();
+    }
     switch (lanes) {
         case 4: e = spmv_dispatch<4>(A, s); break;
         case 8: e = spmv_dispatch<8>(A, s); break;

@@ -11,7 +11,8 @@
 // it; the factor then picks its scheme with that tiling in place.  Every
 // schedule computes the same bits (the factor reproduces the serial up-looking
 // order on all of them), so re-running the caller's factor -- same k, tau and
-// flags -- leaves the handle with the factor it had.
+// flags -- leaves the handle with the factor it had.  With long rows, the spmv's
+// nnz-balanced pass is timed against the row-per-group pass as well.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -217,6 +218,28 @@ extern "C" ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, 
         // leave the caller's factor computed on the chosen schedule
         ilu_status st = factor();
         if (st != ILU_OK) return restore(st);
+    }
+    // ---- spmv: the nnz-balanced pass against the row-per-group pass, when built ----
+    if (h->nz_waves > 0 && h->bvals) {
+        auto spmv = [&]() { return ilu_spmv(h, 1.0, b, 0.0, x, 1, 1, ILU_PERMUTED_SPACE, s); };
+        const bool save_nz = h->spmv_nz;
+        double best = 1e300;
+        bool best_nz = save_nz;
+        for (int nz = 0; nz <= 1; ++nz) {
+            h->spmv_nz = nz != 0;
+            double us = 0;
+            ilu_status st = time_it(spmv, &us);
+            if (st != ILU_OK) {
+                h->spmv_nz = save_nz;
+                return restore(st);
+            }
+            rows.insert(rows.end(), {2.0, nz ? 21.0 : 20.0, 0.0, us});
+            if (us < best) {
+                best = us;
+                best_nz = nz != 0;
+            }
+        }
+        h->spmv_nz = best_nz;
     }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "ilu_tune: synchronize");
     const int nr = (int)(rows.size() / 4);

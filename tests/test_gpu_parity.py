@@ -470,6 +470,67 @@ def test_spmv(jv, name, mk, k, tau):
     assert np.array_equal(ilu.spmv(dev(xi)).cpu().numpy(), O.spmv(A.n, A.row_ptr, A.col_idx, Ai, xi))
 
 
+@pytest.mark.parametrize("name,mk", [
+    ("heavy_6000_rows_over_waves", lambda: synth.heavy_rows(6000, heavy_len=(900, 3500), heavy_frac=0.02,
+                                                            rng=np.random.default_rng(31))),
+    ("heavy_3000_short_and_long", lambda: synth.heavy_rows(3000, heavy_len=(65, 200), heavy_frac=0.05,
+                                                           rng=np.random.default_rng(32))),
+], ids=lambda v: v if isinstance(v, str) else "")
+def test_spmv_nnz_balanced(jv, name, mk):
+    # the nnz-balanced pass (rows cut across lanes and waves, the pieces of rows
+    # over several waves added by the second kernel) against the oracle and the
+    # row-per-group pass; integer values exactly; the same bits run after run
+    A = mk()
+    rng = np.random.default_rng(33)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
+    ilu.set_values(dev(A.val))
+    ilu.set_tuning("spmv_nz", 1)
+    assert ilu.get_tuning("spmv_nz") == 1
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    x = rng.uniform(-1, 1, A.n)
+    y0 = rng.uniform(-1, 1, A.n)
+    for permuted in (False, True):
+        if permuted:
+            yr = O.spmv(A.n, an.b_rp, an.b_ci, O.b_values(an, A.val), x)
+        else:
+            yr = O.spmv(A.n, A.row_ptr, A.col_idx, A.val, x)
+        got = ilu.spmv(dev(x), permuted=permuted).cpu().numpy()
+        assert relerr(got, yr) <= 1e-12
+        again = ilu.spmv(dev(x), permuted=permuted).cpu().numpy()
+        assert np.array_equal(got.view(np.uint64), again.view(np.uint64))
+        got2 = ilu.spmv(dev(x), y=dev(y0), alpha=-1.5, beta=0.25, permuted=permuted).cpu().numpy()
+        assert relerr(got2, -1.5 * yr + 0.25 * y0) <= 1e-12
+        ilu.set_tuning("spmv_nz", 0)
+        assert ilu.get_tuning("spmv_nz") == 0
+        assert relerr(ilu.spmv(dev(x), permuted=permuted).cpu().numpy(), yr) <= 1e-12
+        ilu.set_tuning("spmv_nz", 1)
+    Ai = rng.integers(-4, 5, A.nnz).astype(np.float64)
+    xi = rng.integers(-4, 5, A.n).astype(np.float64)
+    ilu.set_values(dev(Ai))
+    assert np.array_equal(ilu.spmv(dev(xi)).cpu().numpy(), O.spmv(A.n, A.row_ptr, A.col_idx, Ai, xi))
+
+
+def test_spmv_nnz_balanced_default_and_tuned(jv):
+    # rows beyond 4096 entries take the nnz-balanced pass by default
+    A = synth.heavy_rows(20000, heavy_len=(5000, 9000), heavy_frac=0.001, rng=np.random.default_rng(34))
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
+    ilu.set_values(dev(A.val))
+    assert np.diff(A.row_ptr).max() > 4096 and ilu.get_tuning("spmv_nz") == 1
+    x = np.random.default_rng(35).uniform(-1, 1, A.n)
+    assert relerr(ilu.spmv(dev(x)).cpu().numpy(), O.spmv(A.n, A.row_ptr, A.col_idx, A.val, x)) <= 1e-12
+    # shorter long rows: the row pass by default; the autotuner times both
+    B = synth.heavy_rows(6000, heavy_len=(300, 1200), heavy_frac=0.02, rng=np.random.default_rng(36))
+    ilu = jv.Ilu(B.n, B.row_ptr, B.col_idx)
+    assert ilu.get_tuning("spmv_nz") == 0
+    ilu.factor(dev(B.val))
+    res, _ = ilu.tune(dev(B.val), reps=2)
+    spmv_rows = res[res[:, 0] == 2]
+    assert sorted(spmv_rows[:, 1].tolist()) == [20.0, 21.0]
+    assert ilu.get_tuning("spmv_nz") == int(spmv_rows[np.argmin(spmv_rows[:, 3]), 1] == 21.0)
+    xb = np.random.default_rng(37).uniform(-1, 1, B.n)
+    assert relerr(ilu.spmv(dev(xb)).cpu().numpy(), O.spmv(B.n, B.row_ptr, B.col_idx, B.val, xb)) <= 1e-12
+
+
 @pytest.mark.parametrize("sched", SOLVE_SCHEDS, ids=lambda s: s[1])
 def test_apply_integer_exact(jv, sched):
     rng = np.random.default_rng(12)
