@@ -154,6 +154,12 @@ def run(args):
         # direction streamed by one workgroup per right-hand side
         ilu.set_tuning("tail_min_rows", 64)
         ti = ilu.info()
+        ft = ilu.factor_tail()
+        # the factor's lower stage as well (plain ILU(0): the rows before the tail
+        # sync-free, the tail streamed by one workgroup)
+        ilu.set_tuning("factor_lower_stage", 1)
+        sft = _stage_times(ilu, lambda: ilu.factor(a, casts=("f32",)), 3)
+        ilu.set_tuning("factor_lower_stage", 0)
         q64 = _stage_times(ilu, lambda: ilu.apply(b64), 5)
         q32 = _stage_times(ilu, lambda: ilu.apply(b32, prec="f32"), 5)
         q1 = _stage_times(ilu, lambda: ilu.apply(b1), 5)
@@ -161,6 +167,9 @@ def run(args):
         u32 = q32["forward"][0] + q32["backward"][0]
         u1 = q1["forward"][0] + q1["backward"][0]
         out["tail"] = dict(min_rows=64, rows=ti["tail_rows"], urows=ti["tail_urows"],
+                           factor_stream=ft["level0"] >= 0, factor_steps=ft["nsteps"], factor_q=ft["q"],
+                           factor_us=round(1e3 * sft["factor"][0], 1),
+                           factor_call_us=round(1e3 * sft["factor_call"][0], 1),
                            apply16_f32_us=round(1e3 * u32, 1), apply16_f32_gbs=round(B16["apply"] / u32 / 1e6, 1),
                            apply16_f64_us=round(1e3 * u64, 1), apply16_f64_gbs=round(B64["apply"] / u64 / 1e6, 1),
                            apply1_f64_us=round(1e3 * u1, 1),

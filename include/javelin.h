@@ -209,6 +209,23 @@ ilu_status ilu_copy_tiles(ilu_handle h, int32_t dir, int32_t *tile_ptr, int32_t 
  * for the published buffer, -1: none).  For inspection and tests. */
 ilu_status ilu_copy_tail(ilu_handle h, int32_t dir, int32_t *sizes, int32_t *hdr, int32_t *rec);
 
+/* Copies the factor's lower stage (Sec. III-B, Even-Rows: the forward tail's rows
+ * factored in level-ordered steps by one workgroup; used by ilu_factor for plain
+ * ILU(k) at k = k_max when a tail is set) to host arrays; any pointer may be NULL.
+ * sizes[10] = {first tail level (-1: no plan), first tail position, steps, umax
+ * (longest U part of a tail row), ring rows, staging depth q, row records, L-entry
+ * sources, match bytes, lane-map bytes}.  hdr (4 * (steps + 1)): per step its first
+ * row record, rows, most L entries of a row, lane-map offset.  rows: 8 words per
+ * record {row, first factor entry, len | K << 8 | log2 group << 16 | first lane <<
+ * 24, ring base, first L-entry source, first match byte, 0, 0}.  lsrc: per L entry
+ * the ring base of U(c) (>= 0) or -(diag(c) + 1) (read from the factor buffer).
+ * match: per L entry e and entry t of the row (len bytes per e) the position of
+ * entry t's column in U(c_e) (0 for t == e, 255 none).  lmap: 64 bytes per step,
+ * each lane's row in the step (255: idle).  No plan when a tail row is longer than
+ * 64 entries or has more than 16 L entries.  For inspection and tests. */
+ilu_status ilu_copy_factor_tail(ilu_handle h, int32_t *sizes, int32_t *hdr, int32_t *rows, int32_t *lsrc,
+                                uint8_t *match, uint8_t *lmap);
+
 /* ---------------------------------------------------------------------------- */
 /* Numeric factor (Sec. III, Fig. 1).                                            */
 /* ---------------------------------------------------------------------------- */
@@ -384,7 +401,11 @@ ilu_status ilu_get_schedule(ilu_handle h, int32_t *factor_sched, int32_t *solve_
  * 2: at most that many tiles of a tiled solve resident per compute unit, 0: as many
  * as LDS and waves allow; fewer tiles in flight contend less for the compute
  * unit's issue slots and LDS, which shortens each tile's level-to-level step;
- * same results).  "spmv_nz" (0 or 1; readable as 1 only when in use): the spmv
+ * same results).  "factor_lower_stage" (0, the default, or 1): with a tail set,
+ * ilu_factor of plain ILU(k) at k = k_max runs the rows before the tail sync-free
+ * and streams the tail's rows through one workgroup (ilu_copy_factor_tail); same
+ * bits; readable, with "factor_lower_planned" (read only: 1 when the current tail
+ * has such a plan).  "spmv_nz" (0 or 1; readable as 1 only when in use): the spmv
  * of a matrix with rows longer than 64 entries (one right-hand side, no empty
  * row) in nnz-balanced waves -- 16 consecutive entries per lane, row segments
  * added across lanes by a segmented scan and across waves by a second kernel, in a
@@ -407,7 +428,9 @@ ilu_status ilu_get_tuning(ilu_handle h, const char *key, int64_t *value);
  * both stages, chosen by the apply.  The factor is re-run with the last call's k,
  * tau and flags, so the handle keeps the same factor (every schedule gives the same
  * bits).  The apply also tries the lower stage (tail_min_rows 64, or the handle's
- * own value) and keeps it if faster.  When the matrix has rows longer than 64
+ * own value) and keeps it if faster; with that tail in place and a plan for it, the
+ * factor's lower stage ("factor_lower_stage") is timed against the chosen factor
+ * schedule.  When the matrix has rows longer than 64
  * entries and no empty row, the spmv's nnz-balanced pass is timed against the
  * row-per-group pass ("spmv_nz") and the faster kept.  Requires a factor.
  * Synchronous.  results (may be NULL) receives up to `cap` rows of {stage (0

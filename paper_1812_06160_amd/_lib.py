@@ -29,6 +29,7 @@ STAGES = ["factor", "forward", "backward", "spmv", "factor_call", "apply_call"]
 SYMBOLS = [
     "ilu_analyze", "ilu_analyze_batched", "ilu_batch_offsets", "ilu_get_info", "ilu_copy_schedule", "ilu_copy_tiles",
     "ilu_copy_tail",
+    "ilu_copy_factor_tail",
     "ilu_factor", "ilu_factor_values", "ilu_copy_factor", "ilu_copy_factor_prec", "ilu_apply", "ilu_get_status",
     "ilu_apply_noalloc", "ilu_apply_ex",
     "ilu_apply_adjoint", "ilu_apply_graph_create", "ilu_graph_launch", "ilu_graph_destroy", "ilu_spmv", "ilu_set_values", "ilu_solve_pcg", "ilu_solve_gmres",
@@ -89,6 +90,7 @@ def load(path: str = LIB_PATH):
         "ilu_copy_schedule": [H] + [vp] * 11,
         "ilu_copy_tiles": [H, i32, vp, vp, vp],
         "ilu_copy_tail": [H, i32, vp, vp, vp],
+        "ilu_copy_factor_tail": [H, vp, vp, vp, vp, vp, vp],
         "ilu_factor": [H, vp, i32, f64, i32, C.POINTER(FactorInfo), vp],
         "ilu_factor_values": [H, i32, C.POINTER(vp)],
         "ilu_copy_factor": [H, vp, vp],

@@ -119,30 +119,36 @@ struct TailPlan {
 // has fewer than min_levels levels.
 void build_tail(const HostAnalysis &H, int dir, int32_t min_rows, int32_t min_levels, TailPlan *T);
 
-// Lower stage of the numeric factor: the same rows as the forward solve's tail,
-// cut into steps of rows of one level; each row has an aligned group of G >= its
-// length lanes, lane t holding entry t.  For every L entry e of a row (ascending)
-// and every lane t of it, the source of the U(c_e) value lane t needs: its pivot
-// u_cc when t == e, u_cj when the column of entry t is j of U(c_e), none
-// otherwise.  Sources are the ring of recent U parts in LDS (kFTailW rows of umax
-// entries) or the factor buffer.
+// Lower stage of the numeric factor (plain ILU(k) at k = k_max): the rows of the
+// forward solve's tail, cut into steps of rows of one level; a row gets an aligned
+// group of 2^g >= its length lanes, lane t holding entry t.  Per row: its record
+// {row, first factor entry, len | K << 8 | g << 16 | first lane << 24, ring base}
+// and {first L-entry source, first match byte, 0, 0}; per L entry e the source of
+// U(c_e): its ring base (>= 0: c_e's U part is in the LDS ring of recent rows)
+// or -(diag(c_e) + 1) (read from the factor buffer); per L entry e and entry t of
+// the row (e-major, len bytes per e) the position of entry t's column in U(c_e)
+// (0 for t == e, the pivot; 255 none).  Per step: {first row record, rows, most L
+// entries of a row, lane map offset}; the lane map gives each of the 64 lanes its
+// row in the step (255: idle).  The ring holds kFTailRing values: ring_rows
+// slots of umax entries, a row's slot at (row mod ring_rows).  A U part read
+// from the ring was written at most ring_rows rows (in level order) before the
+// step's last row; the stagers work q steps ahead, and every source fewer than q
+// steps old is in the ring.
 constexpr int kFTailK = 16;      // most L entries of a tail row
-constexpr int kFTailQ = 8;       // steps staged ahead
-constexpr int kFTailW = 512;     // ring of recent U parts (rows)
+constexpr int kFTailQ = 6;       // most steps staged ahead
+constexpr int kFTailRing = 8192; // ring entries (FP64)
 struct FactorTailPlan {
-    int32_t pos0 = 0, nsteps = 0;
-    int32_t umax = 0;            // longest U part (diagonal included) of a tail row
-    // 4 per step (+ a sentinel): record offset, nrows | nlanes << 8 | kmax << 16, 0, 0
-    std::vector<int32_t> hdr;
-    // per step: per lane 4 words (row in the step | t << 8 | K << 16 | len << 24;
-    // factor entry of entry t (-1 past the row); input entry of it (-1: fill);
-    // ring index of entry t if it is in the U part, else -1), then per L entry e
-    // < kmax (e-major) and lane the source: -1 none, < kFTailW * umax a ring index,
-    // else kFTailW * umax + factor entry
-    std::vector<int32_t> rec;
+    int32_t level0 = -1, pos0 = 0, nsteps = 0;
+    int32_t umax = 0, ring_rows = 0, q = 0;
+    std::vector<int32_t> hdr;     // 4 per step
+    std::vector<int32_t> rows;    // 8 per row record
+    std::vector<int32_t> lsrc;    // per L entry
+    std::vector<uint8_t> match;   // per L entry and row entry
+    std::vector<uint8_t> lmap;    // 64 per step
 };
-// false (and no plan) when a tail row is longer than 64 entries, has more than
-// kFTailK L entries, or the forward solve has no tail
+// false (no plan) when the forward solve has no tail, a tail row is longer than 64
+// entries or has more than kFTailK L entries, or no staging depth of at least 2
+// steps keeps every recent source in the ring
 bool build_factor_tail(const HostAnalysis &H, const TailPlan &fwd, FactorTailPlan *T);
 
 // Data of the tiled factor on the forward tiles.  LDS of a tile: the value area

@@ -421,7 +421,7 @@ ilu_status ilu_handle_s::make_tail(int32_t min_rows) {
         return fail(ILU_ERR_NOMEM, "tail: out of host memory");
     }
     tail_min_rows = min_rows;
-    if (host_only) return ILU_OK;
+    if (host_only) return make_factor_tail();
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "tail: synchronize");
     for (int d = 0; d < 2; ++d) {
@@ -437,6 +437,43 @@ ilu_status ilu_handle_s::make_tail(int32_t min_rows) {
             return hip_fail(e, "tail: upload");
         if (dtail[d].hdr) allocs.push_back(dtail[d].hdr);
         if (dtail[d].rec) allocs.push_back(dtail[d].rec);
+    }
+    return make_factor_tail();
+}
+
+// The factor's lower stage follows the forward solve's tail.
+ilu_status ilu_handle_s::make_factor_tail() {
+    ftail_ok = false;
+    try {
+        ftail_ok = build_factor_tail(H, tail[0], &ftail);
+    } catch (const std::bad_alloc &) {
+        return fail(ILU_ERR_NOMEM, "factor tail: out of host memory");
+    }
+    if (host_only) return ILU_OK;
+    auto drop = [&](auto *&d) {
+        if (d) {
+            (void)hipFree(d);
+            allocs_erase(this, d);
+            d = nullptr;
+        }
+    };
+    drop(dftail.hdr);
+    drop(dftail.rows);
+    drop(dftail.lsrc);
+    drop(dftail.match);
+    drop(dftail.lmap);
+    if (!ftail_ok) return ILU_OK;
+    hipError_t e;
+    auto put = [&](auto *&d, const auto &v) -> hipError_t {
+        hipError_t r = upload(&d, v);
+        if (r == hipSuccess && d) allocs.push_back(d);
+        return r;
+    };
+    if ((e = put(dftail.hdr, ftail.hdr)) != hipSuccess || (e = put(dftail.rows, ftail.rows)) != hipSuccess ||
+        (e = put(dftail.lsrc, ftail.lsrc)) != hipSuccess || (e = put(dftail.match, ftail.match)) != hipSuccess ||
+        (e = put(dftail.lmap, ftail.lmap)) != hipSuccess) {
+        ftail_ok = false;
+        return hip_fail(e, "factor tail: upload");
     }
     return ILU_OK;
 }
@@ -754,6 +791,27 @@ extern "C" ilu_status ilu_copy_tail(ilu_handle h, int32_t dir, int32_t *sizes, i
     return ILU_OK;
 }
 
+extern "C" ilu_status ilu_copy_factor_tail(ilu_handle h, int32_t *sizes, int32_t *hdr, int32_t *rows, int32_t *lsrc,
+                                           uint8_t *match, uint8_t *lmap) {
+    if (!h) return fail(ILU_ERR_ARG, "ilu_copy_factor_tail: NULL handle");
+    const FactorTailPlan &T = h->ftail;
+    const bool ok = h->ftail_ok;
+    if (sizes) {
+        const int32_t v[10] = {ok ? T.level0 : -1, ok ? T.pos0 : 0, ok ? T.nsteps : 0, ok ? T.umax : 0,
+                               ok ? T.ring_rows : 0, ok ? T.q : 0, ok ? (int32_t)(T.rows.size() / 8) : 0,
+                               ok ? (int32_t)T.lsrc.size() : 0, ok ? (int32_t)T.match.size() : 0,
+                               ok ? (int32_t)T.lmap.size() : 0};
+        std::copy(v, v + 10, sizes);
+    }
+    if (!ok) return ILU_OK;
+    if (hdr) std::copy(T.hdr.begin(), T.hdr.end(), hdr);
+    if (rows) std::copy(T.rows.begin(), T.rows.end(), rows);
+    if (lsrc) std::copy(T.lsrc.begin(), T.lsrc.end(), lsrc);
+    if (match) std::copy(T.match.begin(), T.match.end(), match);
+    if (lmap) std::copy(T.lmap.begin(), T.lmap.end(), lmap);
+    return ILU_OK;
+}
+
 // -------------------------------------------------------------------------------------
 // Factor
 // -------------------------------------------------------------------------------------
@@ -782,9 +840,13 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
         info->n_dropped = 0;
     }
     const bool use_tau = tau > 0.0;
+    // the lower stage (a tail set, plain ILU(k) at k = k_max, rows of at most 64
+    // entries): the rows before the tail sync-free, the tail streamed
+    const bool stream = h->factor_lower && h->ftail_ok && h->tail_min_rows > 0 && k == H.k_max && !use_tau &&
+                        !milu && !long_rows;
     // the tiled factor covers ILU(k, tau), plain or modified, at k = k_max (no
     // absent entries); anything else runs the sync-free factor
-    const bool tiled = h->sched_factor == ILU_SCHED_TILED && h->ftiles_ok && k == H.k_max;
+    const bool tiled = !stream && h->sched_factor == ILU_SCHED_TILED && h->ftiles_ok && k == H.k_max;
     // storage copies are allocated before the first launch of the call
     void *p;
     if ((casts & ILU_CAST_F32) && !h->d_lu32) {
@@ -825,7 +887,33 @@ extern "C" ilu_status ilu_factor(ilu_handle h, const double *a_val, int32_t k, d
     A.tcap = (h->factor_staged && factor_lds_bytes(lanes, h->factor_tcap)) ? h->factor_tcap : 0;
     A.max_lower = H.max_lower_lu;
     A.lcap = long_rows ? H.max_row_lu : 0;
-    if (tiled) {
+    if (stream) {
+        if ((e = launch_fill_u64((uint64_t *)h->d_lu, kPending64, H.lu_rp[H.n], s)) != hipSuccess)
+            return hip_fail(e, "ilu_factor: arm");
+        const int pp_ = h->prof.begin(ILU_STAGE_FACTOR, s);
+        if (h->ftail.level0 > 0) {
+            const TaskList *tl = h->task_list(kTasksForward, lanes, h->ftail.level0);
+            if (!tl) return fail(ILU_ERR_NOMEM, "ilu_factor: task list");
+            if ((e = h->prepare_claims(kPassFactor, tl, &A.claims, s)) != hipSuccess)
+                return hip_fail(e, "ilu_factor: claims");
+            A.nstreams = h->nstreams;
+            A.poll_sleep = h->poll_sleep;
+            if ((e = launch_factor(A, lanes, true, h->grid_syncfree(tl), s)) != hipSuccess)
+                return hip_fail(e, "ilu_factor: upper stage");
+        }
+        FactorStreamArgs F{};
+        F.hdr = reinterpret_cast<const int4 *>(h->dftail.hdr);
+        F.rows = reinterpret_cast<const int4 *>(h->dftail.rows);
+        F.lsrc = h->dftail.lsrc;
+        F.match = h->dftail.match;
+        F.lmap = h->dftail.lmap;
+        F.nsteps = h->ftail.nsteps;
+        F.q = h->ftail.q;
+        A.poll_sleep = h->poll_sleep;
+        e = launch_factor_stream(A, F, s);
+        h->prof.end(pp_, s);
+        if (e != hipSuccess) return hip_fail(e, "ilu_factor: lower stage");
+    } else if (tiled) {
         const TileSet &T0 = h->ftset_own ? h->ftset : h->tiles[0];
         FactorTileArgs T{};
         T.hdr = h->dft.hdr;
@@ -1401,6 +1489,11 @@ extern "C" ilu_status ilu_set_tuning(ilu_handle h, const char *key, int64_t valu
         if (value < 16 || value > 65536) return fail(ILU_ERR_ARG, "ilu_set_tuning: tile_rows must be in [16, 65536]");
         return h->make_tiles((int32_t)value, false);
     }
+    if (k == "factor_lower_stage") {
+        if (value != 0 && value != 1) return fail(ILU_ERR_ARG, "ilu_set_tuning: factor_lower_stage must be 0 or 1");
+        h->factor_lower = value != 0;
+        return ILU_OK;
+    }
     if (k == "spmv_nz") {
         if (value != 0 && value != 1) return fail(ILU_ERR_ARG, "ilu_set_tuning: spmv_nz must be 0 or 1");
         h->spmv_nz = value != 0;
@@ -1446,6 +1539,8 @@ extern "C" ilu_status ilu_get_tuning(ilu_handle h, const char *key, int64_t *val
     if (k == "tile_rows") { *value = h->tile_rows; return ILU_OK; }
     if (k == "solve_blocks_per_cu") { *value = h->solve_bpc; return ILU_OK; }
     if (k == "spmv_nz") { *value = (h->spmv_nz && h->nz_waves > 0) ? 1 : 0; return ILU_OK; }
+    if (k == "factor_lower_stage") { *value = h->factor_lower ? 1 : 0; return ILU_OK; }
+    if (k == "factor_lower_planned") { *value = h->ftail_ok ? 1 : 0; return ILU_OK; }
     if (k == "factor_tiled") { *value = h->ftiles_ok ? 1 : 0; return ILU_OK; }
     if (k == "factor_staged") { *value = h->factor_staged ? 1 : 0; return ILU_OK; }
     if (k == "tail_min_rows") { *value = h->tail_min_rows; return ILU_OK; }

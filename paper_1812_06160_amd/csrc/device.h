@@ -162,6 +162,18 @@ struct StreamArgs {
     int32_t off_vals, off_a, off_c, off_lane, off_rhs, off_piv, off_hdr, off_sync, lds_bytes;
 };
 constexpr int kStreamStagers = 15;
+// The factor's lower stage (one block): the plan of build_factor_tail.
+struct FactorStreamArgs {
+    const int4 *hdr;          // [nsteps + 1] per step: first row record, rows, most L entries, lane map offset
+    const int4 *rows;         // 2 per row record
+    const int32_t *lsrc;      // per L entry: ring base of U(c) (>= 0) or -(diag(c) + 1)
+    const uint8_t *match;     // per L entry and row entry: position in U(c), 255 none
+    const uint8_t *lmap;      // 64 per step: lane -> row of the step (255 idle)
+    int32_t nsteps, q;        // steps; steps staged ahead (<= kFTailQ)
+};
+// factor's lower stage: rows of the tail in steps; every row before the tail must
+// be final in A.lu, the tail rows' entries armed with the pending pattern
+hipError_t launch_factor_stream(const FactorArgs &A, const FactorStreamArgs &T, hipStream_t s);
 // The stream launch: A.nrhs blocks (block b solves right-hand side b of the
 // direction's tail); the direction's rows before the tail must be finished.
 hipError_t launch_solve_stream(const SolveArgs &A, const StreamArgs &T, bool forward, int prec, int vec,

@@ -116,6 +116,14 @@ struct ilu_handle_s {
     struct DevTail {
         int32_t *hdr = nullptr, *rec = nullptr;
     } dtail[2];
+    // the factor's lower stage (rows of the forward tail; plain ILU(k) at k_max)
+    jv::FactorTailPlan ftail;
+    bool ftail_ok = false;
+    bool factor_lower = false;         // factor through the lower stage when planned (tunable)
+    struct DevFTail {
+        int32_t *hdr = nullptr, *rows = nullptr, *lsrc = nullptr;
+        uint8_t *match = nullptr, *lmap = nullptr;
+    } dftail;
     jv::Profiler prof;
     int32_t *d_counters = nullptr;     // kPasses sets of claim counters
     bool counters_dirty[jv::kPasses] = {false, false, false, false, false, false, false, false};
@@ -176,6 +184,8 @@ struct ilu_handle_s {
     ilu_status make_factor_tiles();
     // (re)builds the lower stage of both solve directions (min_rows 0: none)
     ilu_status make_tail(int32_t min_rows);
+    // (re)builds the factor's lower stage from the forward tail (called by make_tail)
+    ilu_status make_factor_tail();
     // claim counter of a tiled pass (launching a counter reset when needed)
     hipError_t prepare_tile_claims(int pass, jv::TileArgs *t, hipStream_t s);
 };

@@ -1717,6 +1717,205 @@ __global__ __launch_bounds__(kStreamBlock) void k_solve_stream(SolveArgs A, Stre
 }
 
 // ---------------------------------------------------------------------------------
+// Lower stage of the numeric factor (Sec. III-B, Even-Rows, Fig. 7): one workgroup
+// factors the tail rows in level order, a step (rows of one level) at a time
+// ---------------------------------------------------------------------------------
+// Wave 0 computes.  Lane t of a row's group holds entry t; for the row's L
+// entries e ascending, lane e divides by u_(c_e c_e), the multiplier goes to the
+// group, and each later entry whose column lies in U(c_e) subtracts l * u --
+// the serial up-looking order, hence the serial bits.  The U values a step needs
+// come from the ring of recent rows' U parts in LDS (written by wave 0 itself in
+// an earlier step) or, for older rows and rows before the tail, from the factor
+// buffer, fetched by a stager into the step's buffer.  Waves 1..15 take steps
+// round-robin and stage step s into buffer s % q once step s - q is done.
+constexpr int kFStreamStagers = 15;
+constexpr int kFStreamBlock = 64 * (1 + kFStreamStagers);
+constexpr int kFStreamNone = 0xFFFF;
+
+struct FStreamLds {
+    double *vals;        // ring [kFTailRing], then staged values [q][kFTailK][64]
+    uint16_t *sidx;      // [q][kFTailK][64] LDS index of each (L entry, lane) U value
+    int4 *smeta;         // [q][64]: g | t << 8 | K << 16 | len << 24, factor entry, ring slot, row
+    double *sa;          // [q][64] input value
+    int32_t *skmax;      // [q]
+    int32_t *ready;      // [q]
+    int32_t *done;
+    int32_t *labort;
+};
+
+__device__ __forceinline__ FStreamLds fstream_lds(unsigned char *m, int q) {
+    FStreamLds L;
+    size_t o = 0;
+    L.vals = reinterpret_cast<double *>(m + o);
+    o += (size_t)(kFTailRing + q * kFTailK * 64) * 8;
+    L.sa = reinterpret_cast<double *>(m + o);
+    o += (size_t)q * 64 * 8;
+    L.smeta = reinterpret_cast<int4 *>(m + o);
+    o += (size_t)q * 64 * 16;
+    L.sidx = reinterpret_cast<uint16_t *>(m + o);
+    o += (size_t)q * kFTailK * 64 * 2;
+    L.skmax = reinterpret_cast<int32_t *>(m + o);
+    L.ready = L.skmax + q;
+    L.done = L.ready + q;
+    L.labort = L.done + 1;
+    return L;
+}
+
+__host__ __device__ inline size_t fstream_lds_bytes(int q) {
+    return (size_t)(kFTailRing + q * kFTailK * 64) * 8 + (size_t)q * 64 * (8 + 16) + (size_t)q * kFTailK * 64 * 2 +
+           (size_t)(2 * q + 2) * 4;
+}
+
+__global__ __launch_bounds__(kFStreamBlock) void k_factor_stream(FactorArgs A, FactorStreamArgs T) {
+    extern __shared__ __align__(16) unsigned char fs_smem[];
+    const int q = T.q;
+    const FStreamLds L = fstream_lds(fs_smem, q);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < q; i += kFStreamBlock) L.ready[i] = -1;
+    if (threadIdx.x == 0) {
+        *L.done = -1;
+        *L.labort = 0;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        for (int s = 0; s < T.nsteps; ++s) {
+            const int slot = s % q;
+            if (!lds_wait_ge(&L.ready[slot], s, L.labort, A.info, false)) break;
+            const int kmax = L.skmax[slot];
+            const int4 m = L.smeta[slot * 64 + lane];
+            const int g = m.x & 255, t = (m.x >> 8) & 255, K = (m.x >> 16) & 255, len = (m.x >> 24) & 255;
+            const bool act = t < len;
+            const int gbase = lane & ~((1 << g) - 1);
+            const double a = L.sa[slot * 64 + lane];
+            double u[kFTailK];
+            uint32_t hasu = 0;   // bit e: entry e of the row meets U(c_e)
+#pragma unroll
+            for (int e = 0; e < kFTailK; ++e) {
+                const int ix = e < kmax ? (int)L.sidx[(slot * kFTailK + e) * 64 + lane] : kFStreamNone;
+                u[e] = L.vals[ix != kFStreamNone ? ix : 0];
+                if (ix != kFStreamNone) hasu |= 1u << e;
+            }
+            double v = a;
+#pragma unroll
+            for (int e = 0; e < kFTailK; ++e) {
+                if (e < kmax) {   // uniform: the step's longest L part
+                    if (t == e && e < K && act) v = v / u[e];   // (a row with fewer L entries is done)
+                    const double l = __shfl(v, gbase + e);
+                    if (t > e && hasu >> e & 1) {
+                        const double prod = l * u[e];
+                        v = v - prod;
+                    }
+                }
+            }
+            // the U part to the ring (read by later steps), then the published row
+            if (act && t >= K) L.vals[m.z] = v;
+            if (act) {
+                const uint64_t bits = (v != v) ? kQNaN64 : (uint64_t)__double_as_longlong(v);
+                st_pub_u64(reinterpret_cast<uint64_t *>(&A.lu[m.y]), bits);
+                const float f = (float)__longlong_as_double((long long)bits);
+                if (A.lu32) A.lu32[m.y] = f;
+                if (A.lu16) A.lu16[m.y] = to_bf16(f);
+                if (A.bval) A.bval[m.y] = a;
+            }
+            // a zero pivot or a non-finite entry (the checks of the other schedules)
+            const uint64_t zp = __ballot(act && t == K && v == 0.0);
+            const uint64_t nf = __ballot(act && !isfinite(v));
+            if (act && t == 0) {
+                const uint64_t gm = (g == 6) ? ~0ull : (((1ull << (1 << g)) - 1ull) << gbase);
+                if (zp & gm) atomicMin(&A.info[kInfoBadKey], 2 * m.w);
+                else if (nf & gm) atomicMin(&A.info[kInfoBadKey], 2 * m.w + 1);
+            }
+            // the step's buffer is free: its reads have returned (their values were
+            // used above) and LDS takes this write after them
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            if (lane == 0) __hip_atomic_store(L.done, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        return;
+    }
+    // stagers
+    for (int s = wave - 1; s < T.nsteps; s += kFStreamStagers) {
+        const int slot = s % q;
+        const int4 hd = T.hdr[s];
+        const int k = T.lmap[(size_t)hd.w + lane];
+        int4 ra = make_int4(0, 0, 0, 0), rb = make_int4(0, 0, 0, 0);
+        if (k != 255) {
+            ra = T.rows[2 * (size_t)(hd.x + k)];
+            rb = T.rows[2 * (size_t)(hd.x + k) + 1];
+        }
+        const int len = k != 255 ? (ra.z & 255) : 0, K = (ra.z >> 8) & 255, g = (ra.z >> 16) & 255;
+        const int t = k != 255 ? lane - ((ra.z >> 24) & 255) : 64;
+        const bool act = t < len;
+        const int p = act ? ra.y + t : 0;
+        const int pin = act ? A.src[p] : -1;
+        const double a = pin >= 0 ? A.a[pin] : 0.0;
+        // the sources of this lane's U values, one per L entry e of its row
+        int ix[kFTailK];
+        double xo[kFTailK];
+        int64_t gsrc[kFTailK];
+#pragma unroll
+        for (int e = 0; e < kFTailK; ++e) {
+            ix[e] = kFStreamNone;
+            gsrc[e] = -1;
+            xo[e] = 0.0;
+            if (e < K && act && t >= e) {
+                const int j = T.match[(size_t)rb.y + (size_t)e * len + t];
+                if (j != 255) {
+                    const int src = T.lsrc[rb.x + e];
+                    if (src >= 0) ix[e] = src + j;
+                    else gsrc[e] = (int64_t)(-src - 1) + j;
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < kFTailK; ++e)
+            if (gsrc[e] >= 0) xo[e] = __longlong_as_double((long long)ld_acq_u64(reinterpret_cast<const uint64_t *>(A.lu + gsrc[e])));
+        // the buffer is free once step s - q is done
+        if (s >= q && !lds_wait_ge(L.done, s - q, L.labort, A.info, true, true)) break;
+        // a value not yet visible was computed at least q steps ago: wait for it
+#pragma unroll
+        for (int e = 0; e < kFTailK; ++e)
+            if (gsrc[e] >= 0 && (uint64_t)__double_as_longlong(xo[e]) == kPending64)
+                xo[e] = __longlong_as_double((long long)wait_u64(reinterpret_cast<const uint64_t *>(A.lu + gsrc[e]),
+                                                                 A.info, A.poll_sleep));
+#pragma unroll
+        for (int e = 0; e < kFTailK; ++e) {
+            const int qi = (slot * kFTailK + e) * 64 + lane;
+            int idx = ix[e];
+            if (gsrc[e] >= 0) {
+                idx = kFTailRing + qi;
+                L.vals[idx] = xo[e];
+            }
+            L.sidx[qi] = (uint16_t)idx;
+        }
+        L.smeta[slot * 64 + lane] = make_int4(g | (act ? t : 255) << 8 | K << 16 | len << 24, p,
+                                              act && t >= K ? ra.w + (t - K) : 0, ra.x);
+        L.sa[slot * 64 + lane] = a;
+        if (lane == 0) {
+            L.skmax[slot] = hd.z;
+            __hip_atomic_store(&L.ready[slot], s, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_factor_stream(const FactorArgs &A, const FactorStreamArgs &T, hipStream_t s) {
+    if (T.nsteps <= 0) return hipSuccess;
+    if (T.q < 2 || T.q > kFTailQ) return hipErrorInvalidValue;
+    const size_t lds = fstream_lds_bytes(T.q);
+    if (lds > 163840) return hipErrorInvalidValue;
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute((const void *)k_factor_stream, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_factor_stream, dim3(1), dim3(kFStreamBlock), lds, s, A, T);
+    return hipGetLastError();
+}
+
+namespace {
+
+// ---------------------------------------------------------------------------------
 // Tiled factor (ILU(k, tau) at k = k_max on the forward tiles): rows and imported
 // U rows in LDS
 // ---------------------------------------------------------------------------------

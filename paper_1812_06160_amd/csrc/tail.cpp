@@ -176,123 +176,125 @@ void build_tail(const HostAnalysis &H, int dir, int32_t min_rows, int32_t min_le
 }
 
 
-// The factor's lower stage.  Row r of the tail is factored in one step: for its
-// L entries e ascending, lane e divides by the pivot of column c_e, the
-// multiplier goes to every lane of the row, and each lane whose column is in
-// U(c_e) subtracts multiplier * u -- the serial up-looking algorithm's operations
-// in its order (Sec. III, Fig. 1), hence its bits.  ER's "rows in parallel" part is
-// the rows before the tail, factored first; the corner is streamed.
+// The factor's lower stage (Sec. III-B, Even-Rows and Fig. 7): the tail rows are
+// factored in level order, a step at a time.  For its L entries e ascending a
+// row divides entry e by the pivot of column c_e and every later entry whose
+// column lies in U(c_e) subtracts multiplier * u -- the serial up-looking
+// algorithm's operations in its order (Sec. III, Fig. 1), hence its bits; the
+// entries with c_e before the tail (already final, ER's rows-in-parallel part)
+// and the corner's (c_e in the tail) come in that same column order.
 bool build_factor_tail(const HostAnalysis &H, const TailPlan &fwd, FactorTailPlan *T) {
     *T = FactorTailPlan();
-    if (fwd.nsteps == 0) return false;
-    const int32_t n = H.n, pos0 = fwd.pos0;
+    if (fwd.nsteps == 0 || fwd.level0 < 0) return false;
+    const int32_t n = H.n, pos0 = fwd.pos0, t0 = fwd.level0;
+    const int32_t nl = (int32_t)H.level_ptr.size() - 1;
     int32_t umax = 1;
     for (int32_t r = pos0; r < n; ++r) {
         const int32_t len = H.lu_rp[r + 1] - H.lu_rp[r], K = H.diag[r] - H.lu_rp[r];
         if (len > 64 || K > kFTailK) return false;
         umax = std::max(umax, H.lu_rp[r + 1] - H.diag[r]);
     }
-    const int32_t W = kFTailW, RW = kFTailW * umax;
-    // steps: rows of one level, groups of G >= len lanes packed largest first
-    std::vector<std::vector<std::pair<int32_t, int32_t>>> steps;   // (row, log2 G)
-    std::vector<int32_t> step_level;
-    const int32_t nl = (int32_t)H.level_ptr.size() - 1, t0 = fwd.level0;
+    int32_t W = 1;
+    while (2 * W * umax <= kFTailRing) W *= 2;
+    // steps: rows of one level, groups of 2^g >= len lanes packed largest first
+    struct Step {
+        int32_t level;
+        std::vector<std::pair<int32_t, int32_t>> rows;   // (row, g)
+    };
+    std::vector<Step> steps;
     std::vector<int32_t> step_of(n - pos0, -1);
     for (int32_t l = t0; l < nl; ++l) {
-        std::vector<std::pair<int32_t, int32_t>> rows;
+        std::vector<std::pair<int32_t, int32_t>> rs;
         for (int32_t r = H.level_ptr[l]; r < H.level_ptr[l + 1]; ++r) {
             const int32_t len = H.lu_rp[r + 1] - H.lu_rp[r];
             int32_t g = 0;
             while ((1 << g) < len) ++g;
-            rows.push_back({r, g});
+            rs.push_back({r, g});
         }
-        std::stable_sort(rows.begin(), rows.end(), [](const auto &a, const auto &b) { return a.second > b.second; });
-        std::vector<std::pair<int32_t, int32_t>> cur;
+        std::stable_sort(rs.begin(), rs.end(), [](const auto &a, const auto &b) { return a.second > b.second; });
+        Step cur{l, {}};
         int32_t lanes = 0;
-        for (const auto &rg : rows) {
+        for (const auto &rg : rs) {
             if (lanes + (1 << rg.second) > 64) {
                 steps.push_back(cur);
-                step_level.push_back(l);
-                cur.clear();
+                cur = Step{l, {}};
                 lanes = 0;
             }
-            cur.push_back(rg);
+            cur.rows.push_back(rg);
             lanes += 1 << rg.second;
             step_of[rg.first - pos0] = (int32_t)steps.size();
         }
-        if (!cur.empty()) {
-            steps.push_back(cur);
-            step_level.push_back(l);
+        if (!cur.rows.empty()) steps.push_back(cur);
+    }
+    const int32_t ns = (int32_t)steps.size();
+    // Ring rule: c's slot is intact when read at step s if no row written from c's
+    // step through s holds the same slot: the levels of those steps span at most W
+    // rows (rows are numbered in level order).  Staging depth q: the largest <=
+    // kFTailQ for which every source at most q steps old passes.
+    auto span_ok = [&](int32_t sd, int32_t s) {
+        return H.level_ptr[steps[s].level + 1] - H.level_ptr[steps[sd].level] <= W;
+    };
+    int32_t q = kFTailQ;
+    for (int32_t s = 0; s < ns && q >= 2; ++s) {
+        for (const auto &rg : steps[s].rows) {
+            const int32_t r = rg.first;
+            for (int32_t p = H.lu_rp[r]; p < H.diag[r]; ++p) {
+                const int32_t c = H.lu_ci[p];
+                if (c < pos0) continue;
+                const int32_t sd = step_of[c - pos0];
+                while (q >= 2 && s - sd < q && !span_ok(sd, s)) --q;
+            }
         }
     }
+    if (q < 2) return false;
+    T->level0 = t0;
     T->pos0 = pos0;
+    T->nsteps = ns;
     T->umax = umax;
-    T->nsteps = (int32_t)steps.size();
-    for (int32_t s = 0; s < T->nsteps; ++s) {
-        const auto &S = steps[s];
-        int32_t nlanes = 0, kmax = 0;
-        for (const auto &rg : S) {
-            nlanes += 1 << rg.second;
-            kmax = std::max(kmax, H.diag[rg.first] - H.lu_rp[rg.first]);
-        }
-        T->hdr.push_back((int32_t)T->rec.size());
-        T->hdr.push_back((int32_t)S.size() | nlanes << 8 | kmax << 16);
-        T->hdr.push_back(0);
-        T->hdr.push_back(0);
-        // lanes
-        std::vector<int32_t> row_of(nlanes, -1), t_of(nlanes, 0);
-        for (int32_t k = 0, l0 = 0; k < (int32_t)S.size(); ++k) {
-            for (int32_t t = 0; t < (1 << S[k].second); ++t) {
-                row_of[l0 + t] = k;
-                t_of[l0 + t] = t;
-            }
-            l0 += 1 << S[k].second;
-        }
-        for (int32_t ln = 0; ln < nlanes; ++ln) {
-            const int32_t r = S[row_of[ln]].first, t = t_of[ln];
+    T->ring_rows = W;
+    T->q = q;
+    for (int32_t s = 0; s < ns; ++s) {
+        const Step &S = steps[s];
+        int32_t kmax = 0;
+        for (const auto &rg : S.rows) kmax = std::max(kmax, H.diag[rg.first] - H.lu_rp[rg.first]);
+        T->hdr.insert(T->hdr.end(), {(int32_t)(T->rows.size() / 8), (int32_t)S.rows.size(), kmax,
+                                     (int32_t)T->lmap.size()});
+        std::vector<uint8_t> lm(64, 255);
+        int32_t lane0 = 0;
+        for (int32_t k = 0; k < (int32_t)S.rows.size(); ++k) {
+            const int32_t r = S.rows[k].first, g = S.rows[k].second;
             const int32_t len = H.lu_rp[r + 1] - H.lu_rp[r], K = H.diag[r] - H.lu_rp[r];
-            T->rec.push_back(row_of[ln] | t << 8 | K << 16 | len << 24);
-            const int32_t p = t < len ? H.lu_rp[r] + t : -1;
-            T->rec.push_back(p);
-            T->rec.push_back(p >= 0 ? H.lu_src[p] : -1);
-            T->rec.push_back(t >= K && t < len ? (r & (W - 1)) * umax + (t - K) : -1);
-        }
-        // sources of the U values each lane needs, L entry by L entry
-        for (int32_t e = 0; e < kmax; ++e)
-            for (int32_t ln = 0; ln < nlanes; ++ln) {
-                const int32_t r = S[row_of[ln]].first, t = t_of[ln];
-                const int32_t len = H.lu_rp[r + 1] - H.lu_rp[r], K = H.diag[r] - H.lu_rp[r];
-                int32_t src = -1;
-                if (e < K && t < len && t >= e) {
-                    const int32_t c = H.lu_ci[H.lu_rp[r] + e];
-                    int32_t j = -1;   // position of entry t's column in U(c)
+            for (int32_t t = 0; t < (1 << g); ++t) lm[lane0 + t] = (uint8_t)k;
+            T->rows.insert(T->rows.end(), {r, H.lu_rp[r], len | K << 8 | g << 16 | lane0 << 24,
+                                           (r & (W - 1)) * umax, (int32_t)T->lsrc.size(), (int32_t)T->match.size(),
+                                           0, 0});
+            for (int32_t e = 0; e < K; ++e) {
+                const int32_t c = H.lu_ci[H.lu_rp[r] + e];
+                bool ring = false;
+                if (c >= pos0) {
+                    const int32_t sd = step_of[c - pos0];
+                    ring = s - sd < q || span_ok(sd, s);
+                }
+                T->lsrc.push_back(ring ? (c & (W - 1)) * umax : -(H.diag[c] + 1));
+                // positions in U(c) of the row's entries t > e (both rows sorted)
+                const int32_t *ub = H.lu_ci.data() + H.diag[c], *ue = H.lu_ci.data() + H.lu_rp[c + 1];
+                for (int32_t t = 0; t < len; ++t) {
+                    uint8_t j = 255;
                     if (t == e) {
                         j = 0;
-                    } else {
+                    } else if (t > e) {
                         const int32_t col = H.lu_ci[H.lu_rp[r] + t];
-                        const auto b = H.lu_ci.begin() + H.diag[c], en = H.lu_ci.begin() + H.lu_rp[c + 1];
-                        const auto it = std::lower_bound(b, en, col);
-                        if (it != en && *it == col) j = (int32_t)(it - b);
+                        const int32_t *f = std::lower_bound(ub, ue, col);
+                        if (f != ue && *f == col) j = (uint8_t)(f - ub);
                     }
-                    if (j >= 0) {
-                        src = RW + H.diag[c] + j;   // the factor buffer
-                        if (c >= pos0) {
-                            const int32_t sd = step_of[c - pos0];
-                            // in the ring when no row written since holds its slot:
-                            // rows written after c's step lie between the start of
-                            // its level and the end of the previous step's level
-                            if (sd < s && H.level_ptr[step_level[s - 1] + 1] - H.level_ptr[step_level[sd]] <= W)
-                                src = (c & (W - 1)) * umax + j;
-                        }
-                    }
+                    T->match.push_back(j);
                 }
-                T->rec.push_back(src);
             }
+            lane0 += 1 << g;
+        }
+        T->lmap.insert(T->lmap.end(), lm.begin(), lm.end());
     }
-    T->hdr.push_back((int32_t)T->rec.size());
-    T->hdr.push_back(0);
-    T->hdr.push_back(0);
-    T->hdr.push_back(0);
+    T->hdr.insert(T->hdr.end(), {(int32_t)(T->rows.size() / 8), 0, 0, (int32_t)T->lmap.size()});
     return true;
 }
 

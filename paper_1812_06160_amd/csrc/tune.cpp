@@ -215,6 +215,20 @@ extern "C" ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, 
             }
         h->sched_factor = best_fs;
         h->lanes_factor = best_fs == ILU_SCHED_TILED ? save_lf : best_lf;
+        // the factor's lower stage, when the chosen tail has a plan for it
+        const bool save_fl = h->factor_lower;
+        h->factor_lower = false;
+        if (h->ftail_ok && h->tail_min_rows > 0 && k == H.k_max && tau == 0.0 && !(fflags & ILU_FACTOR_MODIFIED)) {
+            h->factor_lower = true;
+            double us = 0;
+            ilu_status st = time_it(factor, &us);
+            if (st != ILU_OK) {
+                h->factor_lower = save_fl;
+                return restore(st);
+            }
+            rows.insert(rows.end(), {0.0, 10.0, (double)h->tail_min_rows, us});
+            h->factor_lower = us < best;
+        }
         // leave the caller's factor computed on the chosen schedule
         ilu_status st = factor();
         if (st != ILU_OK) return restore(st);

@@ -133,6 +133,25 @@ class Ilu:
         L.check(self.lib.ilu_copy_tail(self.h, int(direction), None, _np_ptr(hdr), _np_ptr(rec)), "ilu_copy_tail")
         return dict(level0=int(sz[0]), pos0=int(sz[1]), nsteps=int(sz[2]), hdr=hdr.reshape(-1, 4), rec=rec)
 
+    def factor_tail(self):
+        """The factor's lower stage: dict(level0, pos0, nsteps, umax, ring_rows, q, hdr
+        [nsteps+1][4], rows [records][8], lsrc, match, lmap [nsteps][64]); level0 -1 when
+        the handle has no plan."""
+        sz = np.zeros(10, np.int32)
+        L.check(self.lib.ilu_copy_factor_tail(self.h, _np_ptr(sz), None, None, None, None, None),
+                "ilu_copy_factor_tail")
+        ns = int(sz[2])
+        hdr = np.zeros((ns + 1) * 4 if ns > 0 else 0, np.int32)
+        rows = np.zeros(int(sz[6]) * 8, np.int32)
+        lsrc = np.zeros(int(sz[7]), np.int32)
+        match = np.zeros(int(sz[8]), np.uint8)
+        lmap = np.zeros(int(sz[9]), np.uint8)
+        L.check(self.lib.ilu_copy_factor_tail(self.h, None, _np_ptr(hdr), _np_ptr(rows), _np_ptr(lsrc),
+                                              _np_ptr(match), _np_ptr(lmap)), "ilu_copy_factor_tail")
+        return dict(level0=int(sz[0]), pos0=int(sz[1]), nsteps=ns, umax=int(sz[3]), ring_rows=int(sz[4]),
+                    q=int(sz[5]), hdr=hdr.reshape(-1, 4), rows=rows.reshape(-1, 8), lsrc=lsrc, match=match,
+                    lmap=lmap.reshape(-1, 64))
+
     def batch_offsets(self):
         cnt = self._info.batch_count
         ro = np.empty(cnt + 1, np.int64)

@@ -84,6 +84,12 @@ def test_random_1m_tail_full(jv):
     ilu.factor(dev(A.val), casts=("f32",))
     an = O.analyze(A.n, A.row_ptr, A.col_idx)
     f = O.factor(an, A.val)
+    # the factor streamed as well (the lower stage of the factor): the serial bits
+    assert ilu.factor_tail()["level0"] >= 0
+    ilu.set_tuning("factor_lower_stage", 1)
+    ilu.factor(dev(A.val), casts=("f32",))
+    lu, _ = ilu.factor_values()
+    assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
     cols = [0, 7, 15]
     x = ilu.apply(dev(B)).cpu().numpy()
     assert relerr(x[:, cols], O.apply(an, f.val, np.ascontiguousarray(B[:, cols]))) <= 1e-12

@@ -358,6 +358,59 @@ TAIL_CASES = [
 ]
 
 
+FACTOR_TAIL_CASES = [
+    ("random_banded_6000_all", lambda: synth.random_banded(6000, rng=np.random.default_rng(31)), 0, 65536),
+    ("laplace2d_150_tail65", lambda: synth.laplace2d(150), 0, 65),
+    ("tridiag_3000_chain", lambda: synth.tridiag(3000), 0, 65536),
+    ("laplace2d_60_ilu1", lambda: synth.laplace2d(60), 1, 65536),
+    ("random_banded_3000_ilu1_narrow", lambda: synth.random_banded(3000, band=2, rnd=2, rng=np.random.default_rng(6)),
+     1, 65536),
+]
+
+
+@pytest.mark.parametrize("name,mk,k,M", FACTOR_TAIL_CASES, ids=[c[0] for c in FACTOR_TAIL_CASES])
+def test_factor_tail_bit_exact(jv, name, mk, k, M):
+    # the factor's lower stage (rows before the tail sync-free, the tail streamed by
+    # one workgroup): the serial factor's bits, its FP32/BF16 copies and the spmv
+    # operand as on the other schedules, every schedule of the handle alike
+    A = mk()
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k)
+    f = O.factor(an, A.val, k=k)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=k, tile_rows=128, tail_min_rows=M)
+    assert ilu.factor_tail()["level0"] >= 0 and ilu.get_tuning("factor_lower_planned") == 1
+    assert ilu.get_tuning("factor_lower_stage") == 0
+    ilu.set_tuning("factor_lower_stage", 1)
+    for sched in ("tiled", "syncfree", "level"):
+        ilu.set_schedule(sched, "syncfree")
+        for rep in range(2):
+            ilu.factor(dev(A.val * (1.0 + rep)), k=k, casts=("f32", "bf16"))
+            fr = f if rep == 0 else O.factor(an, A.val * 2.0, k=k)
+            lu, _ = ilu.factor_values()
+            assert np.array_equal(lu.view(np.uint64), fr.val.view(np.uint64)), (sched, rep)
+            assert np.array_equal(ilu.factor_values_prec("f32").view(np.uint32), O.cast_f32(fr.val).view(np.uint32))
+            assert np.array_equal(ilu.factor_values_prec("bf16"), O.cast_bf16(fr.val))
+            x = np.random.default_rng(38).uniform(-1, 1, A.n)
+            yr = O.spmv(A.n, A.row_ptr, A.col_idx, A.val * (1.0 + rep), x)
+            assert relerr(ilu.spmv(dev(x)).cpu().numpy(), yr) <= 1e-12
+    # a non-finite input value in the tail: the first bad row, as the serial factor
+    v = A.val.copy()
+    r_bad = A.n - A.n // 5
+    v[A.row_ptr[r_bad]] = np.nan
+    fb = O.factor(an, v, k=k)
+    with pytest.raises(jv.IluError) as e:
+        ilu.factor(dev(v), k=k)
+    assert e.value.status == "ILU_ERR_NONFINITE" and e.value.info["bad_row"] == fb.bad_row
+    ilu.factor(dev(A.val), k=k)
+    lu, _ = ilu.factor_values()
+    assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
+    # the autotuner times it against the other schedules and keeps the faster
+    res, _ = ilu.tune(dev(A.val), reps=2)
+    planned = ilu.get_tuning("tail_min_rows") > 0 and ilu.get_tuning("factor_lower_planned") == 1
+    assert ((res[:, 0] == 0) & (res[:, 1] == 10)).sum() == int(planned)
+    lu, _ = ilu.factor_values()
+    assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
+
+
 @pytest.mark.parametrize("sched", ["tiled", "syncfree", "level"])
 @pytest.mark.parametrize("name,mk,k,M", TAIL_CASES, ids=[c[0] for c in TAIL_CASES])
 def test_tail_apply(jv, name, mk, k, M, sched):
