@@ -42,11 +42,11 @@ HBM_PEAK_GBS = 8000.0
 # scaled by what the same counters read for the calibration copy kernels.  Valid
 # only for the kernel source it was taken with: a different hash reports null.
 PMC_TRAFFIC = dict(
-    kernels_sha256="a9eee54bbd52941742d98d9ad40a00e2d4778a8832d729e5a085bc9e9ac1763b",
-    fetch_scale=1.9987, write_scale=0.9945,
-    forward=dict(f64=(209072, 66171), f32=(159291, 50766)),
-    backward=dict(f64=(211735, 94306), f32=(150668, 77626)),
-    factor=(281816, 146456),
+    kernels_sha256="5fe46c138a7265daab942f82aebb069138bad60ba2da20f1fcd3825b9eef1a3f",
+    fetch_scale=1.9988, write_scale=0.9943,
+    forward=dict(f64=(197325, 66082), f32=(160067, 50874)),
+    backward=dict(f64=(196338, 93590), f32=(150919, 77568)),
+    factor=(218870, 337879),
 )
 
 
