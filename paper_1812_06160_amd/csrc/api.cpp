@@ -87,6 +87,8 @@ ilu_handle_s::~ilu_handle_s() {
     prof.release();
 
     for (void *p : allocs) (void)hipFree(p);
+    if (h_kry_pin) (void)hipHostFree(h_kry_pin);
+    if (kry_ev) (void)hipEventDestroy(kry_ev);
     for (auto &kv : tasks) {
         (void)hipFree(kv.second.ptr);
         (void)hipFree(kv.second.stream_tasks);

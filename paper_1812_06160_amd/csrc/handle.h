@@ -81,6 +81,10 @@ struct ilu_handle_s {
     // Krylov workspace
     size_t kry_bytes = 0;
     double *d_kry = nullptr;
+    // pinned host block the drivers read their scalars and the info words into, and
+    // the event that marks a posted readback complete
+    double *h_kry_pin = nullptr;
+    hipEvent_t kry_ev = nullptr;
 
     std::map<int64_t, jv::TaskList> tasks;
 

@@ -53,6 +53,25 @@ struct Ctx {
     double *work;   // dot partials
 };
 
+// Pinned readback block: kPinScal scalars, then kPinCoef GMRES coefficients, then the
+// info words.
+constexpr int kPinScal = 64, kPinCoef = 64;
+constexpr size_t kPinBytes = sizeof(double) * (kPinScal + kPinCoef) + sizeof(int32_t) * kInfoSlots;
+
+ilu_status ensure_pin(ilu_handle_s *h) {
+    if (!h->h_kry_pin) {
+        void *p = nullptr;
+        hipError_t e = hipHostMalloc(&p, kPinBytes, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "krylov pinned block");
+        h->h_kry_pin = (double *)p;
+    }
+    if (!h->kry_ev) {
+        hipError_t e = hipEventCreateWithFlags(&h->kry_ev, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "krylov event");
+    }
+    return ILU_OK;
+}
+
 // Applies inside a driver skip the per-call guard: the driver runs it once at its
 // start and checks the abort flag at every readback, so each apply starts clear.
 ilu_status apply(Ctx &c, const double *in, double *out) {
@@ -64,17 +83,37 @@ ilu_status spmv(Ctx &c, double alpha, const double *x, double beta, double *y) {
     return ilu_spmv(c.h, alpha, x, beta, y, 1, 1, ILU_PERMUTED_SPACE, c.s);
 }
 
-// Reads `count` device scalars, and with them the abort flag and the timeout
-// count of the applies: a preconditioner apply whose wait expired makes the
-// iterate meaningless, so the driver stops with ILU_ERR_TIMEOUT.
-ilu_status readback(Ctx &c, const double *dev, double *host, int count) {
-    int32_t w[kInfoSlots];
-    hipError_t e = hipMemcpyAsync(host, dev, sizeof(double) * count, hipMemcpyDeviceToHost, c.s);
-    if (e == hipSuccess) e = hipMemcpyAsync(w, c.h->d_info, sizeof(w), hipMemcpyDeviceToHost, c.s);
-    if (e == hipSuccess) e = hipStreamSynchronize(c.s);
+// A readback is posted and later awaited, so that work that does not depend on the
+// scalars (the next preconditioner apply) is queued behind the copies before the host
+// waits: the device never idles during the host's convergence test.  post_readback
+// queues the copy of `count` device scalars and of the info words (the abort flag and
+// the timeout count of the applies queued before it) into the pinned block and
+// records the event; wait_readback waits for it, hands the scalars over, and stops
+// the driver with ILU_ERR_TIMEOUT when an apply's wait expired, since the iterate is
+// then meaningless.
+ilu_status post_readback(Ctx &c, const double *dev, int count) {
+    hipError_t e = hipMemcpyAsync(c.h->h_kry_pin, dev, sizeof(double) * count, hipMemcpyDeviceToHost, c.s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c.h->h_kry_pin + kPinScal + kPinCoef, c.h->d_info, sizeof(int32_t) * kInfoSlots,
+                           hipMemcpyDeviceToHost, c.s);
+    if (e == hipSuccess) e = hipEventRecord(c.h->kry_ev, c.s);
     if (e != hipSuccess) return hip_fail(e, "krylov readback");
+    return ILU_OK;
+}
+
+ilu_status wait_readback(Ctx &c, double *host, int count) {
+    hipError_t e = hipEventSynchronize(c.h->kry_ev);
+    if (e != hipSuccess) return hip_fail(e, "krylov readback");
+    std::memcpy(host, c.h->h_kry_pin, sizeof(double) * count);
+    int32_t w[kInfoSlots];
+    std::memcpy(w, c.h->h_kry_pin + kPinScal + kPinCoef, sizeof(w));
     if (w[kInfoAbort] || w[kInfoTimeouts]) return c.h->take_timeout(c.s, "krylov");
     return ILU_OK;
+}
+
+ilu_status readback(Ctx &c, const double *dev, double *host, int count) {
+    ilu_status st = post_readback(c, dev, count);
+    return st == ILU_OK ? wait_readback(c, host, count) : st;
 }
 
 #define CHK(x)                          \
@@ -105,11 +144,12 @@ extern "C" ilu_status ilu_solve_pcg(ilu_handle h, const double *b, double *x, do
     CHK(check_common(h, b, x, rtol, fac_prec, flags));
     const int64_t n = h->H.n;
     CHK(ensure_kry(h, sizeof(double) * (size_t)n * 6, s));
+    CHK(ensure_pin(h));
     CHK(h->ensure_workspace(1, fac_prec == ILU_PREC_F64 ? 0 : 1, s) == hipSuccess ? ILU_OK : fail(ILU_ERR_HIP, "pcg workspace"));
     HCHK(h->guard(s), "pcg guard");
     double *bp = h->d_kry, *xp = bp + n, *r = xp + n, *z = r + n, *p = z + n, *q = p + n;
     Ctx c{h, n, fac_prec, s, h->d_dotwork + kDotParts, h->d_dotwork};
-    double *S = c.scal;   // 0 bnorm^2, 1 rz, 2 rz_new, 3 pq, 4 rr
+    double *S = c.scal;   // 0 bnorm^2, 1 and 2 r.z (the two alternate), 3 pq, 4 rr
     if (flags & ILU_PERMUTED_SPACE) HCHK(hipMemcpyAsync(bp, b, n * 8, hipMemcpyDeviceToDevice, s), "pcg copy");
     else HCHK(blas_permute(n, h->d_perm, b, bp, 0, s), "pcg permute");
     HCHK(hipMemsetAsync(xp, 0, n * 8, s), "pcg zero");
@@ -128,15 +168,27 @@ extern "C" ilu_status ilu_solve_pcg(ilu_handle h, const double *b, double *x, do
         HCHK(hipMemcpyAsync(r, bp, n * 8, hipMemcpyDeviceToDevice, s), "pcg copy");
         for (;;) {
             bool converged = false;
+            int cur = 1;   // slot of r.z for the current direction p
             CHK(apply(c, r, z));
             HCHK(hipMemcpyAsync(p, z, n * 8, hipMemcpyDeviceToDevice, s), "pcg copy");
-            HCHK(blas_dot(n, r, z, &S[1], c.work, s), "pcg dot");
+            HCHK(blas_dot(n, r, z, &S[cur], c.work, s), "pcg dot");
             while (I.iters < maxit) {
                 CHK(spmv(c, 1.0, p, 0.0, q));
                 HCHK(blas_dot(n, p, q, &S[3], c.work, s), "pcg dot");
-                HCHK(blas_pcg_xr(n, &S[1], &S[3], p, q, xp, r, s), "pcg update");
+                HCHK(blas_pcg_xr(n, &S[cur], &S[3], p, q, xp, r, s), "pcg update");
                 HCHK(blas_dot(n, r, r, &S[4], c.work, s), "pcg dot");
-                CHK(readback(c, &S[3], hb, 2));
+                CHK(post_readback(c, &S[3], 2));
+                // The next direction needs only device data: queue it before the host
+                // wait.  When the test below stops the loop, x and r are already final
+                // and the speculative z, p and r.z are overwritten before any later use.
+                const int nxt = 3 - cur;
+                const bool more = I.iters + 1 < maxit;
+                if (more) {
+                    CHK(apply(c, r, z));
+                    HCHK(blas_dot(n, r, z, &S[nxt], c.work, s), "pcg dot");
+                    HCHK(blas_xpby_dev(n, &S[nxt], &S[cur], z, p, s), "pcg p update");
+                }
+                CHK(wait_readback(c, hb, 2));
                 ++I.iters;
                 if (hb[0] == 0.0) {
                     I.status = ILU_ERR_BREAKDOWN;
@@ -147,10 +199,7 @@ extern "C" ilu_status ilu_solve_pcg(ilu_handle h, const double *b, double *x, do
                     converged = true;
                     break;
                 }
-                CHK(apply(c, r, z));
-                HCHK(blas_dot(n, r, z, &S[2], c.work, s), "pcg dot");
-                HCHK(blas_xpby_dev(n, &S[2], &S[1], z, p, s), "pcg p update");
-                HCHK(hipMemcpyAsync(&S[1], &S[2], 8, hipMemcpyDeviceToDevice, s), "pcg scalar copy");
+                cur = nxt;
             }
             // true residual
             HCHK(hipMemcpyAsync(r, bp, n * 8, hipMemcpyDeviceToDevice, s), "pcg copy");
@@ -185,6 +234,7 @@ extern "C" ilu_status ilu_solve_gmres(ilu_handle h, const double *b, double *x, 
     const int m = restart;
     const int64_t n = h->H.n;
     CHK(ensure_kry(h, sizeof(double) * (size_t)n * (size_t)(2 * m + 4), s));
+    CHK(ensure_pin(h));
     CHK(h->ensure_workspace(1, fac_prec == ILU_PREC_F64 ? 0 : 1, s) == hipSuccess ? ILU_OK : fail(ILU_ERR_HIP, "gmres workspace"));
     HCHK(h->guard(s), "gmres guard");
     double *bp = h->d_kry, *xp = bp + n, *w = xp + n, *V = w + n, *Z = V + (size_t)n * (m + 1);
@@ -224,10 +274,13 @@ extern "C" ilu_status ilu_solve_gmres(ilu_handle h, const double *b, double *x, 
             g[0] = beta;
             int jend = -1;
             bool breakdown = false;
+            bool queued = false;   // apply and spmv of step j already queued
             for (int j = 0; j < m && I.iters < maxit; ++j) {
                 double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
-                CHK(apply(c, vj, zj));
-                CHK(spmv(c, 1.0, zj, 0.0, w));
+                if (!queued) {
+                    CHK(apply(c, vj, zj));
+                    CHK(spmv(c, 1.0, zj, 0.0, w));
+                }
                 for (int i = 0; i <= j; ++i) {   // modified Gram-Schmidt
                     double *vi = V + (size_t)i * n;
                     HCHK(blas_dot(n, w, vi, &S[i], c.work, s), "gmres dot");
@@ -235,7 +288,17 @@ extern "C" ilu_status ilu_solve_gmres(ilu_handle h, const double *b, double *x, 
                 }
                 HCHK(blas_dot(n, w, w, &S[j + 1], c.work, s, 1), "gmres norm");
                 HCHK(blas_scale_inv_dev(n, &S[j + 1], w, V + (size_t)(j + 1) * n, s), "gmres scale");
-                CHK(readback(c, S, hb, j + 2));
+                CHK(post_readback(c, S, j + 2));
+                // The next Arnoldi step's apply and spmv need only v_{j+1}: queue them
+                // before the host wait.  If the test below ends the cycle, their results
+                // (z_{j+1} and w) are overwritten before any later use.
+                queued = j + 1 < m && I.iters + 1 < maxit;
+                if (queued) {
+                    double *vn = V + (size_t)(j + 1) * n, *zn = Z + (size_t)(j + 1) * n;
+                    CHK(apply(c, vn, zn));
+                    CHK(spmv(c, 1.0, zn, 0.0, w));
+                }
+                CHK(wait_readback(c, hb, j + 2));
                 for (int i = 0; i <= j + 1; ++i) H[(size_t)i * m + j] = hb[i];
                 for (int i = 0; i < j; ++i) {   // previous rotations
                     const double a = H[(size_t)i * m + j], cc = H[(size_t)(i + 1) * m + j];
@@ -267,10 +330,13 @@ extern "C" ilu_status ilu_solve_gmres(ilu_handle h, const double *b, double *x, 
                 }
                 yv[i] = sum / H[(size_t)i * m + i];
             }
-            HCHK(hipMemcpyAsync(&S[m + 2], yv.data(), sizeof(double) * (jend + 1), hipMemcpyHostToDevice, s),
+            // The coefficients go through the pinned block's own area, which no later
+            // readback writes; the next readback's wait orders any reuse of it.
+            double *coef = h->h_kry_pin + kPinScal;
+            std::memcpy(coef, yv.data(), sizeof(double) * (jend + 1));
+            HCHK(hipMemcpyAsync(&S[m + 2], coef, sizeof(double) * (jend + 1), hipMemcpyHostToDevice, s),
                  "gmres coefficients");
             HCHK(blas_combine(n, jend + 1, &S[m + 2], Z, n, xp, s), "gmres update");
-            HCHK(hipStreamSynchronize(s), "gmres sync");   // yv is pageable host memory
         }
     }
     if (flags & ILU_PERMUTED_SPACE) HCHK(hipMemcpyAsync(x, xp, n * 8, hipMemcpyDeviceToDevice, s), "gmres copy");
