@@ -390,7 +390,19 @@ ilu_status ilu_get_schedule(ilu_handle h, int32_t *factor_sched, int32_t *solve_
 /* Named tuning knobs.  Settable: "poll_sleep" (0..64, pause steps of about 64
  * clocks between polls of a value that is still pending), "tile_rows" (16..65536,
  * rebuilds the tiles of the tiled solves on the host and uploads them;
- * synchronous), "factor_staged" (1, the default: the sync-free and level factors
+ * synchronous), "tile_lattice" (1, the default, or 0; rebuilds the tiles like
+ * "tile_rows"): a matrix recognised as a 2D or 3D structured grid in natural order
+ * (every factor entry joins rows at most 3 apart on each grid axis, the extents read
+ * off the index offsets) is tiled in boxes of a basis of grid functionals that no
+ * dependency decreases, taken in wavefront order -- cubes for ILU(0) on a 7-point
+ * grid, sheared boxes once ILU(1) fill joins (x+1, y-1); 0, or any other matrix:
+ * greedy growth; same results either way; read back, 1 means the current tiles are
+ * boxes, "factor_tile_rows" (0, the default, or 16..65536; rebuilds the tiled
+ * factor's tiles only): rows per tile of the tiled factor; the default shrinks
+ * the solves' size by halves until a tile carries about the update work of 512
+ * rows of ILU(0) on a 7-point grid (ILU(1) there: 128 rows); halved further
+ * while the tile image does not fit LDS; read back, the size in use (0: no tiled
+ * factor), "factor_staged" (1, the default: the sync-free and level factors
  * gather a row's dependency rows into LDS when they fit; 0: each dependency row
  * is read from global memory when its turn comes; same results).  Readable as well:
  * "nstreams" (task streams = XCDs found), "factor_tcap" (LDS entries staged per

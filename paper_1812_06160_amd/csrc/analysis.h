@@ -79,13 +79,15 @@ struct TileSet {
 // entry p = (r, c) with c != r, sci[p] = LDS slot of c in r's tile of the
 // direction that reads the entry; diagonal entries get -1.  A direction whose
 // rows have at most short_row dependencies is padded to chunks of 64 positions
-// (one lane per row), otherwise to chunks of 16 (four lanes per row).
-void build_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, TileSet *fwd, TileSet *bwd,
+// (one lane per row), otherwise to chunks of 16 (four lanes per row).  With
+// `lattice`, a matrix recognised as a structured grid in natural order gets box
+// tiles (returns true), any other the greedy growth.
+bool build_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, bool lattice, TileSet *fwd, TileSet *bwd,
                  std::vector<int32_t> *sci);
 
 // Forward tiles only (a tiling of its own for the factor when the solves' tiles
 // are too large for its LDS image).
-void build_forward_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, TileSet *fwd);
+void build_forward_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, bool lattice, TileSet *fwd);
 
 // Lower stage ("tail") of one triangular-solve direction: the longest suffix of
 // its level order whose levels hold fewer than min_rows rows, cut into steps (rows

@@ -281,6 +281,26 @@ static size_t default_tile_budget(const HostAnalysis &H) {
     return sizes[sizes.size() / 2] < 256 ? (size_t)kTileLdsMax : (size_t)65536;
 }
 
+// Default rows per tile of the tiled factor.  A tile's life is its rows' update
+// work (each L entry of a row subtracts the dependency row's U part), and the
+// factor runs fewer tiles at once than the solves, so tiles shrink from the
+// solves' size until they carry about as much of it as a 512-row tile of ILU(0) on
+// a 7-point grid (about 9 multiply-subtracts per row): ILU(1) on a 7-point grid
+// (about 36) gets 128-row tiles.
+static int32_t default_factor_rows(const HostAnalysis &H, int32_t tile_rows) {
+    if (H.n == 0) return tile_rows;
+    double work = 0.0;
+    for (int32_t r = 0; r < H.n; ++r)
+        for (int32_t p = H.lu_rp[r]; p < H.diag[r]; ++p) {
+            const int32_t c = H.lu_ci[p];
+            work += (double)(H.lu_rp[c + 1] - H.diag[c] - 1);
+        }
+    work /= H.n;
+    int32_t rows = tile_rows;
+    while (rows > 64 && (double)rows * work > 16.0 * (double)tile_rows) rows /= 2;
+    return rows;
+}
+
 // LDS slot of every position of a tiling (-1 for padding)
 static std::vector<int16_t> position_slots(const TileSet &T) {
     std::vector<int16_t> pslot(T.row.size());
@@ -295,7 +315,7 @@ ilu_status ilu_handle_s::make_tiles(int32_t rows, bool shrink) {
     try {
         const size_t budget = default_tile_budget(H);
         for (;;) {
-            build_tiles(H, rows, kTileShortRow, &tiles[0], &tiles[1], &sci);
+            tiles_on_lattice = build_tiles(H, rows, kTileShortRow, tile_lattice, &tiles[0], &tiles[1], &sci);
             if (!shrink || rows <= 16 || (tiles_fit(tiles[0], budget) && tiles_fit(tiles[1], budget))) break;
             rows /= 2;
         }
@@ -363,10 +383,18 @@ ilu_status ilu_handle_s::make_factor_tiles() {
         return ftiles.lds_need[3] <= (size_t)kFactorTileLdsMax;
     };
     try {
-        bool ok = fits(tiles[0]);
-        // too large an LDS image: a forward tiling of its own, halving the tile size
-        for (int32_t rows = tile_rows / 2; !ok && rows >= 16; rows /= 2) {
-            build_forward_tiles(H, rows, kTileShortRow, &ftset);
+        // the solves' forward tiles unless another size is asked for; too large an
+        // LDS image: a forward tiling of its own, halving the tile size
+        const int32_t want = factor_rows > 0 ? factor_rows : default_factor_rows(H, tile_rows);
+        bool ok = false;
+        if (want == tile_rows) {
+            ok = fits(tiles[0]);
+        } else {
+            build_forward_tiles(H, want, kTileShortRow, tile_lattice, &ftset);
+            ok = ftset_own = fits(ftset);
+        }
+        for (int32_t rows = want / 2; !ok && rows >= 16; rows /= 2) {
+            build_forward_tiles(H, rows, kTileShortRow, tile_lattice, &ftset);
             ok = fits(ftset);
             ftset_own = ok;
         }
@@ -1491,6 +1519,21 @@ extern "C" ilu_status ilu_set_tuning(ilu_handle h, const char *key, int64_t valu
         if (value < 16 || value > 65536) return fail(ILU_ERR_ARG, "ilu_set_tuning: tile_rows must be in [16, 65536]");
         return h->make_tiles((int32_t)value, false);
     }
+    if (k == "factor_tile_rows") {
+        if (value != 0 && (value < 16 || value > 65536))
+            return fail(ILU_ERR_ARG, "ilu_set_tuning: factor_tile_rows must be 0 or in [16, 65536]");
+        if (!h->host_only) {
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) return hip_fail(e, "factor tiles: synchronize");
+        }
+        h->factor_rows = (int32_t)value;
+        return h->make_factor_tiles();
+    }
+    if (k == "tile_lattice") {
+        if (value != 0 && value != 1) return fail(ILU_ERR_ARG, "ilu_set_tuning: tile_lattice must be 0 or 1");
+        h->tile_lattice = value != 0;
+        return h->make_tiles(h->tile_rows, false);
+    }
     if (k == "factor_lower_stage") {
         if (value != 0 && value != 1) return fail(ILU_ERR_ARG, "ilu_set_tuning: factor_lower_stage must be 0 or 1");
         h->factor_lower = value != 0;
@@ -1539,6 +1582,11 @@ extern "C" ilu_status ilu_get_tuning(ilu_handle h, const char *key, int64_t *val
     if (k == "nstreams") { *value = h->nstreams; return ILU_OK; }
     if (k == "factor_tcap") { *value = h->factor_tcap; return ILU_OK; }
     if (k == "tile_rows") { *value = h->tile_rows; return ILU_OK; }
+    if (k == "tile_lattice") { *value = h->tiles_on_lattice ? 1 : 0; return ILU_OK; }
+    if (k == "factor_tile_rows") {
+        *value = !h->ftiles_ok ? 0 : h->ftset_own ? h->ftset.cap : h->tile_rows;
+        return ILU_OK;
+    }
     if (k == "solve_blocks_per_cu") { *value = h->solve_bpc; return ILU_OK; }
     if (k == "spmv_nz") { *value = (h->spmv_nz && h->nz_waves > 0) ? 1 : 0; return ILU_OK; }
     if (k == "factor_lower_stage") { *value = h->factor_lower ? 1 : 0; return ILU_OK; }

@@ -92,6 +92,9 @@ struct ilu_handle_s {
     jv::TileSet tiles[2];
     std::vector<int32_t> sci;
     int32_t tile_rows = 0;             // rows per tile of the current tiles
+    bool tile_lattice = true;          // box tiles on structured grids (else greedy growth)
+    int32_t factor_rows = 0;           // rows per tile of the tiled factor (0: the solves' size)
+    bool tiles_on_lattice = false;     // the current tiles are lattice boxes
     bool pattern_sym = false;          // factor pattern symmetric: the transposed views (adjoint)
                                        // have the same rows and columns and use the same tiles
     struct DevTiles {

@@ -1,18 +1,34 @@
-// Tiles of the triangular solves: greedy topological growth (host).
+// Tiles of the triangular solves (host).
 //
 // The sync-free solve pays one global-memory hop (publish, then a poll on
 // another compute unit) for every dependency on its critical path.  Grouping rows
 // into tiles that one workgroup solves lets the dependencies inside a tile go
-// through LDS instead.  Tiles are grown by Kahn's algorithm on the direction's
-// dependency graph: the next row placed is the ready row with the most
-// dependencies already in the open tile (ties: lower level, then lower index),
-// or, when no ready row touches the open tile, the ready row of lowest level.  A
-// tile closes at `cap` rows.  Placement order is topological, so tile order is
-// too, which is what the kernel's start-ordered tile claims need to be free of
-// deadlock.  On grids in natural order the tiles come out as compact blocks
-// (cubes of side 8 or 16 for cap 512 or 4096 on 3D 7-point stencils) without any
-// coordinate information.
+// through LDS instead.  Two ways of forming tiles:
+//
+// - Lattice boxes.  When the matrix is a 2D or 3D structured grid in natural
+//   order (every factor entry joins rows whose grid coordinates differ by at most
+//   kLatR per axis, the extents read off the index offsets), each direction's
+//   dependency vectors are taken in grid coordinates and a unimodular basis of
+//   small integer functionals is chosen that no dependency decreases.  Tiles are
+//   the boxes of that basis (sides of powers of two, `cap` lattice points), so a
+//   dependency between two tiles never goes from a later box coordinate to an
+//   earlier one, and tiles are ordered by the sum of their box coordinates (a
+//   wavefront order).  For ILU(0) on a 7-point grid the basis is the axes and the
+//   tiles are cubes; the fill of ILU(1) adds dependencies such as (x+1, y-1) that
+//   make axis-aligned cubes depend on each other in cycles, and the basis becomes
+//   the sheared one (z, y+z, x+y+z).
+// - Greedy growth, for every other matrix: Kahn's algorithm on the direction's
+//   dependency graph, the next row placed being the ready row with the most
+//   dependencies already in the open tile (ties: lower level, then lower index),
+//   or, when no ready row touches the open tile, the ready row of lowest level.  A
+//   tile closes at `cap` rows.
+//
+// Either way tile order is topological, which is what the kernels' start-ordered
+// tile claims need to be free of deadlock.
 #include <algorithm>
+#include <array>
+#include <climits>
+#include <cstdlib>
 #include <cstdint>
 #include <cstring>
 #include <queue>
@@ -25,21 +41,237 @@ namespace jv {
 
 namespace {
 
-void tiles_one(const HostAnalysis &H, int dir, int32_t cap, int32_t short_row, TileSet *T, std::vector<int32_t> *sci) {
+// Structured-grid view of the input ordering: row i sits at x = i mod e0,
+// y = (i / e0) mod e1, z = i / (e0 e1) (dim 2: y = i / e0, z = 0).
+struct Lattice {
+    int dim = 0;
+    int64_t e0 = 0, e1 = 1;
+};
+
+constexpr int kLatR = 3;           // largest per-axis coordinate difference of a factor entry
+constexpr int kLatMaxOffsets = 48; // more distinct index offsets in L: not a grid
+constexpr int kLatF = 2;           // basis functionals take coefficients in [-kLatF, kLatF]
+
+inline void lat_coords(const Lattice &L, int64_t i, int64_t c[3]) {
+    c[0] = i % L.e0;
+    if (L.dim == 2) {
+        c[1] = i / L.e0;
+        c[2] = 0;
+    } else {
+        c[1] = (i / L.e0) % L.e1;
+        c[2] = i / (L.e0 * L.e1);
+    }
+}
+
+// every offset is a + b e0 + c e0 e1 with |a|, |b|, |c| <= kLatR
+bool lat_offsets_fit(const std::vector<int64_t> &D, int dim, int64_t e0, int64_t e01) {
+    for (int64_t o : D) {
+        bool ok = false;
+        for (int c = dim == 3 ? -kLatR : 0; c <= (dim == 3 ? kLatR : 0) && !ok; ++c)
+            for (int b = -kLatR; b <= kLatR && !ok; ++b) {
+                const int64_t a = o - b * e0 - c * e01;
+                ok = a >= -kLatR && a <= kLatR;
+            }
+        if (!ok) return false;
+    }
+    return true;
+}
+
+// Every off-diagonal factor entry joins rows at most kLatR apart on each axis.
+bool lat_valid(const HostAnalysis &H, const Lattice &L) {
+    for (int32_t q = 0; q < H.n; ++q) {
+        int64_t a[3], b[3];
+        lat_coords(L, H.perm[q], a);
+        for (int32_t p = H.lu_rp[q]; p < H.lu_rp[q + 1]; ++p) {
+            lat_coords(L, H.perm[H.lu_ci[p]], b);
+            for (int k = 0; k < 3; ++k)
+                if (a[k] - b[k] > kLatR || b[k] - a[k] > kLatR) return false;
+        }
+    }
+    return true;
+}
+
+// Grid extents from the distinct index offsets of L's entries (input ordering):
+// the x extent is an offset give or take kLatR, the xy extent likewise a large
+// offset minus small multiples of the x extent.  Every extent must exceed
+// 2 kLatR + 1, so that a dependency wrapping around an axis cannot pass the
+// check.  Returns false when no candidate fits every entry.
+bool detect_lattice(const HostAnalysis &H, Lattice *out) {
+    const int64_t n = H.n;
+    std::vector<int64_t> D;
+    for (int32_t q = 0; q < H.n; ++q) {
+        const int64_t r = H.perm[q];
+        for (int32_t p = H.lu_rp[q]; p < H.diag[q]; ++p) {
+            const int64_t o = r - H.perm[H.lu_ci[p]];
+            if (o <= 0) return false;   // not in natural order
+            if (std::find(D.begin(), D.end(), o) == D.end()) {
+                if ((int)D.size() == kLatMaxOffsets) return false;
+                D.push_back(o);
+            }
+        }
+    }
+    if (D.empty()) return false;
+    std::sort(D.begin(), D.end());
+    const int64_t emin = 2 * kLatR + 2;
+    std::vector<std::pair<int64_t, int64_t>> tried;
+    for (int dim = 3; dim >= 2; --dim)
+        for (int64_t o : D)
+            for (int d0 = -kLatR; d0 <= kLatR; ++d0) {
+                const int64_t e0 = o + d0;
+                if (e0 < emin) continue;
+                for (int64_t o2 : dim == 3 ? D : std::vector<int64_t>{0})
+                    for (int b = dim == 3 ? -kLatR : 0; b <= (dim == 3 ? kLatR : 0); ++b)
+                        for (int a = dim == 3 ? -kLatR : 0; a <= (dim == 3 ? kLatR : 0); ++a) {
+                            const int64_t e01 = dim == 3 ? o2 - b * e0 - a : n;
+                            if (e01 % e0 != 0 || e01 / e0 < emin || n % e01 != 0 || n / e01 < (dim == 3 ? emin : 1))
+                                continue;
+                            if (dim == 2 && n / e0 < emin) continue;
+                            const std::pair<int64_t, int64_t> key{e0, dim == 3 ? e01 : 0};
+                            if (std::find(tried.begin(), tried.end(), key) != tried.end()) continue;
+                            tried.push_back(key);
+                            if (!lat_offsets_fit(D, dim, e0, e01)) continue;
+                            Lattice L;
+                            L.dim = dim;
+                            L.e0 = e0;
+                            L.e1 = dim == 3 ? e01 / e0 : n / e0;
+                            if (lat_valid(H, L)) {
+                                *out = L;
+                                return true;
+                            }
+                        }
+            }
+    return false;
+}
+
+int64_t gcd64(int64_t a, int64_t b) {
+    a = a < 0 ? -a : a;
+    b = b < 0 ? -b : b;
+    while (b) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// Box tiles of one direction on a lattice.  Fills tile_of and order (rows by
+// tile, in a topological order of the direction inside each tile); returns the
+// tile count, or 0 when no basis of small functionals fits the dependencies.
+int32_t lattice_tiles(const HostAnalysis &H, const Lattice &L, int dir, int32_t cap, const std::vector<int32_t> &lev,
+                      std::vector<int32_t> &tile_of, std::vector<int32_t> &order) {
+    const int32_t n = H.n;
+    const int dim = L.dim;
+    // dependency vectors (row minus dependency, grid coordinates)
+    std::vector<std::array<int64_t, 3>> V;
+    for (int32_t q = 0; q < n; ++q) {
+        int64_t a[3], b[3];
+        lat_coords(L, H.perm[q], a);
+        const int32_t p0 = dir == 0 ? H.lu_rp[q] : H.diag[q] + 1, p1 = dir == 0 ? H.diag[q] : H.lu_rp[q + 1];
+        for (int32_t p = p0; p < p1; ++p) {
+            lat_coords(L, H.perm[H.lu_ci[p]], b);
+            const std::array<int64_t, 3> u{a[0] - b[0], a[1] - b[1], a[2] - b[2]};
+            if (std::find(V.begin(), V.end(), u) == V.end()) V.push_back(u);
+        }
+    }
+    // admissible functionals: primitive, no dependency decreases them; cheapest first
+    std::vector<std::array<int64_t, 3>> F;
+    const int hi2 = dim == 3 ? kLatF : 0;
+    for (int f2 = -hi2; f2 <= hi2; ++f2)
+        for (int f1 = -kLatF; f1 <= kLatF; ++f1)
+            for (int f0 = -kLatF; f0 <= kLatF; ++f0) {
+                if (gcd64(gcd64(f0, f1), f2) != 1) continue;
+                bool ok = true;
+                for (const auto &u : V) ok = ok && f0 * u[0] + f1 * u[1] + f2 * u[2] >= 0;
+                if (ok) F.push_back({f0, f1, f2});
+            }
+    auto cost = [](const std::array<int64_t, 3> &f) { return std::abs(f[0]) + std::abs(f[1]) + std::abs(f[2]); };
+    std::stable_sort(F.begin(), F.end(), [&](const auto &x, const auto &y) { return cost(x) < cost(y); });
+    int best[3] = {-1, -1, -1};
+    int64_t best_cost = -1;
+    const int nf = (int)F.size();
+    for (int i = 0; i < nf; ++i)
+        for (int j = i + 1; j < nf; ++j) {
+            if (dim == 2) {
+                const int64_t det = F[i][0] * F[j][1] - F[i][1] * F[j][0];
+                const int64_t c = cost(F[i]) + cost(F[j]);
+                if ((det == 1 || det == -1) && (best_cost < 0 || c < best_cost)) {
+                    best_cost = c;
+                    best[0] = i;
+                    best[1] = j;
+                }
+                continue;
+            }
+            for (int k = j + 1; k < nf; ++k) {
+                const auto &x = F[i], &y = F[j], &z = F[k];
+                const int64_t det = x[0] * (y[1] * z[2] - y[2] * z[1]) - x[1] * (y[0] * z[2] - y[2] * z[0]) +
+                                    x[2] * (y[0] * z[1] - y[1] * z[0]);
+                const int64_t c = cost(x) + cost(y) + cost(z);
+                if ((det == 1 || det == -1) && (best_cost < 0 || c < best_cost)) {
+                    best_cost = c;
+                    best[0] = i;
+                    best[1] = j;
+                    best[2] = k;
+                }
+            }
+        }
+    if (best_cost < 0) return 0;
+    // box sides: powers of two, as even as possible, product at most cap
+    int64_t side[3] = {1, 1, 1}, prod = 1;
+    for (int i = 0; prod * 2 <= cap; ++i) {
+        side[i % dim] *= 2;
+        prod *= 2;
+    }
+    // box coordinates of every row
+    std::vector<int64_t> g((size_t)n * dim);
+    int64_t gmin[3] = {INT64_MAX, INT64_MAX, INT64_MAX};
+    for (int32_t q = 0; q < n; ++q) {
+        int64_t a[3];
+        lat_coords(L, H.perm[q], a);
+        for (int i = 0; i < dim; ++i) {
+            const auto &f = F[best[i]];
+            const int64_t v = f[0] * a[0] + f[1] * a[1] + f[2] * a[2];
+            g[(size_t)q * dim + i] = v;
+            gmin[i] = std::min(gmin[i], v);
+        }
+    }
+    int64_t nb[3] = {1, 1, 1};
+    for (int32_t q = 0; q < n; ++q)
+        for (int i = 0; i < dim; ++i) {
+            int64_t &v = g[(size_t)q * dim + i];
+            v = (v - gmin[i]) / side[i];
+            nb[i] = std::max(nb[i], v + 1);
+        }
+    // wavefront order of boxes: sum of box coordinates, then the coordinates
+    std::vector<int64_t> key(n);
+    for (int32_t q = 0; q < n; ++q) {
+        int64_t s = 0, k = 0;
+        for (int i = 0; i < dim; ++i) {
+            s += g[(size_t)q * dim + i];
+            k = k * nb[i] + g[(size_t)q * dim + i];
+        }
+        key[q] = s * nb[0] * nb[1] * nb[2] + k;
+    }
+    std::vector<int64_t> keys(key);
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    for (int32_t q = 0; q < n; ++q)
+        tile_of[q] = (int32_t)(std::lower_bound(keys.begin(), keys.end(), key[q]) - keys.begin());
+    order.resize(n);
+    for (int32_t q = 0; q < n; ++q) order[q] = q;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return tile_of[x] != tile_of[y] ? tile_of[x] < tile_of[y] : lev[x] < lev[y];
+    });
+    return (int32_t)keys.size();
+}
+
+// Greedy growth (see the file comment).  Fills tile_of and order (placement
+// order, topological) and returns the tile count.
+int32_t greedy_tiles(const HostAnalysis &H, int dir, int32_t cap, const std::vector<int32_t> &lev,
+                     std::vector<int32_t> &tile_of, std::vector<int32_t> &order) {
     const int32_t n = H.n;
     const std::vector<int32_t> &rp = H.lu_rp, &ci = H.lu_ci, &dg = H.diag;
     auto dbeg = [&](int32_t r) { return dir == 0 ? rp[r] : dg[r] + 1; };
     auto dend = [&](int32_t r) { return dir == 0 ? dg[r] : rp[r + 1]; };
-
-    // level of every row in this direction
-    std::vector<int32_t> lev(n, 0);
-    if (dir == 0) {
-        for (int32_t l = 0; l < H.n_levels; ++l)
-            for (int32_t q = H.level_ptr[l]; q < H.level_ptr[l + 1]; ++q) lev[q] = l;
-    } else {
-        for (int32_t l = 0; l < H.n_ulevels; ++l)
-            for (int32_t q = H.ulevel_ptr[l]; q < H.ulevel_ptr[l + 1]; ++q) lev[H.ulevel_rows[q]] = l;
-    }
     // successor lists
     std::vector<int32_t> sp(n + 1, 0), indeg(n, 0);
     for (int32_t r = 0; r < n; ++r) {
@@ -55,8 +287,9 @@ void tiles_one(const HostAnalysis &H, int dir, int32_t cap, int32_t short_row, T
     std::priority_queue<Seed, std::vector<Seed>, std::greater<Seed>> seed;
     using Hot = std::tuple<int32_t, int32_t, int32_t>;              // (score, -level, -row), largest first
     std::priority_queue<Hot> hot;
-    std::vector<int32_t> score(n, 0), touched, tile_of(n, -1), order;
+    std::vector<int32_t> score(n, 0), touched;
     std::vector<char> placed(n, 0);
+    order.clear();
     order.reserve(n);
     for (int32_t r = 0; r < n; ++r)
         if (indeg[r] == 0) seed.push({lev[r], r});
@@ -96,7 +329,28 @@ void tiles_one(const HostAnalysis &H, int dir, int32_t cap, int32_t short_row, T
             hot = std::priority_queue<Hot>();
         }
     }
-    const int32_t ntiles = cur + (size > 0 ? 1 : 0);
+    return cur + (size > 0 ? 1 : 0);
+}
+
+void tiles_one(const HostAnalysis &H, int dir, int32_t cap, int32_t short_row, const Lattice *lat, TileSet *T,
+               std::vector<int32_t> *sci) {
+    const int32_t n = H.n;
+    const std::vector<int32_t> &rp = H.lu_rp, &ci = H.lu_ci, &dg = H.diag;
+    auto dbeg = [&](int32_t r) { return dir == 0 ? rp[r] : dg[r] + 1; };
+    auto dend = [&](int32_t r) { return dir == 0 ? dg[r] : rp[r + 1]; };
+
+    // level of every row in this direction
+    std::vector<int32_t> lev(n, 0);
+    if (dir == 0) {
+        for (int32_t l = 0; l < H.n_levels; ++l)
+            for (int32_t q = H.level_ptr[l]; q < H.level_ptr[l + 1]; ++q) lev[q] = l;
+    } else {
+        for (int32_t l = 0; l < H.n_ulevels; ++l)
+            for (int32_t q = H.ulevel_ptr[l]; q < H.ulevel_ptr[l + 1]; ++q) lev[H.ulevel_rows[q]] = l;
+    }
+    std::vector<int32_t> tile_of(n, -1), order;
+    int32_t ntiles = lat ? lattice_tiles(H, *lat, dir, cap, lev, tile_of, order) : 0;
+    if (ntiles == 0) ntiles = greedy_tiles(H, dir, cap, lev, tile_of, order);
 
     // local levels (placement order is topological)
     std::vector<int32_t> llev(n, 0);
@@ -169,16 +423,21 @@ void tiles_one(const HostAnalysis &H, int dir, int32_t cap, int32_t short_row, T
 
 }  // namespace
 
-void build_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, TileSet *fwd, TileSet *bwd,
+bool build_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, bool lattice, TileSet *fwd, TileSet *bwd,
                  std::vector<int32_t> *sci) {
     sci->assign(H.lu_ci.size(), -1);
-    tiles_one(H, 0, cap, short_row, fwd, sci);
-    tiles_one(H, 1, cap, short_row, bwd, sci);
+    Lattice L;
+    const bool lat = lattice && detect_lattice(H, &L);
+    tiles_one(H, 0, cap, short_row, lat ? &L : nullptr, fwd, sci);
+    tiles_one(H, 1, cap, short_row, lat ? &L : nullptr, bwd, sci);
+    return lat;
 }
 
-void build_forward_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, TileSet *fwd) {
+void build_forward_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, bool lattice, TileSet *fwd) {
     std::vector<int32_t> sci(H.lu_ci.size(), -1);
-    tiles_one(H, 0, cap, short_row, fwd, &sci);
+    Lattice L;
+    const bool lat = lattice && detect_lattice(H, &L);
+    tiles_one(H, 0, cap, short_row, lat ? &L : nullptr, fwd, &sci);
 }
 
 namespace {

@@ -1030,6 +1030,37 @@ def test_apply_tiled_blocks_per_cu_same_bits(jv):
         ilu.set_tuning("solve_blocks_per_cu", 9)
 
 
+@pytest.mark.parametrize("name,mk,k,tau,tile_rows", [
+    ("convdiff3d_14_ilu1_tau", lambda: synth.convdiff3d(14), 1, 1e-3, 512),
+    ("convdiff3d_17_ilu1", lambda: synth.convdiff3d(17), 1, 0.0, 128),
+    ("laplace3d_20x12x9_ilu2", lambda: synth.laplace3d(20, 12, 9), 2, 0.0, 256),
+    ("laplace2d_50", lambda: synth.laplace2d(50), 0, 0.0, 256),
+], ids=["convdiff3d_14_ilu1_tau", "convdiff3d_17_ilu1", "laplace3d_20x12x9_ilu2", "laplace2d_50"])
+def test_lattice_tiles_same_bits(jv, name, mk, k, tau, tile_rows):
+    # box tiles of a grid (sheared once fill appears) against the greedy tiles: the
+    # tiled factor is bit-exact with the oracle on both, and the tiled applies give
+    # the same bits, FP64 and FP32
+    A = mk()
+    ilu = make(jv, A, k, True, ("tiled", "tiled"), tile_rows=tile_rows)
+    assert ilu.get_tuning("tile_lattice") == 1 and ilu.get_tuning("factor_tiled") == 1
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k)
+    f = O.factor(an, A.val, k=k, tau=tau)
+    b = np.random.default_rng(31).uniform(-1, 1, A.n)
+    xr = O.apply(an, f.val, b)
+    out = {}
+    for lat in (1, 0):
+        ilu.set_tuning("tile_lattice", lat)
+        assert ilu.get_tuning("tile_lattice") == lat
+        ilu.factor(dev(A.val), k=k, tau=tau)
+        lu, st = ilu.factor_values()
+        np.testing.assert_array_equal(st, f.stat)
+        assert np.array_equal(lu.view(np.uint64), f.val.view(np.uint64))
+        out[lat] = {p: ilu.apply(dev(b), prec=p).cpu().numpy() for p in ("f64", "f32")}
+    assert relerr(out[1]["f64"], xr) <= 1e-12
+    for p in ("f64", "f32"):
+        assert np.array_equal(out[1][p].view(np.uint64), out[0][p].view(np.uint64))
+
+
 @pytest.mark.parametrize("tile_rows", [16, 100, 512])
 @pytest.mark.parametrize("name,mk,k,sym", [
     ("laplace3d_20", lambda: synth.laplace3d(20), 0, True),

@@ -249,6 +249,78 @@ def test_tiles_are_cubes_on_grids():
                 assert len(o) == t and all(len(np.unique(c)) == 1 for c in coords)
 
 
+@pytest.mark.parametrize("name,mk,k,ordering,on", [
+    ("laplace3d_16", lambda: synth.laplace3d(16), 0, "natural", 1),
+    ("convdiff3d_12_ilu1", lambda: synth.convdiff3d(12), 1, "natural", 1),
+    ("laplace2d_30", lambda: synth.laplace2d(30), 0, "natural", 1),
+    ("laplace3d_16x10x9", lambda: synth.laplace3d(16, 10, 9), 2, "natural", 1),
+    ("laplace3d_6_too_small", lambda: synth.laplace3d(6), 0, "natural", 0),
+    ("laplace3d_16_rcm", lambda: synth.laplace3d(16), 0, "rcm", 0),
+    ("random_1500", lambda: synth.random_banded(1500, rng=np.random.default_rng(21)), 0, "natural", 0),
+    ("tridiag_200", lambda: synth.tridiag(200), 0, "natural", 0),
+], ids=lambda v: v if isinstance(v, str) else "")
+def test_lattice_tiles_detection(name, mk, k, ordering, on):
+    # box tiles only where the factor pattern is a grid stencil in natural order with
+    # every extent above 7; everything else keeps the greedy growth
+    A = mk()
+    h = jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=k, host_only=True, tile_rows=128, ordering=ordering)
+    assert h.get_tuning("tile_lattice") == on
+    _check_tiles(h, A.n)
+    if on:
+        h.set_tuning("tile_lattice", 0)
+        assert h.get_tuning("tile_lattice") == 0
+        _check_tiles(h, A.n)
+        h.set_tuning("tile_lattice", 1)
+        assert h.get_tuning("tile_lattice") == 1
+    with pytest.raises(jv.IluError):
+        h.set_tuning("tile_lattice", 2)
+
+
+def test_lattice_tiles_sheared_boxes_ilu1():
+    # ILU(1) on a 7-point grid makes row (x, y, z) depend on (x+1, y-1, z),
+    # (x+1, y, z-1) and (x, y+1, z-1) besides its three lower neighbours: no dependency
+    # decreases z, y+z or x+y+z, and the tiles are 8 x 8 x 8 boxes of those three
+    # functionals (clipped by the grid), taken in wavefront order
+    m = 16
+    A = synth.convdiff3d(m)
+    h = jv.Ilu(A.n, A.row_ptr, A.col_idx, k_max=1, host_only=True, tile_rows=512)
+    assert h.get_tuning("tile_lattice") == 1
+    perm = h.schedule()["perm"]
+    for d in (0, 1):
+        ptr, row, _ = h.tiles(d)
+        total = 0
+        for t in range(len(ptr) - 1):
+            o = perm[row[ptr[t]:ptr[t + 1]][row[ptr[t]:ptr[t + 1]] >= 0]]
+            x, y, z = o % m, (o // m) % m, o // (m * m)
+            total += len(o)
+            for f in (z, y + z, x + y + z):
+                assert np.ptp(f) < 8
+        assert total == A.n
+    # 3D 7-point ILU(0) at 512 rows: the boxes are the axis-aligned 8^3 cubes
+    A = synth.laplace3d(m)
+    h = jv.Ilu(A.n, A.row_ptr, A.col_idx, host_only=True, tile_rows=512)
+    assert h.get_tuning("tile_lattice") == 1 and len(h.tiles(0)[0]) - 1 == 8
+
+
+def test_factor_tile_rows_default_and_key():
+    # the tiled factor's tiles shrink with the update work per row: 512 rows for
+    # ILU(0) on a 7-point grid, 128 for ILU(1) (about four times the work per row)
+    A = synth.laplace3d(16)
+    h = jv.Ilu(A.n, A.row_ptr, A.col_idx, host_only=True)
+    assert h.get_tuning("tile_rows") == 512 and h.get_tuning("factor_tile_rows") == 512
+    C = synth.convdiff3d(24)
+    hc = jv.Ilu(C.n, C.row_ptr, C.col_idx, k_max=1, host_only=True)
+    assert hc.get_tuning("tile_rows") == 512 and hc.get_tuning("factor_tile_rows") == 128
+    for fr, want in ((256, 256), (64, 64), (0, 128)):
+        hc.set_tuning("factor_tile_rows", fr)
+        assert hc.get_tuning("factor_tile_rows") == want and hc.get_tuning("factor_tiled") == 1
+    # the solves' tiles do not move
+    assert hc.get_tuning("tile_rows") == 512 and hc.info()["n_tiles"] == len(hc.tiles(0)[0]) - 1
+    for bad in (8, 70000, -1):
+        with pytest.raises(jv.IluError):
+            hc.set_tuning("factor_tile_rows", bad)
+
+
 def test_tiles_default_fits_and_retile():
     A = synth.laplace3d(10)
     h = jv.Ilu(A.n, A.row_ptr, A.col_idx, host_only=True)
