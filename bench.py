@@ -234,8 +234,10 @@ def main():
         stage[name] = ilu.profile_read()
 
     # per-call distributions, warm and cold (the 256 MB MALL flushed by a 1 GiB
-    # write before each call): p10 / median / p90 of 20 calls; the factor and apply
-    # entries are whole calls (every kernel they launch)
+    # write before each call), and cold_clean (flushed by a 1 GiB read instead, so
+    # the call does not also pay for writing back the flush's dirty lines): p10 /
+    # median / p90 of 20 calls; the factor and apply entries are whole calls (every
+    # kernel they launch)
     flush = torch.zeros(1 << 28, dtype=torch.float32, device="cuda")
     dist = {}
     for name, fn, keys in (("factor_call", lambda: ilu.factor(a_d, casts=("f32",)), ("factor_call",)),
@@ -244,11 +246,13 @@ def main():
                            ("apply_f64_kernels", lambda: ilu.apply(bp_d, x=x_d, permuted=True),
                             ("forward", "backward")),
                            ("spmv", lambda: ilu.spmv(bp_d, y=y_d, permuted=True), ("spmv",))):
-        for mode in ("warm", "cold"):
+        for mode in ("warm", "cold", "cold_clean"):
             vals = []
             for _ in range(20):
                 if mode == "cold":
                     flush.add_(1.0)
+                elif mode == "cold_clean":
+                    flush.sum()
                 torch.cuda.synchronize()
                 ilu.profile_read()
                 fn()
@@ -389,7 +393,8 @@ def main():
                         apply_f64=round(B64["apply"] / t_apply64 / 1e6, 1),
                         apply_f32=round(B32["apply"] / t_apply32 / 1e6, 1),
                         spmv=round(B64["spmv"] / t_spmv / 1e6, 1),
-                        spmv_cold=round(B64["spmv"] / dist["spmv"]["cold"][1] / 1e3, 1)),
+                        spmv_cold=round(B64["spmv"] / dist["spmv"]["cold"][1] / 1e3, 1),
+                        spmv_cold_clean=round(B64["spmv"] / dist["spmv"]["cold_clean"][1] / 1e3, 1)),
         rows_per_s=dict(factor=round(n / (t_factor_call * 1e-3), 1)),
         calls_us_p10_p50_p90=dist,
         pcg=pcg,

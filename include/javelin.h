@@ -422,7 +422,12 @@ ilu_status ilu_get_schedule(ilu_handle h, int32_t *factor_sched, int32_t *solve_
  * row) in nnz-balanced waves -- 16 consecutive entries per lane, row segments
  * added across lanes by a segmented scan and across waves by a second kernel, in a
  * fixed order -- instead of a lane group per row and one wave per long row; on by
- * default when a row exceeds 4096 entries.  "force_abort" (set only;
+ * default when a row exceeds 4096 entries.  "spmv_lanes" (1, 4, 8, 16, 32 or 64;
+ * readable): lanes per row of the spmv's row pass; 1 takes one row per lane with
+ * its entries loaded eight at a time, all in flight together (the default for rows
+ * averaging at most 8 entries), otherwise a lane group per row with a butterfly sum
+ * (default: half the mean row length rounded up to a power of two, at least 4);
+ * same products, summed in another order.  "force_abort" (set only;
  * failure-path tests): 1 raises the device abort flag now, as an apply that timed
  * out and was not yet reported leaves it; 2 raises it inside the next apply, after
  * that apply's guard, so its kernels leave through their bounded waits (outputs

@@ -606,8 +606,10 @@ static ilu_status finish_analysis(ilu_handle_s *h) {
     h->factor_tcap = (int32_t)std::min<int64_t>(tcap, 1 << 20);
     h->lanes_factor = pow2_lanes(H.max_row_lu, 4, 64);
     h->lanes_solve = pow2_lanes(std::max(H.max_lower_lu, H.max_upper_lu), 4, 64);
-    // spmv: rows longer than one wave go to a one-wave-per-row pass; the lanes of the
-    // rest follow their mean length
+    // spmv: rows longer than one wave go to a one-wave-per-row pass; the rest take one
+    // lane per row when they average at most 8 entries (every load of a row in
+    // flight at once), else a lane group of half their mean length, rounded up to a
+    // power of two (two entries per lane)
     {
         constexpr int32_t kHeavy = 64;
         std::vector<int32_t> heavy;
@@ -618,7 +620,8 @@ static ilu_status finish_analysis(ilu_handle_s *h) {
             else light_nnz += len;
         }
         const int64_t light_rows = std::max<int64_t>(1, H.n - (int64_t)heavy.size());
-        h->lanes_spmv = pow2_lanes((int)std::max<int64_t>(1, (light_nnz + light_rows - 1) / light_rows), 4, 64);
+        const int64_t mean = std::max<int64_t>(1, (light_nnz + light_rows - 1) / light_rows);
+        h->lanes_spmv = mean <= 8 ? 1 : std::max(4, pow2_lanes((int)mean, 4, 64) / 2);
         if (!heavy.empty()) {
             UPLOAD_ONE(h->d_spmv_heavy, heavy);
             h->n_spmv_heavy = (int32_t)heavy.size();
@@ -1519,6 +1522,12 @@ extern "C" ilu_status ilu_set_tuning(ilu_handle h, const char *key, int64_t valu
         if (value < 16 || value > 65536) return fail(ILU_ERR_ARG, "ilu_set_tuning: tile_rows must be in [16, 65536]");
         return h->make_tiles((int32_t)value, false);
     }
+    if (k == "spmv_lanes") {
+        if (value != 1 && value != 4 && value != 8 && value != 16 && value != 32 && value != 64)
+            return fail(ILU_ERR_ARG, "ilu_set_tuning: spmv_lanes must be 1, 4, 8, 16, 32 or 64");
+        h->lanes_spmv = (int32_t)value;
+        return ILU_OK;
+    }
     if (k == "factor_tile_rows") {
         if (value != 0 && (value < 16 || value > 65536))
             return fail(ILU_ERR_ARG, "ilu_set_tuning: factor_tile_rows must be 0 or in [16, 65536]");
@@ -1583,6 +1592,7 @@ extern "C" ilu_status ilu_get_tuning(ilu_handle h, const char *key, int64_t *val
     if (k == "factor_tcap") { *value = h->factor_tcap; return ILU_OK; }
     if (k == "tile_rows") { *value = h->tile_rows; return ILU_OK; }
     if (k == "tile_lattice") { *value = h->tiles_on_lattice ? 1 : 0; return ILU_OK; }
+    if (k == "spmv_lanes") { *value = h->lanes_spmv; return ILU_OK; }
     if (k == "factor_tile_rows") {
         *value = !h->ftiles_ok ? 0 : h->ftset_own ? h->ftset.cap : h->tile_rows;
         return ILU_OK;

@@ -2309,6 +2309,48 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpmvArgs A) {
     }
 }
 
+// One row per lane, for short rows: the lane loads its row's column indices and
+// values eight at a time, all at once, then the x entries they name, so every load
+// of a row is in flight together and a wave covers 64 rows; entries are added in
+// column-position order.
+template <bool PERM>
+__global__ __launch_bounds__(kBlock) void k_spmv_lane(SpmvArgs A) {
+    constexpr int K = 8;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= A.n) return;
+    const int rs = A.rp[r], re = A.rp[r + 1];
+    if (re - rs > A.heavy_min) return;   // a long row: the one-wave pass takes it
+    const int yr = PERM ? A.perm[r] : r;
+    for (int s = 0; s < A.nrhs; ++s) {
+        double acc = 0.0;
+        for (int b = rs; b < re; b += K) {
+            int c[K];
+            double v[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                if (b + j < re) {
+                    c[j] = A.ci[b + j];
+                    v[j] = A.val[b + j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                if (b + j < re) {
+                    const int cc = PERM ? A.perm[c[j]] : c[j];
+                    const double prod = v[j] * A.x[(int64_t)cc * A.ld + s];
+                    acc = acc + prod;
+                }
+            }
+        }
+        double out = A.alpha * acc;
+        if (A.beta != 0.0) {
+            const double by = A.beta * A.y[(int64_t)yr * A.ld + s];
+            out = out + by;
+        }
+        A.y[(int64_t)yr * A.ld + s] = out;
+    }
+}
+
 // ---------------------------------------------------------------------------------
 // Adjoint outer products restricted to the factor pattern, one row per 8 lanes
 // ---------------------------------------------------------------------------------
@@ -2965,6 +3007,13 @@ hipError_t launch_spmv(const SpmvArgs &A, int lanes, hipStream_t s) {
         return hipGetLastError();
     }
     switch (lanes) {
+        case 1: {
+            dim3 g(grid_for((int64_t)A.n, kBlock));
+            if (A.perm) hipLaunchKernelGGL((k_spmv_lane<true>), g, dim3(kBlock), 0, s, A);
+            else hipLaunchKernelGGL((k_spmv_lane<false>), g, dim3(kBlock), 0, s, A);
+            e = hipGetLastError();
+            break;
+        }
         case 4: e = spmv_dispatch<4>(A, s); break;
         case 8: e = spmv_dispatch<8>(A, s); break;
         case 16: e = spmv_dispatch<16>(A, s); break;

@@ -523,6 +523,38 @@ def test_spmv(jv, name, mk, k, tau):
     assert np.array_equal(ilu.spmv(dev(xi)).cpu().numpy(), O.spmv(A.n, A.row_ptr, A.col_idx, Ai, xi))
 
 
+@pytest.mark.parametrize("name,mk,default", [
+    ("laplace3d_20", lambda: synth.laplace3d(20), 1),
+    ("random_sparse_ragged", lambda: synth.random_sparse(333, 0.05, np.random.default_rng(6)), 16),
+    ("heavy_3000_short_and_long", lambda: synth.heavy_rows(3000, heavy_len=(65, 200), heavy_frac=0.05,
+                                                           rng=np.random.default_rng(32)), 1),
+], ids=lambda v: v if isinstance(v, str) else "")
+def test_spmv_lanes_every_setting(jv, name, mk, default):
+    # one row per lane (rows averaging at most 8 entries; longer rows in batches of
+    # 8) and every lane-group size: the oracle's products to rounding, several
+    # right-hand sides, alpha and beta, both orderings; long rows still go to the
+    # one-wave pass
+    A = mk()
+    rng = np.random.default_rng(41)
+    ilu = jv.Ilu(A.n, A.row_ptr, A.col_idx)
+    ilu.set_values(dev(A.val))
+    assert ilu.get_tuning("spmv_lanes") == default
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    x3 = rng.uniform(-1, 1, (A.n, 3))
+    y0 = rng.uniform(-1, 1, (A.n, 3))
+    yr = O.spmv(A.n, A.row_ptr, A.col_idx, A.val, x3)
+    xp = rng.uniform(-1, 1, A.n)
+    yp = O.spmv(A.n, an.b_rp, an.b_ci, O.b_values(an, A.val), xp)
+    for lanes in (1, 4, 8, 16, 32, 64):
+        ilu.set_tuning("spmv_lanes", lanes)
+        assert relerr(ilu.spmv(dev(x3)).cpu().numpy(), yr) <= 1e-12
+        got = ilu.spmv(dev(x3), y=dev(y0), alpha=2.0, beta=-0.5).cpu().numpy()
+        assert relerr(got, 2.0 * yr - 0.5 * y0) <= 1e-12
+        assert relerr(ilu.spmv(dev(xp), permuted=True).cpu().numpy(), yp) <= 1e-12
+    with pytest.raises(jv.IluError):
+        ilu.set_tuning("spmv_lanes", 2)
+
+
 @pytest.mark.parametrize("name,mk", [
     ("heavy_6000_rows_over_waves", lambda: synth.heavy_rows(6000, heavy_len=(900, 3500), heavy_frac=0.02,
                                                             rng=np.random.default_rng(31))),
