@@ -581,7 +581,7 @@ static ilu_status finish_analysis(ilu_handle_s *h) {
     if ((e = h->alloc_bytes(&p, kInfoSlots * 4)) != hipSuccess) return hip_fail(e, "alloc info");
     h->d_info = (int32_t *)p;
     if ((e = hipMemset(h->d_info, 0, kInfoSlots * 4)) != hipSuccess) return hip_fail(e, "zero info");
-    if ((e = h->alloc_bytes(&p, kDotParts * 8 + 64 * 8)) != hipSuccess) return hip_fail(e, "alloc dot work");
+    if ((e = h->alloc_bytes(&p, kDotWorkBytes)) != hipSuccess) return hip_fail(e, "alloc dot work");
     h->d_dotwork = (double *)p;
     const size_t cbytes = (size_t)kPasses * kStreams * kCounterStride * 4;
     if ((e = h->alloc_bytes(&p, cbytes)) != hipSuccess) return hip_fail(e, "alloc counters");

@@ -38,7 +38,7 @@ __global__ __launch_bounds__(kBlock) void k_dot_partial(int64_t n, const double 
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// out = scale * sum(part); mode 1 stores sqrt of the sum instead
+// out = sum(part); mode 1 stores sqrt of the sum instead
 __global__ __launch_bounds__(kBlock) void k_dot_final(int nparts, const double *__restrict__ part, double *out,
                                                       int mode) {
     double acc = 0.0;
@@ -47,17 +47,25 @@ __global__ __launch_bounds__(kBlock) void k_dot_final(int nparts, const double *
     if (threadIdx.x == 0) *out = mode == 1 ? sqrt(s) : s;
 }
 
-// y += (sign * num / den) * x, with num / den read from device memory (den may be null)
-__global__ __launch_bounds__(kBlock) void k_axpy_dev(int64_t n, const double *num, const double *den, double sign,
-                                                     const double *__restrict__ x, double *__restrict__ y) {
-    double a = *num;
-    if (den) a = a / *den;
-    a = sign * a;
+// One modified Gram-Schmidt step fused with the next one's dot: y += (sign * *num)
+// * x, then the partials of y . z for the updated y (z may be y itself), on the
+// dot's grid, so k_dot_final gives the bits of a separate dot after the update
+__global__ __launch_bounds__(kBlock) void k_axpy_dot(int64_t n, const double *num, double sign,
+                                                     const double *__restrict__ x, double *y, const double *z,
+                                                     double *__restrict__ part) {
+    const double a = sign * *num;
+    const bool self = z == y;
+    double acc = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
         const double t = a * x[i];
-        y[i] = y[i] + t;
+        const double yn = y[i] + t;
+        y[i] = yn;
+        const double p = yn * (self ? yn : z[i]);
+        acc = acc + p;
     }
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 // y = x + (num / den) * y
@@ -71,18 +79,27 @@ __global__ __launch_bounds__(kBlock) void k_xpby_dev(int64_t n, const double *nu
     }
 }
 
-// PCG step: alpha = rz / pq; x += alpha p; r -= alpha q
-__global__ __launch_bounds__(kBlock) void k_pcg_xr(int64_t n, const double *rz, const double *pq,
-                                                   const double *__restrict__ p, const double *__restrict__ q,
-                                                   double *__restrict__ x, double *__restrict__ r) {
+// PCG step: alpha = rz / pq; x += alpha p; r -= alpha q; with the partials of
+// r . r (the new r) on the dot's grid, so k_dot_final gives the bits of a separate
+// dot of r with itself
+__global__ __launch_bounds__(kBlock) void k_pcg_xr_rr(int64_t n, const double *rz, const double *pq,
+                                                      const double *__restrict__ p, const double *__restrict__ q,
+                                                      double *__restrict__ x, double *__restrict__ r,
+                                                      double *__restrict__ part) {
     const double alpha = *rz / *pq;
+    double acc = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
         const double tp = alpha * p[i];
         x[i] = x[i] + tp;
         const double tq = alpha * q[i];
-        r[i] = r[i] - tq;
+        const double rn = r[i] - tq;
+        r[i] = rn;
+        const double sq = rn * rn;
+        acc = acc + sq;
     }
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 // y = x * (1 / s) with s read from device memory; leaves y untouched if s == 0
@@ -150,9 +167,10 @@ hipError_t blas_dot(int64_t n, const double *x, const double *y, double *out, do
     return hipGetLastError();
 }
 
-hipError_t blas_axpy_dev(int64_t n, const double *num, const double *den, double sign, const double *x, double *y,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(k_axpy_dev, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, num, den, sign, x, y);
+hipError_t blas_axpy_dot(int64_t n, const double *num, double sign, const double *x, double *y, const double *z,
+                         double *out, double *work, hipStream_t s, int sqrt_mode) {
+    hipLaunchKernelGGL(k_axpy_dot, dim3(kDotParts), dim3(kBlock), 0, s, n, num, sign, x, y, z, work);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kBlock), 0, s, kDotParts, work, out, sqrt_mode);
     return hipGetLastError();
 }
 
@@ -162,9 +180,10 @@ hipError_t blas_xpby_dev(int64_t n, const double *num, const double *den, const 
     return hipGetLastError();
 }
 
-hipError_t blas_pcg_xr(int64_t n, const double *rz, const double *pq, const double *p, const double *q, double *x,
-                       double *r, hipStream_t s) {
-    hipLaunchKernelGGL(k_pcg_xr, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, rz, pq, p, q, x, r);
+hipError_t blas_pcg_xr_rr(int64_t n, const double *rz, const double *pq, const double *p, const double *q, double *x,
+                          double *r, double *rr, double *work, hipStream_t s) {
+    hipLaunchKernelGGL(k_pcg_xr_rr, dim3(kDotParts), dim3(kBlock), 0, s, n, rz, pq, p, q, x, r, work);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(kBlock), 0, s, kDotParts, work, rr, 0);
     return hipGetLastError();
 }
 

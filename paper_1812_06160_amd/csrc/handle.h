@@ -68,7 +68,7 @@ struct ilu_handle_s {
     uint16_t *d_lu16 = nullptr;
     int8_t *d_stat = nullptr;
     int32_t *d_info = nullptr;
-    double *d_dotwork = nullptr;     // kDotParts partials + 64 scalar slots
+    double *d_dotwork = nullptr;     // dot work area: kDotParts partials, kDotScalars scalar slots
 
     // published solve intermediates [n][cap], kept "all pending" between calls
     int cap64 = 0, cap32 = 0;

@@ -175,8 +175,7 @@ extern "C" ilu_status ilu_solve_pcg(ilu_handle h, const double *b, double *x, do
             while (I.iters < maxit) {
                 CHK(spmv(c, 1.0, p, 0.0, q));
                 HCHK(blas_dot(n, p, q, &S[3], c.work, s), "pcg dot");
-                HCHK(blas_pcg_xr(n, &S[cur], &S[3], p, q, xp, r, s), "pcg update");
-                HCHK(blas_dot(n, r, r, &S[4], c.work, s), "pcg dot");
+                HCHK(blas_pcg_xr_rr(n, &S[cur], &S[3], p, q, xp, r, &S[4], c.work, s), "pcg update");
                 CHK(post_readback(c, &S[3], 2));
                 // The next direction needs only device data: queue it before the host
                 // wait.  When the test below stops the loop, x and r are already final
@@ -240,7 +239,7 @@ extern "C" ilu_status ilu_solve_gmres(ilu_handle h, const double *b, double *x, 
     double *bp = h->d_kry, *xp = bp + n, *w = xp + n, *V = w + n, *Z = V + (size_t)n * (m + 1);
     Ctx c{h, n, fac_prec, s, h->d_dotwork + kDotParts, h->d_dotwork};
     double *S = c.scal;  // 0..m: current Hessenberg column, m+1: beta, m+2..: y coefficients (<= 30)
-    if (m + 2 + m > 64) return fail(ILU_ERR_ARG, "gmres: restart too large for the scalar area");
+    if (m + 2 + m > kDotScalars) return fail(ILU_ERR_ARG, "gmres: restart too large for the scalar area");
     if (flags & ILU_PERMUTED_SPACE) HCHK(hipMemcpyAsync(bp, b, n * 8, hipMemcpyDeviceToDevice, s), "gmres copy");
     else HCHK(blas_permute(n, h->d_perm, b, bp, 0, s), "gmres permute");
     HCHK(hipMemsetAsync(xp, 0, n * 8, s), "gmres zero");
@@ -281,12 +280,15 @@ extern "C" ilu_status ilu_solve_gmres(ilu_handle h, const double *b, double *x, 
                     CHK(apply(c, vj, zj));
                     CHK(spmv(c, 1.0, zj, 0.0, w));
                 }
-                for (int i = 0; i <= j; ++i) {   // modified Gram-Schmidt
+                // modified Gram-Schmidt: each step's update fused with the next
+                // step's dot (the last one with the norm)
+                HCHK(blas_dot(n, w, V, &S[0], c.work, s), "gmres dot");
+                for (int i = 0; i <= j; ++i) {
                     double *vi = V + (size_t)i * n;
-                    HCHK(blas_dot(n, w, vi, &S[i], c.work, s), "gmres dot");
-                    HCHK(blas_axpy_dev(n, &S[i], nullptr, -1.0, vi, w, s), "gmres axpy");
+                    const bool last = i == j;
+                    HCHK(blas_axpy_dot(n, &S[i], -1.0, vi, w, last ? w : vi + n, &S[i + 1], c.work, s, last ? 1 : 0),
+                         "gmres orthogonalisation");
                 }
-                HCHK(blas_dot(n, w, w, &S[j + 1], c.work, s, 1), "gmres norm");
                 HCHK(blas_scale_inv_dev(n, &S[j + 1], w, V + (size_t)(j + 1) * n, s), "gmres scale");
                 CHK(post_readback(c, S, j + 2));
                 // The next Arnoldi step's apply and spmv need only v_{j+1}: queue them
