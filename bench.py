@@ -42,11 +42,11 @@ HBM_PEAK_GBS = 8000.0
 # scaled by what the same counters read for the calibration copy kernels.  Valid
 # only for the kernel source it was taken with: a different hash reports null.
 PMC_TRAFFIC = dict(
-    kernels_sha256="5fe46c138a7265daab942f82aebb069138bad60ba2da20f1fcd3825b9eef1a3f",
-    fetch_scale=1.9988, write_scale=0.9943,
-    forward=dict(f64=(197325, 66082), f32=(160067, 50874)),
-    backward=dict(f64=(196338, 93590), f32=(150919, 77568)),
-    factor=(218870, 337879),
+    kernels_sha256="c6dbd0da594b7ddef98eb472e211bf4b515bb86fd4a8788bbc6ee5512f133dbe",
+    fetch_scale=1.9986, write_scale=0.9944,
+    forward=dict(f64=(206981, 56426), f32=(176864, 43436)),
+    backward=dict(f64=(195612, 81617), f32=(150258, 66371)),
+    factor=(217370, 323572),
 )
 
 
