@@ -441,18 +441,20 @@ ilu_status ilu_get_tuning(ilu_handle h, const char *key, int64_t *value);
  * fastest: level launches and sync-free launches with 1x and 2x the lanes per row
  * the rows need, and tiled launches at tile sizes 128, 256, 512 and 1024 rows (and
  * the current size).  The tile size is the level-merge threshold (a tile merges
- * consecutive levels of up to that many rows into one workgroup); one tiling serves
- * both stages, chosen by the apply.  The factor is re-run with the last call's k,
+ * consecutive levels of up to that many rows into one workgroup); the apply chooses
+ * the tiling, and the tiled factor then has its own tile size timed
+ * ("factor_tile_rows": its default and 64 .. 1024 rows).  The factor is re-run with the last call's k,
  * tau and flags, so the handle keeps the same factor (every schedule gives the same
  * bits).  The apply also tries the lower stage (tail_min_rows 64, or the handle's
  * own value) and keeps it if faster; with that tail in place and a plan for it, the
  * factor's lower stage ("factor_lower_stage") is timed against the chosen factor
- * schedule.  When the matrix has rows longer than 64
- * entries and no empty row, the spmv's nnz-balanced pass is timed against the
- * row-per-group pass ("spmv_nz") and the faster kept.  Requires a factor.
- * Synchronous.  results (may be NULL) receives up to `cap` rows of {stage (0
- * factor, 1 apply, 2 spmv), sched (10: lower stage; 20 spmv by rows, 21 spmv
- * nnz-balanced), lanes or tile rows (tiled) or tail_min_rows (lower stage),
+ * schedule.  The spmv's row pass is timed at 1, 4, 8, 16, 32 and 64 lanes per row
+ * ("spmv_lanes"); when the matrix has rows longer than 64 entries and no empty
+ * row, its nnz-balanced pass is timed as well ("spmv_nz"); the fastest is kept.
+ * Requires a factor.  Synchronous.  results (may be NULL) receives up to `cap`
+ * rows of {stage (0 factor, 1 apply, 2 spmv), sched (10: lower stage; 11: tiled
+ * factor at its own tile size; 20 spmv by rows, 21 spmv nnz-balanced), lanes or
+ * tile rows (tiled, 11) or tail_min_rows (lower stage) or spmv lanes (20),
  * microseconds} as doubles; *n_results the row count. */
 ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, double *results, int32_t cap,
                     int32_t *n_results, hipStream_t stream);

@@ -6,13 +6,14 @@
 // level-merge threshold: a tile merges consecutive levels of up to that many rows
 // into one workgroup whose dependencies go through LDS.  The apply also tries the
 // lower stage (narrow levels at the end of each direction streamed by one
-// workgroup, levels of fewer than 64 rows or the handle's own threshold).  One tiling serves the
-// factor and the solves, so the apply -- called many times per factor -- picks
-// it; the factor then picks its scheme with that tiling in place.  Every
+// workgroup, levels of fewer than 64 rows or the handle's own threshold).  The
+// apply -- called many times per factor -- picks the tiling; the tiled factor then
+// has its own tile size timed (its default, by update work per row, and 64 to 1024
+// rows) before its scheme is picked.  Every
 // schedule computes the same bits (the factor reproduces the serial up-looking
 // order on all of them), so re-running the caller's factor -- same k, tau and
-// flags -- leaves the handle with the factor it had.  With long rows, the spmv's
-// nnz-balanced pass is timed against the row-per-group pass as well.
+// flags -- leaves the handle with the factor it had.  The spmv's lanes per row
+// are timed too, and with long rows its nnz-balanced pass.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -58,6 +59,7 @@ extern "C" ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, 
     const int32_t save_fs = h->sched_factor, save_ss = h->sched_solve;
     const int32_t save_lf = h->lanes_factor, save_ls = h->lanes_solve;
     const int32_t save_tr = h->tile_rows;
+    const int32_t save_fr = h->factor_rows;
     // the caller's factor: same k, tau and flags (casts, modified form)
     const int32_t k = h->k_used;
     const double tau = h->tau_used;
@@ -85,6 +87,10 @@ extern "C" ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, 
         h->sched_solve = save_ss;
         h->lanes_factor = save_lf;
         h->lanes_solve = save_ls;
+        if (h->factor_rows != save_fr) {
+            h->factor_rows = save_fr;
+            if (h->tile_rows == save_tr) (void)h->make_factor_tiles();
+        }
         if (h->tile_rows != save_tr) (void)h->make_tiles(save_tr, false);
         return st;
     };
@@ -189,7 +195,8 @@ extern "C" ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, 
         ilu_status st = h->make_tiles(best_tr, false);
         if (st != ILU_OK) return restore(st);
     }
-    // ---- factor: tiled on the chosen tiling vs sync-free and level launches ----
+    // ---- factor: tiled on the chosen tiling (its own tile size searched) vs
+    // sync-free and level launches ----
     if (a_val) {
         double best = 1e300;
         int best_fs = save_fs, best_lf = save_lf;
@@ -198,6 +205,33 @@ extern "C" ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, 
                 best = r.factor_us;
                 best_fs = ILU_SCHED_TILED;
             }
+        if (best_fs == ILU_SCHED_TILED) {
+            // the tiled factor's tile size: the default (by update work per row) and
+            // 64 .. 1024 rows, each size timed once
+            int32_t best_fr = h->factor_rows;
+            std::vector<int32_t> seen;
+            for (int32_t fr : {0, 64, 128, 256, 512, 1024}) {
+                if (fr > std::max<int32_t>(H.n, 16)) continue;
+                h->factor_rows = fr;
+                ilu_status st = h->make_factor_tiles();
+                if (st != ILU_OK) return restore(st);
+                if (!h->ftiles_ok) continue;
+                const int32_t used = h->ftset_own ? h->ftset.cap : h->tile_rows;
+                if (std::find(seen.begin(), seen.end(), used) != seen.end()) continue;
+                seen.push_back(used);
+                h->sched_factor = ILU_SCHED_TILED;
+                double us = 0;
+                if ((st = time_it(factor, &us)) != ILU_OK) return restore(st);
+                rows.insert(rows.end(), {0.0, 11.0, (double)used, us});
+                if (us < best) {
+                    best = us;
+                    best_fr = fr;
+                }
+            }
+            h->factor_rows = best_fr;
+            ilu_status st = h->make_factor_tiles();
+            if (st != ILU_OK) return restore(st);
+        }
         const int lmin = std::max(4, std::min(save_lf, 64));
         for (int sched = ILU_SCHED_LEVEL; sched <= ILU_SCHED_SYNCFREE; ++sched)
             for (int lanes = lmin; lanes <= 64 && lanes <= 2 * lmin; lanes *= 2) {
@@ -233,25 +267,41 @@ extern "C" ilu_status ilu_tune(ilu_handle h, const double *a_val, int32_t reps, 
         ilu_status st = factor();
         if (st != ILU_OK) return restore(st);
     }
-    // ---- spmv: the nnz-balanced pass against the row-per-group pass, when built ----
-    if (h->nz_waves > 0 && h->bvals) {
+    // ---- spmv: lanes per row of the row pass, then the nnz-balanced pass when built ----
+    if (h->bvals) {
         auto spmv = [&]() { return ilu_spmv(h, 1.0, b, 0.0, x, 1, 1, ILU_PERMUTED_SPACE, s); };
         const bool save_nz = h->spmv_nz;
+        const int32_t save_lsp = h->lanes_spmv;
+        h->spmv_nz = false;
         double best = 1e300;
-        bool best_nz = save_nz;
-        for (int nz = 0; nz <= 1; ++nz) {
-            h->spmv_nz = nz != 0;
+        int32_t best_l = save_lsp;
+        for (int32_t lanes : {1, 4, 8, 16, 32, 64}) {
+            h->lanes_spmv = lanes;
+            double us = 0;
+            ilu_status st = time_it(spmv, &us);
+            if (st != ILU_OK) {
+                h->spmv_nz = save_nz;
+                h->lanes_spmv = save_lsp;
+                return restore(st);
+            }
+            rows.insert(rows.end(), {2.0, 20.0, (double)lanes, us});
+            if (us < best) {
+                best = us;
+                best_l = lanes;
+            }
+        }
+        h->lanes_spmv = best_l;
+        bool best_nz = false;
+        if (h->nz_waves > 0) {
+            h->spmv_nz = true;
             double us = 0;
             ilu_status st = time_it(spmv, &us);
             if (st != ILU_OK) {
                 h->spmv_nz = save_nz;
                 return restore(st);
             }
-            rows.insert(rows.end(), {2.0, nz ? 21.0 : 20.0, 0.0, us});
-            if (us < best) {
-                best = us;
-                best_nz = nz != 0;
-            }
+            rows.insert(rows.end(), {2.0, 21.0, 0.0, us});
+            best_nz = us < best;
         }
         h->spmv_nz = best_nz;
     }

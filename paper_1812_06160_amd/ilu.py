@@ -298,9 +298,9 @@ class Ilu:
         return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(L.STAGES)}
 
     def tune(self, a_val=None, reps=3):
-        res = np.zeros((64, 4), np.float64)
+        res = np.zeros((128, 4), np.float64)
         nres = C.c_int32()
-        L.check(self.lib.ilu_tune(self.h, _ptr(a_val), int(reps), _np_ptr(res), 64, C.byref(nres), _stream()),
+        L.check(self.lib.ilu_tune(self.h, _ptr(a_val), int(reps), _np_ptr(res), 128, C.byref(nres), _stream()),
                 "ilu_tune")
         return res[:nres.value], self.get_schedule()
 

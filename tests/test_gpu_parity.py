@@ -610,7 +610,8 @@ def test_spmv_nnz_balanced_default_and_tuned(jv):
     ilu.factor(dev(B.val))
     res, _ = ilu.tune(dev(B.val), reps=2)
     spmv_rows = res[res[:, 0] == 2]
-    assert sorted(spmv_rows[:, 1].tolist()) == [20.0, 21.0]
+    assert sorted(spmv_rows[spmv_rows[:, 1] == 20.0][:, 2].astype(int).tolist()) == [1, 4, 8, 16, 32, 64]
+    assert (spmv_rows[:, 1] == 21.0).sum() == 1 and set(spmv_rows[:, 1].tolist()) == {20.0, 21.0}
     assert ilu.get_tuning("spmv_nz") == int(spmv_rows[np.argmin(spmv_rows[:, 3]), 1] == 21.0)
     xb = np.random.default_rng(37).uniform(-1, 1, B.n)
     assert relerr(ilu.spmv(dev(xb)).cpu().numpy(), O.spmv(B.n, B.row_ptr, B.col_idx, B.val, xb)) <= 1e-12
@@ -806,6 +807,14 @@ def test_tune_no_slower_and_same_factor(jv, name, mk, k, tau, milu):
     res, chosen = ilu.tune(a, reps=3)
     assert (res[:, 1] == 3).any(), "tiled candidates were timed"
     assert {128, 256, 512} <= set(res[res[:, 1] == 3][:, 2].astype(int))
+    # the tiled factor's own tile size, when the tiled factor runs on the chosen tiling
+    ft = res[(res[:, 0] == 0) & (res[:, 1] == 11)]
+    if len(ft):
+        assert len(set(ft[:, 2].astype(int))) == len(ft) and ilu.get_tuning("factor_tiled") == 1
+    # the spmv's lanes per row: every setting timed, the fastest kept
+    sp = res[(res[:, 0] == 2) & (res[:, 1] == 20)]
+    assert sorted(sp[:, 2].astype(int).tolist()) == [1, 4, 8, 16, 32, 64]
+    assert ilu.get_tuning("spmv_lanes") == int(sp[np.argmin(sp[:, 3]), 2])
     an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=k)
     f = O.factor(an, A.val, k=k, tau=tau, milu=milu)
     lu, st = ilu.factor_values()
