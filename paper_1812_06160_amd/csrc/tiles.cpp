@@ -32,6 +32,7 @@
 #include <cstdint>
 #include <cstring>
 #include <queue>
+#include <set>
 #include <tuple>
 #include <vector>
 
@@ -113,7 +114,7 @@ bool detect_lattice(const HostAnalysis &H, Lattice *out) {
     if (D.empty()) return false;
     std::sort(D.begin(), D.end());
     const int64_t emin = 2 * kLatR + 2;
-    std::vector<std::pair<int64_t, int64_t>> tried;
+    std::set<std::pair<int64_t, int64_t>> tried;
     for (int dim = 3; dim >= 2; --dim)
         for (int64_t o : D)
             for (int d0 = -kLatR; d0 <= kLatR; ++d0) {
@@ -127,8 +128,7 @@ bool detect_lattice(const HostAnalysis &H, Lattice *out) {
                                 continue;
                             if (dim == 2 && n / e0 < emin) continue;
                             const std::pair<int64_t, int64_t> key{e0, dim == 3 ? e01 : 0};
-                            if (std::find(tried.begin(), tried.end(), key) != tried.end()) continue;
-                            tried.push_back(key);
+                            if (!tried.insert(key).second) continue;
                             if (!lat_offsets_fit(D, dim, e0, e01)) continue;
                             Lattice L;
                             L.dim = dim;
