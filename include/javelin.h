@@ -399,8 +399,8 @@ ilu_status ilu_get_schedule(ilu_handle h, int32_t *factor_sched, int32_t *solve_
  * greedy growth; same results either way; read back, 1 means the current tiles are
  * boxes, "factor_tile_rows" (0, the default, or 16..65536; rebuilds the tiled
  * factor's tiles only): rows per tile of the tiled factor; the default shrinks
- * the solves' size by halves until a tile carries about the update work of 512
- * rows of ILU(0) on a 7-point grid (ILU(1) there: 128 rows); halved further
+ * the solves' size by halves until a tile carries at most 8192 multiply-subtracts
+ * of updates (ILU(0) on a 7-point grid: 512 rows; ILU(1) there: 128 rows); halved further
  * while the tile image does not fit LDS; read back, the size in use (0: no tiled
  * factor), "factor_staged" (1, the default: the sync-free and level factors
  * gather a row's dependency rows into LDS when they fit; 0: each dependency row

@@ -284,9 +284,9 @@ static size_t default_tile_budget(const HostAnalysis &H) {
 // Default rows per tile of the tiled factor.  A tile's life is its rows' update
 // work (each L entry of a row subtracts the dependency row's U part), and the
 // factor runs fewer tiles at once than the solves, so tiles shrink from the
-// solves' size until they carry about as much of it as a 512-row tile of ILU(0) on
-// a 7-point grid (about 9 multiply-subtracts per row): ILU(1) on a 7-point grid
-// (about 36) gets 128-row tiles.
+// solves' size by halves until they carry at most 8192 multiply-subtracts: 512
+// rows for ILU(0) on a 7-point grid (about 9 per row), 128 for ILU(1) there
+// (about 36).
 static int32_t default_factor_rows(const HostAnalysis &H, int32_t tile_rows) {
     if (H.n == 0) return tile_rows;
     double work = 0.0;
@@ -296,8 +296,10 @@ static int32_t default_factor_rows(const HostAnalysis &H, int32_t tile_rows) {
             work += (double)(H.lu_rp[c + 1] - H.diag[c] - 1);
         }
     work /= H.n;
+    constexpr double kTileWork = 8192.0;   // multiply-subtracts per tile: a 512-row tile of 7-point
+                                           // ILU(0) does about 4600, one of ILU(1) about 18000
     int32_t rows = tile_rows;
-    while (rows > 64 && (double)rows * work > 16.0 * (double)tile_rows) rows /= 2;
+    while (rows > 64 && (double)rows * work > kTileWork) rows /= 2;
     return rows;
 }
 
