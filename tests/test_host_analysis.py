@@ -276,6 +276,31 @@ def test_lattice_tiles_detection(name, mk, k, ordering, on):
         h.set_tuning("tile_lattice", 2)
 
 
+def _with_extra_pairs(A, pairs):
+    # symmetric extra couplings (i, j) added to a CSR pattern
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    r = np.concatenate([rows] + [[i, j] for i, j in pairs])
+    c = np.concatenate([A.col_idx] + [[j, i] for i, j in pairs])
+    v = np.concatenate([A.val, np.full(2 * len(pairs), -0.01)])
+    return synth.csr_from_coo(A.n, r, c, v)
+
+
+def test_lattice_tiles_reject_non_grid_couplings():
+    # one long-range coupling breaks the grid reading (a factor entry joins rows far
+    # apart on an axis): the greedy growth takes over and the tiles stay valid; a
+    # coupling within the stencil's reach (a diagonal neighbour) keeps the boxes
+    m = 12
+    A = synth.laplace3d(m)
+    far = _with_extra_pairs(A, [(5 * m * m + 3, 5 * m * m + 3 + 6 * m + 7)])
+    h = jv.Ilu(far.n, far.row_ptr, far.col_idx, host_only=True, tile_rows=128)
+    assert h.get_tuning("tile_lattice") == 0
+    _check_tiles(h, far.n)
+    near = _with_extra_pairs(A, [(5 * m * m + 3 * m + 3, 5 * m * m + 4 * m + 4)])
+    h = jv.Ilu(near.n, near.row_ptr, near.col_idx, host_only=True, tile_rows=128)
+    assert h.get_tuning("tile_lattice") == 1
+    _check_tiles(h, near.n)
+
+
 def test_lattice_tiles_sheared_boxes_ilu1():
     # ILU(1) on a 7-point grid makes row (x, y, z) depend on (x+1, y-1, z),
     # (x+1, y, z-1) and (x, y+1, z-1) besides its three lower neighbours: no dependency
