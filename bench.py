@@ -44,9 +44,9 @@ HBM_PEAK_GBS = 8000.0
 PMC_TRAFFIC = dict(
     kernels_sha256="c6dbd0da594b7ddef98eb472e211bf4b515bb86fd4a8788bbc6ee5512f133dbe",
     fetch_scale=1.9986, write_scale=0.9944,
-    forward=dict(f64=(206981, 56426), f32=(176864, 43436)),
-    backward=dict(f64=(195612, 81617), f32=(150258, 66371)),
-    factor=(217370, 323572),
+    forward=dict(f64=(194165, 51157), f32=(166217, 37773)),
+    backward=dict(f64=(193308, 81933), f32=(151189, 66715)),
+    factor=(217397, 323584),
 )
 
 

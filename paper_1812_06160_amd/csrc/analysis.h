@@ -81,9 +81,10 @@ struct TileSet {
 // rows have at most short_row dependencies is padded to chunks of 64 positions
 // (one lane per row), otherwise to chunks of 16 (four lanes per row).  With
 // `lattice`, a matrix recognised as a structured grid in natural order gets box
-// tiles (returns true), any other the greedy growth.
-bool build_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, bool lattice, TileSet *fwd, TileSet *bwd,
-                 std::vector<int32_t> *sci);
+// tiles (returns the grid's dimension, 2 or 3), any other the greedy growth
+// (returns 0).
+int build_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, bool lattice, TileSet *fwd, TileSet *bwd,
+                std::vector<int32_t> *sci);
 
 // Forward tiles only (a tiling of its own for the factor when the solves' tiles
 // are too large for its LDS image).

@@ -316,10 +316,28 @@ static std::vector<int16_t> position_slots(const TileSet &T) {
 ilu_status ilu_handle_s::make_tiles(int32_t rows, bool shrink) {
     try {
         const size_t budget = default_tile_budget(H);
+        int dim = 0;
         for (;;) {
-            tiles_on_lattice = build_tiles(H, rows, kTileShortRow, tile_lattice, &tiles[0], &tiles[1], &sci);
+            dim = build_tiles(H, rows, kTileShortRow, tile_lattice, &tiles[0], &tiles[1], &sci);
             if (!shrink || rows <= 16 || (tiles_fit(tiles[0], budget) && tiles_fit(tiles[1], budget))) break;
             rows /= 2;
+        }
+        tiles_on_lattice = dim > 0;
+        // 3D grid boxes: the default size doubled (fewer crossings on the critical
+        // path of both solves) when two such tiles still fit a CU's LDS, the number
+        // the solves keep resident by default, and the grid still makes a tile per
+        // CU and more
+        if (shrink && dim == 3 && rows == kDefaultTileRows && (int64_t)H.n >= 256 * 2 * (int64_t)rows) {
+            const size_t budget2 = std::max(budget, (size_t)kTileLdsMax / 2);
+            TileSet t0, t1;
+            std::vector<int32_t> sci2;
+            if (build_tiles(H, 2 * rows, kTileShortRow, tile_lattice, &t0, &t1, &sci2) == 3 &&
+                tiles_fit(t0, budget2) && tiles_fit(t1, budget2)) {
+                tiles[0] = std::move(t0);
+                tiles[1] = std::move(t1);
+                sci = std::move(sci2);
+                rows *= 2;
+            }
         }
     } catch (const std::bad_alloc &) {
         return fail(ILU_ERR_NOMEM, "tiles: out of host memory");

@@ -423,14 +423,14 @@ void tiles_one(const HostAnalysis &H, int dir, int32_t cap, int32_t short_row, c
 
 }  // namespace
 
-bool build_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, bool lattice, TileSet *fwd, TileSet *bwd,
-                 std::vector<int32_t> *sci) {
+int build_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, bool lattice, TileSet *fwd, TileSet *bwd,
+                std::vector<int32_t> *sci) {
     sci->assign(H.lu_ci.size(), -1);
     Lattice L;
     const bool lat = lattice && detect_lattice(H, &L);
     tiles_one(H, 0, cap, short_row, lat ? &L : nullptr, fwd, sci);
     tiles_one(H, 1, cap, short_row, lat ? &L : nullptr, bwd, sci);
-    return lat;
+    return lat ? L.dim : 0;
 }
 
 void build_forward_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, bool lattice, TileSet *fwd) {

@@ -344,6 +344,12 @@ def test_factor_tile_rows_default_and_key():
     for bad in (8, 70000, -1):
         with pytest.raises(jv.IluError):
             hc.set_tuning("factor_tile_rows", bad)
+    # a 3D grid of 256 or more 1024-row boxes: the solves take the doubled size
+    # (two tiles still fit a CU's LDS), the factor keeps 512-row tiles of its own
+    G = synth.laplace3d(64)
+    hg = jv.Ilu(G.n, G.row_ptr, G.col_idx, host_only=True)
+    assert hg.get_tuning("tile_rows") == 1024 and hg.get_tuning("factor_tile_rows") == 512
+    _check_tiles(hg, G.n)
 
 
 def test_tiles_default_fits_and_retile():
