@@ -91,7 +91,9 @@ typedef struct {
                                  planning without a device); numeric calls then fail with
                                  ILU_ERR_STATE */
     int32_t tile_rows;        /* rows per tile of the tiled solves (0 = default: 512, halved until a
-                                 tile fits the LDS budget; else 16..65536, used as given) */
+                                 tile fits the LDS budget, or doubled to 1024 on a 3D grid read as a
+                                 lattice when such a tile fits a CU's LDS and the grid makes 256 of
+                                 them; else 16..65536, used as given) */
     int32_t ordering;         /* ILU_ORDER_NATURAL (default: A as given) or ILU_ORDER_RCM */
     int32_t tail_min_rows;    /* lower stage of the triangular solves (Sec. III-B, "Lower Stage";
                                  Fig. 7): 0 = none; M > 0: in each direction the longest suffix of

@@ -324,11 +324,11 @@ ilu_status ilu_handle_s::make_tiles(int32_t rows, bool shrink) {
         }
         tiles_on_lattice = dim > 0;
         // 3D grid boxes: the default size doubled (fewer crossings on the critical
-        // path of both solves) when two such tiles still fit a CU's LDS, the number
-        // the solves keep resident by default, and the grid still makes a tile per
-        // CU and more
+        // path of both solves) when such a tile still fits a CU's LDS and the grid
+        // makes a tile per CU and more; measured faster on 7-point ILU(0), two tiles
+        // per CU, and on ILU(1), whose doubled tiles leave room for one
         if (shrink && dim == 3 && rows == kDefaultTileRows && (int64_t)H.n >= 256 * 2 * (int64_t)rows) {
-            const size_t budget2 = std::max(budget, (size_t)kTileLdsMax / 2);
+            const size_t budget2 = (size_t)kTileLdsMax;
             TileSet t0, t1;
             std::vector<int32_t> sci2;
             if (build_tiles(H, 2 * rows, kTileShortRow, tile_lattice, &t0, &t1, &sci2) == 3 &&
