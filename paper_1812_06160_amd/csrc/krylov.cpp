@@ -116,6 +116,15 @@ ilu_status readback(Ctx &c, const double *dev, double *host, int count) {
     return st == ILU_OK ? wait_readback(c, host, count) : st;
 }
 
+// Whether the step under test is likely not the last: its relative residual,
+// extrapolated from the last two by one geometric step, is still above rtol.  A
+// speculative apply queued on the last step is a whole apply spent for nothing,
+// which costs more than the host wait it hides when applies are long.
+bool likely_more(double rel0, double rel1, double rtol) {
+    const double pred = rel0 > 0.0 ? rel1 * (rel1 / rel0) : rel1;
+    return pred > rtol;
+}
+
 #define CHK(x)                          \
     do {                                \
         ilu_status st_ = (x);           \
@@ -166,6 +175,7 @@ extern "C" ilu_status ilu_solve_pcg(ilu_handle h, const double *b, double *x, do
         I.relres = I.true_relres = 0.0;
     } else {
         HCHK(hipMemcpyAsync(r, bp, n * 8, hipMemcpyDeviceToDevice, s), "pcg copy");
+        double rel0 = 1.0, rel1 = 1.0;   // the last two relative residuals
         for (;;) {
             bool converged = false;
             int cur = 1;   // slot of r.z for the current direction p
@@ -178,11 +188,12 @@ extern "C" ilu_status ilu_solve_pcg(ilu_handle h, const double *b, double *x, do
                 HCHK(blas_pcg_xr_rr(n, &S[cur], &S[3], p, q, xp, r, &S[4], c.work, s), "pcg update");
                 CHK(post_readback(c, &S[3], 2));
                 // The next direction needs only device data: queue it before the host
-                // wait.  When the test below stops the loop, x and r are already final
-                // and the speculative z, p and r.z are overwritten before any later use.
+                // wait, unless this step is likely the last.  When the test below stops
+                // the loop, x and r are already final and the speculative z, p and r.z
+                // are overwritten before any later use.
                 const int nxt = 3 - cur;
-                const bool more = I.iters + 1 < maxit;
-                if (more) {
+                const bool spec = I.iters + 1 < maxit && likely_more(rel0, rel1, rtol);
+                if (spec) {
                     CHK(apply(c, r, z));
                     HCHK(blas_dot(n, r, z, &S[nxt], c.work, s), "pcg dot");
                     HCHK(blas_xpby_dev(n, &S[nxt], &S[cur], z, p, s), "pcg p update");
@@ -197,6 +208,13 @@ extern "C" ilu_status ilu_solve_pcg(ilu_handle h, const double *b, double *x, do
                 if (I.relres <= rtol) {
                     converged = true;
                     break;
+                }
+                rel0 = rel1;
+                rel1 = I.relres;
+                if (!spec && I.iters < maxit) {
+                    CHK(apply(c, r, z));
+                    HCHK(blas_dot(n, r, z, &S[nxt], c.work, s), "pcg dot");
+                    HCHK(blas_xpby_dev(n, &S[nxt], &S[cur], z, p, s), "pcg p update");
                 }
                 cur = nxt;
             }
@@ -274,6 +292,7 @@ extern "C" ilu_status ilu_solve_gmres(ilu_handle h, const double *b, double *x, 
             int jend = -1;
             bool breakdown = false;
             bool queued = false;   // apply and spmv of step j already queued
+            double rel0 = I.true_relres, rel1 = I.true_relres;   // the last two relative residuals
             for (int j = 0; j < m && I.iters < maxit; ++j) {
                 double *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
                 if (!queued) {
@@ -292,9 +311,10 @@ extern "C" ilu_status ilu_solve_gmres(ilu_handle h, const double *b, double *x, 
                 HCHK(blas_scale_inv_dev(n, &S[j + 1], w, V + (size_t)(j + 1) * n, s), "gmres scale");
                 CHK(post_readback(c, S, j + 2));
                 // The next Arnoldi step's apply and spmv need only v_{j+1}: queue them
-                // before the host wait.  If the test below ends the cycle, their results
-                // (z_{j+1} and w) are overwritten before any later use.
-                queued = j + 1 < m && I.iters + 1 < maxit;
+                // before the host wait, unless this step is likely the last.  If the
+                // test below ends the cycle, their results (z_{j+1} and w) are
+                // overwritten before any later use.
+                queued = j + 1 < m && I.iters + 1 < maxit && likely_more(rel0, rel1, rtol);
                 if (queued) {
                     double *vn = V + (size_t)(j + 1) * n, *zn = Z + (size_t)(j + 1) * n;
                     CHK(apply(c, vn, zn));
@@ -322,6 +342,8 @@ extern "C" ilu_status ilu_solve_gmres(ilu_handle h, const double *b, double *x, 
                 I.relres = std::fabs(g[j + 1]) / bnorm;
                 breakdown = hb[j + 1] == 0.0;
                 if (I.relres <= rtol || breakdown) break;
+                rel0 = rel1;
+                rel1 = I.relres;
             }
             if (jend < 0) break;
             for (int i = jend; i >= 0; --i) {
