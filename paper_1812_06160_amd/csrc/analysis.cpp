@@ -7,6 +7,7 @@
 // or lower(S + S^T) (Sec. III); rows of a level keep their input order, so the
 // permutation is the stable sort by level.
 #include "analysis.h"
+#include "par.h"
 
 #include <algorithm>
 #include <cstring>
@@ -100,6 +101,8 @@ static ilu_status check_input(int32_t n, const int32_t *rp, const int32_t *ci, i
     }
     return ILU_OK;
 }
+
+static void transpose_and_schedules(HostAnalysis &H);
 
 static ilu_status analyze_natural(int32_t n, const int32_t *rp, const int32_t *ci, int64_t nnz, int32_t k_max,
                                   int32_t pattern, HostAnalysis *out, std::string *err) {
@@ -229,22 +232,28 @@ static ilu_status analyze_natural(int32_t n, const int32_t *rp, const int32_t *c
         osrc.resize(orp[n]);
         if (olev) olev->resize(orp[n]);
         if (odiag) odiag->assign(n, -1);
-        maxrow = 0;
-        std::vector<std::pair<int32_t, int32_t>> tmp;
-        for (int32_t r = 0; r < n; ++r) {
-            int32_t i = H.perm[r];
-            tmp.clear();
-            for (int32_t p = xrp[i]; p < xrp[i + 1]; ++p) tmp.emplace_back(H.iperm[xci[p]], p);
-            std::sort(tmp.begin(), tmp.end());
-            int32_t o = orp[r];
-            maxrow = std::max(maxrow, (int32_t)tmp.size());
-            for (size_t t = 0; t < tmp.size(); ++t) {
-                oci[o + t] = tmp[t].first;
-                osrc[o + t] = xsrc[tmp[t].second];
-                if (olev) (*olev)[o + t] = (*xlev)[tmp[t].second];
-                if (odiag && tmp[t].first == r) (*odiag)[r] = o + (int32_t)t;
+        // rows write disjoint ranges: chunks of rows run on their own threads
+        std::vector<int32_t> cmax(host_threads(), 0);
+        parallel_chunks(n, 1 << 14, [&](int c, int64_t lo, int64_t hi) {
+            std::vector<std::pair<int32_t, int32_t>> tmp;
+            int32_t m = 0;
+            for (int32_t r = (int32_t)lo; r < (int32_t)hi; ++r) {
+                int32_t i = H.perm[r];
+                tmp.clear();
+                for (int32_t p = xrp[i]; p < xrp[i + 1]; ++p) tmp.emplace_back(H.iperm[xci[p]], p);
+                std::sort(tmp.begin(), tmp.end());
+                int32_t o = orp[r];
+                m = std::max(m, (int32_t)tmp.size());
+                for (size_t t = 0; t < tmp.size(); ++t) {
+                    oci[o + t] = tmp[t].first;
+                    osrc[o + t] = xsrc[tmp[t].second];
+                    if (olev) (*olev)[o + t] = (*xlev)[tmp[t].second];
+                    if (odiag && tmp[t].first == r) (*odiag)[r] = o + (int32_t)t;
+                }
             }
-        }
+            cmax[c] = m;
+        });
+        maxrow = *std::max_element(cmax.begin(), cmax.end());
     };
     permute_rows(srp, sci, ssrc, &slev, H.lu_rp, H.lu_ci, H.lu_src, &H.flev, &H.diag, H.max_row_lu);
     for (int32_t r = 0; r < n; ++r) {
@@ -253,27 +262,36 @@ static ilu_status analyze_natural(int32_t n, const int32_t *rp, const int32_t *c
     }
     permute_rows(crp, cci, csrc, nullptr, H.b_rp, H.b_ci, H.b_src, nullptr, nullptr, H.max_row_b);
 
-    // every strictly lower factor entry must point to an earlier level (the
-    // schedule is valid); checked once here because the kernels rely on it
-    {
-        std::vector<int32_t> lvl_of(n);
-        for (int32_t l = 0; l < H.n_levels; ++l)
-            for (int32_t r = H.level_ptr[l]; r < H.level_ptr[l + 1]; ++r) lvl_of[r] = l;
-        for (int32_t r = 0; r < n; ++r)
-            for (int32_t p = H.lu_rp[r]; p < H.diag[r]; ++p)
-                if (lvl_of[H.lu_ci[p]] >= lvl_of[r]) { *err = "analyze: invalid level schedule (internal error)"; return ILU_ERR_ARG; }
-    }
+    // The check of the level schedule with the backward schedule, and the
+    // transposed structure with its two schedules, read only the factor
+    // structure and write disjoint fields: the two groups run side by side.
+    bool level_ok = true;
+    run_pair(
+        [&] {
+            // every strictly lower factor entry must point to an earlier level (the
+            // schedule is valid); checked once here because the kernels rely on it
+            std::vector<int32_t> lvl_of(n);
+            for (int32_t l = 0; l < H.n_levels; ++l)
+                for (int32_t r = H.level_ptr[l]; r < H.level_ptr[l + 1]; ++r) lvl_of[r] = l;
+            for (int32_t r = 0; r < n && level_ok; ++r)
+                for (int32_t p = H.lu_rp[r]; p < H.diag[r]; ++p)
+                    if (lvl_of[H.lu_ci[p]] >= lvl_of[r]) { level_ok = false; break; }
+            // ---- backward schedule: peel the upper dependencies from the last rows ----
+            std::vector<int64_t> sp;
+            std::vector<int32_t> succ, indeg;
+            triangular_deps(n, H.lu_rp, H.lu_ci, false, sp, succ, indeg);
+            H.n_ulevels = peel(n, sp, succ, indeg, H.ulevel_rows, H.ulevel_ptr, nullptr);
+        },
+        [&] { transpose_and_schedules(H); });
+    if (!level_ok) { *err = "analyze: invalid level schedule (internal error)"; return ILU_ERR_ARG; }
+    if (H.n_ulevels < 0) { *err = "analyze: upper schedule cycle (internal error)"; return ILU_ERR_ARG; }
+    if (H.n_tlevels < 0 || H.n_tulevels < 0) { *err = "analyze: transposed schedule cycle (internal error)"; return ILU_ERR_ARG; }
+    return ILU_OK;
+}
 
-    // ---- backward schedule: peel the upper dependencies from the last rows ----
-    {
-        std::vector<int64_t> sp;
-        std::vector<int32_t> succ, indeg;
-        triangular_deps(n, H.lu_rp, H.lu_ci, false, sp, succ, indeg);
-        H.n_ulevels = peel(n, sp, succ, indeg, H.ulevel_rows, H.ulevel_ptr, nullptr);
-        if (H.n_ulevels < 0) { *err = "analyze: upper schedule cycle (internal error)"; return ILU_ERR_ARG; }
-    }
-
-    // ---- transposed factor structure and its schedules (adjoint) ----
+// ---- transposed factor structure and its schedules (adjoint) ----
+static void transpose_and_schedules(HostAnalysis &H) {
+    const int32_t n = H.n;
     {
         const int64_t nz = H.lu_rp[n];
         H.t_rp.assign((size_t)n + 1, 0);
@@ -291,15 +309,20 @@ static ilu_status analyze_natural(int32_t n, const int32_t *rp, const int32_t *c
                 H.t_map[o] = p;
                 if (i == j) H.t_diag[j] = o;
             }
-        std::vector<int64_t> sp;
-        std::vector<int32_t> succ, indeg;
-        triangular_deps(n, H.t_rp, H.t_ci, true, sp, succ, indeg);
-        H.n_tlevels = peel(n, sp, succ, indeg, H.tlevel_rows, H.tlevel_ptr, nullptr);
-        triangular_deps(n, H.t_rp, H.t_ci, false, sp, succ, indeg);
-        H.n_tulevels = peel(n, sp, succ, indeg, H.tulevel_rows, H.tulevel_ptr, nullptr);
-        if (H.n_tlevels < 0 || H.n_tulevels < 0) { *err = "analyze: transposed schedule cycle (internal error)"; return ILU_ERR_ARG; }
+        run_pair(
+            [&] {
+                std::vector<int64_t> sp;
+                std::vector<int32_t> succ, indeg;
+                triangular_deps(n, H.t_rp, H.t_ci, true, sp, succ, indeg);
+                H.n_tlevels = peel(n, sp, succ, indeg, H.tlevel_rows, H.tlevel_ptr, nullptr);
+            },
+            [&] {
+                std::vector<int64_t> sp;
+                std::vector<int32_t> succ, indeg;
+                triangular_deps(n, H.t_rp, H.t_ci, false, sp, succ, indeg);
+                H.n_tulevels = peel(n, sp, succ, indeg, H.tulevel_rows, H.tulevel_ptr, nullptr);
+            });
     }
-    return ILU_OK;
 }
 
 

@@ -16,6 +16,7 @@
 #include "blas.h"
 #include "device.h"
 #include "handle.h"
+#include "par.h"
 #include "javelin.h"
 
 using namespace jv;
@@ -314,30 +315,36 @@ static std::vector<int16_t> position_slots(const TileSet &T) {
 }
 
 ilu_status ilu_handle_s::make_tiles(int32_t rows, bool shrink) {
+    spare_fwd = jv::TileSet();
     try {
         const size_t budget = default_tile_budget(H);
-        int dim = 0;
-        for (;;) {
-            dim = build_tiles(H, rows, kTileShortRow, tile_lattice, &tiles[0], &tiles[1], &sci);
+        // 3D grid boxes: the default size doubled (fewer crossings on the critical
+        // path of both solves) when such a tile still fits a CU's LDS and the grid
+        // makes a tile per CU and more; measured faster on 7-point ILU(0), two tiles
+        // per CU, and on ILU(1), whose doubled tiles leave room for one.  The
+        // doubled candidate is built beside the default one.
+        const bool try_double = shrink && rows == kDefaultTileRows && (int64_t)H.n >= 256 * 2 * (int64_t)rows;
+        TileSet t0, t1;
+        std::vector<int32_t> sci2;
+        int dim = 0, dim2 = 0;
+        for (bool first = true;; first = false) {
+            if (first && try_double)
+                run_pair([&] { dim = build_tiles(H, rows, kTileShortRow, tile_lattice, &tiles[0], &tiles[1], &sci); },
+                         [&] { dim2 = build_tiles(H, 2 * rows, kTileShortRow, tile_lattice, &t0, &t1, &sci2); });
+            else
+                dim = build_tiles(H, rows, kTileShortRow, tile_lattice, &tiles[0], &tiles[1], &sci);
             if (!shrink || rows <= 16 || (tiles_fit(tiles[0], budget) && tiles_fit(tiles[1], budget))) break;
             rows /= 2;
         }
         tiles_on_lattice = dim > 0;
-        // 3D grid boxes: the default size doubled (fewer crossings on the critical
-        // path of both solves) when such a tile still fits a CU's LDS and the grid
-        // makes a tile per CU and more; measured faster on 7-point ILU(0), two tiles
-        // per CU, and on ILU(1), whose doubled tiles leave room for one
-        if (shrink && dim == 3 && rows == kDefaultTileRows && (int64_t)H.n >= 256 * 2 * (int64_t)rows) {
-            const size_t budget2 = (size_t)kTileLdsMax;
-            TileSet t0, t1;
-            std::vector<int32_t> sci2;
-            if (build_tiles(H, 2 * rows, kTileShortRow, tile_lattice, &t0, &t1, &sci2) == 3 &&
-                tiles_fit(t0, budget2) && tiles_fit(t1, budget2)) {
-                tiles[0] = std::move(t0);
-                tiles[1] = std::move(t1);
-                sci = std::move(sci2);
-                rows *= 2;
-            }
+        const size_t budget2 = (size_t)kTileLdsMax;
+        if (try_double && dim == 3 && rows == kDefaultTileRows && dim2 == 3 && tiles_fit(t0, budget2) &&
+            tiles_fit(t1, budget2)) {
+            spare_fwd = std::move(tiles[0]);
+            tiles[0] = std::move(t0);
+            tiles[1] = std::move(t1);
+            sci = std::move(sci2);
+            rows *= 2;
         }
     } catch (const std::bad_alloc &) {
         return fail(ILU_ERR_NOMEM, "tiles: out of host memory");
@@ -410,7 +417,11 @@ ilu_status ilu_handle_s::make_factor_tiles() {
         if (want == tile_rows) {
             ok = fits(tiles[0]);
         } else {
-            build_forward_tiles(H, want, kTileShortRow, tile_lattice, &ftset);
+            // the same tiling as build_forward_tiles(want) when it was kept from make_tiles
+            if (spare_fwd.ntiles > 0 && spare_fwd.cap == want)
+                ftset = spare_fwd;
+            else
+                build_forward_tiles(H, want, kTileShortRow, tile_lattice, &ftset);
             ok = ftset_own = fits(ftset);
         }
         for (int32_t rows = want / 2; !ok && rows >= 16; rows /= 2) {

@@ -109,6 +109,9 @@ struct ilu_handle_s {
     // image for it (ftset_own); otherwise the factor uses tiles[0] / dtiles[0]
     jv::TileSet ftset;
     bool ftset_own = false;
+    // the forward tiling of the size the default tiles were doubled from, kept
+    // for the factor (whose default tile size is often that one); empty otherwise
+    jv::TileSet spare_fwd;
     struct DevFactorTiles {
         int32_t *hdr = nullptr, *blob = nullptr, *vsrc = nullptr;
         uint32_t *cmask = nullptr;

@@ -36,6 +36,8 @@
 #include <tuple>
 #include <vector>
 
+#include "par.h"
+
 #include "analysis.h"
 
 namespace jv {
@@ -428,8 +430,10 @@ int build_tiles(const HostAnalysis &H, int32_t cap, int32_t short_row, bool latt
     sci->assign(H.lu_ci.size(), -1);
     Lattice L;
     const bool lat = lattice && detect_lattice(H, &L);
-    tiles_one(H, 0, cap, short_row, lat ? &L : nullptr, fwd, sci);
-    tiles_one(H, 1, cap, short_row, lat ? &L : nullptr, bwd, sci);
+    // the directions write disjoint entries of sci (lower and upper parts of each
+    // row): built side by side
+    run_pair([&] { tiles_one(H, 0, cap, short_row, lat ? &L : nullptr, fwd, sci); },
+             [&] { tiles_one(H, 1, cap, short_row, lat ? &L : nullptr, bwd, sci); });
     return lat ? L.dim : 0;
 }
 
