@@ -170,6 +170,26 @@ ilu_status ilu_analyze(const ilu_csr *A, const ilu_analyze_opts *opts, ilu_handl
 ilu_status ilu_analyze_batched(int32_t count, const ilu_csr *As, const ilu_analyze_opts *opts,
                                ilu_handle *out);
 
+/* Level sets computed on the device (Sec. II, level scheduling; Sec. III, the
+ * dependency graph): row i depends on every j < i with (i, j) in the pattern,
+ * and with ILU_PATTERN_LOWER_SYM also on every j < i with (j, i) in it.  Level 0
+ * holds the rows with no dependency; a row's level is one more than the deepest
+ * level it depends on.  Outputs (device, caller-owned): perm[r] = the row at
+ * position r of the order by (level, row index), iperm its inverse (both n),
+ * level_ptr[l] = first position of level l, level_ptr[n_levels] = n (capacity
+ * n + 1); *n_levels (host).  These equal the schedule ilu_analyze computes on
+ * the host for the same pattern (its ILU(k) fill pattern S passed here as the
+ * CSR).  row_ptr (n + 1) and col_idx (nnz) are device arrays, checked first:
+ * ILU_ERR_CSR for row pointers that do not run monotonically from 0 to nnz, or
+ * columns unsorted, repeated or out of range.  The diagonal is optional.
+ * Allocates its scratch (about 20 bytes per row, plus 4 per strictly upper
+ * entry with the symmetric pattern) and frees it; returns after the work on
+ * `stream` has finished.  ILU_ERR_TIMEOUT if a dependency wait exceeded its
+ * bound (nothing is then written to the outputs). */
+ilu_status ilu_levels_device(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                             int32_t pattern, int32_t *level_ptr, int32_t *perm, int32_t *iperm,
+                             int32_t *n_levels, hipStream_t stream);
+
 /* Row and entry offsets of matrix i in a batched handle (host arrays of count+1). */
 ilu_status ilu_batch_offsets(ilu_handle h, int64_t *row_off, int64_t *nnz_off);
 

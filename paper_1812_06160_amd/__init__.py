@@ -8,7 +8,7 @@ csrc/); this package only marshals arguments.  Build with
 from . import _lib
 from ._lib import IluError, load
 
-__all__ = ["load", "Ilu", "IluApply", "IluError", "build"]
+__all__ = ["load", "Ilu", "IluApply", "IluError", "build", "levels_device"]
 
 
 def __getattr__(name):
@@ -17,6 +17,9 @@ def __getattr__(name):
     if name == "Ilu":
         from .ilu import Ilu
         return Ilu
+    if name == "levels_device":
+        from .ilu import levels_device
+        return levels_device
     if name == "IluApply":
         from .autograd import IluApply
         return IluApply

@@ -1,0 +1,341 @@
+// Level sets on the device (Sec. II, level scheduling; Sec. III, the dependency
+// graph of lower(S) or lower(S + S^T)).
+//
+// A row's level is 0 when it depends on no row, else one more than the deepest
+// row it depends on; the level order lists the rows by (level, row index).  This
+// is the same result as the host analysis's frontier peeling, reached in one
+// sync-free sweep instead of one pass per level:
+//   1. the CSR pattern is checked (monotone row pointers, sorted unique columns in
+//      range), so every dependency index read later is in bounds;
+//   2. with the symmetric pattern, the strictly upper entries are transposed
+//      (column counts, a scan, a scatter), giving each row the earlier rows that
+//      list it;
+//   3. one persistent sweep: blocks claim 256-row slots in start order, one lane
+//      per row; a lane reads its dependencies' levels as they are published (a
+//      level is its own ready flag: -1 until written) and publishes its own;
+//   4. keys (level << 32 | row) are radix-sorted, which gives the stable order,
+//      and the level pointers are read off the sorted keys.
+#include <hip/hip_runtime.h>
+#include <hipcub/device/device_radix_sort.hpp>
+#include <hipcub/device/device_scan.hpp>
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+
+#include "device.h"
+#include "handle.h"
+#include "javelin.h"
+
+namespace jv {
+
+namespace {
+
+constexpr int kLvBlock = 256;
+
+__device__ __forceinline__ int32_t lv_load(const int32_t *p) {
+    return __hip_atomic_load(const_cast<int32_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void lv_store(int32_t *p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// err bits: 1 row pointers, 2 column out of range, 4 columns unsorted or repeated
+__global__ void k_lv_check(int32_t n, int64_t nnz, const int32_t *rp, const int32_t *ci, int32_t *err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t b = rp[i], e = rp[i + 1];
+    int bits = 0;
+    if ((i == 0 && b != 0) || (i == n - 1 && e != nnz) || b < 0 || e < b || e > nnz) {
+        bits = 1;
+    } else {
+        int32_t prev = -1;
+        for (int32_t p = b; p < e; ++p) {
+            const int32_t c = ci[p];
+            if (c < 0 || c >= n) bits |= 2;
+            else if (c <= prev) bits |= 4;
+            prev = c;
+        }
+    }
+    if (bits) atomicOr(err, bits);
+}
+
+// strictly upper entries (i, j), j > i: row j gains the dependency i
+__global__ void k_lv_upper_count(int32_t n, const int32_t *rp, const int32_t *ci, int32_t *cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int32_t p = rp[i]; p < rp[i + 1]; ++p)
+        if (ci[p] > i) atomicAdd(&cnt[ci[p]], 1);
+}
+
+__global__ void k_lv_upper_scatter(int32_t n, const int32_t *rp, const int32_t *ci, const int32_t *tptr,
+                                   int32_t *fill, int32_t *tdep) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
+        const int32_t j = ci[p];
+        if (j > i) tdep[tptr[j] + atomicAdd(&fill[j], 1)] = (int32_t)i;
+    }
+}
+
+__global__ void k_lv_fill(int32_t n, int32_t *level, int32_t *cnt, int32_t *fill) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        level[i] = -1;
+        if (cnt) cnt[i] = 0;
+        if (fill) fill[i] = 0;
+    }
+    if (i == 0 && cnt) cnt[n] = 0;
+}
+
+// One lane per row; blocks claim consecutive 256-row slots in start order, so a
+// lane only waits on rows of blocks that started earlier (or of earlier lanes of
+// its own block), which always progress.  A lane polls without blocking its
+// wave.  It scans its dependencies eight at a time (all eight loads in flight
+// together), folds the published levels and keeps up to kLvPend pending
+// dependencies in registers; later passes re-read only those (one round of
+// loads), and the scan resumes when a slot frees up.  The wave leaves when
+// every lane has published.  A pass in which some lane of the wave published is
+// followed at once by the next (a dependency inside the wave is then ready);
+// otherwise the wave sleeps, longer after each pass without progress (up to
+// kLvSleepMax), so that waves far from the ready front load the memory system
+// less.  Bounded: after kWaitTicks without progress in its wave, or when
+// another wave has given up, the lane stops and raises the abort word (the
+// host reports ILU_ERR_TIMEOUT).
+constexpr int kLvBatch = 8;
+constexpr int kLvPend = 4;
+constexpr int kLvSleepMax = 8;
+
+// Scans deps [*cur, end): published levels are folded into *lev, pending
+// dependencies go to free slots of pend (-1 = free); the scan stops at a pending
+// dependency with no free slot (*cur is left there).  idx(u) gives the
+// dependency at u, or -1 for an entry that is not one.  Returns true when the
+// whole range has been scanned.
+template <typename Idx>
+__device__ __forceinline__ bool lv_scan(int32_t *cur, int32_t end, int32_t *lev, const int32_t *level, Idx idx,
+                                        int32_t (&pend)[kLvPend]) {
+    int32_t u = *cur;
+    while (u < end) {
+        int32_t j[kLvBatch], v[kLvBatch];
+#pragma unroll
+        for (int k = 0; k < kLvBatch; ++k) j[k] = u + k < end ? idx(u + k) : -1;
+#pragma unroll
+        for (int k = 0; k < kLvBatch; ++k) v[k] = j[k] >= 0 ? lv_load(level + j[k]) : 0;
+        int32_t stop = kLvBatch;
+#pragma unroll
+        for (int k = 0; k < kLvBatch; ++k) {
+            if (stop == kLvBatch && j[k] >= 0) {
+                if (v[k] >= 0) {
+                    *lev = max(*lev, v[k] + 1);
+                } else {
+                    bool placed = false;
+#pragma unroll
+                    for (int s = 0; s < kLvPend; ++s)
+                        if (!placed && pend[s] < 0) {
+                            pend[s] = j[k];
+                            placed = true;
+                        }
+                    if (!placed) stop = k;
+                }
+            }
+        }
+        u += stop;
+        if (stop < kLvBatch) {
+            *cur = u;
+            return false;
+        }
+    }
+    *cur = end;
+    return true;
+}
+
+__global__ __launch_bounds__(kLvBlock) void k_lv_sweep(int32_t n, const int32_t *rp, const int32_t *ci,
+                                                       const int32_t *tptr, const int32_t *tdep,
+                                                       int32_t *level, int32_t *counter, int32_t *info,
+                                                       uint32_t *maxlev) {
+    __shared__ int32_t slot;
+    if (threadIdx.x == 0) slot = atomicAdd(counter, 1);
+    __syncthreads();
+    const int64_t i64 = (int64_t)slot * kLvBlock + threadIdx.x;
+    bool done = i64 >= n;
+    const int32_t i = done ? 0 : (int32_t)i64;
+    int32_t p = done ? 0 : rp[i], pe = done ? 0 : rp[i + 1];
+    int32_t q = (done || !tptr) ? 0 : tptr[i], qe = (done || !tptr) ? 0 : tptr[i + 1];
+    int32_t lev = 0;
+    int32_t pend[kLvPend];
+#pragma unroll
+    for (int s = 0; s < kLvPend; ++s) pend[s] = -1;
+    bool scanned = false;
+    uint64_t t0 = 0;
+    int spins = 0, nap = 1;
+    for (;;) {
+        bool published = false;
+        if (!done) {
+            int32_t v[kLvPend];
+#pragma unroll
+            for (int s = 0; s < kLvPend; ++s) v[s] = pend[s] >= 0 ? lv_load(level + pend[s]) : -1;
+            bool clear = true;
+#pragma unroll
+            for (int s = 0; s < kLvPend; ++s) {
+                if (pend[s] >= 0 && v[s] >= 0) {
+                    lev = max(lev, v[s] + 1);
+                    pend[s] = -1;
+                }
+                clear = clear && pend[s] < 0;
+            }
+            // row entries (columns below i are dependencies), then the transposed ones
+            if (!scanned)
+                scanned = lv_scan(&p, pe, &lev, level, [&](int32_t u) { const int32_t c = ci[u]; return c < i ? c : -1; },
+                                  pend) &&
+                          lv_scan(&q, qe, &lev, level, [&](int32_t u) { return tdep[u]; }, pend);
+            if (scanned) {
+                clear = true;
+#pragma unroll
+                for (int s = 0; s < kLvPend; ++s) clear = clear && pend[s] < 0;
+            }
+            if (scanned && clear) {
+                lv_store(level + i, lev);
+                done = published = true;
+            }
+        }
+        if (__all(done)) break;
+        if (__any(published)) {
+            t0 = 0;   // the bound counts time without progress
+            nap = 1;
+            continue;
+        }
+        if ((++spins & 63) == 0) {
+            if (__hip_atomic_load(&info[kInfoAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+            const uint64_t now = __builtin_amdgcn_s_memrealtime();
+            if (t0 == 0) {
+                t0 = now;
+            } else if (now - t0 > kWaitTicks) {
+                __hip_atomic_store(&info[kInfoAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+        for (int k = 0; k < nap; ++k) __builtin_amdgcn_s_sleep(1);
+        nap = min(2 * nap, kLvSleepMax);
+    }
+    // deepest level: one atomic per wave
+    int32_t m = i64 < n ? lev : 0;
+    for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(maxlev, (uint32_t)m);
+}
+
+__global__ void k_lv_keys(int32_t n, const int32_t *level, uint64_t *keys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) keys[i] = (uint64_t)(uint32_t)level[i] << 32 | (uint32_t)i;
+}
+
+// sorted keys -> perm, iperm, level_ptr (every level from 0 to the last holds a
+// row: a row of level l > 0 depends on one of level l - 1)
+__global__ void k_lv_out(int32_t n, const uint64_t *keys, int32_t *perm, int32_t *iperm, int32_t *level_ptr) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const uint64_t k = keys[r];
+    const int32_t row = (int32_t)(uint32_t)k, lev = (int32_t)(k >> 32);
+    perm[r] = row;
+    iperm[row] = (int32_t)r;
+    if (r == 0 || (int32_t)(keys[r - 1] >> 32) != lev) level_ptr[lev] = (int32_t)r;
+    if (r == n - 1) level_ptr[lev + 1] = n;
+}
+
+unsigned grid_of(int64_t n) { return (unsigned)((n + kLvBlock - 1) / kLvBlock); }
+
+}  // namespace
+
+}  // namespace jv
+
+using namespace jv;
+
+extern "C" ilu_status ilu_levels_device(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                                        int32_t pattern, int32_t *level_ptr, int32_t *perm, int32_t *iperm,
+                                        int32_t *n_levels, hipStream_t stream) {
+    if (n <= 0 || n >= (1 << 30) || nnz < 0 || nnz >= ((int64_t)1 << 31) || !row_ptr || (nnz > 0 && !col_idx) ||
+        !level_ptr || !perm || !iperm || !n_levels)
+        return fail(ILU_ERR_ARG, "ilu_levels_device: bad argument");
+    if (pattern != ILU_PATTERN_LOWER_SYM && pattern != ILU_PATTERN_LOWER_A)
+        return fail(ILU_ERR_ARG, "ilu_levels_device: unknown pattern");
+    const bool sym = pattern == ILU_PATTERN_LOWER_SYM;
+    // one device block: err, abort/info words, claim counter, max level
+    int32_t *ctl = nullptr, *level = nullptr, *cnt = nullptr, *tptr = nullptr, *fill = nullptr, *tdep = nullptr;
+    uint64_t *keys = nullptr, *keys2 = nullptr;
+    void *tmp = nullptr;
+    struct Guard {
+        std::vector<void *> p;
+        hipStream_t s;
+        ~Guard() {
+            (void)hipStreamSynchronize(s);
+            for (void *x : p)
+                if (x) (void)hipFree(x);
+        }
+    } g{{}, stream};
+    auto alloc = [&](auto **ptr, size_t bytes) -> hipError_t {
+        hipError_t e = hipMalloc((void **)ptr, std::max<size_t>(bytes, 16));
+        if (e == hipSuccess) g.p.push_back((void *)*ptr);
+        return e;
+    };
+    hipError_t e;
+    if ((e = alloc(&ctl, 64 * sizeof(int32_t))) != hipSuccess || (e = alloc(&level, (size_t)n * 4)) != hipSuccess ||
+        (e = alloc(&keys, (size_t)n * 8)) != hipSuccess || (e = alloc(&keys2, (size_t)n * 8)) != hipSuccess)
+        return e == hipErrorOutOfMemory ? fail(ILU_ERR_NOMEM, "ilu_levels_device: device memory")
+                                        : hip_fail(e, "ilu_levels_device: allocate");
+    if (sym && ((e = alloc(&cnt, ((size_t)n + 1) * 4)) != hipSuccess ||
+                (e = alloc(&tptr, ((size_t)n + 1) * 4)) != hipSuccess ||
+                (e = alloc(&fill, (size_t)n * 4)) != hipSuccess))
+        return e == hipErrorOutOfMemory ? fail(ILU_ERR_NOMEM, "ilu_levels_device: device memory")
+                                        : hip_fail(e, "ilu_levels_device: allocate");
+    int32_t *err = ctl, *info = ctl + 16, *counter = ctl + 32;
+    uint32_t *maxlev = reinterpret_cast<uint32_t *>(ctl + 48);
+    if ((e = hipMemsetAsync(ctl, 0, 64 * sizeof(int32_t), stream)) != hipSuccess)
+        return hip_fail(e, "ilu_levels_device: clear");
+    k_lv_check<<<grid_of(n), kLvBlock, 0, stream>>>(n, nnz, row_ptr, col_idx, err);
+    k_lv_fill<<<grid_of((int64_t)n + 1), kLvBlock, 0, stream>>>(n, level, cnt, fill);
+    int32_t h_err = 0;
+    if ((e = hipMemcpyAsync(&h_err, err, 4, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess)
+        return hip_fail(e, "ilu_levels_device: check");
+    if (h_err & 1) return fail(ILU_ERR_CSR, "ilu_levels_device: row_ptr not monotone or not ending at nnz");
+    if (h_err & 2) return fail(ILU_ERR_CSR, "ilu_levels_device: column index out of range");
+    if (h_err & 4) return fail(ILU_ERR_CSR, "ilu_levels_device: columns unsorted or repeated");
+    if (sym) {
+        k_lv_upper_count<<<grid_of(n), kLvBlock, 0, stream>>>(n, row_ptr, col_idx, cnt);
+        size_t tb = 0;
+        if ((e = hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt, tptr, n + 1, stream)) != hipSuccess ||
+            (e = alloc(&tmp, tb)) != hipSuccess ||
+            (e = hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt, tptr, n + 1, stream)) != hipSuccess)
+            return hip_fail(e, "ilu_levels_device: scan");
+        int32_t nup = 0;
+        if ((e = hipMemcpyAsync(&nup, tptr + n, 4, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(stream)) != hipSuccess)
+            return hip_fail(e, "ilu_levels_device: upper count");
+        if ((e = alloc(&tdep, (size_t)nup * 4)) != hipSuccess)
+            return e == hipErrorOutOfMemory ? fail(ILU_ERR_NOMEM, "ilu_levels_device: device memory")
+                                            : hip_fail(e, "ilu_levels_device: allocate");
+        k_lv_upper_scatter<<<grid_of(n), kLvBlock, 0, stream>>>(n, row_ptr, col_idx, tptr, fill, tdep);
+    }
+    k_lv_sweep<<<grid_of(n), kLvBlock, 0, stream>>>(n, row_ptr, col_idx, sym ? tptr : nullptr, tdep, level,
+                                                    counter, info, maxlev);
+    k_lv_keys<<<grid_of(n), kLvBlock, 0, stream>>>(n, level, keys);
+    uint32_t h_max = 0;
+    int32_t h_abort = 0;
+    if ((e = hipGetLastError()) != hipSuccess ||
+        (e = hipMemcpyAsync(&h_max, maxlev, 4, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(&h_abort, info + kInfoAbort, 4, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess)
+        return hip_fail(e, "ilu_levels_device: sweep");
+    if (h_abort) return fail(ILU_ERR_TIMEOUT, "ilu_levels_device: a dependency wait expired");
+    int end_bit = 32;
+    while (end_bit < 64 && (h_max >> (end_bit - 32)) != 0) ++end_bit;
+    size_t sb = 0;
+    void *stmp = nullptr;
+    if ((e = hipcub::DeviceRadixSort::SortKeys(nullptr, sb, keys, keys2, n, 0, end_bit, stream)) != hipSuccess ||
+        (e = alloc(&stmp, sb)) != hipSuccess ||
+        (e = hipcub::DeviceRadixSort::SortKeys(stmp, sb, keys, keys2, n, 0, end_bit, stream)) != hipSuccess)
+        return hip_fail(e, "ilu_levels_device: sort");
+    k_lv_out<<<grid_of(n), kLvBlock, 0, stream>>>(n, keys2, perm, iperm, level_ptr);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "ilu_levels_device: output");
+    *n_levels = (int32_t)h_max + 1;
+    return ILU_OK;
+}

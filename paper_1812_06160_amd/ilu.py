@@ -38,6 +38,24 @@ def _rhs_shape(t):
     raise ValueError("vectors must be [n] or [n][nrhs]")
 
 
+def levels_device(row_ptr: torch.Tensor, col_idx: torch.Tensor, pattern: str = "sym"):
+    """Level sets of a CSR pattern computed on the GPU (ilu_levels_device).
+
+    row_ptr / col_idx: int32 device tensors.  Returns (level_ptr, perm, iperm) as
+    int32 device tensors, level_ptr trimmed to n_levels + 1 entries."""
+    lib = L.load()
+    n = row_ptr.numel() - 1
+    dev = row_ptr.device
+    lp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    iperm = torch.empty(n, dtype=torch.int32, device=dev)
+    nl = C.c_int32(0)
+    pat = L.PATTERN_LOWER_SYM if pattern == "sym" else L.PATTERN_LOWER_A
+    L.check(lib.ilu_levels_device(int(n), int(col_idx.numel()), _ptr(row_ptr), _ptr(col_idx), pat, _ptr(lp),
+                                  _ptr(perm), _ptr(iperm), C.byref(nl), _stream()), "ilu_levels_device")
+    return lp[:nl.value + 1], perm, iperm
+
+
 class Ilu:
     """Analysis handle: ILU(k_max) pattern, level schedule and permuted structure of A."""
 

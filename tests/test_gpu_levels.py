@@ -1,0 +1,121 @@
+"""Level sets computed on the device (ilu_levels_device) against the oracle's
+level schedule (Sec. II peeling of lower(S) or lower(S + S^T)): perm and the level
+pointers bit for bit, on small structured and random patterns, degenerate cases
+(one row, no dependencies, one long chain), ILU(1) fill patterns, both dependency
+patterns, the full-size 128^3 Laplacian and random_1m, and the CSR errors."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.int32)).cuda()
+
+
+def run(jv, n, rp, ci, sym=True):
+    lp, perm, ip = jv.levels_device(dev(rp), dev(ci), "sym" if sym else "lower")
+    return lp.cpu().numpy(), perm.cpu().numpy(), ip.cpu().numpy()
+
+
+def check(jv, n, rp, ci, sym=True, k_max=0):
+    an = O.analyze(n, rp, ci, k_max=k_max, sym=sym)
+    srp, sci = (rp, ci) if k_max == 0 else (an.s_rp, an.s_ci)
+    lp, perm, ip = run(jv, n, srp, sci, sym)
+    np.testing.assert_array_equal(lp, an.level_ptr)
+    np.testing.assert_array_equal(perm, an.perm)
+    np.testing.assert_array_equal(ip, an.iperm)
+    return an
+
+
+CASES = {
+    "laplace2d_64": lambda: synth.laplace2d(64),
+    "laplace3d_20": lambda: synth.laplace3d(20),
+    "convdiff3d_12": lambda: synth.convdiff3d(12),
+    "random_nonsym": lambda: synth.random_sparse(3000, 2e-3, np.random.default_rng(7)),
+    "random_missing_diag": lambda: synth.random_sparse(2500, 1.5e-3, np.random.default_rng(8), drop_diag_frac=0.3),
+    "heavy_rows": lambda: synth.heavy_rows(4000, heavy_len=(64, 300), rng=np.random.default_rng(9)),
+}
+
+
+@pytest.mark.parametrize("sym", [True, False], ids=["lower_sym", "lower_a"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_levels_match_oracle(jv, name, sym):
+    A = CASES[name]()
+    check(jv, A.n, A.row_ptr, A.col_idx, sym=sym)
+
+
+@pytest.mark.parametrize("sym", [True, False], ids=["lower_sym", "lower_a"])
+def test_levels_ilu1_pattern(jv, sym):
+    A = synth.convdiff3d(10)
+    check(jv, A.n, A.row_ptr, A.col_idx, sym=sym, k_max=1)
+    B = synth.random_sparse(1500, 3e-3, np.random.default_rng(3))
+    check(jv, B.n, B.row_ptr, B.col_idx, sym=sym, k_max=2)
+
+
+def test_levels_degenerate(jv):
+    # one row without entries
+    lp, perm, ip = run(jv, 1, np.array([0, 0]), np.array([], np.int32))
+    assert lp.tolist() == [0, 1] and perm.tolist() == [0] and ip.tolist() == [0]
+    # diagonal only: a single level in input order
+    n = 1000
+    lp, perm, _ = run(jv, n, np.arange(n + 1), np.arange(n))
+    assert lp.tolist() == [0, n] and perm.tolist() == list(range(n))
+    # lower bidiagonal: one level per row, across many claimed blocks
+    n = 3000
+    rp = np.concatenate([[0, 1], 1 + 2 * np.arange(1, n)])
+    ci = np.concatenate([[0], np.stack([np.arange(n - 1), np.arange(1, n)], 1).ravel()])
+    lp, perm, _ = run(jv, n, rp, ci)
+    np.testing.assert_array_equal(lp, np.arange(n + 1))
+    # upper entries only: one level under lower(A), a chain under lower(A + A^T)
+    rp = np.minimum(np.arange(n + 1), n - 1)
+    ci = np.arange(1, n)
+    lp, _, _ = run(jv, n, rp, ci, sym=False)
+    assert lp.tolist() == [0, n]
+    lp, _, _ = run(jv, n, rp, ci, sym=True)
+    np.testing.assert_array_equal(lp, np.arange(n + 1))
+    check(jv, n, rp, ci, sym=True)
+
+
+def test_levels_csr_errors(jv):
+    A = synth.laplace2d(8)
+    bad = []
+    ci = A.col_idx.copy()
+    ci[[3, 4]] = ci[[4, 3]]                                     # unsorted row
+    bad.append((A.row_ptr, ci))
+    ci = A.col_idx.copy()
+    ci[5] = ci[4]                                               # repeated column
+    bad.append((A.row_ptr, ci))
+    ci = A.col_idx.copy()
+    ci[-1] = A.n                                                # out of range
+    bad.append((A.row_ptr, ci))
+    rp = A.row_ptr.copy()
+    rp[10], rp[11] = rp[11], rp[10]                             # not monotone
+    bad.append((rp, A.col_idx))
+    rp = A.row_ptr.copy()
+    rp[-1] -= 1                                                 # does not end at nnz
+    bad.append((rp, A.col_idx))
+    for rp, ci in bad:
+        with pytest.raises(jv.IluError) as e:
+            run(jv, A.n, rp, ci)
+        assert e.value.status == "ILU_ERR_CSR"
+    # a good call afterwards still matches
+    check(jv, A.n, A.row_ptr, A.col_idx)
+
+
+@pytest.mark.slow
+def test_levels_laplace3d_128_full(jv):
+    A, _ = synth.workload(2)
+    an = check(jv, A.n, A.row_ptr, A.col_idx)
+    assert an.n_levels == 382
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("sym", [True, False], ids=["lower_sym", "lower_a"])
+def test_levels_random_1m_full(jv, sym):
+    A, _ = synth.workload(4)
+    check(jv, A.n, A.row_ptr, A.col_idx, sym=sym)
