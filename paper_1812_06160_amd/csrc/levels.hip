@@ -103,8 +103,8 @@ __global__ void k_lv_fill(int32_t n, int32_t *level, int32_t *cnt, int32_t *fill
 // another wave has given up, the lane stops and raises the abort word (the
 // host reports ILU_ERR_TIMEOUT).
 constexpr int kLvBatch = 8;
-constexpr int kLvPend = 4;
-constexpr int kLvSleepMax = 8;
+constexpr int kLvPend = 8;
+constexpr int kLvSleepMax = 32;
 
 // Scans deps [*cur, end): published levels are folded into *lev, pending
 // dependencies go to free slots of pend (-1 = free); the scan stops at a pending
