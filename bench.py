@@ -139,7 +139,7 @@ def main():
                     help="a tuning knob of the handles (ilu_set_tuning), repeatable")
     ap.add_argument("--workload", default="laplace3d_128",
                     choices=["laplace3d_128", "laplace2d_64", "convdiff3d_96", "random_1m", "batch512", "heavy_1m",
-                             "ordering"])
+                             "ordering", "levels"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus must be 1)", file=sys.stderr)

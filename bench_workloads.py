@@ -293,6 +293,33 @@ def run(args):
                 del ilu
                 torch.cuda.empty_cache()
         out.update(rows=rows)
+    elif wl == "levels":
+        # level sets on the device (ilu_levels_device) against the whole host
+        # analysis, both dependency patterns, the pattern already in HBM
+        from paper_1812_06160_amd.ilu import levels_device
+        rows = []
+        for wid, name in ((2, "laplace3d_128"), (3, "convdiff3d_96"), (4, "random_1m")):
+            A, _ = synth.workload(wid)
+            rp = torch.from_numpy(A.row_ptr.astype(np.int32)).cuda()
+            ci = torch.from_numpy(A.col_idx.astype(np.int32)).cuda()
+            row = dict(matrix=name, n=A.n, nnz=A.nnz)
+            for pat in ("sym", "lower"):
+                levels_device(rp, ci, pat)
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(5):
+                    t0 = time.perf_counter()
+                    lp, _, _ = levels_device(rp, ci, pat)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                row[f"levels_{pat}"] = int(lp.numel() - 1)
+                row[f"device_ms_{pat}"] = round(1e3 * float(np.median(ts)), 2)
+            t0 = time.perf_counter()
+            jv.Ilu(A.n, A.row_ptr, A.col_idx, host_only=True)
+            row["host_analysis_s"] = round(time.perf_counter() - t0, 3)
+            log(json.dumps(row))
+            rows.append(row)
+        out.update(matrices=rows)
     elif wl == "batch512":
         mats, rhs = synth.workload(5)
         t0 = time.perf_counter()
