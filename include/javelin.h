@@ -182,10 +182,11 @@ ilu_status ilu_analyze_batched(int32_t count, const ilu_csr *As, const ilu_analy
  * CSR).  row_ptr (n + 1) and col_idx (nnz) are device arrays, checked first:
  * ILU_ERR_CSR for row pointers that do not run monotonically from 0 to nnz, or
  * columns unsorted, repeated or out of range.  The diagonal is optional.
- * Allocates its scratch (about 20 bytes per row, plus 4 per strictly upper
- * entry with the symmetric pattern) and frees it; returns after the work on
- * `stream` has finished.  ILU_ERR_TIMEOUT if a dependency wait exceeded its
- * bound (nothing is then written to the outputs). */
+ * Allocates one scratch block (about 20 bytes per row; with the symmetric
+ * pattern 12 more per row and 4 per stored entry; plus the sort's
+ * temporaries) and frees it; returns after the work on `stream` has finished.
+ * ILU_ERR_TIMEOUT if a dependency wait exceeded its bound.  On either error
+ * nothing is written to the outputs. */
 ilu_status ilu_levels_device(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                              int32_t pattern, int32_t *level_ptr, int32_t *perm, int32_t *iperm,
                              int32_t *n_levels, hipStream_t stream);

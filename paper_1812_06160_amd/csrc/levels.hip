@@ -61,17 +61,17 @@ __global__ void k_lv_check(int32_t n, int64_t nnz, const int32_t *rp, const int3
 }
 
 // strictly upper entries (i, j), j > i: row j gains the dependency i
-__global__ void k_lv_upper_count(int32_t n, const int32_t *rp, const int32_t *ci, int32_t *cnt) {
+__global__ void k_lv_upper_count(int32_t n, const int32_t *rp, const int32_t *ci, int32_t *cnt, const int32_t *err) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || *err) return;
     for (int32_t p = rp[i]; p < rp[i + 1]; ++p)
         if (ci[p] > i) atomicAdd(&cnt[ci[p]], 1);
 }
 
 __global__ void k_lv_upper_scatter(int32_t n, const int32_t *rp, const int32_t *ci, const int32_t *tptr,
-                                   int32_t *fill, int32_t *tdep) {
+                                   int32_t *fill, int32_t *tdep, const int32_t *err) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || *err) return;
     for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
         const int32_t j = ci[p];
         if (j > i) tdep[tptr[j] + atomicAdd(&fill[j], 1)] = (int32_t)i;
@@ -152,7 +152,8 @@ __device__ __forceinline__ bool lv_scan(int32_t *cur, int32_t end, int32_t *lev,
 __global__ __launch_bounds__(kLvBlock) void k_lv_sweep(int32_t n, const int32_t *rp, const int32_t *ci,
                                                        const int32_t *tptr, const int32_t *tdep,
                                                        int32_t *level, int32_t *counter, int32_t *info,
-                                                       uint32_t *maxlev) {
+                                                       uint32_t *maxlev, const int32_t *err) {
+    if (*err) return;   // the pattern failed its check: nothing is read
     __shared__ int32_t slot;
     if (threadIdx.x == 0) slot = atomicAdd(counter, 1);
     __syncthreads();
@@ -223,16 +224,18 @@ __global__ __launch_bounds__(kLvBlock) void k_lv_sweep(int32_t n, const int32_t 
     if ((threadIdx.x & 63) == 0) atomicMax(maxlev, (uint32_t)m);
 }
 
-__global__ void k_lv_keys(int32_t n, const int32_t *level, uint64_t *keys) {
+__global__ void k_lv_keys(int32_t n, const int32_t *level, uint64_t *keys, const int32_t *err, const int32_t *info) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (*err || info[kInfoAbort]) return;
     if (i < n) keys[i] = (uint64_t)(uint32_t)level[i] << 32 | (uint32_t)i;
 }
 
 // sorted keys -> perm, iperm, level_ptr (every level from 0 to the last holds a
 // row: a row of level l > 0 depends on one of level l - 1)
-__global__ void k_lv_out(int32_t n, const uint64_t *keys, int32_t *perm, int32_t *iperm, int32_t *level_ptr) {
+__global__ void k_lv_out(int32_t n, const uint64_t *keys, int32_t *perm, int32_t *iperm, int32_t *level_ptr,
+                         const int32_t *err, const int32_t *info) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
+    if (r >= n || *err || info[kInfoAbort]) return;
     const uint64_t k = keys[r];
     const int32_t row = (int32_t)(uint32_t)k, lev = (int32_t)(k >> 32);
     perm[r] = row;
@@ -258,84 +261,76 @@ extern "C" ilu_status ilu_levels_device(int32_t n, int64_t nnz, const int32_t *r
     if (pattern != ILU_PATTERN_LOWER_SYM && pattern != ILU_PATTERN_LOWER_A)
         return fail(ILU_ERR_ARG, "ilu_levels_device: unknown pattern");
     const bool sym = pattern == ILU_PATTERN_LOWER_SYM;
-    // one device block: err, abort/info words, claim counter, max level
-    int32_t *ctl = nullptr, *level = nullptr, *cnt = nullptr, *tptr = nullptr, *fill = nullptr, *tdep = nullptr;
-    uint64_t *keys = nullptr, *keys2 = nullptr;
-    void *tmp = nullptr;
+    // Levels are below n < 2^30, so the sort keys need 32 + bits(n - 1) bits.
+    int end_bit = 32;
+    while (end_bit < 62 && ((int64_t)(n - 1) >> (end_bit - 32)) != 0) ++end_bit;
+    // Scratch sizes, then one allocation: control words, levels, two key arrays,
+    // and with the symmetric pattern the counts, their scan, the fill cursors and
+    // the transposed lists (at most nnz entries), plus the library temporaries.
+    hipError_t e;
+    size_t scan_b = 0, sort_b = 0;
+    if (sym && (e = hipcub::DeviceScan::ExclusiveSum(nullptr, scan_b, (int32_t *)nullptr, (int32_t *)nullptr, n + 1,
+                                                     stream)) != hipSuccess)
+        return hip_fail(e, "ilu_levels_device: scan size");
+    if ((e = hipcub::DeviceRadixSort::SortKeys(nullptr, sort_b, (uint64_t *)nullptr, (uint64_t *)nullptr, n, 0,
+                                               end_bit, stream)) != hipSuccess)
+        return hip_fail(e, "ilu_levels_device: sort size");
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t o_level = 256, o_keys = o_level + al((size_t)n * 4), o_keys2 = o_keys + al((size_t)n * 8),
+                 o_cnt = o_keys2 + al((size_t)n * 8), o_tptr = o_cnt + (sym ? al(((size_t)n + 1) * 4) : 0),
+                 o_fill = o_tptr + (sym ? al(((size_t)n + 1) * 4) : 0), o_tdep = o_fill + (sym ? al((size_t)n * 4) : 0),
+                 o_scan = o_tdep + (sym ? al((size_t)std::max<int64_t>(nnz, 1) * 4) : 0), o_sort = o_scan + al(scan_b),
+                 total = o_sort + al(std::max<size_t>(sort_b, 1));
+    char *base = nullptr;
+    if ((e = hipMalloc((void **)&base, total)) != hipSuccess)
+        return e == hipErrorOutOfMemory ? fail(ILU_ERR_NOMEM, "ilu_levels_device: device memory")
+                                        : hip_fail(e, "ilu_levels_device: allocate");
     struct Guard {
-        std::vector<void *> p;
+        void *p;
         hipStream_t s;
         ~Guard() {
             (void)hipStreamSynchronize(s);
-            for (void *x : p)
-                if (x) (void)hipFree(x);
+            (void)hipFree(p);
         }
-    } g{{}, stream};
-    auto alloc = [&](auto **ptr, size_t bytes) -> hipError_t {
-        hipError_t e = hipMalloc((void **)ptr, std::max<size_t>(bytes, 16));
-        if (e == hipSuccess) g.p.push_back((void *)*ptr);
-        return e;
-    };
-    hipError_t e;
-    if ((e = alloc(&ctl, 64 * sizeof(int32_t))) != hipSuccess || (e = alloc(&level, (size_t)n * 4)) != hipSuccess ||
-        (e = alloc(&keys, (size_t)n * 8)) != hipSuccess || (e = alloc(&keys2, (size_t)n * 8)) != hipSuccess)
-        return e == hipErrorOutOfMemory ? fail(ILU_ERR_NOMEM, "ilu_levels_device: device memory")
-                                        : hip_fail(e, "ilu_levels_device: allocate");
-    if (sym && ((e = alloc(&cnt, ((size_t)n + 1) * 4)) != hipSuccess ||
-                (e = alloc(&tptr, ((size_t)n + 1) * 4)) != hipSuccess ||
-                (e = alloc(&fill, (size_t)n * 4)) != hipSuccess))
-        return e == hipErrorOutOfMemory ? fail(ILU_ERR_NOMEM, "ilu_levels_device: device memory")
-                                        : hip_fail(e, "ilu_levels_device: allocate");
+    } g{base, stream};
+    int32_t *ctl = reinterpret_cast<int32_t *>(base);
     int32_t *err = ctl, *info = ctl + 16, *counter = ctl + 32;
     uint32_t *maxlev = reinterpret_cast<uint32_t *>(ctl + 48);
+    int32_t *level = reinterpret_cast<int32_t *>(base + o_level);
+    uint64_t *keys = reinterpret_cast<uint64_t *>(base + o_keys), *keys2 = reinterpret_cast<uint64_t *>(base + o_keys2);
+    int32_t *cnt = sym ? reinterpret_cast<int32_t *>(base + o_cnt) : nullptr;
+    int32_t *tptr = sym ? reinterpret_cast<int32_t *>(base + o_tptr) : nullptr;
+    int32_t *fill = sym ? reinterpret_cast<int32_t *>(base + o_fill) : nullptr;
+    int32_t *tdep = sym ? reinterpret_cast<int32_t *>(base + o_tdep) : nullptr;
+    // Every kernel after the check reads the error word first and does nothing
+    // when it is set, so an invalid pattern is never indexed; the sort then runs
+    // on keys nobody reads.  One synchronisation at the end.
     if ((e = hipMemsetAsync(ctl, 0, 64 * sizeof(int32_t), stream)) != hipSuccess)
         return hip_fail(e, "ilu_levels_device: clear");
     k_lv_check<<<grid_of(n), kLvBlock, 0, stream>>>(n, nnz, row_ptr, col_idx, err);
     k_lv_fill<<<grid_of((int64_t)n + 1), kLvBlock, 0, stream>>>(n, level, cnt, fill);
-    int32_t h_err = 0;
-    if ((e = hipMemcpyAsync(&h_err, err, 4, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
-        (e = hipStreamSynchronize(stream)) != hipSuccess)
-        return hip_fail(e, "ilu_levels_device: check");
-    if (h_err & 1) return fail(ILU_ERR_CSR, "ilu_levels_device: row_ptr not monotone or not ending at nnz");
-    if (h_err & 2) return fail(ILU_ERR_CSR, "ilu_levels_device: column index out of range");
-    if (h_err & 4) return fail(ILU_ERR_CSR, "ilu_levels_device: columns unsorted or repeated");
     if (sym) {
-        k_lv_upper_count<<<grid_of(n), kLvBlock, 0, stream>>>(n, row_ptr, col_idx, cnt);
-        size_t tb = 0;
-        if ((e = hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt, tptr, n + 1, stream)) != hipSuccess ||
-            (e = alloc(&tmp, tb)) != hipSuccess ||
-            (e = hipcub::DeviceScan::ExclusiveSum(tmp, tb, cnt, tptr, n + 1, stream)) != hipSuccess)
+        k_lv_upper_count<<<grid_of(n), kLvBlock, 0, stream>>>(n, row_ptr, col_idx, cnt, err);
+        if ((e = hipcub::DeviceScan::ExclusiveSum(base + o_scan, scan_b, cnt, tptr, n + 1, stream)) != hipSuccess)
             return hip_fail(e, "ilu_levels_device: scan");
-        int32_t nup = 0;
-        if ((e = hipMemcpyAsync(&nup, tptr + n, 4, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
-            (e = hipStreamSynchronize(stream)) != hipSuccess)
-            return hip_fail(e, "ilu_levels_device: upper count");
-        if ((e = alloc(&tdep, (size_t)nup * 4)) != hipSuccess)
-            return e == hipErrorOutOfMemory ? fail(ILU_ERR_NOMEM, "ilu_levels_device: device memory")
-                                            : hip_fail(e, "ilu_levels_device: allocate");
-        k_lv_upper_scatter<<<grid_of(n), kLvBlock, 0, stream>>>(n, row_ptr, col_idx, tptr, fill, tdep);
+        k_lv_upper_scatter<<<grid_of(n), kLvBlock, 0, stream>>>(n, row_ptr, col_idx, tptr, fill, tdep, err);
     }
-    k_lv_sweep<<<grid_of(n), kLvBlock, 0, stream>>>(n, row_ptr, col_idx, sym ? tptr : nullptr, tdep, level,
-                                                    counter, info, maxlev);
-    k_lv_keys<<<grid_of(n), kLvBlock, 0, stream>>>(n, level, keys);
-    uint32_t h_max = 0;
-    int32_t h_abort = 0;
-    if ((e = hipGetLastError()) != hipSuccess ||
-        (e = hipMemcpyAsync(&h_max, maxlev, 4, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
-        (e = hipMemcpyAsync(&h_abort, info + kInfoAbort, 4, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
-        (e = hipStreamSynchronize(stream)) != hipSuccess)
-        return hip_fail(e, "ilu_levels_device: sweep");
-    if (h_abort) return fail(ILU_ERR_TIMEOUT, "ilu_levels_device: a dependency wait expired");
-    int end_bit = 32;
-    while (end_bit < 64 && (h_max >> (end_bit - 32)) != 0) ++end_bit;
-    size_t sb = 0;
-    void *stmp = nullptr;
-    if ((e = hipcub::DeviceRadixSort::SortKeys(nullptr, sb, keys, keys2, n, 0, end_bit, stream)) != hipSuccess ||
-        (e = alloc(&stmp, sb)) != hipSuccess ||
-        (e = hipcub::DeviceRadixSort::SortKeys(stmp, sb, keys, keys2, n, 0, end_bit, stream)) != hipSuccess)
+    k_lv_sweep<<<grid_of(n), kLvBlock, 0, stream>>>(n, row_ptr, col_idx, tptr, tdep, level, counter, info, maxlev,
+                                                    err);
+    k_lv_keys<<<grid_of(n), kLvBlock, 0, stream>>>(n, level, keys, err, info);
+    if ((e = hipcub::DeviceRadixSort::SortKeys(base + o_sort, sort_b, keys, keys2, n, 0, end_bit, stream)) !=
+        hipSuccess)
         return hip_fail(e, "ilu_levels_device: sort");
-    k_lv_out<<<grid_of(n), kLvBlock, 0, stream>>>(n, keys2, perm, iperm, level_ptr);
-    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "ilu_levels_device: output");
-    *n_levels = (int32_t)h_max + 1;
+    k_lv_out<<<grid_of(n), kLvBlock, 0, stream>>>(n, keys2, perm, iperm, level_ptr, err, info);
+    int32_t h[64];
+    if ((e = hipGetLastError()) != hipSuccess ||
+        (e = hipMemcpyAsync(h, ctl, sizeof(h), hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess)
+        return hip_fail(e, "ilu_levels_device: run");
+    if (h[0] & 1) return fail(ILU_ERR_CSR, "ilu_levels_device: row_ptr not monotone or not ending at nnz");
+    if (h[0] & 2) return fail(ILU_ERR_CSR, "ilu_levels_device: column index out of range");
+    if (h[0] & 4) return fail(ILU_ERR_CSR, "ilu_levels_device: columns unsorted or repeated");
+    if (h[16 + kInfoAbort]) return fail(ILU_ERR_TIMEOUT, "ilu_levels_device: a dependency wait expired");
+    *n_levels = h[48] + 1;
     return ILU_OK;
 }
