@@ -449,11 +449,14 @@ namespace {
 size_t a16(size_t b) { return (b + 15) & ~(size_t)15; }
 
 // Tile t's header, blob and value sources (its tables are the last ones appended
-// to F's per-entry arrays).  A tile whose offsets do not fit the packed fields
-// makes the whole set unusable (lds_need beyond any LDS).
-void append_tile_blob(const HostAnalysis &H, const TileSet &T, int32_t t, int32_t lanes, FactorTiles *F) {
+// to F's per-entry arrays).  F holds the tiles from tb on, whose first row
+// position is rb (its per-row and per-tile arrays are indexed from there).  A
+// tile whose offsets do not fit the packed fields makes the whole set unusable
+// (lds_need beyond any LDS).
+void append_tile_blob(const HostAnalysis &H, const TileSet &T, int32_t t, int32_t lanes, int32_t tb, int32_t rb,
+                      FactorTiles *F) {
     const int32_t r0 = T.rows_ptr[t], nrows = T.rows_ptr[t + 1] - r0;
-    const int32_t l0 = F->lptr[t], nl = F->lptr[t + 1] - l0;
+    const int32_t l0 = F->lptr[t - tb], nl = F->lptr[t - tb + 1] - l0;
     const int32_t i0 = T.imp_ptr[t], nimp = T.imp_ptr[t + 1] - i0;
     const int32_t p0 = T.ptr[t], npos = T.ptr[t + 1] - p0;
     size_t o = 0;
@@ -471,7 +474,7 @@ void append_tile_blob(const HostAnalysis &H, const TileSet &T, int32_t t, int32_
     bool packs = nrows + nimp <= 65536;
     int32_t *rw = reinterpret_cast<int32_t *>(b.data() + o_rows);
     for (int32_t k = 0; k < nrows; ++k) {
-        const int32_t *m = F->meta.data() + 4 * (size_t)(r0 + k), *of = F->off.data() + 2 * (size_t)(r0 + k);
+        const int32_t *m = F->meta.data() + 4 * (size_t)(r0 - rb + k), *of = F->off.data() + 2 * (size_t)(r0 - rb + k);
         const int32_t len = m[2] - m[1], K = m[3] - m[1];
         packs = packs && of[0] < 65536 && len < 256 && K < 256;
         rw[4 * k] = m[0];
@@ -515,10 +518,11 @@ void append_tile_blob(const HostAnalysis &H, const TileSet &T, int32_t t, int32_
     }
 }
 
-}  // namespace
-
-void build_factor_tiles(const HostAnalysis &H, const TileSet &T, int32_t lanes, FactorTiles *F) {
+// Tiles [tb, te) into F, indexed from tile tb and its first row position.
+void build_factor_range(const HostAnalysis &H, const TileSet &T, int32_t lanes, int32_t tb, int32_t te,
+                        FactorTiles *F) {
     const std::vector<int32_t> &rp = H.lu_rp, &ci = H.lu_ci, &dg = H.diag;
+    const int32_t rb = T.rows_ptr[tb];
     F->lanes = lanes;
     F->max_vals = F->max_lents = 0;
     F->hdr.clear();
@@ -534,7 +538,7 @@ void build_factor_tiles(const HostAnalysis &H, const TileSet &T, int32_t lanes, 
     F->cmask.clear();
     F->imp.clear();
     std::vector<int32_t> slot_of(H.n, -1), imp_of(H.n, -1), iloc(H.n, -1);
-    for (int32_t t = 0; t < T.ntiles; ++t) {
+    for (int32_t t = tb; t < te; ++t) {
         const int32_t r0 = T.rows_ptr[t], r1 = T.rows_ptr[t + 1];
         const int32_t nrows = r1 - r0;
         // value area: rows in slot order, then imports' U parts
@@ -563,7 +567,7 @@ void build_factor_tiles(const HostAnalysis &H, const TileSet &T, int32_t lanes, 
             for (int32_t p = rp[r]; p < dg[r]; ++p) {
                 const int32_t c = ci[p];
                 if (slot_of[c] >= 0) {
-                    F->dloc.push_back(F->off[2 * (r0 + slot_of[c])] + (dg[c] - rp[c]));
+                    F->dloc.push_back(F->off[2 * (r0 - rb + slot_of[c])] + (dg[c] - rp[c]));
                     F->dflag.push_back(slot_of[c]);
                 } else {
                     F->dloc.push_back(iloc[c]);
@@ -600,15 +604,63 @@ void build_factor_tiles(const HostAnalysis &H, const TileSet &T, int32_t lanes, 
                         flat = false;
                         break;
                     }
-            if (flat) F->meta[4 * (size_t)q] = ~r;
+            if (flat) F->meta[4 * (size_t)(q - rb)] = ~r;
         }
         F->lptr.push_back((int32_t)F->dloc.size());
-        append_tile_blob(H, T, t, lanes, F);
+        append_tile_blob(H, T, t, lanes, tb, rb, F);
         for (int32_t q = r0; q < r1; ++q) slot_of[T.rows[q]] = -1;
         for (int32_t i = T.imp_ptr[t]; i < T.imp_ptr[t + 1]; ++i) {
             imp_of[T.imp[i]] = -1;
             iloc[T.imp[i]] = -1;
         }
+    }
+}
+
+}  // namespace
+
+// Ranges of tiles are built side by side, each into a part of its own, and the
+// parts concatenated: the tables a tile stages are tile-local, so only the
+// global offsets (a tile's blob, value sources and first L entry, and the L
+// pointers) move by what the earlier parts hold.
+void build_factor_tiles(const HostAnalysis &H, const TileSet &T, int32_t lanes, FactorTiles *F) {
+    std::vector<FactorTiles> part(host_threads());
+    const int nparts = parallel_chunks(T.ntiles, 64, [&](int c, int64_t lo, int64_t hi) {
+        build_factor_range(H, T, lanes, (int32_t)lo, (int32_t)hi, &part[c]);
+    });
+    if (nparts == 1) {
+        *F = std::move(part[0]);
+        return;
+    }
+    FactorTiles &out = *F;
+    out = FactorTiles();
+    out.lanes = lanes;
+    out.lptr.assign(1, 0);
+    for (int c = 0; c < nparts; ++c) {
+        FactorTiles &P = part[c];
+        const int32_t loff = out.lptr.back(), voff = (int32_t)out.vsrc.size(), boff = (int32_t)(out.blob.size() / 4);
+        out.max_vals = std::max(out.max_vals, P.max_vals);
+        out.max_lents = std::max(out.max_lents, P.max_lents);
+        for (int v = 0; v < 4; ++v) out.lds_need[v] = std::max(out.lds_need[v], P.lds_need[v]);
+        for (size_t k = 1; k < P.lptr.size(); ++k) out.lptr.push_back(P.lptr[k] + loff);
+        for (size_t h = 0; h < P.hdr.size(); h += kFactorHdr) {
+            P.hdr[h + kFhBlob] += boff;
+            P.hdr[h + kFhVsrc] += voff;
+            P.hdr[h + kFhL0] += loff;
+        }
+        auto cat = [](auto &dst, auto &src) {
+            dst.insert(dst.end(), src.begin(), src.end());
+            std::vector<typename std::decay_t<decltype(src)>::value_type>().swap(src);
+        };
+        cat(out.meta, P.meta);
+        cat(out.off, P.off);
+        cat(out.dloc, P.dloc);
+        cat(out.dflag, P.dflag);
+        cat(out.match, P.match);
+        cat(out.cmask, P.cmask);
+        cat(out.imp, P.imp);
+        cat(out.hdr, P.hdr);
+        cat(out.blob, P.blob);
+        cat(out.vsrc, P.vsrc);
     }
 }
 
