@@ -334,23 +334,41 @@ static void transpose_and_schedules(HostAnalysis &H) {
 // (degree, index); the concatenated sweep is reversed.  order[i] = input vertex
 // that becomes vertex i.
 std::vector<int32_t> rcm_order(int32_t n, const int32_t *rp, const int32_t *ci) {
-    // symmetric adjacency from the sorted, de-duplicated list of both directions
-    std::vector<int64_t> arcs;
-    arcs.reserve((size_t)rp[n] * 2);
+    // symmetric adjacency: each vertex's neighbours in both directions, sorted and
+    // de-duplicated per vertex (vertices in chunks on threads)
+    std::vector<int64_t> bp((size_t)n + 1, 0);
     for (int32_t i = 0; i < n; ++i)
         for (int32_t p = rp[i]; p < rp[i + 1]; ++p)
             if (ci[p] != i) {
-                arcs.push_back((int64_t)i * n + ci[p]);
-                arcs.push_back((int64_t)ci[p] * n + i);
+                bp[i + 1]++;
+                bp[ci[p] + 1]++;
             }
-    std::sort(arcs.begin(), arcs.end());
-    arcs.erase(std::unique(arcs.begin(), arcs.end()), arcs.end());
-    std::vector<int32_t> gp((size_t)n + 1, 0), gj(arcs.size());
-    for (size_t e = 0; e < arcs.size(); ++e) {
-        gp[arcs[e] / n + 1]++;
-        gj[e] = (int32_t)(arcs[e] % n);
+    for (int32_t i = 0; i < n; ++i) bp[i + 1] += bp[i];
+    std::vector<int32_t> buf((size_t)bp[n]);
+    {
+        std::vector<int64_t> cur(bp.begin(), bp.end() - 1);
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t p = rp[i]; p < rp[i + 1]; ++p)
+                if (ci[p] != i) {
+                    buf[cur[i]++] = ci[p];
+                    buf[cur[ci[p]]++] = i;
+                }
     }
-    for (int32_t i = 0; i < n; ++i) gp[i + 1] += gp[i];
+    std::vector<int32_t> len(n);
+    parallel_chunks(n, 1 << 14, [&](int, int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) {
+            int32_t *b = buf.data() + bp[i], *e = buf.data() + bp[i + 1];
+            std::sort(b, e);
+            len[i] = (int32_t)(std::unique(b, e) - b);
+        }
+    });
+    std::vector<int32_t> gp((size_t)n + 1, 0);
+    for (int32_t i = 0; i < n; ++i) gp[i + 1] = gp[i] + len[i];
+    std::vector<int32_t> gj((size_t)gp[n]);
+    parallel_chunks(n, 1 << 14, [&](int, int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) std::copy(buf.data() + bp[i], buf.data() + bp[i] + len[i], gj.data() + gp[i]);
+    });
+    std::vector<int32_t>().swap(buf);
     auto deg = [&](int32_t v) { return gp[v + 1] - gp[v]; };
     auto before = [&](int32_t a, int32_t b) { return deg(a) != deg(b) ? deg(a) < deg(b) : a < b; };
 
@@ -435,18 +453,20 @@ ilu_status analyze_host(int32_t n, const int32_t *rp, const int32_t *ci, int64_t
     std::vector<int32_t> iq(n);
     for (int32_t i = 0; i < n; ++i) iq[q[i]] = i;
     std::vector<int32_t> qrp((size_t)n + 1, 0), qci((size_t)nnz), qsrc((size_t)nnz);
-    std::vector<std::pair<int32_t, int32_t>> row;
-    for (int32_t i = 0; i < n; ++i) {
-        const int32_t o = q[i];
-        row.clear();
-        for (int32_t p = rp[o]; p < rp[o + 1]; ++p) row.emplace_back(iq[ci[p]], p);
-        std::sort(row.begin(), row.end());
-        qrp[i + 1] = qrp[i] + (int32_t)row.size();
-        for (size_t k = 0; k < row.size(); ++k) {
-            qci[qrp[i] + k] = row[k].first;
-            qsrc[qrp[i] + k] = row[k].second;
+    for (int32_t i = 0; i < n; ++i) qrp[i + 1] = qrp[i] + (rp[q[i] + 1] - rp[q[i]]);
+    parallel_chunks(n, 1 << 14, [&](int, int64_t lo, int64_t hi) {
+        std::vector<std::pair<int32_t, int32_t>> row;
+        for (int32_t i = (int32_t)lo; i < (int32_t)hi; ++i) {
+            const int32_t o = q[i];
+            row.clear();
+            for (int32_t p = rp[o]; p < rp[o + 1]; ++p) row.emplace_back(iq[ci[p]], p);
+            std::sort(row.begin(), row.end());
+            for (size_t k = 0; k < row.size(); ++k) {
+                qci[qrp[i] + k] = row[k].first;
+                qsrc[qrp[i] + k] = row[k].second;
+            }
         }
-    }
+    });
     st = analyze_natural(n, qrp.data(), qci.data(), nnz, k_max, pattern, out, err);
     if (st != ILU_OK) return st;
     HostAnalysis &H = *out;
