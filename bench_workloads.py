@@ -315,8 +315,22 @@ def run(args):
                 row[f"levels_{pat}"] = int(lp.numel() - 1)
                 row[f"device_ms_{pat}"] = round(1e3 * float(np.median(ts)), 2)
             t0 = time.perf_counter()
-            jv.Ilu(A.n, A.row_ptr, A.col_idx, host_only=True)
+            h = jv.Ilu(A.n, A.row_ptr, A.col_idx, host_only=True)
             row["host_analysis_s"] = round(time.perf_counter() - t0, 3)
+            # the backward schedule from the permuted factor pattern
+            sch = h.schedule()
+            urp = torch.from_numpy(sch["lu_row_ptr"]).cuda()
+            uci = torch.from_numpy(sch["lu_col_idx"]).cuda()
+            levels_device(urp, uci, "upper")
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(5):
+                t0 = time.perf_counter()
+                lp, _, _ = levels_device(urp, uci, "upper")
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            row["levels_upper"] = int(lp.numel() - 1)
+            row["device_ms_upper"] = round(1e3 * float(np.median(ts)), 2)
             log(json.dumps(row))
             rows.append(row)
         out.update(matrices=rows)

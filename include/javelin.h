@@ -52,8 +52,11 @@ enum {
 };
 
 /* Dependency pattern used to build level sets (Sec. III; Sec. VII recommends the
- * symmetric one by default). */
-enum { ILU_PATTERN_LOWER_SYM = 0, ILU_PATTERN_LOWER_A = 1 };
+ * symmetric one by default).  ILU_PATTERN_UPPER_A (ilu_levels_device only): row
+ * i depends on every j > i of its own row, levels counted from the last row --
+ * the backward solve's schedule (Sec. VI) when the CSR is the permuted factor
+ * pattern. */
+enum { ILU_PATTERN_LOWER_SYM = 0, ILU_PATTERN_LOWER_A = 1, ILU_PATTERN_UPPER_A = 2 };
 
 /* Storage precision of the factor values used by an apply. */
 enum { ILU_PREC_F64 = 0, ILU_PREC_F32 = 1, ILU_PREC_BF16 = 2 };
@@ -172,14 +175,16 @@ ilu_status ilu_analyze_batched(int32_t count, const ilu_csr *As, const ilu_analy
 
 /* Level sets computed on the device (Sec. II, level scheduling; Sec. III, the
  * dependency graph): row i depends on every j < i with (i, j) in the pattern,
- * and with ILU_PATTERN_LOWER_SYM also on every j < i with (j, i) in it.  Level 0
- * holds the rows with no dependency; a row's level is one more than the deepest
- * level it depends on.  Outputs (device, caller-owned): perm[r] = the row at
+ * and with ILU_PATTERN_LOWER_SYM also on every j < i with (j, i) in it; with
+ * ILU_PATTERN_UPPER_A on every j > i with (i, j) in it.  Level 0 holds the rows
+ * with no dependency; a row's level is one more than the deepest level it
+ * depends on.  Outputs (device, caller-owned): perm[r] = the row at
  * position r of the order by (level, row index), iperm its inverse (both n),
  * level_ptr[l] = first position of level l, level_ptr[n_levels] = n (capacity
  * n + 1); *n_levels (host).  These equal the schedule ilu_analyze computes on
  * the host for the same pattern (its ILU(k) fill pattern S passed here as the
- * CSR).  row_ptr (n + 1) and col_idx (nnz) are device arrays, checked first:
+ * CSR; for ILU_PATTERN_UPPER_A, the permuted factor pattern, whose result is
+ * the backward schedule ulevel_ptr / ulevel_rows).  row_ptr (n + 1) and col_idx (nnz) are device arrays, checked first:
  * ILU_ERR_CSR for row pointers that do not run monotonically from 0 to nnz, or
  * columns unsorted, repeated or out of range.  The diagonal is optional.
  * Allocates one scratch block (about 20 bytes per row; with the symmetric

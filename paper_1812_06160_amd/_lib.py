@@ -15,7 +15,7 @@ STATUS = {0: "ILU_OK", 1: "ILU_ERR_ARG", 2: "ILU_ERR_CSR", 3: "ILU_ERR_NOMEM", 4
           9: "ILU_ERR_STATE", 10: "ILU_ERR_UNSUPPORTED", 11: "ILU_ERR_TIMEOUT"}
 ERR_ARG, ERR_CSR, ERR_NOMEM, ERR_HIP, ERR_ZERO_PIVOT, ERR_NONFINITE = 1, 2, 3, 4, 5, 6
 ERR_NOCONV, ERR_BREAKDOWN, ERR_STATE, ERR_UNSUPPORTED, ERR_TIMEOUT = 7, 8, 9, 10, 11
-PATTERN_LOWER_SYM, PATTERN_LOWER_A = 0, 1
+PATTERN_LOWER_SYM, PATTERN_LOWER_A, PATTERN_UPPER_A = 0, 1, 2
 PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
 PERMUTED_SPACE = 1
 SCHED_AUTO, SCHED_LEVEL, SCHED_SYNCFREE, SCHED_TILED = 0, 1, 2, 3

@@ -15,6 +15,8 @@
 //      level is its own ready flag: -1 until written) and publishes its own;
 //   4. keys (level << 32 | row) are radix-sorted, which gives the stable order,
 //      and the level pointers are read off the sorted keys.
+// The same sweep on the strictly upper part, from the last row down, gives the
+// backward solve's schedule (Sec. VI) of a permuted factor pattern.
 #include <hip/hip_runtime.h>
 #include <hipcub/device/device_radix_sort.hpp>
 #include <hipcub/device/device_scan.hpp>
@@ -90,7 +92,8 @@ __global__ void k_lv_fill(int32_t n, int32_t *level, int32_t *cnt, int32_t *fill
 
 // One lane per row; blocks claim consecutive 256-row slots in start order, so a
 // lane only waits on rows of blocks that started earlier (or of earlier lanes of
-// its own block), which always progress.  A lane polls without blocking its
+// its own block), which always progress.  With the upper pattern the slots run
+// from the last row down, so the same holds for dependencies on later rows.  A lane polls without blocking its
 // wave.  It scans its dependencies eight at a time (all eight loads in flight
 // together), folds the published levels and keeps up to kLvPend pending
 // dependencies in registers; later passes re-read only those (one round of
@@ -152,14 +155,15 @@ __device__ __forceinline__ bool lv_scan(int32_t *cur, int32_t end, int32_t *lev,
 __global__ __launch_bounds__(kLvBlock) void k_lv_sweep(int32_t n, const int32_t *rp, const int32_t *ci,
                                                        const int32_t *tptr, const int32_t *tdep,
                                                        int32_t *level, int32_t *counter, int32_t *info,
-                                                       uint32_t *maxlev, const int32_t *err) {
+                                                       uint32_t *maxlev, const int32_t *err, int32_t upper) {
     if (*err) return;   // the pattern failed its check: nothing is read
     __shared__ int32_t slot;
     if (threadIdx.x == 0) slot = atomicAdd(counter, 1);
     __syncthreads();
-    const int64_t i64 = (int64_t)slot * kLvBlock + threadIdx.x;
-    bool done = i64 >= n;
-    const int32_t i = done ? 0 : (int32_t)i64;
+    // slots run from the first row, or (upper pattern) from the last row down
+    const int64_t s64 = (int64_t)slot * kLvBlock + threadIdx.x;
+    bool done = s64 >= n;
+    const int32_t i = done ? 0 : (int32_t)(upper ? n - 1 - s64 : s64);
     int32_t p = done ? 0 : rp[i], pe = done ? 0 : rp[i + 1];
     int32_t q = (done || !tptr) ? 0 : tptr[i], qe = (done || !tptr) ? 0 : tptr[i + 1];
     int32_t lev = 0;
@@ -186,7 +190,11 @@ __global__ __launch_bounds__(kLvBlock) void k_lv_sweep(int32_t n, const int32_t 
             }
             // row entries (columns below i are dependencies), then the transposed ones
             if (!scanned)
-                scanned = lv_scan(&p, pe, &lev, level, [&](int32_t u) { const int32_t c = ci[u]; return c < i ? c : -1; },
+                scanned = lv_scan(&p, pe, &lev, level,
+                                  [&](int32_t u) {
+                                      const int32_t c = ci[u];
+                                      return (upper ? c > i : c < i) ? c : -1;
+                                  },
                                   pend) &&
                           lv_scan(&q, qe, &lev, level, [&](int32_t u) { return tdep[u]; }, pend);
             if (scanned) {
@@ -219,7 +227,7 @@ __global__ __launch_bounds__(kLvBlock) void k_lv_sweep(int32_t n, const int32_t 
         nap = min(2 * nap, kLvSleepMax);
     }
     // deepest level: one atomic per wave
-    int32_t m = i64 < n ? lev : 0;
+    int32_t m = s64 < n ? lev : 0;
     for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
     if ((threadIdx.x & 63) == 0) atomicMax(maxlev, (uint32_t)m);
 }
@@ -258,9 +266,9 @@ extern "C" ilu_status ilu_levels_device(int32_t n, int64_t nnz, const int32_t *r
     if (n <= 0 || n >= (1 << 30) || nnz < 0 || nnz >= ((int64_t)1 << 31) || !row_ptr || (nnz > 0 && !col_idx) ||
         !level_ptr || !perm || !iperm || !n_levels)
         return fail(ILU_ERR_ARG, "ilu_levels_device: bad argument");
-    if (pattern != ILU_PATTERN_LOWER_SYM && pattern != ILU_PATTERN_LOWER_A)
+    if (pattern != ILU_PATTERN_LOWER_SYM && pattern != ILU_PATTERN_LOWER_A && pattern != ILU_PATTERN_UPPER_A)
         return fail(ILU_ERR_ARG, "ilu_levels_device: unknown pattern");
-    const bool sym = pattern == ILU_PATTERN_LOWER_SYM;
+    const bool sym = pattern == ILU_PATTERN_LOWER_SYM, upper = pattern == ILU_PATTERN_UPPER_A;
     // Levels are below n < 2^30, so the sort keys need 32 + bits(n - 1) bits.
     int end_bit = 32;
     while (end_bit < 62 && ((int64_t)(n - 1) >> (end_bit - 32)) != 0) ++end_bit;
@@ -316,7 +324,7 @@ extern "C" ilu_status ilu_levels_device(int32_t n, int64_t nnz, const int32_t *r
         k_lv_upper_scatter<<<grid_of(n), kLvBlock, 0, stream>>>(n, row_ptr, col_idx, tptr, fill, tdep, err);
     }
     k_lv_sweep<<<grid_of(n), kLvBlock, 0, stream>>>(n, row_ptr, col_idx, tptr, tdep, level, counter, info, maxlev,
-                                                    err);
+                                                    err, upper ? 1 : 0);
     k_lv_keys<<<grid_of(n), kLvBlock, 0, stream>>>(n, level, keys, err, info);
     if ((e = hipcub::DeviceRadixSort::SortKeys(base + o_sort, sort_b, keys, keys2, n, 0, end_bit, stream)) !=
         hipSuccess)

@@ -41,8 +41,10 @@ def _rhs_shape(t):
 def levels_device(row_ptr: torch.Tensor, col_idx: torch.Tensor, pattern: str = "sym"):
     """Level sets of a CSR pattern computed on the GPU (ilu_levels_device).
 
-    row_ptr / col_idx: int32 device tensors.  Returns (level_ptr, perm, iperm) as
-    int32 device tensors, level_ptr trimmed to n_levels + 1 entries."""
+    row_ptr / col_idx: int32 device tensors; pattern "sym" (lower(S + S^T)),
+    "lower" (lower(S)) or "upper" (the strictly upper part, levels from the last
+    row: the backward schedule).  Returns (level_ptr, perm, iperm) as int32 device
+    tensors, level_ptr trimmed to n_levels + 1 entries."""
     lib = L.load()
     n = row_ptr.numel() - 1
     dev = row_ptr.device
@@ -50,7 +52,7 @@ def levels_device(row_ptr: torch.Tensor, col_idx: torch.Tensor, pattern: str = "
     perm = torch.empty(n, dtype=torch.int32, device=dev)
     iperm = torch.empty(n, dtype=torch.int32, device=dev)
     nl = C.c_int32(0)
-    pat = L.PATTERN_LOWER_SYM if pattern == "sym" else L.PATTERN_LOWER_A
+    pat = {"sym": L.PATTERN_LOWER_SYM, "lower": L.PATTERN_LOWER_A, "upper": L.PATTERN_UPPER_A}[pattern]
     L.check(lib.ilu_levels_device(int(n), int(col_idx.numel()), _ptr(row_ptr), _ptr(col_idx), pat, _ptr(lp),
                                   _ptr(perm), _ptr(iperm), C.byref(nl), _stream()), "ilu_levels_device")
     return lp[:nl.value + 1], perm, iperm

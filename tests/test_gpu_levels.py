@@ -2,7 +2,9 @@
 level schedule (Sec. II peeling of lower(S) or lower(S + S^T)): perm and the level
 pointers bit for bit, on small structured and random patterns, degenerate cases
 (one row, no dependencies, one long chain), ILU(1) fill patterns, both dependency
-patterns, the full-size 128^3 Laplacian and random_1m, and the CSR errors."""
+patterns, the full-size 128^3 Laplacian and random_1m, and the CSR errors; and the
+upper pattern against the backward schedule of the permuted factor pattern and the
+oracle's upper levels."""
 import numpy as np
 import pytest
 import torch
@@ -17,9 +19,13 @@ def dev(x):
     return torch.from_numpy(np.ascontiguousarray(x, dtype=np.int32)).cuda()
 
 
-def run(jv, n, rp, ci, sym=True):
-    lp, perm, ip = jv.levels_device(dev(rp), dev(ci), "sym" if sym else "lower")
+def run_pattern(jv, rp, ci, pattern):
+    lp, perm, ip = jv.levels_device(dev(rp), dev(ci), pattern)
     return lp.cpu().numpy(), perm.cpu().numpy(), ip.cpu().numpy()
+
+
+def run(jv, n, rp, ci, sym=True):
+    return run_pattern(jv, rp, ci, "sym" if sym else "lower")
 
 
 def check(jv, n, rp, ci, sym=True, k_max=0):
@@ -119,3 +125,47 @@ def test_levels_laplace3d_128_full(jv):
 def test_levels_random_1m_full(jv, sym):
     A, _ = synth.workload(4)
     check(jv, A.n, A.row_ptr, A.col_idx, sym=sym)
+
+
+UPPER_CASES = ["laplace2d_64", "convdiff3d_12", "random_nonsym", "random_missing_diag", "heavy_rows"]
+
+
+@pytest.mark.parametrize("name", UPPER_CASES)
+def test_upper_levels_match_backward_schedule(jv, name):
+    # the backward schedule of the permuted factor pattern, and the upper levels
+    # of the input pattern as given
+    A = CASES[name]()
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    lp, perm, ip = run_pattern(jv, an.lu_rp, an.lu_ci, "upper")
+    np.testing.assert_array_equal(lp, an.ulevel_ptr)
+    np.testing.assert_array_equal(perm, an.ulevel_rows)
+    ulev, nul = O.upper_levels(A.n, A.row_ptr.astype(np.int32), A.col_idx.astype(np.int32))
+    rperm, riperm, rptr = O.sort_by_key(ulev, nul)
+    lp, perm, ip = run_pattern(jv, A.row_ptr, A.col_idx, "upper")
+    np.testing.assert_array_equal(lp, rptr)
+    np.testing.assert_array_equal(perm, rperm)
+    np.testing.assert_array_equal(ip, riperm)
+
+
+def test_upper_levels_chain_and_ilu1(jv):
+    # upper bidiagonal: one level per row, the last row first
+    n = 3000
+    rp = np.concatenate([2 * np.arange(n), [2 * n - 1]])
+    ci = np.concatenate([np.stack([np.arange(n - 1), np.arange(1, n)], 1).ravel(), [n - 1]])
+    lp, perm, _ = run_pattern(jv, rp, ci, "upper")
+    np.testing.assert_array_equal(lp, np.arange(n + 1))
+    np.testing.assert_array_equal(perm, np.arange(n)[::-1])
+    A = synth.convdiff3d(10)
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=1)
+    lp, perm, _ = run_pattern(jv, an.lu_rp, an.lu_ci, "upper")
+    np.testing.assert_array_equal(lp, an.ulevel_ptr)
+    np.testing.assert_array_equal(perm, an.ulevel_rows)
+
+
+@pytest.mark.slow
+def test_upper_levels_random_1m_full(jv):
+    A, _ = synth.workload(4)
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    lp, perm, _ = run_pattern(jv, an.lu_rp, an.lu_ci, "upper")
+    np.testing.assert_array_equal(lp, an.ulevel_ptr)
+    np.testing.assert_array_equal(perm, an.ulevel_rows)
