@@ -331,6 +331,19 @@ def run(args):
                 ts.append(time.perf_counter() - t0)
             row["levels_upper"] = int(lp.numel() - 1)
             row["device_ms_upper"] = round(1e3 * float(np.median(ts)), 2)
+            # the permuted structure in the device level order (the workloads store
+            # every diagonal, so A's pattern is S of ILU(0))
+            from paper_1812_06160_amd.ilu import permute_device
+            _, perm, iperm = levels_device(rp, ci, "sym")
+            permute_device(rp, ci, perm, iperm)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(5):
+                t0 = time.perf_counter()
+                permute_device(rp, ci, perm, iperm)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            row["device_ms_permute"] = round(1e3 * float(np.median(ts)), 2)
             log(json.dumps(row))
             rows.append(row)
         out.update(matrices=rows)

@@ -196,6 +196,24 @@ ilu_status ilu_levels_device(int32_t n, int64_t nnz, const int32_t *row_ptr, con
                              int32_t pattern, int32_t *level_ptr, int32_t *perm, int32_t *iperm,
                              int32_t *n_levels, hipStream_t stream);
 
+/* Permuted structure on the device (Sec. III: A copied into the level-ordered
+ * CSR of L and U): row r of the output is row perm[r] of the input pattern, its
+ * columns renamed c -> iperm[c] and sorted ascending; out_src[q] is the input
+ * entry that output entry q came from, diag_pos[r] the position of column r in
+ * output row r (-1 if absent).  With the ILU(k) pattern S and the level order
+ * of ilu_levels_device this is the factor pattern P S P^T, its diagonal
+ * positions and its entry map, as ilu_analyze builds them on the host.  All
+ * arrays are device, caller-owned: row_ptr (n + 1), col_idx (nnz), perm and
+ * iperm (n), out_row_ptr (n + 1), out_col_idx and out_src (nnz), diag_pos (n).
+ * ILU_ERR_CSR for an invalid pattern (as ilu_levels_device), ILU_ERR_ARG when
+ * perm is not a permutation with inverse iperm; the outputs are then
+ * unspecified.  Allocates one scratch block (about 8 bytes per entry plus the
+ * sort's temporaries) and frees it; returns after the work on `stream` has
+ * finished. */
+ilu_status ilu_permute_device(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                              const int32_t *perm, const int32_t *iperm, int32_t *out_row_ptr,
+                              int32_t *out_col_idx, int32_t *out_src, int32_t *diag_pos, hipStream_t stream);
+
 /* Row and entry offsets of matrix i in a batched handle (host arrays of count+1). */
 ilu_status ilu_batch_offsets(ilu_handle h, int64_t *row_off, int64_t *nnz_off);
 

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 #include <hipcub/device/device_radix_sort.hpp>
 #include <hipcub/device/device_scan.hpp>
+#include <hipcub/device/device_segmented_radix_sort.hpp>
 
 #include <algorithm>
 #include <cstdint>
@@ -254,6 +255,47 @@ __global__ void k_lv_out(int32_t n, const uint64_t *keys, int32_t *perm, int32_t
 
 unsigned grid_of(int64_t n) { return (unsigned)((n + kLvBlock - 1) / kLvBlock); }
 
+// Permuted structure P S P^T (Sec. III: the parallel copy into the level-ordered
+// CSR of L and U): row r of the result is row perm[r] of S with its columns
+// renamed by iperm and sorted.  err bit 8: perm is not a permutation.
+__global__ void k_pm_check(int32_t n, const int32_t *perm, const int32_t *iperm, int32_t *err) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int32_t i = perm[r];
+    if (i < 0 || i >= n || iperm[i] != (int32_t)r) atomicOr(err, 8);
+}
+
+__global__ void k_pm_len(int32_t n, const int32_t *rp, const int32_t *perm, int32_t *len, const int32_t *err) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > n) return;
+    // zero lengths after a failed check: the scan and the sort then see empty rows
+    len[r] = r < n && !*err ? rp[perm[r] + 1] - rp[perm[r]] : 0;
+}
+
+__global__ void k_pm_gather(int32_t n, const int32_t *rp, const int32_t *ci, const int32_t *perm,
+                            const int32_t *iperm, const int32_t *orp, int32_t *key, int32_t *src, const int32_t *err) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n || *err) return;
+    const int32_t i = perm[r], o = orp[r];
+    for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
+        key[o + (p - rp[i])] = iperm[ci[p]];
+        src[o + (p - rp[i])] = p;
+    }
+}
+
+// position of column r in row r (binary search of the sorted row), -1 if absent
+__global__ void k_pm_diag(int32_t n, const int32_t *orp, const int32_t *oci, int32_t *diag, const int32_t *err) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n || *err) return;
+    int32_t lo = orp[r], hi = orp[r + 1];
+    while (lo < hi) {
+        const int32_t mid = lo + (hi - lo) / 2;
+        if (oci[mid] < r) lo = mid + 1;
+        else hi = mid;
+    }
+    diag[r] = lo < orp[r + 1] && oci[lo] == r ? lo : -1;
+}
+
 }  // namespace
 
 }  // namespace jv
@@ -340,5 +382,72 @@ extern "C" ilu_status ilu_levels_device(int32_t n, int64_t nnz, const int32_t *r
     if (h[0] & 4) return fail(ILU_ERR_CSR, "ilu_levels_device: columns unsorted or repeated");
     if (h[16 + kInfoAbort]) return fail(ILU_ERR_TIMEOUT, "ilu_levels_device: a dependency wait expired");
     *n_levels = h[48] + 1;
+    return ILU_OK;
+}
+
+extern "C" ilu_status ilu_permute_device(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                                         const int32_t *perm, const int32_t *iperm, int32_t *out_row_ptr,
+                                         int32_t *out_col_idx, int32_t *out_src, int32_t *diag_pos,
+                                         hipStream_t stream) {
+    if (n <= 0 || n >= (1 << 30) || nnz < 0 || nnz >= ((int64_t)1 << 31) || !row_ptr || (nnz > 0 && !col_idx) ||
+        !perm || !iperm || !out_row_ptr || (nnz > 0 && (!out_col_idx || !out_src)) || !diag_pos)
+        return fail(ILU_ERR_ARG, "ilu_permute_device: bad argument");
+    int kbits = 1;
+    while (kbits < 31 && ((int64_t)(n - 1) >> kbits) != 0) ++kbits;
+    hipError_t e;
+    size_t scan_b = 0, sort_b = 0;
+    if ((e = hipcub::DeviceScan::ExclusiveSum(nullptr, scan_b, (int32_t *)nullptr, (int32_t *)nullptr, n + 1,
+                                              stream)) != hipSuccess)
+        return hip_fail(e, "ilu_permute_device: scan size");
+    if (nnz > 0 &&
+        (e = hipcub::DeviceSegmentedRadixSort::SortPairs(nullptr, sort_b, (int32_t *)nullptr, (int32_t *)nullptr,
+                                                         (int32_t *)nullptr, (int32_t *)nullptr, (int)nnz, n,
+                                                         (int32_t *)nullptr, (int32_t *)nullptr, 0, kbits,
+                                                         stream)) != hipSuccess)
+        return hip_fail(e, "ilu_permute_device: sort size");
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t o_len = 256, o_key = o_len + al(((size_t)n + 1) * 4), o_src = o_key + al((size_t)nnz * 4 + 4),
+                 o_scan = o_src + al((size_t)nnz * 4 + 4), o_sort = o_scan + al(scan_b),
+                 total = o_sort + al(std::max<size_t>(sort_b, 1));
+    char *base = nullptr;
+    if ((e = hipMalloc((void **)&base, total)) != hipSuccess)
+        return e == hipErrorOutOfMemory ? fail(ILU_ERR_NOMEM, "ilu_permute_device: device memory")
+                                        : hip_fail(e, "ilu_permute_device: allocate");
+    struct Guard {
+        void *p;
+        hipStream_t s;
+        ~Guard() {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(p);
+        }
+    } g{base, stream};
+    int32_t *err = reinterpret_cast<int32_t *>(base);
+    int32_t *len = reinterpret_cast<int32_t *>(base + o_len);
+    int32_t *key = reinterpret_cast<int32_t *>(base + o_key), *src = reinterpret_cast<int32_t *>(base + o_src);
+    // as for the level sets: every kernel after the checks does nothing once one
+    // has failed, and one synchronisation at the end reports it
+    if ((e = hipMemsetAsync(err, 0, 64 * sizeof(int32_t), stream)) != hipSuccess)
+        return hip_fail(e, "ilu_permute_device: clear");
+    k_lv_check<<<grid_of(n), kLvBlock, 0, stream>>>(n, nnz, row_ptr, col_idx, err);
+    k_pm_check<<<grid_of(n), kLvBlock, 0, stream>>>(n, perm, iperm, err);
+    k_pm_len<<<grid_of((int64_t)n + 1), kLvBlock, 0, stream>>>(n, row_ptr, perm, len, err);
+    if ((e = hipcub::DeviceScan::ExclusiveSum(base + o_scan, scan_b, len, out_row_ptr, n + 1, stream)) != hipSuccess)
+        return hip_fail(e, "ilu_permute_device: scan");
+    if (nnz > 0) {
+        k_pm_gather<<<grid_of(n), kLvBlock, 0, stream>>>(n, row_ptr, col_idx, perm, iperm, out_row_ptr, key, src, err);
+        if ((e = hipcub::DeviceSegmentedRadixSort::SortPairs(base + o_sort, sort_b, key, out_col_idx, src, out_src,
+                                                             (int)nnz, n, out_row_ptr, out_row_ptr + 1, 0, kbits,
+                                                             stream)) != hipSuccess)
+            return hip_fail(e, "ilu_permute_device: sort");
+    }
+    k_pm_diag<<<grid_of(n), kLvBlock, 0, stream>>>(n, out_row_ptr, out_col_idx, diag_pos, err);
+    int32_t h = 0;
+    if ((e = hipGetLastError()) != hipSuccess || (e = hipMemcpyAsync(&h, err, 4, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess)
+        return hip_fail(e, "ilu_permute_device: run");
+    if (h & 1) return fail(ILU_ERR_CSR, "ilu_permute_device: row_ptr not monotone or not ending at nnz");
+    if (h & 2) return fail(ILU_ERR_CSR, "ilu_permute_device: column index out of range");
+    if (h & 4) return fail(ILU_ERR_CSR, "ilu_permute_device: columns unsorted or repeated");
+    if (h & 8) return fail(ILU_ERR_ARG, "ilu_permute_device: perm / iperm not a permutation and its inverse");
     return ILU_OK;
 }

@@ -58,6 +58,22 @@ def levels_device(row_ptr: torch.Tensor, col_idx: torch.Tensor, pattern: str = "
     return lp[:nl.value + 1], perm, iperm
 
 
+def permute_device(row_ptr: torch.Tensor, col_idx: torch.Tensor, perm: torch.Tensor, iperm: torch.Tensor):
+    """Permuted structure P S P^T on the GPU (ilu_permute_device): returns
+    (row_ptr, col_idx, src, diag_pos) as int32 device tensors."""
+    lib = L.load()
+    n = row_ptr.numel() - 1
+    nnz = col_idx.numel()
+    dev = row_ptr.device
+    orp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    oci = torch.empty(nnz, dtype=torch.int32, device=dev)
+    src = torch.empty(nnz, dtype=torch.int32, device=dev)
+    dp = torch.empty(n, dtype=torch.int32, device=dev)
+    L.check(lib.ilu_permute_device(int(n), int(nnz), _ptr(row_ptr), _ptr(col_idx), _ptr(perm), _ptr(iperm), _ptr(orp),
+                                   _ptr(oci), _ptr(src), _ptr(dp), _stream()), "ilu_permute_device")
+    return orp, oci, src, dp
+
+
 class Ilu:
     """Analysis handle: ILU(k_max) pattern, level schedule and permuted structure of A."""
 

@@ -169,3 +169,71 @@ def test_upper_levels_random_1m_full(jv):
     lp, perm, _ = run_pattern(jv, an.lu_rp, an.lu_ci, "upper")
     np.testing.assert_array_equal(lp, an.ulevel_ptr)
     np.testing.assert_array_equal(perm, an.ulevel_rows)
+
+
+def dev_perm(an):
+    return dev(an.perm), dev(an.iperm)
+
+
+def check_permute(jv, an, k0_src=True):
+    p, ip = dev_perm(an)
+    orp, oci, src, dp = [t.cpu().numpy() for t in jv.permute_device(dev(an.s_rp), dev(an.s_ci), p, ip)]
+    np.testing.assert_array_equal(orp, an.lu_rp)
+    np.testing.assert_array_equal(oci, an.lu_ci)
+    np.testing.assert_array_equal(dp, an.diag_pos)
+    if k0_src:
+        # S is the canonical A: its entry map to A's input entries gives the factor's
+        np.testing.assert_array_equal(np.asarray(an.a_src)[src], an.lu_src)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_permute_matches_oracle(jv, name):
+    A = CASES[name]()
+    check_permute(jv, O.analyze(A.n, A.row_ptr, A.col_idx))
+
+
+def test_permute_fill_patterns_and_errors(jv):
+    A = synth.convdiff3d(10)
+    check_permute(jv, O.analyze(A.n, A.row_ptr, A.col_idx, k_max=1), k0_src=False)
+    B = synth.random_sparse(1500, 3e-3, np.random.default_rng(3))
+    check_permute(jv, O.analyze(B.n, B.row_ptr, B.col_idx, k_max=2, sym=False), k0_src=False)
+    # identity permutation on a pattern without some diagonals: diag_pos -1 there
+    C = synth.random_sparse(800, 4e-3, np.random.default_rng(5), drop_diag_frac=0.5)
+    ident = dev(np.arange(C.n))
+    orp, oci, _, dp = [t.cpu().numpy() for t in jv.permute_device(dev(C.row_ptr), dev(C.col_idx), ident, ident)]
+    np.testing.assert_array_equal(orp, C.row_ptr)
+    np.testing.assert_array_equal(oci, C.col_idx)
+    for r in range(C.n):
+        cols = C.col_idx[C.row_ptr[r]:C.row_ptr[r + 1]]
+        assert dp[r] == (C.row_ptr[r] + int(np.searchsorted(cols, r)) if r in cols else -1)
+    # a perm that is not a permutation, and an iperm that is not its inverse
+    bad = np.arange(C.n)
+    bad[3] = 4
+    with pytest.raises(jv.IluError) as e:
+        jv.permute_device(dev(C.row_ptr), dev(C.col_idx), dev(bad), ident)
+    assert e.value.status == "ILU_ERR_ARG"
+    ci = C.col_idx.copy()
+    ci[-1] = C.n
+    with pytest.raises(jv.IluError) as e:
+        jv.permute_device(dev(C.row_ptr), dev(ci), ident, ident)
+    assert e.value.status == "ILU_ERR_CSR"
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("wid", [2, 4])
+def test_device_schedule_pipeline_full(jv, wid):
+    # levels, permuted factor pattern and backward schedule all on the device,
+    # against the oracle's analysis (128^3 Laplacian, random_1m)
+    A, _ = synth.workload(wid)
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    srp, sci = dev(an.s_rp), dev(an.s_ci)
+    lp, perm, iperm = jv.levels_device(srp, sci, "sym")
+    np.testing.assert_array_equal(lp.cpu().numpy(), an.level_ptr)
+    orp, oci, src, dp = jv.permute_device(srp, sci, perm, iperm)
+    np.testing.assert_array_equal(orp.cpu().numpy(), an.lu_rp)
+    np.testing.assert_array_equal(oci.cpu().numpy(), an.lu_ci)
+    np.testing.assert_array_equal(dp.cpu().numpy(), an.diag_pos)
+    np.testing.assert_array_equal(np.asarray(an.a_src)[src.cpu().numpy()], an.lu_src)
+    ulp, urows, _ = jv.levels_device(orp, oci, "upper")
+    np.testing.assert_array_equal(ulp.cpu().numpy(), an.ulevel_ptr)
+    np.testing.assert_array_equal(urows.cpu().numpy(), an.ulevel_rows)
