@@ -214,6 +214,19 @@ ilu_status ilu_permute_device(int32_t n, int64_t nnz, const int32_t *row_ptr, co
                               const int32_t *perm, const int32_t *iperm, int32_t *out_row_ptr,
                               int32_t *out_col_idx, int32_t *out_src, int32_t *diag_pos, hipStream_t stream);
 
+/* Transposed structure on the device (the transposed views the adjoint's
+ * solves run on, Sec. VI): t_row_ptr / t_col_idx is the CSR of the pattern's
+ * transpose with columns ascending, t_map[q] the input entry that transposed
+ * entry q came from, t_diag[j] the position of column j in transposed row j (-1
+ * if absent).  Device arrays, caller-owned: row_ptr and t_row_ptr (n + 1),
+ * col_idx, t_col_idx and t_map (nnz), t_diag (n).  ILU_ERR_CSR for an invalid
+ * pattern (outputs then unspecified).  Allocates one scratch block (about 8
+ * bytes per row and per entry plus the sort's temporaries) and frees it;
+ * returns after the work on `stream` has finished. */
+ilu_status ilu_transpose_device(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                                int32_t *t_row_ptr, int32_t *t_col_idx, int32_t *t_map, int32_t *t_diag,
+                                hipStream_t stream);
+
 /* Row and entry offsets of matrix i in a batched handle (host arrays of count+1). */
 ilu_status ilu_batch_offsets(ilu_handle h, int64_t *row_off, int64_t *nnz_off);
 

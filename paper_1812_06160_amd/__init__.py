@@ -8,7 +8,7 @@ csrc/); this package only marshals arguments.  Build with
 from . import _lib
 from ._lib import IluError, load
 
-__all__ = ["load", "Ilu", "IluApply", "IluError", "build", "levels_device", "permute_device"]
+__all__ = ["load", "Ilu", "IluApply", "IluError", "build", "levels_device", "permute_device", "transpose_device"]
 
 
 def __getattr__(name):
@@ -23,6 +23,9 @@ def __getattr__(name):
     if name == "permute_device":
         from .ilu import permute_device
         return permute_device
+    if name == "transpose_device":
+        from .ilu import transpose_device
+        return transpose_device
     if name == "IluApply":
         from .autograd import IluApply
         return IluApply

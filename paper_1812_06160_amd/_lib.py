@@ -27,7 +27,7 @@ STAGES = ["factor", "forward", "backward", "spmv", "factor_call", "apply_call"]
 
 # exported symbols that include/javelin.h declares
 SYMBOLS = [
-    "ilu_analyze", "ilu_analyze_batched", "ilu_levels_device", "ilu_permute_device", "ilu_batch_offsets", "ilu_get_info", "ilu_copy_schedule", "ilu_copy_tiles",
+    "ilu_analyze", "ilu_analyze_batched", "ilu_levels_device", "ilu_permute_device", "ilu_transpose_device", "ilu_batch_offsets", "ilu_get_info", "ilu_copy_schedule", "ilu_copy_tiles",
     "ilu_copy_tail",
     "ilu_copy_factor_tail",
     "ilu_factor", "ilu_factor_values", "ilu_copy_factor", "ilu_copy_factor_prec", "ilu_apply", "ilu_get_status",
@@ -88,6 +88,7 @@ def load(path: str = LIB_PATH):
         "ilu_batch_offsets": [H, vp, vp],
         "ilu_levels_device": [i32, i64, vp, vp, i32, vp, vp, vp, C.POINTER(i32), vp],
         "ilu_permute_device": [i32, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp],
+        "ilu_transpose_device": [i32, i64, vp, vp, vp, vp, vp, vp, vp],
         "ilu_get_info": [H, C.POINTER(Info)],
         "ilu_copy_schedule": [H] + [vp] * 11,
         "ilu_copy_tiles": [H, i32, vp, vp, vp],

@@ -283,6 +283,26 @@ __global__ void k_pm_gather(int32_t n, const int32_t *rp, const int32_t *ci, con
     }
 }
 
+// Transposed structure: entries counted per column, then scattered to their
+// column's range in any order (a segmented sort by row restores the order).
+__global__ void k_tr_count(int32_t n, const int32_t *rp, const int32_t *ci, int32_t *cnt, const int32_t *err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || *err) return;
+    for (int32_t p = rp[i]; p < rp[i + 1]; ++p) atomicAdd(&cnt[ci[p]], 1);
+}
+
+__global__ void k_tr_scatter(int32_t n, const int32_t *rp, const int32_t *ci, const int32_t *trp, int32_t *fill,
+                             int32_t *key, int32_t *map, const int32_t *err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || *err) return;
+    for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
+        const int32_t j = ci[p];
+        const int32_t o = trp[j] + atomicAdd(&fill[j], 1);
+        key[o] = (int32_t)i;
+        map[o] = p;
+    }
+}
+
 // position of column r in row r (binary search of the sorted row), -1 if absent
 __global__ void k_pm_diag(int32_t n, const int32_t *orp, const int32_t *oci, int32_t *diag, const int32_t *err) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -449,5 +469,68 @@ extern "C" ilu_status ilu_permute_device(int32_t n, int64_t nnz, const int32_t *
     if (h & 2) return fail(ILU_ERR_CSR, "ilu_permute_device: column index out of range");
     if (h & 4) return fail(ILU_ERR_CSR, "ilu_permute_device: columns unsorted or repeated");
     if (h & 8) return fail(ILU_ERR_ARG, "ilu_permute_device: perm / iperm not a permutation and its inverse");
+    return ILU_OK;
+}
+
+extern "C" ilu_status ilu_transpose_device(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                                           int32_t *t_row_ptr, int32_t *t_col_idx, int32_t *t_map, int32_t *t_diag,
+                                           hipStream_t stream) {
+    if (n <= 0 || n >= (1 << 30) || nnz < 0 || nnz >= ((int64_t)1 << 31) || !row_ptr || (nnz > 0 && !col_idx) ||
+        !t_row_ptr || (nnz > 0 && (!t_col_idx || !t_map)) || !t_diag)
+        return fail(ILU_ERR_ARG, "ilu_transpose_device: bad argument");
+    int kbits = 1;
+    while (kbits < 31 && ((int64_t)(n - 1) >> kbits) != 0) ++kbits;
+    hipError_t e;
+    size_t scan_b = 0, sort_b = 0;
+    if ((e = hipcub::DeviceScan::ExclusiveSum(nullptr, scan_b, (int32_t *)nullptr, (int32_t *)nullptr, n + 1,
+                                              stream)) != hipSuccess)
+        return hip_fail(e, "ilu_transpose_device: scan size");
+    if (nnz > 0 &&
+        (e = hipcub::DeviceSegmentedRadixSort::SortPairs(nullptr, sort_b, (int32_t *)nullptr, (int32_t *)nullptr,
+                                                         (int32_t *)nullptr, (int32_t *)nullptr, (int)nnz, n,
+                                                         (int32_t *)nullptr, (int32_t *)nullptr, 0, kbits,
+                                                         stream)) != hipSuccess)
+        return hip_fail(e, "ilu_transpose_device: sort size");
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t o_cnt = 256, o_fill = o_cnt + al(((size_t)n + 1) * 4), o_key = o_fill + al((size_t)n * 4),
+                 o_map = o_key + al((size_t)nnz * 4 + 4), o_scan = o_map + al((size_t)nnz * 4 + 4),
+                 o_sort = o_scan + al(scan_b), total = o_sort + al(std::max<size_t>(sort_b, 1));
+    char *base = nullptr;
+    if ((e = hipMalloc((void **)&base, total)) != hipSuccess)
+        return e == hipErrorOutOfMemory ? fail(ILU_ERR_NOMEM, "ilu_transpose_device: device memory")
+                                        : hip_fail(e, "ilu_transpose_device: allocate");
+    struct Guard {
+        void *p;
+        hipStream_t s;
+        ~Guard() {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(p);
+        }
+    } g{base, stream};
+    int32_t *err = reinterpret_cast<int32_t *>(base);
+    int32_t *cnt = reinterpret_cast<int32_t *>(base + o_cnt), *fill = reinterpret_cast<int32_t *>(base + o_fill);
+    int32_t *key = reinterpret_cast<int32_t *>(base + o_key), *map = reinterpret_cast<int32_t *>(base + o_map);
+    if ((e = hipMemsetAsync(err, 0, 64 * sizeof(int32_t), stream)) != hipSuccess)
+        return hip_fail(e, "ilu_transpose_device: clear");
+    k_lv_check<<<grid_of(n), kLvBlock, 0, stream>>>(n, nnz, row_ptr, col_idx, err);
+    k_lv_fill<<<grid_of((int64_t)n + 1), kLvBlock, 0, stream>>>(n, t_diag, cnt, fill);   // t_diag is overwritten below
+    k_tr_count<<<grid_of(n), kLvBlock, 0, stream>>>(n, row_ptr, col_idx, cnt, err);
+    if ((e = hipcub::DeviceScan::ExclusiveSum(base + o_scan, scan_b, cnt, t_row_ptr, n + 1, stream)) != hipSuccess)
+        return hip_fail(e, "ilu_transpose_device: scan");
+    if (nnz > 0) {
+        k_tr_scatter<<<grid_of(n), kLvBlock, 0, stream>>>(n, row_ptr, col_idx, t_row_ptr, fill, key, map, err);
+        if ((e = hipcub::DeviceSegmentedRadixSort::SortPairs(base + o_sort, sort_b, key, t_col_idx, map, t_map, (int)nnz,
+                                                             n, t_row_ptr, t_row_ptr + 1, 0, kbits, stream)) !=
+            hipSuccess)
+            return hip_fail(e, "ilu_transpose_device: sort");
+    }
+    k_pm_diag<<<grid_of(n), kLvBlock, 0, stream>>>(n, t_row_ptr, t_col_idx, t_diag, err);
+    int32_t h = 0;
+    if ((e = hipGetLastError()) != hipSuccess || (e = hipMemcpyAsync(&h, err, 4, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess)
+        return hip_fail(e, "ilu_transpose_device: run");
+    if (h & 1) return fail(ILU_ERR_CSR, "ilu_transpose_device: row_ptr not monotone or not ending at nnz");
+    if (h & 2) return fail(ILU_ERR_CSR, "ilu_transpose_device: column index out of range");
+    if (h & 4) return fail(ILU_ERR_CSR, "ilu_transpose_device: columns unsorted or repeated");
     return ILU_OK;
 }

@@ -74,6 +74,22 @@ def permute_device(row_ptr: torch.Tensor, col_idx: torch.Tensor, perm: torch.Ten
     return orp, oci, src, dp
 
 
+def transpose_device(row_ptr: torch.Tensor, col_idx: torch.Tensor):
+    """Transposed structure on the GPU (ilu_transpose_device): returns
+    (t_row_ptr, t_col_idx, t_map, t_diag) as int32 device tensors."""
+    lib = L.load()
+    n = row_ptr.numel() - 1
+    nnz = col_idx.numel()
+    dev = row_ptr.device
+    trp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    tci = torch.empty(nnz, dtype=torch.int32, device=dev)
+    tmap = torch.empty(nnz, dtype=torch.int32, device=dev)
+    tdg = torch.empty(n, dtype=torch.int32, device=dev)
+    L.check(lib.ilu_transpose_device(int(n), int(nnz), _ptr(row_ptr), _ptr(col_idx), _ptr(trp), _ptr(tci), _ptr(tmap),
+                                     _ptr(tdg), _stream()), "ilu_transpose_device")
+    return trp, tci, tmap, tdg
+
+
 class Ilu:
     """Analysis handle: ILU(k_max) pattern, level schedule and permuted structure of A."""
 

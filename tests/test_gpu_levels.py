@@ -194,7 +194,14 @@ def test_permute_matches_oracle(jv, name):
 
 def test_permute_fill_patterns_and_errors(jv):
     A = synth.convdiff3d(10)
-    check_permute(jv, O.analyze(A.n, A.row_ptr, A.col_idx, k_max=1), k0_src=False)
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=1)
+    check_permute(jv, an, k0_src=False)
+    # the level-ordered copy of A for spmv: the same call on A's canonical pattern
+    p, ip = dev_perm(an)
+    orp, oci, src, _ = [t.cpu().numpy() for t in jv.permute_device(dev(an.a_rp), dev(an.a_ci), p, ip)]
+    np.testing.assert_array_equal(orp, an.b_rp)
+    np.testing.assert_array_equal(oci, an.b_ci)
+    np.testing.assert_array_equal(np.asarray(an.a_src)[src], an.b_src)
     B = synth.random_sparse(1500, 3e-3, np.random.default_rng(3))
     check_permute(jv, O.analyze(B.n, B.row_ptr, B.col_idx, k_max=2, sym=False), k0_src=False)
     # identity permutation on a pattern without some diagonals: diag_pos -1 there
@@ -237,3 +244,51 @@ def test_device_schedule_pipeline_full(jv, wid):
     ulp, urows, _ = jv.levels_device(orp, oci, "upper")
     np.testing.assert_array_equal(ulp.cpu().numpy(), an.ulevel_ptr)
     np.testing.assert_array_equal(urows.cpu().numpy(), an.ulevel_rows)
+
+
+def check_transpose(jv, rp, ci):
+    # the transpose of a pattern is unique: scipy's CSR transpose with sorted
+    # columns, the entry map carried as the values
+    import scipy.sparse as sp
+    n = len(rp) - 1
+    M = sp.csr_matrix((np.arange(1, len(ci) + 1, dtype=np.int64), np.asarray(ci), np.asarray(rp)), shape=(n, n))
+    T = M.T.tocsr()
+    T.sort_indices()
+    trp, tci, tmap, tdg = [t.cpu().numpy() for t in jv.transpose_device(dev(rp), dev(ci))]
+    np.testing.assert_array_equal(trp, T.indptr)
+    np.testing.assert_array_equal(tci, T.indices)
+    np.testing.assert_array_equal(tmap, T.data - 1)
+    rows = np.repeat(np.arange(n), np.diff(trp))
+    np.testing.assert_array_equal(np.asarray(ci)[tmap], rows)   # entry q of row j came from column j
+    want = np.full(n, -1)
+    hit = tci == rows
+    want[rows[hit]] = np.nonzero(hit)[0]
+    np.testing.assert_array_equal(tdg, want)
+
+
+@pytest.mark.parametrize("name", ["laplace2d_64", "convdiff3d_12", "random_nonsym", "random_missing_diag",
+                                  "heavy_rows"])
+def test_transpose_matches_definition(jv, name):
+    A = CASES[name]()
+    check_transpose(jv, A.row_ptr, A.col_idx)
+    an = O.analyze(A.n, A.row_ptr, A.col_idx, k_max=1)
+    check_transpose(jv, an.lu_rp, an.lu_ci)
+
+
+def test_transpose_degenerate_and_errors(jv):
+    check_transpose(jv, np.array([0, 0]), np.array([], np.int32))
+    n = 500
+    check_transpose(jv, np.minimum(np.arange(n + 1), n - 1), np.arange(1, n))   # upper shift only
+    A = synth.laplace2d(8)
+    ci = A.col_idx.copy()
+    ci[[3, 4]] = ci[[4, 3]]
+    with pytest.raises(jv.IluError) as e:
+        jv.transpose_device(dev(A.row_ptr), dev(ci))
+    assert e.value.status == "ILU_ERR_CSR"
+
+
+@pytest.mark.slow
+def test_transpose_random_1m_full(jv):
+    A, _ = synth.workload(4)
+    an = O.analyze(A.n, A.row_ptr, A.col_idx)
+    check_transpose(jv, an.lu_rp, an.lu_ci)
