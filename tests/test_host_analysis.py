@@ -149,6 +149,25 @@ def test_analyze_error_paths():
     assert _analyze_raw(2, ok_rp, ok_ci, pattern=7) == L.ERR_ARG
     assert _analyze_raw(2, ok_rp, ok_ci, reserved=1) == L.ERR_ARG
     assert _analyze_raw(2, ok_rp, ok_ci, host_only=2) == L.ERR_ARG
+    assert _analyze_raw(2, ok_rp, ok_ci, pattern=L.PATTERN_UPPER_A) == L.ERR_ARG   # device level sets only
+
+
+def test_device_analysis_argument_errors():
+    # rejected before any device work, so these run without a GPU
+    lib = jv.load()
+    p = C.c_void_p(64)
+    nl = C.c_int32(0)
+    assert lib.ilu_levels_device(0, 0, p, p, 0, p, p, p, C.byref(nl), None) == L.ERR_ARG         # n = 0
+    assert lib.ilu_levels_device(4, -1, p, p, 0, p, p, p, C.byref(nl), None) == L.ERR_ARG        # nnz < 0
+    assert lib.ilu_levels_device(4, 4, p, None, 0, p, p, p, C.byref(nl), None) == L.ERR_ARG      # no columns
+    assert lib.ilu_levels_device(4, 4, p, p, 3, p, p, p, C.byref(nl), None) == L.ERR_ARG         # pattern
+    assert lib.ilu_levels_device(4, 4, p, p, 0, None, p, p, C.byref(nl), None) == L.ERR_ARG      # no level_ptr
+    assert lib.ilu_levels_device(4, 4, p, p, 0, p, p, p, None, None) == L.ERR_ARG                # no n_levels
+    assert lib.ilu_permute_device(4, 4, p, p, None, p, p, p, p, p, None) == L.ERR_ARG            # no perm
+    assert lib.ilu_permute_device(4, 4, p, p, p, p, p, None, p, p, None) == L.ERR_ARG            # no out columns
+    assert lib.ilu_permute_device(1 << 30, 4, p, p, p, p, p, p, p, p, None) == L.ERR_ARG         # n too large
+    assert lib.ilu_transpose_device(4, 4, p, p, p, p, None, p, None) == L.ERR_ARG                 # no t_map
+    assert lib.ilu_transpose_device(4, 1 << 31, p, p, p, p, p, p, None) == L.ERR_ARG              # nnz too large
 
 
 def test_numeric_calls_on_host_only_handle_report_state():
