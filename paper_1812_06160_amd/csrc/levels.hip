@@ -17,6 +17,16 @@
 //      and the level pointers are read off the sorted keys.
 // The same sweep on the strictly upper part, from the last row down, gives the
 // backward solve's schedule (Sec. VI) of a permuted factor pattern.
+//
+// The other device-side analysis calls of this file:
+//   - the permuted structure P S P^T in a given order (Sec. III's copy into the
+//     level-ordered CSR of L and U): row lengths gathered and scanned, columns
+//     renamed, one segmented radix sort by row, diagonal positions;
+//   - the transposed structure the adjoint's solves use: column counts, a scan,
+//     a scatter, the same segmented sort.
+// Every kernel after a call's input check reads the check's error word first
+// and does nothing when it is set, so a bad input is never indexed; each call
+// makes one scratch allocation and synchronises with the host once, at the end.
 #include <hip/hip_runtime.h>
 #include <hipcub/device/device_radix_sort.hpp>
 #include <hipcub/device/device_scan.hpp>
